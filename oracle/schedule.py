@@ -1,0 +1,104 @@
+"""Reveal schedules and the confidence-ranked reveal rule.
+
+Paper (overall refinement loop; Appendix, masked-diffusion inference):
+at each step the masked sites with the highest confidence are set to their
+argmax symbol, the number revealed so far following a schedule; on the
+first step of decoding from the all-mask grid each slot is first narrowed
+to its single most confident row ("first-reveal stabilisation").
+
+Readings taken here (all stated in the design notes):
+  * confidence is ranked by the logit margin |L0 - L1|, which orders sites
+    exactly as max softmax probability does for two symbols (and as it does
+    at any temperature), without saturating to 1.0;
+  * ties in the ranking go to the smaller flat index k*n + l, ties in the
+    first-reveal row choice to the smaller k, ties in the argmax to bit 0;
+  * first-reveal restricts the step-1 candidate set, and the number revealed
+    still follows the schedule;
+  * linear schedule (R_t = floor(t N / T)) by default; the cosine schedule
+    R_t = floor(rho(t) N), rho(t) = (1 - cos(pi t / T)) / 2, evaluated in
+    float64 with at least one site per step.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, List
+
+import numpy as np
+
+MASK = 2
+
+
+def linear_targets(n_masked: int, T: int) -> List[int]:
+    """Cumulative reveal targets R_1..R_T with R_t = floor(t * N / T)."""
+    return [(t * n_masked) // T for t in range(1, T + 1)]
+
+
+def cosine_targets(n_masked: int, T: int) -> List[int]:
+    """Cumulative targets R_t = floor(rho(t) * N) computed in float64."""
+    return [int(math.floor(0.5 * (1.0 - math.cos(math.pi * t / T)) * n_masked)) for t in range(1, T + 1)]
+
+
+def step_counts(n_masked: int, T: int, kind: str = "linear") -> List[int]:
+    """Per-step reveal counts r_t assuming every requested site is available."""
+    if kind == "linear":
+        R = linear_targets(n_masked, T)
+    elif kind == "cosine":
+        R = cosine_targets(n_masked, T)
+    else:
+        raise ValueError(kind)
+    out, done = [], 0
+    for t, Rt in enumerate(R, start=1):
+        r = Rt - done
+        if kind == "cosine":
+            r = max(1, r)
+            if t == T:
+                r = n_masked - done
+        r = max(0, min(r, n_masked - done))
+        out.append(r)
+        done += r
+    return out
+
+
+def margins(logits: np.ndarray) -> np.ndarray:
+    return np.abs(logits[..., 0] - logits[..., 1])
+
+
+def reveal(X: np.ndarray, logits: np.ndarray, r: int, first_reveal: bool) -> Dict:
+    """Reveal up to r masked sites of X [K][n] in place; returns selection info.
+
+    'gaps' reports how far each integer decision in this step sits from a tie:
+    cut (r-th minus (r+1)-th candidate margin), sel (smallest selected margin,
+    i.e. the argmax decision) and slot (first-reveal best-minus-second row).
+    """
+    K, n = X.shape
+    c = margins(logits)
+    masked = X == MASK
+    inf = float("inf")
+    gaps = {"cut": inf, "sel": inf, "slot": inf}
+    if first_reveal:
+        cm = np.where(masked, c, -np.inf)
+        cand = []
+        for l in range(n):
+            if not masked[:, l].any():
+                continue
+            k = int(np.argmax(cm[:, l]))           # first maximum -> smallest k
+            cand.append((k, l))
+            col = np.sort(cm[:, l][masked[:, l]])[::-1]
+            if col.size > 1:
+                gaps["slot"] = min(gaps["slot"], float(col[0] - col[1]))
+    else:
+        ks, ls = np.nonzero(masked)
+        cand = list(zip(ks.tolist(), ls.tolist()))
+    if not cand or r <= 0:
+        return {"selected": [], "gaps": gaps}
+    cvals = np.array([c[k, l] for k, l in cand])
+    flat = np.array([k * n + l for k, l in cand])
+    order = np.lexsort((flat, -cvals))             # by margin desc, then flat index asc
+    take = order[:min(r, len(cand))]
+    if len(cand) > r:
+        gaps["cut"] = float(cvals[order[r - 1]] - cvals[order[r]])
+    sel = [cand[i] for i in take]
+    gaps["sel"] = float(min(cvals[i] for i in take))
+    for k, l in sel:
+        X[k, l] = 0 if logits[k, l, 0] >= logits[k, l, 1] else 1
+    return {"selected": sel, "gaps": gaps}

@@ -1,0 +1,225 @@
+"""Pins for the reveal schedule, the reveal rule, the refinement loop with
+remasking, and the set-recovery metrics."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import brute, metrics
+from oracle.decode import DecodeOpts, decode_bin, decode_grid, row_status
+from oracle.schedule import MASK, cosine_targets, linear_targets, reveal, step_counts
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_cosine_schedule_matches_paper_figures():
+    g = json.load(open(os.path.join(GOLDEN, "cosine_reveal_T12_N24.json")))
+    counts = step_counts(g["sites"], g["T"], "cosine")
+    cum = np.concatenate([[0], np.cumsum(counts)])
+    for t, want in g["cumulative_revealed"].items():
+        assert cum[int(t)] == want, (t, cum[int(t)], want)
+    # the float64 floor is what gives 5 at t=4 (rho(4)*24 rounds below 6)
+    assert cosine_targets(24, 12)[3] == 5
+
+
+@pytest.mark.parametrize("K,n,T,per", [(2, 32, 8, 8), (4, 128, 16, 32), (8, 256, 32, 64)])
+def test_linear_schedule_counts(K, n, T, per):
+    c = step_counts(K * n, T, "linear")
+    assert c == [per] * T and sum(c) == K * n
+    assert linear_targets(K * n, T)[-1] == K * n
+
+
+@pytest.mark.parametrize("N,T", [(7, 3), (24, 12), (100, 7), (5, 5), (3, 1)])
+def test_schedules_reveal_everything(N, T):
+    for kind in ("linear", "cosine"):
+        c = step_counts(N, T, kind)
+        assert sum(c) == N and len(c) == T and min(c) >= 0
+
+
+def test_reveal_picks_top_margins_with_index_tiebreak():
+    X = np.full((2, 4), MASK, np.uint8)
+    X[1, 3] = 1
+    lg = np.zeros((2, 4, 2))
+    marg = np.array([[0.5, -0.9, 0.9, 0.1], [0.9, 0.2, -0.3, 5.0]])
+    lg[..., 0] = marg
+    info = reveal(X, lg, 3, first_reveal=False)
+    # margins 0.9 at (0,1),(0,2),(1,0) tie -> flat order 1, 2, 4; (1,3) is not masked
+    assert info["selected"] == [(0, 1), (0, 2), (1, 0)]
+    assert X[0, 1] == 1 and X[0, 2] == 0 and X[1, 0] == 0 and X[1, 3] == 1
+    assert (X == MASK).sum() == 8 - 1 - 3
+
+
+def test_first_reveal_restricts_to_best_row_per_slot():
+    X = np.full((3, 4), MASK, np.uint8)
+    marg = np.array([[0.1, 0.7, 0.3, 0.3],
+                     [0.6, 0.2, 0.3, 0.1],
+                     [0.9, 0.8, 0.3, 0.0]])
+    lg = np.zeros((3, 4, 2))
+    lg[..., 1] = -marg
+    info = reveal(X, lg, 2, first_reveal=True)
+    # slot winners: l0 -> k2 (0.9), l1 -> k2 (0.8), l2 -> k0 (tie 0.3, smallest k), l3 -> k0
+    assert info["selected"] == [(2, 0), (2, 1)]
+    info = reveal(X, lg, 5, first_reveal=True)
+    # second call: slot winners among still-masked rows are (1,0) 0.6, (0,1) 0.7,
+    # (0,2) 0.3 and (0,3) 0.3; only 4 candidates exist for r = 5
+    assert info["selected"] == [(0, 1), (1, 0), (0, 2), (0, 3)]
+
+
+def test_argmax_tie_goes_to_bit_zero():
+    X = np.full((1, 2), MASK, np.uint8)
+    lg = np.zeros((1, 2, 2))
+    reveal(X, lg, 2, first_reveal=False)
+    assert (X == 0).all()
+
+
+def _tiny():
+    return synth.regular_ldpc(12, seed=12)
+
+
+def test_genie_refinement_recovers_map_set():
+    """With an exact-posterior denoiser, confidence-ranked refinement must end
+    on the brute-force joint-MAP message set whenever that set holds >= 0.99
+    of the posterior mass (tiny code n=12, k=6, K=2)."""
+    code = _tiny()
+    C = brute.codebook(code)
+    checked = 0
+    for seed in range(40):
+        bins = synth.make_bins(code, 2, 1, 5.0 + (seed % 4), seed=1000 + seed)
+        y, s2 = bins.y[0].astype(np.float64), float(bins.sigma2[0])
+        (i, j), mass = brute.map_pair(C, y, s2)
+        if mass < 0.99:
+            continue
+        den = brute.genie_denoiser(C, y, s2)
+        res = decode_grid(2, 12, code, den, T=24, opts=DecodeOpts(first_reveal=True, parity=False))
+        assert metrics.same_multiset(res.X, C[[i, j]]), seed
+        assert res.row_valid.all()
+        checked += 1
+    assert checked >= 10
+
+
+def test_map_pair_beats_truth_likelihood():
+    code = _tiny()
+    C = brute.codebook(code)
+    bins = synth.make_bins(code, 2, 1, 1.0, seed=3)
+    y, s2 = bins.y[0].astype(np.float64), float(bins.sigma2[0])
+    (i, j), _ = brute.map_pair(C, y, s2)
+    L = brute.pair_loglik(C, y, s2)
+    ti = int(np.nonzero((C == bins.codewords[0][0]).all(axis=1))[0][0])
+    tj = int(np.nonzero((C == bins.codewords[0][1]).all(axis=1))[0][0])
+    assert L[i, j] >= L[ti, tj] - 1e-12
+    iu = np.triu_indices(C.shape[0], 1)
+    assert abs(L[i, j] - L[iu].max()) < 1e-12
+
+
+def _small_setup(K=3, n=32, L=2, d=32, h=4):
+    cfg = synth.ModelCfg(L, d, h, n_max=n)
+    w = synth.unpack_weights(synth.make_weights(cfg, 5, bias_std=0.02), cfg)
+    code = synth.regular_ldpc(n, seed=1000 + n)
+    bins = synth.make_bins(code, K, 2, 4.0, seed=77)
+    return cfg, w, code, bins
+
+
+def test_decode_invariants_hold_fixed_and_counts():
+    cfg, w, code, bins = _small_setup()
+    K, n, T = 3, 32, 8
+    res = decode_bin(bins.y[0], bins.sigma2[0], code, K, w, cfg.n_layers, cfg.heads, T,
+                     DecodeOpts(), keep=True)
+    assert len(res.steps) == T
+    for a, b in zip(res.steps[:-1], res.steps[1:]):
+        rev = a["X_in"] != MASK
+        assert np.array_equal(a["X_in"][rev], b["X_in"][rev])   # revealed tokens never change
+    for s in res.steps:
+        assert len(s["selected"]) == s["r"] == K * n // T
+        assert len(set(s["selected"])) == s["r"]
+        assert all(s["X_in"][k, l] == MASK for k, l in s["selected"])
+    assert res.steps[0]["first"] and not res.steps[1]["first"]
+    assert (res.X != MASK).all()
+    assert np.isclose(res.steps[0]["gamma"], 1.0) and np.isclose(res.steps[-1]["gamma"], 1.0 / T)
+
+
+def test_remask_rounds_clamp_and_trm():
+    cfg, w, code, bins = _small_setup()
+    K, n, T = 3, 32, 8
+    opts = DecodeOpts(remask=True, remask_thr=0.9, remask_max_rounds=2)
+    res = decode_bin(bins.y[0], bins.sigma2[0], code, K, w, cfg.n_layers, cfg.heads, T, opts, keep=True)
+    assert res.rounds <= 2 and len(res.finals) == res.rounds + 1
+    start = T
+    grid_after = res.steps[T - 1]["X_in"].copy()
+    for r in range(res.rounds):
+        low = res.finals[r]["low"]
+        T_rm = max(1, int(math.floor(T * int(low.sum()) / K)))
+        seg = res.steps[start:start + T_rm]
+        assert len(seg) == T_rm
+        for s in seg:
+            assert not s["first"]
+            assert all(low[k] for k, _ in s["selected"])             # only remasked rows change
+            assert (s["X_in"][~low] != MASK).all()
+        assert sum(len(s["selected"]) for s in seg) == int(low.sum()) * n
+        start += T_rm
+    assert start == len(res.steps)
+
+
+def test_remask_criterion():
+    code = synth.regular_ldpc(32, seed=1032)
+    cw = synth.make_bins(code, 2, 1, 4.0, seed=2).codewords[0]
+    X = cw.copy()
+    X[1, 0] ^= 1                                   # row 1 fails parity
+    fin = np.zeros((2, 32, 2))
+    fin[0, :, 0] = np.where(cw[0] == 0, 5.0, -5.0)  # confident row 0
+    fin[1, :, 0] = 10.0
+    syn, q, low = row_status(X, fin, code, 0.9)
+    assert list(syn) == [False, True] and list(low) == [False, True]
+    fin[0, :, 0] = 0.1                              # unconfident row 0: q = sigmoid(0.1) < 0.9
+    _, q, low = row_status(X, fin, code, 0.9)
+    assert low[0] and abs(q[0] - 1 / (1 + math.exp(-0.1))) < 1e-15
+
+
+def test_hungarian_matches_bruteforce():
+    rng = np.random.default_rng(0)
+    for K in range(1, 7):
+        for _ in range(5):
+            A = rng.integers(0, 2, size=(K, 12))
+            B = A[rng.permutation(K)] ^ (rng.random((K, 12)) < 0.2)
+            pi = metrics.match_rows(A, B)
+            _, best = metrics.match_rows_bruteforce(A, B)
+            assert int(metrics.hamming_cost(A, B)[np.arange(K), pi].sum()) == best
+
+
+def test_toy_example_set_rule():
+    g = json.load(open(os.path.join(GOLDEN, "toy_set_recovery.json")))
+    alpha = {c: i for i, c in enumerate(g["alphabet"])}
+    enc = lambda s: np.array([alpha[c] for c in s], np.uint8)
+    book = {enc(s).tobytes(): int(m) for m, s in g["codebook"].items()}
+    grid = np.stack([enc(s) for s in g["decoded_grid"]])
+    assert metrics.decoded_set(grid, book) == set(g["message_set"])
+    assert metrics.decoded_set(grid[::-1], book) == set(g["message_set"])
+    truth = np.stack([enc(g["codebook"]["3"]), enc(g["codebook"]["4"])])
+    assert metrics.ser_cer(grid, truth) == (0.0, 0.0)
+
+
+def test_single_step_reveals_everything():
+    cfg, w, code, bins = _small_setup(K=2)
+    res = decode_bin(bins.y[0], bins.sigma2[0], code, 2, w, cfg.n_layers, cfg.heads, 1, DecodeOpts())
+    assert (res.X != MASK).all()
+
+
+def test_remask_step_counts_by_hand():
+    """Stub denoiser: row 0 always decodes to the all-zero codeword, rows 1 and
+    2 to a word with a single 1 (nonzero syndrome).  With K=3, T=8 both
+    remask rounds remask rows {1, 2}, so T_rm = floor(8*2/3) = 5 steps each:
+    8 + 5 + 5 = 18 reveal steps and 3 final passes."""
+    code = synth.regular_ldpc(32, seed=1032)
+
+    def den(X, gamma):
+        lg = np.zeros((3, 32, 2))
+        lg[..., 0] = 3.0
+        lg[1:, 0, 0] = -3.0
+        return lg
+
+    res = decode_grid(3, 32, code, den, T=8, opts=DecodeOpts(remask=True, remask_max_rounds=2))
+    assert res.rounds == 2 and len(res.finals) == 3
+    assert [len(s["selected"]) for s in res.steps] == [12] * 8 + [12, 13, 13, 13, 13] * 2
+    assert list(res.row_valid) == [1, 0, 0]
