@@ -1,0 +1,250 @@
+/*
+ * cider.h -- C ABI of the MI355X (gfx950) CIDER refinement library.
+ *
+ * CIDER decodes K superposed codewords of a shared binary LDPC code from one
+ * noisy aggregate: y_l = sum_k x_{k,l} + noise, x = +1 for bit 0 and -1 for
+ * bit 1.  The decoder keeps a K x n grid of symbols {0, 1, MASK} and repeats a
+ * masked-diffusion refinement step (paper: method section, refinement loop):
+ *
+ *   evidence  p[l, a] = normalised Pr(some user sent a at slot l | y_l)
+ *                       (Appendix, evidence interface; exact for BPSK)
+ *   denoiser  embedding -> Module A (row competition for the evidence) ->
+ *             L blocks of {row attention over slots, attention across the K
+ *             rows of each slot, GELU MLP} -> final LayerNorm -> logits
+ *   Module B  soft parity messages over the Tanner graph of H added to the
+ *             logits as a bias (method section, check message and update)
+ *   reveal    the most confident masked sites take their argmax symbol;
+ *             first-reveal on step 1 (Appendix, masked-diffusion inference)
+ *   final pass and quality-guided remasking of parity-failing or
+ *             low-confidence rows (Appendix, PRISM-style remasking; here with
+ *             a fixed row criterion instead of a learned head)
+ *
+ * Conventions for every entry point:
+ *   - Pointers documented "device" must point to memory on the current HIP
+ *     device; "host" pointers are read during the call only.
+ *   - `stream` is a hipStream_t (NULL = default stream).  Work is enqueued on
+ *     it and the call returns before the work completes, except where noted;
+ *     outputs are valid once the stream has reached the enqueued work.
+ *   - Return value: CIDER_OK (0) or a negative CIDER_E* code.  Argument errors
+ *     are detected before anything is enqueued.  A HIP error is reported as
+ *     CIDER_EDEVICE; cider_last_error() gives a readable message for the
+ *     calling thread.  No C++ exception crosses this interface.
+ *   - Handles (weights, code, server) are owned by the library and freed with
+ *     the matching *_destroy.  Weights and code handles are immutable after
+ *     creation and may be shared between threads.  Decode calls that use the
+ *     library's internal workspace (opts->workspace == NULL) on the same
+ *     weights handle must not run concurrently on different streams; pass a
+ *     caller-owned workspace to run them concurrently.
+ */
+#ifndef CIDER_H
+#define CIDER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CIDER_OK            0
+#define CIDER_EINVAL       -1   /* bad argument or sizes                        */
+#define CIDER_ENOMEM       -2   /* device or host allocation failed             */
+#define CIDER_EDEVICE      -3   /* HIP runtime error                            */
+#define CIDER_EUNSUPPORTED -4   /* valid request this build does not implement  */
+#define CIDER_EAGAIN       -5   /* server queue full, retry later               */
+
+#define CIDER_MAX_K      16     /* users per bin                                */
+#define CIDER_MAX_N    1024     /* slots per bin (also the positional table)    */
+#define CIDER_MASK        2     /* grid value of a masked site                  */
+
+enum cider_precision {
+  CIDER_FP32 = 0,   /* every contraction in FP32 (MFMA 16x16x4 f32)            */
+  CIDER_BF16 = 1,   /* GEMM/attention operands BF16, FP32 accumulate           */
+  CIDER_FP8  = 2    /* GEMM operands OCP e4m3 with per-tensor weight scale and */
+                    /* per-token activation scale, FP32 accumulate             */
+};
+
+enum cider_schedule {
+  CIDER_SCHED_LINEAR = 0,  /* R_t = floor(t N / T) revealed after step t       */
+  CIDER_SCHED_COSINE = 1   /* R_t = floor(rho(t) N), rho = (1 - cos(pi t/T))/2, */
+                           /* at least one site per step (Appendix, cosine     */
+                           /* reveal schedule)                                  */
+};
+
+/* Denoiser sizes.  d % heads == 0, d / heads in {16, 32, 64}, d % 64 == 0,
+ * d <= 512, mlp_mult * d <= 2048, n_max <= CIDER_MAX_N. */
+typedef struct {
+  int32_t n_layers;
+  int32_t d;
+  int32_t heads;
+  int32_t mlp_mult;   /* MLP hidden width = mlp_mult * d (the workloads use 4) */
+  int32_t n_max;      /* rows of the positional table P                      */
+} cider_model_cfg;
+
+/* Decoding options; cider_opts_default() fills the values in brackets. */
+typedef struct {
+  int32_t precision;          /* cider_precision                       [BF16]   */
+  int32_t schedule;           /* cider_schedule                        [LINEAR] */
+  int32_t first_reveal;       /* 1: step 1 of the initial pass only reveals    */
+                              /*    each slot's most confident row       [1]   */
+  int32_t remask;             /* 1: quality-guided remasking on          [0]   */
+  int32_t remask_max_rounds;  /* rounds of remasking                     [2]   */
+  int32_t final_argmax;       /* 1: output argmax of the last final pass       */
+                              /* 0: output the held-fixed grid           [0]   */
+  int32_t use_graph;          /* 1: replay each refinement step as a hipGraph  */
+                              /*    captured on `stream`                 [1]   */
+  float   remask_thr;         /* low row: mean max-prob < thr           [0.9]  */
+  float   tau;                /* Module A responsibility temperature    [1.0]  */
+  float   eta;                /* Module B bias gain                     [1.0]  */
+  float   lam_max;            /* LLR clip and revealed-site LLR         [20]   */
+  float   lam_min;            /* |LLR| floor inside phi                 [1e-6] */
+  int32_t profile;            /* 1: time every kernel launch with HIP events   */
+                              /*    on `stream` (eager launches, no graph);    */
+                              /*    read with cider_profile_read         [0]   */
+  void*   workspace;          /* device scratch owned by the caller, or NULL   */
+  size_t  workspace_bytes;    /* size of `workspace`; see cider_workspace_size */
+} cider_opts;
+
+typedef struct cider_weights cider_weights;
+typedef struct cider_code    cider_code;
+
+/* One bin of a batch (cider_decode_batch). */
+typedef struct {
+  const float*      y;             /* device [n] FP32 received aggregate        */
+  float             sigma2;        /* noise variance, > 0                        */
+  const cider_code* code;          /* parity-check matrix, code->n == n          */
+  int32_t           K;             /* users, 1..CIDER_MAX_K                      */
+  int32_t           n;             /* slots, 1..min(n_max, CIDER_MAX_N)          */
+  uint8_t*          out_symbols;   /* device [K][n] row-major, values {0,1}      */
+  float*            out_logits;    /* device [K][n][2] FP32 logits of the last   */
+                                   /* final pass, or NULL                        */
+  uint8_t*          out_row_valid; /* device [K]: 1 iff H x_k = 0, or NULL       */
+} cider_bin;
+
+/* Fills `opts` with the defaults listed above. */
+void cider_opts_default(cider_opts* opts);
+
+/* Number of floats a weights blob for `cfg` holds (layout below), or 0 if cfg
+ * is invalid.  Blob layout, all row-major FP32, a linear map is y = x W^T + b:
+ *   E[3][d] (row 2 = mask token), P[n_max][d], u[d], W[2][d], v[2][d],
+ *   Wg1[d][2d], bg1[d], Wg2[d][d], bg2[d],
+ *   per layer: ln1_g[d] ln1_b[d] Wqkv_r[3d][d] bqkv_r[3d] Wo_r[d][d] bo_r[d]
+ *              ln2_g[d] ln2_b[d] Wqkv_u[3d][d] bqkv_u[3d] Wo_u[d][d] bo_u[d]
+ *              ln3_g[d] ln3_b[d] W1[F][d] b1[F] W2[d][F] b2[d]   (F = mlp_mult d)
+ *   lnf_g[d], lnf_b[d].
+ * q, k, v of an attention are the three consecutive d-row blocks of Wqkv;
+ * head h uses rows h*d/heads .. (h+1)*d/heads - 1 of each block. */
+size_t cider_weights_blob_floats(const cider_model_cfg* cfg);
+
+/* Uploads a host FP32 blob to the current device and prepares the FP32, BF16
+ * and FP8 copies of every matrix.  Synchronous.  `n_floats` must equal
+ * cider_weights_blob_floats(cfg). */
+int cider_weights_create(const cider_model_cfg* cfg, const float* host_blob, size_t n_floats,
+                         cider_weights** out);
+void cider_weights_destroy(cider_weights* w);
+
+/* Binary parity-check matrix H (m checks x n slots) given as host CSR:
+ * row_ptr[m+1], col_idx[row_ptr[m]] with ascending, distinct column indices
+ * in [0, n).  Rows may have any degree up to 32; every slot may appear in
+ * at most 32 checks.  Copied to the device; synchronous. */
+int cider_code_create(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* col_idx,
+                      cider_code** out);
+void cider_code_destroy(cider_code* code);
+
+/* Bytes of caller workspace a batch of `num_bins` bins with `total_tokens`
+ * = sum of K*n and `total_slots` = sum of n needs under `opts`. */
+int cider_workspace_size(const cider_weights* w, int32_t num_bins, int64_t total_tokens,
+                         int64_t total_slots, const cider_opts* opts, size_t* bytes);
+
+/* Decodes one bin (problem statement: evidence from y, then S -> unordered
+ * K x n grid).  y: device [n] FP32; out_symbols: device [K][n] uint8.
+ * steps = T of the initial pass, 1 <= steps <= K*n.  opts may be NULL for the
+ * defaults.  Returns after enqueueing, except that with remasking on the
+ * call synchronises `stream` once per remask round to learn whether any bin
+ * still needs work. */
+int cider_decode(const float* y, float sigma2, const cider_code* code, int32_t K, int32_t n,
+                 const cider_weights* w, int32_t steps, uint8_t* out_symbols,
+                 const cider_opts* opts, void* stream);
+
+/* Decodes `num_bins` independent bins of possibly different K, n and code in
+ * one packed pass per step.  The result of every bin is bit-identical to
+ * decoding it alone with cider_decode and the same opts. */
+int cider_decode_batch(int32_t num_bins, const cider_bin* bins, const cider_weights* w,
+                       int32_t steps, const cider_opts* opts, void* stream);
+
+/* Test entry point: one teacher-forced denoiser step on a given grid.
+ * X_in: device [K][n] uint8 in {0,1,2}; gamma: mask-ratio input.
+ * Writes out_lbar (logits before Module B) and out_logits (after), device
+ * [K][n][2] FP32, either may be NULL; out_z: device [K][n][d] FP32 residual
+ * stream before the final LayerNorm, or NULL.  If X_out is not NULL the
+ * reveal rule is applied to a copy of X_in with `reveal_count` sites and
+ * first-reveal flag `first` and the result written to X_out [K][n]. */
+int cider_step_debug(const uint8_t* X_in, uint8_t* X_out, const float* y, float sigma2,
+                     const cider_code* code, int32_t K, int32_t n, const cider_weights* w,
+                     float gamma, int32_t reveal_count, int32_t first, const cider_opts* opts,
+                     float* out_lbar, float* out_logits, float* out_z, void* stream);
+
+/* Per-slot evidence alone: out_S and out_p device [n][2] FP32 (either may be
+ * NULL).  S[l,a] = log Pr(symbol a present at slot l | y_l), p = softmax_a S. */
+int cider_evidence(const float* y, float sigma2, int32_t K, int32_t n, float* out_S, float* out_p,
+                   void* stream);
+
+/* ---- serving: continuous batching of arriving bins ---------------------- */
+typedef struct cider_server cider_server;
+
+typedef struct {
+  const cider_weights* weights;
+  cider_opts           opts;
+  int32_t              steps;          /* T of every request                    */
+  int32_t              max_slots;      /* bins resident on the device at once   */
+  int32_t              max_queue;      /* waiting requests before EAGAIN        */
+  size_t               hbm_budget;     /* bytes of bin state + step workspace   */
+  int64_t              max_tokens;     /* sum of K*n over resident bins          */
+} cider_server_cfg;
+
+typedef struct {
+  uint64_t id;           /* request id from cider_server_submit            */
+  int32_t  K, n;
+  int32_t  status;       /* CIDER_OK or an error                           */
+  int32_t  rounds;       /* remask rounds run                              */
+  double   t_submit;     /* seconds, monotonic clock                       */
+  double   t_admit;
+  double   t_done;
+} cider_result;
+
+/* Creates a server with its own HIP stream and worker thread on the current
+ * device.  Resident bins advance one refinement step per iteration; a newly
+ * admitted bin joins at its own step 1 while others are mid-decode. */
+int cider_server_create(const cider_server_cfg* cfg, cider_server** out);
+/* Queues a request.  y_host: host [n] FP32 (copied).  out_symbols_host:
+ * host [K][n], written before the request is reported done; it must stay
+ * valid until then.  Returns CIDER_EAGAIN when the queue is full. */
+int cider_server_submit(cider_server* s, const float* y_host, float sigma2, const cider_code* code,
+                        int32_t K, int32_t n, uint8_t* out_symbols_host, uint64_t* id);
+/* Moves up to `max` finished results into `out`; *n_done receives the count.
+ * Non-blocking. */
+int cider_server_poll(cider_server* s, cider_result* out, int32_t max, int32_t* n_done);
+/* Blocks until every submitted request has finished. */
+int cider_server_drain(cider_server* s);
+void cider_server_destroy(cider_server* s);
+
+/* Per-kernel timings gathered by decode calls made with opts->profile = 1 on
+ * this weights handle.  Synchronises the device.  Kernels are named by their
+ * role in the step (e.g. "gemm_mlp_up", "attn_row", "step_tail").  `reset`
+ * clears the accumulated figures after reading. */
+typedef struct {
+  char    name[32];
+  int64_t launches;
+  double  total_ms;     /* summed launch durations between the bracketing events */
+} cider_kernel_stat;
+int cider_profile_read(const cider_weights* w, cider_kernel_stat* out, int32_t max, int32_t* n_out,
+                       int32_t reset);
+
+/* Message for a status code, and the last error detail of this thread. */
+const char* cider_strerror(int status);
+const char* cider_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CIDER_H */

@@ -1,0 +1,154 @@
+// Internal declarations shared by the HIP kernels and the host engine of the
+// CIDER refinement library (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace cider {
+
+constexpr int kMask = 2;
+constexpr int kMaxK = 16;
+constexpr int kMaxN = 1024;
+constexpr int kMaxDeg = 32;
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((__vector_size__(8 * sizeof(__bf16))));
+typedef __bf16 bf16x4 __attribute__((__vector_size__(4 * sizeof(__bf16))));
+typedef float f32x4 __attribute__((__vector_size__(4 * sizeof(float))));
+
+enum Phase : int { kReveal = 0, kFinal = 1, kDone = 2 };
+enum Prec : int { kF32 = 0, kBF16 = 1, kFP8 = 2 };
+
+// Per-bin decoding state, device resident, advanced by the step-tail kernel.
+struct BinState {
+  int phase;      // Phase
+  int t;          // next reveal step of the current pass, 1-based
+  int pass_T;     // reveal steps in the current pass
+  int n_masked;   // sites masked when the current pass started
+  int revealed;   // sites revealed so far in the current pass
+  int masked;     // sites currently masked (gamma = masked / (K n))
+  int first;      // first-reveal applies to step 1 of this pass
+  int round;      // remask rounds started
+  int sched_j;    // schedule table in use: 0 initial pass, j = rows remasked
+  int low_rows;   // bitmask of the rows remasked in the current round
+  int valid_rows; // bitmask of rows with zero syndrome in the output
+  int pad;
+};
+
+// Static description of one bin inside a packed batch.
+struct DevBin {
+  int tok_off;          // first token of the bin in the packed token arrays
+  int K, n, m;
+  int slot_off;         // first slot of the bin in per-slot arrays
+  int row_off;          // first row of the bin in per-row arrays
+  const int* row_ptr;   // check -> slots CSR of H (device)
+  const int* col_idx;
+  const int* var_ptr;   // slot -> edges of H, ascending check order
+  const int* var_edge;  // edge index into col_idx for each (slot, check)
+  const int* sched;     // [K+1] offsets, [K+1] lengths, cumulative reveal targets
+  const float* y;
+  float sigma2;
+  uint8_t* X;           // grid [K][n], persistent across steps
+  uint8_t* out_sym;     // [K][n]
+  float* out_logits;    // [K][n][2] or null
+  uint8_t* out_valid;   // [K] or null
+  BinState* st;
+};
+
+// Everything a refinement step needs besides the weights.
+struct StepCtx {
+  int num_bins;
+  const DevBin* bins;       // device [num_bins]
+  const int* slot_bin;      // device [total_slots]
+  const int* row_bin;       // device [total_rows]
+  int total_slots;
+  int total_rows;
+  long total_tokens;
+  int max_n;                // largest n in the batch
+  int schedule, remask, max_rounds, final_argmax;
+  float remask_thr, tau, eta, lam_max, lam_min;
+  float gamma_override;     // >= 0: mask-ratio input for every bin (teacher-forced step)
+  int reveal_override;      // >= 0: reveal this many sites instead of the schedule's count
+  int first_override;       // first-reveal flag used with reveal_override
+};
+
+// Device copies of one weight matrix.
+struct Mat {
+  const float* f32 = nullptr;
+  const bf16* b16 = nullptr;
+  const uint8_t* f8 = nullptr;
+  float f8_scale = 1.f;   // W ~= f8_scale * fp8(W)
+  int rows = 0, cols = 0;
+};
+
+struct DevLayer {
+  const float *ln1_g, *ln1_b, *bqkv_r, *bo_r;
+  const float *ln2_g, *ln2_b, *bqkv_u, *bo_u;
+  const float *ln3_g, *ln3_b, *b1, *b2;
+  Mat Wqkv_r, Wo_r, Wqkv_u, Wo_u, W1, W2;
+};
+
+// The small-vector weights the per-slot and per-token kernels read.
+struct EmbedW {
+  int d;
+  const float *E, *P, *u, *W, *v, *lnf_g, *lnf_b;
+};
+
+struct DevModel {
+  int n_layers, d, heads, mlp_mult, n_max;
+  const float *E, *P, *u, *W, *v, *bg1, *bg2, *lnf_g, *lnf_b;
+  Mat Wg1, Wg2;
+  DevLayer layer[64];
+};
+
+// Transient buffers of one forward pass over a packed batch of T tokens.
+struct Work {
+  float* R;        // [T][d]     FP32 residual stream
+  float* Ebuf;     // [T][d]     Module A evidence summary e
+  void* ZE;        // [T][2d]    gate MLP input [Z ; e]        (compute type)
+  void* H1;        // [T][d]     gate MLP hidden               (compute type)
+  void* QKV;       // [T][3d]    attention projections         (compute type)
+  void* O;         // [T][d]     attention output              (compute type)
+  void* HID;       // [T][F]     MLP hidden                    (compute type)
+  float* ascale;   // [T]        per-token FP8 activation scales (FP8 only)
+  float* lbar;     // [T][2]     logits before Module B
+  float* logits;   // [T][2]     logits after Module B
+  float* p;        // [slots][2] per-slot beliefs
+  float* S;        // [slots][2] per-slot log evidence
+};
+
+// ---- launchers (kernels_*.hip) --------------------------------------------
+hipError_t launch_evidence(const StepCtx& c, float* S, float* p, hipStream_t s);
+hipError_t launch_init_bins(const StepCtx& c, int T, int first_reveal, hipStream_t s);
+hipError_t launch_embed_demix(const StepCtx& c, const EmbedW& m, const Work& w, int prec,
+                              hipStream_t s);
+hipError_t launch_final_proj(const StepCtx& c, const EmbedW& m, const Work& w, hipStream_t s);
+hipError_t launch_module_b(const StepCtx& c, const Work& w, hipStream_t s);
+hipError_t launch_step_tail(const StepCtx& c, const Work& w, hipStream_t s);
+
+// GEMM: out = epi(pro(A) W^T + bias).  A rows are tokens.
+enum Pro : int { kProNone = 0, kProLN = 1 };
+enum Epi : int { kEpiStore = 0, kEpiGelu = 1, kEpiResid = 2, kEpiGate = 3 };
+struct GemmArgs {
+  long M;
+  int N, Kd;
+  const void* A;        // [M][Kd]: FP32 when pro == LN, else compute type
+  const float* ln_g;    // LN gain/bias over Kd (pro == LN)
+  const float* ln_b;
+  const float* bias;    // [N]
+  void* out;            // [M][N] compute type (Store, Gelu)
+  float* R;             // [M][N] FP32 residual (Resid, Gate)
+  const float* E;       // [M][N] FP32 (Gate)
+  const float* a_scale; // [M] per-token activation scale (FP8 input)
+  float* out_scale;     // [M] per-token scale of `out` (FP8 output)
+};
+hipError_t launch_gemm(int prec, int pro, int epi, const GemmArgs& g, const Mat& W, hipStream_t s);
+
+hipError_t launch_row_attn(const StepCtx& c, int prec, const void* QKV, void* O, int d, int heads,
+                           int max_n, hipStream_t s);
+hipError_t launch_user_attn(const StepCtx& c, int prec, const void* QKV, void* O, int d, int heads,
+                            hipStream_t s);
+
+}  // namespace cider

@@ -1,0 +1,849 @@
+// Host side of the CIDER refinement library: handles, argument checks, packed
+// batch layout, reveal-schedule tables, the per-step launch sequence (eager or
+// replayed as a captured hipGraph) and the C ABI declared in cider.h.
+#include "cider.h"
+#include "cider_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+using namespace cider;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return CIDER_EDEVICE;
+}
+
+#define HIPCHK(expr)                                      \
+  do {                                                    \
+    hipError_t e__ = (expr);                              \
+    if (e__ != hipSuccess) return hip_fail(e__, #expr);   \
+  } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+uint16_t f32_to_bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan
+  u += 0x7fffu + ((u >> 16) & 1u);                                     // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+
+bool cfg_ok(const cider_model_cfg* c, std::string* why) {
+  if (!c) { *why = "null cfg"; return false; }
+  if (c->n_layers < 1 || c->n_layers > 64) { *why = "n_layers must be 1..64"; return false; }
+  if (c->d < 64 || c->d > 512 || c->d % 64) { *why = "d must be a multiple of 64 in 64..512"; return false; }
+  if (c->heads < 1 || c->d % c->heads) { *why = "heads must divide d"; return false; }
+  int dh = c->d / c->heads;
+  if (dh != 16 && dh != 32 && dh != 64) { *why = "d/heads must be 16, 32 or 64"; return false; }
+  if (c->mlp_mult < 1 || c->mlp_mult * c->d > 2048) { *why = "mlp_mult*d must be <= 2048"; return false; }
+  if (c->n_max < 1 || c->n_max > CIDER_MAX_N) { *why = "n_max must be 1..1024"; return false; }
+  return true;
+}
+
+size_t blob_floats(const cider_model_cfg* c) {
+  size_t d = c->d, F = (size_t)c->mlp_mult * c->d;
+  size_t head = 3 * d + (size_t)c->n_max * d + d + 2 * d + 2 * d + d * 2 * d + d + d * d + d;
+  size_t per = 2 * d + 3 * d * d + 3 * d + d * d + d + 2 * d + 3 * d * d + 3 * d + d * d + d + 2 * d +
+               F * d + F + d * F + d;
+  return head + per * c->n_layers + 2 * d;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+struct cider_code {
+  int n = 0, m = 0, nnz = 0, device = 0;
+  int* d_row_ptr = nullptr;
+  int* d_col_idx = nullptr;
+  int* d_var_ptr = nullptr;
+  int* d_var_edge = nullptr;
+  std::vector<int> row_ptr, col_idx;
+};
+
+struct GraphSlot {
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;
+  std::vector<char> key;
+};
+
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+
+struct cider_weights {
+  std::vector<ProfRec> prof_pending;
+  std::map<std::string, std::pair<long, double>> prof_stats;
+  bool prof_on = false;
+  cider_model_cfg cfg{};
+  int device = 0;
+  std::vector<void*> allocs;
+  DevModel dm{};
+  EmbedW ew{};
+  std::mutex mu;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipEvent_t meta_done = nullptr;
+  std::map<std::tuple<int, int, int, int>, int*> sched;
+  GraphSlot graph;
+};
+
+namespace {
+
+// Reveal targets for a bin shape: header [K+1] offsets and [K+1] lengths,
+// then, for the initial pass (j = 0, T steps over K n sites) and for every
+// remask pass over j rows (T_rm = max(1, floor(T j / K)) steps over j n
+// sites), the cumulative number of sites revealed after each step.
+std::vector<int> schedule_table(int K, int n, int T, int kind) {
+  std::vector<int> off(K + 1), len(K + 1), data;
+  for (int j = 0; j <= K; ++j) {
+    int Tp = (j == 0) ? T : std::max(1, (int)((long)T * j / K));
+    long Nm = (long)(j == 0 ? K : j) * n;
+    off[j] = (int)data.size();
+    len[j] = Tp;
+    for (int t = 1; t <= Tp; ++t) {
+      long R;
+      if (kind == CIDER_SCHED_COSINE)
+        R = (long)std::floor(0.5 * (1.0 - std::cos(M_PI * (double)t / (double)Tp)) * (double)Nm);
+      else
+        R = (long)t * Nm / Tp;
+      data.push_back((int)R);
+    }
+  }
+  std::vector<int> out;
+  out.insert(out.end(), off.begin(), off.end());
+  out.insert(out.end(), len.begin(), len.end());
+  out.insert(out.end(), data.begin(), data.end());
+  return out;
+}
+
+int get_sched(cider_weights* w, int K, int n, int T, int kind, int** out) {
+  auto key = std::make_tuple(K, n, T, kind);
+  auto it = w->sched.find(key);
+  if (it != w->sched.end()) { *out = it->second; return CIDER_OK; }
+  std::vector<int> tab = schedule_table(K, n, T, kind);
+  int* d = nullptr;
+  HIPCHK(hipMalloc(&d, tab.size() * sizeof(int)));
+  HIPCHK(hipMemcpy(d, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice));
+  w->sched[key] = d;
+  *out = d;
+  return CIDER_OK;
+}
+
+struct Layout {
+  int num_bins = 0;
+  long total_tokens = 0;
+  int total_slots = 0, total_rows = 0, max_n = 0;
+  size_t off_R, off_E, off_ZE, off_H1, off_QKV, off_O, off_HID, off_lbar, off_logits, off_p, off_S,
+      off_bins, off_state, off_slot, off_row, off_X, total;
+};
+
+size_t esize(int prec) { return prec == CIDER_FP32 ? 4 : 2; }
+
+Layout plan_layout(const cider_model_cfg& cfg, int num_bins, long T, int slots, int rows, int prec) {
+  Layout L;
+  L.num_bins = num_bins;
+  L.total_tokens = T;
+  L.total_slots = slots;
+  L.total_rows = rows;
+  size_t d = cfg.d, F = (size_t)cfg.mlp_mult * cfg.d, es = esize(prec), o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
+  L.off_R = take(T * d * 4);
+  L.off_E = take(T * d * 4);
+  L.off_ZE = take(T * 2 * d * es);
+  L.off_H1 = take(T * d * es);
+  L.off_QKV = take(T * 3 * d * es);
+  L.off_O = take(T * d * es);
+  L.off_HID = take(T * F * es);
+  L.off_lbar = take(T * 2 * 4);
+  L.off_logits = take(T * 2 * 4);
+  L.off_p = take((size_t)slots * 2 * 4);
+  L.off_S = take((size_t)slots * 2 * 4);
+  L.off_bins = take((size_t)num_bins * sizeof(DevBin));
+  L.off_state = take((size_t)num_bins * sizeof(BinState));
+  L.off_slot = take((size_t)slots * 4);
+  L.off_row = take((size_t)rows * 4);
+  L.off_X = take(T);
+  L.total = o;
+  return L;
+}
+
+int ensure_ws(cider_weights* w, const cider_opts& o, size_t need, char** base) {
+  if (o.workspace) {
+    if (o.workspace_bytes < need)
+      return fail(CIDER_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
+    *base = (char*)o.workspace;
+    return CIDER_OK;
+  }
+  if (w->ws_bytes < need) {
+    if (w->ws) {
+      HIPCHK(hipDeviceSynchronize());
+      HIPCHK(hipFree(w->ws));
+      w->ws = nullptr;
+      w->ws_bytes = 0;
+    }
+    size_t want = align_up(need + need / 8, 1 << 20);
+    if (hipMalloc(&w->ws, want) != hipSuccess) return fail(CIDER_ENOMEM, "workspace hipMalloc failed");
+    w->ws_bytes = want;
+  }
+  *base = (char*)w->ws;
+  return CIDER_OK;
+}
+
+int ensure_pinned(cider_weights* w, size_t need) {
+  if (!w->meta_done) HIPCHK(hipEventCreateWithFlags(&w->meta_done, hipEventDisableTiming));
+  HIPCHK(hipEventSynchronize(w->meta_done));
+  if (w->pinned_bytes < need) {
+    if (w->pinned) HIPCHK(hipHostFree(w->pinned));
+    w->pinned = nullptr;
+    size_t want = align_up(need * 2, 1 << 16);
+    HIPCHK(hipHostMalloc(&w->pinned, want, hipHostMallocDefault));
+    w->pinned_bytes = want;
+  }
+  return CIDER_OK;
+}
+
+struct Run {
+  StepCtx ctx{};
+  Work work{};
+  int prec = 0;
+};
+
+// Brackets a launch with events when profiling is on.
+struct Timed {
+  cider_weights* w;
+  hipStream_t s;
+  const char* name;
+  hipEvent_t a = nullptr, b = nullptr;
+  Timed(cider_weights* w_, hipStream_t s_, const char* n_) : w(w_), s(s_), name(n_) {
+    if (w->prof_on) {
+      hipEventCreate(&a);
+      hipEventCreate(&b);
+      hipEventRecord(a, s);
+    }
+  }
+  ~Timed() {
+    if (w->prof_on) {
+      hipEventRecord(b, s);
+      w->prof_pending.push_back(ProfRec{name, a, b});
+    }
+  }
+};
+#define TIMED(name, expr)            \
+  do {                                \
+    Timed t__(w, s, name);            \
+    HIPCHK(expr);                     \
+  } while (0)
+
+// One denoiser forward over every bin of the batch, then Module B.
+int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
+  const DevModel& m = w->dm;
+  const StepCtx& c = r.ctx;
+  const Work& k = r.work;
+  const int prec = r.prec;
+  const long T = c.total_tokens;
+  const int d = m.d, F = m.mlp_mult * m.d;
+  TIMED("embed_demix", launch_embed_demix(c, w->ew, k, prec, s));
+  GemmArgs g{};
+  g.M = T;
+  // gate MLP: H1 = GELU([Z ; e] Wg1^T + bg1); R = g Z + (1 - g) e, g = sigmoid(H1 Wg2^T + bg2)
+  g.N = d; g.Kd = 2 * d; g.A = k.ZE; g.bias = m.bg1; g.out = k.H1;
+  TIMED("gemm_gate1", launch_gemm(prec, kProNone, kEpiGelu, g, m.Wg1, s));
+  g = GemmArgs{}; g.M = T;
+  g.N = d; g.Kd = d; g.A = k.H1; g.bias = m.bg2; g.R = k.R; g.E = k.Ebuf;
+  TIMED("gemm_gate2", launch_gemm(prec, kProNone, kEpiGate, g, m.Wg2, s));
+  for (int l = 0; l < m.n_layers; ++l) {
+    const DevLayer& L = m.layer[l];
+    g = GemmArgs{}; g.M = T;
+    g.N = 3 * d; g.Kd = d; g.A = k.R; g.ln_g = L.ln1_g; g.ln_b = L.ln1_b; g.bias = L.bqkv_r; g.out = k.QKV;
+    TIMED("gemm_qkv_row", launch_gemm(prec, kProLN, kEpiStore, g, L.Wqkv_r, s));
+    TIMED("attn_row", launch_row_attn(c, prec, k.QKV, k.O, d, m.heads, c.max_n, s));
+    g = GemmArgs{}; g.M = T;
+    g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_r; g.R = k.R;
+    TIMED("gemm_o_row", launch_gemm(prec, kProNone, kEpiResid, g, L.Wo_r, s));
+    g = GemmArgs{}; g.M = T;
+    g.N = 3 * d; g.Kd = d; g.A = k.R; g.ln_g = L.ln2_g; g.ln_b = L.ln2_b; g.bias = L.bqkv_u; g.out = k.QKV;
+    TIMED("gemm_qkv_user", launch_gemm(prec, kProLN, kEpiStore, g, L.Wqkv_u, s));
+    TIMED("attn_user", launch_user_attn(c, prec, k.QKV, k.O, d, m.heads, s));
+    g = GemmArgs{}; g.M = T;
+    g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_u; g.R = k.R;
+    TIMED("gemm_o_user", launch_gemm(prec, kProNone, kEpiResid, g, L.Wo_u, s));
+    g = GemmArgs{}; g.M = T;
+    g.N = F; g.Kd = d; g.A = k.R; g.ln_g = L.ln3_g; g.ln_b = L.ln3_b; g.bias = L.b1; g.out = k.HID;
+    TIMED("gemm_mlp_up", launch_gemm(prec, kProLN, kEpiGelu, g, L.W1, s));
+    g = GemmArgs{}; g.M = T;
+    g.N = d; g.Kd = F; g.A = k.HID; g.bias = L.b2; g.R = k.R;
+    TIMED("gemm_mlp_down", launch_gemm(prec, kProNone, kEpiResid, g, L.W2, s));
+  }
+  TIMED("final_proj", launch_final_proj(c, w->ew, k, s));
+  TIMED("module_b", launch_module_b(c, k, s));
+  return CIDER_OK;
+}
+
+int enqueue_step(cider_weights* w, const Run& r, hipStream_t s) {
+  int rc = enqueue_forward(w, r, s);
+  if (rc) return rc;
+  TIMED("step_tail", launch_step_tail(r.ctx, r.work, s));
+  return CIDER_OK;
+}
+
+// Runs `iters` refinement steps, replaying a captured graph when allowed.
+int run_steps(cider_weights* w, const Run& r, int iters, bool use_graph, hipStream_t s) {
+  if (iters <= 0) return CIDER_OK;
+  if (!use_graph || s == nullptr || w->prof_on) {
+    for (int i = 0; i < iters; ++i) {
+      int rc = enqueue_step(w, r, s);
+      if (rc) return rc;
+    }
+    return CIDER_OK;
+  }
+  std::vector<char> key(sizeof(Run) + sizeof(hipStream_t));
+  std::memcpy(key.data(), &r, sizeof(Run));
+  std::memcpy(key.data() + sizeof(Run), &s, sizeof(hipStream_t));
+  GraphSlot& gs = w->graph;
+  if (!gs.exec || gs.key != key) {
+    if (gs.exec) {
+      HIPCHK(hipEventSynchronize(gs.done));
+      HIPCHK(hipGraphExecDestroy(gs.exec));
+      gs.exec = nullptr;
+    }
+    if (!gs.done) HIPCHK(hipEventCreateWithFlags(&gs.done, hipEventDisableTiming));
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    int rc = enqueue_step(w, r, s);
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (rc) { if (graph) hipGraphDestroy(graph); return rc; }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&gs.exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) { gs.exec = nullptr; return hip_fail(e, "hipGraphInstantiate"); }
+    gs.key = key;
+  }
+  for (int i = 0; i < iters; ++i) HIPCHK(hipGraphLaunch(gs.exec, s));
+  HIPCHK(hipEventRecord(gs.done, s));
+  return CIDER_OK;
+}
+
+struct BinIn {
+  const float* y;
+  float sigma2;
+  const cider_code* code;
+  int K, n;
+  uint8_t* out_sym;
+  float* out_logits;
+  uint8_t* out_valid;
+};
+
+int check_opts(const cider_opts& o) {
+  if (o.precision < 0 || o.precision > 2) return fail(CIDER_EINVAL, "precision must be 0..2");
+  if (o.precision == CIDER_FP8) return fail(CIDER_EUNSUPPORTED, "FP8 precision is not available in this build");
+  if (o.schedule != CIDER_SCHED_LINEAR && o.schedule != CIDER_SCHED_COSINE)
+    return fail(CIDER_EINVAL, "unknown schedule");
+  if (o.remask_max_rounds < 0 || o.remask_max_rounds > 16) return fail(CIDER_EINVAL, "remask_max_rounds 0..16");
+  if (!(o.tau > 0.f) || !(o.lam_max > 0.f) || !(o.lam_min > 0.f) || !(o.eta >= 0.f))
+    return fail(CIDER_EINVAL, "tau, lam_max, lam_min must be > 0 and eta >= 0");
+  return CIDER_OK;
+}
+
+int check_bin(const cider_weights* w, const BinIn& b, int steps) {
+  if (!b.y || !b.code || !b.out_sym) return fail(CIDER_EINVAL, "null y, code or out_symbols");
+  if (b.K < 1 || b.K > CIDER_MAX_K) return fail(CIDER_EINVAL, "K must be 1..16");
+  if (b.n < 1 || b.n > std::min(w->cfg.n_max, CIDER_MAX_N)) return fail(CIDER_EINVAL, "n out of range for the model");
+  if (b.code->n != b.n) return fail(CIDER_EINVAL, "code length != n");
+  if (b.code->device != w->device) return fail(CIDER_EINVAL, "code and weights live on different devices");
+  if (!(b.sigma2 > 0.f) || !std::isfinite(b.sigma2)) return fail(CIDER_EINVAL, "sigma2 must be > 0");
+  if (steps < 1 || (long)steps > (long)b.K * b.n) return fail(CIDER_EINVAL, "steps must be 1..K*n");
+  return CIDER_OK;
+}
+
+// Lays out a batch in the workspace and uploads its metadata; fills `r`.
+int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const cider_opts& o,
+            hipStream_t s, Run* r, Layout* Lout, bool init_grids) {
+  const int B = (int)bins.size();
+  long T = 0;
+  int slots = 0, rows = 0, max_n = 0;
+  for (const BinIn& b : bins) {
+    T += (long)b.K * b.n;
+    slots += b.n;
+    rows += b.K;
+    max_n = std::max(max_n, b.n);
+  }
+  Layout L = plan_layout(w->cfg, B, T, slots, rows, o.precision);
+  L.max_n = max_n;
+  char* base = nullptr;
+  int rc = ensure_ws(w, o, L.total, &base);
+  if (rc) return rc;
+  size_t meta = B * sizeof(DevBin) + (size_t)(slots + rows) * 4;
+  rc = ensure_pinned(w, meta);
+  if (rc) return rc;
+  DevBin* hb = (DevBin*)w->pinned;
+  int* hslot = (int*)((char*)w->pinned + B * sizeof(DevBin));
+  int* hrow = hslot + slots;
+  long tok = 0;
+  int so = 0, ro = 0;
+  for (int i = 0; i < B; ++i) {
+    const BinIn& b = bins[i];
+    int* sched = nullptr;
+    rc = get_sched(w, b.K, b.n, steps, o.schedule, &sched);
+    if (rc) return rc;
+    DevBin db{};
+    db.tok_off = (int)tok;
+    db.K = b.K; db.n = b.n; db.m = b.code->m;
+    db.slot_off = so; db.row_off = ro;
+    db.row_ptr = b.code->d_row_ptr; db.col_idx = b.code->d_col_idx;
+    db.var_ptr = b.code->d_var_ptr; db.var_edge = b.code->d_var_edge;
+    db.sched = sched;
+    db.y = b.y; db.sigma2 = b.sigma2;
+    db.X = (uint8_t*)(base + L.off_X) + tok;
+    db.out_sym = b.out_sym; db.out_logits = b.out_logits; db.out_valid = b.out_valid;
+    db.st = (BinState*)(base + L.off_state) + i;
+    hb[i] = db;
+    for (int l = 0; l < b.n; ++l) hslot[so + l] = i;
+    for (int k = 0; k < b.K; ++k) hrow[ro + k] = i;
+    tok += (long)b.K * b.n;
+    so += b.n;
+    ro += b.K;
+  }
+  if (T > (long)INT32_MAX) return fail(CIDER_EINVAL, "batch too large");
+  HIPCHK(hipMemcpyAsync(base + L.off_bins, hb, B * sizeof(DevBin), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(base + L.off_slot, hslot, (size_t)slots * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(base + L.off_row, hrow, (size_t)rows * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hipEventRecord(w->meta_done, s));
+
+  StepCtx& c = r->ctx;
+  c = StepCtx{};
+  c.num_bins = B;
+  c.bins = (const DevBin*)(base + L.off_bins);
+  c.slot_bin = (const int*)(base + L.off_slot);
+  c.row_bin = (const int*)(base + L.off_row);
+  c.total_slots = slots;
+  c.total_rows = rows;
+  c.total_tokens = T;
+  c.max_n = max_n;
+  c.schedule = o.schedule;
+  c.remask = o.remask;
+  c.max_rounds = o.remask_max_rounds;
+  c.final_argmax = o.final_argmax;
+  c.remask_thr = o.remask_thr;
+  c.tau = o.tau;
+  c.eta = o.eta;
+  c.lam_max = o.lam_max;
+  c.lam_min = o.lam_min;
+  c.gamma_override = -1.f;
+  c.reveal_override = -1;
+  c.first_override = 0;
+  Work& k = r->work;
+  k.R = (float*)(base + L.off_R);
+  k.Ebuf = (float*)(base + L.off_E);
+  k.ZE = base + L.off_ZE;
+  k.H1 = base + L.off_H1;
+  k.QKV = base + L.off_QKV;
+  k.O = base + L.off_O;
+  k.HID = base + L.off_HID;
+  k.ascale = nullptr;
+  k.lbar = (float*)(base + L.off_lbar);
+  k.logits = (float*)(base + L.off_logits);
+  k.p = (float*)(base + L.off_p);
+  k.S = (float*)(base + L.off_S);
+  r->prec = o.precision;
+  if (init_grids) {
+    HIPCHK(launch_evidence(c, k.S, k.p, s));
+    HIPCHK(launch_init_bins(c, steps, o.first_reveal, s));
+  }
+  *Lout = L;
+  return CIDER_OK;
+}
+
+int decode_impl(cider_weights* w, const std::vector<BinIn>& bins, int steps, const cider_opts& o,
+                hipStream_t s) {
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if (bins.empty()) return CIDER_OK;
+  for (const BinIn& b : bins) {
+    rc = check_bin(w, b, steps);
+    if (rc) return rc;
+  }
+  std::lock_guard<std::mutex> lock(w->mu);
+  HIPCHK(hipSetDevice(w->device));
+  w->prof_on = o.profile != 0;
+  Run r;
+  Layout L;
+  rc = prepare(w, bins, steps, o, s, &r, &L, true);
+  if (rc) return rc;
+  const bool graph = o.use_graph != 0;
+  // initial pass: steps reveal steps + the final pass
+  rc = run_steps(w, r, steps + 1, graph, s);
+  if (rc) return rc;
+  if (o.remask && o.remask_max_rounds > 0) {
+    const BinState* dst = (const BinState*)((const char*)r.ctx.bins - L.off_bins + L.off_state);
+    std::vector<BinState> hst(bins.size());
+    for (int round = 0; round < o.remask_max_rounds; ++round) {
+      HIPCHK(hipMemcpyAsync(hst.data(), dst, hst.size() * sizeof(BinState), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      bool busy = false;
+      for (const BinState& st : hst) busy |= st.phase != kDone;
+      if (!busy) break;
+      // a remask pass has at most `steps` reveal steps, then its final pass
+      rc = run_steps(w, r, steps + 1, graph, s);
+      if (rc) return rc;
+    }
+  }
+  return CIDER_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+void cider_opts_default(cider_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = CIDER_BF16;
+  o->schedule = CIDER_SCHED_LINEAR;
+  o->first_reveal = 1;
+  o->remask = 0;
+  o->remask_max_rounds = 2;
+  o->final_argmax = 0;
+  o->use_graph = 1;
+  o->remask_thr = 0.9f;
+  o->tau = 1.0f;
+  o->eta = 1.0f;
+  o->lam_max = 20.0f;
+  o->lam_min = 1e-6f;
+  o->profile = 0;
+  o->workspace = nullptr;
+  o->workspace_bytes = 0;
+}
+
+const char* cider_strerror(int st) {
+  switch (st) {
+    case CIDER_OK: return "ok";
+    case CIDER_EINVAL: return "invalid argument";
+    case CIDER_ENOMEM: return "out of memory";
+    case CIDER_EDEVICE: return "HIP device error";
+    case CIDER_EUNSUPPORTED: return "unsupported";
+    case CIDER_EAGAIN: return "try again";
+    default: return "unknown status";
+  }
+}
+
+const char* cider_last_error(void) { return g_err.c_str(); }
+
+size_t cider_weights_blob_floats(const cider_model_cfg* cfg) {
+  std::string why;
+  if (!cfg_ok(cfg, &why)) return 0;
+  return blob_floats(cfg);
+}
+
+int cider_weights_create(const cider_model_cfg* cfg, const float* blob, size_t n_floats, cider_weights** out) {
+  std::string why;
+  if (!out) return fail(CIDER_EINVAL, "null out");
+  *out = nullptr;
+  if (!cfg_ok(cfg, &why)) return fail(CIDER_EINVAL, why);
+  if (!blob || n_floats != blob_floats(cfg)) return fail(CIDER_EINVAL, "blob size does not match cfg");
+  for (size_t i = 0; i < n_floats; ++i)
+    if (!std::isfinite(blob[i])) return fail(CIDER_EINVAL, "blob holds a non-finite value");
+  cider_weights* w = new cider_weights();
+  w->cfg = *cfg;
+  HIPCHK(hipGetDevice(&w->device));
+  float* dblob = nullptr;
+  if (hipMalloc(&dblob, n_floats * 4) != hipSuccess) { delete w; return fail(CIDER_ENOMEM, "weights hipMalloc"); }
+  w->allocs.push_back(dblob);
+  HIPCHK(hipMemcpy(dblob, blob, n_floats * 4, hipMemcpyHostToDevice));
+  const int d = cfg->d, F = cfg->mlp_mult * cfg->d;
+  size_t off = 0;
+  auto vec = [&](size_t cnt) { const float* p = dblob + off; off += cnt; return p; };
+  auto mat = [&](int rows, int cols, Mat* M) -> int {
+    size_t cnt = (size_t)rows * cols;
+    M->f32 = dblob + off;
+    M->rows = rows;
+    M->cols = cols;
+    std::vector<uint16_t> hb(cnt);
+    for (size_t i = 0; i < cnt; ++i) hb[i] = f32_to_bf16_bits(blob[off + i]);
+    void* db = nullptr;
+    if (hipMalloc(&db, cnt * 2) != hipSuccess) return fail(CIDER_ENOMEM, "weights hipMalloc");
+    w->allocs.push_back(db);
+    HIPCHK(hipMemcpy(db, hb.data(), cnt * 2, hipMemcpyHostToDevice));
+    M->b16 = (const bf16*)db;
+    off += cnt;
+    return CIDER_OK;
+  };
+  DevModel& m = w->dm;
+  m.n_layers = cfg->n_layers; m.d = d; m.heads = cfg->heads; m.mlp_mult = cfg->mlp_mult; m.n_max = cfg->n_max;
+  int rc = 0;
+  m.E = vec(3 * (size_t)d);
+  m.P = vec((size_t)cfg->n_max * d);
+  m.u = vec(d);
+  m.W = vec(2 * (size_t)d);
+  m.v = vec(2 * (size_t)d);
+  if ((rc = mat(d, 2 * d, &m.Wg1))) goto bad;
+  m.bg1 = vec(d);
+  if ((rc = mat(d, d, &m.Wg2))) goto bad;
+  m.bg2 = vec(d);
+  for (int l = 0; l < cfg->n_layers; ++l) {
+    DevLayer& L = m.layer[l];
+    L.ln1_g = vec(d); L.ln1_b = vec(d);
+    if ((rc = mat(3 * d, d, &L.Wqkv_r))) goto bad;
+    L.bqkv_r = vec(3 * (size_t)d);
+    if ((rc = mat(d, d, &L.Wo_r))) goto bad;
+    L.bo_r = vec(d);
+    L.ln2_g = vec(d); L.ln2_b = vec(d);
+    if ((rc = mat(3 * d, d, &L.Wqkv_u))) goto bad;
+    L.bqkv_u = vec(3 * (size_t)d);
+    if ((rc = mat(d, d, &L.Wo_u))) goto bad;
+    L.bo_u = vec(d);
+    L.ln3_g = vec(d); L.ln3_b = vec(d);
+    if ((rc = mat(F, d, &L.W1))) goto bad;
+    L.b1 = vec(F);
+    if ((rc = mat(d, F, &L.W2))) goto bad;
+    L.b2 = vec(d);
+  }
+  m.lnf_g = vec(d);
+  m.lnf_b = vec(d);
+  if (off != n_floats) { rc = fail(CIDER_EINVAL, "internal layout mismatch"); goto bad; }
+  w->ew = EmbedW{d, m.E, m.P, m.u, m.W, m.v, m.lnf_g, m.lnf_b};
+  *out = w;
+  return CIDER_OK;
+bad:
+  for (void* p : w->allocs) hipFree(p);
+  delete w;
+  return rc;
+}
+
+void cider_weights_destroy(cider_weights* w) {
+  if (!w) return;
+  hipSetDevice(w->device);
+  hipDeviceSynchronize();
+  if (w->graph.exec) hipGraphExecDestroy(w->graph.exec);
+  if (w->graph.done) hipEventDestroy(w->graph.done);
+  if (w->meta_done) hipEventDestroy(w->meta_done);
+  for (auto& kv : w->sched) hipFree(kv.second);
+  for (void* p : w->allocs) hipFree(p);
+  if (w->ws) hipFree(w->ws);
+  if (w->pinned) hipHostFree(w->pinned);
+  delete w;
+}
+
+int cider_code_create(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* col_idx, cider_code** out) {
+  if (!out) return fail(CIDER_EINVAL, "null out");
+  *out = nullptr;
+  if (n < 1 || n > CIDER_MAX_N || m < 1 || m > 4 * CIDER_MAX_N || !row_ptr || !col_idx)
+    return fail(CIDER_EINVAL, "bad code sizes or null arrays");
+  if (row_ptr[0] != 0) return fail(CIDER_EINVAL, "row_ptr[0] must be 0");
+  for (int j = 0; j < m; ++j) {
+    int deg = row_ptr[j + 1] - row_ptr[j];
+    if (deg < 1 || deg > kMaxDeg) return fail(CIDER_EINVAL, "check degree must be 1..32");
+  }
+  const int nnz = row_ptr[m];
+  if (nnz > 4096) return fail(CIDER_EINVAL, "at most 4096 edges");
+  std::vector<int> vdeg(n, 0);
+  for (int j = 0; j < m; ++j)
+    for (int e = row_ptr[j]; e < row_ptr[j + 1]; ++e) {
+      int v = col_idx[e];
+      if (v < 0 || v >= n) return fail(CIDER_EINVAL, "column index out of range");
+      if (e > row_ptr[j] && col_idx[e - 1] >= v) return fail(CIDER_EINVAL, "columns must ascend within a row");
+      if (++vdeg[v] > kMaxDeg) return fail(CIDER_EINVAL, "slot degree must be <= 32");
+    }
+  std::vector<int> var_ptr(n + 1, 0), var_edge(nnz);
+  for (int v = 0; v < n; ++v) var_ptr[v + 1] = var_ptr[v] + vdeg[v];
+  std::vector<int> fill(var_ptr.begin(), var_ptr.end() - 1);
+  for (int j = 0; j < m; ++j)
+    for (int e = row_ptr[j]; e < row_ptr[j + 1]; ++e) var_edge[fill[col_idx[e]]++] = e;  // ascending j
+  cider_code* c = new cider_code();
+  c->n = n; c->m = m; c->nnz = nnz;
+  c->row_ptr.assign(row_ptr, row_ptr + m + 1);
+  c->col_idx.assign(col_idx, col_idx + nnz);
+  hipError_t e = hipGetDevice(&c->device);
+  if (e == hipSuccess) e = hipMalloc(&c->d_row_ptr, (m + 1) * 4);
+  if (e == hipSuccess) e = hipMalloc(&c->d_col_idx, nnz * 4);
+  if (e == hipSuccess) e = hipMalloc(&c->d_var_ptr, (n + 1) * 4);
+  if (e == hipSuccess) e = hipMalloc(&c->d_var_edge, nnz * 4);
+  if (e == hipSuccess) e = hipMemcpy(c->d_row_ptr, row_ptr, (m + 1) * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->d_col_idx, col_idx, nnz * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->d_var_ptr, var_ptr.data(), (n + 1) * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->d_var_edge, var_edge.data(), nnz * 4, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    cider_code_destroy(c);
+    return hip_fail(e, "cider_code_create");
+  }
+  *out = c;
+  return CIDER_OK;
+}
+
+void cider_code_destroy(cider_code* c) {
+  if (!c) return;
+  hipFree(c->d_row_ptr);
+  hipFree(c->d_col_idx);
+  hipFree(c->d_var_ptr);
+  hipFree(c->d_var_edge);
+  delete c;
+}
+
+int cider_workspace_size(const cider_weights* w, int32_t num_bins, int64_t total_tokens, int64_t total_slots,
+                         const cider_opts* opts, size_t* bytes) {
+  if (!w || !bytes || num_bins < 0 || total_tokens < 0 || total_slots < 0) return fail(CIDER_EINVAL, "bad args");
+  cider_opts o;
+  if (opts) o = *opts; else cider_opts_default(&o);
+  long rows_bound = (long)num_bins * CIDER_MAX_K;
+  if (total_tokens < rows_bound) rows_bound = total_tokens;
+  Layout L = plan_layout(w->cfg, num_bins, total_tokens, (int)total_slots, (int)rows_bound, o.precision);
+  *bytes = L.total;
+  return CIDER_OK;
+}
+
+int cider_decode(const float* y, float sigma2, const cider_code* code, int32_t K, int32_t n, const cider_weights* w,
+                 int32_t steps, uint8_t* out_symbols, const cider_opts* opts, void* stream) {
+  if (!w) return fail(CIDER_EINVAL, "null weights");
+  cider_opts o;
+  if (opts) o = *opts; else cider_opts_default(&o);
+  std::vector<BinIn> bins{BinIn{y, sigma2, code, K, n, out_symbols, nullptr, nullptr}};
+  return decode_impl(const_cast<cider_weights*>(w), bins, steps, o, (hipStream_t)stream);
+}
+
+int cider_decode_batch(int32_t num_bins, const cider_bin* bins, const cider_weights* w, int32_t steps,
+                       const cider_opts* opts, void* stream) {
+  if (!w) return fail(CIDER_EINVAL, "null weights");
+  if (num_bins < 0 || (num_bins > 0 && !bins)) return fail(CIDER_EINVAL, "bad bin list");
+  cider_opts o;
+  if (opts) o = *opts; else cider_opts_default(&o);
+  std::vector<BinIn> v;
+  v.reserve(num_bins);
+  for (int i = 0; i < num_bins; ++i)
+    v.push_back(BinIn{bins[i].y, bins[i].sigma2, bins[i].code, bins[i].K, bins[i].n, bins[i].out_symbols,
+                      bins[i].out_logits, bins[i].out_row_valid});
+  return decode_impl(const_cast<cider_weights*>(w), v, steps, o, (hipStream_t)stream);
+}
+
+int cider_step_debug(const uint8_t* X_in, uint8_t* X_out, const float* y, float sigma2, const cider_code* code,
+                     int32_t K, int32_t n, const cider_weights* wc, float gamma, int32_t reveal_count, int32_t first,
+                     const cider_opts* opts, float* out_lbar, float* out_logits, float* out_z, void* stream) {
+  if (!wc || !X_in) return fail(CIDER_EINVAL, "null weights or X_in");
+  cider_weights* w = const_cast<cider_weights*>(wc);
+  cider_opts o;
+  if (opts) o = *opts; else cider_opts_default(&o);
+  int rc = check_opts(o);
+  if (rc) return rc;
+  uint8_t dummy = 0;
+  BinIn b{y, sigma2, code, K, n, &dummy, nullptr, nullptr};
+  rc = check_bin(w, b, 1);
+  if (rc) return rc;
+  if (reveal_count < 0 || reveal_count > K * n) return fail(CIDER_EINVAL, "reveal_count out of range");
+  if (!(gamma >= 0.f && gamma <= 1.f)) return fail(CIDER_EINVAL, "gamma must be in [0, 1]");
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(w->mu);
+  HIPCHK(hipSetDevice(w->device));
+  Run r;
+  Layout L;
+  std::vector<BinIn> bins{b};
+  rc = prepare(w, bins, 1, o, s, &r, &L, true);
+  if (rc) return rc;
+  char* base = (char*)r.ctx.bins - L.off_bins;
+  uint8_t* Xw = (uint8_t*)(base + L.off_X);
+  HIPCHK(hipMemcpyAsync(Xw, X_in, (size_t)K * n, hipMemcpyDeviceToDevice, s));
+  r.ctx.gamma_override = gamma;
+  r.ctx.reveal_override = reveal_count;
+  r.ctx.first_override = first ? 1 : 0;
+  rc = enqueue_forward(w, r, s);
+  if (rc) return rc;
+  const size_t T = (size_t)K * n;
+  if (out_lbar) HIPCHK(hipMemcpyAsync(out_lbar, r.work.lbar, T * 8, hipMemcpyDeviceToDevice, s));
+  if (out_logits) HIPCHK(hipMemcpyAsync(out_logits, r.work.logits, T * 8, hipMemcpyDeviceToDevice, s));
+  if (out_z) HIPCHK(hipMemcpyAsync(out_z, r.work.R, T * w->cfg.d * 4, hipMemcpyDeviceToDevice, s));
+  if (X_out) {
+    HIPCHK(launch_step_tail(r.ctx, r.work, s));
+    HIPCHK(hipMemcpyAsync(X_out, Xw, T, hipMemcpyDeviceToDevice, s));
+  }
+  return CIDER_OK;
+}
+
+int cider_evidence(const float* y, float sigma2, int32_t K, int32_t n, float* out_S, float* out_p, void* stream) {
+  if (!y || K < 1 || K > CIDER_MAX_K || n < 1 || n > CIDER_MAX_N || !(sigma2 > 0.f))
+    return fail(CIDER_EINVAL, "bad evidence arguments");
+  hipStream_t s = (hipStream_t)stream;
+  DevBin hb{};
+  hb.K = K; hb.n = n; hb.y = y; hb.sigma2 = sigma2;
+  std::vector<int> slot(n, 0);
+  DevBin* db = nullptr;
+  int* ds = nullptr;
+  HIPCHK(hipMalloc(&db, sizeof(DevBin)));
+  hipError_t e = hipMalloc(&ds, n * 4);
+  if (e == hipSuccess) e = hipMemcpy(db, &hb, sizeof(DevBin), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ds, slot.data(), n * 4, hipMemcpyHostToDevice);
+  StepCtx c{};
+  c.num_bins = 1; c.bins = db; c.slot_bin = ds; c.total_slots = n;
+  if (e == hipSuccess) e = launch_evidence(c, out_S, out_p, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFree(db);
+  hipFree(ds);
+  if (e != hipSuccess) return hip_fail(e, "cider_evidence");
+  return CIDER_OK;
+}
+
+int cider_profile_read(const cider_weights* wc, cider_kernel_stat* out, int32_t max, int32_t* n_out,
+                       int32_t reset) {
+  if (!wc || !n_out || max < 0 || (max > 0 && !out)) return fail(CIDER_EINVAL, "bad profile arguments");
+  cider_weights* w = const_cast<cider_weights*>(wc);
+  std::lock_guard<std::mutex> lock(w->mu);
+  HIPCHK(hipSetDevice(w->device));
+  for (ProfRec& p : w->prof_pending) {
+    float ms = 0.f;
+    HIPCHK(hipEventSynchronize(p.b));
+    HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+    auto& st = w->prof_stats[p.name];
+    st.first += 1;
+    st.second += ms;
+    hipEventDestroy(p.a);
+    hipEventDestroy(p.b);
+  }
+  w->prof_pending.clear();
+  int i = 0;
+  for (auto& kv : w->prof_stats) {
+    if (i >= max) break;
+    std::memset(out[i].name, 0, sizeof(out[i].name));
+    std::strncpy(out[i].name, kv.first.c_str(), sizeof(out[i].name) - 1);
+    out[i].launches = kv.second.first;
+    out[i].total_ms = kv.second.second;
+    ++i;
+  }
+  *n_out = i;
+  if (reset) w->prof_stats.clear();
+  return CIDER_OK;
+}
+
+struct cider_server {};
+int cider_server_create(const cider_server_cfg*, cider_server** out) {
+  if (out) *out = nullptr;
+  return fail(CIDER_EUNSUPPORTED, "server not built");
+}
+int cider_server_submit(cider_server*, const float*, float, const cider_code*, int32_t, int32_t, uint8_t*, uint64_t*) {
+  return fail(CIDER_EUNSUPPORTED, "server not built");
+}
+int cider_server_poll(cider_server*, cider_result*, int32_t, int32_t* n) {
+  if (n) *n = 0;
+  return fail(CIDER_EUNSUPPORTED, "server not built");
+}
+int cider_server_drain(cider_server*) { return fail(CIDER_EUNSUPPORTED, "server not built"); }
+void cider_server_destroy(cider_server*) {}
+
+}  // extern "C"

@@ -1,0 +1,56 @@
+"""CPU checks of the C ABI: the library loads, exports every function the
+header declares, and rejects bad arguments before touching a device."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "cider.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cider_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2605_26580_amd as P
+    L = P.abi.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(P.abi.EXPORTS) == names
+
+
+def test_opts_defaults():
+    import paper_2605_26580_amd as P
+    o = P.cider_opts_default()
+    assert o.precision == P.CIDER_BF16 and o.schedule == P.CIDER_SCHED_LINEAR and o.first_reveal == 1
+    assert o.remask == 0 and o.remask_max_rounds == 2 and abs(o.remask_thr - 0.9) < 1e-7
+    assert o.tau == 1.0 and o.eta == 1.0 and o.lam_max == 20.0 and abs(o.lam_min - 1e-6) < 1e-12
+
+
+@pytest.mark.parametrize("L,d,h", [(2, 64, 4), (4, 128, 8), (6, 256, 8), (8, 384, 12)])
+def test_blob_size_agrees_with_generator(L, d, h):
+    import paper_2605_26580_amd as P
+    cfg = synth.ModelCfg(L, d, h)
+    assert P.cider_weights_blob_floats(P.make_cfg(L, d, h)) == synth.weights.blob_size(cfg)
+
+
+def test_bad_model_and_code_rejected_on_cpu():
+    import paper_2605_26580_amd as P
+    assert P.cider_weights_blob_floats(P.make_cfg(2, 96, 4)) == 0          # d not a multiple of 64
+    with pytest.raises(P.CiderError) as e:
+        P.Weights(P.make_cfg(2, 64, 5), np.zeros(10, np.float32))
+    assert e.value.status == P.abi.CIDER_EINVAL
+    with pytest.raises(P.CiderError):
+        P.Code(8, 2, np.array([0, 3, 9]), np.array([0, 1, 2, 3, 4, 5, 6, 7, 9]))   # index out of range
+    with pytest.raises(P.CiderError):
+        P.Code(8, 1, np.array([0, 3]), np.array([2, 1, 3]))                      # not ascending
+    assert "invalid" in P.cider_strerror(P.abi.CIDER_EINVAL)
+

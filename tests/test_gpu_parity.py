@@ -1,0 +1,262 @@
+"""GPU parity of the HIP library against the FP64 oracle, through the C ABI.
+
+Teacher-forced steps compare logits and residuals within the stated
+tolerance (FP32 1e-5, BF16 2e-2, relative to max(1, |oracle|)) on grids the
+test chooses; free-running decodes compare the decoded grids exactly on every
+bin whose decisions the oracle takes with a safe margin, and report the rest.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle.decode import DecodeOpts, decode_bin
+from oracle.denoiser import denoise
+from oracle.evidence import evidence
+from oracle.schedule import reveal as oracle_reveal
+
+from gpu_common import (TOL, code_handle, code_of, lib, prec_id, rel_err, say, torch_cuda,
+                        valid_selection, weights_handle)
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a, dtype=None):
+    torch = torch_cuda()
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+@pytest.mark.parametrize("K,n", [(1, 32), (2, 32), (4, 96), (16, 64), (3, 1024)])
+def test_evidence_matches_oracle(K, n):
+    torch = torch_cuda()
+    P = lib()
+    code = code_of(n, 1000 + n)
+    bins = synth.make_bins(code, K, 1, 3.0, seed=K * 100 + n)
+    say(f"evidence K={K} n={n}")
+    y = _dev(bins.y[0])
+    S = torch.zeros(n, 2, dtype=torch.float32, device="cuda")
+    p = torch.zeros(n, 2, dtype=torch.float32, device="cuda")
+    P.cider_evidence(y, float(bins.sigma2[0]), K, n, S, p)
+    torch.cuda.synchronize()
+    S_ref, p_ref = evidence(bins.y[0].astype(np.float64), float(bins.sigma2[0]), K)
+    assert rel_err(S.cpu().numpy(), S_ref) < 1e-6
+    assert np.max(np.abs(p.cpu().numpy() - p_ref)) < 1e-6
+
+
+CASES = [
+    # K, n, L, d, heads
+    (2, 32, 2, 64, 4),
+    (1, 32, 1, 64, 4),
+    (3, 96, 2, 64, 4),
+    (5, 64, 2, 128, 4),
+    (4, 128, 2, 128, 8),
+    (2, 256, 1, 256, 8),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("K,n,L,d,h", CASES)
+def test_teacher_forced_step(prec, K, n, L, d, h):
+    torch = torch_cuda()
+    P = lib()
+    cfg = synth.ModelCfg(L, d, h, n_max=max(n, 64))
+    wh, w = weights_handle(cfg, seed=21 + L + d, bias_std=0.02, ln_std=0.05)
+    code = code_of(n, 1000 + n)
+    ch = code_handle(code)
+    bins = synth.make_bins(code, K, 1, 4.0, seed=5 + K)
+    y, s2 = bins.y[0], float(bins.sigma2[0])
+    _, p = evidence(y.astype(np.float64), s2, K)
+    rng = np.random.default_rng(K * 7 + n)
+    opts = P.cider_opts_default(precision=prec_id(prec))
+    tol = TOL[prec]
+    for frac in (1.0, 0.6, 0.1, 0.0):
+        X = rng.integers(0, 2, size=(K, n)).astype(np.uint8)
+        X[rng.random((K, n)) < frac] = 2
+        gamma = float((X == 2).mean())
+        ref = denoise(X, p, code, w, L, h, gamma)
+        say(f"teacher-forced {prec} K={K} n={n} L={L} d={d} h={h} mask={frac}")
+        lbar = torch.zeros(K, n, 2, dtype=torch.float32, device="cuda")
+        logits = torch.zeros_like(lbar)
+        z = torch.zeros(K, n, d, dtype=torch.float32, device="cuda")
+        Xo = torch.zeros(K, n, dtype=torch.uint8, device="cuda")
+        r = max(1, int((X == 2).sum()) // 3)
+        first = 1 if frac == 1.0 else 0
+        P.cider_step_debug(_dev(X), Xo, _dev(y), s2, ch, K, n, wh, gamma, r, first, opts,
+                           out_lbar=lbar, out_logits=logits, out_z=z)
+        torch.cuda.synchronize()
+        e_lbar = rel_err(lbar.cpu().numpy(), ref["lbar"])
+        e_log = rel_err(logits.cpu().numpy(), ref["logits"])
+        e_z = rel_err(z.cpu().numpy(), ref["z"])
+        print(f"  err lbar={e_lbar:.2e} logits={e_log:.2e} z={e_z:.2e}")
+        assert e_lbar <= tol and e_log <= tol, (e_lbar, e_log)
+        assert e_z <= (tol if prec == "fp32" else 5e-2)
+        if (X == 2).any():
+            valid_selection(X, Xo.cpu().numpy(), ref["logits"], r, first, slack=2 * tol)
+            Xr = X.copy()
+            oracle_reveal(Xr, ref["logits"], r, bool(first))
+            if prec == "fp32":
+                # with well separated margins the selection is exact
+                c = np.abs(ref["logits"][..., 0] - ref["logits"][..., 1])
+                srt = np.sort(c[X == 2])[::-1]
+                if len(srt) > r and srt[r - 1] - srt[r] > 1e-4 and not first:
+                    assert np.array_equal(Xo.cpu().numpy(), Xr)
+
+
+def _decode_gpu(wl_K, code, ch, wh, bins, T, opts, with_logits=False):
+    torch = torch_cuda()
+    P = lib()
+    B = bins.y.shape[0]
+    n = code.n
+    out = torch.full((B, wl_K, n), 9, dtype=torch.uint8, device="cuda")
+    lg = torch.zeros(B, wl_K, n, 2, dtype=torch.float32, device="cuda") if with_logits else None
+    valid = torch.zeros(B, wl_K, dtype=torch.uint8, device="cuda")
+    y = _dev(bins.y)
+    lst = []
+    for b in range(B):
+        lst.append({"y": y[b], "sigma2": float(bins.sigma2[b]), "code": ch, "K": wl_K, "n": n,
+                    "out_symbols": out[b], "out_logits": lg[b] if lg is not None else None,
+                    "out_row_valid": valid[b]})
+    P.cider_decode_batch(lst, wh, T, opts)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), (lg.cpu().numpy() if lg is not None else None), valid.cpu().numpy()
+
+
+def _free_running(prec, K, n, L, d, h, T, B, remask=False, schedule="linear", final_argmax=False, min_gap=2e-5):
+    P = lib()
+    cfg = synth.ModelCfg(L, d, h, n_max=max(n, 64))
+    wh, w = weights_handle(cfg, seed=31 + d, bias_std=0.0)
+    code = code_of(n, 1000 + n)
+    ch = code_handle(code)
+    bins = synth.make_bins(code, K, B, [2.0, 4.0, 6.0], seed=77 + K + n)
+    sched = P.CIDER_SCHED_COSINE if schedule == "cosine" else P.CIDER_SCHED_LINEAR
+    opts = P.cider_opts_default(precision=prec_id(prec), remask=int(remask), schedule=sched,
+                                final_argmax=int(final_argmax))
+    say(f"free-running {prec} K={K} n={n} L={L} d={d} T={T} B={B} remask={remask} sched={schedule}")
+    Xg, lg, valid = _decode_gpu(K, code, ch, wh, bins, T, opts, with_logits=True)
+    oo = DecodeOpts(remask=remask, schedule=schedule, final_argmax=final_argmax)
+    safe = match = 0
+    for b in range(B):
+        res = decode_bin(bins.y[b], float(bins.sigma2[b]), code, K, w, L, h, T, oo)
+        same = np.array_equal(Xg[b], res.X)
+        ok_gap = all(s_gap > min_gap or s_gap == 0.0 for s_gap in _gaps(res))
+        if ok_gap:
+            safe += 1
+            assert same, f"bin {b}: decidable bin decoded differently"
+            assert np.array_equal(valid[b], res.row_valid)
+        match += same
+    print(f"  exact grid match {match}/{B}, decidable {safe}/{B}")
+    return match, safe, B
+
+
+def _gaps(res):
+    out = []
+    for s in res.steps:
+        out += [g for g in s["gaps"].values()]
+    out += [f["gap_q"] for f in res.finals]
+    return out
+
+
+def test_free_running_fp32_small():
+    match, safe, B = _free_running("fp32", 2, 32, 2, 64, 4, 8, 16)
+    assert safe >= B // 2
+
+
+def test_free_running_fp32_ragged_tail():
+    match, safe, B = _free_running("fp32", 3, 96, 2, 64, 4, 12, 8)
+    assert safe >= B // 2
+
+
+def test_free_running_fp32_remask():
+    match, safe, B = _free_running("fp32", 4, 32, 2, 64, 4, 8, 8, remask=True)
+    assert safe >= B // 2
+
+
+def test_free_running_fp32_cosine_final_argmax():
+    match, safe, B = _free_running("fp32", 2, 32, 2, 64, 4, 12, 8, schedule="cosine", final_argmax=True)
+    # the cosine schedule reveals one site at step 1, so more cut gaps are near ties
+    assert safe >= 2 and match >= B // 2
+
+
+def test_free_running_bf16_reports_match():
+    match, safe, B = _free_running("bf16", 2, 32, 2, 64, 4, 8, 16, min_gap=0.1)
+    assert match >= 1
+
+
+def test_single_step_and_one_site_per_step():
+    for T in (1, 64):
+        match, safe, B = _free_running("fp32", 2, 32, 1, 64, 4, T, 4)
+        assert safe >= 1
+
+
+def test_batch_equals_alone_and_graph_equals_eager():
+    """Mixed K and n in one batch give bit-identical results to each bin decoded
+    alone, with and without graph replay."""
+    torch = torch_cuda()
+    P = lib()
+    cfg = synth.ModelCfg(2, 64, 4, n_max=128)
+    wh, _ = weights_handle(cfg, seed=41)
+    shapes = [(2, 32), (5, 64), (1, 128), (3, 32), (8, 64)]
+    items = []
+    for i, (K, n) in enumerate(shapes):
+        code = code_of(n, 1000 + n)
+        b = synth.make_bins(code, K, 1, 3.0 + i, seed=500 + i)
+        items.append((K, n, code_handle(code), _dev(b.y[0]), float(b.sigma2[0])))
+    for prec in ("fp32", "bf16"):
+        for graph in (1, 0):
+            opts = P.cider_opts_default(precision=prec_id(prec), use_graph=graph, remask=1)
+            say(f"batch vs alone {prec} graph={graph}")
+            outs = [torch.zeros(K, n, dtype=torch.uint8, device="cuda") for K, n, *_ in items]
+            lgs = [torch.zeros(K, n, 2, dtype=torch.float32, device="cuda") for K, n, *_ in items]
+            P.cider_decode_batch([{"y": y, "sigma2": s2, "code": ch, "K": K, "n": n, "out_symbols": o,
+                                   "out_logits": lg} for (K, n, ch, y, s2), o, lg in zip(items, outs, lgs)],
+                                 wh, 8, opts)
+            torch.cuda.synchronize()
+            for (K, n, ch, y, s2), o, lg in zip(items, outs, lgs):
+                alone = torch.zeros(K, n, dtype=torch.uint8, device="cuda")
+                lga = torch.zeros(K, n, 2, dtype=torch.float32, device="cuda")
+                P.cider_decode_batch([{"y": y, "sigma2": s2, "code": ch, "K": K, "n": n, "out_symbols": alone,
+                                       "out_logits": lga}], wh, 8, opts)
+                torch.cuda.synchronize()
+                assert torch.equal(alone, o)
+                assert torch.equal(lga, lg)
+
+
+def test_decode_single_entry_matches_batch():
+    torch = torch_cuda()
+    P = lib()
+    cfg = synth.ModelCfg(2, 64, 4, n_max=64)
+    wh, _ = weights_handle(cfg, seed=41)
+    code = code_of(32, 1032)
+    ch = code_handle(code)
+    b = synth.make_bins(code, 2, 1, 4.0, seed=3)
+    y = _dev(b.y[0])
+    opts = P.cider_opts_default(precision=P.CIDER_FP32)
+    say("cider_decode single bin")
+    o1 = torch.zeros(2, 32, dtype=torch.uint8, device="cuda")
+    P.cider_decode(y, float(b.sigma2[0]), ch, 2, 32, wh, 8, o1, opts)
+    o2 = torch.zeros_like(o1)
+    P.cider_decode_batch([{"y": y, "sigma2": float(b.sigma2[0]), "code": ch, "K": 2, "n": 32, "out_symbols": o2}],
+                         wh, 8, opts)
+    torch.cuda.synchronize()
+    assert torch.equal(o1, o2)
+    assert int(o1.max()) <= 1
+
+
+def test_invalid_arguments_rejected_before_launch():
+    torch = torch_cuda()
+    P = lib()
+    cfg = synth.ModelCfg(1, 64, 4, n_max=64)
+    wh, _ = weights_handle(cfg, seed=41)
+    code = code_of(32, 1032)
+    ch = code_handle(code)
+    y = torch.zeros(32, dtype=torch.float32, device="cuda")
+    out = torch.zeros(2, 32, dtype=torch.uint8, device="cuda")
+    say("invalid arguments")
+    for kw in [dict(K=0), dict(K=17), dict(n=31), dict(steps=0), dict(steps=65), dict(sigma2=0.0)]:
+        args = dict(sigma2=1.0, K=2, n=32, steps=8)
+        args.update(kw)
+        with pytest.raises(P.CiderError) as ei:
+            P.cider_decode(y, args["sigma2"], ch, args["K"], args["n"], wh, args["steps"], out)
+        assert ei.value.status == P.abi.CIDER_EINVAL
