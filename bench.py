@@ -57,19 +57,31 @@ def cpu_baseline(name: str, n_bins: int, workers: int):
     return out, wall
 
 
-def algorithmic(wl, tokens_per_bin: int):
-    """FLOP of one forward per token and per GEMM role, for the roofline."""
+def algorithmic(wl, es: int):
+    """Per token and per forward: model FLOP, and FLOP / algorithmic HBM bytes
+    of each kernel role (es = bytes per element of the compute type)."""
     d, L, F = wl.model.d, wl.model.n_layers, wl.model.d_ff
     n, K = wl.n, wl.K
     per_tok = L * (32 * d * d + 4 * n * d + 4 * K * d) + 6 * d * d + 12 * d
-    roles = {
+    flop = {
         "gemm_gate1": 2 * d * 2 * d, "gemm_gate2": 2 * d * d,
         "gemm_qkv_row": 2 * d * 3 * d, "gemm_o_row": 2 * d * d,
         "gemm_qkv_user": 2 * d * 3 * d, "gemm_o_user": 2 * d * d,
         "gemm_mlp_up": 2 * d * F, "gemm_mlp_down": 2 * F * d,
         "attn_row": 4 * n * d, "attn_user": 4 * K * d,
     }
-    return per_tok, roles
+    # bytes each kernel must move at minimum (inputs read once, outputs written once);
+    # residual updates read and write the FP32 stream and, with the next LayerNorm
+    # fused, also write its compute-type copy
+    byt = {
+        "gemm_gate1": (2 * d + d) * es, "gemm_gate2": d * es + 3 * 4 * d + d * es,
+        "gemm_qkv_row": (d + 3 * d) * es, "gemm_qkv_user": (d + 3 * d) * es,
+        "gemm_o_row": d * es + 8 * d + d * es, "gemm_o_user": d * es + 8 * d + d * es,
+        "gemm_mlp_up": (d + F) * es, "gemm_mlp_down": F * es + 8 * d + d * es,
+        "attn_row": (3 * d + d) * es, "attn_user": (3 * d + d) * es,
+        "layernorm": 4 * d + d * es,
+    }
+    return per_tok, flop, byt
 
 
 def main():
@@ -175,20 +187,25 @@ def main():
         stream.synchronize()
     prof = P.cider_profile_read(wh, reset=True)
     tokens = B * K * n
-    per_tok, roles = algorithmic(wl, K * n)
-    dom = max(prof.items(), key=lambda kv: kv[1][1])
-    dom_name, (dom_launches, dom_ms) = dom
-    dom_avg_ms = dom_ms / dom_launches
     kind = "fp32" if args.precision == "fp32" else "bf16"
+    per_tok, flop_role, byte_role = algorithmic(wl, 4 if kind == "fp32" else 2)
+    dom_name, (dom_launches, dom_ms) = max(prof.items(), key=lambda kv: kv[1][1])
+    dom_avg_ms = dom_ms / dom_launches
     roof = None
-    if dom_name in roles:
-        flop = roles[dom_name] * tokens
-        achieved = flop / (dom_avg_ms * 1e-3) / 1e12
-        bound = "alu" if dom_name.startswith("attn") and True else "mfma"
-        peak = PEAK["fp32"] if bound == "alu" else PEAK[kind]
-        roof = {"bound": bound, "kernel": dom_name, "achieved": round(achieved, 2), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-                "avg_launch_ms": round(dom_avg_ms, 4), "flop_per_launch": flop}
+    if dom_name in byte_role:
+        secs = dom_avg_ms * 1e-3
+        fl = flop_role.get(dom_name, 0) * tokens
+        by = byte_role[dom_name] * tokens
+        if kind == "fp32" and dom_name.startswith("attn"):
+            bound, peak, unit, ach = "alu", PEAK["fp32"], "TFLOP/s", fl / secs / 1e12
+        elif fl / by >= PEAK[kind] * 1e12 / (HBM_PEAK * 1e9):
+            bound, peak, unit, ach = "mfma", PEAK[kind], "TFLOP/s", fl / secs / 1e12
+        else:
+            bound, peak, unit, ach = "hbm", HBM_PEAK, "GB/s", by / secs / 1e9
+        roof = {"bound": bound, "kernel": dom_name, "achieved": round(ach, 2), "peak": peak, "unit": unit,
+                "frac": round(ach / peak, 4), "traffic": None, "avg_launch_ms": round(dom_avg_ms, 4),
+                "flop_per_launch": fl, "bytes_per_launch": by,
+                "tflops": round(fl / secs / 1e12, 2)}
     kernel_table = {k: {"launches": v[0], "avg_ms": round(v[1] / v[0], 4), "total_ms": round(v[1], 3)}
                     for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
 

@@ -98,6 +98,11 @@ typedef struct {
   float   eta;                /* Module B bias gain                     [1.0]  */
   float   lam_max;            /* LLR clip and revealed-site LLR         [20]   */
   float   lam_min;            /* |LLR| floor inside phi                 [1e-6] */
+  int32_t autotune;           /* 1: before the first decode of a new batch     */
+                              /*    size, time every GEMM tile shape on it and */
+                              /*    keep the fastest (results do not depend on */
+                              /*    the tile)                            [1]   */
+                              /*    2 + t: use tile t everywhere (tests)       */
   int32_t profile;            /* 1: time every kernel launch with HIP events   */
                               /*    on `stream` (eager launches, no graph);    */
                               /*    read with cider_profile_read         [0]   */
@@ -239,6 +244,18 @@ typedef struct {
 } cider_kernel_stat;
 int cider_profile_read(const cider_weights* w, cider_kernel_stat* out, int32_t max, int32_t* n_out,
                        int32_t reset);
+
+/* The GEMM tile shapes the autotuner chose on this weights handle: one entry
+ * per (role, N, Kd, token-count bucket 2^bucket) with the tile index and the
+ * best measured launch time.  Tile indices are those of the library's GEMM
+ * (0 = the default shape). */
+typedef struct {
+  char    role[24];
+  int32_t n, kd, bucket, tile;
+  double  best_ms;
+  double  default_ms;
+} cider_tuning_entry;
+int cider_tuning_read(const cider_weights* w, cider_tuning_entry* out, int32_t max, int32_t* n_out);
 
 /* Message for a status code, and the last error detail of this thread. */
 const char* cider_strerror(int status);

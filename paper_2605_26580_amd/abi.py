@@ -26,7 +26,7 @@ EXPORTS = [
     "cider_code_create", "cider_code_destroy", "cider_workspace_size", "cider_decode",
     "cider_decode_batch", "cider_step_debug", "cider_evidence", "cider_server_create",
     "cider_server_submit", "cider_server_poll", "cider_server_drain", "cider_server_destroy",
-    "cider_strerror", "cider_last_error", "cider_profile_read",
+    "cider_strerror", "cider_last_error", "cider_profile_read", "cider_tuning_read",
 ]
 
 
@@ -46,7 +46,8 @@ class cider_opts(C.Structure):
                 ("remask", C.c_int32), ("remask_max_rounds", C.c_int32), ("final_argmax", C.c_int32),
                 ("use_graph", C.c_int32), ("remask_thr", C.c_float), ("tau", C.c_float),
                 ("eta", C.c_float), ("lam_max", C.c_float), ("lam_min", C.c_float),
-                ("profile", C.c_int32), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
+                ("autotune", C.c_int32), ("profile", C.c_int32), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_size_t)]
 
 
 class cider_bin(C.Structure):
@@ -57,6 +58,11 @@ class cider_bin(C.Structure):
 
 class cider_kernel_stat(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double)]
+
+
+class cider_tuning_entry(C.Structure):
+    _fields_ = [("role", C.c_char * 24), ("n", C.c_int32), ("kd", C.c_int32), ("bucket", C.c_int32),
+                ("tile", C.c_int32), ("best_ms", C.c_double), ("default_ms", C.c_double)]
 
 
 class cider_server_cfg(C.Structure):
@@ -107,13 +113,15 @@ def lib() -> C.CDLL:
     L.cider_server_destroy.argtypes = [vp]
     L.cider_server_destroy.restype = None
     L.cider_profile_read.argtypes = [vp, C.POINTER(cider_kernel_stat), i32, C.POINTER(i32), i32]
+    L.cider_tuning_read.argtypes = [vp, C.POINTER(cider_tuning_entry), i32, C.POINTER(i32)]
     L.cider_strerror.argtypes = [C.c_int]
     L.cider_strerror.restype = C.c_char_p
     L.cider_last_error.argtypes = []
     L.cider_last_error.restype = C.c_char_p
     for name in ("cider_weights_create", "cider_code_create", "cider_workspace_size", "cider_decode",
                  "cider_decode_batch", "cider_step_debug", "cider_evidence", "cider_server_create",
-                 "cider_server_submit", "cider_server_poll", "cider_server_drain", "cider_profile_read"):
+                 "cider_server_submit", "cider_server_poll", "cider_server_drain", "cider_profile_read",
+                 "cider_tuning_read"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -263,6 +271,15 @@ def cider_profile_read(w: Weights, reset: bool = True) -> dict:
     n = C.c_int32()
     check(lib().cider_profile_read(w.handle, arr, 64, C.byref(n), int(reset)), "cider_profile_read")
     return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(n.value)}
+
+
+def cider_tuning_read(w: Weights) -> list:
+    """[(role, N, Kd, bucket, tile, best_ms, default_ms)] chosen by the GEMM autotuner."""
+    arr = (cider_tuning_entry * 128)()
+    n = C.c_int32()
+    check(lib().cider_tuning_read(w.handle, arr, 128, C.byref(n)), "cider_tuning_read")
+    return [(arr[i].role.decode(), arr[i].n, arr[i].kd, arr[i].bucket, arr[i].tile, arr[i].best_ms,
+             arr[i].default_ms) for i in range(n.value)]
 
 
 def cider_strerror(status: int) -> str:

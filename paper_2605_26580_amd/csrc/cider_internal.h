@@ -109,6 +109,7 @@ struct Work {
   float* Ebuf;     // [T][d]     Module A evidence summary e
   void* ZE;        // [T][2d]    gate MLP input [Z ; e]        (compute type)
   void* H1;        // [T][d]     gate MLP hidden               (compute type)
+  void* XN;        // [T][d]     LayerNorm output              (compute type)
   void* QKV;       // [T][3d]    attention projections         (compute type)
   void* O;         // [T][d]     attention output              (compute type)
   void* HID;       // [T][F]     MLP hidden                    (compute type)
@@ -146,6 +147,14 @@ struct GemmArgs {
 };
 hipError_t launch_gemm(int prec, int pro, int epi, const GemmArgs& g, const Mat& W, hipStream_t s);
 
+hipError_t launch_layernorm(int prec, long T, int d, const float* R, const float* g, const float* b, void* out,
+                            hipStream_t s);
+hipError_t launch_gemm_bf16(int epi, const GemmArgs& g, const Mat& W, hipStream_t s, int tile);
+int gemm_tile_count(int epi, int N, bool ln);
+hipError_t launch_row_attn_mfma(const StepCtx& c, const void* QKV, void* O, int d, int heads, int max_n,
+                                hipStream_t s);
+hipError_t launch_user_attn_bf16(const StepCtx& c, const void* QKV, void* O, int d, int heads, hipStream_t s);
+size_t row_attn_mfma_lds(int max_n, int dh);
 hipError_t launch_row_attn(const StepCtx& c, int prec, const void* QKV, void* O, int d, int heads,
                            int max_n, hipStream_t s);
 hipError_t launch_user_attn(const StepCtx& c, int prec, const void* QKV, void* O, int d, int heads,

@@ -5,6 +5,10 @@
 #include "cider_internal.h"
 
 #include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <thread>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -89,7 +93,21 @@ struct ProfRec {
   hipEvent_t a, b;
 };
 
+struct TuneKey {
+  int epi, ln, N, Kd, bucket;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(epi, ln, N, Kd, bucket) < std::tie(o.epi, o.ln, o.N, o.Kd, o.bucket);
+  }
+};
+struct TuneVal {
+  int tile;
+  double best_ms, default_ms;
+  std::string role;
+};
+
 struct cider_weights {
+  std::map<TuneKey, TuneVal> tune;
+  bool tuning = false;          // true while candidates are being timed
   std::vector<ProfRec> prof_pending;
   std::map<std::string, std::pair<long, double>> prof_stats;
   bool prof_on = false;
@@ -155,7 +173,7 @@ struct Layout {
   long total_tokens = 0;
   int total_slots = 0, total_rows = 0, max_n = 0;
   size_t off_R, off_E, off_ZE, off_H1, off_QKV, off_O, off_HID, off_lbar, off_logits, off_p, off_S,
-      off_bins, off_state, off_slot, off_row, off_X, total;
+      off_bins, off_state, off_slot, off_row, off_X, off_XN, total;
 };
 
 size_t esize(int prec) { return prec == CIDER_FP32 ? 4 : 2; }
@@ -172,6 +190,7 @@ Layout plan_layout(const cider_model_cfg& cfg, int num_bins, long T, int slots, 
   L.off_E = take(T * d * 4);
   L.off_ZE = take(T * 2 * d * es);
   L.off_H1 = take(T * d * es);
+  L.off_XN = take(T * d * es);
   L.off_QKV = take(T * 3 * d * es);
   L.off_O = take(T * d * es);
   L.off_HID = take(T * F * es);
@@ -227,6 +246,7 @@ struct Run {
   StepCtx ctx{};
   Work work{};
   int prec = 0;
+  int forced_tile = -1;   // >= 0: every GEMM uses this tile (tests)
 };
 
 // Brackets a launch with events when profiling is on.
@@ -255,7 +275,58 @@ struct Timed {
     HIPCHK(expr);                     \
   } while (0)
 
+int bucket_of(long M) {
+  int b = 0;
+  while ((1L << (b + 1)) <= M) ++b;
+  return b;
+}
+
+TuneKey tune_key(int epi, const GemmArgs& g) {
+  const int ln = ((epi == kEpiResid || epi == kEpiGate) && g.ln_g) ? 1 : 0;
+  return TuneKey{epi, ln, g.N, g.Kd, bucket_of(g.M)};
+}
+
+int tile_for(cider_weights* w, int epi, const GemmArgs& g) {
+  auto it = w->tune.find(tune_key(epi, g));
+  return it == w->tune.end() ? 0 : it->second.tile;
+}
+
+// Times every tile shape of one GEMM on the live buffers (3 launches each,
+// best of them) and records the fastest.  Only transient buffers are written
+// (the next forward recomputes them), never a grid or a bin state.
+int tune_gemm(cider_weights* w, const char* role, int epi, const GemmArgs& g, const Mat& W, hipStream_t s) {
+  TuneKey key = tune_key(epi, g);
+  if (w->tune.count(key)) return CIDER_OK;
+  const int cand = gemm_tile_count(epi, g.N, key.ln != 0);
+  hipEvent_t a, b;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  double best = 1e30, dflt = 0;
+  int best_t = 0;
+  for (int t = 0; t < cand; ++t) {
+    if (launch_gemm_bf16(epi, g, W, s, t) != hipSuccess) { (void)hipGetLastError(); continue; }
+    double tmin = 1e30;
+    for (int rep = 0; rep < 3; ++rep) {
+      HIPCHK(hipEventRecord(a, s));
+      HIPCHK(launch_gemm_bf16(epi, g, W, s, t));
+      HIPCHK(hipEventRecord(b, s));
+      HIPCHK(hipEventSynchronize(b));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, a, b));
+      tmin = std::min(tmin, (double)ms);
+    }
+    if (t == 0) dflt = tmin;
+    if (tmin < best) { best = tmin; best_t = t; }
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  w->tune[key] = TuneVal{best_t, best, dflt, role};
+  return CIDER_OK;
+}
+
 // One denoiser forward over every bin of the batch, then Module B.
+// GEMM operands are in the compute type (BF16 on the fast path), LayerNorms
+// write a normalised copy XN, and the residual stream R stays FP32.
 int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
   const DevModel& m = w->dm;
   const StepCtx& c = r.ctx;
@@ -263,40 +334,95 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
   const int prec = r.prec;
   const long T = c.total_tokens;
   const int d = m.d, F = m.mlp_mult * m.d;
+  auto gemm = [&](int epi, const GemmArgs& g, const Mat& W) -> hipError_t {
+    if (prec == kF32) return launch_gemm(prec, kProNone, epi, g, W, s);
+    int tile = tile_for(w, epi, g);
+    if (r.forced_tile >= 0) {
+      const bool lnf = (epi == kEpiResid || epi == kEpiGate) && g.ln_g;
+      tile = r.forced_tile < gemm_tile_count(epi, g.N, lnf) ? r.forced_tile : 0;
+    }
+    return launch_gemm_bf16(epi, g, W, s, tile);
+  };
+  auto ln = [&](const float* gg, const float* bb) { return launch_layernorm(prec, T, d, k.R, gg, bb, k.XN, s); };
+  // BF16: the LayerNorm that follows a residual update runs in that GEMM's
+  // epilogue (set ln_g / ln_b / out); FP32 runs it as its own kernel.
+  const bool fused_ln = prec != kF32;
+  auto next_ln = [&](GemmArgs& g, const float* gg, const float* bb) {
+    if (fused_ln) { g.ln_g = gg; g.ln_b = bb; g.out = k.XN; }
+  };
   TIMED("embed_demix", launch_embed_demix(c, w->ew, k, prec, s));
   GemmArgs g{};
   g.M = T;
   // gate MLP: H1 = GELU([Z ; e] Wg1^T + bg1); R = g Z + (1 - g) e, g = sigmoid(H1 Wg2^T + bg2)
   g.N = d; g.Kd = 2 * d; g.A = k.ZE; g.bias = m.bg1; g.out = k.H1;
-  TIMED("gemm_gate1", launch_gemm(prec, kProNone, kEpiGelu, g, m.Wg1, s));
+  TIMED("gemm_gate1", gemm(kEpiGelu, g, m.Wg1));
   g = GemmArgs{}; g.M = T;
   g.N = d; g.Kd = d; g.A = k.H1; g.bias = m.bg2; g.R = k.R; g.E = k.Ebuf;
-  TIMED("gemm_gate2", launch_gemm(prec, kProNone, kEpiGate, g, m.Wg2, s));
+  next_ln(g, m.layer[0].ln1_g, m.layer[0].ln1_b);
+  TIMED("gemm_gate2", gemm(kEpiGate, g, m.Wg2));
   for (int l = 0; l < m.n_layers; ++l) {
     const DevLayer& L = m.layer[l];
+    if (!fused_ln) TIMED("layernorm", ln(L.ln1_g, L.ln1_b));
     g = GemmArgs{}; g.M = T;
-    g.N = 3 * d; g.Kd = d; g.A = k.R; g.ln_g = L.ln1_g; g.ln_b = L.ln1_b; g.bias = L.bqkv_r; g.out = k.QKV;
-    TIMED("gemm_qkv_row", launch_gemm(prec, kProLN, kEpiStore, g, L.Wqkv_r, s));
-    TIMED("attn_row", launch_row_attn(c, prec, k.QKV, k.O, d, m.heads, c.max_n, s));
+    g.N = 3 * d; g.Kd = d; g.A = k.XN; g.bias = L.bqkv_r; g.out = k.QKV;
+    TIMED("gemm_qkv_row", gemm(kEpiStore, g, L.Wqkv_r));
+    if (prec == kF32) TIMED("attn_row", launch_row_attn(c, prec, k.QKV, k.O, d, m.heads, c.max_n, s));
+    else TIMED("attn_row", launch_row_attn_mfma(c, k.QKV, k.O, d, m.heads, c.max_n, s));
     g = GemmArgs{}; g.M = T;
     g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_r; g.R = k.R;
-    TIMED("gemm_o_row", launch_gemm(prec, kProNone, kEpiResid, g, L.Wo_r, s));
+    next_ln(g, L.ln2_g, L.ln2_b);
+    TIMED("gemm_o_row", gemm(kEpiResid, g, L.Wo_r));
+    if (!fused_ln) TIMED("layernorm", ln(L.ln2_g, L.ln2_b));
     g = GemmArgs{}; g.M = T;
-    g.N = 3 * d; g.Kd = d; g.A = k.R; g.ln_g = L.ln2_g; g.ln_b = L.ln2_b; g.bias = L.bqkv_u; g.out = k.QKV;
-    TIMED("gemm_qkv_user", launch_gemm(prec, kProLN, kEpiStore, g, L.Wqkv_u, s));
-    TIMED("attn_user", launch_user_attn(c, prec, k.QKV, k.O, d, m.heads, s));
+    g.N = 3 * d; g.Kd = d; g.A = k.XN; g.bias = L.bqkv_u; g.out = k.QKV;
+    TIMED("gemm_qkv_user", gemm(kEpiStore, g, L.Wqkv_u));
+    if (prec == kF32) TIMED("attn_user", launch_user_attn(c, prec, k.QKV, k.O, d, m.heads, s));
+    else TIMED("attn_user", launch_user_attn_bf16(c, k.QKV, k.O, d, m.heads, s));
     g = GemmArgs{}; g.M = T;
     g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_u; g.R = k.R;
-    TIMED("gemm_o_user", launch_gemm(prec, kProNone, kEpiResid, g, L.Wo_u, s));
+    next_ln(g, L.ln3_g, L.ln3_b);
+    TIMED("gemm_o_user", gemm(kEpiResid, g, L.Wo_u));
+    if (!fused_ln) TIMED("layernorm", ln(L.ln3_g, L.ln3_b));
     g = GemmArgs{}; g.M = T;
-    g.N = F; g.Kd = d; g.A = k.R; g.ln_g = L.ln3_g; g.ln_b = L.ln3_b; g.bias = L.b1; g.out = k.HID;
-    TIMED("gemm_mlp_up", launch_gemm(prec, kProLN, kEpiGelu, g, L.W1, s));
+    g.N = F; g.Kd = d; g.A = k.XN; g.bias = L.b1; g.out = k.HID;
+    TIMED("gemm_mlp_up", gemm(kEpiGelu, g, L.W1));
     g = GemmArgs{}; g.M = T;
     g.N = d; g.Kd = F; g.A = k.HID; g.bias = L.b2; g.R = k.R;
-    TIMED("gemm_mlp_down", launch_gemm(prec, kProNone, kEpiResid, g, L.W2, s));
+    if (l + 1 < m.n_layers) next_ln(g, m.layer[l + 1].ln1_g, m.layer[l + 1].ln1_b);
+    TIMED("gemm_mlp_down", gemm(kEpiResid, g, L.W2));
   }
   TIMED("final_proj", launch_final_proj(c, w->ew, k, s));
   TIMED("module_b", launch_module_b(c, k, s));
+  return CIDER_OK;
+}
+
+// Tunes every GEMM shape of the forward for this batch size (BF16 only).
+int autotune_forward(cider_weights* w, const Run& r, hipStream_t s) {
+  if (r.prec == kF32) return CIDER_OK;
+  const DevModel& m = w->dm;
+  const Work& k = r.work;
+  const long T = r.ctx.total_tokens;
+  const int d = m.d, F = m.mlp_mult * m.d;
+  const DevLayer& L = m.layer[0];
+  int rc;
+  GemmArgs g{};
+  g.M = T; g.N = d; g.Kd = 2 * d; g.A = k.ZE; g.bias = m.bg1; g.out = k.H1;
+  if ((rc = tune_gemm(w, "gemm_gate1", kEpiGelu, g, m.Wg1, s))) return rc;
+  g = GemmArgs{}; g.M = T; g.N = d; g.Kd = d; g.A = k.H1; g.bias = m.bg2; g.R = k.R; g.E = k.Ebuf;
+  g.ln_g = L.ln1_g; g.ln_b = L.ln1_b; g.out = k.XN;
+  if ((rc = tune_gemm(w, "gemm_gate2_ln", kEpiGate, g, m.Wg2, s))) return rc;
+  g = GemmArgs{}; g.M = T; g.N = 3 * d; g.Kd = d; g.A = k.XN; g.bias = L.bqkv_r; g.out = k.QKV;
+  if ((rc = tune_gemm(w, "gemm_qkv", kEpiStore, g, L.Wqkv_r, s))) return rc;
+  g = GemmArgs{}; g.M = T; g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_r; g.R = k.R;
+  g.ln_g = L.ln2_g; g.ln_b = L.ln2_b; g.out = k.XN;
+  if ((rc = tune_gemm(w, "gemm_o_ln", kEpiResid, g, L.Wo_r, s))) return rc;
+  g = GemmArgs{}; g.M = T; g.N = F; g.Kd = d; g.A = k.XN; g.bias = L.b1; g.out = k.HID;
+  if ((rc = tune_gemm(w, "gemm_mlp_up", kEpiGelu, g, L.W1, s))) return rc;
+  g = GemmArgs{}; g.M = T; g.N = d; g.Kd = F; g.A = k.HID; g.bias = L.b2; g.R = k.R;
+  g.ln_g = L.ln1_g; g.ln_b = L.ln1_b; g.out = k.XN;
+  if ((rc = tune_gemm(w, "gemm_mlp_down_ln", kEpiResid, g, L.W2, s))) return rc;
+  g.ln_g = nullptr; g.ln_b = nullptr; g.out = nullptr;
+  if ((rc = tune_gemm(w, "gemm_mlp_down", kEpiResid, g, L.W2, s))) return rc;
   return CIDER_OK;
 }
 
@@ -352,6 +478,8 @@ struct BinIn {
   uint8_t* out_sym;
   float* out_logits;
   uint8_t* out_valid;
+  uint8_t* X = nullptr;     // persistent grid (serving); null: workspace
+  BinState* st = nullptr;   // persistent state (serving); null: workspace
 };
 
 int check_opts(const cider_opts& o) {
@@ -367,6 +495,8 @@ int check_opts(const cider_opts& o) {
 
 int check_bin(const cider_weights* w, const BinIn& b, int steps) {
   if (!b.y || !b.code || !b.out_sym) return fail(CIDER_EINVAL, "null y, code or out_symbols");
+  if (row_attn_mfma_lds(b.n, w->cfg.d / w->cfg.heads) > 160 * 1024)
+    return fail(CIDER_EUNSUPPORTED, "n * d/heads too large for LDS-resident row attention (n*dh*4 <= 160 KB)");
   if (b.K < 1 || b.K > CIDER_MAX_K) return fail(CIDER_EINVAL, "K must be 1..16");
   if (b.n < 1 || b.n > std::min(w->cfg.n_max, CIDER_MAX_N)) return fail(CIDER_EINVAL, "n out of range for the model");
   if (b.code->n != b.n) return fail(CIDER_EINVAL, "code length != n");
@@ -414,9 +544,9 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
     db.var_ptr = b.code->d_var_ptr; db.var_edge = b.code->d_var_edge;
     db.sched = sched;
     db.y = b.y; db.sigma2 = b.sigma2;
-    db.X = (uint8_t*)(base + L.off_X) + tok;
+    db.X = b.X ? b.X : (uint8_t*)(base + L.off_X) + tok;
     db.out_sym = b.out_sym; db.out_logits = b.out_logits; db.out_valid = b.out_valid;
-    db.st = (BinState*)(base + L.off_state) + i;
+    db.st = b.st ? b.st : (BinState*)(base + L.off_state) + i;
     hb[i] = db;
     for (int l = 0; l < b.n; ++l) hslot[so + l] = i;
     for (int k = 0; k < b.K; ++k) hrow[ro + k] = i;
@@ -457,6 +587,7 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
   k.Ebuf = (float*)(base + L.off_E);
   k.ZE = base + L.off_ZE;
   k.H1 = base + L.off_H1;
+  k.XN = base + L.off_XN;
   k.QKV = base + L.off_QKV;
   k.O = base + L.off_O;
   k.HID = base + L.off_HID;
@@ -466,8 +597,8 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
   k.p = (float*)(base + L.off_p);
   k.S = (float*)(base + L.off_S);
   r->prec = o.precision;
+  HIPCHK(launch_evidence(c, k.S, k.p, s));
   if (init_grids) {
-    HIPCHK(launch_evidence(c, k.S, k.p, s));
     HIPCHK(launch_init_bins(c, steps, o.first_reveal, s));
   }
   *Lout = L;
@@ -490,6 +621,11 @@ int decode_impl(cider_weights* w, const std::vector<BinIn>& bins, int steps, con
   Layout L;
   rc = prepare(w, bins, steps, o, s, &r, &L, true);
   if (rc) return rc;
+  if (o.autotune >= 2) r.forced_tile = o.autotune - 2;
+  if (o.autotune == 1 && !w->prof_on) {
+    rc = autotune_forward(w, r, s);
+    if (rc) return rc;
+  }
   const bool graph = o.use_graph != 0;
   // initial pass: steps reveal steps + the final pass
   rc = run_steps(w, r, steps + 1, graph, s);
@@ -531,6 +667,7 @@ void cider_opts_default(cider_opts* o) {
   o->eta = 1.0f;
   o->lam_max = 20.0f;
   o->lam_min = 1e-6f;
+  o->autotune = 1;
   o->profile = 0;
   o->workspace = nullptr;
   o->workspace_bytes = 0;
@@ -800,6 +937,27 @@ int cider_evidence(const float* y, float sigma2, int32_t K, int32_t n, float* ou
   return CIDER_OK;
 }
 
+int cider_tuning_read(const cider_weights* wc, cider_tuning_entry* out, int32_t max, int32_t* n_out) {
+  if (!wc || !n_out || max < 0 || (max > 0 && !out)) return fail(CIDER_EINVAL, "bad tuning arguments");
+  cider_weights* w = const_cast<cider_weights*>(wc);
+  std::lock_guard<std::mutex> lock(w->mu);
+  int i = 0;
+  for (auto& kv : w->tune) {
+    if (i >= max) break;
+    std::memset(out[i].role, 0, sizeof(out[i].role));
+    std::strncpy(out[i].role, kv.second.role.c_str(), sizeof(out[i].role) - 1);
+    out[i].n = kv.first.N;
+    out[i].kd = kv.first.Kd;
+    out[i].bucket = kv.first.bucket;
+    out[i].tile = kv.second.tile;
+    out[i].best_ms = kv.second.best_ms;
+    out[i].default_ms = kv.second.default_ms;
+    ++i;
+  }
+  *n_out = i;
+  return CIDER_OK;
+}
+
 int cider_profile_read(const cider_weights* wc, cider_kernel_stat* out, int32_t max, int32_t* n_out,
                        int32_t reset) {
   if (!wc || !n_out || max < 0 || (max > 0 && !out)) return fail(CIDER_EINVAL, "bad profile arguments");
@@ -831,19 +989,296 @@ int cider_profile_read(const cider_weights* wc, cider_kernel_stat* out, int32_t 
   return CIDER_OK;
 }
 
-struct cider_server {};
-int cider_server_create(const cider_server_cfg*, cider_server** out) {
-  if (out) *out = nullptr;
-  return fail(CIDER_EUNSUPPORTED, "server not built");
+}  // extern "C"
+
+// ===========================================================================
+// Serving: continuous batching of arriving bins.
+//
+// A worker thread owns a HIP stream and a set of device-resident slots.  A
+// slot holds one admitted bin's received samples, grid, decoding state and
+// output; the transient per-token buffers are shared and re-laid out only when
+// the resident set changes.  Each iteration advances every resident bin by one
+// refinement step (each at its own phase: reveal step, final pass, remask
+// pass), reads back the bin states, hands finished bins to the completion list
+// and admits waiting requests while slots, tokens and the HBM budget allow.
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
-int cider_server_submit(cider_server*, const float*, float, const cider_code*, int32_t, int32_t, uint8_t*, uint64_t*) {
-  return fail(CIDER_EUNSUPPORTED, "server not built");
+
+struct Request {
+  uint64_t id;
+  std::vector<float> y;
+  float sigma2;
+  const cider_code* code;
+  int K, n;
+  uint8_t* out_host;
+  double t_submit;
+};
+
+struct Slot {
+  bool used = false;
+  Request req;
+  double t_admit = 0;
+  float* y = nullptr;
+  uint8_t* X = nullptr;
+  uint8_t* out = nullptr;
+  BinState* st = nullptr;
+};
+
+}  // namespace
+
+struct cider_server {
+  cider_server_cfg cfg{};
+  cider_weights* w = nullptr;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv, cv_done;
+  bool stop = false;
+  int status = CIDER_OK;
+  std::string err;
+  std::deque<Request> queue;
+  std::vector<Slot> slots;
+  std::vector<cider_result> done;
+  uint64_t next_id = 1;
+  long inflight = 0;  // queued + resident
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  char* dev_pool = nullptr;
+  BinState* h_states = nullptr;
+};
+
+namespace {
+
+void server_loop(cider_server* S) {
+  hipSetDevice(S->device);
+  cider_weights* w = S->w;
+  const int T = S->cfg.steps;
+  cider_opts o = S->cfg.opts;
+  o.workspace = S->ws;
+  o.workspace_bytes = S->ws_bytes;
+  o.profile = 0;
+  long tokens_in_use = 0;
+  bool changed = true;
+  Run run;
+  Layout L;
+  std::vector<int> order;  // slot index of each packed bin
+  auto fail_all = [&](int rc) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->status = rc;
+    S->err = g_err;
+    S->stop = true;
+    S->cv_done.notify_all();
+  };
+  while (true) {
+    // ---- admit
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      if (S->stop) break;
+      bool any = false;
+      for (const Slot& sl : S->slots) any |= sl.used;
+      if (!any && S->queue.empty()) {
+        S->cv.wait_for(lk, std::chrono::milliseconds(2));
+        continue;
+      }
+      while (!S->queue.empty()) {
+        const Request& rq = S->queue.front();
+        long tok = (long)rq.K * rq.n;
+        if (tokens_in_use + tok > S->cfg.max_tokens) break;
+        int free_i = -1;
+        for (int i = 0; i < (int)S->slots.size(); ++i)
+          if (!S->slots[i].used) { free_i = i; break; }
+        if (free_i < 0) break;
+        Slot& sl = S->slots[free_i];
+        sl.used = true;
+        sl.req = std::move(S->queue.front());
+        S->queue.pop_front();
+        sl.t_admit = now_s();
+        tokens_in_use += tok;
+        // device state of the new bin: samples, all-mask grid, initial pass
+        const int K = sl.req.K, n = sl.req.n;
+        hipMemcpyAsync(sl.y, sl.req.y.data(), n * sizeof(float), hipMemcpyHostToDevice, S->stream);
+        hipMemsetAsync(sl.X, kMask, (size_t)K * n, S->stream);
+        BinState st{};
+        st.phase = kReveal; st.t = 1; st.pass_T = T; st.n_masked = K * n; st.masked = K * n;
+        st.first = (o.first_reveal && T > 1) ? 1 : 0;
+        S->h_states[free_i] = st;
+        hipMemcpyAsync(sl.st, &S->h_states[free_i], sizeof(BinState), hipMemcpyHostToDevice, S->stream);
+        hipStreamSynchronize(S->stream);   // the host copies above are staged from pageable memory
+        changed = true;
+      }
+    }
+    // ---- (re)build the packed layout when the resident set changed
+    if (changed) {
+      std::vector<BinIn> bins;
+      order.clear();
+      for (int i = 0; i < (int)S->slots.size(); ++i) {
+        Slot& sl = S->slots[i];
+        if (!sl.used) continue;
+        BinIn b{sl.y, sl.req.sigma2, sl.req.code, sl.req.K, sl.req.n, sl.out, nullptr, nullptr};
+        b.X = sl.X;
+        b.st = sl.st;
+        bins.push_back(b);
+        order.push_back(i);
+      }
+      if (bins.empty()) continue;
+      std::lock_guard<std::mutex> lk(w->mu);
+      int rc = prepare(w, bins, T, o, S->stream, &run, &L, false);
+      if (rc) { fail_all(rc); break; }
+      changed = false;
+    }
+    // ---- one refinement step for every resident bin
+    {
+      std::lock_guard<std::mutex> lk(w->mu);
+      int rc = enqueue_step(w, run, S->stream);
+      if (rc) { fail_all(rc); break; }
+    }
+    // ---- read back states; retire finished bins
+    for (size_t j = 0; j < order.size(); ++j)
+      hipMemcpyAsync(&S->h_states[order[j]], S->slots[order[j]].st, sizeof(BinState), hipMemcpyDeviceToHost,
+                     S->stream);
+    hipError_t e = hipStreamSynchronize(S->stream);
+    if (e != hipSuccess) { g_err = hipGetErrorString(e); fail_all(CIDER_EDEVICE); break; }
+    for (size_t j = 0; j < order.size(); ++j) {
+      Slot& sl = S->slots[order[j]];
+      const BinState& st = S->h_states[order[j]];
+      if (st.phase != kDone) continue;
+      hipMemcpy(sl.req.out_host, sl.out, (size_t)sl.req.K * sl.req.n, hipMemcpyDeviceToHost);
+      cider_result res{};
+      res.id = sl.req.id; res.K = sl.req.K; res.n = sl.req.n; res.status = CIDER_OK; res.rounds = st.round;
+      res.t_submit = sl.req.t_submit; res.t_admit = sl.t_admit; res.t_done = now_s();
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->done.push_back(res);
+      tokens_in_use -= (long)sl.req.K * sl.req.n;
+      sl.used = false;
+      sl.req.y.clear();
+      S->inflight -= 1;
+      changed = true;
+      S->cv_done.notify_all();
+    }
+  }
 }
-int cider_server_poll(cider_server*, cider_result*, int32_t, int32_t* n) {
-  if (n) *n = 0;
-  return fail(CIDER_EUNSUPPORTED, "server not built");
+
+}  // namespace
+
+extern "C" {
+
+int cider_server_create(const cider_server_cfg* cfg, cider_server** out) {
+  if (!out) return fail(CIDER_EINVAL, "null out");
+  *out = nullptr;
+  if (!cfg || !cfg->weights) return fail(CIDER_EINVAL, "null cfg or weights");
+  if (cfg->steps < 1 || cfg->max_slots < 1 || cfg->max_slots > 65536 || cfg->max_queue < 1 || cfg->max_tokens < 1)
+    return fail(CIDER_EINVAL, "steps, max_slots, max_queue and max_tokens must be positive");
+  int rc = check_opts(cfg->opts);
+  if (rc) return rc;
+  cider_server* S = new cider_server();
+  S->cfg = *cfg;
+  S->w = const_cast<cider_weights*>(cfg->weights);
+  S->device = S->w->device;
+  hipSetDevice(S->device);
+  // step workspace for max_tokens spread over up to max_slots bins of n <= n_max
+  long slots_bound = std::min<long>((long)cfg->max_slots * CIDER_MAX_N, cfg->max_tokens);
+  Layout Lw = plan_layout(S->w->cfg, cfg->max_slots, cfg->max_tokens, (int)slots_bound,
+                          (int)std::min<long>((long)cfg->max_slots * CIDER_MAX_K, cfg->max_tokens), cfg->opts.precision);
+  const size_t per_slot = align_up(CIDER_MAX_N * 4, 256) + 2 * align_up(CIDER_MAX_K * CIDER_MAX_N, 256) +
+                          align_up(sizeof(BinState), 256);
+  const size_t need = Lw.total + per_slot * cfg->max_slots;
+  if (cfg->hbm_budget && need > cfg->hbm_budget) {
+    delete S;
+    return fail(CIDER_EINVAL, "hbm_budget below what max_tokens and max_slots need: " + std::to_string(need));
+  }
+  if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipMalloc(&S->ws, Lw.total) != hipSuccess ||
+      hipMalloc((void**)&S->dev_pool, per_slot * cfg->max_slots) != hipSuccess ||
+      hipHostMalloc((void**)&S->h_states, sizeof(BinState) * cfg->max_slots, hipHostMallocDefault) != hipSuccess) {
+    if (S->stream) hipStreamDestroy(S->stream);
+    if (S->ws) hipFree(S->ws);
+    if (S->dev_pool) hipFree(S->dev_pool);
+    delete S;
+    return fail(CIDER_ENOMEM, "server allocation failed");
+  }
+  S->ws_bytes = Lw.total;
+  S->slots.resize(cfg->max_slots);
+  for (int i = 0; i < cfg->max_slots; ++i) {
+    char* p = S->dev_pool + per_slot * i;
+    Slot& sl = S->slots[i];
+    sl.y = (float*)p;
+    p += align_up(CIDER_MAX_N * 4, 256);
+    sl.X = (uint8_t*)p;
+    p += align_up(CIDER_MAX_K * CIDER_MAX_N, 256);
+    sl.out = (uint8_t*)p;
+    p += align_up(CIDER_MAX_K * CIDER_MAX_N, 256);
+    sl.st = (BinState*)p;
+  }
+  S->worker = std::thread(server_loop, S);
+  *out = S;
+  return CIDER_OK;
 }
-int cider_server_drain(cider_server*) { return fail(CIDER_EUNSUPPORTED, "server not built"); }
-void cider_server_destroy(cider_server*) {}
+
+int cider_server_submit(cider_server* S, const float* y_host, float sigma2, const cider_code* code, int32_t K,
+                        int32_t n, uint8_t* out_host, uint64_t* id) {
+  if (!S || !y_host || !out_host || !id) return fail(CIDER_EINVAL, "null argument");
+  uint8_t dummy = 0;
+  BinIn b{y_host, sigma2, code, K, n, &dummy, nullptr, nullptr};
+  int rc = check_bin(S->w, b, S->cfg.steps);
+  if (rc) return rc;
+  if ((long)K * n > S->cfg.max_tokens) return fail(CIDER_EINVAL, "bin larger than max_tokens");
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (S->status != CIDER_OK) return fail(S->status, "server stopped: " + S->err);
+  if ((int)S->queue.size() >= S->cfg.max_queue) return fail(CIDER_EAGAIN, "queue full");
+  Request rq;
+  rq.id = S->next_id++;
+  rq.y.assign(y_host, y_host + n);
+  rq.sigma2 = sigma2;
+  rq.code = code;
+  rq.K = K;
+  rq.n = n;
+  rq.out_host = out_host;
+  rq.t_submit = now_s();
+  *id = rq.id;
+  S->queue.push_back(std::move(rq));
+  S->inflight += 1;
+  S->cv.notify_one();
+  return CIDER_OK;
+}
+
+int cider_server_poll(cider_server* S, cider_result* out, int32_t max, int32_t* n_done) {
+  if (!S || !n_done || max < 0 || (max > 0 && !out)) return fail(CIDER_EINVAL, "bad poll arguments");
+  std::lock_guard<std::mutex> lk(S->mu);
+  int k = std::min<int>(max, (int)S->done.size());
+  for (int i = 0; i < k; ++i) out[i] = S->done[i];
+  S->done.erase(S->done.begin(), S->done.begin() + k);
+  *n_done = k;
+  if (S->status != CIDER_OK) return fail(S->status, "server stopped: " + S->err);
+  return CIDER_OK;
+}
+
+int cider_server_drain(cider_server* S) {
+  if (!S) return fail(CIDER_EINVAL, "null server");
+  std::unique_lock<std::mutex> lk(S->mu);
+  S->cv_done.wait(lk, [&] { return S->inflight == 0 || S->status != CIDER_OK; });
+  if (S->status != CIDER_OK) return fail(S->status, "server stopped: " + S->err);
+  return CIDER_OK;
+}
+
+void cider_server_destroy(cider_server* S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+    S->cv.notify_all();
+  }
+  if (S->worker.joinable()) S->worker.join();
+  hipSetDevice(S->device);
+  hipStreamSynchronize(S->stream);
+  hipStreamDestroy(S->stream);
+  hipFree(S->ws);
+  hipFree(S->dev_pool);
+  hipHostFree(S->h_states);
+  delete S;
+}
 
 }  // extern "C"

@@ -1,0 +1,651 @@
+// BF16 hot-path kernels for gfx950: LayerNorm to the compute type, a
+// double-buffered MFMA GEMM, and MFMA row attention.
+//
+// MFMA conventions used below (16x16 output blocks, 64-lane wave):
+//   output   lane l, register r  ->  row 4*(l/16) + r, column l % 16
+//   operands lane l holds row (A) / column (B) l % 16 and the k-group l / 16;
+// both operands of one instruction always use the same k-group assignment,
+// so the sum over k is the full dot product whatever order the hardware
+// walks the k elements of a group in.
+#include "cider_internal.h"
+
+namespace cider {
+
+namespace {
+
+typedef __bf16 bf16x2 __attribute__((__vector_size__(2 * sizeof(__bf16))));
+typedef float f32x2 __attribute__((__vector_size__(2 * sizeof(float))));
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// LayerNorm over d of the FP32 residual, written in the compute type.  One
+// wavefront per token; lane i owns the NC consecutive columns i*NC.. so loads
+// and stores are vectorised.  Two-pass mean / variance in FP32.
+template <typename TC, int NC>
+__global__ __launch_bounds__(256) void k_layernorm(long T, int d, const float* __restrict__ R,
+                                                   const float* __restrict__ g, const float* __restrict__ b,
+                                                   TC* __restrict__ out) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long t = (long)blockIdx.x * 4 + wave;
+  if (t >= T) return;
+  const int c0 = lane * NC;
+  const bool on = c0 < d;
+  float x[NC];
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < NC; ++i) {
+    x[i] = on ? R[t * d + c0 + i] : 0.f;
+    s += x[i];
+  }
+  const float mean = wave_sum(s) / (float)d;
+  float q = 0.f;
+#pragma unroll
+  for (int i = 0; i < NC; ++i) {
+    float dv = on ? x[i] - mean : 0.f;
+    q = fmaf(dv, dv, q);
+  }
+  const float rstd = 1.0f / sqrtf(wave_sum(q) / (float)d + 1e-5f);
+  if (on) {
+#pragma unroll
+    for (int i = 0; i < NC; ++i) out[t * d + c0 + i] = (TC)((x[i] - mean) * rstd * g[c0 + i] + b[c0 + i]);
+  }
+}
+
+hipError_t launch_layernorm(int prec, long T, int d, const float* R, const float* g, const float* b, void* out,
+                            hipStream_t s) {
+  if (T == 0) return hipSuccess;
+  dim3 grid((unsigned)((T + 3) / 4)), block(256);
+  const int nc = d / 64;  // d is a multiple of 64, at most 512
+#define LN_CASE(TC, NCV) hipLaunchKernelGGL((k_layernorm<TC, NCV>), grid, block, 0, s, T, d, R, g, b, (TC*)out)
+  if (prec == kF32) {
+    if (nc == 1) LN_CASE(float, 1); else if (nc == 2) LN_CASE(float, 2); else if (nc <= 4) LN_CASE(float, 4);
+    else LN_CASE(float, 8);
+  } else {
+    if (nc == 1) LN_CASE(bf16, 1); else if (nc == 2) LN_CASE(bf16, 2); else if (nc <= 4) LN_CASE(bf16, 4);
+    else LN_CASE(bf16, 8);
+  }
+#undef LN_CASE
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// BF16 GEMM  out = epi(A W^T + bias), A [M][Kd] tokens, W [N][Kd].
+//
+// Workgroup tile BM tokens x BN columns, K in slices of BK staged through two
+// LDS buffers (the next slice is fetched into registers while the current one
+// is multiplied).  Four waves in a 2 x 2 arrangement; a wave computes BN/2
+// columns x BM/2 tokens as (BN/32) x (BM/32) MFMA 16x16x32 blocks.  The FP32
+// results are then staged in LDS (reusing the slice buffers) and a row pass
+// writes whole token rows with coalesced accesses:
+//   Store / Gelu     out (BF16) = v or GELU(v)
+//   Resid            R += v
+//   Gate             R = g R + (1 - g) E,  g = sigmoid(v)      (Module A blend)
+//   ResidLN, GateLN  as Resid / Gate, then XN = LayerNorm(R) with the next
+//                    block's gain and bias; needs BN == N so a workgroup owns
+//                    complete rows.
+// Each output is accumulated over k in the same order in every tile, so a
+// token's result does not depend on the other tokens of its batch.
+namespace {
+
+constexpr int GPAD = 8;
+
+enum : int { kEpiResidLN = 4, kEpiGateLN = 5 };
+
+template <int BM, int BN, int BK>
+struct GemmSmem {
+  static constexpr size_t loop = (size_t)2 * (BM + BN) * (BK + GPAD) * sizeof(bf16);
+  static constexpr size_t stage = (size_t)BM * (BN + 4) * sizeof(float);
+  static constexpr size_t bytes = loop > stage ? loop : stage;
+};
+
+template <int BM, int BN, int BK, int EPI>
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, const bf16* __restrict__ W) {
+  constexpr int TI = BN / 32;  // column blocks per wave
+  constexpr int TJ = BM / 32;  // token blocks per wave
+  constexpr int LDK = BK + GPAD;
+  __shared__ __attribute__((aligned(16))) char smem[GemmSmem<BM, BN, BK>::bytes];
+  bf16* sA = (bf16*)smem;                       // [2][BM][LDK]
+  bf16* sW = sA + 2 * BM * LDK;                 // [2][BN][LDK]
+  float* sC = (float*)smem;                     // [BM][BN + 4] after the K loop
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const long m0 = (long)blockIdx.x * BM;
+  const int n0 = blockIdx.y * BN;
+  const int Kd = g.Kd;
+  const bf16* A = (const bf16*)g.A;
+  const int wn = (wave >> 1) * (BN / 2), wm = (wave & 1) * (BM / 2);
+
+  constexpr int CPR = BK / 8;                    // 16-byte chunks per row of a slice
+  constexpr int ACH = (BM * CPR + 255) / 256;
+  constexpr int WCH = (BN * CPR + 255) / 256;
+  bf16x8 ra[ACH], rw[WCH];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int c = 0; c < ACH; ++c) {
+      const int idx = tid + c * 256, row = idx / CPR, kc = (idx % CPR) * 8;
+      const long gm = m0 + row;
+      if (row < BM && gm < g.M) ra[c] = *(const bf16x8*)(A + gm * Kd + k0 + kc);
+      else ra[c] = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int c = 0; c < WCH; ++c) {
+      const int idx = tid + c * 256, row = idx / CPR, kc = (idx % CPR) * 8;
+      if (row < BN) rw[c] = *(const bf16x8*)(W + (long)(n0 + row) * Kd + k0 + kc);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int c = 0; c < ACH; ++c) {
+      const int idx = tid + c * 256, row = idx / CPR, kc = (idx % CPR) * 8;
+      if (row < BM) *(bf16x8*)&sA[(buf * BM + row) * LDK + kc] = ra[c];
+    }
+#pragma unroll
+    for (int c = 0; c < WCH; ++c) {
+      const int idx = tid + c * 256, row = idx / CPR, kc = (idx % CPR) * 8;
+      if (row < BN) *(bf16x8*)&sW[(buf * BN + row) * LDK + kc] = rw[c];
+    }
+  };
+
+  f32x4 acc[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int nk = Kd / BK;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) fetch((kt + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 32) {
+      bf16x8 fw[TI], fa[TJ];
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+        fw[i] = *(const bf16x8*)&sW[(buf * BN + wn + i * 16 + (lane & 15)) * LDK + ks + (lane >> 4) * 8];
+#pragma unroll
+      for (int j = 0; j < TJ; ++j)
+        fa[j] = *(const bf16x8*)&sA[(buf * BM + wm + j * 16 + (lane & 15)) * LDK + ks + (lane >> 4) * 8];
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fw[i], fa[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) stash(buf ^ 1);
+    __syncthreads();
+  }
+
+  // stage v = acc + bias: lane holds columns wn + 16 i + 4 (lane/16) + r of token wm + 16 j + lane%16
+  constexpr int LDC = BN + 4;
+#pragma unroll
+  for (int i = 0; i < TI; ++i) {
+    const int nl = wn + i * 16 + (lane >> 4) * 4;
+    f32x4 bias = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (g.bias) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bias[r] = g.bias[n0 + nl + r];
+    }
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
+      const int ml = wm + j * 16 + (lane & 15);
+      *(f32x4*)&sC[ml * LDC + nl] = acc[i][j] + bias;
+    }
+  }
+  __syncthreads();
+
+  // row pass: a lane group of LPR lanes owns one token row per pass and covers its
+  // BN columns in 4-column groups; all loads of a chunk of passes are issued
+  // before any of them is used, so the global-memory latency overlaps.
+  constexpr int CG = BN / 4;                     // 4-column groups per row
+  constexpr int LPR = CG <= 16 ? 16 : (CG <= 32 ? 32 : 64);   // lanes per row, a power of two
+  constexpr int RPI = 64 / LPR;                  // rows per wave pass
+  constexpr int GPL = (CG + LPR - 1) / LPR;      // column groups per lane
+  constexpr int NIT = BM / (4 * RPI);            // passes per wave
+  constexpr int CH = (NIT * GPL <= 16) ? NIT : (16 / GPL > 0 ? 16 / GPL : 1);
+  constexpr bool RES = EPI != kEpiStore && EPI != kEpiGelu;
+  constexpr bool GATE = EPI == kEpiGate || EPI == kEpiGateLN;
+  constexpr bool LNX = EPI == kEpiResidLN || EPI == kEpiGateLN;
+  const int grp = lane / LPR, cl = lane % LPR;
+  float* __restrict__ Rg = g.R;
+  const float* __restrict__ Eg = g.E;
+  bf16* __restrict__ Og = (bf16*)g.out;
+#pragma unroll
+  for (int it0 = 0; it0 < NIT; it0 += CH) {
+    f32x4 vv[CH][GPL], rr[CH][GPL], ee[GATE ? CH : 1][GPL];
+#pragma unroll
+    for (int it = 0; it < CH; ++it) {
+      const int ml = ((it0 + it) * 4 + wave) * RPI + grp;
+      const long m = m0 + ml;
+#pragma unroll
+      for (int u = 0; u < GPL; ++u) {
+        const int cg = cl + u * LPR;
+        if (cg < CG) {
+          vv[it][u] = *(const f32x4*)&sC[ml * LDC + cg * 4];
+          if (RES && m < g.M) {
+            const long o = m * g.N + n0 + cg * 4;
+            rr[it][u] = *(const f32x4*)(Rg + o);
+            if (GATE) ee[GATE ? it : 0][u] = *(const f32x4*)(Eg + o);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < CH; ++it) {
+      const int ml = ((it0 + it) * 4 + wave) * RPI + grp;
+      const long m = m0 + ml;
+      const bool mv = m < g.M;
+      float sum = 0.f;
+#pragma unroll
+      for (int u = 0; u < GPL; ++u) {
+        const int cg = cl + u * LPR;
+        if (cg >= CG || !mv) continue;
+        f32x4 v = vv[it][u];
+        if (!RES) {
+          if (EPI == kEpiGelu) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = gelu_f(v[r]);
+          }
+          bf16x4 h = {(bf16)v[0], (bf16)v[1], (bf16)v[2], (bf16)v[3]};
+          *(bf16x4*)(Og + m * g.N + n0 + cg * 4) = h;
+        } else {
+          f32x4 res;
+          if (!GATE) {
+            res = rr[it][u] + v;
+          } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const float gt = 1.0f / (1.0f + expf(-v[r]));
+              res[r] = gt * rr[it][u][r] + (1.0f - gt) * ee[GATE ? it : 0][u][r];
+            }
+          }
+          *(f32x4*)(Rg + m * g.N + n0 + cg * 4) = res;
+          vv[it][u] = res;
+          sum += (res[0] + res[1]) + (res[2] + res[3]);
+        }
+      }
+      if (LNX) {
+        // reduce over the LPR lanes of this row's group (a power of two)
+#pragma unroll
+        for (int o = LPR / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        const float mean = sum / (float)BN;
+        float q = 0.f;
+#pragma unroll
+        for (int u = 0; u < GPL; ++u) {
+          const int cg = cl + u * LPR;
+          if (cg >= CG || !mv) continue;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float dv = vv[it][u][r] - mean;
+            q = fmaf(dv, dv, q);
+          }
+        }
+#pragma unroll
+        for (int o = LPR / 2; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
+        const float rstd = 1.0f / sqrtf(q / (float)BN + 1e-5f);
+#pragma unroll
+        for (int u = 0; u < GPL; ++u) {
+          const int cg = cl + u * LPR;
+          if (cg >= CG || !mv) continue;
+          const int c = cg * 4;
+          bf16x4 h;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) h[r] = (bf16)((vv[it][u][r] - mean) * rstd * g.ln_g[c + r] + g.ln_b[c + r]);
+          *(bf16x4*)(Og + m * BN + c) = h;
+        }
+      }
+    }
+  }
+}
+
+template <int BM, int BN, int BK>
+hipError_t gemm_bf16_t(int epi, const GemmArgs& g, const bf16* W, hipStream_t s) {
+  dim3 grid((unsigned)((g.M + BM - 1) / BM), (unsigned)(g.N / BN)), block(256);
+  switch (epi) {
+    case kEpiStore: hipLaunchKernelGGL((k_gemm_bf16<BM, BN, BK, kEpiStore>), grid, block, 0, s, g, W); break;
+    case kEpiGelu: hipLaunchKernelGGL((k_gemm_bf16<BM, BN, BK, kEpiGelu>), grid, block, 0, s, g, W); break;
+    case kEpiResid: hipLaunchKernelGGL((k_gemm_bf16<BM, BN, BK, kEpiResid>), grid, block, 0, s, g, W); break;
+    case kEpiGate: hipLaunchKernelGGL((k_gemm_bf16<BM, BN, BK, kEpiGate>), grid, block, 0, s, g, W); break;
+    case kEpiResidLN: hipLaunchKernelGGL((k_gemm_bf16<BM, BN, BK, kEpiResidLN>), grid, block, 0, s, g, W); break;
+    case kEpiGateLN: hipLaunchKernelGGL((k_gemm_bf16<BM, BN, BK, kEpiGateLN>), grid, block, 0, s, g, W); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// Tile shapes the GEMM can run with.  Every shape accumulates each output over
+// k in the same order (32-wide MFMA steps from k = 0 up), and the fused
+// LayerNorm always spans the full row, so the choice never changes a result;
+// the autotuner picks among them by measured time.
+//   plain epilogues : 0 = 128x128, 1 = 64x128, 2 = 128x64, 3 = 64x64 (BM x BN)
+//   LayerNorm fused : BN = N, 0 = BM 128 (N <= 128) or 64, 1 = BM 64, 2 = BM 32
+int gemm_tile_count(int epi, int N, bool ln) {
+  if (ln) return N <= 128 ? 3 : 2;
+  return (N % 128 == 0) ? 4 : 2;
+}
+
+// epi: Store, Gelu, Resid, Gate; with ln_g set (Resid / Gate) the next
+// LayerNorm is applied in the epilogue and written to g.out.
+hipError_t launch_gemm_bf16(int epi, const GemmArgs& g, const Mat& W, hipStream_t s, int tile) {
+  if (g.M == 0) return hipSuccess;
+  if (g.Kd % 64 != 0) return hipErrorInvalidValue;
+  const bool ln = (epi == kEpiResid || epi == kEpiGate) && g.ln_g != nullptr;
+  if (ln) {
+    const int e = epi == kEpiResid ? kEpiResidLN : kEpiGateLN;
+    const int bm = (tile == 0) ? (g.N <= 128 ? 128 : 64) : (tile == 1 ? 64 : 32);
+#define LNT(BNV, BKV)                                                    \
+  if (bm == 128) return gemm_bf16_t<128, BNV, BKV>(e, g, W.b16, s);      \
+  if (bm == 64) return gemm_bf16_t<64, BNV, BKV>(e, g, W.b16, s);        \
+  return gemm_bf16_t<32, BNV, BKV>(e, g, W.b16, s);
+#define LNT_SMALL(BNV, BKV)                                              \
+  if (bm == 128) return hipErrorInvalidValue;                            \
+  if (bm == 64) return gemm_bf16_t<64, BNV, BKV>(e, g, W.b16, s);        \
+  return gemm_bf16_t<32, BNV, BKV>(e, g, W.b16, s);
+    switch (g.N) {
+      case 64: { LNT(64, 64) }
+      case 128: { LNT(128, 64) }
+      case 192: { LNT_SMALL(192, 64) }
+      case 256: { LNT_SMALL(256, 64) }
+      case 320: { LNT_SMALL(320, 32) }
+      case 384: { LNT_SMALL(384, 32) }
+      case 448: { LNT_SMALL(448, 32) }
+      case 512: { LNT_SMALL(512, 32) }
+      default: return hipErrorInvalidValue;
+    }
+#undef LNT_SMALL
+#undef LNT
+  }
+  if (g.N % 128 == 0) {
+    switch (tile) {
+      case 0: return gemm_bf16_t<128, 128, 64>(epi, g, W.b16, s);
+      case 1: return gemm_bf16_t<64, 128, 64>(epi, g, W.b16, s);
+      case 2: return gemm_bf16_t<128, 64, 64>(epi, g, W.b16, s);
+      default: return gemm_bf16_t<64, 64, 64>(epi, g, W.b16, s);
+    }
+  }
+  if (g.N % 64 == 0) {
+    if (tile == 0 || tile == 2) return gemm_bf16_t<128, 64, 64>(epi, g, W.b16, s);
+    return gemm_bf16_t<64, 64, 64>(epi, g, W.b16, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Row attention on MFMA.  One workgroup per (row, head): the row's keys K
+// [key][dh] and transposed values V^T [dh][key] for that head are loaded into
+// LDS once (n * dh * 4 bytes <= 128 KB), then each wave takes 16-query tiles
+// and streams the resident keys 64 at a time:
+//   S^T = K Q^T       (A = keys from LDS, B = the tile's queries)
+//   O^T += V^T P^T    (A = values from LDS, B = probabilities)
+// so a lane keeps one query (lane % 16): its running max, its sum and its
+// output columns; the online-softmax rescale is applied in FP32.
+namespace {
+
+constexpr int AKB = 64;   // keys per MFMA block
+
+template <int DH>
+__global__ __launch_bounds__(256) void k_row_attn_mfma(StepCtx c, const bf16* __restrict__ QKV, bf16* __restrict__ O,
+                                                       int d, int heads) {
+  constexpr int DT = DH / 16;                    // output column blocks
+  constexpr int QE = (DH == 16) ? 4 : 8;         // dh elements per lane per MFMA
+  constexpr int QS = (DH == 64) ? 2 : 1;         // MFMA k-steps over dh
+  constexpr int LDK = DH + 8;
+  typedef __bf16 qv_t __attribute__((__vector_size__(QE * sizeof(__bf16))));
+  extern __shared__ __attribute__((aligned(16))) char smem_attn[];
+  const int r = blockIdx.x / heads, h = blockIdx.x - (blockIdx.x / heads) * heads;
+  const DevBin& b = c.bins[c.row_bin[r]];
+  if (b.st->phase == kDone) return;
+  const int n = b.n, k = r - b.row_off;
+  const int nkp = (n + AKB - 1) / AKB * AKB;     // keys padded to whole blocks
+  const int LDV = nkp + 8;
+  bf16* sK = (bf16*)smem_attn;                   // [nkp][LDK]
+  bf16* sVt = sK + nkp * LDK;                    // [DH][LDV]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const long tok0 = (long)b.tok_off + (long)k * n;
+  const long ld = 3L * d;
+  const float scale = 1.0f / sqrtf((float)DH);
+
+  for (int idx = tid; idx < nkp * (DH / 8); idx += 256) {
+    const int key = idx / (DH / 8), c8 = (idx - key * (DH / 8)) * 8;
+    bf16x8 kv = bf16x8{0, 0, 0, 0, 0, 0, 0, 0}, vv = kv;
+    if (key < n) {
+      const bf16* base = QKV + (tok0 + key) * ld + h * DH + c8;
+      kv = *(const bf16x8*)(base + d);
+      vv = *(const bf16x8*)(base + 2 * d);
+    }
+    *(bf16x8*)&sK[key * LDK + c8] = kv;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) sVt[(c8 + e) * LDV + key] = vv[e];
+  }
+  __syncthreads();
+
+  for (int q0 = wave * 16; q0 < n; q0 += 64) {
+    const int q = q0 + (lane & 15);
+    const bool qvalid = q < n;
+    qv_t fq[QS];
+#pragma unroll
+    for (int s = 0; s < QS; ++s) {
+      if (qvalid) {
+        fq[s] = *(const qv_t*)(QKV + (tok0 + q) * ld + h * DH + s * 32 + (lane >> 4) * QE);
+      } else {
+#pragma unroll
+        for (int e = 0; e < QE; ++e) fq[s][e] = (bf16)0.f;
+      }
+    }
+    float mrun = -INFINITY, lsum = 0.f;
+    f32x4 oacc[DT];
+#pragma unroll
+    for (int t = 0; t < DT; ++t) oacc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j0 = 0; j0 < n; j0 += AKB) {
+      // scores of 64 keys: lane holds keys j0 + 16 t + 4 (lane/16) + rr of its query
+      f32x4 st[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        f32x4 a = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < QS; ++s) {
+          const qv_t fk = *(const qv_t*)&sK[(j0 + t * 16 + (lane & 15)) * LDK + s * 32 + (lane >> 4) * QE];
+          if constexpr (DH == 16) a = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fk, fq[s], a, 0, 0, 0);
+          else a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fk, fq[s], a, 0, 0, 0);
+        }
+        st[t] = a;
+      }
+      float bmax = -INFINITY;
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int key = j0 + t * 16 + (lane >> 4) * 4 + rr;
+          const float sv = key < n ? st[t][rr] * scale : -INFINITY;
+          st[t][rr] = sv;
+          bmax = fmaxf(bmax, sv);
+        }
+      bmax = fmaxf(bmax, __shfl_xor(bmax, 16, 64));
+      bmax = fmaxf(bmax, __shfl_xor(bmax, 32, 64));
+      const float mnew = fmaxf(mrun, bmax);
+      const float corr = expf(mrun - mnew);
+      float psum = 0.f;
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const float pv = expf(st[t][rr] - mnew);
+          st[t][rr] = pv;
+          psum += pv;
+        }
+      psum += __shfl_xor(psum, 16, 64);
+      psum += __shfl_xor(psum, 32, 64);
+      lsum = lsum * corr + psum;
+      mrun = mnew;
+#pragma unroll
+      for (int t = 0; t < DT; ++t) oacc[t] = oacc[t] * corr;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        bf16x8 fp;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          fp[rr] = (bf16)st[2 * u][rr];
+          fp[4 + rr] = (bf16)st[2 * u + 1][rr];
+        }
+#pragma unroll
+        for (int t = 0; t < DT; ++t) {
+          const bf16* vrow = &sVt[(t * 16 + (lane & 15)) * LDV + j0];
+          const bf16x4 v0 = *(const bf16x4*)(vrow + (2 * u) * 16 + (lane >> 4) * 4);
+          const bf16x4 v1 = *(const bf16x4*)(vrow + (2 * u + 1) * 16 + (lane >> 4) * 4);
+          bf16x8 fv = {v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
+          oacc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fv, fp, oacc[t], 0, 0, 0);
+        }
+      }
+    }
+    if (qvalid) {
+      const float inv = 1.0f / lsum;
+#pragma unroll
+      for (int t = 0; t < DT; ++t) {
+        const f32x4 v = oacc[t] * inv;
+        bf16x4 hv = {(bf16)v[0], (bf16)v[1], (bf16)v[2], (bf16)v[3]};
+        *(bf16x4*)(O + (tok0 + q) * d + h * DH + t * 16 + (lane >> 4) * 4) = hv;
+      }
+    }
+  }
+}
+
+// Cross-user attention, one wavefront per slot: the slot's K rows of keys and
+// values (K <= 16 tokens, 2d values each) are staged in this wave's LDS
+// region with 16-byte loads, then each lane takes (head, query row) pairs and
+// runs an FP32 softmax over the K keys.
+template <int DH>
+__global__ __launch_bounds__(256) void k_user_attn_wave(StepCtx c, const bf16* __restrict__ QKV,
+                                                        bf16* __restrict__ O, int d, int heads, int kmax) {
+  extern __shared__ __attribute__((aligned(16))) char smem_user[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long s = (long)blockIdx.x * 4 + wave;
+  if (s >= c.total_slots) return;
+  const DevBin& b = c.bins[c.slot_bin[s]];
+  if (b.st->phase == kDone) return;
+  const int n = b.n, l = (int)(s - b.slot_off), K = b.K;
+  const long ld = 3L * d;
+  bf16* sKV = (bf16*)smem_user + (size_t)wave * kmax * 2 * d;   // [K][2d]: k | v
+  const int cpr = 2 * d / 8;                                     // 16-byte chunks per token
+  for (int idx = lane; idx < K * cpr; idx += 64) {
+    const int j = idx / cpr, c8 = (idx - j * cpr) * 8;
+    const long tk = (long)b.tok_off + (long)j * n + l;
+    *(bf16x8*)&sKV[j * 2 * d + c8] = *(const bf16x8*)(QKV + tk * ld + d + c8);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const float scale = 1.0f / sqrtf((float)DH);
+  constexpr int NV = DH / 8;
+  for (int item = lane; item < heads * K; item += 64) {
+    const int h = item / K, kq = item - h * K;
+    const long tq = (long)b.tok_off + (long)kq * n + l;
+    float q[DH];
+#pragma unroll
+    for (int v8 = 0; v8 < NV; ++v8) {
+      const bf16x8 x = *(const bf16x8*)(QKV + tq * ld + h * DH + v8 * 8);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) q[v8 * 8 + e] = (float)x[e] * scale;
+    }
+    float sc[kMaxK];
+    float mx = -INFINITY;
+    for (int j = 0; j < K; ++j) {
+      float a = 0.f;
+#pragma unroll
+      for (int v8 = 0; v8 < NV; ++v8) {
+        const bf16x8 x = *(const bf16x8*)&sKV[j * 2 * d + h * DH + v8 * 8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) a = fmaf(q[v8 * 8 + e], (float)x[e], a);
+      }
+      sc[j] = a;
+      mx = fmaxf(mx, a);
+    }
+    float o[DH];
+#pragma unroll
+    for (int i = 0; i < DH; ++i) o[i] = 0.f;
+    float lsum = 0.f;
+    for (int j = 0; j < K; ++j) {
+      const float pj = expf(sc[j] - mx);
+      lsum += pj;
+#pragma unroll
+      for (int v8 = 0; v8 < NV; ++v8) {
+        const bf16x8 x = *(const bf16x8*)&sKV[j * 2 * d + d + h * DH + v8 * 8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) o[v8 * 8 + e] = fmaf(pj, (float)x[e], o[v8 * 8 + e]);
+      }
+    }
+    const float inv = 1.0f / lsum;
+#pragma unroll
+    for (int v8 = 0; v8 < NV; ++v8) {
+      bf16x8 y;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) y[e] = (bf16)(o[v8 * 8 + e] * inv);
+      *(bf16x8*)(O + tq * d + h * DH + v8 * 8) = y;
+    }
+  }
+}
+
+}  // namespace
+
+size_t row_attn_mfma_lds(int max_n, int dh) {
+  const int nkp = (max_n + AKB - 1) / AKB * AKB;
+  return (size_t)nkp * (dh + 8) * 2 + (size_t)dh * (nkp + 8) * 2;
+}
+
+hipError_t launch_row_attn_mfma(const StepCtx& c, const void* QKV, void* O, int d, int heads, int max_n,
+                                hipStream_t s) {
+  if (c.total_rows == 0) return hipSuccess;
+  const int dh = d / heads;
+  const size_t lds = row_attn_mfma_lds(max_n, dh);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  dim3 grid((unsigned)(c.total_rows * heads)), block(256);
+  // raise the dynamic-LDS limit once per instance (idempotent; allowed while capturing)
+  static bool attr_set[3] = {false, false, false};
+  const int which = dh == 16 ? 0 : (dh == 32 ? 1 : 2);
+  if (!attr_set[which]) {
+    const void* fn = dh == 16 ? (const void*)k_row_attn_mfma<16>
+                              : (dh == 32 ? (const void*)k_row_attn_mfma<32> : (const void*)k_row_attn_mfma<64>);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set[which] = true;
+  }
+  if (dh == 16) hipLaunchKernelGGL((k_row_attn_mfma<16>), grid, block, lds, s, c, (const bf16*)QKV, (bf16*)O, d, heads);
+  else if (dh == 32) hipLaunchKernelGGL((k_row_attn_mfma<32>), grid, block, lds, s, c, (const bf16*)QKV, (bf16*)O, d, heads);
+  else if (dh == 64) hipLaunchKernelGGL((k_row_attn_mfma<64>), grid, block, lds, s, c, (const bf16*)QKV, (bf16*)O, d, heads);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_user_attn_bf16(const StepCtx& c, const void* QKV, void* O, int d, int heads, hipStream_t s) {
+  if (c.total_slots == 0) return hipSuccess;
+  const int kmax = kMaxK;
+  const size_t lds = (size_t)4 * kmax * 2 * d * sizeof(bf16);   // four waves, K <= 16 rows of k|v
+  static bool attr_set[3] = {false, false, false};
+  const int dh = d / heads;
+  const int which = dh == 16 ? 0 : (dh == 32 ? 1 : 2);
+  if (!attr_set[which]) {
+    const void* fn = dh == 16 ? (const void*)k_user_attn_wave<16>
+                              : (dh == 32 ? (const void*)k_user_attn_wave<32> : (const void*)k_user_attn_wave<64>);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set[which] = true;
+  }
+  dim3 grid((unsigned)((c.total_slots + 3) / 4)), block(256);
+  if (dh == 16) hipLaunchKernelGGL((k_user_attn_wave<16>), grid, block, lds, s, c, (const bf16*)QKV, (bf16*)O, d, heads, kmax);
+  else if (dh == 32) hipLaunchKernelGGL((k_user_attn_wave<32>), grid, block, lds, s, c, (const bf16*)QKV, (bf16*)O, d, heads, kmax);
+  else if (dh == 64) hipLaunchKernelGGL((k_user_attn_wave<64>), grid, block, lds, s, c, (const bf16*)QKV, (bf16*)O, d, heads, kmax);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace cider

@@ -53,6 +53,8 @@ CASES = [
     (5, 64, 2, 128, 4),
     (4, 128, 2, 128, 8),
     (2, 256, 1, 256, 8),
+    (3, 64, 1, 192, 6),
+    (2, 128, 1, 384, 12),
 ]
 
 
@@ -260,3 +262,31 @@ def test_invalid_arguments_rejected_before_launch():
         with pytest.raises(P.CiderError) as ei:
             P.cider_decode(y, args["sigma2"], ch, args["K"], args["n"], wh, args["steps"], out)
         assert ei.value.status == P.abi.CIDER_EINVAL
+
+
+def test_every_gemm_tile_gives_identical_decodes():
+    """Tile shapes change only the work split, never an element's accumulation
+    order, so the autotuner cannot change a result."""
+    torch = torch_cuda()
+    P = lib()
+    for (K, n, L, d, h) in [(4, 128, 2, 128, 8), (3, 64, 1, 256, 8), (2, 64, 1, 384, 12)]:
+        cfg = synth.ModelCfg(L, d, h, n_max=128)
+        wh, _ = weights_handle(cfg, seed=51 + d, bias_std=0.02, ln_std=0.05)
+        code = code_of(n, 1000 + n)
+        ch = code_handle(code)
+        bins = synth.make_bins(code, K, 6, 4.0, seed=60 + d)
+        y = _dev(bins.y)
+        ref = None
+        for mode in (0, 1, 2, 3, 4, 5):
+            say(f"tiles d={d} autotune={mode}")
+            opts = P.cider_opts_default(precision=P.CIDER_BF16, autotune=mode)
+            out = torch.zeros(6, K, n, dtype=torch.uint8, device="cuda")
+            lg = torch.zeros(6, K, n, 2, dtype=torch.float32, device="cuda")
+            P.cider_decode_batch([{"y": y[b], "sigma2": float(bins.sigma2[b]), "code": ch, "K": K, "n": n,
+                                   "out_symbols": out[b], "out_logits": lg[b]} for b in range(6)], wh, 8, opts)
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = (out.clone(), lg.clone())
+            else:
+                assert torch.equal(out, ref[0]) and torch.equal(lg, ref[1]), mode
+        assert len(P.cider_tuning_read(wh)) > 0
