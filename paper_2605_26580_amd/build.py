@@ -21,7 +21,7 @@ SOURCES = ["engine.cpp", "kernels_misc.hip", "kernels_gemm.hip", "kernels_attn.h
            "server.cpp"]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-x", "hip",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-x", "hip", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result", "-I" + INCLUDE, "-I" + CSRC,
 ]

@@ -151,6 +151,7 @@ hipError_t launch_layernorm(int prec, long T, int d, const float* R, const float
                             hipStream_t s);
 hipError_t launch_gemm_bf16(int epi, const GemmArgs& g, const Mat& W, hipStream_t s, int tile);
 int gemm_tile_count(int epi, int N, bool ln);
+hipError_t launch_mlp_bf16(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s);
 hipError_t launch_row_attn_mfma(const StepCtx& c, const void* QKV, void* O, int d, int heads, int max_n,
                                 hipStream_t s);
 hipError_t launch_user_attn_bf16(const StepCtx& c, const void* QKV, void* O, int d, int heads, hipStream_t s);

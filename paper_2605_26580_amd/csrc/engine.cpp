@@ -383,13 +383,20 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
     next_ln(g, L.ln3_g, L.ln3_b);
     TIMED("gemm_o_user", gemm(kEpiResid, g, L.Wo_u));
     if (!fused_ln) TIMED("layernorm", ln(L.ln3_g, L.ln3_b));
-    g = GemmArgs{}; g.M = T;
-    g.N = F; g.Kd = d; g.A = k.XN; g.bias = L.b1; g.out = k.HID;
-    TIMED("gemm_mlp_up", gemm(kEpiGelu, g, L.W1));
-    g = GemmArgs{}; g.M = T;
-    g.N = d; g.Kd = F; g.A = k.HID; g.bias = L.b2; g.R = k.R;
-    if (l + 1 < m.n_layers) next_ln(g, m.layer[l + 1].ln1_g, m.layer[l + 1].ln1_b);
-    TIMED("gemm_mlp_down", gemm(kEpiResid, g, L.W2));
+    if (fused_ln) {
+      // BF16: up, GELU and down in one kernel, hidden layer on chip
+      g = GemmArgs{}; g.M = T;
+      g.N = d; g.Kd = d; g.A = k.XN; g.bias = L.b2; g.R = k.R;
+      if (l + 1 < m.n_layers) next_ln(g, m.layer[l + 1].ln1_g, m.layer[l + 1].ln1_b);
+      TIMED("mlp_fused", launch_mlp_bf16(g, L.W1, L.b1, L.W2, F, s));
+    } else {
+      g = GemmArgs{}; g.M = T;
+      g.N = F; g.Kd = d; g.A = k.XN; g.bias = L.b1; g.out = k.HID;
+      TIMED("gemm_mlp_up", gemm(kEpiGelu, g, L.W1));
+      g = GemmArgs{}; g.M = T;
+      g.N = d; g.Kd = F; g.A = k.HID; g.bias = L.b2; g.R = k.R;
+      TIMED("gemm_mlp_down", gemm(kEpiResid, g, L.W2));
+    }
   }
   TIMED("final_proj", launch_final_proj(c, w->ew, k, s));
   TIMED("module_b", launch_module_b(c, k, s));
@@ -416,13 +423,6 @@ int autotune_forward(cider_weights* w, const Run& r, hipStream_t s) {
   g = GemmArgs{}; g.M = T; g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_r; g.R = k.R;
   g.ln_g = L.ln2_g; g.ln_b = L.ln2_b; g.out = k.XN;
   if ((rc = tune_gemm(w, "gemm_o_ln", kEpiResid, g, L.Wo_r, s))) return rc;
-  g = GemmArgs{}; g.M = T; g.N = F; g.Kd = d; g.A = k.XN; g.bias = L.b1; g.out = k.HID;
-  if ((rc = tune_gemm(w, "gemm_mlp_up", kEpiGelu, g, L.W1, s))) return rc;
-  g = GemmArgs{}; g.M = T; g.N = d; g.Kd = F; g.A = k.HID; g.bias = L.b2; g.R = k.R;
-  g.ln_g = L.ln1_g; g.ln_b = L.ln1_b; g.out = k.XN;
-  if ((rc = tune_gemm(w, "gemm_mlp_down_ln", kEpiResid, g, L.W2, s))) return rc;
-  g.ln_g = nullptr; g.ln_b = nullptr; g.out = nullptr;
-  if ((rc = tune_gemm(w, "gemm_mlp_down", kEpiResid, g, L.W2, s))) return rc;
   return CIDER_OK;
 }
 
@@ -898,6 +898,7 @@ int cider_step_debug(const uint8_t* X_in, uint8_t* X_out, const float* y, float 
   char* base = (char*)r.ctx.bins - L.off_bins;
   uint8_t* Xw = (uint8_t*)(base + L.off_X);
   HIPCHK(hipMemcpyAsync(Xw, X_in, (size_t)K * n, hipMemcpyDeviceToDevice, s));
+  if (o.autotune >= 2) r.forced_tile = o.autotune - 2;
   r.ctx.gamma_override = gamma;
   r.ctx.reveal_override = reveal_count;
   r.ctx.first_override = first ? 1 : 0;

@@ -24,6 +24,16 @@ __device__ __forceinline__ float wave_sum(float v) {
 
 __device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
 
+// The dispatcher sends workgroup b to XCD b % 8, and each XCD has its own L2.
+// xcd_logical maps b to a logical id so that XCD x runs one contiguous range
+// of logical ids; workgroups adjacent in logical order (the heads of one row,
+// the column tiles of one token tile) then share an L2 and read their common
+// inputs from HBM once.  A bijection on [0, nb) for any nb.
+__device__ __forceinline__ int xcd_logical(int b, int nb) {
+  const int x = b & 7, i = b >> 3, q = nb >> 3, rem = nb & 7;
+  return x * q + min(x, rem) + i;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -107,105 +117,14 @@ struct GemmSmem {
   static constexpr size_t bytes = loop > stage ? loop : stage;
 };
 
-template <int BM, int BN, int BK, int EPI>
-__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, const bf16* __restrict__ W) {
-  constexpr int TI = BN / 32;  // column blocks per wave
-  constexpr int TJ = BM / 32;  // token blocks per wave
-  constexpr int LDK = BK + GPAD;
-  __shared__ __attribute__((aligned(16))) char smem[GemmSmem<BM, BN, BK>::bytes];
-  bf16* sA = (bf16*)smem;                       // [2][BM][LDK]
-  bf16* sW = sA + 2 * BM * LDK;                 // [2][BN][LDK]
-  float* sC = (float*)smem;                     // [BM][BN + 4] after the K loop
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const long m0 = (long)blockIdx.x * BM;
-  const int n0 = blockIdx.y * BN;
-  const int Kd = g.Kd;
-  const bf16* A = (const bf16*)g.A;
-  const int wn = (wave >> 1) * (BN / 2), wm = (wave & 1) * (BM / 2);
-
-  constexpr int CPR = BK / 8;                    // 16-byte chunks per row of a slice
-  constexpr int ACH = (BM * CPR + 255) / 256;
-  constexpr int WCH = (BN * CPR + 255) / 256;
-  bf16x8 ra[ACH], rw[WCH];
-  auto fetch = [&](int k0) {
-#pragma unroll
-    for (int c = 0; c < ACH; ++c) {
-      const int idx = tid + c * 256, row = idx / CPR, kc = (idx % CPR) * 8;
-      const long gm = m0 + row;
-      if (row < BM && gm < g.M) ra[c] = *(const bf16x8*)(A + gm * Kd + k0 + kc);
-      else ra[c] = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
-    }
-#pragma unroll
-    for (int c = 0; c < WCH; ++c) {
-      const int idx = tid + c * 256, row = idx / CPR, kc = (idx % CPR) * 8;
-      if (row < BN) rw[c] = *(const bf16x8*)(W + (long)(n0 + row) * Kd + k0 + kc);
-    }
-  };
-  auto stash = [&](int buf) {
-#pragma unroll
-    for (int c = 0; c < ACH; ++c) {
-      const int idx = tid + c * 256, row = idx / CPR, kc = (idx % CPR) * 8;
-      if (row < BM) *(bf16x8*)&sA[(buf * BM + row) * LDK + kc] = ra[c];
-    }
-#pragma unroll
-    for (int c = 0; c < WCH; ++c) {
-      const int idx = tid + c * 256, row = idx / CPR, kc = (idx % CPR) * 8;
-      if (row < BN) *(bf16x8*)&sW[(buf * BN + row) * LDK + kc] = rw[c];
-    }
-  };
-
-  f32x4 acc[TI][TJ];
-#pragma unroll
-  for (int i = 0; i < TI; ++i)
-#pragma unroll
-    for (int j = 0; j < TJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  const int nk = Kd / BK;
-  fetch(0);
-  stash(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) fetch((kt + 1) * BK);
-#pragma unroll
-    for (int ks = 0; ks < BK; ks += 32) {
-      bf16x8 fw[TI], fa[TJ];
-#pragma unroll
-      for (int i = 0; i < TI; ++i)
-        fw[i] = *(const bf16x8*)&sW[(buf * BN + wn + i * 16 + (lane & 15)) * LDK + ks + (lane >> 4) * 8];
-#pragma unroll
-      for (int j = 0; j < TJ; ++j)
-        fa[j] = *(const bf16x8*)&sA[(buf * BM + wm + j * 16 + (lane & 15)) * LDK + ks + (lane >> 4) * 8];
-#pragma unroll
-      for (int i = 0; i < TI; ++i)
-#pragma unroll
-        for (int j = 0; j < TJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fw[i], fa[j], acc[i][j], 0, 0, 0);
-    }
-    if (kt + 1 < nk) stash(buf ^ 1);
-    __syncthreads();
-  }
-
-  // stage v = acc + bias: lane holds columns wn + 16 i + 4 (lane/16) + r of token wm + 16 j + lane%16
+// Row pass of the GEMM epilogues: sC holds the BM x BN FP32 tile (bias
+// added, row stride BN + 4).  A lane group of LPR lanes owns one token row per
+// pass and covers its BN columns in 4-column groups; all loads of a chunk of
+// passes are issued before any of them is used, so global-memory latency
+// overlaps.
+template <int BM, int BN, int EPI>
+__device__ __forceinline__ void row_pass(const float* sC, long m0, int n0, const GemmArgs& g, int wave, int lane) {
   constexpr int LDC = BN + 4;
-#pragma unroll
-  for (int i = 0; i < TI; ++i) {
-    const int nl = wn + i * 16 + (lane >> 4) * 4;
-    f32x4 bias = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (g.bias) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) bias[r] = g.bias[n0 + nl + r];
-    }
-#pragma unroll
-    for (int j = 0; j < TJ; ++j) {
-      const int ml = wm + j * 16 + (lane & 15);
-      *(f32x4*)&sC[ml * LDC + nl] = acc[i][j] + bias;
-    }
-  }
-  __syncthreads();
-
-  // row pass: a lane group of LPR lanes owns one token row per pass and covers its
-  // BN columns in 4-column groups; all loads of a chunk of passes are issued
-  // before any of them is used, so the global-memory latency overlaps.
   constexpr int CG = BN / 4;                     // 4-column groups per row
   constexpr int LPR = CG <= 16 ? 16 : (CG <= 32 ? 32 : 64);   // lanes per row, a power of two
   constexpr int RPI = 64 / LPR;                  // rows per wave pass
@@ -307,9 +226,110 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, const bf16* __res
   }
 }
 
+template <int BM, int BN, int BK, int EPI>
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, const bf16* __restrict__ W) {
+  constexpr int TI = BN / 32;  // column blocks per wave
+  constexpr int TJ = BM / 32;  // token blocks per wave
+  constexpr int LDK = BK + GPAD;
+  __shared__ __attribute__((aligned(16))) char smem[GemmSmem<BM, BN, BK>::bytes];
+  bf16* sA = (bf16*)smem;                       // [2][BM][LDK]
+  bf16* sW = sA + 2 * BM * LDK;                 // [2][BN][LDK]
+  float* sC = (float*)smem;                     // [BM][BN + 4] after the K loop
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int nN = g.N / BN;
+  const int lb = xcd_logical((int)blockIdx.x, (int)gridDim.x);
+  const long m0 = (long)(lb / nN) * BM;
+  const int n0 = (lb - (lb / nN) * nN) * BN;
+  const int Kd = g.Kd;
+  const bf16* A = (const bf16*)g.A;
+  const int wn = (wave >> 1) * (BN / 2), wm = (wave & 1) * (BM / 2);
+
+  constexpr int CPR = BK / 8;                    // 16-byte chunks per row of a slice
+  constexpr int ACH = (BM * CPR + 255) / 256;
+  constexpr int WCH = (BN * CPR + 255) / 256;
+  bf16x8 ra[ACH], rw[WCH];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int c = 0; c < ACH; ++c) {
+      const int idx = tid + c * 256, row = idx / CPR, kc = (idx % CPR) * 8;
+      const long gm = m0 + row;
+      if (row < BM && gm < g.M) ra[c] = *(const bf16x8*)(A + gm * Kd + k0 + kc);
+      else ra[c] = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int c = 0; c < WCH; ++c) {
+      const int idx = tid + c * 256, row = idx / CPR, kc = (idx % CPR) * 8;
+      if (row < BN) rw[c] = *(const bf16x8*)(W + (long)(n0 + row) * Kd + k0 + kc);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int c = 0; c < ACH; ++c) {
+      const int idx = tid + c * 256, row = idx / CPR, kc = (idx % CPR) * 8;
+      if (row < BM) *(bf16x8*)&sA[(buf * BM + row) * LDK + kc] = ra[c];
+    }
+#pragma unroll
+    for (int c = 0; c < WCH; ++c) {
+      const int idx = tid + c * 256, row = idx / CPR, kc = (idx % CPR) * 8;
+      if (row < BN) *(bf16x8*)&sW[(buf * BN + row) * LDK + kc] = rw[c];
+    }
+  };
+
+  f32x4 acc[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int nk = Kd / BK;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) fetch((kt + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 32) {
+      bf16x8 fw[TI], fa[TJ];
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+        fw[i] = *(const bf16x8*)&sW[(buf * BN + wn + i * 16 + (lane & 15)) * LDK + ks + (lane >> 4) * 8];
+#pragma unroll
+      for (int j = 0; j < TJ; ++j)
+        fa[j] = *(const bf16x8*)&sA[(buf * BM + wm + j * 16 + (lane & 15)) * LDK + ks + (lane >> 4) * 8];
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fw[i], fa[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) stash(buf ^ 1);
+    __syncthreads();
+  }
+
+  // stage v = acc + bias: lane holds columns wn + 16 i + 4 (lane/16) + r of token wm + 16 j + lane%16
+  constexpr int LDC = BN + 4;
+#pragma unroll
+  for (int i = 0; i < TI; ++i) {
+    const int nl = wn + i * 16 + (lane >> 4) * 4;
+    f32x4 bias = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (g.bias) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bias[r] = g.bias[n0 + nl + r];
+    }
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
+      const int ml = wm + j * 16 + (lane & 15);
+      *(f32x4*)&sC[ml * LDC + nl] = acc[i][j] + bias;
+    }
+  }
+  __syncthreads();
+
+  row_pass<BM, BN, EPI>(sC, m0, n0, g, wave, lane);
+}
+
 template <int BM, int BN, int BK>
 hipError_t gemm_bf16_t(int epi, const GemmArgs& g, const bf16* W, hipStream_t s) {
-  dim3 grid((unsigned)((g.M + BM - 1) / BM), (unsigned)(g.N / BN)), block(256);
+  dim3 grid((unsigned)(((g.M + BM - 1) / BM) * (g.N / BN))), block(256);
   switch (epi) {
     case kEpiStore: hipLaunchKernelGGL((k_gemm_bf16<BM, BN, BK, kEpiStore>), grid, block, 0, s, g, W); break;
     case kEpiGelu: hipLaunchKernelGGL((k_gemm_bf16<BM, BN, BK, kEpiGelu>), grid, block, 0, s, g, W); break;
@@ -382,6 +402,194 @@ hipError_t launch_gemm_bf16(int epi, const GemmArgs& g, const Mat& W, hipStream_
 }
 
 // ---------------------------------------------------------------------------
+// Fused MLP block: R += W2 GELU(W1 XN + b1) + b2 for a tile of BM tokens, with
+// the 4d-wide hidden layer kept on chip.  The XN tile sits in LDS; the hidden
+// layer is produced FCH columns at a time (up GEMM, GELU, BF16 into LDS) and
+// consumed at once by the down GEMM, whose BM x D accumulators stay in
+// registers across chunks.  The weight chunks W1[c:c+FCH][:] and
+// W2[:][c:c+FCH] are staged in LDS with 16-byte loads, and the next chunk is
+// fetched into registers while the current one is multiplied.  The epilogue is
+// the GEMM row pass: residual add and, with ln_g set, the next LayerNorm.
+namespace {
+
+template <int BM, int D, int FCH>
+struct MlpSmem {
+  static constexpr size_t a = (size_t)BM * (D + GPAD) * sizeof(bf16);
+  static constexpr size_t h = (size_t)BM * (FCH + GPAD) * sizeof(bf16);
+  static constexpr size_t w1 = (size_t)FCH * (D + GPAD) * sizeof(bf16);
+  static constexpr size_t w2 = (size_t)D * (FCH + GPAD) * sizeof(bf16);
+  static constexpr size_t c = (size_t)BM * (D + 4) * sizeof(float);
+  static constexpr size_t loop = a + h + w1 + w2;
+  static constexpr size_t bytes = loop > c ? loop : c;
+};
+
+template <int BM, int D, int FCH, int EPI>
+__global__ __launch_bounds__(256) void k_mlp_bf16(GemmArgs g, const bf16* __restrict__ W1, const float* __restrict__ b1,
+                                                  const bf16* __restrict__ W2, int F) {
+  constexpr int LDA = D + GPAD, LDH = FCH + GPAD, LDW1 = D + GPAD, LDW2 = FCH + GPAD;
+  constexpr int TI1 = FCH / 32, TJ1 = BM / 32;   // up GEMM: (FCH/2) hidden x (BM/2) tokens per wave
+  constexpr int TI2 = D / 32, TJ2 = BM / 32;     // down GEMM: (D/2) outputs x (BM/2) tokens per wave
+  constexpr int PW1 = FCH * D / 8 / 256;         // 16-byte chunks per thread of a W1 chunk
+  constexpr int PW2 = D * FCH / 8 / 256;
+  __shared__ __attribute__((aligned(16))) char smem[MlpSmem<BM, D, FCH>::bytes];
+  bf16* sA = (bf16*)smem;
+  bf16* sH = sA + BM * LDA;
+  bf16* sW1 = sH + BM * LDH;
+  bf16* sW2 = sW1 + FCH * LDW1;
+  float* sC = (float*)smem;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const long m0 = (long)blockIdx.x * BM;
+  const bf16* A = (const bf16*)g.A;
+
+  bf16x8 pw1[PW1], pw2[PW2];
+  auto fetchW = [&](int c0) {
+#pragma unroll
+    for (int i = 0; i < PW1; ++i) {
+      const int idx = tid + i * 256, row = idx / (D / 8), kc = (idx - row * (D / 8)) * 8;
+      pw1[i] = *(const bf16x8*)(W1 + (long)(c0 + row) * D + kc);
+    }
+#pragma unroll
+    for (int i = 0; i < PW2; ++i) {
+      const int idx = tid + i * 256, row = idx / (FCH / 8), kc = (idx - row * (FCH / 8)) * 8;
+      pw2[i] = *(const bf16x8*)(W2 + (long)row * F + c0 + kc);
+    }
+  };
+  auto stashW = [&]() {
+#pragma unroll
+    for (int i = 0; i < PW1; ++i) {
+      const int idx = tid + i * 256, row = idx / (D / 8), kc = (idx - row * (D / 8)) * 8;
+      *(bf16x8*)&sW1[row * LDW1 + kc] = pw1[i];
+    }
+#pragma unroll
+    for (int i = 0; i < PW2; ++i) {
+      const int idx = tid + i * 256, row = idx / (FCH / 8), kc = (idx - row * (FCH / 8)) * 8;
+      *(bf16x8*)&sW2[row * LDW2 + kc] = pw2[i];
+    }
+  };
+
+  fetchW(0);
+  constexpr int CPR = D / 8;
+  for (int idx = tid; idx < BM * CPR; idx += 256) {
+    const int row = idx / CPR, kc = (idx - row * CPR) * 8;
+    const long gm = m0 + row;
+    bf16x8 v = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    if (gm < g.M) v = *(const bf16x8*)(A + gm * D + kc);
+    *(bf16x8*)&sA[row * LDA + kc] = v;
+  }
+  stashW();
+  __syncthreads();
+
+  f32x4 acc2[TI2][TJ2];
+#pragma unroll
+  for (int i = 0; i < TI2; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ2; ++j) acc2[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int wn1 = (wave >> 1) * (FCH / 2), wm = (wave & 1) * (BM / 2), wn2 = (wave >> 1) * (D / 2);
+
+  for (int c0 = 0; c0 < F; c0 += FCH) {
+    const bool more = c0 + FCH < F;
+    if (more) fetchW(c0 + FCH);
+    // up: H[token][j] = GELU(sum_k XN[token][k] W1[c0 + j][k] + b1[c0 + j])
+    f32x4 acc1[TI1][TJ1];
+#pragma unroll
+    for (int i = 0; i < TI1; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ1; ++j) acc1[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < D; ks += 32) {
+      bf16x8 fw[TI1], fa[TJ1];
+#pragma unroll
+      for (int i = 0; i < TI1; ++i) fw[i] = *(const bf16x8*)&sW1[(wn1 + i * 16 + (lane & 15)) * LDW1 + ks + (lane >> 4) * 8];
+#pragma unroll
+      for (int j = 0; j < TJ1; ++j) fa[j] = *(const bf16x8*)&sA[(wm + j * 16 + (lane & 15)) * LDA + ks + (lane >> 4) * 8];
+#pragma unroll
+      for (int i = 0; i < TI1; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ1; ++j) acc1[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fw[i], fa[j], acc1[i][j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < TI1; ++i) {
+      const int hn = wn1 + i * 16 + (lane >> 4) * 4;
+      f32x4 bb;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bb[r] = b1[c0 + hn + r];
+#pragma unroll
+      for (int j = 0; j < TJ1; ++j) {
+        const int ml = wm + j * 16 + (lane & 15);
+        const f32x4 v = acc1[i][j] + bb;
+        bf16x4 hv = {(bf16)gelu_f(v[0]), (bf16)gelu_f(v[1]), (bf16)gelu_f(v[2]), (bf16)gelu_f(v[3])};
+        *(bf16x4*)&sH[ml * LDH + hn] = hv;
+      }
+    }
+    __syncthreads();
+    // down: acc2[token][o] += sum_j H[token][j] W2[o][c0 + j]
+#pragma unroll
+    for (int ks = 0; ks < FCH; ks += 32) {
+      bf16x8 fw[TI2], fh[TJ2];
+#pragma unroll
+      for (int i = 0; i < TI2; ++i) fw[i] = *(const bf16x8*)&sW2[(wn2 + i * 16 + (lane & 15)) * LDW2 + ks + (lane >> 4) * 8];
+#pragma unroll
+      for (int j = 0; j < TJ2; ++j) fh[j] = *(const bf16x8*)&sH[(wm + j * 16 + (lane & 15)) * LDH + ks + (lane >> 4) * 8];
+#pragma unroll
+      for (int i = 0; i < TI2; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ2; ++j) acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fw[i], fh[j], acc2[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+    if (more) {
+      stashW();
+      __syncthreads();
+    }
+  }
+
+  // stage out = acc2 + b2 (sC overlaps the loop buffers, no longer read)
+  constexpr int LDC = D + 4;
+#pragma unroll
+  for (int i = 0; i < TI2; ++i) {
+    const int nl = wn2 + i * 16 + (lane >> 4) * 4;
+    f32x4 bias;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bias[r] = g.bias[nl + r];
+#pragma unroll
+    for (int j = 0; j < TJ2; ++j) {
+      const int ml = wm + j * 16 + (lane & 15);
+      *(f32x4*)&sC[ml * LDC + nl] = acc2[i][j] + bias;
+    }
+  }
+  __syncthreads();
+  row_pass<BM, D, EPI>(sC, m0, 0, g, wave, lane);
+}
+
+template <int BM, int D, int FCH>
+hipError_t mlp_t(bool ln, const GemmArgs& g, const bf16* W1, const float* b1, const bf16* W2, int F, hipStream_t s) {
+  if (F % FCH != 0) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((g.M + BM - 1) / BM)), block(256);
+  if (ln) hipLaunchKernelGGL((k_mlp_bf16<BM, D, FCH, kEpiResidLN>), grid, block, 0, s, g, W1, b1, W2, F);
+  else hipLaunchKernelGGL((k_mlp_bf16<BM, D, FCH, kEpiResid>), grid, block, 0, s, g, W1, b1, W2, F);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// R += W2 GELU(W1 XN + b1) + b2 (g.A = XN, g.bias = b2, g.R = R, and with
+// g.ln_g set the next LayerNorm into g.out).
+hipError_t launch_mlp_bf16(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s) {
+  if (g.M == 0) return hipSuccess;
+  const bool ln = g.ln_g != nullptr;
+  switch (g.N) {
+    case 64: return mlp_t<64, 64, 64>(ln, g, W1.b16, b1, W2.b16, F, s);
+    case 128: return mlp_t<64, 128, 64>(ln, g, W1.b16, b1, W2.b16, F, s);
+    case 192: return mlp_t<64, 192, 64>(ln, g, W1.b16, b1, W2.b16, F, s);
+    case 256: return mlp_t<64, 256, 64>(ln, g, W1.b16, b1, W2.b16, F, s);
+    case 320: return mlp_t<32, 320, 64>(ln, g, W1.b16, b1, W2.b16, F, s);
+    case 384: return mlp_t<32, 384, 64>(ln, g, W1.b16, b1, W2.b16, F, s);
+    case 448: return mlp_t<32, 448, 32>(ln, g, W1.b16, b1, W2.b16, F, s);
+    case 512: return mlp_t<32, 512, 32>(ln, g, W1.b16, b1, W2.b16, F, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Row attention on MFMA.  One workgroup per (row, head): the row's keys K
 // [key][dh] and transposed values V^T [dh][key] for that head are loaded into
 // LDS once (n * dh * 4 bytes <= 128 KB), then each wave takes 16-query tiles
@@ -403,7 +611,8 @@ __global__ __launch_bounds__(256) void k_row_attn_mfma(StepCtx c, const bf16* __
   constexpr int LDK = DH + 8;
   typedef __bf16 qv_t __attribute__((__vector_size__(QE * sizeof(__bf16))));
   extern __shared__ __attribute__((aligned(16))) char smem_attn[];
-  const int r = blockIdx.x / heads, h = blockIdx.x - (blockIdx.x / heads) * heads;
+  const int lb = xcd_logical((int)blockIdx.x, (int)gridDim.x);
+  const int r = lb / heads, h = lb - (lb / heads) * heads;
   const DevBin& b = c.bins[c.row_bin[r]];
   if (b.st->phase == kDone) return;
   const int n = b.n, k = r - b.row_off;
@@ -414,7 +623,8 @@ __global__ __launch_bounds__(256) void k_row_attn_mfma(StepCtx c, const bf16* __
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const long tok0 = (long)b.tok_off + (long)k * n;
   const long ld = 3L * d;
-  const float scale = 1.0f / sqrtf((float)DH);
+  // scores are scaled by log2(e)/sqrt(dh) so the softmax uses exp2 (one v_exp_f32)
+  const float scale = 1.4426950408889634f / sqrtf((float)DH);
 
   for (int idx = tid; idx < nkp * (DH / 8); idx += 256) {
     const int key = idx / (DH / 8), c8 = (idx - key * (DH / 8)) * 8;
@@ -474,13 +684,13 @@ __global__ __launch_bounds__(256) void k_row_attn_mfma(StepCtx c, const bf16* __
       bmax = fmaxf(bmax, __shfl_xor(bmax, 16, 64));
       bmax = fmaxf(bmax, __shfl_xor(bmax, 32, 64));
       const float mnew = fmaxf(mrun, bmax);
-      const float corr = expf(mrun - mnew);
+      const float corr = exp2f(mrun - mnew);
       float psum = 0.f;
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-          const float pv = expf(st[t][rr] - mnew);
+          const float pv = exp2f(st[t][rr] - mnew);
           st[t][rr] = pv;
           psum += pv;
         }

@@ -264,6 +264,41 @@ def test_invalid_arguments_rejected_before_launch():
         assert ei.value.status == P.abi.CIDER_EINVAL
 
 
+@pytest.mark.parametrize("K,n,L,d,h", [(4, 128, 2, 128, 8), (3, 64, 1, 256, 8), (2, 64, 1, 384, 12), (2, 32, 1, 64, 4)])
+def test_every_gemm_tile_teacher_forced(K, n, L, d, h):
+    """Each GEMM tile shape, forced everywhere, meets the BF16 tolerance against
+    the oracle and matches the default tile bit for bit."""
+    torch = torch_cuda()
+    P = lib()
+    cfg = synth.ModelCfg(L, d, h, n_max=max(n, 64))
+    wh, w = weights_handle(cfg, seed=71 + d, bias_std=0.02, ln_std=0.05)
+    code = code_of(n, 1000 + n)
+    ch = code_handle(code)
+    bins = synth.make_bins(code, K, 1, 4.0, seed=3 + K)
+    y, s2 = bins.y[0], float(bins.sigma2[0])
+    _, p = evidence(y.astype(np.float64), s2, K)
+    rng = np.random.default_rng(5)
+    X = rng.integers(0, 2, size=(K, n)).astype(np.uint8)
+    X[rng.random((K, n)) < 0.5] = 2
+    gamma = float((X == 2).mean())
+    ref = denoise(X, p, code, w, L, h, gamma)
+    base = None
+    for tile in (0, 1, 2, 3, 0):
+        say(f"forced tile {tile} d={d}")
+        opts = P.cider_opts_default(precision=P.CIDER_BF16, autotune=2 + tile)
+        lg = torch.zeros(K, n, 2, dtype=torch.float32, device="cuda")
+        P.cider_step_debug(_dev(X), None, _dev(y), s2, ch, K, n, wh, gamma, 0, 0, opts, out_logits=lg)
+        torch.cuda.synchronize()
+        got = lg.cpu().numpy()
+        err = rel_err(got, ref["logits"])
+        print(f"  tile {tile}: err {err:.2e}")
+        assert err <= TOL["bf16"], (tile, err)
+        if base is None:
+            base = got
+        else:
+            assert np.array_equal(got, base), f"tile {tile} differs from tile 0"
+
+
 def test_every_gemm_tile_gives_identical_decodes():
     """Tile shapes change only the work split, never an element's accumulation
     order, so the autotuner cannot change a result."""
