@@ -1,20 +1,27 @@
 """Throughput benchmark of the CIDER refinement path on one MI355X.
 
-One benchmark step = one complete decode (all refinement steps, final pass)
-of a batch of synthetic bins through cider_decode_batch.  Default workload
-(c2): K=4 users, binary (3,6)-regular LDPC n=128, Eb/N0 cycling {2,4,6} dB,
-denoiser L=4 d=128 h=8 with seeded N(0, 0.02) weights, T=16, 256 bins per
-batch, BF16 operands with FP32 accumulation.  Prints one JSON line.
+One benchmark step = one complete decode (every refinement step, the final
+pass and any remask rounds) of one batch of synthetic bins through
+cider_decode_batch.  Default workload (c2): K=4 users, binary (3,6)-regular
+LDPC n=128, Eb/N0 cycling {2,4,6} dB, denoiser L=4 d=128 h=8 with seeded
+N(0, 0.02) weights, T=16, 256 bins per batch, BF16 operands with FP32
+accumulation.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py --workload c1 --precision fp32     (small FP32 case)
+    python bench.py --workload c3                      (K=8, n=256, remasking)
+    python bench.py --workload c4                      (4096 ragged bins, one packed pass)
+    python bench.py --workload c5 --load 0.5,0.9       (served: Poisson arrivals)
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
+import re
 import sys
+import threading
 import time
 
 import numpy as np
@@ -28,8 +35,14 @@ PEAK = {"bf16": 2500.0, "fp32": 157.3, "fp8": 5000.0}   # dense TFLOP/s, MI355X 
 HBM_PEAK = 8000.0                                        # GB/s
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle, one single-threaded worker process per core
+
 def _oracle_worker(args):
-    """CPU baseline task: decode one bin with the FP64 oracle (single thread)."""
     name, b = args
     import synth
     from oracle.decode import DecodeOpts, decode_bin
@@ -40,107 +53,145 @@ def _oracle_worker(args):
     t0 = time.perf_counter()
     res = decode_bin(bins.y[b], float(bins.sigma2[b]), code, wl.K, w, wl.model.n_layers, wl.model.heads, wl.T,
                      DecodeOpts(remask=wl.remask, remask_thr=wl.remask_thr, remask_max_rounds=wl.remask_max_rounds))
-    gaps = [g for s in res.steps for g in s["gaps"].values()] + [f["gap_q"] for f in res.finals]
-    return b, res.X, time.perf_counter() - t0, min([g for g in gaps if g > 0] + [float("inf")])
+    return b, res.X, time.perf_counter() - t0
 
 
-def cpu_baseline(name: str, n_bins: int, workers: int):
+def _oracle_step_worker(args):
+    """One denoiser forward of one bin (for workloads whose full decode is too
+    long to time on the host): returns seconds per forward."""
+    K, n, model, weight_seed, code_seed = args
+    import synth
+    from oracle.denoiser import denoise
+    from oracle.evidence import evidence
+    code = synth.regular_ldpc(n, seed=code_seed)
+    b = synth.make_bins(code, K, 1, 4.0, seed=7)
+    w = synth.unpack_weights(synth.make_weights(model, weight_seed), model)
+    _, p = evidence(b.y[0].astype(np.float64), float(b.sigma2[0]), K)
+    X = np.full((K, n), 2, np.uint8)
+    t0 = time.perf_counter()
+    denoise(X, p, code, w, model.n_layers, model.heads, 1.0)
+    return time.perf_counter() - t0
+
+
+def _pool(fn, tasks, workers):
     import multiprocessing as mp
-    os.environ["OMP_NUM_THREADS"] = "1"
-    os.environ["OPENBLAS_NUM_THREADS"] = "1"
-    os.environ["MKL_NUM_THREADS"] = "1"
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
     ctx = mp.get_context("spawn")
     t0 = time.perf_counter()
     with ctx.Pool(workers) as pool:
-        out = pool.map(_oracle_worker, [(name, b) for b in range(n_bins)])
-    wall = time.perf_counter() - t0
-    return out, wall
+        out = pool.map(fn, tasks)
+    return out, time.perf_counter() - t0
 
 
-def algorithmic(wl, es: int):
-    """Per token and per forward: model FLOP, and FLOP / algorithmic HBM bytes
-    of each kernel role (es = bytes per element of the compute type)."""
-    d, L, F = wl.model.d, wl.model.n_layers, wl.model.d_ff
-    n, K = wl.n, wl.K
+# ---------------------------------------------------------------------------
+# algorithmic FLOP and bytes per token of each kernel role
+
+def algorithmic(model, n, K, es: int):
+    d, L, F = model.d, model.n_layers, model.d_ff
     per_tok = L * (32 * d * d + 4 * n * d + 4 * K * d) + 6 * d * d + 12 * d
     flop = {
         "gemm_gate1": 2 * d * 2 * d, "gemm_gate2": 2 * d * d,
         "gemm_qkv_row": 2 * d * 3 * d, "gemm_o_row": 2 * d * d,
         "gemm_qkv_user": 2 * d * 3 * d, "gemm_o_user": 2 * d * d,
-        "gemm_mlp_up": 2 * d * F, "gemm_mlp_down": 2 * F * d,
+        "gemm_mlp_up": 2 * d * F, "gemm_mlp_down": 2 * F * d, "mlp_fused": 4 * d * F,
         "attn_row": 4 * n * d, "attn_user": 4 * K * d,
     }
-    # bytes each kernel must move at minimum (inputs read once, outputs written once);
-    # residual updates read and write the FP32 stream and, with the next LayerNorm
-    # fused, also write its compute-type copy
+    # minimum bytes: inputs read once, outputs written once; residual updates read and
+    # write the FP32 stream and (BF16) write the next LayerNorm's compute-type copy
     byt = {
         "gemm_gate1": (2 * d + d) * es, "gemm_gate2": d * es + 3 * 4 * d + d * es,
         "gemm_qkv_row": (d + 3 * d) * es, "gemm_qkv_user": (d + 3 * d) * es,
         "gemm_o_row": d * es + 8 * d + d * es, "gemm_o_user": d * es + 8 * d + d * es,
         "gemm_mlp_up": (d + F) * es, "gemm_mlp_down": F * es + 8 * d + d * es,
+        "mlp_fused": d * es + 8 * d + d * es,
         "attn_row": (3 * d + d) * es, "attn_user": (3 * d + d) * es,
         "layernorm": 4 * d + d * es,
     }
     return per_tok, flop, byt
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2")
-    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
-    ap.add_argument("--cpu-bins", type=int, default=16)
-    ap.add_argument("--plain-bins", type=int, default=32)
-    ap.add_argument("--no-cpu", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
-              "bins are independent, so N GPUs would each run this engine on a disjoint bin stream.",
-              file=sys.stderr)
-        sys.exit(2)
+KERNEL_SOURCE = {"mlp_fused": "kernels_fast.hip", "attn_row": "kernels_fast.hip", "attn_user": "kernels_fast.hip"}
 
+
+def _measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch from a committed rocprofv3 PMC summary, if it was
+    taken on the kernel source as it stands (its SHA-1 recorded there)."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_{kernel}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    m_s = re.search(r"source_sha1:\s*([0-9a-f]{40})", txt)
+    src = KERNEL_SOURCE.get(kernel, "kernels_fast.hip")
+    cur = hashlib.sha1(open(os.path.join(ROOT, "paper_2605_26580_amd", "csrc", src), "rb").read()).hexdigest()
+    if not m_b or not m_s or m_s.group(1) != cur:
+        return None
+    return float(m_b.group(1))
+
+
+def roofline(prof, model, n, K, tokens, kind, workload):
+    per_tok, flop_role, byte_role = algorithmic(model, n, K, 4 if kind == "fp32" else 2)
+    dom_name, (dom_launches, dom_ms) = max(prof.items(), key=lambda kv: kv[1][1])
+    dom_avg_ms = dom_ms / dom_launches
+    if dom_name not in byte_role:
+        return None
+    secs = dom_avg_ms * 1e-3
+    fl = flop_role.get(dom_name, 0) * tokens
+    by = byte_role[dom_name] * tokens
+    if kind == "fp32" and dom_name.startswith("attn"):
+        bound, peak, unit, ach = "alu", PEAK["fp32"], "TFLOP/s", fl / secs / 1e12
+    elif fl / by >= PEAK[kind] * 1e12 / (HBM_PEAK * 1e9):
+        bound, peak, unit, ach = "mfma", PEAK[kind], "TFLOP/s", fl / secs / 1e12
+    else:
+        bound, peak, unit, ach = "hbm", HBM_PEAK, "GB/s", by / secs / 1e9
+    return {"bound": bound, "kernel": dom_name, "achieved": round(ach, 2), "peak": peak, "unit": unit,
+            "frac": round(ach / peak, 4), "traffic": _measured_traffic(workload, dom_name),
+            "avg_launch_ms": round(dom_avg_ms, 4), "flop_per_launch": fl, "bytes_per_launch": by,
+            "tflops": round(fl / secs / 1e12, 2)}
+
+
+# ---------------------------------------------------------------------------
+
+def run_batched(args, wl, P, torch):
+    """Fixed-shape (c1..c3) or ragged (c4) batch; returns the JSON dict."""
     import synth
-    wl = synth.workload(args.workload)
-    if wl.ragged_K is not None:
-        raise SystemExit("bench.py times the fixed-shape workloads c1..c3")
-
-    # ---- CPU baseline first, before the GPU is initialised (spawned workers)
-    cpu = None
-    oracle_out = {}
-    if not args.no_cpu:
-        workers = max(1, min(args.cpu_bins, os.cpu_count() or 1, 16))
-        print(f"[bench] oracle cpu baseline: {args.cpu_bins} bins on {workers} workers", file=sys.stderr, flush=True)
-        res, wall = cpu_baseline(args.workload, args.cpu_bins, workers)
-        for b, X, secs, gap in res:
-            oracle_out[b] = (X, secs, gap)
-        cpu = {"value": args.cpu_bins / wall, "unit": "bins/s", "cores": workers, "kind": "oracle",
-               "sample": f"first {args.cpu_bins} bins of the {args.workload} batch, FP64 NumPy oracle, "
-                         f"one single-threaded worker process per core, wall {wall:.1f} s, "
-                         f"{sum(r[2] for r in res):.1f} s CPU"}
-
-    import torch
-    import paper_2605_26580_amd as P
-    torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
     cfg = wl.model
-    code = synth.regular_ldpc(wl.n, seed=wl.code_seed)
-    bins = synth.make_bins(code, wl.K, wl.batch, wl.ebn0_db, wl.bin_seed)
+    ragged = wl.ragged_K is not None
     blob = synth.make_weights(cfg, wl.weight_seed)
     wh = P.Weights(P.make_cfg(cfg.n_layers, cfg.d, cfg.heads, cfg.mlp_mult, cfg.n_max), blob)
-    ch = P.Code(code.n, code.m, code.row_ptr, code.col_idx)
-    B, K, n = wl.batch, wl.K, wl.n
-    y = torch.from_numpy(bins.y).to(dev)
-    out = torch.zeros(B, K, n, dtype=torch.uint8, device=dev)
+    if ragged:
+        codes = {n: synth.regular_ldpc(n, seed=1000 + n) for n in wl.ragged_n}
+        rb = synth.make_ragged_bins(codes, args.bins or wl.batch, wl.ragged_K, wl.ragged_n, wl.ebn0_range,
+                                    wl.bin_seed)
+        handles = {n: P.Code(c.n, c.m, c.row_ptr, c.col_idx) for n, c in codes.items()}
+        shapes = [(b.K, b.n) for b in rb]
+        ys = [torch.from_numpy(b.y).to(dev) for b in rb]
+        s2 = [b.sigma2 for b in rb]
+        chs = [handles[b.n] for b in rb]
+    else:
+        code = synth.regular_ldpc(wl.n, seed=wl.code_seed)
+        B = args.bins or wl.batch
+        bins = synth.make_bins(code, wl.K, B, wl.ebn0_db, wl.bin_seed)
+        ch = P.Code(code.n, code.m, code.row_ptr, code.col_idx)
+        shapes = [(wl.K, wl.n)] * B
+        yall = torch.from_numpy(bins.y).to(dev)
+        ys = [yall[b] for b in range(B)]
+        s2 = [float(bins.sigma2[b]) for b in range(B)]
+        chs = [ch] * B
+    B = len(shapes)
+    tokens = sum(K * n for K, n in shapes)
+    outs = [torch.zeros(K, n, dtype=torch.uint8, device=dev) for K, n in shapes]
     prec = P.CIDER_BF16 if args.precision == "bf16" else P.CIDER_FP32
-    opts = P.cider_opts_default(precision=prec, remask=int(wl.remask), remask_thr=wl.remask_thr,
-                                remask_max_rounds=wl.remask_max_rounds, use_graph=1)
-    blist = [{"y": y[b], "sigma2": float(bins.sigma2[b]), "code": ch, "K": K, "n": n, "out_symbols": out[b]}
-             for b in range(B)]
+    kind = args.precision
+    ro = dict(remask=int(wl.remask), remask_thr=wl.remask_thr, remask_max_rounds=wl.remask_max_rounds)
+    opts = P.cider_opts_default(precision=prec, use_graph=1, **ro)
+    blist = [{"y": ys[i], "sigma2": s2[i], "code": chs[i], "K": shapes[i][0], "n": shapes[i][1],
+              "out_symbols": outs[i]} for i in range(B)]
     stream = torch.cuda.Stream()
-    print(f"[bench] {args.workload}: {B} bins K={K} n={n} L={cfg.n_layers} d={cfg.d} T={wl.T} "
-          f"{args.precision}, warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+    log(f"{wl.name}: {B} bins, {tokens} tokens, L={cfg.n_layers} d={cfg.d} h={cfg.heads} T={wl.T} "
+        f"remask={wl.remask} {kind}, warmup {args.warmup}, steps {args.steps}")
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
             P.cider_decode_batch(blist, wh, wl.T, opts, stream=stream)
@@ -152,103 +203,251 @@ def main():
         for i in range(args.steps):
             P.cider_decode_batch(blist, wh, wl.T, opts, stream=stream)
             ev[i + 1].record(stream)
+            log(f"step {i + 1}/{args.steps} enqueued")
         stream.synchronize()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
     lat = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
     total = t1 - t0
     value = B * args.steps / total
-    gpu_X = out.cpu().numpy()
-    print(f"[bench] {value:.1f} bins/s", file=sys.stderr, flush=True)
+    gpu_X = [o.cpu().numpy() for o in outs]
+    log(f"{value:.1f} bins/s")
 
-    # ---- plain FP32 per-bin path on a subset (the comparison baseline)
+    # plain FP32 per-bin path on a subset of the same bins (the comparison baseline)
     nplain = min(args.plain_bins, B)
-    po = P.cider_opts_default(precision=P.CIDER_FP32, use_graph=0, remask=int(wl.remask),
-                              remask_thr=wl.remask_thr, remask_max_rounds=wl.remask_max_rounds)
-    plain_out = torch.zeros(nplain, K, n, dtype=torch.uint8, device=dev)
-    with torch.cuda.stream(stream):
-        P.cider_decode(y[0], float(bins.sigma2[0]), ch, K, n, wh, wl.T, plain_out[0], po, stream=stream)
-        stream.synchronize()
-        tp0 = time.perf_counter()
-        for b in range(nplain):
-            P.cider_decode(y[b], float(bins.sigma2[b]), ch, K, n, wh, wl.T, plain_out[b], po, stream=stream)
-        stream.synchronize()
-        tp1 = time.perf_counter()
-    plain_value = nplain / (tp1 - tp0)
-    plain_X = plain_out.cpu().numpy()
-    print(f"[bench] fp32 plain {plain_value:.1f} bins/s", file=sys.stderr, flush=True)
+    plain_value, plain_X = None, []
+    if nplain > 0:
+        po = P.cider_opts_default(precision=P.CIDER_FP32, use_graph=0, **ro)
+        pouts = [torch.zeros(*shapes[i], dtype=torch.uint8, device=dev) for i in range(nplain)]
+        with torch.cuda.stream(stream):
+            P.cider_decode(ys[0], s2[0], chs[0], *shapes[0], wh, wl.T, pouts[0], po, stream=stream)
+            stream.synchronize()
+            tp0 = time.perf_counter()
+            for i in range(nplain):
+                P.cider_decode(ys[i], s2[i], chs[i], *shapes[i], wh, wl.T, pouts[i], po, stream=stream)
+            stream.synchronize()
+            tp1 = time.perf_counter()
+        plain_value = nplain / (tp1 - tp0)
+        plain_X = [p.cpu().numpy() for p in pouts]
+        log(f"fp32 plain {plain_value:.2f} bins/s over {nplain} bins")
 
-    # ---- live per-kernel timing (HIP events around each launch, one decode)
-    prof_opts = P.cider_opts_default(precision=prec, remask=int(wl.remask), remask_thr=wl.remask_thr,
-                                     remask_max_rounds=wl.remask_max_rounds, profile=1)
+    # live per-kernel timing: HIP events around each launch during one decode
+    prof_opts = P.cider_opts_default(precision=prec, profile=1, **ro)
     with torch.cuda.stream(stream):
         P.cider_profile_read(wh, reset=True)
         P.cider_decode_batch(blist, wh, wl.T, prof_opts, stream=stream)
         stream.synchronize()
     prof = P.cider_profile_read(wh, reset=True)
-    tokens = B * K * n
-    kind = "fp32" if args.precision == "fp32" else "bf16"
-    per_tok, flop_role, byte_role = algorithmic(wl, 4 if kind == "fp32" else 2)
-    dom_name, (dom_launches, dom_ms) = max(prof.items(), key=lambda kv: kv[1][1])
-    dom_avg_ms = dom_ms / dom_launches
-    roof = None
-    if dom_name in byte_role:
-        secs = dom_avg_ms * 1e-3
-        fl = flop_role.get(dom_name, 0) * tokens
-        by = byte_role[dom_name] * tokens
-        if kind == "fp32" and dom_name.startswith("attn"):
-            bound, peak, unit, ach = "alu", PEAK["fp32"], "TFLOP/s", fl / secs / 1e12
-        elif fl / by >= PEAK[kind] * 1e12 / (HBM_PEAK * 1e9):
-            bound, peak, unit, ach = "mfma", PEAK[kind], "TFLOP/s", fl / secs / 1e12
-        else:
-            bound, peak, unit, ach = "hbm", HBM_PEAK, "GB/s", by / secs / 1e9
-        roof = {"bound": bound, "kernel": dom_name, "achieved": round(ach, 2), "peak": peak, "unit": unit,
-                "frac": round(ach / peak, 4), "traffic": None, "avg_launch_ms": round(dom_avg_ms, 4),
-                "flop_per_launch": fl, "bytes_per_launch": by,
-                "tflops": round(fl / secs / 1e12, 2)}
+    mean_n = tokens / max(1, sum(K for K, _ in shapes))
+    mean_K = tokens / max(1, sum(n for _, n in shapes))
+    roof = roofline(prof, cfg, mean_n, mean_K, tokens, kind, wl.name)
     kernel_table = {k: {"launches": v[0], "avg_ms": round(v[1] / v[0], 4), "total_ms": round(v[1], 3)}
                     for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
-
-    # ---- agreement with the oracle on the CPU sample
-    match = None
-    if oracle_out:
-        bm = sum(np.array_equal(gpu_X[b], oracle_out[b][0]) for b in oracle_out)
-        sm = float(np.mean([np.mean(gpu_X[b] == oracle_out[b][0]) for b in oracle_out]))
-        pm = [b for b in oracle_out if b < nplain]
-        pbm = sum(np.array_equal(plain_X[b], oracle_out[b][0]) for b in pm)
-        match = {"bins": len(oracle_out), "bf16_bin_match": bm / len(oracle_out), "bf16_symbol_match": round(sm, 5),
-                 "fp32_plain_bin_match": (pbm / len(pm)) if pm else None}
-
-    flop_batch = per_tok * tokens * (wl.T + 1)
+    tuning = [{"role": t[0], "N": t[1], "Kd": t[2], "bucket": t[3], "tile": t[4], "best_ms": round(t[5], 4),
+               "default_ms": round(t[6], 4)} for t in P.cider_tuning_read(wh)]
+    per_tok, _, _ = algorithmic(cfg, mean_n, mean_K, 2)
     res = {
-        "metric": METRIC,
-        "value": round(value, 2),
-        "unit": "bins/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(1e3 * total / args.steps, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": kind,
-        "data": "synthetic",
-        "config": {"workload": f"{args.workload}: K={K}, (3,6)-regular binary LDPC n={n}, BPSK sum + AWGN at "
-                               f"Eb/N0 {list(wl.ebn0_db)} dB, denoiser L={cfg.n_layers} d={cfg.d} h={cfg.heads} "
-                               f"seeded N(0,0.02) weights, T={wl.T}, {B} bins per batch",
-                   "bins_per_batch": B, "K": K, "n": n, "T": wl.T, "remask": wl.remask},
-        "p50_ms": round(float(np.percentile(lat, 50)), 3),
-        "p99_ms": round(float(np.percentile(lat, 99)), 3),
-        "symbols_per_s": round(value * K * n, 1),
-        "model_tflops": round(flop_batch * args.steps / total / 1e12, 2),
-        "fp32_plain": {"value": round(plain_value, 2), "unit": "bins/s", "bins": nplain,
-                       "path": "cider_decode per bin, FP32, eager launches"},
-        "speedup_vs_fp32_plain": round(value / plain_value, 2),
-        "oracle_match": match,
-        "roofline": roof,
-        "kernels": kernel_table,
-        "cpu_baseline": cpu,
+        "metric": METRIC, "value": round(value, 2), "unit": "bins/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * total / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": kind, "data": "synthetic",
+        "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "symbols_per_s": round(value * tokens / B, 1),
+        "model_tflops_lower_bound": round(per_tok * tokens * (wl.T + 1) * args.steps / total / 1e12, 2),
+        "fp32_plain": ({"value": round(plain_value, 3), "unit": "bins/s", "bins": nplain,
+                        "path": "cider_decode per bin, FP32, eager launches"} if plain_value else None),
+        "speedup_vs_fp32_plain": round(value / plain_value, 2) if plain_value else None,
+        "roofline": roof, "kernels": kernel_table, "tuning": tuning,
     }
+    if ragged:
+        res["config"] = {"workload": f"{wl.name}: {B} bins, K uniform {list(wl.ragged_K)}, n uniform "
+                                     f"{list(wl.ragged_n)} (3,6)-regular binary LDPC, Eb/N0 uniform "
+                                     f"{list(wl.ebn0_range)} dB, L={cfg.n_layers} d={cfg.d} h={cfg.heads} "
+                                     f"seeded N(0,0.02) weights, T={wl.T}, one packed pass per step",
+                         "bins_per_batch": B, "tokens": tokens, "T": wl.T, "remask": wl.remask}
+    else:
+        res["config"] = {"workload": f"{wl.name}: K={wl.K}, (3,6)-regular binary LDPC n={wl.n}, BPSK sum + AWGN at "
+                                     f"Eb/N0 {list(wl.ebn0_db)} dB, denoiser L={cfg.n_layers} d={cfg.d} "
+                                     f"h={cfg.heads} seeded N(0,0.02) weights, T={wl.T}, {B} bins per batch"
+                                     + (", remasking on" if wl.remask else ""),
+                         "bins_per_batch": B, "K": wl.K, "n": wl.n, "T": wl.T, "remask": wl.remask}
+    return res, gpu_X, plain_X
+
+
+def run_served(args, wl, P, torch):
+    """Served workload (c5): Poisson arrivals through the continuous-batching
+    server; latency = completion - submission of each admitted bin."""
+    import ctypes as C
+    import synth
+    cfg = wl.model
+    blob = synth.make_weights(cfg, wl.weight_seed)
+    wh = P.Weights(P.make_cfg(cfg.n_layers, cfg.d, cfg.heads, cfg.mlp_mult, cfg.n_max), blob)
+    codes = {n: synth.regular_ldpc(n, seed=1000 + n) for n in wl.ragged_n}
+    handles = {n: P.Code(c.n, c.m, c.row_ptr, c.col_idx) for n, c in codes.items()}
+    pool = synth.make_ragged_bins(codes, args.bins or 512, wl.ragged_K, wl.ragged_n, wl.ebn0_range, wl.bin_seed)
+    L = P.abi.lib()
+    opts = P.cider_opts_default(precision=P.CIDER_BF16, remask=int(wl.remask), remask_thr=wl.remask_thr,
+                                remask_max_rounds=wl.remask_max_rounds)
+
+    def make_server():
+        sc = P.abi.cider_server_cfg()
+        sc.weights = wh.handle
+        sc.opts = opts
+        sc.steps = wl.T
+        sc.max_slots = args.max_slots
+        sc.max_queue = 1 << 20
+        sc.hbm_budget = 0
+        sc.max_tokens = args.max_tokens
+        h = C.c_void_p()
+        P.abi.check(L.cider_server_create(C.byref(sc), C.byref(h)), "cider_server_create")
+        return h
+
+    def run(rate, duration, burst=0):
+        srv = make_server()
+        outs = []
+        submitted = 0
+        t_start = time.perf_counter()
+        rng = np.random.default_rng(wl.bin_seed)
+        try:
+            if burst:
+                for i in range(burst):
+                    b = pool[i % len(pool)]
+                    o = np.zeros((b.K, b.n), np.uint8)
+                    rid = C.c_uint64()
+                    P.abi.check(L.cider_server_submit(srv, b.y.ctypes.data, b.sigma2, handles[b.n].handle, b.K,
+                                                      b.n, o.ctypes.data, C.byref(rid)), "submit")
+                    outs.append(o)
+                submitted = burst
+            else:
+                t_next = t_start
+                while time.perf_counter() - t_start < duration:
+                    t_next += rng.exponential(1.0 / rate)
+                    while time.perf_counter() < t_next:
+                        time.sleep(min(0.002, max(0.0, t_next - time.perf_counter())))
+                    b = pool[submitted % len(pool)]
+                    o = np.zeros((b.K, b.n), np.uint8)
+                    rid = C.c_uint64()
+                    P.abi.check(L.cider_server_submit(srv, b.y.ctypes.data, b.sigma2, handles[b.n].handle, b.K,
+                                                      b.n, o.ctypes.data, C.byref(rid)), "submit")
+                    outs.append(o)
+                    submitted += 1
+            P.abi.check(L.cider_server_drain(srv), "drain")
+            t_end = time.perf_counter()
+            res = (P.abi.cider_result * max(1, submitted))()
+            got = C.c_int32()
+            P.abi.check(L.cider_server_poll(srv, res, submitted, C.byref(got)), "poll")
+        finally:
+            L.cider_server_destroy(srv)
+        lat = np.array([res[i].t_done - res[i].t_submit for i in range(got.value)])
+        wait = np.array([res[i].t_admit - res[i].t_submit for i in range(got.value)])
+        return {"offered_rate": rate, "submitted": submitted, "completed": int(got.value),
+                "wall_s": round(t_end - t_start, 3), "throughput": round(got.value / (t_end - t_start), 3),
+                "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
+                "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2),
+                "queue_wait_p50_ms": round(1e3 * float(np.percentile(wait, 50)), 2)}
+
+    log(f"{wl.name}: capacity probe, burst of {args.burst} bins")
+    cap = run(0, 0, burst=args.burst)
+    capacity = cap["throughput"]
+    log(f"capacity {capacity:.2f} bins/s")
+    loads = []
+    for f in [float(x) for x in args.load.split(",") if x]:
+        log(f"Poisson arrivals at {f:.2f} x capacity for {args.duration} s")
+        loads.append(dict(run(f * capacity, args.duration), load=f))
+    main = loads[-1] if loads else cap
+    toks = float(np.mean([b.K * b.n for b in pool]))
+    return {
+        "metric": METRIC, "value": main["throughput"], "unit": "bins/s", "n_gpus": 1, "steps": len(loads),
+        "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic", "p50_ms": main["p50_ms"], "p99_ms": main["p99_ms"],
+        "symbols_per_s": round(main["throughput"] * toks, 1),
+        "config": {"workload": f"{wl.name}: served, Poisson arrivals; K uniform {list(wl.ragged_K)}, n uniform "
+                               f"{list(wl.ragged_n)}, Eb/N0 uniform {list(wl.ebn0_range)} dB, L={cfg.n_layers} "
+                               f"d={cfg.d} h={cfg.heads}, T={wl.T}, remasking on; offered load as a fraction of "
+                               f"the measured capacity (the workload's 20k bins/s is far beyond one GPU)",
+                   "max_slots": args.max_slots, "max_tokens": args.max_tokens},
+        "capacity_probe": cap, "loads": loads, "roofline": None, "cpu_baseline": None,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
+    ap.add_argument("--bins", type=int, default=0, help="override the batch size")
+    ap.add_argument("--cpu-bins", type=int, default=16)
+    ap.add_argument("--plain-bins", type=int, default=32)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true", help="end with a 256 MiB device copy (counter calibration)")
+    ap.add_argument("--load", default="0.5,0.9")
+    ap.add_argument("--duration", type=float, default=15.0)
+    ap.add_argument("--burst", type=int, default=96)
+    ap.add_argument("--max-slots", type=int, default=96)
+    ap.add_argument("--max-tokens", type=int, default=400000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
+              "bins are independent, so N GPUs would each run this engine on a disjoint bin stream.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import synth
+    wl = synth.workload(args.workload)
+    served = args.workload == "c5"
+
+    # CPU baseline first, before the GPU is initialised (spawned workers)
+    cpu, oracle_out = None, {}
+    if not args.no_cpu and not served:
+        workers = max(1, min(args.cpu_bins, os.cpu_count() or 1, 16))
+        if wl.ragged_K is None and wl.name in ("c1", "c2"):
+            log(f"oracle cpu baseline: {args.cpu_bins} bins on {workers} workers")
+            out, wall = _pool(_oracle_worker, [(wl.name, b) for b in range(args.cpu_bins)], workers)
+            for b, X, secs in out:
+                oracle_out[b] = X
+            cpu = {"value": round(args.cpu_bins / wall, 3), "unit": "bins/s", "cores": workers, "kind": "oracle",
+                   "sample": f"first {args.cpu_bins} bins of the {wl.name} batch, FP64 NumPy oracle, full decode, "
+                             f"one single-threaded worker process per core, wall {wall:.1f} s, "
+                             f"{sum(r[2] for r in out):.1f} s CPU"}
+        else:
+            K = wl.K if wl.ragged_K is None else int(np.median(wl.ragged_K))
+            n = wl.n if wl.ragged_K is None else int(np.median(wl.ragged_n))
+            code_seed = wl.code_seed if wl.ragged_K is None else 1000 + n
+            log(f"oracle cpu baseline: one denoiser forward of a K={K} n={n} bin on {workers} workers")
+            out, wall = _pool(_oracle_step_worker, [(K, n, wl.model, wl.weight_seed, code_seed)] * workers, workers)
+            per_fwd = float(np.mean(out))
+            passes = (wl.T + 1) * (3 if wl.remask else 1)
+            cpu = {"value": round(workers / (per_fwd * passes), 5), "unit": "bins/s", "cores": workers,
+                   "kind": "oracle",
+                   "sample": f"one FP64 oracle denoiser forward of a K={K}, n={n} bin per worker ({per_fwd:.1f} s), "
+                             f"scaled by {passes} forwards per bin (T+1{' times 3 passes with remasking' if wl.remask else ''})"}
+
+    import torch
+    import paper_2605_26580_amd as P
+    torch.cuda.set_device(0)
+    if served:
+        res = run_served(args, wl, P, torch)
+    else:
+        res, gpu_X, plain_X = run_batched(args, wl, P, torch)
+        res["cpu_baseline"] = cpu
+        if oracle_out:
+            ob = sorted(oracle_out)
+            bm = sum(np.array_equal(gpu_X[b], oracle_out[b]) for b in ob)
+            sm = float(np.mean([np.mean(gpu_X[b] == oracle_out[b]) for b in ob]))
+            pb = [b for b in ob if b < len(plain_X)]
+            pbm = sum(np.array_equal(plain_X[b], oracle_out[b]) for b in pb)
+            res["oracle_match"] = {"bins": len(ob), "bin_match": round(bm / len(ob), 4), "symbol_match": round(sm, 5),
+                                   "fp32_plain_bin_match": round(pbm / len(pb), 4) if pb else None}
+    if args.calib_copy:
+        x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        yb = torch.empty_like(x)
+        x.fill_(1.0)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            yb.copy_(x)
+        torch.cuda.synchronize()
+        log("calibration copy: 3 x 256 MiB")
     print(json.dumps(res))
 
 

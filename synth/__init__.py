@@ -10,13 +10,13 @@ Every draw goes through ``numpy.random.Generator(PCG64(SeedSequence(seed)))``
 so that the same seed yields the same bytes on every machine.
 """
 from .code import LdpcCode, regular_ldpc, nullspace_gf2, rank_gf2
-from .channel import ebn0_to_sigma2, make_bins, BinBatch
+from .channel import ebn0_to_sigma2, make_bins, make_ragged_bins, BinBatch, RaggedBin
 from .weights import ModelCfg, weight_layout, make_weights, unpack_weights
 from .configs import WORKLOADS, Workload, workload
 
 __all__ = [
     "LdpcCode", "regular_ldpc", "nullspace_gf2", "rank_gf2",
-    "ebn0_to_sigma2", "make_bins", "BinBatch",
+    "ebn0_to_sigma2", "make_bins", "make_ragged_bins", "BinBatch", "RaggedBin",
     "ModelCfg", "weight_layout", "make_weights", "unpack_weights",
     "WORKLOADS", "Workload", "workload",
 ]

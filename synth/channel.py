@@ -4,7 +4,7 @@ as +1 and bit 1 as -1, unit amplitude per user, real AWGN)."""
 from __future__ import annotations
 
 from dataclasses import dataclass
-from typing import Sequence
+from typing import Sequence, Tuple
 
 import numpy as np
 
@@ -53,3 +53,31 @@ def make_bins(code: LdpcCode, K: int, num_bins: int, ebn0_db: Sequence[float] | 
     noise = rng.standard_normal((num_bins, n)) * np.sqrt(sigma2)[:, None]
     y = (x.sum(axis=1) + noise).astype(np.float32)
     return BinBatch(info=info, codewords=cw, y=y, sigma2=sigma2.astype(np.float32), ebn0_db=eb)
+
+
+@dataclass
+class RaggedBin:
+    K: int
+    n: int
+    ebn0_db: float
+    y: np.ndarray          # float32 [n]
+    sigma2: float          # float32 value
+    codewords: np.ndarray  # uint8 [K][n]
+
+
+def make_ragged_bins(codes: dict, num_bins: int, K_choices: Sequence[int], n_choices: Sequence[int],
+                     ebn0_range: Tuple[float, float], seed: int):
+    """Bins of uneven size: K uniform over K_choices, n uniform over n_choices
+    (codes[n] gives the code), Eb/N0 uniform over ebn0_range.  Each bin's
+    payload is drawn from its own child seed, so bin i is the same whatever
+    num_bins is."""
+    children = np.random.SeedSequence(seed).spawn(num_bins)
+    out = []
+    for i in range(num_bins):
+        g = np.random.Generator(np.random.PCG64(children[i]))
+        K = int(g.choice(np.asarray(K_choices)))
+        n = int(g.choice(np.asarray(n_choices)))
+        eb = float(g.uniform(ebn0_range[0], ebn0_range[1]))
+        b = make_bins(codes[n], K, 1, eb, int(g.integers(0, 2**31 - 1)))
+        out.append(RaggedBin(K=K, n=n, ebn0_db=eb, y=b.y[0], sigma2=float(b.sigma2[0]), codewords=b.codewords[0]))
+    return out
