@@ -132,6 +132,10 @@ def _measured_traffic(workload: str, kernel: str):
 
 def roofline(prof, model, n, K, tokens, kind, workload):
     per_tok, flop_role, byte_role = algorithmic(model, n, K, 4 if kind == "fp32" else 2)
+    if kind == "fp8":   # the LayerNorm-fed GEMMs read 1-byte activations
+        d = model.d
+        byte_role["gemm_qkv_row"] = byte_role["gemm_qkv_user"] = d + 3 * d * 2 + 4
+        byte_role["mlp_fused"] = d + 4 + 8 * d + d + 4
     dom_name, (dom_launches, dom_ms) = max(prof.items(), key=lambda kv: kv[1][1])
     dom_avg_ms = dom_ms / dom_launches
     if dom_name not in byte_role:
@@ -183,7 +187,7 @@ def run_batched(args, wl, P, torch):
     B = len(shapes)
     tokens = sum(K * n for K, n in shapes)
     outs = [torch.zeros(K, n, dtype=torch.uint8, device=dev) for K, n in shapes]
-    prec = P.CIDER_BF16 if args.precision == "bf16" else P.CIDER_FP32
+    prec = {"bf16": P.CIDER_BF16, "fp32": P.CIDER_FP32, "fp8": P.CIDER_FP8}[args.precision]
     kind = args.precision
     ro = dict(remask=int(wl.remask), remask_thr=wl.remask_thr, remask_max_rounds=wl.remask_max_rounds)
     opts = P.cider_opts_default(precision=prec, use_graph=1, **ro)
@@ -375,7 +379,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2")
-    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp8"])
     ap.add_argument("--bins", type=int, default=0, help="override the batch size")
     ap.add_argument("--cpu-bins", type=int, default=16)
     ap.add_argument("--plain-bins", type=int, default=32)

@@ -110,6 +110,8 @@ struct Work {
   void* ZE;        // [T][2d]    gate MLP input [Z ; e]        (compute type)
   void* H1;        // [T][d]     gate MLP hidden               (compute type)
   void* XN;        // [T][d]     LayerNorm output              (compute type)
+  uint8_t* XN8;    // [T][d]     LayerNorm output, OCP e4m3 (FP8 precision)
+  float* xscale;   // [T]        per-token scale of XN8
   void* QKV;       // [T][3d]    attention projections         (compute type)
   void* O;         // [T][d]     attention output              (compute type)
   void* HID;       // [T][F]     MLP hidden                    (compute type)
@@ -143,7 +145,7 @@ struct GemmArgs {
   float* R;             // [M][N] FP32 residual (Resid, Gate)
   const float* E;       // [M][N] FP32 (Gate)
   const float* a_scale; // [M] per-token activation scale (FP8 input)
-  float* out_scale;     // [M] per-token scale of `out` (FP8 output)
+  float* out_scale;     // [M] per-token scale of `out` (FP8 LayerNorm output)
 };
 hipError_t launch_gemm(int prec, int pro, int epi, const GemmArgs& g, const Mat& W, hipStream_t s);
 
@@ -152,6 +154,8 @@ hipError_t launch_layernorm(int prec, long T, int d, const float* R, const float
 hipError_t launch_gemm_bf16(int epi, const GemmArgs& g, const Mat& W, hipStream_t s, int tile);
 int gemm_tile_count(int epi, int N, bool ln);
 hipError_t launch_mlp_bf16(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s);
+hipError_t launch_gemm_fp8(const GemmArgs& g, const Mat& W, hipStream_t s);
+hipError_t launch_mlp_fp8(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s);
 hipError_t launch_row_attn_mfma(const StepCtx& c, const void* QKV, void* O, int d, int heads, int max_n,
                                 hipStream_t s);
 hipError_t launch_user_attn_bf16(const StepCtx& c, const void* QKV, void* O, int d, int heads, hipStream_t s);

@@ -50,6 +50,27 @@ uint16_t f32_to_bf16_bits(float f) {
   return (uint16_t)(u >> 16);
 }
 
+// float -> OCP FP8 e4m3 (bias 7, no infinities, largest finite 448), round to
+// nearest even, saturating at +-448.
+uint8_t f32_to_e4m3(float x) {
+  const uint8_t sign = std::signbit(x) ? 0x80 : 0x00;
+  const float a = std::fabs(x);
+  if (std::isnan(a)) return 0x7F;
+  if (a >= 448.0f) return sign | 0x7E;
+  if (a < 0.015625f) {                              // below 2^-6: subnormal m * 2^-9
+    const int m = (int)std::nearbyint(a * 512.0f);  // 0..8, ties to even
+    return sign | (uint8_t)(m >= 8 ? 0x08 : m);
+  }
+  int e = 0;
+  const float f = std::frexp(a, &e);                // a = f 2^e, f in [0.5, 1)
+  int E = e - 1;
+  int m = (int)std::nearbyint((f * 2.0f - 1.0f) * 8.0f);
+  if (m == 8) { m = 0; E += 1; }
+  const int ef = E + 7;
+  if (ef > 15 || (ef == 15 && m > 6)) return sign | 0x7E;
+  return sign | (uint8_t)((ef << 3) | m);
+}
+
 bool cfg_ok(const cider_model_cfg* c, std::string* why) {
   if (!c) { *why = "null cfg"; return false; }
   if (c->n_layers < 1 || c->n_layers > 64) { *why = "n_layers must be 1..64"; return false; }
@@ -173,7 +194,7 @@ struct Layout {
   long total_tokens = 0;
   int total_slots = 0, total_rows = 0, max_n = 0;
   size_t off_R, off_E, off_ZE, off_H1, off_QKV, off_O, off_HID, off_lbar, off_logits, off_p, off_S,
-      off_bins, off_state, off_slot, off_row, off_X, off_XN, total;
+      off_bins, off_state, off_slot, off_row, off_X, off_XN, off_XN8, off_xscale, total;
 };
 
 size_t esize(int prec) { return prec == CIDER_FP32 ? 4 : 2; }
@@ -191,6 +212,8 @@ Layout plan_layout(const cider_model_cfg& cfg, int num_bins, long T, int slots, 
   L.off_ZE = take(T * 2 * d * es);
   L.off_H1 = take(T * d * es);
   L.off_XN = take(T * d * es);
+  L.off_XN8 = take(prec == CIDER_FP8 ? T * d : 0);
+  L.off_xscale = take(prec == CIDER_FP8 ? T * 4 : 0);
   L.off_QKV = take(T * 3 * d * es);
   L.off_O = take(T * d * es);
   L.off_HID = take(T * F * es);
@@ -347,8 +370,21 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
   // BF16: the LayerNorm that follows a residual update runs in that GEMM's
   // epilogue (set ln_g / ln_b / out); FP32 runs it as its own kernel.
   const bool fused_ln = prec != kF32;
+  const bool f8 = prec == kFP8;
   auto next_ln = [&](GemmArgs& g, const float* gg, const float* bb) {
-    if (fused_ln) { g.ln_g = gg; g.ln_b = bb; g.out = k.XN; }
+    if (!fused_ln) return;
+    g.ln_g = gg;
+    g.ln_b = bb;
+    if (f8) { g.out = k.XN8; g.out_scale = k.xscale; }
+    else g.out = k.XN;
+  };
+  // the GEMMs fed by a LayerNorm (QKV, MLP up) read XN8 with its per-token
+  // scale in FP8, the others stay BF16
+  auto qkv = [&](GemmArgs& g, const Mat& W) -> hipError_t {
+    if (!f8) return gemm(kEpiStore, g, W);
+    g.A = k.XN8;
+    g.a_scale = k.xscale;
+    return launch_gemm_fp8(g, W, s);
   };
   TIMED("embed_demix", launch_embed_demix(c, w->ew, k, prec, s));
   GemmArgs g{};
@@ -365,7 +401,7 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
     if (!fused_ln) TIMED("layernorm", ln(L.ln1_g, L.ln1_b));
     g = GemmArgs{}; g.M = T;
     g.N = 3 * d; g.Kd = d; g.A = k.XN; g.bias = L.bqkv_r; g.out = k.QKV;
-    TIMED("gemm_qkv_row", gemm(kEpiStore, g, L.Wqkv_r));
+    TIMED("gemm_qkv_row", qkv(g, L.Wqkv_r));
     if (prec == kF32) TIMED("attn_row", launch_row_attn(c, prec, k.QKV, k.O, d, m.heads, c.max_n, s));
     else TIMED("attn_row", launch_row_attn_mfma(c, k.QKV, k.O, d, m.heads, c.max_n, s));
     g = GemmArgs{}; g.M = T;
@@ -375,7 +411,7 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
     if (!fused_ln) TIMED("layernorm", ln(L.ln2_g, L.ln2_b));
     g = GemmArgs{}; g.M = T;
     g.N = 3 * d; g.Kd = d; g.A = k.XN; g.bias = L.bqkv_u; g.out = k.QKV;
-    TIMED("gemm_qkv_user", gemm(kEpiStore, g, L.Wqkv_u));
+    TIMED("gemm_qkv_user", qkv(g, L.Wqkv_u));
     if (prec == kF32) TIMED("attn_user", launch_user_attn(c, prec, k.QKV, k.O, d, m.heads, s));
     else TIMED("attn_user", launch_user_attn_bf16(c, k.QKV, k.O, d, m.heads, s));
     g = GemmArgs{}; g.M = T;
@@ -388,7 +424,13 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
       g = GemmArgs{}; g.M = T;
       g.N = d; g.Kd = d; g.A = k.XN; g.bias = L.b2; g.R = k.R;
       if (l + 1 < m.n_layers) next_ln(g, m.layer[l + 1].ln1_g, m.layer[l + 1].ln1_b);
-      TIMED("mlp_fused", launch_mlp_bf16(g, L.W1, L.b1, L.W2, F, s));
+      if (f8) {
+        g.A = k.XN8;
+        g.a_scale = k.xscale;
+        TIMED("mlp_fused", launch_mlp_fp8(g, L.W1, L.b1, L.W2, F, s));
+      } else {
+        TIMED("mlp_fused", launch_mlp_bf16(g, L.W1, L.b1, L.W2, F, s));
+      }
     } else {
       g = GemmArgs{}; g.M = T;
       g.N = F; g.Kd = d; g.A = k.XN; g.bias = L.b1; g.out = k.HID;
@@ -484,12 +526,17 @@ struct BinIn {
 
 int check_opts(const cider_opts& o) {
   if (o.precision < 0 || o.precision > 2) return fail(CIDER_EINVAL, "precision must be 0..2");
-  if (o.precision == CIDER_FP8) return fail(CIDER_EUNSUPPORTED, "FP8 precision is not available in this build");
   if (o.schedule != CIDER_SCHED_LINEAR && o.schedule != CIDER_SCHED_COSINE)
     return fail(CIDER_EINVAL, "unknown schedule");
   if (o.remask_max_rounds < 0 || o.remask_max_rounds > 16) return fail(CIDER_EINVAL, "remask_max_rounds 0..16");
   if (!(o.tau > 0.f) || !(o.lam_max > 0.f) || !(o.lam_min > 0.f) || !(o.eta >= 0.f))
     return fail(CIDER_EINVAL, "tau, lam_max, lam_min must be > 0 and eta >= 0");
+  return CIDER_OK;
+}
+
+int check_prec(const cider_weights* w, const cider_opts& o) {
+  if (o.precision == CIDER_FP8 && (w->cfg.d % 128 != 0 || (w->cfg.mlp_mult * w->cfg.d) % 64 != 0))
+    return fail(CIDER_EUNSUPPORTED, "FP8 needs d to be a multiple of 128");
   return CIDER_OK;
 }
 
@@ -588,6 +635,8 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
   k.ZE = base + L.off_ZE;
   k.H1 = base + L.off_H1;
   k.XN = base + L.off_XN;
+  k.XN8 = (uint8_t*)(base + L.off_XN8);
+  k.xscale = (float*)(base + L.off_xscale);
   k.QKV = base + L.off_QKV;
   k.O = base + L.off_O;
   k.HID = base + L.off_HID;
@@ -608,6 +657,8 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
 int decode_impl(cider_weights* w, const std::vector<BinIn>& bins, int steps, const cider_opts& o,
                 hipStream_t s) {
   int rc = check_opts(o);
+  if (rc) return rc;
+  rc = check_prec(w, o);
   if (rc) return rc;
   if (bins.empty()) return CIDER_OK;
   for (const BinIn& b : bins) {
@@ -723,6 +774,18 @@ int cider_weights_create(const cider_model_cfg* cfg, const float* blob, size_t n
     w->allocs.push_back(db);
     HIPCHK(hipMemcpy(db, hb.data(), cnt * 2, hipMemcpyHostToDevice));
     M->b16 = (const bf16*)db;
+    // OCP e4m3 copy with one per-tensor scale amax / 448
+    float amax = 0.f;
+    for (size_t i = 0; i < cnt; ++i) amax = std::max(amax, std::fabs(blob[off + i]));
+    const float sc = amax > 0.f ? amax / 448.0f : 1.0f;
+    std::vector<uint8_t> h8(cnt);
+    for (size_t i = 0; i < cnt; ++i) h8[i] = f32_to_e4m3(blob[off + i] / sc);
+    void* d8 = nullptr;
+    if (hipMalloc(&d8, cnt) != hipSuccess) return fail(CIDER_ENOMEM, "weights hipMalloc");
+    w->allocs.push_back(d8);
+    HIPCHK(hipMemcpy(d8, h8.data(), cnt, hipMemcpyHostToDevice));
+    M->f8 = (const uint8_t*)d8;
+    M->f8_scale = sc;
     off += cnt;
     return CIDER_OK;
   };
@@ -880,6 +943,8 @@ int cider_step_debug(const uint8_t* X_in, uint8_t* X_out, const float* y, float 
   cider_opts o;
   if (opts) o = *opts; else cider_opts_default(&o);
   int rc = check_opts(o);
+  if (rc) return rc;
+  rc = check_prec(w, o);
   if (rc) return rc;
   uint8_t dummy = 0;
   BinIn b{y, sigma2, code, K, n, &dummy, nullptr, nullptr};
@@ -1174,6 +1239,8 @@ int cider_server_create(const cider_server_cfg* cfg, cider_server** out) {
   if (cfg->steps < 1 || cfg->max_slots < 1 || cfg->max_slots > 65536 || cfg->max_queue < 1 || cfg->max_tokens < 1)
     return fail(CIDER_EINVAL, "steps, max_slots, max_queue and max_tokens must be positive");
   int rc = check_opts(cfg->opts);
+  if (rc) return rc;
+  rc = check_prec(cfg->weights, cfg->opts);
   if (rc) return rc;
   cider_server* S = new cider_server();
   S->cfg = *cfg;

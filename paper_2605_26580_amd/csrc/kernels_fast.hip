@@ -108,7 +108,10 @@ namespace {
 
 constexpr int GPAD = 8;
 
-enum : int { kEpiResidLN = 4, kEpiGateLN = 5 };
+enum : int { kEpiResidLN = 4, kEpiGateLN = 5, kEpiResidLN8 = 6, kEpiGateLN8 = 7 };
+
+typedef int i32x8 __attribute__((__vector_size__(8 * sizeof(int))));
+typedef int i32x4 __attribute__((__vector_size__(4 * sizeof(int))));
 
 template <int BM, int BN, int BK>
 struct GemmSmem {
@@ -132,8 +135,9 @@ __device__ __forceinline__ void row_pass(const float* sC, long m0, int n0, const
   constexpr int NIT = BM / (4 * RPI);            // passes per wave
   constexpr int CH = (NIT * GPL <= 16) ? NIT : (16 / GPL > 0 ? 16 / GPL : 1);
   constexpr bool RES = EPI != kEpiStore && EPI != kEpiGelu;
-  constexpr bool GATE = EPI == kEpiGate || EPI == kEpiGateLN;
-  constexpr bool LNX = EPI == kEpiResidLN || EPI == kEpiGateLN;
+  constexpr bool GATE = EPI == kEpiGate || EPI == kEpiGateLN || EPI == kEpiGateLN8;
+  constexpr bool F8OUT = EPI == kEpiResidLN8 || EPI == kEpiGateLN8;
+  constexpr bool LNX = EPI == kEpiResidLN || EPI == kEpiGateLN || F8OUT;
   const int grp = lane / LPR, cl = lane % LPR;
   float* __restrict__ Rg = g.R;
   const float* __restrict__ Eg = g.E;
@@ -211,15 +215,48 @@ __device__ __forceinline__ void row_pass(const float* sC, long m0, int n0, const
 #pragma unroll
         for (int o = LPR / 2; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
         const float rstd = 1.0f / sqrtf(q / (float)BN + 1e-5f);
+        if (!F8OUT) {
 #pragma unroll
-        for (int u = 0; u < GPL; ++u) {
-          const int cg = cl + u * LPR;
-          if (cg >= CG || !mv) continue;
-          const int c = cg * 4;
-          bf16x4 h;
+          for (int u = 0; u < GPL; ++u) {
+            const int cg = cl + u * LPR;
+            if (cg >= CG || !mv) continue;
+            const int c = cg * 4;
+            bf16x4 h;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) h[r] = (bf16)((vv[it][u][r] - mean) * rstd * g.ln_g[c + r] + g.ln_b[c + r]);
-          *(bf16x4*)(Og + m * BN + c) = h;
+            for (int r = 0; r < 4; ++r) h[r] = (bf16)((vv[it][u][r] - mean) * rstd * g.ln_g[c + r] + g.ln_b[c + r]);
+            *(bf16x4*)(Og + m * BN + c) = h;
+          }
+        } else {
+          // OCP e4m3 copy with a per-token scale amax / 448
+          float amax = 0.f;
+#pragma unroll
+          for (int u = 0; u < GPL; ++u) {
+            const int cg = cl + u * LPR;
+            if (cg >= CG || !mv) continue;
+            const int c = cg * 4;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              amax = fmaxf(amax, fabsf((vv[it][u][r] - mean) * rstd * g.ln_g[c + r] + g.ln_b[c + r]));
+          }
+#pragma unroll
+          for (int o = LPR / 2; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+          const float sc = amax > 0.f ? amax / 448.0f : 1.0f;
+          const float inv = 1.0f / sc;
+          uint8_t* O8 = (uint8_t*)g.out;
+#pragma unroll
+          for (int u = 0; u < GPL; ++u) {
+            const int cg = cl + u * LPR;
+            if (cg >= CG || !mv) continue;
+            const int c = cg * 4;
+            float hq[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              hq[r] = fminf(fmaxf(((vv[it][u][r] - mean) * rstd * g.ln_g[c + r] + g.ln_b[c + r]) * inv, -448.f), 448.f);
+            int pk = __builtin_amdgcn_cvt_pk_fp8_f32(hq[0], hq[1], 0, false);
+            pk = __builtin_amdgcn_cvt_pk_fp8_f32(hq[2], hq[3], pk, true);
+            *(int*)(O8 + m * BN + c) = pk;
+          }
+          if (cl == 0 && mv) g.out_scale[m] = sc;
         }
       }
     }
@@ -337,6 +374,8 @@ hipError_t gemm_bf16_t(int epi, const GemmArgs& g, const bf16* W, hipStream_t s)
     case kEpiGate: hipLaunchKernelGGL((k_gemm_bf16<BM, BN, BK, kEpiGate>), grid, block, 0, s, g, W); break;
     case kEpiResidLN: hipLaunchKernelGGL((k_gemm_bf16<BM, BN, BK, kEpiResidLN>), grid, block, 0, s, g, W); break;
     case kEpiGateLN: hipLaunchKernelGGL((k_gemm_bf16<BM, BN, BK, kEpiGateLN>), grid, block, 0, s, g, W); break;
+    case kEpiResidLN8: hipLaunchKernelGGL((k_gemm_bf16<BM, BN, BK, kEpiResidLN8>), grid, block, 0, s, g, W); break;
+    case kEpiGateLN8: hipLaunchKernelGGL((k_gemm_bf16<BM, BN, BK, kEpiGateLN8>), grid, block, 0, s, g, W); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -362,7 +401,8 @@ hipError_t launch_gemm_bf16(int epi, const GemmArgs& g, const Mat& W, hipStream_
   if (g.Kd % 64 != 0) return hipErrorInvalidValue;
   const bool ln = (epi == kEpiResid || epi == kEpiGate) && g.ln_g != nullptr;
   if (ln) {
-    const int e = epi == kEpiResid ? kEpiResidLN : kEpiGateLN;
+    const bool f8 = g.out_scale != nullptr;
+    const int e = epi == kEpiResid ? (f8 ? kEpiResidLN8 : kEpiResidLN) : (f8 ? kEpiGateLN8 : kEpiGateLN);
     const int bm = (tile == 0) ? (g.N <= 128 ? 128 : 64) : (tile == 1 ? 64 : 32);
 #define LNT(BNV, BKV)                                                    \
   if (bm == 128) return gemm_bf16_t<128, BNV, BKV>(e, g, W.b16, s);      \
@@ -564,7 +604,8 @@ template <int BM, int D, int FCH>
 hipError_t mlp_t(bool ln, const GemmArgs& g, const bf16* W1, const float* b1, const bf16* W2, int F, hipStream_t s) {
   if (F % FCH != 0) return hipErrorInvalidValue;
   dim3 grid((unsigned)((g.M + BM - 1) / BM)), block(256);
-  if (ln) hipLaunchKernelGGL((k_mlp_bf16<BM, D, FCH, kEpiResidLN>), grid, block, 0, s, g, W1, b1, W2, F);
+  if (ln && g.out_scale) hipLaunchKernelGGL((k_mlp_bf16<BM, D, FCH, kEpiResidLN8>), grid, block, 0, s, g, W1, b1, W2, F);
+  else if (ln) hipLaunchKernelGGL((k_mlp_bf16<BM, D, FCH, kEpiResidLN>), grid, block, 0, s, g, W1, b1, W2, F);
   else hipLaunchKernelGGL((k_mlp_bf16<BM, D, FCH, kEpiResid>), grid, block, 0, s, g, W1, b1, W2, F);
   return hipGetLastError();
 }
@@ -585,6 +626,291 @@ hipError_t launch_mlp_bf16(const GemmArgs& g, const Mat& W1, const float* b1, co
     case 384: return mlp_t<32, 384, 64>(ln, g, W1.b16, b1, W2.b16, F, s);
     case 448: return mlp_t<32, 448, 32>(ln, g, W1.b16, b1, W2.b16, F, s);
     case 512: return mlp_t<32, 512, 32>(ln, g, W1.b16, b1, W2.b16, F, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP8 (OCP e4m3) token GEMMs fed by a LayerNorm: out = A W^T with A = XN8
+// (per-token scale a_scale[m]) and W in e4m3 with one per-tensor scale.  Uses
+// v_mfma_scale_f32_16x16x128_f8f6f4 with unit block scales (E8M0 127), a lane
+// holding 32 consecutive k of its row; the FP32 result is scaled by
+// a_scale[m] * w_scale, the bias added, and the row pass writes BF16.
+namespace {
+
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void k_gemm_fp8(GemmArgs g, const uint8_t* __restrict__ W, float w_scale) {
+  constexpr int BK = 128, LDK = BK + 16;
+  constexpr int TI = BN / 32, TJ = BM / 32;
+  constexpr size_t loop = (size_t)2 * (BM + BN) * LDK;
+  constexpr size_t stage = (size_t)BM * (BN + 4) * sizeof(float);
+  __shared__ __attribute__((aligned(16))) char smem[loop > stage ? loop : stage];
+  uint8_t* sA = (uint8_t*)smem;              // [2][BM][LDK]
+  uint8_t* sW = sA + 2 * BM * LDK;           // [2][BN][LDK]
+  float* sC = (float*)smem;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int nN = g.N / BN;
+  const int lb = xcd_logical((int)blockIdx.x, (int)gridDim.x);
+  const long m0 = (long)(lb / nN) * BM;
+  const int n0 = (lb - (lb / nN) * nN) * BN;
+  const int Kd = g.Kd;
+  const uint8_t* A = (const uint8_t*)g.A;
+  const int wn = (wave >> 1) * (BN / 2), wm = (wave & 1) * (BM / 2);
+  constexpr int CPR = BK / 16;
+  constexpr int ACH = (BM * CPR + 255) / 256, WCH = (BN * CPR + 255) / 256;
+  i32x4 ra[ACH], rw[WCH];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int c = 0; c < ACH; ++c) {
+      const int idx = tid + c * 256, row = idx / CPR, kc = (idx % CPR) * 16;
+      const long gm = m0 + row;
+      if (row < BM && gm < g.M) ra[c] = *(const i32x4*)(A + gm * Kd + k0 + kc);
+      else ra[c] = i32x4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int c = 0; c < WCH; ++c) {
+      const int idx = tid + c * 256, row = idx / CPR, kc = (idx % CPR) * 16;
+      if (row < BN) rw[c] = *(const i32x4*)(W + (long)(n0 + row) * Kd + k0 + kc);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int c = 0; c < ACH; ++c) {
+      const int idx = tid + c * 256, row = idx / CPR, kc = (idx % CPR) * 16;
+      if (row < BM) *(i32x4*)&sA[(buf * BM + row) * LDK + kc] = ra[c];
+    }
+#pragma unroll
+    for (int c = 0; c < WCH; ++c) {
+      const int idx = tid + c * 256, row = idx / CPR, kc = (idx % CPR) * 16;
+      if (row < BN) *(i32x4*)&sW[(buf * BN + row) * LDK + kc] = rw[c];
+    }
+  };
+  auto frag = [&](const uint8_t* p) {
+    const i32x4 lo = *(const i32x4*)p, hi = *(const i32x4*)(p + 16);
+    return i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  };
+  f32x4 acc[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int nk = Kd / BK;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) fetch((kt + 1) * BK);
+    i32x8 fw[TI], fa[TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i) fw[i] = frag(&sW[(buf * BN + wn + i * 16 + (lane & 15)) * LDK + (lane >> 4) * 32]);
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) fa[j] = frag(&sA[(buf * BM + wm + j * 16 + (lane & 15)) * LDK + (lane >> 4) * 32]);
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(fw[i], fa[j], acc[i][j], 0, 0, 0, 127, 0, 127);
+    if (kt + 1 < nk) stash(buf ^ 1);
+    __syncthreads();
+  }
+  constexpr int LDC = BN + 4;
+#pragma unroll
+  for (int i = 0; i < TI; ++i) {
+    const int nl = wn + i * 16 + (lane >> 4) * 4;
+    f32x4 bias = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (g.bias) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bias[r] = g.bias[n0 + nl + r];
+    }
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
+      const int ml = wm + j * 16 + (lane & 15);
+      const long m = m0 + ml;
+      const float sc = (m < g.M ? g.a_scale[m] : 0.f) * w_scale;
+      *(f32x4*)&sC[ml * LDC + nl] = acc[i][j] * sc + bias;
+    }
+  }
+  __syncthreads();
+  row_pass<BM, BN, kEpiStore>(sC, m0, n0, g, wave, lane);
+}
+
+// The fused MLP with its up-projection in FP8: the XN8 tile and the W1 chunks
+// are e4m3 in LDS, GELU(acc * a_scale[token] * w1_scale + b1) goes to LDS in
+// BF16 and the down-projection runs in BF16 as in k_mlp_bf16.
+template <int BM, int D, int FCH, int EPI>
+__global__ __launch_bounds__(256) void k_mlp_fp8(GemmArgs g, const uint8_t* __restrict__ W1, float w1_scale,
+                                                 const float* __restrict__ b1, const bf16* __restrict__ W2, int F) {
+  constexpr int LDA = D + 16, LDH = FCH + GPAD, LDW1 = D + 16, LDW2 = FCH + GPAD;
+  constexpr int TI1 = FCH / 32, TJ1 = BM / 32;
+  constexpr int TI2 = D / 32, TJ2 = BM / 32;
+  constexpr int PW1 = FCH * D / 16 / 256;        // 16-byte chunks per thread of a W1 chunk (e4m3)
+  constexpr int PW2 = D * FCH / 8 / 256;
+  constexpr size_t a = (size_t)BM * LDA, h = (size_t)BM * LDH * 2, w1 = (size_t)FCH * LDW1,
+                   w2 = (size_t)D * LDW2 * 2, cst = (size_t)BM * (D + 4) * 4;
+  constexpr size_t loop = a + h + w1 + w2;
+  __shared__ __attribute__((aligned(16))) char smem[loop > cst ? loop : cst];
+  uint8_t* sA = (uint8_t*)smem;
+  bf16* sH = (bf16*)(smem + a);
+  uint8_t* sW1 = (uint8_t*)(smem + a + h);
+  bf16* sW2 = (bf16*)(smem + a + h + w1);
+  float* sC = (float*)smem;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const long m0 = (long)blockIdx.x * BM;
+  const uint8_t* A = (const uint8_t*)g.A;
+  i32x4 pw1[PW1];
+  bf16x8 pw2[PW2];
+  auto fetchW = [&](int c0) {
+#pragma unroll
+    for (int i = 0; i < PW1; ++i) {
+      const int idx = tid + i * 256, row = idx / (D / 16), kc = (idx - row * (D / 16)) * 16;
+      pw1[i] = *(const i32x4*)(W1 + (long)(c0 + row) * D + kc);
+    }
+#pragma unroll
+    for (int i = 0; i < PW2; ++i) {
+      const int idx = tid + i * 256, row = idx / (FCH / 8), kc = (idx - row * (FCH / 8)) * 8;
+      pw2[i] = *(const bf16x8*)(W2 + (long)row * F + c0 + kc);
+    }
+  };
+  auto stashW = [&]() {
+#pragma unroll
+    for (int i = 0; i < PW1; ++i) {
+      const int idx = tid + i * 256, row = idx / (D / 16), kc = (idx - row * (D / 16)) * 16;
+      *(i32x4*)&sW1[row * LDW1 + kc] = pw1[i];
+    }
+#pragma unroll
+    for (int i = 0; i < PW2; ++i) {
+      const int idx = tid + i * 256, row = idx / (FCH / 8), kc = (idx - row * (FCH / 8)) * 8;
+      *(bf16x8*)&sW2[row * LDW2 + kc] = pw2[i];
+    }
+  };
+  auto frag8 = [&](const uint8_t* p) {
+    const i32x4 lo = *(const i32x4*)p, hi = *(const i32x4*)(p + 16);
+    return i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  };
+  fetchW(0);
+  constexpr int CPR = D / 16;
+  for (int idx = tid; idx < BM * CPR; idx += 256) {
+    const int row = idx / CPR, kc = (idx - row * CPR) * 16;
+    const long gm = m0 + row;
+    i32x4 v = i32x4{0, 0, 0, 0};
+    if (gm < g.M) v = *(const i32x4*)(A + gm * D + kc);
+    *(i32x4*)&sA[row * LDA + kc] = v;
+  }
+  stashW();
+  __syncthreads();
+  f32x4 acc2[TI2][TJ2];
+#pragma unroll
+  for (int i = 0; i < TI2; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ2; ++j) acc2[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int wn1 = (wave >> 1) * (FCH / 2), wm = (wave & 1) * (BM / 2), wn2 = (wave >> 1) * (D / 2);
+  float tsc[TJ1];
+#pragma unroll
+  for (int j = 0; j < TJ1; ++j) {
+    const long m = m0 + wm + j * 16 + (lane & 15);
+    tsc[j] = (m < g.M ? g.a_scale[m] : 0.f) * w1_scale;
+  }
+  for (int c0 = 0; c0 < F; c0 += FCH) {
+    const bool more = c0 + FCH < F;
+    if (more) fetchW(c0 + FCH);
+    f32x4 acc1[TI1][TJ1];
+#pragma unroll
+    for (int i = 0; i < TI1; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ1; ++j) acc1[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < D; ks += 128) {
+      i32x8 fw[TI1], fa[TJ1];
+#pragma unroll
+      for (int i = 0; i < TI1; ++i) fw[i] = frag8(&sW1[(wn1 + i * 16 + (lane & 15)) * LDW1 + ks + (lane >> 4) * 32]);
+#pragma unroll
+      for (int j = 0; j < TJ1; ++j) fa[j] = frag8(&sA[(wm + j * 16 + (lane & 15)) * LDA + ks + (lane >> 4) * 32]);
+#pragma unroll
+      for (int i = 0; i < TI1; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ1; ++j)
+          acc1[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(fw[i], fa[j], acc1[i][j], 0, 0, 0, 127, 0, 127);
+    }
+#pragma unroll
+    for (int i = 0; i < TI1; ++i) {
+      const int hn = wn1 + i * 16 + (lane >> 4) * 4;
+      f32x4 bb;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bb[r] = b1[c0 + hn + r];
+#pragma unroll
+      for (int j = 0; j < TJ1; ++j) {
+        const int ml = wm + j * 16 + (lane & 15);
+        const f32x4 v = acc1[i][j] * tsc[j] + bb;
+        bf16x4 hv = {(bf16)gelu_f(v[0]), (bf16)gelu_f(v[1]), (bf16)gelu_f(v[2]), (bf16)gelu_f(v[3])};
+        *(bf16x4*)&sH[ml * LDH + hn] = hv;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < FCH; ks += 32) {
+      bf16x8 fw[TI2], fh[TJ2];
+#pragma unroll
+      for (int i = 0; i < TI2; ++i) fw[i] = *(const bf16x8*)&sW2[(wn2 + i * 16 + (lane & 15)) * LDW2 + ks + (lane >> 4) * 8];
+#pragma unroll
+      for (int j = 0; j < TJ2; ++j) fh[j] = *(const bf16x8*)&sH[(wm + j * 16 + (lane & 15)) * LDH + ks + (lane >> 4) * 8];
+#pragma unroll
+      for (int i = 0; i < TI2; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ2; ++j) acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fw[i], fh[j], acc2[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+    if (more) {
+      stashW();
+      __syncthreads();
+    }
+  }
+  constexpr int LDC = D + 4;
+#pragma unroll
+  for (int i = 0; i < TI2; ++i) {
+    const int nl = wn2 + i * 16 + (lane >> 4) * 4;
+    f32x4 bias;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bias[r] = g.bias[nl + r];
+#pragma unroll
+    for (int j = 0; j < TJ2; ++j) {
+      const int ml = wm + j * 16 + (lane & 15);
+      *(f32x4*)&sC[ml * LDC + nl] = acc2[i][j] + bias;
+    }
+  }
+  __syncthreads();
+  row_pass<BM, D, EPI>(sC, m0, 0, g, wave, lane);
+}
+
+template <int BM, int D, int FCH>
+hipError_t mlp8_t(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s) {
+  if (F % FCH != 0) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((g.M + BM - 1) / BM)), block(256);
+  if (g.ln_g && g.out_scale)
+    hipLaunchKernelGGL((k_mlp_fp8<BM, D, FCH, kEpiResidLN8>), grid, block, 0, s, g, W1.f8, W1.f8_scale, b1, W2.b16, F);
+  else
+    hipLaunchKernelGGL((k_mlp_fp8<BM, D, FCH, kEpiResid>), grid, block, 0, s, g, W1.f8, W1.f8_scale, b1, W2.b16, F);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gemm_fp8(const GemmArgs& g, const Mat& W, hipStream_t s) {
+  if (g.M == 0) return hipSuccess;
+  if (g.Kd % 128 != 0 || g.N % 128 != 0 || !W.f8 || !g.a_scale) return hipErrorInvalidValue;
+  dim3 grid((unsigned)(((g.M + 127) / 128) * (g.N / 128))), block(256);
+  hipLaunchKernelGGL((k_gemm_fp8<128, 128>), grid, block, 0, s, g, W.f8, W.f8_scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_fp8(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s) {
+  if (g.M == 0) return hipSuccess;
+  if (!W1.f8 || !g.a_scale) return hipErrorInvalidValue;
+  switch (g.N) {
+    case 128: return mlp8_t<64, 128, 64>(g, W1, b1, W2, F, s);
+    case 256: return mlp8_t<64, 256, 64>(g, W1, b1, W2, F, s);
+    case 384: return mlp8_t<32, 384, 64>(g, W1, b1, W2, F, s);
+    case 512: return mlp8_t<32, 512, 32>(g, W1, b1, W2, F, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -9,7 +9,7 @@ import numpy as np
 
 import synth
 
-TOL = {"fp32": 1e-5, "bf16": 2e-2}
+TOL = {"fp32": 1e-5, "bf16": 2e-2, "fp8": 1.5e-1}
 
 
 def say(msg: str) -> None:
@@ -33,7 +33,7 @@ def lib():
 
 def prec_id(name: str) -> int:
     import paper_2605_26580_amd as P
-    return {"fp32": P.CIDER_FP32, "bf16": P.CIDER_BF16}[name]
+    return {"fp32": P.CIDER_FP32, "bf16": P.CIDER_BF16, "fp8": P.CIDER_FP8}[name]
 
 
 @lru_cache(maxsize=None)
