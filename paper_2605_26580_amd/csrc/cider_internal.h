@@ -146,6 +146,8 @@ struct GemmArgs {
   const float* E;       // [M][N] FP32 (Gate)
   const float* a_scale; // [M] per-token activation scale (FP8 input)
   float* out_scale;     // [M] per-token scale of `out` (FP8 LayerNorm output)
+  const float* proj_w;  // [2][N] symbol projection applied after the final LayerNorm
+  float* proj_out;      // [M][2] logits before Module B (final-projection epilogue)
 };
 hipError_t launch_gemm(int prec, int pro, int epi, const GemmArgs& g, const Mat& W, hipStream_t s);
 
@@ -153,7 +155,11 @@ hipError_t launch_layernorm(int prec, long T, int d, const float* R, const float
                             hipStream_t s);
 hipError_t launch_gemm_bf16(int epi, const GemmArgs& g, const Mat& W, hipStream_t s, int tile);
 int gemm_tile_count(int epi, int N, bool ln);
-hipError_t launch_mlp_bf16(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s);
+hipError_t launch_mlp_bf16(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s,
+                           int tile);
+int mlp_tile_count(int D);
+bool gate_fusable(int d);
+hipError_t launch_gate_bf16(const GemmArgs& g, const Mat& Wg1, const float* bg1, const Mat& Wg2, hipStream_t s);
 hipError_t launch_gemm_fp8(const GemmArgs& g, const Mat& W, hipStream_t s);
 hipError_t launch_mlp_fp8(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s);
 hipError_t launch_row_attn_mfma(const StepCtx& c, const void* QKV, void* O, int d, int heads, int max_n,

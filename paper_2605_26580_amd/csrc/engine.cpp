@@ -298,6 +298,8 @@ struct Timed {
     HIPCHK(expr);                     \
   } while (0)
 
+constexpr int kMlpKey = 100;   // tuning-table key of the fused MLP
+
 int bucket_of(long M) {
   int b = 0;
   while ((1L << (b + 1)) <= M) ++b;
@@ -390,12 +392,19 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
   GemmArgs g{};
   g.M = T;
   // gate MLP: H1 = GELU([Z ; e] Wg1^T + bg1); R = g Z + (1 - g) e, g = sigmoid(H1 Wg2^T + bg2)
-  g.N = d; g.Kd = 2 * d; g.A = k.ZE; g.bias = m.bg1; g.out = k.H1;
-  TIMED("gemm_gate1", gemm(kEpiGelu, g, m.Wg1));
-  g = GemmArgs{}; g.M = T;
-  g.N = d; g.Kd = d; g.A = k.H1; g.bias = m.bg2; g.R = k.R; g.E = k.Ebuf;
-  next_ln(g, m.layer[0].ln1_g, m.layer[0].ln1_b);
-  TIMED("gemm_gate2", gemm(kEpiGate, g, m.Wg2));
+  if (fused_ln && gate_fusable(d)) {
+    // BF16 / FP8: both gate layers, the blend and the first LayerNorm in one kernel
+    g.N = d; g.Kd = 2 * d; g.A = k.ZE; g.bias = m.bg2; g.R = k.R; g.E = k.Ebuf;
+    next_ln(g, m.layer[0].ln1_g, m.layer[0].ln1_b);
+    TIMED("gate_fused", launch_gate_bf16(g, m.Wg1, m.bg1, m.Wg2, s));
+  } else {
+    g.N = d; g.Kd = 2 * d; g.A = k.ZE; g.bias = m.bg1; g.out = k.H1;
+    TIMED("gemm_gate1", gemm(kEpiGelu, g, m.Wg1));
+    g = GemmArgs{}; g.M = T;
+    g.N = d; g.Kd = d; g.A = k.H1; g.bias = m.bg2; g.R = k.R; g.E = k.Ebuf;
+    if (fused_ln) next_ln(g, m.layer[0].ln1_g, m.layer[0].ln1_b);
+    TIMED("gemm_gate2", gemm(kEpiGate, g, m.Wg2));
+  }
   for (int l = 0; l < m.n_layers; ++l) {
     const DevLayer& L = m.layer[l];
     if (!fused_ln) TIMED("layernorm", ln(L.ln1_g, L.ln1_b));
@@ -423,13 +432,20 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
       // BF16: up, GELU and down in one kernel, hidden layer on chip
       g = GemmArgs{}; g.M = T;
       g.N = d; g.Kd = d; g.A = k.XN; g.bias = L.b2; g.R = k.R;
-      if (l + 1 < m.n_layers) next_ln(g, m.layer[l + 1].ln1_g, m.layer[l + 1].ln1_b);
+      if (l + 1 < m.n_layers) {
+        next_ln(g, m.layer[l + 1].ln1_g, m.layer[l + 1].ln1_b);
+      } else {
+        // last block: final LayerNorm and symbol projection in the epilogue
+        g.ln_g = m.lnf_g; g.ln_b = m.lnf_b; g.proj_w = m.W; g.proj_out = k.lbar;
+      }
       if (f8) {
         g.A = k.XN8;
         g.a_scale = k.xscale;
         TIMED("mlp_fused", launch_mlp_fp8(g, L.W1, L.b1, L.W2, F, s));
       } else {
-        TIMED("mlp_fused", launch_mlp_bf16(g, L.W1, L.b1, L.W2, F, s));
+        int mt = tile_for(w, kMlpKey, g);
+        if (r.forced_tile >= 0) mt = r.forced_tile < mlp_tile_count(d) ? r.forced_tile : 0;
+        TIMED("mlp_fused", launch_mlp_bf16(g, L.W1, L.b1, L.W2, F, s, mt));
       }
     } else {
       g = GemmArgs{}; g.M = T;
@@ -440,8 +456,38 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
       TIMED("gemm_mlp_down", gemm(kEpiResid, g, L.W2));
     }
   }
-  TIMED("final_proj", launch_final_proj(c, w->ew, k, s));
+  if (!fused_ln) TIMED("final_proj", launch_final_proj(c, w->ew, k, s));
   TIMED("module_b", launch_module_b(c, k, s));
+  return CIDER_OK;
+}
+
+int tune_mlp(cider_weights* w, const GemmArgs& g, const DevLayer& L, int F, hipStream_t s) {
+  TuneKey key = tune_key(kMlpKey, g);
+  if (w->tune.count(key)) return CIDER_OK;
+  const int cand = mlp_tile_count(g.N);
+  hipEvent_t a, b;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  double best = 1e30, dflt = 0;
+  int best_t = 0;
+  for (int t = 0; t < cand; ++t) {
+    if (launch_mlp_bf16(g, L.W1, L.b1, L.W2, F, s, t) != hipSuccess) { (void)hipGetLastError(); continue; }
+    double tmin = 1e30;
+    for (int rep = 0; rep < 3; ++rep) {
+      HIPCHK(hipEventRecord(a, s));
+      HIPCHK(launch_mlp_bf16(g, L.W1, L.b1, L.W2, F, s, t));
+      HIPCHK(hipEventRecord(b, s));
+      HIPCHK(hipEventSynchronize(b));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, a, b));
+      tmin = std::min(tmin, (double)ms);
+    }
+    if (t == 0) dflt = tmin;
+    if (tmin < best) { best = tmin; best_t = t; }
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  w->tune[key] = TuneVal{best_t, best, dflt, "mlp_fused"};
   return CIDER_OK;
 }
 
@@ -455,16 +501,16 @@ int autotune_forward(cider_weights* w, const Run& r, hipStream_t s) {
   const DevLayer& L = m.layer[0];
   int rc;
   GemmArgs g{};
-  g.M = T; g.N = d; g.Kd = 2 * d; g.A = k.ZE; g.bias = m.bg1; g.out = k.H1;
-  if ((rc = tune_gemm(w, "gemm_gate1", kEpiGelu, g, m.Wg1, s))) return rc;
-  g = GemmArgs{}; g.M = T; g.N = d; g.Kd = d; g.A = k.H1; g.bias = m.bg2; g.R = k.R; g.E = k.Ebuf;
-  g.ln_g = L.ln1_g; g.ln_b = L.ln1_b; g.out = k.XN;
-  if ((rc = tune_gemm(w, "gemm_gate2_ln", kEpiGate, g, m.Wg2, s))) return rc;
   g = GemmArgs{}; g.M = T; g.N = 3 * d; g.Kd = d; g.A = k.XN; g.bias = L.bqkv_r; g.out = k.QKV;
   if ((rc = tune_gemm(w, "gemm_qkv", kEpiStore, g, L.Wqkv_r, s))) return rc;
   g = GemmArgs{}; g.M = T; g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_r; g.R = k.R;
   g.ln_g = L.ln2_g; g.ln_b = L.ln2_b; g.out = k.XN;
   if ((rc = tune_gemm(w, "gemm_o_ln", kEpiResid, g, L.Wo_r, s))) return rc;
+  if (r.prec == kBF16) {
+    g = GemmArgs{}; g.M = T; g.N = d; g.Kd = d; g.A = k.XN; g.bias = L.b2; g.R = k.R;
+    g.ln_g = L.ln1_g; g.ln_b = L.ln1_b; g.out = k.XN;
+    if ((rc = tune_mlp(w, g, L, F, s))) return rc;
+  }
   return CIDER_OK;
 }
 

@@ -22,7 +22,26 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-__device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// GELU(x) = x Phi(x) with Phi(x) written as a logistic of an odd polynomial,
+// Phi(x) ~ 1 / (1 + 2^f(x)), f(x) = c x (a0 + a2 x^2 + a4 x^4), c = -log2 e,
+// coefficients fitted here for the least maximum error against x Phi(x) with
+// the polynomial's argument clamped to [-10, 10] (beyond it Phi is 0 or 1 to
+// FP32 precision).  The largest |error| over [-40, 40] in FP32 is 2.6e-5, far
+// below the BF16 / FP8 rounding of the hidden values it feeds.  It costs seven
+// VALU operations and the two hardware transcendentals (2^x, 1/x); the FP32
+// plain path keeps the erf form.
+__device__ __forceinline__ float gelu_f(float x) {
+  const float xc = fminf(fmaxf(x, -10.0f), 10.0f);
+  const float s = xc * xc;
+  const float f = xc * fmaf(fmaf(0.0010142630f, s, -0.10677572f), s, -2.3011212f);
+  return x * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(f));
+}
+
+// Logistic 1 / (1 + e^-v) from the hardware 2^x and 1/x (relative error a few
+// FP32 ulps; e^-v overflowing to +inf gives 0).
+__device__ __forceinline__ float sigmoid_f(float v) {
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-v * 1.4426950408889634f));
+}
 
 // The dispatcher sends workgroup b to XCD b % 8, and each XCD has its own L2.
 // xcd_logical maps b to a logical id so that XCD x runs one contiguous range
@@ -108,7 +127,7 @@ namespace {
 
 constexpr int GPAD = 8;
 
-enum : int { kEpiResidLN = 4, kEpiGateLN = 5, kEpiResidLN8 = 6, kEpiGateLN8 = 7 };
+enum : int { kEpiResidLN = 4, kEpiGateLN = 5, kEpiResidLN8 = 6, kEpiGateLN8 = 7, kEpiResidProj = 8 };
 
 typedef int i32x8 __attribute__((__vector_size__(8 * sizeof(int))));
 typedef int i32x4 __attribute__((__vector_size__(4 * sizeof(int))));
@@ -137,7 +156,8 @@ __device__ __forceinline__ void row_pass(const float* sC, long m0, int n0, const
   constexpr bool RES = EPI != kEpiStore && EPI != kEpiGelu;
   constexpr bool GATE = EPI == kEpiGate || EPI == kEpiGateLN || EPI == kEpiGateLN8;
   constexpr bool F8OUT = EPI == kEpiResidLN8 || EPI == kEpiGateLN8;
-  constexpr bool LNX = EPI == kEpiResidLN || EPI == kEpiGateLN || F8OUT;
+  constexpr bool PROJ = EPI == kEpiResidProj;   // final LayerNorm + symbol projection
+  constexpr bool LNX = EPI == kEpiResidLN || EPI == kEpiGateLN || F8OUT || PROJ;
   const int grp = lane / LPR, cl = lane % LPR;
   float* __restrict__ Rg = g.R;
   const float* __restrict__ Eg = g.E;
@@ -187,7 +207,7 @@ __device__ __forceinline__ void row_pass(const float* sC, long m0, int n0, const
           } else {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              const float gt = 1.0f / (1.0f + expf(-v[r]));
+              const float gt = sigmoid_f(v[r]);
               res[r] = gt * rr[it][u][r] + (1.0f - gt) * ee[GATE ? it : 0][u][r];
             }
           }
@@ -215,7 +235,30 @@ __device__ __forceinline__ void row_pass(const float* sC, long m0, int n0, const
 #pragma unroll
         for (int o = LPR / 2; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
         const float rstd = 1.0f / sqrtf(q / (float)BN + 1e-5f);
-        if (!F8OUT) {
+        if (PROJ) {
+          float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+          for (int u = 0; u < GPL; ++u) {
+            const int cg = cl + u * LPR;
+            if (cg >= CG || !mv) continue;
+            const int c = cg * 4;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const float hv = (vv[it][u][r] - mean) * rstd * g.ln_g[c + r] + g.ln_b[c + r];
+              a0 = fmaf(hv, g.proj_w[c + r], a0);
+              a1 = fmaf(hv, g.proj_w[BN + c + r], a1);
+            }
+          }
+#pragma unroll
+          for (int o = LPR / 2; o > 0; o >>= 1) {
+            a0 += __shfl_xor(a0, o, 64);
+            a1 += __shfl_xor(a1, o, 64);
+          }
+          if (cl == 0 && mv) {
+            g.proj_out[2 * m] = a0;
+            g.proj_out[2 * m + 1] = a1;
+          }
+        } else if (!F8OUT) {
 #pragma unroll
           for (int u = 0; u < GPL; ++u) {
             const int cg = cl + u * LPR;
@@ -452,26 +495,28 @@ hipError_t launch_gemm_bf16(int epi, const GemmArgs& g, const Mat& W, hipStream_
 // the GEMM row pass: residual add and, with ln_g set, the next LayerNorm.
 namespace {
 
-template <int BM, int D, int FCH>
+template <int BM, int DIN, int D, int FCH>
 struct MlpSmem {
-  static constexpr size_t a = (size_t)BM * (D + GPAD) * sizeof(bf16);
+  static constexpr size_t a = (size_t)BM * (DIN + GPAD) * sizeof(bf16);
   static constexpr size_t h = (size_t)BM * (FCH + GPAD) * sizeof(bf16);
-  static constexpr size_t w1 = (size_t)FCH * (D + GPAD) * sizeof(bf16);
+  static constexpr size_t w1 = (size_t)FCH * (DIN + GPAD) * sizeof(bf16);
   static constexpr size_t w2 = (size_t)D * (FCH + GPAD) * sizeof(bf16);
   static constexpr size_t c = (size_t)BM * (D + 4) * sizeof(float);
   static constexpr size_t loop = a + h + w1 + w2;
   static constexpr size_t bytes = loop > c ? loop : c;
 };
 
-template <int BM, int D, int FCH, int EPI>
+template <int BM, int DIN, int D, int FCH, int EPI>
 __global__ __launch_bounds__(256) void k_mlp_bf16(GemmArgs g, const bf16* __restrict__ W1, const float* __restrict__ b1,
                                                   const bf16* __restrict__ W2, int F) {
-  constexpr int LDA = D + GPAD, LDH = FCH + GPAD, LDW1 = D + GPAD, LDW2 = FCH + GPAD;
+  constexpr int LDA = DIN + GPAD, LDH = FCH + GPAD, LDW1 = DIN + GPAD, LDW2 = FCH + GPAD;
   constexpr int TI1 = FCH / 32, TJ1 = BM / 32;   // up GEMM: (FCH/2) hidden x (BM/2) tokens per wave
   constexpr int TI2 = D / 32, TJ2 = BM / 32;     // down GEMM: (D/2) outputs x (BM/2) tokens per wave
-  constexpr int PW1 = FCH * D / 8 / 256;         // 16-byte chunks per thread of a W1 chunk
+  constexpr int PW1 = FCH * DIN / 8 / 256;       // 16-byte chunks per thread of a W1 chunk
   constexpr int PW2 = D * FCH / 8 / 256;
-  __shared__ __attribute__((aligned(16))) char smem[MlpSmem<BM, D, FCH>::bytes];
+  static_assert(PW1 * 256 * 8 == FCH * DIN && PW2 * 256 * 8 == D * FCH, "weight chunks must split over 256 threads");
+  static_assert(BM % 32 == 0 && FCH % 32 == 0 && D % 32 == 0 && DIN % 32 == 0, "MFMA tiling");
+  __shared__ __attribute__((aligned(16))) char smem[MlpSmem<BM, DIN, D, FCH>::bytes];
   bf16* sA = (bf16*)smem;
   bf16* sH = sA + BM * LDA;
   bf16* sW1 = sH + BM * LDH;
@@ -485,8 +530,8 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(GemmArgs g, const bf16* __rest
   auto fetchW = [&](int c0) {
 #pragma unroll
     for (int i = 0; i < PW1; ++i) {
-      const int idx = tid + i * 256, row = idx / (D / 8), kc = (idx - row * (D / 8)) * 8;
-      pw1[i] = *(const bf16x8*)(W1 + (long)(c0 + row) * D + kc);
+      const int idx = tid + i * 256, row = idx / (DIN / 8), kc = (idx - row * (DIN / 8)) * 8;
+      pw1[i] = *(const bf16x8*)(W1 + (long)(c0 + row) * DIN + kc);
     }
 #pragma unroll
     for (int i = 0; i < PW2; ++i) {
@@ -497,7 +542,7 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(GemmArgs g, const bf16* __rest
   auto stashW = [&]() {
 #pragma unroll
     for (int i = 0; i < PW1; ++i) {
-      const int idx = tid + i * 256, row = idx / (D / 8), kc = (idx - row * (D / 8)) * 8;
+      const int idx = tid + i * 256, row = idx / (DIN / 8), kc = (idx - row * (DIN / 8)) * 8;
       *(bf16x8*)&sW1[row * LDW1 + kc] = pw1[i];
     }
 #pragma unroll
@@ -508,12 +553,12 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(GemmArgs g, const bf16* __rest
   };
 
   fetchW(0);
-  constexpr int CPR = D / 8;
+  constexpr int CPR = DIN / 8;
   for (int idx = tid; idx < BM * CPR; idx += 256) {
     const int row = idx / CPR, kc = (idx - row * CPR) * 8;
     const long gm = m0 + row;
     bf16x8 v = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
-    if (gm < g.M) v = *(const bf16x8*)(A + gm * D + kc);
+    if (gm < g.M) v = *(const bf16x8*)(A + gm * DIN + kc);
     *(bf16x8*)&sA[row * LDA + kc] = v;
   }
   stashW();
@@ -536,7 +581,7 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(GemmArgs g, const bf16* __rest
 #pragma unroll
       for (int j = 0; j < TJ1; ++j) acc1[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ks = 0; ks < D; ks += 32) {
+    for (int ks = 0; ks < DIN; ks += 32) {
       bf16x8 fw[TI1], fa[TJ1];
 #pragma unroll
       for (int i = 0; i < TI1; ++i) fw[i] = *(const bf16x8*)&sW1[(wn1 + i * 16 + (lane & 15)) * LDW1 + ks + (lane >> 4) * 8];
@@ -604,24 +649,50 @@ template <int BM, int D, int FCH>
 hipError_t mlp_t(bool ln, const GemmArgs& g, const bf16* W1, const float* b1, const bf16* W2, int F, hipStream_t s) {
   if (F % FCH != 0) return hipErrorInvalidValue;
   dim3 grid((unsigned)((g.M + BM - 1) / BM)), block(256);
-  if (ln && g.out_scale) hipLaunchKernelGGL((k_mlp_bf16<BM, D, FCH, kEpiResidLN8>), grid, block, 0, s, g, W1, b1, W2, F);
-  else if (ln) hipLaunchKernelGGL((k_mlp_bf16<BM, D, FCH, kEpiResidLN>), grid, block, 0, s, g, W1, b1, W2, F);
-  else hipLaunchKernelGGL((k_mlp_bf16<BM, D, FCH, kEpiResid>), grid, block, 0, s, g, W1, b1, W2, F);
+  if (g.proj_out) hipLaunchKernelGGL((k_mlp_bf16<BM, D, D, FCH, kEpiResidProj>), grid, block, 0, s, g, W1, b1, W2, F);
+  else if (ln && g.out_scale) hipLaunchKernelGGL((k_mlp_bf16<BM, D, D, FCH, kEpiResidLN8>), grid, block, 0, s, g, W1, b1, W2, F);
+  else if (ln) hipLaunchKernelGGL((k_mlp_bf16<BM, D, D, FCH, kEpiResidLN>), grid, block, 0, s, g, W1, b1, W2, F);
+  else hipLaunchKernelGGL((k_mlp_bf16<BM, D, D, FCH, kEpiResid>), grid, block, 0, s, g, W1, b1, W2, F);
+  return hipGetLastError();
+}
+
+// Module A gate MLP: R = g R + (1 - g) E with g = sigmoid(W_g2 GELU(W_g1 [Z ; e] + b1) + b2),
+// then the first block's LayerNorm into XN (or XN8 with its scales).
+template <int BM, int D, int FCH>
+hipError_t gate_t(const GemmArgs& g, const bf16* W1, const float* b1, const bf16* W2, hipStream_t s) {
+  if (D % FCH != 0) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((g.M + BM - 1) / BM)), block(256);
+  if (g.out_scale) hipLaunchKernelGGL((k_mlp_bf16<BM, 2 * D, D, FCH, kEpiGateLN8>), grid, block, 0, s, g, W1, b1, W2, D);
+  else hipLaunchKernelGGL((k_mlp_bf16<BM, 2 * D, D, FCH, kEpiGateLN>), grid, block, 0, s, g, W1, b1, W2, D);
   return hipGetLastError();
 }
 
 }  // namespace
 
+// Fused-MLP tile shapes (BM tokens, FCH hidden columns per chunk).  The
+// hidden dimension is always consumed in 32-wide MFMA steps from 0 up, so every
+// shape gives the same result; the autotuner picks by time.
+int mlp_tile_count(int D) { return D == 128 ? 4 : (D == 64 || D == 256 ? 2 : 1); }
+
 // R += W2 GELU(W1 XN + b1) + b2 (g.A = XN, g.bias = b2, g.R = R, and with
 // g.ln_g set the next LayerNorm into g.out).
-hipError_t launch_mlp_bf16(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s) {
+hipError_t launch_mlp_bf16(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s,
+                           int tile) {
   if (g.M == 0) return hipSuccess;
   const bool ln = g.ln_g != nullptr;
   switch (g.N) {
-    case 64: return mlp_t<64, 64, 64>(ln, g, W1.b16, b1, W2.b16, F, s);
-    case 128: return mlp_t<64, 128, 64>(ln, g, W1.b16, b1, W2.b16, F, s);
+    case 64:
+      if (tile == 1) return mlp_t<32, 64, 64>(ln, g, W1.b16, b1, W2.b16, F, s);
+      return mlp_t<64, 64, 64>(ln, g, W1.b16, b1, W2.b16, F, s);
+    case 128:
+      if (tile == 1) return mlp_t<128, 128, 64>(ln, g, W1.b16, b1, W2.b16, F, s);
+      if (tile == 2) return mlp_t<32, 128, 64>(ln, g, W1.b16, b1, W2.b16, F, s);
+      if (tile == 3) return mlp_t<64, 128, 128>(ln, g, W1.b16, b1, W2.b16, F, s);
+      return mlp_t<64, 128, 64>(ln, g, W1.b16, b1, W2.b16, F, s);
     case 192: return mlp_t<64, 192, 64>(ln, g, W1.b16, b1, W2.b16, F, s);
-    case 256: return mlp_t<64, 256, 64>(ln, g, W1.b16, b1, W2.b16, F, s);
+    case 256:
+      if (tile == 1) return mlp_t<32, 256, 64>(ln, g, W1.b16, b1, W2.b16, F, s);
+      return mlp_t<64, 256, 64>(ln, g, W1.b16, b1, W2.b16, F, s);
     case 320: return mlp_t<32, 320, 64>(ln, g, W1.b16, b1, W2.b16, F, s);
     case 384: return mlp_t<32, 384, 64>(ln, g, W1.b16, b1, W2.b16, F, s);
     case 448: return mlp_t<32, 448, 32>(ln, g, W1.b16, b1, W2.b16, F, s);
@@ -629,6 +700,25 @@ hipError_t launch_mlp_bf16(const GemmArgs& g, const Mat& W1, const float* b1, co
     default: return hipErrorInvalidValue;
   }
 }
+
+// Module A gate MLP fused (g.A = [Z ; e] of width 2d, g.bias = b_g2, g.R = R,
+// g.E = e, g.ln_g / ln_b / out = the first block's LayerNorm output).
+hipError_t launch_gate_bf16(const GemmArgs& g, const Mat& Wg1, const float* bg1, const Mat& Wg2, hipStream_t s) {
+  if (g.M == 0) return hipSuccess;
+  switch (g.N) {
+    case 64: return gate_t<32, 64, 32>(g, Wg1.b16, bg1, Wg2.b16, s);
+    case 128: return gate_t<32, 128, 32>(g, Wg1.b16, bg1, Wg2.b16, s);
+    case 192: return gate_t<32, 192, 32>(g, Wg1.b16, bg1, Wg2.b16, s);
+    case 256: return gate_t<32, 256, 32>(g, Wg1.b16, bg1, Wg2.b16, s);
+    case 320: return gate_t<32, 320, 32>(g, Wg1.b16, bg1, Wg2.b16, s);
+    case 384: return gate_t<32, 384, 32>(g, Wg1.b16, bg1, Wg2.b16, s);
+    case 448: return gate_t<32, 448, 32>(g, Wg1.b16, bg1, Wg2.b16, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// d = 512 would need 172 KB of LDS for the [Z ; e] tile and one W_g1 chunk.
+bool gate_fusable(int d) { return d <= 448 && d % 64 == 0; }
 
 // ---------------------------------------------------------------------------
 // FP8 (OCP e4m3) token GEMMs fed by a LayerNorm: out = A W^T with A = XN8
@@ -886,7 +976,9 @@ template <int BM, int D, int FCH>
 hipError_t mlp8_t(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s) {
   if (F % FCH != 0) return hipErrorInvalidValue;
   dim3 grid((unsigned)((g.M + BM - 1) / BM)), block(256);
-  if (g.ln_g && g.out_scale)
+  if (g.proj_out)
+    hipLaunchKernelGGL((k_mlp_fp8<BM, D, FCH, kEpiResidProj>), grid, block, 0, s, g, W1.f8, W1.f8_scale, b1, W2.b16, F);
+  else if (g.ln_g && g.out_scale)
     hipLaunchKernelGGL((k_mlp_fp8<BM, D, FCH, kEpiResidLN8>), grid, block, 0, s, g, W1.f8, W1.f8_scale, b1, W2.b16, F);
   else
     hipLaunchKernelGGL((k_mlp_fp8<BM, D, FCH, kEpiResid>), grid, block, 0, s, g, W1.f8, W1.f8_scale, b1, W2.b16, F);

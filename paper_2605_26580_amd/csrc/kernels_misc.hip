@@ -353,6 +353,7 @@ __device__ __forceinline__ unsigned long long site_key(float margin, int flat) {
 
 __global__ __launch_bounds__(kTailThreads) void k_step_tail(StepCtx c, const float* logits) {
   __shared__ unsigned s_hist[256];
+  __shared__ int s_wsum[4];
   __shared__ unsigned long long s_prefix;
   __shared__ int s_need;
   __shared__ int s_cnt;
@@ -437,16 +438,26 @@ __global__ __launch_bounds__(kTailThreads) void k_step_tail(StepCtx c, const flo
           if (kk != 0ull && (kk & pmask) == prefix) atomicAdd(&s_hist[(kk >> shift) & 0xFFu], 1u);
         }
         __syncthreads();
-        if (tid == 0) {
-          int acc = 0;
-          for (int bk = 255; bk >= 0; --bk) {
-            int h = (int)s_hist[bk];
-            if (acc + h >= need) {
-              s_prefix = prefix | ((unsigned long long)bk << shift);
-              s_need = need - acc;
-              break;
-            }
-            acc += h;
+        // suffix scan over the 256 buckets (highest first) on four waves: the
+        // bucket where the running count first reaches `need` holds the r-th key
+        int v = 0, incl = 0;
+        if (tid < 256) {
+          v = (int)s_hist[255 - tid];
+          incl = v;
+#pragma unroll
+          for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o, 64);
+            if ((tid & 63) >= o) incl += t;
+          }
+          if ((tid & 63) == 63) s_wsum[tid >> 6] = incl;
+        }
+        __syncthreads();
+        if (tid < 256) {
+          for (int w = 0; w < (tid >> 6); ++w) incl += s_wsum[w];
+          const int excl = incl - v;
+          if (excl < need && incl >= need) {
+            s_prefix = prefix | ((unsigned long long)(255 - tid) << shift);
+            s_need = need - excl;
           }
         }
         __syncthreads();
