@@ -106,6 +106,12 @@ typedef struct {
   int32_t profile;            /* 1: time every kernel launch with HIP events   */
                               /*    on `stream` (eager launches, no graph);    */
                               /*    read with cider_profile_read         [0]   */
+  int32_t fused_blocks;       /* 1: BF16 runs each attention sublayer (QKV,    */
+                              /*    attention, output projection, residual,    */
+                              /*    next LayerNorm) as one kernel where the    */
+                              /*    shapes allow (d in {64,128,192}; row       */
+                              /*    attention needs n <= 128)            [1]   */
+                              /*    0: separate GEMM / attention kernels       */
   void*   workspace;          /* device scratch owned by the caller, or NULL   */
   size_t  workspace_bytes;    /* size of `workspace`; see cider_workspace_size */
 } cider_opts;

@@ -12,6 +12,10 @@ constexpr int kMask = 2;
 constexpr int kMaxK = 16;
 constexpr int kMaxN = 1024;
 constexpr int kMaxDeg = 32;
+// Fused attention blocks: token slots per workgroup (row attention holds a
+// whole row, so rows longer than kBlkRowSlots use the unfused kernels).
+constexpr int kBlkRowSlots = 128;
+constexpr int kBlkUserSlots = 64;
 
 typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((__vector_size__(8 * sizeof(__bf16))));
@@ -63,8 +67,10 @@ struct StepCtx {
   const DevBin* bins;       // device [num_bins]
   const int* slot_bin;      // device [total_slots]
   const int* row_bin;       // device [total_rows]
+  const int* ugrp;          // device [total_ugrp][2]: (bin, first column) of each user-attention block
   int total_slots;
   int total_rows;
+  int total_ugrp;
   long total_tokens;
   int max_n;                // largest n in the batch
   int schedule, remask, max_rounds, final_argmax;
@@ -159,6 +165,11 @@ hipError_t launch_mlp_bf16(const GemmArgs& g, const Mat& W1, const float* b1, co
                            int tile);
 int mlp_tile_count(int D);
 bool gate_fusable(int d);
+bool attn_block_ok(int d, int heads, int max_n, bool user);
+hipError_t launch_attn_block(const StepCtx& c, bool user, void* XN, const DevLayer& L, const float* ln_g,
+                             const float* ln_b, float* R, int d, int heads, hipStream_t s);
+// Columns of one K-row bin that one user-attention block covers.
+inline int ugrp_cols(int K) { return (kBlkUserSlots / 16) * (16 / K); }
 hipError_t launch_gate_bf16(const GemmArgs& g, const Mat& Wg1, const float* bg1, const Mat& Wg2, hipStream_t s);
 hipError_t launch_gemm_fp8(const GemmArgs& g, const Mat& W, hipStream_t s);
 hipError_t launch_mlp_fp8(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s);

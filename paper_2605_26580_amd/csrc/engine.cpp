@@ -192,8 +192,8 @@ int get_sched(cider_weights* w, int K, int n, int T, int kind, int** out) {
 struct Layout {
   int num_bins = 0;
   long total_tokens = 0;
-  int total_slots = 0, total_rows = 0, max_n = 0;
-  size_t off_R, off_E, off_ZE, off_H1, off_QKV, off_O, off_HID, off_lbar, off_logits, off_p, off_S,
+  int total_slots = 0, total_rows = 0, max_n = 0, total_ugrp = 0;
+  size_t off_ugrp = 0, off_R, off_E, off_ZE, off_H1, off_QKV, off_O, off_HID, off_lbar, off_logits, off_p, off_S,
       off_bins, off_state, off_slot, off_row, off_X, off_XN, off_XN8, off_xscale, total;
 };
 
@@ -225,6 +225,7 @@ Layout plan_layout(const cider_model_cfg& cfg, int num_bins, long T, int slots, 
   L.off_state = take((size_t)num_bins * sizeof(BinState));
   L.off_slot = take((size_t)slots * 4);
   L.off_row = take((size_t)rows * 4);
+  L.off_ugrp = take(((size_t)slots + num_bins) * 2 * 4);   // user-attention groups, at most one per column
   L.off_X = take(T);
   L.total = o;
   return L;
@@ -270,6 +271,7 @@ struct Run {
   Work work{};
   int prec = 0;
   int forced_tile = -1;   // >= 0: every GEMM uses this tile (tests)
+  bool use_blocks = true; // fused attention blocks where the shapes allow
 };
 
 // Brackets a launch with events when profiling is on.
@@ -388,6 +390,9 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
     g.a_scale = k.xscale;
     return launch_gemm_fp8(g, W, s);
   };
+  // BF16: fused attention blocks where the shapes allow (row attention needs n <= 128)
+  const bool blk_row = prec == kBF16 && r.use_blocks && attn_block_ok(d, m.heads, c.max_n, false);
+  const bool blk_user = prec == kBF16 && r.use_blocks && attn_block_ok(d, m.heads, c.max_n, true);
   TIMED("embed_demix", launch_embed_demix(c, w->ew, k, prec, s));
   GemmArgs g{};
   g.M = T;
@@ -408,25 +413,34 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
   for (int l = 0; l < m.n_layers; ++l) {
     const DevLayer& L = m.layer[l];
     if (!fused_ln) TIMED("layernorm", ln(L.ln1_g, L.ln1_b));
-    g = GemmArgs{}; g.M = T;
-    g.N = 3 * d; g.Kd = d; g.A = k.XN; g.bias = L.bqkv_r; g.out = k.QKV;
-    TIMED("gemm_qkv_row", qkv(g, L.Wqkv_r));
-    if (prec == kF32) TIMED("attn_row", launch_row_attn(c, prec, k.QKV, k.O, d, m.heads, c.max_n, s));
-    else TIMED("attn_row", launch_row_attn_mfma(c, k.QKV, k.O, d, m.heads, c.max_n, s));
-    g = GemmArgs{}; g.M = T;
-    g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_r; g.R = k.R;
-    next_ln(g, L.ln2_g, L.ln2_b);
-    TIMED("gemm_o_row", gemm(kEpiResid, g, L.Wo_r));
+    if (blk_row) {
+      // BF16: QKV projection, row attention, output projection, residual and LN2 in one kernel
+      TIMED("attn_block_row", launch_attn_block(c, false, k.XN, L, L.ln2_g, L.ln2_b, k.R, d, m.heads, s));
+    } else {
+      g = GemmArgs{}; g.M = T;
+      g.N = 3 * d; g.Kd = d; g.A = k.XN; g.bias = L.bqkv_r; g.out = k.QKV;
+      TIMED("gemm_qkv_row", qkv(g, L.Wqkv_r));
+      if (prec == kF32) TIMED("attn_row", launch_row_attn(c, prec, k.QKV, k.O, d, m.heads, c.max_n, s));
+      else TIMED("attn_row", launch_row_attn_mfma(c, k.QKV, k.O, d, m.heads, c.max_n, s));
+      g = GemmArgs{}; g.M = T;
+      g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_r; g.R = k.R;
+      next_ln(g, L.ln2_g, L.ln2_b);
+      TIMED("gemm_o_row", gemm(kEpiResid, g, L.Wo_r));
+    }
     if (!fused_ln) TIMED("layernorm", ln(L.ln2_g, L.ln2_b));
-    g = GemmArgs{}; g.M = T;
-    g.N = 3 * d; g.Kd = d; g.A = k.XN; g.bias = L.bqkv_u; g.out = k.QKV;
-    TIMED("gemm_qkv_user", qkv(g, L.Wqkv_u));
-    if (prec == kF32) TIMED("attn_user", launch_user_attn(c, prec, k.QKV, k.O, d, m.heads, s));
-    else TIMED("attn_user", launch_user_attn_bf16(c, k.QKV, k.O, d, m.heads, s));
-    g = GemmArgs{}; g.M = T;
-    g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_u; g.R = k.R;
-    next_ln(g, L.ln3_g, L.ln3_b);
-    TIMED("gemm_o_user", gemm(kEpiResid, g, L.Wo_u));
+    if (blk_user) {
+      TIMED("attn_block_user", launch_attn_block(c, true, k.XN, L, L.ln3_g, L.ln3_b, k.R, d, m.heads, s));
+    } else {
+      g = GemmArgs{}; g.M = T;
+      g.N = 3 * d; g.Kd = d; g.A = k.XN; g.bias = L.bqkv_u; g.out = k.QKV;
+      TIMED("gemm_qkv_user", qkv(g, L.Wqkv_u));
+      if (prec == kF32) TIMED("attn_user", launch_user_attn(c, prec, k.QKV, k.O, d, m.heads, s));
+      else TIMED("attn_user", launch_user_attn_bf16(c, k.QKV, k.O, d, m.heads, s));
+      g = GemmArgs{}; g.M = T;
+      g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_u; g.R = k.R;
+      next_ln(g, L.ln3_g, L.ln3_b);
+      TIMED("gemm_o_user", gemm(kEpiResid, g, L.Wo_u));
+    }
     if (!fused_ln) TIMED("layernorm", ln(L.ln3_g, L.ln3_b));
     if (fused_ln) {
       // BF16: up, GELU and down in one kernel, hidden layer on chip
@@ -616,12 +630,16 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
   char* base = nullptr;
   int rc = ensure_ws(w, o, L.total, &base);
   if (rc) return rc;
-  size_t meta = B * sizeof(DevBin) + (size_t)(slots + rows) * 4;
+  int ngrp = 0;
+  for (const BinIn& b : bins) ngrp += (b.n + ugrp_cols(b.K) - 1) / ugrp_cols(b.K);
+  size_t meta = B * sizeof(DevBin) + (size_t)(slots + rows) * 4 + (size_t)ngrp * 2 * 4;
   rc = ensure_pinned(w, meta);
   if (rc) return rc;
   DevBin* hb = (DevBin*)w->pinned;
   int* hslot = (int*)((char*)w->pinned + B * sizeof(DevBin));
   int* hrow = hslot + slots;
+  int* hgrp = hrow + rows;
+  int go = 0;
   long tok = 0;
   int so = 0, ro = 0;
   for (int i = 0; i < B; ++i) {
@@ -643,6 +661,11 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
     hb[i] = db;
     for (int l = 0; l < b.n; ++l) hslot[so + l] = i;
     for (int k = 0; k < b.K; ++k) hrow[ro + k] = i;
+    for (int l0 = 0; l0 < b.n; l0 += ugrp_cols(b.K)) {
+      hgrp[2 * go] = i;
+      hgrp[2 * go + 1] = l0;
+      ++go;
+    }
     tok += (long)b.K * b.n;
     so += b.n;
     ro += b.K;
@@ -651,6 +674,7 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
   HIPCHK(hipMemcpyAsync(base + L.off_bins, hb, B * sizeof(DevBin), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(base + L.off_slot, hslot, (size_t)slots * 4, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(base + L.off_row, hrow, (size_t)rows * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(base + L.off_ugrp, hgrp, (size_t)ngrp * 2 * 4, hipMemcpyHostToDevice, s));
   HIPCHK(hipEventRecord(w->meta_done, s));
 
   StepCtx& c = r->ctx;
@@ -659,8 +683,10 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
   c.bins = (const DevBin*)(base + L.off_bins);
   c.slot_bin = (const int*)(base + L.off_slot);
   c.row_bin = (const int*)(base + L.off_row);
+  c.ugrp = (const int*)(base + L.off_ugrp);
   c.total_slots = slots;
   c.total_rows = rows;
+  c.total_ugrp = ngrp;
   c.total_tokens = T;
   c.max_n = max_n;
   c.schedule = o.schedule;
@@ -719,6 +745,7 @@ int decode_impl(cider_weights* w, const std::vector<BinIn>& bins, int steps, con
   rc = prepare(w, bins, steps, o, s, &r, &L, true);
   if (rc) return rc;
   if (o.autotune >= 2) r.forced_tile = o.autotune - 2;
+  r.use_blocks = o.fused_blocks != 0;
   if (o.autotune == 1 && !w->prof_on) {
     rc = autotune_forward(w, r, s);
     if (rc) return rc;
@@ -766,6 +793,7 @@ void cider_opts_default(cider_opts* o) {
   o->lam_min = 1e-6f;
   o->autotune = 1;
   o->profile = 0;
+  o->fused_blocks = 1;
   o->workspace = nullptr;
   o->workspace_bytes = 0;
 }
@@ -1010,6 +1038,7 @@ int cider_step_debug(const uint8_t* X_in, uint8_t* X_out, const float* y, float 
   uint8_t* Xw = (uint8_t*)(base + L.off_X);
   HIPCHK(hipMemcpyAsync(Xw, X_in, (size_t)K * n, hipMemcpyDeviceToDevice, s));
   if (o.autotune >= 2) r.forced_tile = o.autotune - 2;
+  r.use_blocks = o.fused_blocks != 0;
   r.ctx.gamma_override = gamma;
   r.ctx.reveal_override = reveal_count;
   r.ctx.first_override = first ? 1 : 0;
@@ -1240,6 +1269,7 @@ void server_loop(cider_server* S) {
       std::lock_guard<std::mutex> lk(w->mu);
       int rc = prepare(w, bins, T, o, S->stream, &run, &L, false);
       if (rc) { fail_all(rc); break; }
+      run.use_blocks = o.fused_blocks != 0;
       changed = false;
     }
     // ---- one refinement step for every resident bin

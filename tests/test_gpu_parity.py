@@ -55,6 +55,13 @@ CASES = [
     (2, 256, 1, 256, 8),
     (3, 64, 1, 192, 6),
     (2, 128, 1, 384, 12),
+    # ragged tiles of the fused attention blocks: a row of 44 tokens ends in a
+    # part-filled 16-slot tile; K = 3, 7, 9 leave padding slots in each user
+    # tile (floor(16/K) columns of K tokens); K = 16 fills a tile with one column
+    (3, 44, 1, 64, 4),
+    (7, 36, 1, 128, 8),
+    (9, 20, 1, 64, 2),
+    (16, 24, 1, 64, 4),
 ]
 
 
@@ -284,21 +291,61 @@ def test_every_gemm_tile_teacher_forced(K, n, L, d, h):
     X[rng.random((K, n)) < 0.5] = 2
     gamma = float((X == 2).mean())
     ref = denoise(X, p, code, w, L, h, gamma)
-    base = None
-    for tile in (0, 1, 2, 3, 0):
-        say(f"forced tile {tile} d={d}")
-        opts = P.cider_opts_default(precision=P.CIDER_BF16, autotune=2 + tile)
+    for fused in (1, 0):
+        base = None
+        for tile in (0, 1, 2, 3, 0):
+            say(f"forced tile {tile} d={d} fused_blocks={fused}")
+            opts = P.cider_opts_default(precision=P.CIDER_BF16, autotune=2 + tile, fused_blocks=fused)
+            lg = torch.zeros(K, n, 2, dtype=torch.float32, device="cuda")
+            P.cider_step_debug(_dev(X), None, _dev(y), s2, ch, K, n, wh, gamma, 0, 0, opts, out_logits=lg)
+            torch.cuda.synchronize()
+            got = lg.cpu().numpy()
+            err = rel_err(got, ref["logits"])
+            print(f"  tile {tile} fused {fused}: err {err:.2e}")
+            assert err <= TOL["bf16"], (tile, fused, err)
+            if base is None:
+                base = got
+            else:
+                assert np.array_equal(got, base), f"tile {tile} differs from tile 0 (fused_blocks={fused})"
+
+
+@pytest.mark.parametrize("K,n,L,d,h", [(4, 128, 2, 128, 8), (3, 44, 2, 64, 4), (7, 36, 1, 192, 6),
+                                       (5, 64, 1, 128, 2), (1, 100, 1, 64, 4)])
+def test_fused_blocks_match_separate_kernels(K, n, L, d, h):
+    """The fused attention block (QKV, attention, output projection, residual
+    and LayerNorm in one kernel) rounds at the same points as the separate
+    GEMM / attention kernels, so the two BF16 paths agree far inside the BF16
+    tolerance; both are also held to that tolerance against the oracle."""
+    torch = torch_cuda()
+    P = lib()
+    cfg = synth.ModelCfg(L, d, h, n_max=max(n, 64))
+    wh, w = weights_handle(cfg, seed=91 + d, bias_std=0.02, ln_std=0.05)
+    code = code_of(n, 1000 + n)
+    ch = code_handle(code)
+    bins = synth.make_bins(code, K, 1, 4.0, seed=9 + K)
+    y, s2 = bins.y[0], float(bins.sigma2[0])
+    _, p = evidence(y.astype(np.float64), s2, K)
+    rng = np.random.default_rng(17 + n)
+    X = rng.integers(0, 2, size=(K, n)).astype(np.uint8)
+    X[rng.random((K, n)) < 0.4] = 2
+    gamma = float((X == 2).mean())
+    ref = denoise(X, p, code, w, L, h, gamma)
+    got = {}
+    for fused in (1, 0):
+        say(f"fused_blocks={fused} K={K} n={n} L={L} d={d} h={h}")
+        opts = P.cider_opts_default(precision=P.CIDER_BF16, fused_blocks=fused)
         lg = torch.zeros(K, n, 2, dtype=torch.float32, device="cuda")
-        P.cider_step_debug(_dev(X), None, _dev(y), s2, ch, K, n, wh, gamma, 0, 0, opts, out_logits=lg)
+        z = torch.zeros(K, n, d, dtype=torch.float32, device="cuda")
+        P.cider_step_debug(_dev(X), None, _dev(y), s2, ch, K, n, wh, gamma, 0, 0, opts, out_logits=lg, out_z=z)
         torch.cuda.synchronize()
-        got = lg.cpu().numpy()
-        err = rel_err(got, ref["logits"])
-        print(f"  tile {tile}: err {err:.2e}")
-        assert err <= TOL["bf16"], (tile, err)
-        if base is None:
-            base = got
-        else:
-            assert np.array_equal(got, base), f"tile {tile} differs from tile 0"
+        got[fused] = (lg.cpu().numpy(), z.cpu().numpy())
+        err = rel_err(got[fused][0], ref["logits"])
+        print(f"  fused {fused}: logits err vs oracle {err:.2e}")
+        assert err <= TOL["bf16"], (fused, err)
+    e_log = rel_err(got[1][0], got[0][0])
+    e_z = rel_err(got[1][1], got[0][1])
+    print(f"  fused vs separate: logits {e_log:.2e} z {e_z:.2e}")
+    assert e_log <= TOL["bf16"] / 2 and e_z <= 5e-2, (e_log, e_z)
 
 
 def test_every_gemm_tile_gives_identical_decodes():
