@@ -96,6 +96,8 @@ def algorithmic(model, n, K, es: int):
         "gemm_qkv_user": 2 * d * 3 * d, "gemm_o_user": 2 * d * d,
         "gemm_mlp_up": 2 * d * F, "gemm_mlp_down": 2 * F * d, "mlp_fused": 4 * d * F,
         "attn_row": 4 * n * d, "attn_user": 4 * K * d,
+        "attn_block_row": 8 * d * d + 4 * n * d, "attn_block_user": 8 * d * d + 4 * K * d,
+        "gate_fused": 6 * d * d,
     }
     # minimum bytes: inputs read once, outputs written once; residual updates read and
     # write the FP32 stream and (BF16) write the next LayerNorm's compute-type copy
@@ -107,11 +109,17 @@ def algorithmic(model, n, K, es: int):
         "mlp_fused": d * es + 8 * d + d * es,
         "attn_row": (3 * d + d) * es, "attn_user": (3 * d + d) * es,
         "layernorm": 4 * d + d * es,
+        # fused attention sublayer: XN in, FP32 residual read and written, next XN out
+        "attn_block_row": 2 * d * es + 8 * d, "attn_block_user": 2 * d * es + 8 * d,
+        # gate MLP: [Z ; e] in, residual stream and e read, residual and first XN written
+        "gate_fused": 3 * d * es + 12 * d,
     }
     return per_tok, flop, byt
 
 
-KERNEL_SOURCE = {"mlp_fused": "kernels_fast.hip", "attn_row": "kernels_fast.hip", "attn_user": "kernels_fast.hip"}
+KERNEL_SOURCE = {"mlp_fused": "kernels_fast.hip", "attn_row": "kernels_fast.hip", "attn_user": "kernels_fast.hip",
+                 "gate_fused": "kernels_fast.hip", "attn_block_row": "kernels_block.hip",
+                 "attn_block_user": "kernels_block.hip"}
 
 
 def _measured_traffic(workload: str, kernel: str):

@@ -306,8 +306,15 @@ __device__ __forceinline__ void row_pass(const float* sC, long m0, int n0, const
   }
 }
 
+// Workgroups of 4 waves that LDS lets share a CU: the register budget the
+// compiler may use without lowering occupancy below what LDS already sets.
+constexpr int lds_waves(size_t bytes) {
+  return (int)(163840 / bytes) < 1 ? 1 : ((int)(163840 / bytes) > 8 ? 8 : (int)(163840 / bytes));
+}
+
 template <int BM, int BN, int BK, int EPI>
-__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, const bf16* __restrict__ W) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(lds_waves(GemmSmem<BM, BN, BK>::bytes))))
+void k_gemm_bf16(GemmArgs g, const bf16* __restrict__ W) {
   constexpr int TI = BN / 32;  // column blocks per wave
   constexpr int TJ = BM / 32;  // token blocks per wave
   constexpr int LDK = BK + GPAD;
@@ -507,8 +514,9 @@ struct MlpSmem {
 };
 
 template <int BM, int DIN, int D, int FCH, int EPI>
-__global__ __launch_bounds__(256) void k_mlp_bf16(GemmArgs g, const bf16* __restrict__ W1, const float* __restrict__ b1,
-                                                  const bf16* __restrict__ W2, int F) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(lds_waves(MlpSmem<BM, DIN, D, FCH>::bytes))))
+void k_mlp_bf16(GemmArgs g, const bf16* __restrict__ W1, const float* __restrict__ b1, const bf16* __restrict__ W2,
+                int F) {
   constexpr int LDA = DIN + GPAD, LDH = FCH + GPAD, LDW1 = DIN + GPAD, LDW2 = FCH + GPAD;
   constexpr int TI1 = FCH / 32, TJ1 = BM / 32;   // up GEMM: (FCH/2) hidden x (BM/2) tokens per wave
   constexpr int TI2 = D / 32, TJ2 = BM / 32;     // down GEMM: (D/2) outputs x (BM/2) tokens per wave
@@ -574,12 +582,16 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(GemmArgs g, const bf16* __rest
   for (int c0 = 0; c0 < F; c0 += FCH) {
     const bool more = c0 + FCH < F;
     if (more) fetchW(c0 + FCH);
-    // up: H[token][j] = GELU(sum_k XN[token][k] W1[c0 + j][k] + b1[c0 + j])
+    // up: H[token][j] = GELU(b1[c0 + j] + sum_k XN[token][k] W1[c0 + j][k]),
+    // the accumulators starting from the bias
     f32x4 acc1[TI1][TJ1];
 #pragma unroll
-    for (int i = 0; i < TI1; ++i)
+    for (int i = 0; i < TI1; ++i) {
+      const int hn = wn1 + i * 16 + (lane >> 4) * 4;
+      const f32x4 bb = f32x4{b1[c0 + hn], b1[c0 + hn + 1], b1[c0 + hn + 2], b1[c0 + hn + 3]};
 #pragma unroll
-      for (int j = 0; j < TJ1; ++j) acc1[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int j = 0; j < TJ1; ++j) acc1[i][j] = bb;
+    }
 #pragma unroll
     for (int ks = 0; ks < DIN; ks += 32) {
       bf16x8 fw[TI1], fa[TJ1];
@@ -595,13 +607,10 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(GemmArgs g, const bf16* __rest
 #pragma unroll
     for (int i = 0; i < TI1; ++i) {
       const int hn = wn1 + i * 16 + (lane >> 4) * 4;
-      f32x4 bb;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) bb[r] = b1[c0 + hn + r];
 #pragma unroll
       for (int j = 0; j < TJ1; ++j) {
         const int ml = wm + j * 16 + (lane & 15);
-        const f32x4 v = acc1[i][j] + bb;
+        const f32x4 v = acc1[i][j];
         bf16x4 hv = {(bf16)gelu_f(v[0]), (bf16)gelu_f(v[1]), (bf16)gelu_f(v[2]), (bf16)gelu_f(v[3])};
         *(bf16x4*)&sH[ml * LDH + hn] = hv;
       }
