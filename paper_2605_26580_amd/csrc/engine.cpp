@@ -456,6 +456,9 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
         g.A = k.XN8;
         g.a_scale = k.xscale;
         TIMED("mlp_fused", launch_mlp_fp8(g, L.W1, L.b1, L.W2, F, s));
+      } else if (mlp3_ok(d, F)) {
+        // token-resident MLP: 256 tokens per workgroup, weights streamed once per tile
+        TIMED("mlp_fused", launch_mlp3_bf16(g, L.W1, L.b1, L.W2, F, s));
       } else {
         int mt = tile_for(w, kMlpKey, g);
         if (r.forced_tile >= 0) mt = r.forced_tile < mlp_tile_count(d) ? r.forced_tile : 0;
@@ -515,12 +518,18 @@ int autotune_forward(cider_weights* w, const Run& r, hipStream_t s) {
   const DevLayer& L = m.layer[0];
   int rc;
   GemmArgs g{};
-  g = GemmArgs{}; g.M = T; g.N = 3 * d; g.Kd = d; g.A = k.XN; g.bias = L.bqkv_r; g.out = k.QKV;
-  if ((rc = tune_gemm(w, "gemm_qkv", kEpiStore, g, L.Wqkv_r, s))) return rc;
-  g = GemmArgs{}; g.M = T; g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_r; g.R = k.R;
-  g.ln_g = L.ln2_g; g.ln_b = L.ln2_b; g.out = k.XN;
-  if ((rc = tune_gemm(w, "gemm_o_ln", kEpiResid, g, L.Wo_r, s))) return rc;
-  if (r.prec == kBF16) {
+  // the separate QKV / output-projection GEMMs run only where a fused
+  // attention block does not
+  const bool blocks = r.prec == kBF16 && r.use_blocks && attn_block_ok(d, m.heads, r.ctx.max_n, false) &&
+                      attn_block_ok(d, m.heads, r.ctx.max_n, true);
+  if (!blocks) {
+    g = GemmArgs{}; g.M = T; g.N = 3 * d; g.Kd = d; g.A = k.XN; g.bias = L.bqkv_r; g.out = k.QKV;
+    if ((rc = tune_gemm(w, "gemm_qkv", kEpiStore, g, L.Wqkv_r, s))) return rc;
+    g = GemmArgs{}; g.M = T; g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_r; g.R = k.R;
+    g.ln_g = L.ln2_g; g.ln_b = L.ln2_b; g.out = k.XN;
+    if ((rc = tune_gemm(w, "gemm_o_ln", kEpiResid, g, L.Wo_r, s))) return rc;
+  }
+  if (r.prec == kBF16 && !mlp3_ok(d, F)) {
     g = GemmArgs{}; g.M = T; g.N = d; g.Kd = d; g.A = k.XN; g.bias = L.b2; g.R = k.R;
     g.ln_g = L.ln1_g; g.ln_b = L.ln1_b; g.out = k.XN;
     if ((rc = tune_mlp(w, g, L, F, s))) return rc;

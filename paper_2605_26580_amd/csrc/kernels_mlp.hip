@@ -1,0 +1,274 @@
+// Token-resident fused MLP for the BF16 path (gfx950).
+//
+//   R += W2 GELU(W1 XN + b1) + b2, then the next LayerNorm of R into XN
+//   (or, after the last block, the final LayerNorm and the 2-way symbol
+//   projection into lbar).
+//
+// A workgroup owns 256 tokens: NW waves of TB 32-token blocks each (d = 128:
+// 8 waves x 1 block, two waves per SIMD; d = 256: 4 waves x 2 blocks, one
+// wave per SIMD with the accumulators in AGPRs, so that every weight fragment
+// read from LDS feeds two MFMAs).  Each wave keeps its XN rows in registers
+// for the whole kernel as the B operand of v_mfma_f32_32x32x16_bf16 (lane l:
+// token l%32 of a block, k-group l/32) and walks the hidden dimension in
+// chunks of 32.  The chunk's W1 rows and W2 columns go
+// from global memory straight into LDS (global_load_lds_dwordx4, no register
+// staging), double-buffered, and every wave reads them as A operands:
+//   up:    H[32 hidden][32 tokens]  = W1c[32][D] XN^T, D/16 MFMAs
+//   GELU on the 16 values a lane holds, rounded to BF16;
+//   down:  OUT[D][32 tokens] += W2c[D][32] H, 2 MFMAs per 32 output rows.
+// The H block never leaves registers.  Output register r of lane l holds row
+// 8(r/4) + 4(l/32) + r%4 of the up product; the W1 chunk is stored with its
+// rows permuted (row j holds hidden unit sigma(j)) so that registers
+// 8s..8s+7 of lane group l/32 hold hidden units 16s + 8(l/32) + 0..7 -- the
+// k-values that group supplies to k-step s of the down MFMA, with W2 in its
+// natural column order.
+// Each DMA instruction fills 1 KB of LDS contiguously, 16 bytes per lane;
+// rows are padded by 16 bytes (W1: D + 8 elements, W2: 40) so that the
+// A-operand reads, lane base + a constant per k-step, are free of bank
+// conflicts with 32 or 64 banks.  Lanes that land on a pad write a harmless
+// copy; lanes past the end of a region are masked off.
+#include "cider_internal.h"
+#include "device_math.h"
+
+namespace cider {
+
+namespace {
+
+typedef float f32x16 __attribute__((__vector_size__(16 * sizeof(float))));
+
+constexpr int kM3BM = 256;                        // tokens per workgroup
+constexpr int kM3FCH = 32;                        // hidden units per chunk
+
+template <int D>
+struct M3Smem {
+  static constexpr int RB1 = D * 2 + 16;          // bytes per stored W1 chunk row (16 of them pad)
+  static constexpr int RB2 = kM3FCH * 2 + 16;     // bytes per stored W2 chunk row
+  static constexpr size_t w1 = (size_t)kM3FCH * RB1;
+  static constexpr size_t w2 = (size_t)D * RB2;
+  static constexpr size_t w1a = (w1 + 1023) / 1024 * 1024;   // whole DMA blocks
+  static constexpr size_t w2a = (w2 + 1023) / 1024 * 1024;
+  static constexpr size_t buf = w1a + w2a + 256;  // + the chunk's b1
+  static constexpr size_t bytes = 2 * buf;
+  static_assert(bytes <= 160 * 1024, "LDS");
+};
+
+// Row j of the stored W1 chunk holds hidden unit sigma(j) of the chunk.
+__device__ __forceinline__ int m3_sigma(int j) {
+  const int q = j >> 3, g = (j >> 2) & 1, i = j & 3;
+  return 16 * (q >> 1) + 8 * g + 4 * (q & 1) + i;
+}
+
+template <int D, int TB, int NW, int WPE, bool PROJ>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+void k_mlp3(GemmArgs g, const bf16* __restrict__ W1, const float* __restrict__ b1, const bf16* __restrict__ W2,
+            int F) {
+  using S = M3Smem<D>;
+  static_assert(NW * TB * 32 == kM3BM, "256 tokens per workgroup");
+  constexpr int NTHR = NW * 64;
+  constexpr int RB1 = S::RB1, RB2 = S::RB2;
+  constexpr int KS1 = D / 16;                     // up-projection k-steps
+  constexpr int OBK = D / 32;                     // 32-row output blocks
+  constexpr int N1 = (int)(S::w1a / 1024), N2 = (int)(S::w2a / 1024);   // DMA blocks per chunk
+  constexpr int NPW = (N1 + N2 + NW - 1) / NW;                        // per wave
+  __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
+  const long tok0 = (long)blockIdx.x * kM3BM + wave * (32 * TB) + l32;   // token of block t: tok0 + 32 t
+  const int nch = F / kM3FCH;
+  const bf16* __restrict__ A = (const bf16*)g.A;
+
+  // ---- weight chunk c -> LDS buffer: 1 KB DMA blocks spread over the waves;
+  // lane i of block u writes bytes [1024 u + 16 i, + 16) of its region.  The
+  // chunk's b1 goes through a register, loaded one chunk ahead.
+  float pb = 0.f;
+  auto dma = [&](int c, int buf) {
+    const int c0 = c * kM3FCH;
+    char* base = smem + buf * S::buf;
+#pragma unroll
+    for (int k = 0; k < NPW; ++k) {
+      const int u = wave + k * NW;                  // uniform over the wave
+      if (u >= N1 + N2) break;
+      const bool first = u < N1;
+      const int pos = (first ? u : u - N1) * 1024 + lane * 16;
+      const int rb = first ? RB1 : RB2;
+      const int j = pos / rb, o = pos - j * rb;
+      const bool data = o < rb - 16;                 // else a pad (copy something in bounds)
+      const bf16* src;
+      if (first) src = W1 + (long)(c0 + m3_sigma(data ? j : 0)) * D + (data ? o / 2 : 0);
+      else src = W2 + (long)(data ? j : 0) * F + c0 + (data ? o / 2 : 0);
+      char* dst = base + (first ? 0 : (int)S::w1a) + (pos - lane * 16);
+      if (pos < (first ? (int)S::w1 : (int)S::w2))
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+    }
+  };
+  auto bias_fetch = [&](int c) {
+    if (tid < kM3FCH) pb = b1[c * kM3FCH + tid];
+  };
+  auto bias_stash = [&](int buf) {
+    if (tid < kM3FCH) ((float*)(smem + buf * S::buf + S::w1a + S::w2a))[tid] = pb;
+  };
+
+  // ---- this wave's XN rows, resident for the whole kernel
+  bf16x8 xf[TB][KS1];
+#pragma unroll
+  for (int t = 0; t < TB; ++t) {
+    const long tok = tok0 + 32 * t;
+#pragma unroll
+    for (int s = 0; s < KS1; ++s)
+      xf[t][s] = tok < g.M ? *(const bf16x8*)(A + tok * D + 16 * s + 8 * g2) : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+  }
+
+  f32x16 acc2[OBK][TB];
+#pragma unroll
+  for (int b = 0; b < OBK; ++b)
+#pragma unroll
+    for (int t = 0; t < TB; ++t)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc2[b][t][r] = 0.f;
+
+  bias_fetch(0);
+  dma(0, 0);
+  bias_stash(0);
+  if (nch > 1) bias_fetch(1);
+  __syncthreads();                                // waits for this wave's DMA, then publishes
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    // the other buffer's last readers finished before the previous barrier
+    if (c + 1 < nch) {
+      dma(c + 1, buf ^ 1);
+      bias_stash(buf ^ 1);
+      if (c + 2 < nch) bias_fetch(c + 2);
+    }
+    const char* s1 = smem + buf * S::buf;
+    const char* s2 = smem + buf * S::buf + S::w1a;
+    const float* sb = (const float*)(smem + buf * S::buf + S::w1a + S::w2a);
+    // up: acc1[t][r] = sum_k W1[c0 + sigma(8(r/4) + 4 g2 + r%4)][k] XN[token][k]
+    f32x16 acc1[TB];
+#pragma unroll
+    for (int t = 0; t < TB; ++t)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc1[t][r] = 0.f;
+#pragma unroll
+    for (int s = 0; s < KS1; ++s) {
+      const bf16x8 a = *(const bf16x8*)(s1 + l32 * RB1 + (2 * s + g2) * 16);
+#pragma unroll
+      for (int t = 0; t < TB; ++t) acc1[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, xf[t][s], acc1[t], 0, 0, 0);
+    }
+    // register 4q + i holds hidden unit 16(q/2) + 8 g2 + 4(q%2) + i
+    bf16x8 hf[TB][2];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const f32x4 bq = *(const f32x4*)&sb[16 * (q >> 1) + 8 * g2 + 4 * (q & 1)];
+#pragma unroll
+      for (int t = 0; t < TB; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) hf[t][q >> 1][4 * (q & 1) + i] = (bf16)gelu_f(acc1[t][4 * q + i] + bq[i]);
+    }
+    // down: acc2[b] += W2[32 b + row][c0 + 16 s + 8 g2 + e] H[16 s + 8 g2 + e]
+#pragma unroll
+    for (int b = 0; b < OBK; ++b)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const bf16x8 w = *(const bf16x8*)(s2 + (32 * b + l32) * RB2 + (2 * s + g2) * 16);
+#pragma unroll
+        for (int t = 0; t < TB; ++t)
+          acc2[b][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, hf[t][s], acc2[b][t], 0, 0, 0);
+      }
+    __syncthreads();                              // DMA of chunk c + 1 complete and visible
+  }
+
+  // ---- epilogue per token block: lane holds output rows 32 b + 8 q + 4 g2 + i
+#pragma unroll
+  for (int t = 0; t < TB; ++t) {
+    const long tok = tok0 + 32 * t;
+    const bool tv = tok < g.M;
+    float* __restrict__ Rrow = g.R + (tv ? tok : 0) * D;
+    float sum = 0.f;
+#pragma unroll
+    for (int b = 0; b < OBK; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int f = 32 * b + 8 * q + 4 * g2;
+        const f32x4 bias = f32x4{g.bias[f], g.bias[f + 1], g.bias[f + 2], g.bias[f + 3]};
+        const f32x4 rr = tv ? *(const f32x4*)(Rrow + f) : f32x4{0.f, 0.f, 0.f, 0.f};
+        f32x4 res;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          res[i] = rr[i] + (acc2[b][t][4 * q + i] + bias[i]);
+          acc2[b][t][4 * q + i] = res[i];
+        }
+        if (tv) *(f32x4*)(Rrow + f) = res;
+        sum += (res[0] + res[1]) + (res[2] + res[3]);
+      }
+    sum += __shfl_xor(sum, 32, 64);
+    const float mean = sum / (float)D;
+    float qv = 0.f;
+#pragma unroll
+    for (int b = 0; b < OBK; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float dv = acc2[b][t][r] - mean;
+        qv = fmaf(dv, dv, qv);
+      }
+    qv += __shfl_xor(qv, 32, 64);
+    const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
+    if (!PROJ) {
+      if (tv) {
+        bf16* xo = (bf16*)g.out + tok * D;
+#pragma unroll
+        for (int b = 0; b < OBK; ++b)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int f = 32 * b + 8 * q + 4 * g2;
+            bf16x4 h;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              h[i] = (bf16)((acc2[b][t][4 * q + i] - mean) * rstd * g.ln_g[f + i] + g.ln_b[f + i]);
+            *(bf16x4*)(xo + f) = h;
+          }
+      }
+    } else {
+      float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+      for (int b = 0; b < OBK; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int f = 32 * b + 8 * q + 4 * g2;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float hv = (acc2[b][t][4 * q + i] - mean) * rstd * g.ln_g[f + i] + g.ln_b[f + i];
+            a0 = fmaf(hv, g.proj_w[f + i], a0);
+            a1 = fmaf(hv, g.proj_w[D + f + i], a1);
+          }
+        }
+      a0 += __shfl_xor(a0, 32, 64);
+      a1 += __shfl_xor(a1, 32, 64);
+      if (tv && g2 == 0) {
+        g.proj_out[2 * tok] = a0;
+        g.proj_out[2 * tok + 1] = a1;
+      }
+    }
+  }
+}
+
+template <int D, int TB, int NW, int WPE>
+hipError_t mlp3_t(const GemmArgs& g, const bf16* W1, const float* b1, const bf16* W2, int F, hipStream_t s) {
+  dim3 grid((unsigned)((g.M + kM3BM - 1) / kM3BM)), block(NW * 64);
+  if (g.proj_out) hipLaunchKernelGGL((k_mlp3<D, TB, NW, WPE, true>), grid, block, 0, s, g, W1, b1, W2, F);
+  else hipLaunchKernelGGL((k_mlp3<D, TB, NW, WPE, false>), grid, block, 0, s, g, W1, b1, W2, F);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool mlp3_ok(int d, int F) { return (d == 128 || d == 256) && F % kM3FCH == 0 && F >= kM3FCH; }
+
+// R += W2 GELU(W1 XN + b1) + b2 with the next LayerNorm into g.out (g.ln_g set)
+// or the final LayerNorm and projection into g.proj_out (g.proj_w set).
+hipError_t launch_mlp3_bf16(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s) {
+  if (g.M == 0) return hipSuccess;
+  if (!mlp3_ok(g.N, F) || !g.ln_g || g.out_scale) return hipErrorInvalidValue;
+  if (g.N == 128) return mlp3_t<128, 1, 8, 2>(g, W1.b16, b1, W2.b16, F, s);
+  return mlp3_t<256, 1, 8, 2>(g, W1.b16, b1, W2.b16, F, s);
+}
+
+}  // namespace cider

@@ -373,7 +373,10 @@ def test_every_gemm_tile_gives_identical_decodes():
                 ref = (out.clone(), lg.clone())
             else:
                 assert torch.equal(out, ref[0]) and torch.equal(lg, ref[1]), mode
-        assert len(P.cider_tuning_read(wh)) > 0
+        if d >= 256:
+            # d <= 192 runs fused attention blocks and (d = 128) the token-resident
+            # MLP, which have no tile shapes to tune
+            assert len(P.cider_tuning_read(wh)) > 0
 
 
 def test_fp8_rejects_narrow_models():
