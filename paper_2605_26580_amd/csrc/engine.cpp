@@ -384,7 +384,14 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
   };
   // the GEMMs fed by a LayerNorm (QKV, MLP up) read XN8 with its per-token
   // scale in FP8, the others stay BF16
+  // BF16 at d in {128, 256}: token-resident projections (256 tokens per
+  // workgroup, weights streamed through LDS once per tile)
+  const bool p3 = prec == kBF16 && proj3_ok(d);
+  auto oproj = [&](const GemmArgs& g, const Mat& W) -> hipError_t {
+    return p3 ? launch_oproj3_bf16(g, W, s) : gemm(kEpiResid, g, W);
+  };
   auto qkv = [&](GemmArgs& g, const Mat& W) -> hipError_t {
+    if (p3) return launch_proj3_bf16(g, W, s);
     if (!f8) return gemm(kEpiStore, g, W);
     g.A = k.XN8;
     g.a_scale = k.xscale;
@@ -425,7 +432,7 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
       g = GemmArgs{}; g.M = T;
       g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_r; g.R = k.R;
       next_ln(g, L.ln2_g, L.ln2_b);
-      TIMED("gemm_o_row", gemm(kEpiResid, g, L.Wo_r));
+      TIMED("gemm_o_row", oproj(g, L.Wo_r));
     }
     if (!fused_ln) TIMED("layernorm", ln(L.ln2_g, L.ln2_b));
     if (blk_user) {
@@ -439,7 +446,7 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
       g = GemmArgs{}; g.M = T;
       g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_u; g.R = k.R;
       next_ln(g, L.ln3_g, L.ln3_b);
-      TIMED("gemm_o_user", gemm(kEpiResid, g, L.Wo_u));
+      TIMED("gemm_o_user", oproj(g, L.Wo_u));
     }
     if (!fused_ln) TIMED("layernorm", ln(L.ln3_g, L.ln3_b));
     if (fused_ln) {
@@ -522,7 +529,7 @@ int autotune_forward(cider_weights* w, const Run& r, hipStream_t s) {
   // attention block does not
   const bool blocks = r.prec == kBF16 && r.use_blocks && attn_block_ok(d, m.heads, r.ctx.max_n, false) &&
                       attn_block_ok(d, m.heads, r.ctx.max_n, true);
-  if (!blocks) {
+  if (!blocks && !(r.prec == kBF16 && proj3_ok(d))) {
     g = GemmArgs{}; g.M = T; g.N = 3 * d; g.Kd = d; g.A = k.XN; g.bias = L.bqkv_r; g.out = k.QKV;
     if ((rc = tune_gemm(w, "gemm_qkv", kEpiStore, g, L.Wqkv_r, s))) return rc;
     g = GemmArgs{}; g.M = T; g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_r; g.R = k.R;

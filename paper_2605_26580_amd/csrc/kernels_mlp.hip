@@ -58,6 +58,88 @@ __device__ __forceinline__ int m3_sigma(int j) {
   return 16 * (q >> 1) + 8 * g + 4 * (q & 1) + i;
 }
 
+// Residual epilogue shared by the token-resident kernels: acc2[b][t] holds,
+// for token tok0 + 32 t, output rows 32 b + 8 q + 4 g2 + i in register 4q + i
+// (the two lanes l and l + 32 together hold the row).  R += acc2 + bias, then
+// the next LayerNorm into g.out (BF16) or, with PROJ, the final LayerNorm and
+// the 2-way projection into g.proj_out.
+template <int D, int TB, bool PROJ>
+__device__ __forceinline__ void m3_residual_epilogue(f32x16 (&acc2)[D / 32][TB], long tok0, const GemmArgs& g,
+                                                     int g2) {
+  constexpr int OBK = D / 32;
+#pragma unroll
+  for (int t = 0; t < TB; ++t) {
+    const long tok = tok0 + 32 * t;
+    const bool tv = tok < g.M;
+    float* __restrict__ Rrow = g.R + (tv ? tok : 0) * D;
+    float sum = 0.f;
+#pragma unroll
+    for (int b = 0; b < OBK; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int f = 32 * b + 8 * q + 4 * g2;
+        const f32x4 bias = f32x4{g.bias[f], g.bias[f + 1], g.bias[f + 2], g.bias[f + 3]};
+        const f32x4 rr = tv ? *(const f32x4*)(Rrow + f) : f32x4{0.f, 0.f, 0.f, 0.f};
+        f32x4 res;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          res[i] = rr[i] + (acc2[b][t][4 * q + i] + bias[i]);
+          acc2[b][t][4 * q + i] = res[i];
+        }
+        if (tv) *(f32x4*)(Rrow + f) = res;
+        sum += (res[0] + res[1]) + (res[2] + res[3]);
+      }
+    sum += __shfl_xor(sum, 32, 64);
+    const float mean = sum / (float)D;
+    float qv = 0.f;
+#pragma unroll
+    for (int b = 0; b < OBK; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float dv = acc2[b][t][r] - mean;
+        qv = fmaf(dv, dv, qv);
+      }
+    qv += __shfl_xor(qv, 32, 64);
+    const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
+    if (!PROJ) {
+      if (tv) {
+        bf16* xo = (bf16*)g.out + tok * D;
+#pragma unroll
+        for (int b = 0; b < OBK; ++b)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int f = 32 * b + 8 * q + 4 * g2;
+            bf16x4 h;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              h[i] = (bf16)((acc2[b][t][4 * q + i] - mean) * rstd * g.ln_g[f + i] + g.ln_b[f + i]);
+            *(bf16x4*)(xo + f) = h;
+          }
+      }
+    } else {
+      float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+      for (int b = 0; b < OBK; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int f = 32 * b + 8 * q + 4 * g2;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float hv = (acc2[b][t][4 * q + i] - mean) * rstd * g.ln_g[f + i] + g.ln_b[f + i];
+            a0 = fmaf(hv, g.proj_w[f + i], a0);
+            a1 = fmaf(hv, g.proj_w[D + f + i], a1);
+          }
+        }
+      a0 += __shfl_xor(a0, 32, 64);
+      a1 += __shfl_xor(a1, 32, 64);
+      if (tv && g2 == 0) {
+        g.proj_out[2 * tok] = a0;
+        g.proj_out[2 * tok + 1] = a1;
+      }
+    }
+  }
+}
+
 template <int D, int TB, int NW, int WPE, bool PROJ>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void k_mlp3(GemmArgs g, const bf16* __restrict__ W1, const float* __restrict__ b1, const bf16* __restrict__ W2,
@@ -176,78 +258,7 @@ void k_mlp3(GemmArgs g, const bf16* __restrict__ W1, const float* __restrict__ b
     __syncthreads();                              // DMA of chunk c + 1 complete and visible
   }
 
-  // ---- epilogue per token block: lane holds output rows 32 b + 8 q + 4 g2 + i
-#pragma unroll
-  for (int t = 0; t < TB; ++t) {
-    const long tok = tok0 + 32 * t;
-    const bool tv = tok < g.M;
-    float* __restrict__ Rrow = g.R + (tv ? tok : 0) * D;
-    float sum = 0.f;
-#pragma unroll
-    for (int b = 0; b < OBK; ++b)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int f = 32 * b + 8 * q + 4 * g2;
-        const f32x4 bias = f32x4{g.bias[f], g.bias[f + 1], g.bias[f + 2], g.bias[f + 3]};
-        const f32x4 rr = tv ? *(const f32x4*)(Rrow + f) : f32x4{0.f, 0.f, 0.f, 0.f};
-        f32x4 res;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          res[i] = rr[i] + (acc2[b][t][4 * q + i] + bias[i]);
-          acc2[b][t][4 * q + i] = res[i];
-        }
-        if (tv) *(f32x4*)(Rrow + f) = res;
-        sum += (res[0] + res[1]) + (res[2] + res[3]);
-      }
-    sum += __shfl_xor(sum, 32, 64);
-    const float mean = sum / (float)D;
-    float qv = 0.f;
-#pragma unroll
-    for (int b = 0; b < OBK; ++b)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const float dv = acc2[b][t][r] - mean;
-        qv = fmaf(dv, dv, qv);
-      }
-    qv += __shfl_xor(qv, 32, 64);
-    const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
-    if (!PROJ) {
-      if (tv) {
-        bf16* xo = (bf16*)g.out + tok * D;
-#pragma unroll
-        for (int b = 0; b < OBK; ++b)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int f = 32 * b + 8 * q + 4 * g2;
-            bf16x4 h;
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-              h[i] = (bf16)((acc2[b][t][4 * q + i] - mean) * rstd * g.ln_g[f + i] + g.ln_b[f + i]);
-            *(bf16x4*)(xo + f) = h;
-          }
-      }
-    } else {
-      float a0 = 0.f, a1 = 0.f;
-#pragma unroll
-      for (int b = 0; b < OBK; ++b)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int f = 32 * b + 8 * q + 4 * g2;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const float hv = (acc2[b][t][4 * q + i] - mean) * rstd * g.ln_g[f + i] + g.ln_b[f + i];
-            a0 = fmaf(hv, g.proj_w[f + i], a0);
-            a1 = fmaf(hv, g.proj_w[D + f + i], a1);
-          }
-        }
-      a0 += __shfl_xor(a0, 32, 64);
-      a1 += __shfl_xor(a1, 32, 64);
-      if (tv && g2 == 0) {
-        g.proj_out[2 * tok] = a0;
-        g.proj_out[2 * tok + 1] = a1;
-      }
-    }
-  }
+  m3_residual_epilogue<D, TB, PROJ>(acc2, tok0, g, g2);
 }
 
 template <int D, int TB, int NW, int WPE>
@@ -258,7 +269,191 @@ hipError_t mlp3_t(const GemmArgs& g, const bf16* W1, const float* b1, const bf16
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Token-resident projections with the same machinery (BF16, d in {128, 256}).
+//
+// k_proj3: out[M][N] = XN W^T + b in BF16 (the QKV projection, N = 3d).  A
+// workgroup of 8 waves owns 256 tokens; each wave keeps its 32 XN rows in
+// registers and walks the N outputs in chunks of 32 rows of W, DMA'd into
+// LDS (rows padded by 16 bytes), double-buffered.  Lane l ends a chunk with
+// outputs 8q + 4(l/32) + i of token l%32 and stores them as BF16.
+template <int D>
+struct P3Smem {
+  static constexpr int RB = D * 2 + 16;
+  static constexpr size_t w = (size_t)32 * RB;
+  static constexpr size_t wa = (w + 1023) / 1024 * 1024;
+  static constexpr size_t buf = wa + 256;         // + the chunk's bias
+  static constexpr size_t bytes = 2 * buf;
+};
+
+template <int D, int WPE>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+void k_proj3(GemmArgs g, const bf16* __restrict__ W) {
+  using S = P3Smem<D>;
+  constexpr int NW = 8, RB = S::RB, KS = D / 16;
+  constexpr int NB = (int)(S::wa / 1024), NPW = (NB + NW - 1) / NW;
+  __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
+  const long tok = (long)blockIdx.x * kM3BM + wave * 32 + l32;
+  const bool tv = tok < g.M;
+  const int N = g.N, nch = N / 32;
+  const bf16* __restrict__ A = (const bf16*)g.A;
+  bf16* __restrict__ out = (bf16*)g.out;
+
+  float pb = 0.f;
+  auto dma = [&](int c, int buf) {
+    char* base = smem + buf * S::buf;
+#pragma unroll
+    for (int k = 0; k < NPW; ++k) {
+      const int u = wave + k * NW;
+      if (u >= NB) break;
+      const int pos = u * 1024 + lane * 16, j = pos / RB, o = pos - j * RB;
+      const bool data = o < RB - 16;
+      const bf16* src = W + (long)(c * 32 + (data ? j : 0)) * D + (data ? o / 2 : 0);
+      if (pos < (int)S::w)
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(base + u * 1024), 16, 0, 0);
+    }
+  };
+  auto bias_fetch = [&](int c) {
+    if (tid < 32) pb = g.bias[c * 32 + tid];
+  };
+  auto bias_stash = [&](int buf) {
+    if (tid < 32) ((float*)(smem + buf * S::buf + S::wa))[tid] = pb;
+  };
+
+  bf16x8 xf[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s)
+    xf[s] = tv ? *(const bf16x8*)(A + tok * D + 16 * s + 8 * g2) : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+
+  bias_fetch(0);
+  dma(0, 0);
+  bias_stash(0);
+  if (nch > 1) bias_fetch(1);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) {
+      dma(c + 1, buf ^ 1);
+      bias_stash(buf ^ 1);
+      if (c + 2 < nch) bias_fetch(c + 2);
+    }
+    const char* sw = smem + buf * S::buf;
+    const float* sb = (const float*)(smem + buf * S::buf + S::wa);
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const bf16x8 a = *(const bf16x8*)(sw + l32 * RB + (2 * s + g2) * 16);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, xf[s], acc, 0, 0, 0);
+    }
+    if (tv) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int f = 8 * q + 4 * g2;
+        const f32x4 bq = *(const f32x4*)&sb[f];
+        const bf16x4 h = {(bf16)(acc[4 * q] + bq[0]), (bf16)(acc[4 * q + 1] + bq[1]), (bf16)(acc[4 * q + 2] + bq[2]),
+                          (bf16)(acc[4 * q + 3] + bq[3])};
+        *(bf16x4*)(out + tok * N + c * 32 + f) = h;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// k_oproj3: R += A W^T + b over K = d, then the next LayerNorm into g.out (the
+// output projection after attention, A = O in BF16).  Each wave owns 32
+// tokens and accumulates all d outputs (acc2, as in the MLP's down
+// projection); the contraction walks K in chunks of 32: W[:, k0:k0+32] is
+// DMA'd into LDS (80-byte rows) and the A rows' two k-fragments of the chunk
+// are read from memory one chunk ahead.
+template <int D>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_oproj3(GemmArgs g, const bf16* __restrict__ W) {
+  using S = M3Smem<D>;
+  constexpr int NW = 8, RB2 = S::RB2, OBK = D / 32, NCH = D / 32;
+  constexpr int NB = (int)(S::w2a / 1024), NPW = (NB + NW - 1) / NW;
+  constexpr size_t BUF = S::w2a;
+  __shared__ __attribute__((aligned(1024))) char smem[2 * BUF];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
+  const long tok0 = (long)blockIdx.x * kM3BM + wave * 32 + l32;
+  const bool tv = tok0 < g.M;
+  const bf16* __restrict__ A = (const bf16*)g.A;
+
+  auto dma = [&](int c, int buf) {
+    char* base = smem + buf * BUF;
+#pragma unroll
+    for (int k = 0; k < NPW; ++k) {
+      const int u = wave + k * NW;
+      if (u >= NB) break;
+      const int pos = u * 1024 + lane * 16, j = pos / RB2, o = pos - j * RB2;
+      const bool data = o < RB2 - 16;
+      const bf16* src = W + (long)(data ? j : 0) * D + c * 32 + (data ? o / 2 : 0);
+      if (pos < (int)S::w2)
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(base + u * 1024), 16, 0, 0);
+    }
+  };
+  auto afrag = [&](int c, bf16x8 (&f)[2]) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+      f[s] = tv ? *(const bf16x8*)(A + tok0 * D + c * 32 + 16 * s + 8 * g2) : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+  };
+
+  f32x16 acc2[OBK][1];
+#pragma unroll
+  for (int b = 0; b < OBK; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc2[b][0][r] = 0.f;
+  bf16x8 fa[2], fn[2];
+  afrag(0, fa);
+  dma(0, 0);
+  __syncthreads();
+#pragma unroll 1
+  for (int c = 0; c < NCH; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < NCH) {
+      dma(c + 1, buf ^ 1);
+      afrag(c + 1, fn);
+    }
+    const char* sw = smem + buf * BUF;
+#pragma unroll
+    for (int b = 0; b < OBK; ++b)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const bf16x8 w = *(const bf16x8*)(sw + (32 * b + l32) * RB2 + (2 * s + g2) * 16);
+        acc2[b][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, fa[s], acc2[b][0], 0, 0, 0);
+      }
+    fa[0] = fn[0];
+    fa[1] = fn[1];
+    __syncthreads();
+  }
+  m3_residual_epilogue<D, 1, false>(acc2, tok0, g, g2);
+}
+
 }  // namespace
+
+// out = XN W^T + b (BF16), N a multiple of 32.
+hipError_t launch_proj3_bf16(const GemmArgs& g, const Mat& W, hipStream_t s) {
+  if (g.M == 0) return hipSuccess;
+  if (!(g.Kd == 128 || g.Kd == 256) || g.N % 32 != 0 || g.N <= 0) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((g.M + kM3BM - 1) / kM3BM)), block(512);
+  if (g.Kd == 128) hipLaunchKernelGGL((k_proj3<128, 4>), grid, block, 0, s, g, W.b16);
+  else hipLaunchKernelGGL((k_proj3<256, 2>), grid, block, 0, s, g, W.b16);
+  return hipGetLastError();
+}
+
+// R += A W^T + b (A in BF16, K = N = d), then the next LayerNorm into g.out.
+hipError_t launch_oproj3_bf16(const GemmArgs& g, const Mat& W, hipStream_t s) {
+  if (g.M == 0) return hipSuccess;
+  if (!(g.N == 128 || g.N == 256) || g.Kd != g.N || !g.ln_g || g.out_scale || g.proj_out) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((g.M + kM3BM - 1) / kM3BM)), block(512);
+  if (g.N == 128) hipLaunchKernelGGL((k_oproj3<128>), grid, block, 0, s, g, W.b16);
+  else hipLaunchKernelGGL((k_oproj3<256>), grid, block, 0, s, g, W.b16);
+  return hipGetLastError();
+}
+
+bool proj3_ok(int d) { return d == 128 || d == 256; }
 
 bool mlp3_ok(int d, int F) { return (d == 128 || d == 256) && F % kM3FCH == 0 && F >= kM3FCH; }
 
