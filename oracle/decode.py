@@ -9,8 +9,12 @@ threshold; low rows are remasked, the others clamped, and T_rm =
 max(1, floor(T |K_low| / K)) steps are run, for at most a set number of
 rounds.  First-reveal applies only to the initial pass from the all-mask
 grid, and only when that pass has more than one step (a single step must
-reveal every site).  By default the output is the held-fixed grid; ``final_argmax``
-returns the per-site argmax of the last final pass instead.
+reveal every site); ``first_reveal`` = 1 narrows the step-1 candidates to each
+slot's best row (hybrid), 2 reveals all of those candidates at step 1 (the
+paper's wording).  The remask confidence is taken at the annealed
+temperature's end value tau_min.  By default the output is the held-fixed
+grid; ``final_argmax`` returns the per-site argmax of the last final pass
+instead.
 """
 from __future__ import annotations
 
@@ -23,13 +27,13 @@ import numpy as np
 from .denoiser import denoise
 from .evidence import evidence
 from .parity import syndrome
-from .schedule import MASK, cosine_targets, linear_targets, reveal
+from .schedule import MASK, cosine_targets, linear_targets, reveal, tau_schedule
 
 
 @dataclass
 class DecodeOpts:
     schedule: str = "linear"
-    first_reveal: bool = True
+    first_reveal: int = 1          # 0 off, 1 hybrid (candidates only), 2 verbatim (reveal them all)
     remask: bool = False
     remask_thr: float = 0.9
     remask_max_rounds: int = 2
@@ -38,6 +42,8 @@ class DecodeOpts:
     eta: float = 1.0
     lam_max: float = 20.0
     lam_min: float = 1e-6
+    tau_max: float = 1.0           # inference temperature at the first refinement step
+    tau_min: float = 1.0           # ... at the last; the remask confidence uses it
     parity: bool = True
 
 
@@ -52,11 +58,12 @@ class DecodeResult:
     min_gap: float = float("inf")
 
 
-def row_status(X: np.ndarray, fin_logits: np.ndarray, code, thr: float):
-    """(syndrome nonzero [K] bool, q [K] mean max-prob, low [K] bool)."""
+def row_status(X: np.ndarray, fin_logits: np.ndarray, code, thr: float, tau: float = 1.0):
+    """(syndrome nonzero [K] bool, q [K] mean max-prob at temperature tau, low [K] bool).
+    For two symbols max_a softmax(L / tau)_a = sigmoid(|L0 - L1| / tau)."""
     syn = syndrome(X, code).any(axis=1)
     c = np.abs(fin_logits[..., 0] - fin_logits[..., 1])
-    q = (1.0 / (1.0 + np.exp(-c))).mean(axis=1)
+    q = (1.0 / (1.0 + np.exp(-c / tau))).mean(axis=1)
     return syn, q, syn | (q < thr)
 
 
@@ -82,11 +89,13 @@ def run_pass(X: np.ndarray, T: int, den: Callable, opts: DecodeOpts, first: bool
         X_in = X.copy()
         out = den(X, gamma)
         logits = out["logits"] if isinstance(out, dict) else out
-        use_first = first and t == 1 and T > 1
+        use_first = bool(first) and t == 1 and T > 1
+        if use_first and int(first) == 2:
+            r = K * n                             # verbatim: every slot's selected site
         info = reveal(X, logits, r, use_first)
         done += len(info["selected"])
         rec = {"t": t, "r": r, "gamma": gamma, "first": use_first, "gaps": info["gaps"],
-               "selected": info["selected"]}
+               "selected": info["selected"], "tau": tau_schedule(t, T, opts.tau_max, opts.tau_min)}
         if keep:
             rec["X_in"] = X_in
             rec["logits"] = logits
@@ -105,7 +114,7 @@ def decode_grid(K: int, n: int, code, den: Callable, T: int, opts: DecodeOpts,
     while True:
         out = den(X, float((X == MASK).sum()) / float(K * n))
         fin = out["logits"] if isinstance(out, dict) else out
-        syn, q, low = row_status(X, fin, code, opts.remask_thr)
+        syn, q, low = row_status(X, fin, code, opts.remask_thr, opts.tau_min)
         finals.append({"logits": fin, "low": low.copy(), "q": q, "syn": syn,
                        "gap_q": float(np.min(np.abs(q - opts.remask_thr))) if opts.remask else float("inf")})
         if not opts.remask or rounds >= opts.remask_max_rounds or not low.any():

@@ -13,7 +13,15 @@ Readings taken here (all stated in the design notes):
   * ties in the ranking go to the smaller flat index k*n + l, ties in the
     first-reveal row choice to the smaller k, ties in the argmax to bit 0;
   * first-reveal restricts the step-1 candidate set, and the number revealed
-    still follows the schedule;
+    still follows the schedule ("hybrid", the default); the paper's verbatim
+    rule -- step 1 reveals every slot's selected site -- is the other mode,
+    after which the cumulative targets resume (steps whose target is already
+    met reveal nothing under the linear schedule, one site under cosine);
+  * the inference temperature is annealed from tau_max at the first step to
+    tau_min at the last by the paper's cosine weight; with two symbols the
+    max-probability order of softmax(L / tau) is the margin order for every
+    tau > 0, so tau_t changes no reveal, and only the final pass's
+    confidence (the remask test, taken at tau_min) depends on it;
   * linear schedule (R_t = floor(t N / T)) by default; the cosine schedule
     R_t = floor(rho(t) N), rho(t) = (1 - cos(pi t / T)) / 2, evaluated in
     float64 with at least one site per step.
@@ -57,6 +65,14 @@ def step_counts(n_masked: int, T: int, kind: str = "linear") -> List[int]:
         out.append(r)
         done += r
     return out
+
+
+def tau_schedule(t: int, T: int, tau_max: float, tau_min: float) -> float:
+    """Inference temperature of refinement step t in 1..T:
+    tau_max w(t) + tau_min (1 - w(t)), w(t) = (1 + cos(pi (t - 1) / (T - 1))) / 2,
+    with w = 1 when T = 1 (the first step is also the last)."""
+    w = 1.0 if T == 1 else 0.5 * (1.0 + math.cos(math.pi * (t - 1) / (T - 1)))
+    return tau_max * w + tau_min * (1.0 - w)
 
 
 def margins(logits: np.ndarray) -> np.ndarray:

@@ -223,3 +223,78 @@ def test_remask_step_counts_by_hand():
     assert res.rounds == 2 and len(res.finals) == 3
     assert [len(s["selected"]) for s in res.steps] == [12] * 8 + [12, 13, 13, 13, 13] * 2
     assert list(res.row_valid) == [1, 0, 0]
+
+
+def test_tau_schedule_endpoints_and_monotone():
+    """Cosine temperature annealing (Appendix, inference temperature): tau_max
+    at the first step, tau_min at the last, their mean half way, monotone."""
+    from oracle.schedule import tau_schedule
+    T = 9
+    taus = [tau_schedule(t, T, 2.0, 0.5) for t in range(1, T + 1)]
+    assert taus[0] == 2.0 and abs(taus[-1] - 0.5) < 1e-15
+    assert abs(taus[(T - 1) // 2] - 1.25) < 1e-15        # w = 1/2 at t = (T + 1) / 2
+    assert all(a >= b for a, b in zip(taus[:-1], taus[1:]))
+    assert tau_schedule(1, 1, 2.0, 0.5) == 2.0
+
+
+@pytest.mark.parametrize("tau", [0.25, 1.0, 4.0])
+def test_max_probability_order_is_margin_order_at_any_temperature(tau):
+    """With two symbols, max_a softmax(L / tau)_a is increasing in |L0 - L1|, so
+    the reveal ranking (by margin) is the paper's confidence ranking at every
+    temperature -- the reason tau_t changes no reveal."""
+    rng = np.random.default_rng(3)
+    L = rng.normal(0, 2, size=(400, 2))
+    z = L / tau
+    p = np.exp(z - z.max(axis=1, keepdims=True))
+    p /= p.sum(axis=1, keepdims=True)
+    conf = p.max(axis=1)
+    margin = np.abs(L[:, 0] - L[:, 1])
+    assert np.array_equal(np.argsort(-conf, kind="stable"), np.argsort(-margin, kind="stable"))
+
+
+def _verbatim_den(K, n):
+    # fixed logits: site (k, l) favours bit (k + l) % 2 with margin 1 + ((7 k + 3 l) % 11) / 10
+    lg = np.zeros((K, n, 2))
+    for k in range(K):
+        for l in range(n):
+            m = 1.0 + ((7 * k + 3 * l) % 11) / 10.0
+            lg[k, l, (k + l) % 2] = m
+    return lambda X, gamma: lg, lg
+
+
+class _TinyCode:
+    """A 3 x 6 parity-check matrix; only the final pass's syndrome reads it."""
+    n, m = 6, 3
+    H = np.array([[1, 1, 0, 1, 0, 0], [0, 1, 1, 0, 1, 0], [1, 0, 1, 0, 0, 1]], dtype=np.uint8)
+
+
+@pytest.mark.parametrize("kind,counts", [("linear", [6, 0, 3, 3, 3, 3]), ("cosine", [6, 1, 1, 5, 3, 2])])
+def test_verbatim_first_reveal_counts_by_hand(kind, counts):
+    """first_reveal = 2 (the paper's wording): step 1 reveals each slot's most
+    confident site, then the cumulative targets resume.  K = 3, n = 6, T = 6,
+    N = 18: linear targets 3, 6, 9, 12, 15, 18 give 6, max(0, 6-6)=0, 3, 3, 3, 3;
+    cosine targets floor(rho(t) 18) in float64 = 1, 4, 8, 13, 16, 18 (rho(3) 18
+    evaluates to 8.999999999999998, the rounding the paper's figures pin)
+    give 6, max(1, 4-6)=1, 8-7=1, 5, 3 and the remaining 2."""
+    den, lg = _verbatim_den(3, 6)
+    res = decode_grid(3, 6, _TinyCode(), den, T=6, opts=DecodeOpts(schedule=kind, first_reveal=2), keep=True)
+    assert [len(s["selected"]) for s in res.steps] == counts
+    first = res.steps[0]["selected"]
+    assert sorted(l for _, l in first) == list(range(6))          # one site per slot
+    c = np.abs(lg[..., 0] - lg[..., 1])
+    for k, l in first:
+        assert k == int(np.argmax(c[:, l]))                       # its most confident row
+    hybrid = decode_grid(3, 6, _TinyCode(), den, T=6, opts=DecodeOpts(schedule=kind, first_reveal=1), keep=True)
+    assert len(hybrid.steps[0]["selected"]) == (3 if kind == "linear" else 1)
+
+
+def test_remask_confidence_at_tau_min():
+    """q_k = mean_l max_a softmax(L / tau_min): sigmoid(|L0 - L1| / tau_min)."""
+    code = synth.regular_ldpc(32, seed=1032)
+    X = np.zeros((1, 32), np.uint8)                                # all-zero word: zero syndrome
+    fin = np.zeros((1, 32, 2))
+    fin[0, :16, 0] = 2.0                                           # margins 2 on half the slots, 0 on the rest
+    for tau in (1.0, 0.5, 2.0):
+        _, q, _ = row_status(X, fin, code, 0.9, tau)
+        want = 0.5 * (1 / (1 + math.exp(-2.0 / tau)) + 0.5)
+        assert abs(q[0] - want) < 1e-15
