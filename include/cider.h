@@ -85,8 +85,14 @@ typedef struct {
 typedef struct {
   int32_t precision;          /* cider_precision                       [BF16]   */
   int32_t schedule;           /* cider_schedule                        [LINEAR] */
-  int32_t first_reveal;       /* 1: step 1 of the initial pass only reveals    */
-                              /*    each slot's most confident row       [1]   */
+  int32_t first_reveal;       /* step 1 of the initial pass (first-reveal      */
+                              /* stabilisation, inference appendix):           */
+                              /*  1: candidates narrowed to each slot's most   */
+                              /*     confident masked row, count from the      */
+                              /*     schedule (hybrid)                   [1]   */
+                              /*  2: every slot's selected site is revealed    */
+                              /*     (verbatim); the schedule resumes after    */
+                              /*  0: off                                       */
   int32_t remask;             /* 1: quality-guided remasking on          [0]   */
   int32_t remask_max_rounds;  /* rounds of remasking                     [2]   */
   int32_t final_argmax;       /* 1: output argmax of the last final pass       */
@@ -98,6 +104,12 @@ typedef struct {
   float   eta;                /* Module B bias gain                     [1.0]  */
   float   lam_max;            /* LLR clip and revealed-site LLR         [20]   */
   float   lam_min;            /* |LLR| floor inside phi                 [1e-6] */
+  float   tau_max;            /* inference temperature, cosine-annealed from   */
+  float   tau_min;            /* tau_max (step 1) to tau_min (step T), per the */
+                              /* inference appendix [1, 1].  With two symbols  */
+                              /* the temperature does not change the reveal    */
+                              /* ranking; tau_min sets the final pass's        */
+                              /* confidence in the remask test                 */
   int32_t autotune;           /* 1: before the first decode of a new batch     */
                               /*    size, time every GEMM tile shape on it and */
                               /*    keep the fastest (results do not depend on */

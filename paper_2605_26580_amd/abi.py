@@ -46,6 +46,7 @@ class cider_opts(C.Structure):
                 ("remask", C.c_int32), ("remask_max_rounds", C.c_int32), ("final_argmax", C.c_int32),
                 ("use_graph", C.c_int32), ("remask_thr", C.c_float), ("tau", C.c_float),
                 ("eta", C.c_float), ("lam_max", C.c_float), ("lam_min", C.c_float),
+                ("tau_max", C.c_float), ("tau_min", C.c_float),
                 ("autotune", C.c_int32), ("profile", C.c_int32), ("fused_blocks", C.c_int32),
                 ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t)]

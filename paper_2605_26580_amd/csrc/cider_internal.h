@@ -74,7 +74,9 @@ struct StepCtx {
   long total_tokens;
   int max_n;                // largest n in the batch
   int schedule, remask, max_rounds, final_argmax;
+  int first_verbatim;       // first-reveal step reveals every slot's selected site
   float remask_thr, tau, eta, lam_max, lam_min;
+  float q_inv_tau;          // 1 / tau_min: temperature of the remask confidence
   float gamma_override;     // >= 0: mask-ratio input for every bin (teacher-forced step)
   int reveal_override;      // >= 0: reveal this many sites instead of the schedule's count
   int first_override;       // first-reveal flag used with reveal_override

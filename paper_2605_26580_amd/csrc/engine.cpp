@@ -607,6 +607,8 @@ int check_opts(const cider_opts& o) {
   if (o.remask_max_rounds < 0 || o.remask_max_rounds > 16) return fail(CIDER_EINVAL, "remask_max_rounds 0..16");
   if (!(o.tau > 0.f) || !(o.lam_max > 0.f) || !(o.lam_min > 0.f) || !(o.eta >= 0.f))
     return fail(CIDER_EINVAL, "tau, lam_max, lam_min must be > 0 and eta >= 0");
+  if (o.first_reveal < 0 || o.first_reveal > 2) return fail(CIDER_EINVAL, "first_reveal must be 0, 1 or 2");
+  if (!(o.tau_max > 0.f) || !(o.tau_min > 0.f)) return fail(CIDER_EINVAL, "tau_max and tau_min must be > 0");
   return CIDER_OK;
 }
 
@@ -710,6 +712,8 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
   c.max_rounds = o.remask_max_rounds;
   c.final_argmax = o.final_argmax;
   c.remask_thr = o.remask_thr;
+  c.first_verbatim = o.first_reveal == 2;
+  c.q_inv_tau = 1.0f / o.tau_min;
   c.tau = o.tau;
   c.eta = o.eta;
   c.lam_max = o.lam_max;
@@ -807,6 +811,8 @@ void cider_opts_default(cider_opts* o) {
   o->eta = 1.0f;
   o->lam_max = 20.0f;
   o->lam_min = 1e-6f;
+  o->tau_max = 1.0f;
+  o->tau_min = 1.0f;
   o->autotune = 1;
   o->profile = 0;
   o->fused_blocks = 1;

@@ -333,14 +333,16 @@ hipError_t launch_module_b(const StepCtx& c, const Work& w, hipStream_t s) {
 // Step tail, one workgroup of 1024 threads per bin.
 //
 // Reveal phase: candidates are the masked sites (or, on the first step of a
-// pass with first-reveal, each slot's best masked row, ties to the smaller k).
+// pass with first-reveal, each slot's best masked row, ties to the smaller k;
+// the verbatim mode reveals all of those, the hybrid mode r of them).
 // Each candidate gets the 64-bit key (bits of |L0 - L1|) << 32 | ~(k n + l),
 // which orders by margin and then by smaller flat index; a most-significant-
 // digit radix select finds the r-th largest key and every candidate at or
 // above it takes its argmax symbol (ties to bit 0).
 //
 // Final phase: per row, syndrome H x and q = mean over slots of the max
-// probability sigmoid(|L0 - L1|); rows with nonzero syndrome or q < thr are
+// probability sigmoid(|L0 - L1| / tau_min) (the annealed inference
+// temperature's end value); rows with nonzero syndrome or q < thr are
 // remasked for T_rm steps while rounds remain, otherwise the bin is done and
 // its outputs are written.
 constexpr int kTailThreads = 1024;
@@ -422,7 +424,9 @@ __global__ __launch_bounds__(kTailThreads) void k_step_tail(StepCtx c, const flo
     if (mine) atomicAdd(&s_cnt, mine);
     __syncthreads();
     const int ncand = s_cnt;
-    const int take = min(r, ncand);
+    // verbatim first-reveal: every slot's selected site; the schedule's
+    // cumulative targets take over from the next step
+    const int take = (first && c.first_verbatim && c.reveal_override < 0) ? ncand : min(r, ncand);
     unsigned long long thr = ~0ull;  // select nothing
     if (take > 0 && take == ncand) {
       thr = 1ull;  // every candidate
@@ -502,7 +506,7 @@ __global__ __launch_bounds__(kTailThreads) void k_step_tail(StepCtx c, const flo
     for (int l = lane; l < n; l += 64) {
       int site = wave * n + l;
       float mg = fabsf(lg[2 * site] - lg[2 * site + 1]);
-      acc += 1.0f / (1.0f + expf(-mg));
+      acc += 1.0f / (1.0f + expf(-mg * c.q_inv_tau));
     }
     acc = wave_sum(acc);
     if (lane == 0) s_q[wave] = acc / (float)n;

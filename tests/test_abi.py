@@ -33,6 +33,7 @@ def test_opts_defaults():
     assert o.precision == P.CIDER_BF16 and o.schedule == P.CIDER_SCHED_LINEAR and o.first_reveal == 1
     assert o.remask == 0 and o.remask_max_rounds == 2 and abs(o.remask_thr - 0.9) < 1e-7
     assert o.tau == 1.0 and o.eta == 1.0 and o.lam_max == 20.0 and abs(o.lam_min - 1e-6) < 1e-12
+    assert o.tau_max == 1.0 and o.tau_min == 1.0 and o.fused_blocks == 1 and o.autotune == 1
 
 
 @pytest.mark.parametrize("L,d,h", [(2, 64, 4), (4, 128, 8), (6, 256, 8), (8, 384, 12)])

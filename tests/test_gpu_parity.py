@@ -134,7 +134,8 @@ def _decode_gpu(wl_K, code, ch, wh, bins, T, opts, with_logits=False):
     return out.cpu().numpy(), (lg.cpu().numpy() if lg is not None else None), valid.cpu().numpy()
 
 
-def _free_running(prec, K, n, L, d, h, T, B, remask=False, schedule="linear", final_argmax=False, min_gap=2e-5):
+def _free_running(prec, K, n, L, d, h, T, B, remask=False, schedule="linear", final_argmax=False, min_gap=2e-5,
+                  first_reveal=1, tau_min=1.0):
     P = lib()
     cfg = synth.ModelCfg(L, d, h, n_max=max(n, 64))
     wh, w = weights_handle(cfg, seed=31 + d, bias_std=0.0)
@@ -143,10 +144,11 @@ def _free_running(prec, K, n, L, d, h, T, B, remask=False, schedule="linear", fi
     bins = synth.make_bins(code, K, B, [2.0, 4.0, 6.0], seed=77 + K + n)
     sched = P.CIDER_SCHED_COSINE if schedule == "cosine" else P.CIDER_SCHED_LINEAR
     opts = P.cider_opts_default(precision=prec_id(prec), remask=int(remask), schedule=sched,
-                                final_argmax=int(final_argmax))
+                                final_argmax=int(final_argmax), first_reveal=first_reveal, tau_min=tau_min)
     say(f"free-running {prec} K={K} n={n} L={L} d={d} T={T} B={B} remask={remask} sched={schedule}")
     Xg, lg, valid = _decode_gpu(K, code, ch, wh, bins, T, opts, with_logits=True)
-    oo = DecodeOpts(remask=remask, schedule=schedule, final_argmax=final_argmax)
+    oo = DecodeOpts(remask=remask, schedule=schedule, final_argmax=final_argmax, first_reveal=first_reveal,
+                    tau_min=tau_min)
     safe = match = 0
     for b in range(B):
         res = decode_bin(bins.y[b], float(bins.sigma2[b]), code, K, w, L, h, T, oo)
@@ -188,6 +190,21 @@ def test_free_running_fp32_cosine_final_argmax():
     match, safe, B = _free_running("fp32", 2, 32, 2, 64, 4, 12, 8, schedule="cosine", final_argmax=True)
     # the cosine schedule reveals one site at step 1, so more cut gaps are near ties
     assert safe >= 2 and match >= B // 2
+
+
+@pytest.mark.parametrize("schedule", ["linear", "cosine"])
+def test_free_running_fp32_verbatim_first_reveal(schedule):
+    """first_reveal = 2: step 1 reveals each slot's best site, then the
+    schedule's targets resume; decidable bins match the oracle bit for bit."""
+    m, safe, B = _free_running("fp32", 3, 64, 2, 64, 4, 8, 8, schedule=schedule, first_reveal=2)
+    assert safe >= 1
+
+
+def test_free_running_fp32_remask_at_tau_min():
+    """Remask confidence at the annealed end temperature tau_min = 0.5 (sharper
+    probabilities: fewer rows fall under the 0.9 threshold than at tau = 1)."""
+    m, safe, B = _free_running("fp32", 4, 64, 2, 64, 4, 8, 8, remask=True, tau_min=0.5)
+    assert safe >= 1
 
 
 def test_free_running_bf16_reports_match():
@@ -270,6 +287,10 @@ def test_invalid_arguments_rejected_before_launch():
         args.update(kw)
         with pytest.raises(P.CiderError) as ei:
             P.cider_decode(y, args["sigma2"], ch, args["K"], args["n"], wh, args["steps"], out)
+        assert ei.value.status == P.abi.CIDER_EINVAL
+    for kw in [dict(first_reveal=3), dict(first_reveal=-1), dict(tau_min=0.0), dict(tau_max=-1.0)]:
+        with pytest.raises(P.CiderError) as ei:
+            P.cider_decode(y, 1.0, ch, 2, 32, wh, 8, out, P.cider_opts_default(**kw))
         assert ei.value.status == P.abi.CIDER_EINVAL
 
 
