@@ -39,7 +39,9 @@ typedef float f32x16 __attribute__((__vector_size__(16 * sizeof(float))));
 constexpr int kM3BM = 256;                        // tokens per workgroup
 constexpr int kM3FCH = 32;                        // hidden units per chunk
 
-template <int D>
+constexpr int kM3MaxF = 2048;                     // hidden width the b1 staging holds
+
+template <int D, int NBUF = 2>
 struct M3Smem {
   static constexpr int RB1 = D * 2 + 16;          // bytes per stored W1 chunk row (16 of them pad)
   static constexpr int RB2 = kM3FCH * 2 + 16;     // bytes per stored W2 chunk row
@@ -47,10 +49,40 @@ struct M3Smem {
   static constexpr size_t w2 = (size_t)D * RB2;
   static constexpr size_t w1a = (w1 + 1023) / 1024 * 1024;   // whole DMA blocks
   static constexpr size_t w2a = (w2 + 1023) / 1024 * 1024;
-  static constexpr size_t buf = w1a + w2a + 256;  // + the chunk's b1
-  static constexpr size_t bytes = 2 * buf;
+  static constexpr size_t buf = w1a + w2a;
+  static constexpr size_t vec = (size_t)5 * D * 4;           // epilogue vectors
+  static constexpr size_t bytes = NBUF * buf + kM3MaxF * 4 + vec;   // + all of b1
   static_assert(bytes <= 160 * 1024, "LDS");
 };
+
+// Waits until at most n of this wave's vector-memory operations (here: LDS
+// DMA blocks of later weight chunks) are outstanding, then joins the
+// workgroup barrier.  The count is an instruction immediate, so the
+// uniform n selects one of a few fixed forms.
+template <int N>
+__device__ __forceinline__ void m3_wait_barrier_n() {
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+__device__ __forceinline__ void m3_wait_barrier(int n) {
+  switch (n) {
+    case 0: m3_wait_barrier_n<0>(); break;
+    case 1: m3_wait_barrier_n<1>(); break;
+    case 2: m3_wait_barrier_n<2>(); break;
+    case 3: m3_wait_barrier_n<3>(); break;
+    case 4: m3_wait_barrier_n<4>(); break;
+    case 5: m3_wait_barrier_n<5>(); break;
+    case 6: m3_wait_barrier_n<6>(); break;
+    case 7: m3_wait_barrier_n<7>(); break;
+    case 8: m3_wait_barrier_n<8>(); break;
+    case 9: m3_wait_barrier_n<9>(); break;
+    case 10: m3_wait_barrier_n<10>(); break;
+    case 11: m3_wait_barrier_n<11>(); break;
+    case 12: m3_wait_barrier_n<12>(); break;
+    default: m3_wait_barrier_n<0>(); break;
+  }
+}
 
 // Row j of the stored W1 chunk holds hidden unit sigma(j) of the chunk.
 __device__ __forceinline__ int m3_sigma(int j) {
@@ -58,37 +90,77 @@ __device__ __forceinline__ int m3_sigma(int j) {
   return 16 * (q >> 1) + 8 * g + 4 * (q & 1) + i;
 }
 
+// Per-feature vectors of the residual epilogue, staged in LDS at kernel
+// start: bias [D], LayerNorm gain [D] and bias [D], and with the final
+// projection its two rows [2][D].  Reading them from LDS keeps the
+// epilogue's global traffic to the residual rows, whose loads can then all
+// be issued ahead of the stores (nothing the stores write can alias them).
+template <int D>
+__device__ __forceinline__ void m3_stage_vectors(float* sv, const GemmArgs& g, bool proj, int tid, int nthr) {
+  for (int i = tid; i < D; i += nthr) {
+    sv[i] = g.bias[i];
+    sv[D + i] = g.ln_g[i];
+    sv[2 * D + i] = g.ln_b[i];
+    if (proj) {
+      sv[3 * D + i] = g.proj_w[i];
+      sv[4 * D + i] = g.proj_w[D + i];
+    }
+  }
+}
+
 // Residual epilogue shared by the token-resident kernels: acc2[b][t] holds,
 // for token tok0 + 32 t, output rows 32 b + 8 q + 4 g2 + i in register 4q + i
 // (the two lanes l and l + 32 together hold the row).  R += acc2 + bias, then
 // the next LayerNorm into g.out (BF16) or, with PROJ, the final LayerNorm and
-// the 2-way projection into g.proj_out.
+// the 2-way projection into g.proj_out.  sv: the staged vectors.  Residual
+// rows are loaded in batches of up to four output blocks, all loads of a
+// batch issued before its stores.
 template <int D, int TB, bool PROJ>
 __device__ __forceinline__ void m3_residual_epilogue(f32x16 (&acc2)[D / 32][TB], long tok0, const GemmArgs& g,
-                                                     int g2) {
+                                                     int g2, const float* sv) {
   constexpr int OBK = D / 32;
+  constexpr int HB = OBK > 4 ? 4 : OBK;
+  const float* sbias = sv;
+  const float* slg = sv + D;
+  const float* slb = sv + 2 * D;
 #pragma unroll
   for (int t = 0; t < TB; ++t) {
     const long tok = tok0 + 32 * t;
     const bool tv = tok < g.M;
-    float* __restrict__ Rrow = g.R + (tv ? tok : 0) * D;
+    float* Rrow = g.R + (tv ? tok : 0) * D;
     float sum = 0.f;
 #pragma unroll
-    for (int b = 0; b < OBK; ++b)
+    for (int b0 = 0; b0 < OBK; b0 += HB) {
+      f32x4 rr[HB][4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int f = 32 * b + 8 * q + 4 * g2;
-        const f32x4 bias = f32x4{g.bias[f], g.bias[f + 1], g.bias[f + 2], g.bias[f + 3]};
-        const f32x4 rr = tv ? *(const f32x4*)(Rrow + f) : f32x4{0.f, 0.f, 0.f, 0.f};
-        f32x4 res;
+      for (int bb = 0; bb < HB; ++bb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          res[i] = rr[i] + (acc2[b][t][4 * q + i] + bias[i]);
-          acc2[b][t][4 * q + i] = res[i];
+        for (int q = 0; q < 4; ++q)
+          rr[bb][q] = tv ? *(const f32x4*)(Rrow + 32 * (b0 + bb) + 8 * q + 4 * g2) : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int bb = 0; bb < HB; ++bb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int f = 32 * (b0 + bb) + 8 * q + 4 * g2;
+          const f32x4 bias = *(const f32x4*)&sbias[f];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float res = rr[bb][q][i] + (acc2[b0 + bb][t][4 * q + i] + bias[i]);
+            acc2[b0 + bb][t][4 * q + i] = res;
+            sum += res;
+          }
         }
-        if (tv) *(f32x4*)(Rrow + f) = res;
-        sum += (res[0] + res[1]) + (res[2] + res[3]);
+      if (tv) {
+#pragma unroll
+        for (int bb = 0; bb < HB; ++bb)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int f = 32 * (b0 + bb) + 8 * q + 4 * g2;
+            *(f32x4*)(Rrow + f) = f32x4{acc2[b0 + bb][t][4 * q], acc2[b0 + bb][t][4 * q + 1],
+                                        acc2[b0 + bb][t][4 * q + 2], acc2[b0 + bb][t][4 * q + 3]};
+          }
       }
+    }
     sum += __shfl_xor(sum, 32, 64);
     const float mean = sum / (float)D;
     float qv = 0.f;
@@ -109,25 +181,32 @@ __device__ __forceinline__ void m3_residual_epilogue(f32x16 (&acc2)[D / 32][TB],
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int f = 32 * b + 8 * q + 4 * g2;
+            const f32x4 lg = *(const f32x4*)&slg[f];
+            const f32x4 lb = *(const f32x4*)&slb[f];
             bf16x4 h;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-              h[i] = (bf16)((acc2[b][t][4 * q + i] - mean) * rstd * g.ln_g[f + i] + g.ln_b[f + i]);
+            for (int i = 0; i < 4; ++i) h[i] = (bf16)((acc2[b][t][4 * q + i] - mean) * rstd * lg[i] + lb[i]);
             *(bf16x4*)(xo + f) = h;
           }
       }
     } else {
+      const float* sp0 = sv + 3 * D;
+      const float* sp1 = sv + 4 * D;
       float a0 = 0.f, a1 = 0.f;
 #pragma unroll
       for (int b = 0; b < OBK; ++b)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int f = 32 * b + 8 * q + 4 * g2;
+          const f32x4 lg = *(const f32x4*)&slg[f];
+          const f32x4 lb = *(const f32x4*)&slb[f];
+          const f32x4 w0 = *(const f32x4*)&sp0[f];
+          const f32x4 w1 = *(const f32x4*)&sp1[f];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const float hv = (acc2[b][t][4 * q + i] - mean) * rstd * g.ln_g[f + i] + g.ln_b[f + i];
-            a0 = fmaf(hv, g.proj_w[f + i], a0);
-            a1 = fmaf(hv, g.proj_w[D + f + i], a1);
+            const float hv = (acc2[b][t][4 * q + i] - mean) * rstd * lg[i] + lb[i];
+            a0 = fmaf(hv, w0[i], a0);
+            a1 = fmaf(hv, w1[i], a1);
           }
         }
       a0 += __shfl_xor(a0, 32, 64);
@@ -140,11 +219,11 @@ __device__ __forceinline__ void m3_residual_epilogue(f32x16 (&acc2)[D / 32][TB],
   }
 }
 
-template <int D, int TB, int NW, int WPE, bool PROJ>
+template <int D, int TB, int NW, int WPE, int NBUF, bool PROJ>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void k_mlp3(GemmArgs g, const bf16* __restrict__ W1, const float* __restrict__ b1, const bf16* __restrict__ W2,
             int F) {
-  using S = M3Smem<D>;
+  using S = M3Smem<D, NBUF>;
   static_assert(NW * TB * 32 == kM3BM, "256 tokens per workgroup");
   constexpr int NTHR = NW * 64;
   constexpr int RB1 = S::RB1, RB2 = S::RB2;
@@ -157,11 +236,14 @@ void k_mlp3(GemmArgs g, const bf16* __restrict__ W1, const float* __restrict__ b
   const long tok0 = (long)blockIdx.x * kM3BM + wave * (32 * TB) + l32;   // token of block t: tok0 + 32 t
   const int nch = F / kM3FCH;
   const bf16* __restrict__ A = (const bf16*)g.A;
+  float* sb1 = (float*)(smem + NBUF * S::buf);
+  float* sv = sb1 + kM3MaxF;
+  // DMA blocks this wave issues per chunk (uniform over the wave)
+  const int nw = (N1 + N2) / NW + (wave < (N1 + N2) % NW ? 1 : 0);
 
-  // ---- weight chunk c -> LDS buffer: 1 KB DMA blocks spread over the waves;
-  // lane i of block u writes bytes [1024 u + 16 i, + 16) of its region.  The
-  // chunk's b1 goes through a register, loaded one chunk ahead.
-  float pb = 0.f;
+  // ---- weight chunk c -> LDS buffer c % NBUF: 1 KB DMA blocks spread over
+  // the waves; lane i of block u writes bytes [1024 u + 16 i, + 16) of its
+  // region.  NBUF - 1 chunks are in flight ahead of the one being used.
   auto dma = [&](int c, int buf) {
     const int c0 = c * kM3FCH;
     char* base = smem + buf * S::buf;
@@ -182,12 +264,8 @@ void k_mlp3(GemmArgs g, const bf16* __restrict__ W1, const float* __restrict__ b
         __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
     }
   };
-  auto bias_fetch = [&](int c) {
-    if (tid < kM3FCH) pb = b1[c * kM3FCH + tid];
-  };
-  auto bias_stash = [&](int buf) {
-    if (tid < kM3FCH) ((float*)(smem + buf * S::buf + S::w1a + S::w2a))[tid] = pb;
-  };
+  for (int i = tid; i < F; i += NTHR) sb1[i] = b1[i];
+  m3_stage_vectors<D>(sv, g, PROJ, tid, NTHR);
 
   // ---- this wave's XN rows, resident for the whole kernel
   bf16x8 xf[TB][KS1];
@@ -207,22 +285,16 @@ void k_mlp3(GemmArgs g, const bf16* __restrict__ W1, const float* __restrict__ b
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc2[b][t][r] = 0.f;
 
-  bias_fetch(0);
-  dma(0, 0);
-  bias_stash(0);
-  if (nch > 1) bias_fetch(1);
-  __syncthreads();                                // waits for this wave's DMA, then publishes
+  const int pre = min(NBUF - 1, nch);            // chunks in flight before the loop
+  for (int c = 0; c < pre; ++c) dma(c, c);
+  __syncthreads();                                // b1 staged, and this wave's DMA of chunks < pre done
   for (int c = 0; c < nch; ++c) {
-    const int buf = c & 1;
-    // the other buffer's last readers finished before the previous barrier
-    if (c + 1 < nch) {
-      dma(c + 1, buf ^ 1);
-      bias_stash(buf ^ 1);
-      if (c + 2 < nch) bias_fetch(c + 2);
-    }
+    const int buf = c % NBUF;
+    // buffer (c + NBUF - 1) % NBUF was last read in iteration c - 1, before its closing barrier
+    if (c + NBUF - 1 < nch) dma(c + NBUF - 1, (c + NBUF - 1) % NBUF);
     const char* s1 = smem + buf * S::buf;
     const char* s2 = smem + buf * S::buf + S::w1a;
-    const float* sb = (const float*)(smem + buf * S::buf + S::w1a + S::w2a);
+    const float* sb = sb1 + c * kM3FCH;
     // up: acc1[t][r] = sum_k W1[c0 + sigma(8(r/4) + 4 g2 + r%4)][k] XN[token][k]
     f32x16 acc1[TB];
 #pragma unroll
@@ -255,17 +327,19 @@ void k_mlp3(GemmArgs g, const bf16* __restrict__ W1, const float* __restrict__ b
         for (int t = 0; t < TB; ++t)
           acc2[b][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, hf[t][s], acc2[b][t], 0, 0, 0);
       }
-    __syncthreads();                              // DMA of chunk c + 1 complete and visible
+    // chunk c + 1 complete in every wave: this wave may still have the DMA
+    // of the chunks after it (at most NBUF - 2) outstanding
+    if (c + 1 < nch) m3_wait_barrier(nw * (min(c + NBUF - 1, nch - 1) - (c + 1)));
   }
 
-  m3_residual_epilogue<D, TB, PROJ>(acc2, tok0, g, g2);
+  m3_residual_epilogue<D, TB, PROJ>(acc2, tok0, g, g2, sv);
 }
 
-template <int D, int TB, int NW, int WPE>
+template <int D, int TB, int NW, int WPE, int NBUF>
 hipError_t mlp3_t(const GemmArgs& g, const bf16* W1, const float* b1, const bf16* W2, int F, hipStream_t s) {
   dim3 grid((unsigned)((g.M + kM3BM - 1) / kM3BM)), block(NW * 64);
-  if (g.proj_out) hipLaunchKernelGGL((k_mlp3<D, TB, NW, WPE, true>), grid, block, 0, s, g, W1, b1, W2, F);
-  else hipLaunchKernelGGL((k_mlp3<D, TB, NW, WPE, false>), grid, block, 0, s, g, W1, b1, W2, F);
+  if (g.proj_out) hipLaunchKernelGGL((k_mlp3<D, TB, NW, WPE, NBUF, true>), grid, block, 0, s, g, W1, b1, W2, F);
+  else hipLaunchKernelGGL((k_mlp3<D, TB, NW, WPE, NBUF, false>), grid, block, 0, s, g, W1, b1, W2, F);
   return hipGetLastError();
 }
 
@@ -375,7 +449,8 @@ void k_oproj3(GemmArgs g, const bf16* __restrict__ W) {
   constexpr int NW = 8, RB2 = S::RB2, OBK = D / 32, NCH = D / 32;
   constexpr int NB = (int)(S::w2a / 1024), NPW = (NB + NW - 1) / NW;
   constexpr size_t BUF = S::w2a;
-  __shared__ __attribute__((aligned(1024))) char smem[2 * BUF];
+  __shared__ __attribute__((aligned(1024))) char smem[2 * BUF + 3 * D * 4];
+  float* sv = (float*)(smem + 2 * BUF);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
   const long tok0 = (long)blockIdx.x * kM3BM + wave * 32 + l32;
   const bool tv = tok0 < g.M;
@@ -406,6 +481,7 @@ void k_oproj3(GemmArgs g, const bf16* __restrict__ W) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc2[b][0][r] = 0.f;
   bf16x8 fa[2], fn[2];
+  m3_stage_vectors<D>(sv, g, false, tid, 512);
   afrag(0, fa);
   dma(0, 0);
   __syncthreads();
@@ -428,7 +504,7 @@ void k_oproj3(GemmArgs g, const bf16* __restrict__ W) {
     fa[1] = fn[1];
     __syncthreads();
   }
-  m3_residual_epilogue<D, 1, false>(acc2, tok0, g, g2);
+  m3_residual_epilogue<D, 1, false>(acc2, tok0, g, g2, sv);
 }
 
 }  // namespace
@@ -455,15 +531,15 @@ hipError_t launch_oproj3_bf16(const GemmArgs& g, const Mat& W, hipStream_t s) {
 
 bool proj3_ok(int d) { return d == 128 || d == 256; }
 
-bool mlp3_ok(int d, int F) { return (d == 128 || d == 256) && F % kM3FCH == 0 && F >= kM3FCH; }
+bool mlp3_ok(int d, int F) { return (d == 128 || d == 256) && F % kM3FCH == 0 && F >= kM3FCH && F <= kM3MaxF; }
 
 // R += W2 GELU(W1 XN + b1) + b2 with the next LayerNorm into g.out (g.ln_g set)
 // or the final LayerNorm and projection into g.proj_out (g.proj_w set).
 hipError_t launch_mlp3_bf16(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s) {
   if (g.M == 0) return hipSuccess;
   if (!mlp3_ok(g.N, F) || !g.ln_g || g.out_scale) return hipErrorInvalidValue;
-  if (g.N == 128) return mlp3_t<128, 1, 8, 2>(g, W1.b16, b1, W2.b16, F, s);
-  return mlp3_t<256, 1, 8, 2>(g, W1.b16, b1, W2.b16, F, s);
+  if (g.N == 128) return mlp3_t<128, 1, 8, 2, 4>(g, W1.b16, b1, W2.b16, F, s);
+  return mlp3_t<256, 1, 8, 2, 3>(g, W1.b16, b1, W2.b16, F, s);
 }
 
 }  // namespace cider
