@@ -1078,26 +1078,30 @@ __global__ __launch_bounds__(256) void k_row_attn_mfma(StepCtx c, const bf16* __
         }
         st[t] = a;
       }
+      // raw scores; keys past n (only in the last block) get -inf
+      if (j0 + AKB > n) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr)
+            if (j0 + t * 16 + (lane >> 4) * 4 + rr >= n) st[t][rr] = -INFINITY;
+      }
       float bmax = -INFINITY;
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          const int key = j0 + t * 16 + (lane >> 4) * 4 + rr;
-          const float sv = key < n ? st[t][rr] * scale : -INFINITY;
-          st[t][rr] = sv;
-          bmax = fmaxf(bmax, sv);
-        }
+        for (int rr = 0; rr < 4; ++rr) bmax = fmaxf(bmax, st[t][rr]);
       bmax = fmaxf(bmax, __shfl_xor(bmax, 16, 64));
       bmax = fmaxf(bmax, __shfl_xor(bmax, 32, 64));
-      const float mnew = fmaxf(mrun, bmax);
-      const float corr = exp2f(mrun - mnew);
+      // running max kept in scaled units: p = 2^(scale s - m), one FMA and one v_exp_f32
+      const float mnew = fmaxf(mrun, bmax * scale);
+      const float corr = __builtin_amdgcn_exp2f(mrun - mnew);
       float psum = 0.f;
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-          const float pv = exp2f(st[t][rr] - mnew);
+          const float pv = __builtin_amdgcn_exp2f(fmaf(st[t][rr], scale, -mnew));
           st[t][rr] = pv;
           psum += pv;
         }
