@@ -182,7 +182,7 @@ hipError_t launch_gemm_fp8(const GemmArgs& g, const Mat& W, hipStream_t s);
 hipError_t launch_mlp_fp8(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s);
 hipError_t launch_row_attn_mfma(const StepCtx& c, const void* QKV, void* O, int d, int heads, int max_n,
                                 hipStream_t s);
-hipError_t launch_user_attn_bf16(const StepCtx& c, const void* QKV, void* O, int d, int heads, hipStream_t s);
+hipError_t launch_user_attn_mfma(const StepCtx& c, const void* QKV, void* O, int d, int heads, hipStream_t s);
 size_t row_attn_mfma_lds(int max_n, int dh);
 hipError_t launch_row_attn(const StepCtx& c, int prec, const void* QKV, void* O, int d, int heads,
                            int max_n, hipStream_t s);

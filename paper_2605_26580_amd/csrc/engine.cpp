@@ -442,7 +442,7 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
       g.N = 3 * d; g.Kd = d; g.A = k.XN; g.bias = L.bqkv_u; g.out = k.QKV;
       TIMED("gemm_qkv_user", qkv(g, L.Wqkv_u));
       if (prec == kF32) TIMED("attn_user", launch_user_attn(c, prec, k.QKV, k.O, d, m.heads, s));
-      else TIMED("attn_user", launch_user_attn_bf16(c, k.QKV, k.O, d, m.heads, s));
+      else TIMED("attn_user", launch_user_attn_mfma(c, k.QKV, k.O, d, m.heads, s));
       g = GemmArgs{}; g.M = T;
       g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_u; g.R = k.R;
       next_ln(g, L.ln3_g, L.ln3_b);

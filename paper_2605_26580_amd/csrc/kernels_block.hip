@@ -402,7 +402,118 @@ hipError_t blk_dispatch(const StepCtx& c, int grid, int d, int dh, bf16* XN, con
   return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------------------
+// Attention across the K rows of a slot, from a QKV buffer (the unfused
+// path: d = 256 / 384, FP8).  One wave per 16-slot tile of floor(16/K)
+// columns x K rows (the fused user block's tiling, groups of four tiles from
+// the same (bin, first column) table).  Per head: S^T = K Q^T is one MFMA
+// with Q and K fragments read straight from QKV, keys off the query's column
+// are masked, the exp2 softmax runs over the lane's four keys and its three
+// partner lanes, and O^T = V^T P^T is one 16x16x16 MFMA per 16 features with
+// V^T staged in LDS (d x 16 values, this wave's only LDS).
+template <int DH>
+__global__ __launch_bounds__(64) void k_user_attn_mfma(StepCtx c, const bf16* __restrict__ QKV, bf16* __restrict__ O,
+                                                       int d, int heads) {
+  constexpr int QE = DH == 16 ? 4 : 8;           // k elements per lane of a QK^T MFMA
+  constexpr int QS = DH == 64 ? 2 : 1;           // QK^T k-steps
+  constexpr int DT = DH / 16;
+  constexpr int LDV = 16 + 8;
+  typedef __bf16 qv_t __attribute__((__vector_size__(QE * sizeof(__bf16))));
+  extern __shared__ __attribute__((aligned(16))) char smem_ua[];
+  bf16* sVt = (bf16*)smem_ua;                     // [d][LDV]
+  const int gi = blockIdx.x >> 2, sub = blockIdx.x & 3;
+  const DevBin& b = c.bins[c.ugrp[2 * gi]];
+  if (b.st->phase == kDone) return;
+  const int K = b.K, n = b.n, cpt = 16 / K;
+  const int col0 = c.ugrp[2 * gi + 1] + sub * cpt;
+  if (col0 >= n) return;                          // whole wave
+  const int lane = threadIdx.x, g4 = lane >> 4, l16 = lane & 15;
+  const long ld = 3L * d;
+  auto slot_tok = [&](int j) -> long {
+    const int col = col0 + j / K;
+    return (j < cpt * K && col < n) ? (long)b.tok_off + (long)(j % K) * n + col : -1L;
+  };
+  // V^T of the tile's 16 slots
+  for (int e = lane; e < 16 * (d / 8); e += 64) {
+    const int j = e / (d / 8), c8 = (e - j * (d / 8)) * 8;
+    const long t = slot_tok(j);
+    bf16x8 v = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    if (t >= 0) v = *(const bf16x8*)(QKV + t * ld + 2 * d + c8);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) sVt[(c8 + i) * LDV + j] = v[i];
+  }
+  __syncthreads();
+  const long tq = slot_tok(l16);                  // this lane's query row and key row
+  const bool qv = tq >= 0;
+  float kbias[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int jk = g4 * 4 + r;
+    kbias[r] = (slot_tok(jk) >= 0 && jk / K == l16 / K) ? 0.f : -INFINITY;
+  }
+  const float scale = 1.4426950408889634f / sqrtf((float)DH);
+  const bf16* qrow = QKV + (qv ? tq : 0) * ld;
+  for (int h = 0; h < heads; ++h) {
+    f32x4 a = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < QS; ++s) {
+      qv_t fq, fk;
+      if (qv) {
+        fq = *(const qv_t*)(qrow + h * DH + s * 32 + g4 * QE);
+        fk = *(const qv_t*)(qrow + d + h * DH + s * 32 + g4 * QE);
+      } else {
+#pragma unroll
+        for (int e = 0; e < QE; ++e) fq[e] = fk[e] = (bf16)0.f;
+      }
+      if constexpr (DH == 16) a = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fk, fq, a, 0, 0, 0);
+      else a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fk, fq, a, 0, 0, 0);
+    }
+    // a[r]: score of key slot 4 g4 + r for query slot l16
+    float mx = -INFINITY;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      a[r] += kbias[r];
+      mx = fmaxf(mx, a[r]);
+    }
+    mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+    const float mxs = mx == -INFINITY ? 0.f : -mx * scale;
+    float ps = 0.f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      a[r] = __builtin_amdgcn_exp2f(fmaf(a[r], scale, mxs));
+      ps += a[r];
+    }
+    ps += __shfl_xor(ps, 16, 64);
+    ps += __shfl_xor(ps, 32, 64);
+    const float inv = ps > 0.f ? 1.0f / ps : 0.f;
+    const bf16x4 fp = to_bf16x4(a);
+#pragma unroll
+    for (int t = 0; t < DT; ++t) {
+      const bf16x4 fv = *(const bf16x4*)&sVt[(h * DH + t * 16 + l16) * LDV + g4 * 4];
+      f32x4 oacc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fv, fp, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      // oacc[r]: feature h DH + 16 t + 4 g4 + r of query slot l16
+      if (qv) *(bf16x4*)(O + tq * d + h * DH + t * 16 + g4 * 4) = to_bf16x4(oacc * inv);
+    }
+  }
+}
+
 }  // namespace
+
+// Cross-user attention from QKV into O (BF16): four tiles per (bin, first
+// column) group, one wave each.
+hipError_t launch_user_attn_mfma(const StepCtx& c, const void* QKV, void* O, int d, int heads, hipStream_t s) {
+  if (c.total_ugrp == 0) return hipSuccess;
+  if (heads <= 0 || d % heads || d % 16) return hipErrorInvalidValue;
+  const int dh = d / heads;
+  const size_t lds = (size_t)d * (16 + 8) * sizeof(bf16);
+  dim3 grid((unsigned)(4 * c.total_ugrp)), block(64);
+  if (dh == 16) hipLaunchKernelGGL((k_user_attn_mfma<16>), grid, block, lds, s, c, (const bf16*)QKV, (bf16*)O, d, heads);
+  else if (dh == 32) hipLaunchKernelGGL((k_user_attn_mfma<32>), grid, block, lds, s, c, (const bf16*)QKV, (bf16*)O, d, heads);
+  else if (dh == 64) hipLaunchKernelGGL((k_user_attn_mfma<64>), grid, block, lds, s, c, (const bf16*)QKV, (bf16*)O, d, heads);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
 
 bool attn_block_ok(int d, int heads, int max_n, bool user) {
   if (heads <= 0 || d % heads) return false;

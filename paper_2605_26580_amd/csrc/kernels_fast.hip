@@ -1141,81 +1141,6 @@ __global__ __launch_bounds__(256) void k_row_attn_mfma(StepCtx c, const bf16* __
   }
 }
 
-// Cross-user attention, one wavefront per slot: the slot's K rows of keys and
-// values (K <= 16 tokens, 2d values each) are staged in this wave's LDS
-// region with 16-byte loads, then each lane takes (head, query row) pairs and
-// runs an FP32 softmax over the K keys.
-template <int DH>
-__global__ __launch_bounds__(256) void k_user_attn_wave(StepCtx c, const bf16* __restrict__ QKV,
-                                                        bf16* __restrict__ O, int d, int heads, int kmax) {
-  extern __shared__ __attribute__((aligned(16))) char smem_user[];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const long s = (long)blockIdx.x * 4 + wave;
-  if (s >= c.total_slots) return;
-  const DevBin& b = c.bins[c.slot_bin[s]];
-  if (b.st->phase == kDone) return;
-  const int n = b.n, l = (int)(s - b.slot_off), K = b.K;
-  const long ld = 3L * d;
-  bf16* sKV = (bf16*)smem_user + (size_t)wave * kmax * 2 * d;   // [K][2d]: k | v
-  const int cpr = 2 * d / 8;                                     // 16-byte chunks per token
-  for (int idx = lane; idx < K * cpr; idx += 64) {
-    const int j = idx / cpr, c8 = (idx - j * cpr) * 8;
-    const long tk = (long)b.tok_off + (long)j * n + l;
-    *(bf16x8*)&sKV[j * 2 * d + c8] = *(const bf16x8*)(QKV + tk * ld + d + c8);
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const float scale = 1.0f / sqrtf((float)DH);
-  constexpr int NV = DH / 8;
-  for (int item = lane; item < heads * K; item += 64) {
-    const int h = item / K, kq = item - h * K;
-    const long tq = (long)b.tok_off + (long)kq * n + l;
-    float q[DH];
-#pragma unroll
-    for (int v8 = 0; v8 < NV; ++v8) {
-      const bf16x8 x = *(const bf16x8*)(QKV + tq * ld + h * DH + v8 * 8);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) q[v8 * 8 + e] = (float)x[e] * scale;
-    }
-    float sc[kMaxK];
-    float mx = -INFINITY;
-    for (int j = 0; j < K; ++j) {
-      float a = 0.f;
-#pragma unroll
-      for (int v8 = 0; v8 < NV; ++v8) {
-        const bf16x8 x = *(const bf16x8*)&sKV[j * 2 * d + h * DH + v8 * 8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) a = fmaf(q[v8 * 8 + e], (float)x[e], a);
-      }
-      sc[j] = a;
-      mx = fmaxf(mx, a);
-    }
-    float o[DH];
-#pragma unroll
-    for (int i = 0; i < DH; ++i) o[i] = 0.f;
-    float lsum = 0.f;
-    for (int j = 0; j < K; ++j) {
-      const float pj = expf(sc[j] - mx);
-      lsum += pj;
-#pragma unroll
-      for (int v8 = 0; v8 < NV; ++v8) {
-        const bf16x8 x = *(const bf16x8*)&sKV[j * 2 * d + d + h * DH + v8 * 8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) o[v8 * 8 + e] = fmaf(pj, (float)x[e], o[v8 * 8 + e]);
-      }
-    }
-    const float inv = 1.0f / lsum;
-#pragma unroll
-    for (int v8 = 0; v8 < NV; ++v8) {
-      bf16x8 y;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) y[e] = (bf16)(o[v8 * 8 + e] * inv);
-      *(bf16x8*)(O + tq * d + h * DH + v8 * 8) = y;
-    }
-  }
-}
-
 }  // namespace
 
 size_t row_attn_mfma_lds(int max_n, int dh) {
@@ -1243,28 +1168,6 @@ hipError_t launch_row_attn_mfma(const StepCtx& c, const void* QKV, void* O, int 
   if (dh == 16) hipLaunchKernelGGL((k_row_attn_mfma<16>), grid, block, lds, s, c, (const bf16*)QKV, (bf16*)O, d, heads);
   else if (dh == 32) hipLaunchKernelGGL((k_row_attn_mfma<32>), grid, block, lds, s, c, (const bf16*)QKV, (bf16*)O, d, heads);
   else if (dh == 64) hipLaunchKernelGGL((k_row_attn_mfma<64>), grid, block, lds, s, c, (const bf16*)QKV, (bf16*)O, d, heads);
-  else return hipErrorInvalidValue;
-  return hipGetLastError();
-}
-
-hipError_t launch_user_attn_bf16(const StepCtx& c, const void* QKV, void* O, int d, int heads, hipStream_t s) {
-  if (c.total_slots == 0) return hipSuccess;
-  const int kmax = kMaxK;
-  const size_t lds = (size_t)4 * kmax * 2 * d * sizeof(bf16);   // four waves, K <= 16 rows of k|v
-  static bool attr_set[3] = {false, false, false};
-  const int dh = d / heads;
-  const int which = dh == 16 ? 0 : (dh == 32 ? 1 : 2);
-  if (!attr_set[which]) {
-    const void* fn = dh == 16 ? (const void*)k_user_attn_wave<16>
-                              : (dh == 32 ? (const void*)k_user_attn_wave<32> : (const void*)k_user_attn_wave<64>);
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr_set[which] = true;
-  }
-  dim3 grid((unsigned)((c.total_slots + 3) / 4)), block(256);
-  if (dh == 16) hipLaunchKernelGGL((k_user_attn_wave<16>), grid, block, lds, s, c, (const bf16*)QKV, (bf16*)O, d, heads, kmax);
-  else if (dh == 32) hipLaunchKernelGGL((k_user_attn_wave<32>), grid, block, lds, s, c, (const bf16*)QKV, (bf16*)O, d, heads, kmax);
-  else if (dh == 64) hipLaunchKernelGGL((k_user_attn_wave<64>), grid, block, lds, s, c, (const bf16*)QKV, (bf16*)O, d, heads, kmax);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
