@@ -169,8 +169,8 @@ int mlp_tile_count(int D);
 bool gate_fusable(int d);
 bool mlp3_ok(int d, int F);
 bool proj3_ok(int d);
-hipError_t launch_proj3_bf16(const GemmArgs& g, const Mat& W, hipStream_t s);
-hipError_t launch_oproj3_bf16(const GemmArgs& g, const Mat& W, hipStream_t s);
+hipError_t launch_proj3_bf16(const GemmArgs& g, const Mat& W, hipStream_t s, bool gelu = false);
+hipError_t launch_oproj3_bf16(const GemmArgs& g, const Mat& W, hipStream_t s, bool gate = false);
 hipError_t launch_mlp3_bf16(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s);
 bool attn_block_ok(int d, int heads, int max_n, bool user);
 hipError_t launch_attn_block(const StepCtx& c, bool user, void* XN, const DevLayer& L, const float* ln_g,

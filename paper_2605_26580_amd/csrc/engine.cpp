@@ -404,7 +404,16 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
   GemmArgs g{};
   g.M = T;
   // gate MLP: H1 = GELU([Z ; e] Wg1^T + bg1); R = g Z + (1 - g) e, g = sigmoid(H1 Wg2^T + bg2)
-  if (fused_ln && gate_fusable(d)) {
+  if (prec == kBF16 && d == 256) {
+    // d = 256: the gate MLP as two token-resident kernels (the fused form's
+    // [Z ; e] rows and output accumulators exceed the register file)
+    g.N = d; g.Kd = 2 * d; g.A = k.ZE; g.bias = m.bg1; g.out = k.H1;
+    TIMED("gate1", launch_proj3_bf16(g, m.Wg1, s, true));
+    g = GemmArgs{}; g.M = T;
+    g.N = d; g.Kd = d; g.A = k.H1; g.bias = m.bg2; g.R = k.R; g.E = k.Ebuf;
+    next_ln(g, m.layer[0].ln1_g, m.layer[0].ln1_b);
+    TIMED("gate2", launch_oproj3_bf16(g, m.Wg2, s, true));
+  } else if (fused_ln && gate_fusable(d)) {
     // BF16 / FP8: both gate layers, the blend and the first LayerNorm in one kernel
     g.N = d; g.Kd = 2 * d; g.A = k.ZE; g.bias = m.bg2; g.R = k.R; g.E = k.Ebuf;
     next_ln(g, m.layer[0].ln1_g, m.layer[0].ln1_b);

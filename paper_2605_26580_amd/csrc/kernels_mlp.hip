@@ -112,14 +112,16 @@ __device__ __forceinline__ void m3_stage_vectors(float* sv, const GemmArgs& g, b
 // for token tok0 + 32 t, output rows 32 b + 8 q + 4 g2 + i in register 4q + i
 // (the two lanes l and l + 32 together hold the row).  R += acc2 + bias, then
 // the next LayerNorm into g.out (BF16) or, with PROJ, the final LayerNorm and
-// the 2-way projection into g.proj_out.  sv: the staged vectors.  Residual
-// rows are loaded in batches of up to four output blocks, all loads of a
-// batch issued before its stores.
-template <int D, int TB, bool PROJ>
+// the 2-way projection into g.proj_out.  With GATE (Module A) the update is
+// the gated blend R = s R + (1 - s) E, s = sigmoid(acc2 + bias), instead of
+// R += acc2 + bias.  sv: the staged vectors.  Residual rows are loaded in
+// batches of up to four output blocks, all loads of a batch issued before
+// its stores.
+template <int D, int TB, bool PROJ, bool GATE = false>
 __device__ __forceinline__ void m3_residual_epilogue(f32x16 (&acc2)[D / 32][TB], long tok0, const GemmArgs& g,
                                                      int g2, const float* sv) {
   constexpr int OBK = D / 32;
-  constexpr int HB = OBK > 4 ? 4 : OBK;
+  constexpr int HB = (GATE ? 2 : 4) < OBK ? (GATE ? 2 : 4) : OBK;   // output blocks per load batch
   const float* sbias = sv;
   const float* slg = sv + D;
   const float* slb = sv + 2 * D;
@@ -128,15 +130,19 @@ __device__ __forceinline__ void m3_residual_epilogue(f32x16 (&acc2)[D / 32][TB],
     const long tok = tok0 + 32 * t;
     const bool tv = tok < g.M;
     float* Rrow = g.R + (tv ? tok : 0) * D;
+    const float* Erow = GATE ? g.E + (tv ? tok : 0) * D : nullptr;
     float sum = 0.f;
 #pragma unroll
     for (int b0 = 0; b0 < OBK; b0 += HB) {
-      f32x4 rr[HB][4];
+      f32x4 rr[HB][4], ee[GATE ? HB : 1][4];
 #pragma unroll
       for (int bb = 0; bb < HB; ++bb)
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          rr[bb][q] = tv ? *(const f32x4*)(Rrow + 32 * (b0 + bb) + 8 * q + 4 * g2) : f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < 4; ++q) {
+          const int f = 32 * (b0 + bb) + 8 * q + 4 * g2;
+          rr[bb][q] = tv ? *(const f32x4*)(Rrow + f) : f32x4{0.f, 0.f, 0.f, 0.f};
+          if (GATE) ee[GATE ? bb : 0][q] = tv ? *(const f32x4*)(Erow + f) : f32x4{0.f, 0.f, 0.f, 0.f};
+        }
 #pragma unroll
       for (int bb = 0; bb < HB; ++bb)
 #pragma unroll
@@ -145,7 +151,13 @@ __device__ __forceinline__ void m3_residual_epilogue(f32x16 (&acc2)[D / 32][TB],
           const f32x4 bias = *(const f32x4*)&sbias[f];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const float res = rr[bb][q][i] + (acc2[b0 + bb][t][4 * q + i] + bias[i]);
+            float res;
+            if (GATE) {
+              const float gt = sigmoid_f(acc2[b0 + bb][t][4 * q + i] + bias[i]);
+              res = gt * rr[bb][q][i] + (1.0f - gt) * ee[GATE ? bb : 0][q][i];
+            } else {
+              res = rr[bb][q][i] + (acc2[b0 + bb][t][4 * q + i] + bias[i]);
+            }
             acc2[b0 + bb][t][4 * q + i] = res;
             sum += res;
           }
@@ -360,7 +372,7 @@ struct P3Smem {
   static constexpr size_t bytes = 2 * buf;
 };
 
-template <int D, int WPE>
+template <int D, int WPE, bool GELU>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void k_proj3(GemmArgs g, const bf16* __restrict__ W) {
   using S = P3Smem<D>;
@@ -427,8 +439,10 @@ void k_proj3(GemmArgs g, const bf16* __restrict__ W) {
       for (int q = 0; q < 4; ++q) {
         const int f = 8 * q + 4 * g2;
         const f32x4 bq = *(const f32x4*)&sb[f];
-        const bf16x4 h = {(bf16)(acc[4 * q] + bq[0]), (bf16)(acc[4 * q + 1] + bq[1]), (bf16)(acc[4 * q + 2] + bq[2]),
-                          (bf16)(acc[4 * q + 3] + bq[3])};
+        f32x4 v;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = GELU ? gelu_f(acc[4 * q + i] + bq[i]) : acc[4 * q + i] + bq[i];
+        const bf16x4 h = {(bf16)v[0], (bf16)v[1], (bf16)v[2], (bf16)v[3]};
         *(bf16x4*)(out + tok * N + c * 32 + f) = h;
       }
     }
@@ -442,7 +456,7 @@ void k_proj3(GemmArgs g, const bf16* __restrict__ W) {
 // projection); the contraction walks K in chunks of 32: W[:, k0:k0+32] is
 // DMA'd into LDS (80-byte rows) and the A rows' two k-fragments of the chunk
 // are read from memory one chunk ahead.
-template <int D>
+template <int D, bool GATE>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_oproj3(GemmArgs g, const bf16* __restrict__ W) {
   using S = M3Smem<D>;
@@ -504,28 +518,40 @@ void k_oproj3(GemmArgs g, const bf16* __restrict__ W) {
     fa[1] = fn[1];
     __syncthreads();
   }
-  m3_residual_epilogue<D, 1, false>(acc2, tok0, g, g2, sv);
+  m3_residual_epilogue<D, 1, false, GATE>(acc2, tok0, g, g2, sv);
 }
 
 }  // namespace
 
 // out = XN W^T + b (BF16), N a multiple of 32.
-hipError_t launch_proj3_bf16(const GemmArgs& g, const Mat& W, hipStream_t s) {
+hipError_t launch_proj3_bf16(const GemmArgs& g, const Mat& W, hipStream_t s, bool gelu) {
   if (g.M == 0) return hipSuccess;
-  if (!(g.Kd == 128 || g.Kd == 256) || g.N % 32 != 0 || g.N <= 0) return hipErrorInvalidValue;
+  if (!(g.Kd == 128 || g.Kd == 256 || g.Kd == 512) || g.N % 32 != 0 || g.N <= 0) return hipErrorInvalidValue;
   dim3 grid((unsigned)((g.M + kM3BM - 1) / kM3BM)), block(512);
-  if (g.Kd == 128) hipLaunchKernelGGL((k_proj3<128, 4>), grid, block, 0, s, g, W.b16);
-  else hipLaunchKernelGGL((k_proj3<256, 2>), grid, block, 0, s, g, W.b16);
-  return hipGetLastError();
+#define CIDER_P3(KD, WPE)                                                                          \
+  if (g.Kd == KD) {                                                                                \
+    if (gelu) hipLaunchKernelGGL((k_proj3<KD, WPE, true>), grid, block, 0, s, g, W.b16);           \
+    else hipLaunchKernelGGL((k_proj3<KD, WPE, false>), grid, block, 0, s, g, W.b16);               \
+    return hipGetLastError();                                                                      \
+  }
+  CIDER_P3(128, 4) CIDER_P3(256, 2) CIDER_P3(512, 2)
+#undef CIDER_P3
+  return hipErrorInvalidValue;
 }
 
 // R += A W^T + b (A in BF16, K = N = d), then the next LayerNorm into g.out.
-hipError_t launch_oproj3_bf16(const GemmArgs& g, const Mat& W, hipStream_t s) {
+hipError_t launch_oproj3_bf16(const GemmArgs& g, const Mat& W, hipStream_t s, bool gate) {
   if (g.M == 0) return hipSuccess;
   if (!(g.N == 128 || g.N == 256) || g.Kd != g.N || !g.ln_g || g.out_scale || g.proj_out) return hipErrorInvalidValue;
+  if (gate && !g.E) return hipErrorInvalidValue;
   dim3 grid((unsigned)((g.M + kM3BM - 1) / kM3BM)), block(512);
-  if (g.N == 128) hipLaunchKernelGGL((k_oproj3<128>), grid, block, 0, s, g, W.b16);
-  else hipLaunchKernelGGL((k_oproj3<256>), grid, block, 0, s, g, W.b16);
+  if (g.N == 128) {
+    if (gate) hipLaunchKernelGGL((k_oproj3<128, true>), grid, block, 0, s, g, W.b16);
+    else hipLaunchKernelGGL((k_oproj3<128, false>), grid, block, 0, s, g, W.b16);
+  } else {
+    if (gate) hipLaunchKernelGGL((k_oproj3<256, true>), grid, block, 0, s, g, W.b16);
+    else hipLaunchKernelGGL((k_oproj3<256, false>), grid, block, 0, s, g, W.b16);
+  }
   return hipGetLastError();
 }
 
