@@ -363,30 +363,34 @@ hipError_t mlp3_t(const GemmArgs& g, const bf16* W1, const float* b1, const bf16
 // registers and walks the N outputs in chunks of 32 rows of W, DMA'd into
 // LDS (rows padded by 16 bytes), double-buffered.  Lane l ends a chunk with
 // outputs 8q + 4(l/32) + i of token l%32 and stores them as BF16.
-template <int D>
+template <int D, int CHB>
 struct P3Smem {
   static constexpr int RB = D * 2 + 16;
-  static constexpr size_t w = (size_t)32 * RB;
+  static constexpr size_t w = (size_t)32 * CHB * RB;          // one chunk: 32 CHB rows of W
   static constexpr size_t wa = (w + 1023) / 1024 * 1024;
-  static constexpr size_t buf = wa + 256;         // + the chunk's bias
-  static constexpr size_t bytes = 2 * buf;
+  static constexpr size_t buf = wa;
+  static constexpr size_t bytes = 2 * buf + 3 * 512 * 4;      // + the whole bias (N <= 1536)
+  static_assert(bytes <= 160 * 1024, "LDS");
 };
 
-template <int D, int WPE, bool GELU>
+// Chunks of CHB 32-row blocks of W (128 rows at d <= 256, 64 at input width
+// 512), so that a chunk's 16 CHB d / 256 MFMAs per wave cover the L2 round
+// trip of the next chunk's DMA.
+template <int D, int CHB, int WPE, bool GELU>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void k_proj3(GemmArgs g, const bf16* __restrict__ W) {
-  using S = P3Smem<D>;
+  using S = P3Smem<D, CHB>;
   constexpr int NW = 8, RB = S::RB, KS = D / 16;
   constexpr int NB = (int)(S::wa / 1024), NPW = (NB + NW - 1) / NW;
   __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
+  float* sbias = (float*)(smem + 2 * S::buf);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
   const long tok = (long)blockIdx.x * kM3BM + wave * 32 + l32;
   const bool tv = tok < g.M;
-  const int N = g.N, nch = N / 32;
+  const int N = g.N, nch = N / (32 * CHB);
   const bf16* __restrict__ A = (const bf16*)g.A;
   bf16* __restrict__ out = (bf16*)g.out;
 
-  float pb = 0.f;
   auto dma = [&](int c, int buf) {
     char* base = smem + buf * S::buf;
 #pragma unroll
@@ -395,56 +399,49 @@ void k_proj3(GemmArgs g, const bf16* __restrict__ W) {
       if (u >= NB) break;
       const int pos = u * 1024 + lane * 16, j = pos / RB, o = pos - j * RB;
       const bool data = o < RB - 16;
-      const bf16* src = W + (long)(c * 32 + (data ? j : 0)) * D + (data ? o / 2 : 0);
+      const bf16* src = W + (long)(c * 32 * CHB + (data ? j : 0)) * D + (data ? o / 2 : 0);
       if (pos < (int)S::w)
         __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(base + u * 1024), 16, 0, 0);
     }
   };
-  auto bias_fetch = [&](int c) {
-    if (tid < 32) pb = g.bias[c * 32 + tid];
-  };
-  auto bias_stash = [&](int buf) {
-    if (tid < 32) ((float*)(smem + buf * S::buf + S::wa))[tid] = pb;
-  };
+  for (int i = tid; i < N; i += 512) sbias[i] = g.bias[i];
 
   bf16x8 xf[KS];
 #pragma unroll
   for (int s = 0; s < KS; ++s)
     xf[s] = tv ? *(const bf16x8*)(A + tok * D + 16 * s + 8 * g2) : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
 
-  bias_fetch(0);
   dma(0, 0);
-  bias_stash(0);
-  if (nch > 1) bias_fetch(1);
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
     const int buf = c & 1;
-    if (c + 1 < nch) {
-      dma(c + 1, buf ^ 1);
-      bias_stash(buf ^ 1);
-      if (c + 2 < nch) bias_fetch(c + 2);
-    }
+    if (c + 1 < nch) dma(c + 1, buf ^ 1);       // its last readers finished before the previous barrier
     const char* sw = smem + buf * S::buf;
-    const float* sb = (const float*)(smem + buf * S::buf + S::wa);
-    f32x16 acc;
+    f32x16 acc[CHB];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    for (int cb = 0; cb < CHB; ++cb)
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const bf16x8 a = *(const bf16x8*)(sw + l32 * RB + (2 * s + g2) * 16);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, xf[s], acc, 0, 0, 0);
-    }
+      for (int r = 0; r < 16; ++r) acc[cb][r] = 0.f;
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int cb = 0; cb < CHB; ++cb) {
+        const bf16x8 a = *(const bf16x8*)(sw + (32 * cb + l32) * RB + (2 * s + g2) * 16);
+        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, xf[s], acc[cb], 0, 0, 0);
+      }
     if (tv) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int f = 8 * q + 4 * g2;
-        const f32x4 bq = *(const f32x4*)&sb[f];
-        f32x4 v;
+      for (int cb = 0; cb < CHB; ++cb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) v[i] = GELU ? gelu_f(acc[4 * q + i] + bq[i]) : acc[4 * q + i] + bq[i];
-        const bf16x4 h = {(bf16)v[0], (bf16)v[1], (bf16)v[2], (bf16)v[3]};
-        *(bf16x4*)(out + tok * N + c * 32 + f) = h;
-      }
+        for (int q = 0; q < 4; ++q) {
+          const int f = c * 32 * CHB + 32 * cb + 8 * q + 4 * g2;
+          const f32x4 bq = *(const f32x4*)&sbias[f];
+          f32x4 v;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) v[i] = GELU ? gelu_f(acc[cb][4 * q + i] + bq[i]) : acc[cb][4 * q + i] + bq[i];
+          const bf16x4 h = {(bf16)v[0], (bf16)v[1], (bf16)v[2], (bf16)v[3]};
+          *(bf16x4*)(out + tok * N + f) = h;
+        }
     }
     __syncthreads();
   }
@@ -453,18 +450,29 @@ void k_proj3(GemmArgs g, const bf16* __restrict__ W) {
 // k_oproj3: R += A W^T + b over K = d, then the next LayerNorm into g.out (the
 // output projection after attention, A = O in BF16).  Each wave owns 32
 // tokens and accumulates all d outputs (acc2, as in the MLP's down
-// projection); the contraction walks K in chunks of 32: W[:, k0:k0+32] is
-// DMA'd into LDS (80-byte rows) and the A rows' two k-fragments of the chunk
-// are read from memory one chunk ahead.
+// projection); the contraction walks K in chunks of KCH = 128:
+// W[:, k0:k0+128] is DMA'd into LDS (rows padded by 16 bytes) and the A rows'
+// k-fragments of the chunk are read from memory one chunk ahead.
+template <int D, int KCH>
+struct O3Smem {
+  static constexpr int RB = KCH * 2 + 16;
+  static constexpr size_t w = (size_t)D * RB;
+  static constexpr size_t wa = (w + 1023) / 1024 * 1024;
+  static constexpr int NCH = D / KCH;
+  static constexpr size_t bytes = (NCH > 1 ? 2 : 1) * wa + 3 * D * 4;
+  static_assert(D % KCH == 0 && bytes <= 160 * 1024, "LDS");
+};
+
 template <int D, bool GATE>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_oproj3(GemmArgs g, const bf16* __restrict__ W) {
-  using S = M3Smem<D>;
-  constexpr int NW = 8, RB2 = S::RB2, OBK = D / 32, NCH = D / 32;
-  constexpr int NB = (int)(S::w2a / 1024), NPW = (NB + NW - 1) / NW;
-  constexpr size_t BUF = S::w2a;
-  __shared__ __attribute__((aligned(1024))) char smem[2 * BUF + 3 * D * 4];
-  float* sv = (float*)(smem + 2 * BUF);
+  constexpr int KCH = 128;
+  using S = O3Smem<D, KCH>;
+  constexpr int NW = 8, RB = S::RB, OBK = D / 32, NCH = S::NCH, KSC = KCH / 16;
+  constexpr int NB = (int)(S::wa / 1024), NPW = (NB + NW - 1) / NW;
+  constexpr size_t BUF = S::wa;
+  __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
+  float* sv = (float*)(smem + (NCH > 1 ? 2 : 1) * BUF);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
   const long tok0 = (long)blockIdx.x * kM3BM + wave * 32 + l32;
   const bool tv = tok0 < g.M;
@@ -476,17 +484,17 @@ void k_oproj3(GemmArgs g, const bf16* __restrict__ W) {
     for (int k = 0; k < NPW; ++k) {
       const int u = wave + k * NW;
       if (u >= NB) break;
-      const int pos = u * 1024 + lane * 16, j = pos / RB2, o = pos - j * RB2;
-      const bool data = o < RB2 - 16;
-      const bf16* src = W + (long)(data ? j : 0) * D + c * 32 + (data ? o / 2 : 0);
-      if (pos < (int)S::w2)
+      const int pos = u * 1024 + lane * 16, j = pos / RB, o = pos - j * RB;
+      const bool data = o < RB - 16;
+      const bf16* src = W + (long)(data ? j : 0) * D + c * KCH + (data ? o / 2 : 0);
+      if (pos < (int)S::w)
         __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(base + u * 1024), 16, 0, 0);
     }
   };
-  auto afrag = [&](int c, bf16x8 (&f)[2]) {
+  auto afrag = [&](int c, bf16x8 (&f)[KSC]) {
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
-      f[s] = tv ? *(const bf16x8*)(A + tok0 * D + c * 32 + 16 * s + 8 * g2) : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    for (int s = 0; s < KSC; ++s)
+      f[s] = tv ? *(const bf16x8*)(A + tok0 * D + c * KCH + 16 * s + 8 * g2) : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
   };
 
   f32x16 acc2[OBK][1];
@@ -494,7 +502,7 @@ void k_oproj3(GemmArgs g, const bf16* __restrict__ W) {
   for (int b = 0; b < OBK; ++b)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc2[b][0][r] = 0.f;
-  bf16x8 fa[2], fn[2];
+  bf16x8 fa[KSC], fn[KSC];
   m3_stage_vectors<D>(sv, g, false, tid, 512);
   afrag(0, fa);
   dma(0, 0);
@@ -508,15 +516,17 @@ void k_oproj3(GemmArgs g, const bf16* __restrict__ W) {
     }
     const char* sw = smem + buf * BUF;
 #pragma unroll
-    for (int b = 0; b < OBK; ++b)
+    for (int s = 0; s < KSC; ++s)
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const bf16x8 w = *(const bf16x8*)(sw + (32 * b + l32) * RB2 + (2 * s + g2) * 16);
+      for (int b = 0; b < OBK; ++b) {
+        const bf16x8 w = *(const bf16x8*)(sw + (32 * b + l32) * RB + (2 * s + g2) * 16);
         acc2[b][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, fa[s], acc2[b][0], 0, 0, 0);
       }
-    fa[0] = fn[0];
-    fa[1] = fn[1];
-    __syncthreads();
+    if (c + 1 < NCH) {
+#pragma unroll
+      for (int s = 0; s < KSC; ++s) fa[s] = fn[s];
+      __syncthreads();
+    }
   }
   m3_residual_epilogue<D, 1, false, GATE>(acc2, tok0, g, g2, sv);
 }
@@ -526,15 +536,17 @@ void k_oproj3(GemmArgs g, const bf16* __restrict__ W) {
 // out = XN W^T + b (BF16), N a multiple of 32.
 hipError_t launch_proj3_bf16(const GemmArgs& g, const Mat& W, hipStream_t s, bool gelu) {
   if (g.M == 0) return hipSuccess;
-  if (!(g.Kd == 128 || g.Kd == 256 || g.Kd == 512) || g.N % 32 != 0 || g.N <= 0) return hipErrorInvalidValue;
+  if (!(g.Kd == 128 || g.Kd == 256 || g.Kd == 512) || g.N % 32 != 0 || g.N <= 0 || g.N > 1536)
+    return hipErrorInvalidValue;
   dim3 grid((unsigned)((g.M + kM3BM - 1) / kM3BM)), block(512);
-#define CIDER_P3(KD, WPE)                                                                          \
-  if (g.Kd == KD) {                                                                                \
-    if (gelu) hipLaunchKernelGGL((k_proj3<KD, WPE, true>), grid, block, 0, s, g, W.b16);           \
-    else hipLaunchKernelGGL((k_proj3<KD, WPE, false>), grid, block, 0, s, g, W.b16);               \
+#define CIDER_P3(KD, CHB, WPE)                                                                     \
+  if (g.Kd == KD && g.N % (32 * CHB) == 0) {                                                       \
+    if (gelu) hipLaunchKernelGGL((k_proj3<KD, CHB, WPE, true>), grid, block, 0, s, g, W.b16);      \
+    else hipLaunchKernelGGL((k_proj3<KD, CHB, WPE, false>), grid, block, 0, s, g, W.b16);          \
     return hipGetLastError();                                                                      \
   }
-  CIDER_P3(128, 4) CIDER_P3(256, 2) CIDER_P3(512, 2)
+  CIDER_P3(128, 4, 2) CIDER_P3(128, 1, 4) CIDER_P3(256, 4, 2) CIDER_P3(256, 1, 2) CIDER_P3(512, 2, 2)
+  CIDER_P3(512, 1, 2)
 #undef CIDER_P3
   return hipErrorInvalidValue;
 }
