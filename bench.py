@@ -117,23 +117,21 @@ def algorithmic(model, n, K, es: int):
     return per_tok, flop, byt
 
 
-KERNEL_SOURCE = {"mlp_fused": "kernels_fast.hip", "attn_row": "kernels_fast.hip", "attn_user": "kernels_fast.hip",
-                 "gate_fused": "kernels_fast.hip", "attn_block_row": "kernels_block.hip",
-                 "attn_block_user": "kernels_block.hip"}
-
-
 def _measured_traffic(workload: str, kernel: str):
     """HBM bytes per launch from a committed rocprofv3 PMC summary, if it was
-    taken on the kernel source as it stands (its SHA-1 recorded there)."""
+    taken on the kernel source as it stands (the summary names that source file
+    and records its SHA-1)."""
     path = os.path.join(ROOT, "profiles", f"{workload}_{kernel}_traffic.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     m_s = re.search(r"source_sha1:\s*([0-9a-f]{40})", txt)
-    src = KERNEL_SOURCE.get(kernel, "kernels_fast.hip")
-    cur = hashlib.sha1(open(os.path.join(ROOT, "paper_2605_26580_amd", "csrc", src), "rb").read()).hexdigest()
-    if not m_b or not m_s or m_s.group(1) != cur:
+    m_f = re.search(r"^source:\s*(\S+)", txt, re.M)
+    if not m_b or not m_s or not m_f:
+        return None
+    src = os.path.join(ROOT, m_f.group(1))
+    if not os.path.exists(src) or hashlib.sha1(open(src, "rb").read()).hexdigest() != m_s.group(1):
         return None
     return float(m_b.group(1))
 

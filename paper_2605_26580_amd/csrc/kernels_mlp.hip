@@ -4,10 +4,10 @@
 //   (or, after the last block, the final LayerNorm and the 2-way symbol
 //   projection into lbar).
 //
-// A workgroup owns 256 tokens: NW waves of TB 32-token blocks each (d = 128:
-// 8 waves x 1 block, two waves per SIMD; d = 256: 4 waves x 2 blocks, one
-// wave per SIMD with the accumulators in AGPRs, so that every weight fragment
-// read from LDS feeds two MFMAs).  Each wave keeps its XN rows in registers
+// A workgroup owns 256 tokens: NW waves of TB 32-token blocks each (at
+// d = 128 and 256: 8 waves x 1 block, two waves per SIMD; TB = 2 halves the
+// LDS reads per MFMA but leaves one wave per SIMD, which measured slower).
+// Each wave keeps its XN rows in registers
 // for the whole kernel as the B operand of v_mfma_f32_32x32x16_bf16 (lane l:
 // token l%32 of a block, k-group l/32) and walks the hidden dimension in
 // chunks of 32.  The chunk's W1 rows and W2 columns go
