@@ -231,7 +231,7 @@ __device__ __forceinline__ void m3_residual_epilogue(f32x16 (&acc2)[D / 32][TB],
   }
 }
 
-template <int D, int TB, int NW, int WPE, int NBUF, bool PROJ>
+template <int D, int TB, int NW, int WPE, int NBUF, bool PIPE, int SCHED, bool PROJ>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void k_mlp3(GemmArgs g, const bf16* __restrict__ W1, const float* __restrict__ b1, const bf16* __restrict__ W2,
             int F) {
@@ -297,61 +297,159 @@ void k_mlp3(GemmArgs g, const bf16* __restrict__ W1, const float* __restrict__ b
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc2[b][t][r] = 0.f;
 
-  const int pre = min(NBUF - 1, nch);            // chunks in flight before the loop
-  for (int c = 0; c < pre; ++c) dma(c, c);
-  __syncthreads();                                // b1 staged, and this wave's DMA of chunks < pre done
-  for (int c = 0; c < nch; ++c) {
-    const int buf = c % NBUF;
-    // buffer (c + NBUF - 1) % NBUF was last read in iteration c - 1, before its closing barrier
-    if (c + NBUF - 1 < nch) dma(c + NBUF - 1, (c + NBUF - 1) % NBUF);
-    const char* s1 = smem + buf * S::buf;
-    const char* s2 = smem + buf * S::buf + S::w1a;
+  // up: acc[t][r] = b1[c0 + h] + sum_k W1[c0 + h][k] XN[token][k] for the
+  // hidden unit h = sigma(8(r/4) + 4 g2 + r%4) = 16(q/2) + 8 g2 + 4(q%2) + i,
+  // r = 4q + i (the accumulators start at the bias)
+  auto up = [&](int c, f32x16 (&acc)[TB]) {
+    const char* s1 = smem + (c % NBUF) * S::buf;
     const float* sb = sb1 + c * kM3FCH;
-    // up: acc1[t][r] = sum_k W1[c0 + sigma(8(r/4) + 4 g2 + r%4)][k] XN[token][k]
-    f32x16 acc1[TB];
-#pragma unroll
-    for (int t = 0; t < TB; ++t)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc1[t][r] = 0.f;
-#pragma unroll
-    for (int s = 0; s < KS1; ++s) {
-      const bf16x8 a = *(const bf16x8*)(s1 + l32 * RB1 + (2 * s + g2) * 16);
-#pragma unroll
-      for (int t = 0; t < TB; ++t) acc1[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, xf[t][s], acc1[t], 0, 0, 0);
-    }
-    // register 4q + i holds hidden unit 16(q/2) + 8 g2 + 4(q%2) + i
-    bf16x8 hf[TB][2];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const f32x4 bq = *(const f32x4*)&sb[16 * (q >> 1) + 8 * g2 + 4 * (q & 1)];
 #pragma unroll
       for (int t = 0; t < TB; ++t)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) hf[t][q >> 1][4 * (q & 1) + i] = (bf16)gelu_f(acc1[t][4 * q + i] + bq[i]);
+        for (int i = 0; i < 4; ++i) acc[t][4 * q + i] = bq[i];
     }
-    // down: acc2[b] += W2[32 b + row][c0 + 16 s + 8 g2 + e] H[16 s + 8 g2 + e]
+#pragma unroll
+    for (int s = 0; s < KS1; ++s) {
+      const bf16x8 a = *(const bf16x8*)(s1 + l32 * RB1 + (2 * s + g2) * 16);
+#pragma unroll
+      for (int t = 0; t < TB; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, xf[t][s], acc[t], 0, 0, 0);
+    }
+  };
+  // GELU of an up product, rounded to BF16: register 4q + i of token block t
+  // becomes element 4(q%2) + i of k-fragment q/2, the k-values this lane
+  // supplies to the down MFMAs
+  auto gelu = [&](const f32x16 (&acc)[TB], bf16x8 (&h)[TB][2]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int t = 0; t < TB; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) h[t][q >> 1][4 * (q & 1) + i] = (bf16)gelu_f(acc[t][4 * q + i]);
+  };
+  // down: acc2[b] += W2[32 b + row][c0 + 16 s + 8 g2 + e] H[16 s + 8 g2 + e]
+  auto down = [&](int c, const bf16x8 (&h)[TB][2]) {
+    const char* s2 = smem + (c % NBUF) * S::buf + S::w1a;
 #pragma unroll
     for (int b = 0; b < OBK; ++b)
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         const bf16x8 w = *(const bf16x8*)(s2 + (32 * b + l32) * RB2 + (2 * s + g2) * 16);
 #pragma unroll
-        for (int t = 0; t < TB; ++t)
-          acc2[b][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, hf[t][s], acc2[b][t], 0, 0, 0);
+        for (int t = 0; t < TB; ++t) acc2[b][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, h[t][s], acc2[b][t], 0, 0, 0);
       }
-    // chunk c + 1 complete in every wave: this wave may still have the DMA
-    // of the chunks after it (at most NBUF - 2) outstanding
-    if (c + 1 < nch) m3_wait_barrier(nw * (min(c + NBUF - 1, nch - 1) - (c + 1)));
+  };
+
+  const int pre = min(NBUF - 1, nch);            // chunks in flight before the loop
+  for (int c = 0; c < pre; ++c) dma(c, c);
+  __syncthreads();                                // b1 staged, and this wave's DMA of chunks < pre done
+  f32x16 acc1[TB];
+  bf16x8 hf[TB][2];
+  if constexpr (!PIPE) {
+    // One chunk at a time: up, GELU, down.
+    for (int c = 0; c < nch; ++c) {
+      // buffer (c + NBUF - 1) % NBUF was last read in iteration c - 1, before its closing barrier
+      if (c + NBUF - 1 < nch) dma(c + NBUF - 1, (c + NBUF - 1) % NBUF);
+      up(c, acc1);
+      gelu(acc1, hf);
+      down(c, hf);
+      // chunk c + 1 complete in every wave: this wave may still have the DMA
+      // of the chunks after it (at most NBUF - 2) outstanding
+      if (c + 1 < nch) m3_wait_barrier(nw * (min(c + NBUF - 1, nch - 1) - (c + 1)));
+    }
+  } else {
+    // Two-deep software pipeline: iteration c issues chunk c's down
+    // projection, the GELU of chunk c + 1 and chunk c + 2's up projection,
+    // three independent streams of MFMA and VALU work that the wave can
+    // interleave.  It reads W2 of chunk c and W1 of chunk c + 2 and DMAs
+    // chunk c + NBUF - 1 into the buffer of chunk c - 1, so NBUF >= 4.
+    static_assert(NBUF >= 4, "four weight buffers");
+    up(0, acc1);
+    gelu(acc1, hf);
+    if (nch > 1) up(1, acc1);
+    int c = 0;
+    for (; c + 2 < nch; ++c) {
+      // buffer (c + NBUF - 1) % NBUF = (c - 1) % NBUF was last read in
+      // iteration c - 1 (W2 of chunk c - 1), before its closing barrier
+      if (c + NBUF - 1 < nch) dma(c + NBUF - 1, (c + NBUF - 1) % NBUF);
+      bf16x8 hn[TB][2];
+      if constexpr (SCHED == 0) {
+        gelu(acc1, hn);
+        up(c + 2, acc1);
+        down(c, hf);
+      } else {
+        // The same three streams in a fixed order: every A fragment read
+        // up front, then each MFMA followed by its share of the GELU pairs
+        // (scheduling fences keep the order).
+        const char* s1 = smem + ((c + 2) % NBUF) * S::buf;
+        const char* s2 = smem + (c % NBUF) * S::buf + S::w1a;
+        const float* sb = sb1 + (c + 2) * kM3FCH;
+        bf16x8 a1[KS1], a2[2 * OBK];
+#pragma unroll
+        for (int k = 0; k < KS1; ++k) a1[k] = *(const bf16x8*)(s1 + l32 * RB1 + (2 * k + g2) * 16);
+#pragma unroll
+        for (int j = 0; j < 2 * OBK; ++j) a2[j] = *(const bf16x8*)(s2 + (32 * (j >> 1) + l32) * RB2 + (2 * (j & 1) + g2) * 16);
+        f32x16 an[TB];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const f32x4 bq = *(const f32x4*)&sb[16 * (q >> 1) + 8 * g2 + 4 * (q & 1)];
+#pragma unroll
+          for (int t = 0; t < TB; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) an[t][4 * q + i] = bq[i];
+        }
+        constexpr int NM = (KS1 + 2 * OBK) * TB;   // MFMAs of this iteration
+        constexpr int NP = 8 * TB;                  // GELU pairs
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+          if (m < KS1 * TB) {
+            const int k = m / TB, t = m % TB;
+            an[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[k], xf[t][k], an[t], 0, 0, 0);
+          } else {
+            const int j = (m - KS1 * TB) / TB, t = (m - KS1 * TB) % TB;
+            acc2[j >> 1][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[j], hf[t][j & 1], acc2[j >> 1][t], 0, 0, 0);
+          }
+#pragma unroll
+          for (int pr = (m * NP + NM - 1) / NM; pr < ((m + 1) * NP + NM - 1) / NM; ++pr) {
+            const int t = pr / 8, r = 2 * (pr % 8), q = r >> 2, i = r & 3;
+            hn[t][q >> 1][4 * (q & 1) + i] = (bf16)gelu_f(acc1[t][r]);
+            hn[t][q >> 1][4 * (q & 1) + i + 1] = (bf16)gelu_f(acc1[t][r + 1]);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int t = 0; t < TB; ++t) acc1[t] = an[t];
+      }
+#pragma unroll
+      for (int t = 0; t < TB; ++t) {
+        hf[t][0] = hn[t][0];
+        hf[t][1] = hn[t][1];
+      }
+      // chunk c + 3 complete in every wave (the next iteration's up
+      // projection reads it); later chunks may still be in flight
+      m3_wait_barrier(nw * max(0, min(c + NBUF - 1, nch - 1) - (c + 3)));
+    }
+    // the last one or two chunks: their weights are complete and no DMA follows
+    if (c + 1 < nch) {
+      bf16x8 hn[TB][2];
+      gelu(acc1, hn);
+      down(c, hf);
+      down(c + 1, hn);
+    } else {
+      down(c, hf);
+    }
   }
 
   m3_residual_epilogue<D, TB, PROJ>(acc2, tok0, g, g2, sv);
 }
 
-template <int D, int TB, int NW, int WPE, int NBUF>
+template <int D, int TB, int NW, int WPE, int NBUF, bool PIPE, int SCHED = 0>
 hipError_t mlp3_t(const GemmArgs& g, const bf16* W1, const float* b1, const bf16* W2, int F, hipStream_t s) {
   dim3 grid((unsigned)((g.M + kM3BM - 1) / kM3BM)), block(NW * 64);
-  if (g.proj_out) hipLaunchKernelGGL((k_mlp3<D, TB, NW, WPE, NBUF, true>), grid, block, 0, s, g, W1, b1, W2, F);
-  else hipLaunchKernelGGL((k_mlp3<D, TB, NW, WPE, NBUF, false>), grid, block, 0, s, g, W1, b1, W2, F);
+  if (g.proj_out) hipLaunchKernelGGL((k_mlp3<D, TB, NW, WPE, NBUF, PIPE, SCHED, true>), grid, block, 0, s, g, W1, b1, W2, F);
+  else hipLaunchKernelGGL((k_mlp3<D, TB, NW, WPE, NBUF, PIPE, SCHED, false>), grid, block, 0, s, g, W1, b1, W2, F);
   return hipGetLastError();
 }
 
@@ -576,8 +674,8 @@ bool mlp3_ok(int d, int F) { return (d == 128 || d == 256) && F % kM3FCH == 0 &&
 hipError_t launch_mlp3_bf16(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s) {
   if (g.M == 0) return hipSuccess;
   if (!mlp3_ok(g.N, F) || !g.ln_g || g.out_scale) return hipErrorInvalidValue;
-  if (g.N == 128) return mlp3_t<128, 1, 8, 2, 4>(g, W1.b16, b1, W2.b16, F, s);
-  return mlp3_t<256, 1, 8, 2, 3>(g, W1.b16, b1, W2.b16, F, s);
+  if (g.N == 128) return mlp3_t<128, 1, 8, 2, 4, true, 1>(g, W1.b16, b1, W2.b16, F, s);
+  return mlp3_t<256, 1, 8, 2, 3, false>(g, W1.b16, b1, W2.b16, F, s);
 }
 
 }  // namespace cider
