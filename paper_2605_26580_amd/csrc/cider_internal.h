@@ -68,6 +68,7 @@ struct StepCtx {
   const int* slot_bin;      // device [total_slots]
   const int* row_bin;       // device [total_rows]
   const int* ugrp;          // device [total_ugrp][2]: (bin, first column) of each user-attention block
+  const int* tile_bin;      // device [ceil(T / 256)]: bin holding token 256 i
   int total_slots;
   int total_rows;
   int total_ugrp;
@@ -177,6 +178,20 @@ hipError_t launch_attn_block(const StepCtx& c, bool user, void* XN, const DevLay
                              const float* ln_b, float* R, int d, int heads, hipStream_t s);
 // Columns of one K-row bin that one user-attention block covers.
 inline int ugrp_cols(int K) { return (kBlkUserSlots / 16) * (16 / K); }
+// Embedding + Module A + the first LayerNorm in one kernel (BF16, d = 128).
+struct EmbedGateArgs {
+  const bf16* Wg1;      // [d][2d]
+  const float* bg1;     // [d]
+  const bf16* Wg2;      // [d][d]
+  const float* bg2;     // [d]
+  const float* ln_g;    // first layer's LayerNorm 1
+  const float* ln_b;
+  const float* p;       // [slots][2] per-slot beliefs
+  float* R;             // [T][d] FP32 residual stream (out)
+  bf16* XN;             // [T][d] LayerNorm output (out)
+};
+bool embed_gate3_ok(int d);
+hipError_t launch_embed_gate3(const StepCtx& c, const EmbedW& m, const EmbedGateArgs& a, hipStream_t s);
 hipError_t launch_gate_bf16(const GemmArgs& g, const Mat& Wg1, const float* bg1, const Mat& Wg2, hipStream_t s);
 hipError_t launch_gemm_fp8(const GemmArgs& g, const Mat& W, hipStream_t s);
 hipError_t launch_mlp_fp8(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s);

@@ -193,7 +193,7 @@ struct Layout {
   int num_bins = 0;
   long total_tokens = 0;
   int total_slots = 0, total_rows = 0, max_n = 0, total_ugrp = 0;
-  size_t off_ugrp = 0, off_R, off_E, off_ZE, off_H1, off_QKV, off_O, off_HID, off_lbar, off_logits, off_p, off_S,
+  size_t off_ugrp = 0, off_tile = 0, off_R, off_E, off_ZE, off_H1, off_QKV, off_O, off_HID, off_lbar, off_logits, off_p, off_S,
       off_bins, off_state, off_slot, off_row, off_X, off_XN, off_XN8, off_xscale, total;
 };
 
@@ -226,6 +226,7 @@ Layout plan_layout(const cider_model_cfg& cfg, int num_bins, long T, int slots, 
   L.off_slot = take((size_t)slots * 4);
   L.off_row = take((size_t)rows * 4);
   L.off_ugrp = take(((size_t)slots + num_bins) * 2 * 4);   // user-attention groups, at most one per column
+  L.off_tile = take(((size_t)T / 256 + 1) * 4);              // bin of the first token of each 256-token tile
   L.off_X = take(T);
   L.total = o;
   return L;
@@ -400,11 +401,19 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
   // BF16: fused attention blocks where the shapes allow (row attention needs n <= 128)
   const bool blk_row = prec == kBF16 && r.use_blocks && attn_block_ok(d, m.heads, c.max_n, false);
   const bool blk_user = prec == kBF16 && r.use_blocks && attn_block_ok(d, m.heads, c.max_n, true);
-  TIMED("embed_demix", launch_embed_demix(c, w->ew, k, prec, s));
   GemmArgs g{};
   g.M = T;
+  // BF16 at d = 128: embedding, Module A and the first LayerNorm in one kernel
+  const bool embed_gate = prec == kBF16 && r.use_blocks && fused_ln && embed_gate3_ok(d);
+  if (!embed_gate) TIMED("embed_demix", launch_embed_demix(c, w->ew, k, prec, s));
   // gate MLP: H1 = GELU([Z ; e] Wg1^T + bg1); R = g Z + (1 - g) e, g = sigmoid(H1 Wg2^T + bg2)
-  if (prec == kBF16 && d == 256) {
+  if (embed_gate) {
+    EmbedGateArgs ea{};
+    ea.Wg1 = m.Wg1.b16; ea.bg1 = m.bg1; ea.Wg2 = m.Wg2.b16; ea.bg2 = m.bg2;
+    ea.ln_g = m.layer[0].ln1_g; ea.ln_b = m.layer[0].ln1_b;
+    ea.p = k.p; ea.R = k.R; ea.XN = (bf16*)k.XN;
+    TIMED("embed_gate", launch_embed_gate3(c, w->ew, ea, s));
+  } else if (prec == kBF16 && d == 256) {
     // d = 256: the gate MLP as two token-resident kernels (the fused form's
     // [Z ; e] rows and output accumulators exceed the register file)
     g.N = d; g.Kd = 2 * d; g.A = k.ZE; g.bias = m.bg1; g.out = k.H1;
@@ -659,13 +668,15 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
   if (rc) return rc;
   int ngrp = 0;
   for (const BinIn& b : bins) ngrp += (b.n + ugrp_cols(b.K) - 1) / ugrp_cols(b.K);
-  size_t meta = B * sizeof(DevBin) + (size_t)(slots + rows) * 4 + (size_t)ngrp * 2 * 4;
+  const int ntile = (int)((T + 255) / 256);
+  size_t meta = B * sizeof(DevBin) + (size_t)(slots + rows) * 4 + (size_t)ngrp * 2 * 4 + (size_t)ntile * 4;
   rc = ensure_pinned(w, meta);
   if (rc) return rc;
   DevBin* hb = (DevBin*)w->pinned;
   int* hslot = (int*)((char*)w->pinned + B * sizeof(DevBin));
   int* hrow = hslot + slots;
   int* hgrp = hrow + rows;
+  int* htile = hgrp + 2 * (size_t)ngrp;
   int go = 0;
   long tok = 0;
   int so = 0, ro = 0;
@@ -693,6 +704,7 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
       hgrp[2 * go + 1] = l0;
       ++go;
     }
+    for (long t0 = (tok + 255) / 256 * 256; t0 < tok + (long)b.K * b.n; t0 += 256) htile[t0 / 256] = i;
     tok += (long)b.K * b.n;
     so += b.n;
     ro += b.K;
@@ -702,6 +714,7 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
   HIPCHK(hipMemcpyAsync(base + L.off_slot, hslot, (size_t)slots * 4, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(base + L.off_row, hrow, (size_t)rows * 4, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(base + L.off_ugrp, hgrp, (size_t)ngrp * 2 * 4, hipMemcpyHostToDevice, s));
+  if (ntile) HIPCHK(hipMemcpyAsync(base + L.off_tile, htile, (size_t)ntile * 4, hipMemcpyHostToDevice, s));
   HIPCHK(hipEventRecord(w->meta_done, s));
 
   StepCtx& c = r->ctx;
@@ -711,6 +724,7 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
   c.slot_bin = (const int*)(base + L.off_slot);
   c.row_bin = (const int*)(base + L.off_row);
   c.ugrp = (const int*)(base + L.off_ugrp);
+  c.tile_bin = (const int*)(base + L.off_tile);
   c.total_slots = slots;
   c.total_rows = rows;
   c.total_ugrp = ngrp;

@@ -629,6 +629,257 @@ void k_oproj3(GemmArgs g, const bf16* __restrict__ W) {
   m3_residual_epilogue<D, 1, false, GATE>(acc2, tok0, g, g2, sv);
 }
 
+// ---------------------------------------------------------------------------
+// Module A for the BF16 path, from the symbol grid to the first LayerNorm in
+// one token-resident kernel (method section, Module A; Appendix, one-step
+// algorithm):
+//   Z = E[x] + P[l] + gamma u,    r[k, a] = softmax over the slot's rows of
+//   <Z[k], w_a> / tau,            e = sum_a r[k, a] p[l, a] v_a,
+//   R = g Z + (1 - g) e,  g = sigmoid(Wg2 GELU(Wg1 [Z ; e] + bg1) + bg2),
+//   XN = LayerNorm_1(R) of the first layer.
+// The rows of one slot differ only in E[x]: P[l] + gamma u is common to them
+// and cancels in the softmax over rows, so r[k, a] is the softmax over the
+// slot's rows of <E[x_k], w_a> / tau, six table values (three symbols, two
+// logits) that each workgroup computes once.  Each lane forms Z and e of its
+// token in registers, straight in the B-operand layout of the up MFMAs, and
+// again in the output layout for the blend: neither reaches HBM.  The whole
+// gate MLP (Wg1: d x 2d, Wg2: d x d) is DMA'd into LDS once per workgroup;
+// a workgroup then walks 256-token tiles.
+template <int D>
+struct EG3Smem {
+  static constexpr int DIN = 2 * D;
+  static constexpr int NCH = D / kM3FCH;                 // the gate's hidden width is d
+  static constexpr int RB1 = DIN * 2 + 16;
+  static constexpr int RB2 = kM3FCH * 2 + 16;
+  static constexpr size_t w1 = (size_t)kM3FCH * RB1;
+  static constexpr size_t w2 = (size_t)D * RB2;
+  static constexpr size_t w1a = (w1 + 1023) / 1024 * 1024;
+  static constexpr size_t w2a = (w2 + 1023) / 1024 * 1024;
+  static constexpr size_t buf = w1a + w2a;
+  // E[3], u, v[2], bg1, bg2, LN gain / bias, <E[x], w_a>: at the start of
+  // LDS, so that every vector address is a register base + an immediate
+  static constexpr size_t vec = ((size_t)11 * D * 4 + 8 * 4 + 1023) / 1024 * 1024;
+  static constexpr size_t bytes = vec + NCH * buf;
+  static_assert(bytes <= 160 * 1024, "LDS");
+};
+
+template <int D>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_embed_gate3(StepCtx c, EmbedW m, EmbedGateArgs a, int ntiles) {
+  using S = EG3Smem<D>;
+  constexpr int DIN = S::DIN, NCH = S::NCH, RB1 = S::RB1, RB2 = S::RB2;
+  constexpr int KS1 = DIN / 16, OBK = D / 32, KZ = D / 16;
+  constexpr int N1 = (int)(S::w1a / 1024), N2 = (int)(S::w2a / 1024), NB = NCH * (N1 + N2);
+  __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
+  char* wsm = smem + S::vec;                      // the weight chunks
+  float* sE = (float*)smem;                       // [3][D]
+  float* su = sE + 3 * D;
+  float* sv = su + D;                             // [2][D]
+  float* sbg1 = sv + 2 * D;
+  float* sbg2 = sbg1 + D;
+  float* slg = sbg2 + D;
+  float* slb = slg + D;
+  float* sEW = slb + D;                           // [3][2]: <E[x], w_a>
+
+  // small vectors first: their loads complete before the weight DMA is issued
+  for (int i = tid; i < 3 * D; i += 512) sE[i] = m.E[i];
+  for (int i = tid; i < D; i += 512) {
+    su[i] = m.u[i];
+    sv[i] = m.v[i];
+    sv[D + i] = m.v[D + i];
+    sbg1[i] = a.bg1[i];
+    sbg2[i] = a.bg2[i];
+    slg[i] = a.ln_g[i];
+    slb[i] = a.ln_b[i];
+  }
+  if (wave < 6) {
+    const int x = wave >> 1, al = wave & 1;
+    float acc = 0.f;
+    for (int i = lane; i < D; i += 64) acc = fmaf(m.E[x * D + i], m.W[al * D + i], acc);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) sEW[wave] = acc;
+  }
+  __syncthreads();
+  // the whole gate MLP -> LDS, 1 KB blocks spread over the waves; chunk ch
+  // holds hidden units 32 ch + sigma(j) of Wg1 (rows padded to RB1 bytes)
+  // and columns 32 ch .. + 32 of Wg2 (rows padded to RB2 bytes)
+  for (int u = wave; u < NB; u += 8) {
+    const int ch = u / (N1 + N2), v = u - ch * (N1 + N2);
+    const bool first = v < N1;
+    const int pos = (first ? v : v - N1) * 1024 + lane * 16;
+    const int rb = first ? RB1 : RB2;
+    const int j = pos / rb, o = pos - j * rb;
+    const bool data = o < rb - 16;                 // else a pad (copy something in bounds)
+    const bf16* src;
+    if (first) src = a.Wg1 + (long)(ch * kM3FCH + m3_sigma(data ? j : 0)) * DIN + (data ? o / 2 : 0);
+    else src = a.Wg2 + (long)(data ? j : 0) * D + ch * kM3FCH + (data ? o / 2 : 0);
+    char* dst = wsm + ch * S::buf + (first ? 0 : (int)S::w1a) + (pos - lane * 16);
+    if (pos < (first ? (int)S::w1 : (int)S::w2))
+      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+  }
+  const float inv_tau = 1.0f / c.tau;
+  bool weights_ready = false;
+
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    // the staged vectors are re-read from LDS in every tile, not held in
+    // registers across tiles
+    asm volatile("" ::: "memory");
+    // ---- this lane's token: its bin, row k, slot l, symbol, mask ratio and
+    // the demixing coefficients r[k, a] p[l, a]
+    const long tok = (long)tile * kM3BM + wave * 32 + l32;
+    const bool tv = tok < c.total_tokens;
+    const long tq = tv ? tok : c.total_tokens - 1;
+    int b = c.tile_bin[tile];
+    while (b + 1 < c.num_bins && tq >= c.bins[b + 1].tok_off) ++b;
+    const DevBin* bp = &c.bins[b];
+    const int K = bp->K, n = bp->n;
+    const int rel = (int)(tq - bp->tok_off), k = rel / n, l = rel - k * n;
+    const float gamma = c.gamma_override >= 0.f ? c.gamma_override : (float)bp->st->masked / (float)(K * n);
+    const uint8_t* Xc = bp->X + l;
+    const int x = min((int)Xc[k * n], kMask);
+    float mx0 = -INFINITY, mx1 = -INFINITY;
+    for (int kk = 0; kk < K; ++kk) {
+      const int xk = min((int)Xc[kk * n], kMask);
+      mx0 = fmaxf(mx0, sEW[2 * xk] * inv_tau);
+      mx1 = fmaxf(mx1, sEW[2 * xk + 1] * inv_tau);
+    }
+    float den0 = 0.f, den1 = 0.f;
+    for (int kk = 0; kk < K; ++kk) {
+      const int xk = min((int)Xc[kk * n], kMask);
+      den0 += expf(sEW[2 * xk] * inv_tau - mx0);
+      den1 += expf(sEW[2 * xk + 1] * inv_tau - mx1);
+    }
+    const int slot = bp->slot_off + l;
+    const float c0 = expf(sEW[2 * x] * inv_tau - mx0) / den0 * a.p[2 * slot];
+    const float c1 = expf(sEW[2 * x + 1] * inv_tau - mx1) / den1 * a.p[2 * slot + 1];
+    const float* Pl = m.P + (long)l * D;
+    const float* Ex = sE + x * D;
+
+    // ---- [Z ; e] in the B-operand layout: k-step s holds input features
+    // 16 s + 8 g2 + 0..7 (Z for s < d/16, e after)
+    bf16x8 xf[KS1];
+#pragma unroll
+    for (int s = 0; s < KZ; ++s) {
+      const int f = 16 * s + 8 * g2;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const f32x4 pq = *(const f32x4*)(Pl + f + 4 * h);
+        const f32x4 eq = *(const f32x4*)(Ex + f + 4 * h);
+        const f32x4 uq = *(const f32x4*)(su + f + 4 * h);
+        const f32x4 v0 = *(const f32x4*)(sv + f + 4 * h);
+        const f32x4 v1 = *(const f32x4*)(sv + D + f + 4 * h);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          xf[s][4 * h + i] = (bf16)((eq[i] + pq[i]) + gamma * uq[i]);
+          xf[KZ + s][4 * h + i] = (bf16)(c0 * v0[i] + c1 * v1[i]);
+        }
+      }
+      // finish these fragments before the next loads, so that the loaded
+      // vectors die here (bounds the registers in flight)
+      asm volatile("" : "+v"(xf[s]), "+v"(xf[KZ + s])::"memory");
+    }
+    if (!weights_ready) {
+      __syncthreads();                            // every wave's weight DMA complete
+      weights_ready = true;
+    }
+
+    // ---- gate MLP: up (2d -> d, GELU), down (d -> d), all weights in LDS
+    f32x16 acc2[OBK];
+#pragma unroll
+    for (int ob = 0; ob < OBK; ++ob)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc2[ob][r] = 0.f;
+#pragma unroll 1
+    for (int ch = 0; ch < NCH; ++ch) {
+      const char* s1 = wsm + ch * S::buf;
+      const char* s2 = s1 + S::w1a;
+      f32x16 acc1;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f32x4 bq = *(const f32x4*)&sbg1[ch * kM3FCH + 16 * (q >> 1) + 8 * g2 + 4 * (q & 1)];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc1[4 * q + i] = bq[i];
+      }
+#pragma unroll
+      for (int s = 0; s < KS1; ++s) {
+        const bf16x8 w = *(const bf16x8*)(s1 + l32 * RB1 + (2 * s + g2) * 16);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, xf[s], acc1, 0, 0, 0);
+      }
+      bf16x8 hf[2];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) hf[q >> 1][4 * (q & 1) + i] = (bf16)gelu_f(acc1[4 * q + i]);
+#pragma unroll
+      for (int ob = 0; ob < OBK; ++ob)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const bf16x8 w = *(const bf16x8*)(s2 + (32 * ob + l32) * RB2 + (2 * s + g2) * 16);
+          acc2[ob] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, hf[s], acc2[ob], 0, 0, 0);
+        }
+    }
+
+    // ---- blend R = g Z + (1 - g) e, then the first LayerNorm.  Lane l holds
+    // output features 32 ob + 8 q + 4 g2 + i of its token in register 4 q + i.
+    float* Rrow = a.R + tq * D;
+    float sum = 0.f;
+#pragma unroll
+    for (int ob = 0; ob < OBK; ++ob)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int f = 32 * ob + 8 * q + 4 * g2;
+        const f32x4 pq = *(const f32x4*)(Pl + f);
+        const f32x4 eq = *(const f32x4*)(Ex + f);
+        const f32x4 uq = *(const f32x4*)(su + f);
+        const f32x4 v0 = *(const f32x4*)(sv + f);
+        const f32x4 v1 = *(const f32x4*)(sv + D + f);
+        const f32x4 bq = *(const f32x4*)(sbg2 + f);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float z = (eq[i] + pq[i]) + gamma * uq[i];
+          const float e = c0 * v0[i] + c1 * v1[i];
+          const float gt = sigmoid_f(acc2[ob][4 * q + i] + bq[i]);
+          const float res = gt * z + (1.0f - gt) * e;
+          acc2[ob][4 * q + i] = res;
+          sum += res;
+        }
+        if (tv)
+          *(f32x4*)(Rrow + f) = f32x4{acc2[ob][4 * q], acc2[ob][4 * q + 1], acc2[ob][4 * q + 2], acc2[ob][4 * q + 3]};
+        asm volatile("" ::: "memory");            // bound the loads in flight
+      }
+    sum += __shfl_xor(sum, 32, 64);
+    const float mean = sum / (float)D;
+    float qv = 0.f;
+#pragma unroll
+    for (int ob = 0; ob < OBK; ++ob)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float dv = acc2[ob][r] - mean;
+        qv = fmaf(dv, dv, qv);
+      }
+    qv += __shfl_xor(qv, 32, 64);
+    const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
+    if (tv) {
+      bf16* xo = a.XN + tok * D;
+#pragma unroll
+      for (int ob = 0; ob < OBK; ++ob)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int f = 32 * ob + 8 * q + 4 * g2;
+          const f32x4 lg = *(const f32x4*)(slg + f);
+          const f32x4 lb = *(const f32x4*)(slb + f);
+          bf16x4 h;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) h[i] = (bf16)((acc2[ob][4 * q + i] - mean) * rstd * lg[i] + lb[i]);
+          *(bf16x4*)(xo + f) = h;
+        }
+    }
+  }
+  if (!weights_ready) __syncthreads();            // no tile: drain the DMA before the workgroup ends
+}
+
 }  // namespace
 
 // out = XN W^T + b (BF16), N a multiple of 32.
@@ -676,6 +927,22 @@ hipError_t launch_mlp3_bf16(const GemmArgs& g, const Mat& W1, const float* b1, c
   if (!mlp3_ok(g.N, F) || !g.ln_g || g.out_scale) return hipErrorInvalidValue;
   if (g.N == 128) return mlp3_t<128, 1, 8, 2, 4, true, 1>(g, W1.b16, b1, W2.b16, F, s);
   return mlp3_t<256, 1, 8, 2, 3, false>(g, W1.b16, b1, W2.b16, F, s);
+}
+
+bool embed_gate3_ok(int d) { return d == 128; }
+
+// Embedding, Module A and the first LayerNorm for the BF16 path (d = 128):
+// writes R (FP32) and XN (BF16) of every token of the batch.
+hipError_t launch_embed_gate3(const StepCtx& c, const EmbedW& m, const EmbedGateArgs& a, hipStream_t s) {
+  if (c.total_tokens == 0) return hipSuccess;
+  if (!embed_gate3_ok(m.d) || !c.tile_bin || !a.Wg1 || !a.Wg2) return hipErrorInvalidValue;
+  const int ntiles = (int)((c.total_tokens + kM3BM - 1) / kM3BM);
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return hipErrorInvalidValue;
+  const int grid = std::min(ntiles, std::max(ncu, 1));
+  hipLaunchKernelGGL((k_embed_gate3<128>), dim3(grid), dim3(512), 0, s, c, m, a, ntiles);
+  return hipGetLastError();
 }
 
 }  // namespace cider

@@ -218,12 +218,14 @@ def test_single_step_and_one_site_per_step():
         assert safe >= 1
 
 
-def test_batch_equals_alone_and_graph_equals_eager():
+@pytest.mark.parametrize("d,h", [(64, 4), (128, 8)])
+def test_batch_equals_alone_and_graph_equals_eager(d, h):
     """Mixed K and n in one batch give bit-identical results to each bin decoded
-    alone, with and without graph replay."""
+    alone, with and without graph replay (at d = 128 the BF16 path runs the
+    token-resident kernels, whose 256-token tiles straddle bins here)."""
     torch = torch_cuda()
     P = lib()
-    cfg = synth.ModelCfg(2, 64, 4, n_max=128)
+    cfg = synth.ModelCfg(2, d, h, n_max=128)
     wh, _ = weights_handle(cfg, seed=41)
     shapes = [(2, 32), (5, 64), (1, 128), (3, 32), (8, 64)]
     items = []
@@ -234,7 +236,7 @@ def test_batch_equals_alone_and_graph_equals_eager():
     for prec in ("fp32", "bf16"):
         for graph in (1, 0):
             opts = P.cider_opts_default(precision=prec_id(prec), use_graph=graph, remask=1)
-            say(f"batch vs alone {prec} graph={graph}")
+            say(f"batch vs alone d={d} {prec} graph={graph}")
             outs = [torch.zeros(K, n, dtype=torch.uint8, device="cuda") for K, n, *_ in items]
             lgs = [torch.zeros(K, n, 2, dtype=torch.float32, device="cuda") for K, n, *_ in items]
             P.cider_decode_batch([{"y": y, "sigma2": s2, "code": ch, "K": K, "n": n, "out_symbols": o,
