@@ -138,6 +138,31 @@ def test_module_a_responsibilities_sum_to_one_and_uniform_for_equal_rows():
     np.testing.assert_allclose(parts1["e"][0], p @ w["v"], rtol=1e-14)
 
 
+def test_responsibilities_depend_only_on_the_column_symbols():
+    """The rows of a slot share P[l] + gamma u, which cancels in the softmax
+    over rows: r[k, l, a] is the softmax over k of <E[X[k, l]], w_a> / tau
+    whatever P and gamma are (the identity the fused GPU kernel computes r
+    from, checked here on the oracle's own Module A)."""
+    cfg = synth.ModelCfg(1, 16, 2, n_max=8)
+    w = _w(cfg, seed=12)
+    rng = np.random.default_rng(4)
+    X = rng.integers(0, 3, size=(5, 7)).astype(np.uint8)
+    _, p = evidence(rng.normal(0, 2, size=7), 0.5, 5)
+    tau = 0.7
+    _, a = D.module_a(D.embed(X, 0.3, w), p, w, tau)
+    w2 = dict(w)
+    w2["P"] = rng.normal(0, 1.0, size=w["P"].shape)
+    w2["u"] = rng.normal(0, 1.0, size=w["u"].shape)
+    _, b = D.module_a(D.embed(X, 0.9, w2), p, w2, tau)
+    np.testing.assert_allclose(a["r"], b["r"], rtol=1e-12)
+    table = w["E"] @ w["W"].T                            # [3 symbols][2 logits]
+    lt = table[X] / tau                                  # [K][n][2]
+    r = np.exp(lt - lt.max(axis=0)) / np.exp(lt - lt.max(axis=0)).sum(axis=0)
+    np.testing.assert_allclose(a["r"], r, rtol=1e-12)
+    # and the intermediate logits themselves do depend on P and gamma
+    assert np.max(np.abs(a["lbar"] - b["lbar"])) > 1e-3
+
+
 def test_denoiser_row_permutation_equivariance():
     cfg = synth.ModelCfg(2, 32, 4, n_max=32)
     w = _w(cfg, bias_std=0.02, ln_std=0.05)
