@@ -41,17 +41,19 @@ constexpr int kM3FCH = 32;                        // hidden units per chunk
 
 constexpr int kM3MaxF = 2048;                     // hidden width the b1 staging holds
 
-template <int D, int NBUF = 2>
+template <int D, int NBUF = 2, int MAXF = kM3MaxF>
 struct M3Smem {
   static constexpr int RB1 = D * 2 + 16;          // bytes per stored W1 chunk row (16 of them pad)
   static constexpr int RB2 = kM3FCH * 2 + 16;     // bytes per stored W2 chunk row
   static constexpr size_t w1 = (size_t)kM3FCH * RB1;
   static constexpr size_t w2 = (size_t)D * RB2;
-  static constexpr size_t w1a = (w1 + 1023) / 1024 * 1024;   // whole DMA blocks
-  static constexpr size_t w2a = (w2 + 1023) / 1024 * 1024;
+  // regions on 16-byte boundaries (the DMA's LDS alignment); a region's last
+  // DMA block masks the lanes past its end
+  static constexpr size_t w1a = (w1 + 15) / 16 * 16;
+  static constexpr size_t w2a = (w2 + 15) / 16 * 16;
   static constexpr size_t buf = w1a + w2a;
   static constexpr size_t vec = (size_t)5 * D * 4;           // epilogue vectors
-  static constexpr size_t bytes = NBUF * buf + kM3MaxF * 4 + vec;   // + all of b1
+  static constexpr size_t bytes = NBUF * buf + MAXF * 4 + vec;   // + all of b1
   static_assert(bytes <= 160 * 1024, "LDS");
 };
 
@@ -231,25 +233,25 @@ __device__ __forceinline__ void m3_residual_epilogue(f32x16 (&acc2)[D / 32][TB],
   }
 }
 
-template <int D, int TB, int NW, int WPE, int NBUF, bool PIPE, int SCHED, bool PROJ>
+template <int D, int TB, int NW, int WPE, int NBUF, bool PIPE, int SCHED, int MAXF, bool PROJ>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void k_mlp3(GemmArgs g, const bf16* __restrict__ W1, const float* __restrict__ b1, const bf16* __restrict__ W2,
             int F) {
-  using S = M3Smem<D, NBUF>;
-  static_assert(NW * TB * 32 == kM3BM, "256 tokens per workgroup");
+  using S = M3Smem<D, NBUF, MAXF>;
+  constexpr int BM = NW * TB * 32;                // tokens per workgroup
   constexpr int NTHR = NW * 64;
   constexpr int RB1 = S::RB1, RB2 = S::RB2;
   constexpr int KS1 = D / 16;                     // up-projection k-steps
   constexpr int OBK = D / 32;                     // 32-row output blocks
-  constexpr int N1 = (int)(S::w1a / 1024), N2 = (int)(S::w2a / 1024);   // DMA blocks per chunk
+  constexpr int N1 = (int)((S::w1 + 1023) / 1024), N2 = (int)((S::w2 + 1023) / 1024);   // DMA blocks per chunk
   constexpr int NPW = (N1 + N2 + NW - 1) / NW;                        // per wave
   __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
-  const long tok0 = (long)blockIdx.x * kM3BM + wave * (32 * TB) + l32;   // token of block t: tok0 + 32 t
+  const long tok0 = (long)blockIdx.x * BM + wave * (32 * TB) + l32;   // token of block t: tok0 + 32 t
   const int nch = F / kM3FCH;
   const bf16* __restrict__ A = (const bf16*)g.A;
   float* sb1 = (float*)(smem + NBUF * S::buf);
-  float* sv = sb1 + kM3MaxF;
+  float* sv = sb1 + MAXF;
   // DMA blocks this wave issues per chunk (uniform over the wave)
   const int nw = (N1 + N2) / NW + (wave < (N1 + N2) % NW ? 1 : 0);
 
@@ -445,11 +447,13 @@ void k_mlp3(GemmArgs g, const bf16* __restrict__ W1, const float* __restrict__ b
   m3_residual_epilogue<D, TB, PROJ>(acc2, tok0, g, g2, sv);
 }
 
-template <int D, int TB, int NW, int WPE, int NBUF, bool PIPE, int SCHED = 0>
+template <int D, int TB, int NW, int WPE, int NBUF, bool PIPE, int SCHED = 0, int MAXF = kM3MaxF>
 hipError_t mlp3_t(const GemmArgs& g, const bf16* W1, const float* b1, const bf16* W2, int F, hipStream_t s) {
-  dim3 grid((unsigned)((g.M + kM3BM - 1) / kM3BM)), block(NW * 64);
-  if (g.proj_out) hipLaunchKernelGGL((k_mlp3<D, TB, NW, WPE, NBUF, PIPE, SCHED, true>), grid, block, 0, s, g, W1, b1, W2, F);
-  else hipLaunchKernelGGL((k_mlp3<D, TB, NW, WPE, NBUF, PIPE, SCHED, false>), grid, block, 0, s, g, W1, b1, W2, F);
+  if (F > MAXF) return hipErrorInvalidValue;
+  constexpr int BM = NW * TB * 32;
+  dim3 grid((unsigned)((g.M + BM - 1) / BM)), block(NW * 64);
+  if (g.proj_out) hipLaunchKernelGGL((k_mlp3<D, TB, NW, WPE, NBUF, PIPE, SCHED, MAXF, true>), grid, block, 0, s, g, W1, b1, W2, F);
+  else hipLaunchKernelGGL((k_mlp3<D, TB, NW, WPE, NBUF, PIPE, SCHED, MAXF, false>), grid, block, 0, s, g, W1, b1, W2, F);
   return hipGetLastError();
 }
 
@@ -894,7 +898,7 @@ hipError_t launch_proj3_bf16(const GemmArgs& g, const Mat& W, hipStream_t s, boo
     else hipLaunchKernelGGL((k_proj3<KD, CHB, WPE, false>), grid, block, 0, s, g, W.b16);          \
     return hipGetLastError();                                                                      \
   }
-  CIDER_P3(128, 4, 2) CIDER_P3(128, 1, 4) CIDER_P3(256, 4, 2) CIDER_P3(256, 1, 2) CIDER_P3(512, 2, 2)
+  CIDER_P3(128, 4, 2) CIDER_P3(128, 1, 4) CIDER_P3(256, 2, 4) CIDER_P3(256, 1, 4) CIDER_P3(512, 2, 2)
   CIDER_P3(512, 1, 2)
 #undef CIDER_P3
   return hipErrorInvalidValue;
@@ -925,7 +929,11 @@ bool mlp3_ok(int d, int F) { return (d == 128 || d == 256) && F % kM3FCH == 0 &&
 hipError_t launch_mlp3_bf16(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s) {
   if (g.M == 0) return hipSuccess;
   if (!mlp3_ok(g.N, F) || !g.ln_g || g.out_scale) return hipErrorInvalidValue;
-  if (g.N == 128) return mlp3_t<128, 1, 8, 2, 4, true, 1>(g, W1.b16, b1, W2.b16, F, s);
+  if (g.N == 128) {
+    // 128 tokens per workgroup, two workgroups per CU when the hidden width allows
+    if (F <= 512) return mlp3_t<128, 1, 4, 2, 4, true, 1, 512>(g, W1.b16, b1, W2.b16, F, s);
+    return mlp3_t<128, 1, 8, 2, 4, true, 1>(g, W1.b16, b1, W2.b16, F, s);
+  }
   return mlp3_t<256, 1, 8, 2, 3, false>(g, W1.b16, b1, W2.b16, F, s);
 }
 
