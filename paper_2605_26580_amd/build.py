@@ -23,6 +23,9 @@ SOURCES = ["engine.cpp", "kernels_misc.hip", "kernels_gemm.hip", "kernels_attn.h
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-x", "hip", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs: the softmax and epilogue VALU work
+    # then reads them directly instead of copying each out of the AGPRs
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-Wno-unused-result", "-I" + INCLUDE, "-I" + CSRC,
 ]
 
