@@ -69,9 +69,11 @@ struct StepCtx {
   const int* row_bin;       // device [total_rows]
   const int* ugrp;          // device [total_ugrp][2]: (bin, first column) of each user-attention block
   const int* tile_bin;      // device [ceil(T / 256)]: bin holding token 256 i
+  const int* ugrp32;        // device [total_ugrp32][2]: (bin, first column) of each 32-slot user group
   int total_slots;
   int total_rows;
   int total_ugrp;
+  int total_ugrp32;
   long total_tokens;
   int max_n;                // largest n in the batch
   int schedule, remask, max_rounds, final_argmax;
@@ -176,6 +178,9 @@ hipError_t launch_mlp3_bf16(const GemmArgs& g, const Mat& W1, const float* b1, c
 bool attn_block_ok(int d, int heads, int max_n, bool user);
 hipError_t launch_attn_block(const StepCtx& c, bool user, void* XN, const DevLayer& L, const float* ln_g,
                              const float* ln_b, float* R, int d, int heads, hipStream_t s);
+bool user_qkv_attn_ok(int d, int heads);
+hipError_t launch_user_qkv_attn(const StepCtx& c, const void* XN, const Mat& Wqkv, const float* bqkv, void* O,
+                                int d, int heads, hipStream_t s);
 // Columns of one K-row bin that one user-attention block covers.
 inline int ugrp_cols(int K) { return (kBlkUserSlots / 16) * (16 / K); }
 // Embedding + Module A + the first LayerNorm in one kernel (BF16, d = 128).

@@ -193,7 +193,7 @@ struct Layout {
   int num_bins = 0;
   long total_tokens = 0;
   int total_slots = 0, total_rows = 0, max_n = 0, total_ugrp = 0;
-  size_t off_ugrp = 0, off_tile = 0, off_R, off_E, off_ZE, off_H1, off_QKV, off_O, off_HID, off_lbar, off_logits, off_p, off_S,
+  size_t off_ugrp = 0, off_ugrp32 = 0, off_tile = 0, off_R, off_E, off_ZE, off_H1, off_QKV, off_O, off_HID, off_lbar, off_logits, off_p, off_S,
       off_bins, off_state, off_slot, off_row, off_X, off_XN, off_XN8, off_xscale, total;
 };
 
@@ -227,6 +227,7 @@ Layout plan_layout(const cider_model_cfg& cfg, int num_bins, long T, int slots, 
   L.off_row = take((size_t)rows * 4);
   L.off_ugrp = take(((size_t)slots + num_bins) * 2 * 4);   // user-attention groups, at most one per column
   L.off_tile = take(((size_t)T / 256 + 1) * 4);              // bin of the first token of each 256-token tile
+  L.off_ugrp32 = take(((size_t)slots + num_bins) * 2 * 4);   // 32-slot user groups (at least two columns each)
   L.off_X = take(T);
   L.total = o;
   return L;
@@ -456,11 +457,16 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
     if (blk_user) {
       TIMED("attn_block_user", launch_attn_block(c, true, k.XN, L, L.ln3_g, L.ln3_b, k.R, d, m.heads, s));
     } else {
-      g = GemmArgs{}; g.M = T;
-      g.N = 3 * d; g.Kd = d; g.A = k.XN; g.bias = L.bqkv_u; g.out = k.QKV;
-      TIMED("gemm_qkv_user", qkv(g, L.Wqkv_u));
-      if (prec == kF32) TIMED("attn_user", launch_user_attn(c, prec, k.QKV, k.O, d, m.heads, s));
-      else TIMED("attn_user", launch_user_attn_mfma(c, k.QKV, k.O, d, m.heads, s));
+      if (prec == kBF16 && r.use_blocks && user_qkv_attn_ok(d, m.heads)) {
+        // BF16, head width 32: QKV projection and user attention in one kernel
+        TIMED("qkv_attn_user", launch_user_qkv_attn(c, k.XN, L.Wqkv_u, L.bqkv_u, k.O, d, m.heads, s));
+      } else {
+        g = GemmArgs{}; g.M = T;
+        g.N = 3 * d; g.Kd = d; g.A = k.XN; g.bias = L.bqkv_u; g.out = k.QKV;
+        TIMED("gemm_qkv_user", qkv(g, L.Wqkv_u));
+        if (prec == kF32) TIMED("attn_user", launch_user_attn(c, prec, k.QKV, k.O, d, m.heads, s));
+        else TIMED("attn_user", launch_user_attn_mfma(c, k.QKV, k.O, d, m.heads, s));
+      }
       g = GemmArgs{}; g.M = T;
       g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_u; g.R = k.R;
       next_ln(g, L.ln3_g, L.ln3_b);
@@ -666,10 +672,14 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
   char* base = nullptr;
   int rc = ensure_ws(w, o, L.total, &base);
   if (rc) return rc;
-  int ngrp = 0;
-  for (const BinIn& b : bins) ngrp += (b.n + ugrp_cols(b.K) - 1) / ugrp_cols(b.K);
+  int ngrp = 0, ngrp32 = 0;
+  for (const BinIn& b : bins) {
+    ngrp += (b.n + ugrp_cols(b.K) - 1) / ugrp_cols(b.K);
+    ngrp32 += (b.n + 32 / b.K - 1) / (32 / b.K);
+  }
   const int ntile = (int)((T + 255) / 256);
-  size_t meta = B * sizeof(DevBin) + (size_t)(slots + rows) * 4 + (size_t)ngrp * 2 * 4 + (size_t)ntile * 4;
+  size_t meta = B * sizeof(DevBin) + (size_t)(slots + rows) * 4 + (size_t)ngrp * 2 * 4 + (size_t)ntile * 4 +
+                (size_t)ngrp32 * 2 * 4;
   rc = ensure_pinned(w, meta);
   if (rc) return rc;
   DevBin* hb = (DevBin*)w->pinned;
@@ -677,6 +687,8 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
   int* hrow = hslot + slots;
   int* hgrp = hrow + rows;
   int* htile = hgrp + 2 * (size_t)ngrp;
+  int* hgrp32 = htile + ntile;
+  int go32 = 0;
   int go = 0;
   long tok = 0;
   int so = 0, ro = 0;
@@ -705,6 +717,11 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
       ++go;
     }
     for (long t0 = (tok + 255) / 256 * 256; t0 < tok + (long)b.K * b.n; t0 += 256) htile[t0 / 256] = i;
+    for (int l0 = 0; l0 < b.n; l0 += 32 / b.K) {
+      hgrp32[2 * go32] = i;
+      hgrp32[2 * go32 + 1] = l0;
+      ++go32;
+    }
     tok += (long)b.K * b.n;
     so += b.n;
     ro += b.K;
@@ -715,6 +732,7 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
   HIPCHK(hipMemcpyAsync(base + L.off_row, hrow, (size_t)rows * 4, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(base + L.off_ugrp, hgrp, (size_t)ngrp * 2 * 4, hipMemcpyHostToDevice, s));
   if (ntile) HIPCHK(hipMemcpyAsync(base + L.off_tile, htile, (size_t)ntile * 4, hipMemcpyHostToDevice, s));
+  if (ngrp32) HIPCHK(hipMemcpyAsync(base + L.off_ugrp32, hgrp32, (size_t)ngrp32 * 2 * 4, hipMemcpyHostToDevice, s));
   HIPCHK(hipEventRecord(w->meta_done, s));
 
   StepCtx& c = r->ctx;
@@ -725,6 +743,8 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
   c.row_bin = (const int*)(base + L.off_row);
   c.ugrp = (const int*)(base + L.off_ugrp);
   c.tile_bin = (const int*)(base + L.off_tile);
+  c.ugrp32 = (const int*)(base + L.off_ugrp32);
+  c.total_ugrp32 = ngrp32;
   c.total_slots = slots;
   c.total_rows = rows;
   c.total_ugrp = ngrp;

@@ -634,6 +634,191 @@ void k_oproj3(GemmArgs g, const bf16* __restrict__ W) {
 }
 
 // ---------------------------------------------------------------------------
+// User attention with its QKV projection, for the BF16 path at head width 32
+// (d = 256): QKV = XN Wqkv^T + b, then for every head the softmax attention
+// of each token over the K tokens of its slot; O is written in BF16 and the
+// output projection, residual and LayerNorm follow in k_oproj3.  A wave owns
+// one group of floor(32/K) columns x K rows of one bin (slot s of the group
+// is row s % K of column s / K), so every key a query needs is among the
+// wave's own 32 tokens.  The wave keeps the group's XN rows in registers (B
+// operand of v_mfma_f32_32x32x16_bf16) and walks the heads; weight chunk h
+// holds the Q, K and V rows of head h (96 rows, DMA'd into LDS, double
+// buffered).  Per head, in registers:
+//   S^T = K Q^T   two MFMAs: the projection's output registers are the
+//                 k fragments of both operands, with the same permutation of
+//                 the head dimension on both sides;
+//   softmax       exp2, masked to the query's column; a lane holds 16 keys
+//                 of its query, lane l ^ 32 the other 16;
+//   O^T = V^T P^T two MFMAs; V passes through a per-wave LDS tile to become
+//                 the A operand, read with the keys in P's register order.
+// Only XN is read and only O is written: 4d bytes per token, against 16d for
+// a separate projection and attention kernel.
+template <int D>
+struct UQSmem {
+  static constexpr int RB = D * 2 + 16;             // bytes per stored weight row (16 of them pad)
+  static constexpr int CR = 96;                      // Q, K and V rows of one head
+  static constexpr size_t w = (size_t)CR * RB;
+  static constexpr size_t wa = (w + 15) / 16 * 16;
+  static constexpr int LDT = 40;                     // V^T tile row: 32 keys + pad (bf16)
+  static constexpr size_t vt = (size_t)8 * 32 * LDT * 2;
+  static constexpr size_t bias = (size_t)3 * D * 4;
+  static constexpr size_t bytes = 2 * wa + vt + bias;
+  static_assert(bytes <= 160 * 1024, "LDS");
+};
+
+template <int D>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_user_qkv_attn(StepCtx c, const bf16* __restrict__ XN, const bf16* __restrict__ W,
+                     const float* __restrict__ bqkv, bf16* __restrict__ O) {
+  using S = UQSmem<D>;
+  constexpr int RB = S::RB, LDT = S::LDT, KS = D / 16, HEADS = D / 32;
+  constexpr int NB = (int)((S::w + 1023) / 1024), NPW = (NB + 7) / 8;
+  static_assert(HEADS % 4 == 0, "heads in batches of four");
+  __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
+  bf16* sVt = (bf16*)(smem + 2 * S::wa);
+  float* sbias = (float*)(smem + 2 * S::wa + S::vt);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
+
+  // ---- this lane's slot of the wave's group
+  const int gi = blockIdx.x * 8 + wave;
+  int tok = -1, K = 1;
+  if (gi < c.total_ugrp32) {
+    const int bi = c.ugrp32[2 * gi], c0 = c.ugrp32[2 * gi + 1];
+    const DevBin& b = c.bins[bi];
+    K = b.K;
+    const int C = 32 / K, cl = l32 / K, k = l32 - cl * K;
+    if (l32 < C * K && c0 + cl < b.n) tok = b.tok_off + k * b.n + c0 + cl;
+  }
+  // keys this lane's query may attend to: register r of S^T holds key slot
+  // 8(r/4) + 4 g2 + r%4; valid slot in the query's column
+  const unsigned long long vmask = __ballot(tok >= 0);
+  unsigned okbits = 0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int kr = 8 * (r >> 2) + 4 * g2 + (r & 3);
+    if (((vmask >> kr) & 1ull) && kr / K == l32 / K) okbits |= 1u << r;
+  }
+
+  auto dma = [&](int h, int buf) {
+    char* base = smem + buf * S::wa;
+#pragma unroll
+    for (int k = 0; k < NPW; ++k) {
+      const int u = wave + k * 8;                   // uniform over the wave
+      if (u >= NB) break;
+      const int pos = u * 1024 + lane * 16, j = pos / RB, o = pos - j * RB;
+      const bool data = o < RB - 16;                 // else a pad (copy something in bounds)
+      const int jj = data ? j : 0;
+      const bf16* src = W + (long)((jj >> 5) * D + h * 32 + (jj & 31)) * D + (data ? o / 2 : 0);
+      if (pos < (int)S::w)
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(base + u * 1024), 16, 0, 0);
+    }
+  };
+  for (int i = tid; i < 3 * D; i += 512) sbias[i] = bqkv[i];
+  bf16x8 xf[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s)
+    xf[s] = tok >= 0 ? *(const bf16x8*)(XN + (long)tok * D + 16 * s + 8 * g2) : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+  dma(0, 0);
+  __syncthreads();                                  // bias staged, chunk 0 in LDS
+
+  const float scale = 1.4426950408889634f / sqrtf(32.0f);
+  bf16* tvt = sVt + wave * 32 * LDT;
+  // O of HB heads at a time; each batch is stored right after a closing
+  // barrier, so its stores overlap the next head's work and are complete by
+  // the barrier after it
+  constexpr int HB = 4;
+  bf16x4 ob[HB][4];
+  bf16* orow = O + (long)(tok >= 0 ? tok : 0) * D;
+#pragma unroll
+  for (int h = 0; h < HEADS; ++h) {
+    // buffer (h + 1) & 1 was last read in iteration h - 1, before its closing barrier
+    if (h + 1 < HEADS) dma(h + 1, (h + 1) & 1);
+    const char* sw = smem + (h & 1) * S::wa;
+    f32x16 acc[3];
+#pragma unroll
+    for (int cb = 0; cb < 3; ++cb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[cb][r] = 0.f;
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int cb = 0; cb < 3; ++cb) {
+        const bf16x8 a = *(const bf16x8*)(sw + (32 * cb + l32) * RB + (2 * s + g2) * 16);
+        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, xf[s], acc[cb], 0, 0, 0);
+      }
+    // + bias, BF16; register r holds feature 8(r/4) + 4 g2 + r%4 of the head
+    bf16x8 qf[2], kf[2];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int f = h * 32 + 8 * q + 4 * g2;
+      const f32x4 bq = *(const f32x4*)&sbias[f];
+      const f32x4 bk = *(const f32x4*)&sbias[D + f];
+      const f32x4 bv = *(const f32x4*)&sbias[2 * D + f];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 4 * q + i;
+        qf[r >> 3][r & 7] = (bf16)(acc[0][r] + bq[i]);
+        kf[r >> 3][r & 7] = (bf16)(acc[1][r] + bk[i]);
+        tvt[(8 * q + 4 * g2 + i) * LDT + l32] = (bf16)(acc[2][r] + bv[i]);
+      }
+    }
+    // S^T = K Q^T: lane l holds query l%32, register r key slot 8(r/4) + 4 g2 + r%4
+    f32x16 st;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) st[r] = 0.f;
+    st = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kf[0], qf[0], st, 0, 0, 0);
+    st = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kf[1], qf[1], st, 0, 0, 0);
+    float mx = -INFINITY;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      st[r] = ((okbits >> r) & 1u) ? st[r] : -INFINITY;
+      mx = fmaxf(mx, st[r]);
+    }
+    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+    // a padding query has no valid key (mx = -inf): p = 0 for it
+    const float mxs = mx == -INFINITY ? 0.f : -mx * scale;
+    float ps = 0.f;
+    bf16x8 pf[2];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float p = __builtin_amdgcn_exp2f(fmaf(st[r], scale, mxs));
+      ps += p;
+      pf[r >> 3][r & 7] = (bf16)p;
+    }
+    ps += __shfl_xor(ps, 32, 64);
+    // V^T fragments in P's key order: element j of k-step s is key
+    // 16 s + 4 g2 + j (j < 4) or 16 s + 8 + 4 g2 + j - 4
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // this wave's V^T writes are in LDS
+    bf16x8 vf[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const bf16x4 a0 = *(const bf16x4*)&tvt[l32 * LDT + 16 * s + 4 * g2];
+      const bf16x4 a1 = *(const bf16x4*)&tvt[l32 * LDT + 16 * s + 8 + 4 * g2];
+      vf[s] = bf16x8{a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+    }
+    f32x16 o;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) o[r] = 0.f;
+    o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vf[0], pf[0], o, 0, 0, 0);
+    o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vf[1], pf[1], o, 0, 0, 0);
+    const float inv = ps > 0.f ? 1.0f / ps : 0.f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      ob[h % HB][q] = bf16x4{(bf16)(o[4 * q] * inv), (bf16)(o[4 * q + 1] * inv), (bf16)(o[4 * q + 2] * inv),
+                             (bf16)(o[4 * q + 3] * inv)};
+    // chunk h + 1 complete in every wave: this wave's memory operations in
+    // flight are its part of that DMA and the O stores of the previous batch
+    if (h + 1 < HEADS) m3_wait_barrier(0);
+    if (h % HB == HB - 1 && tok >= 0) {
+#pragma unroll
+      for (int hh = 0; hh < HB; ++hh)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *(bf16x4*)(orow + (h - HB + 1 + hh) * 32 + 8 * q + 4 * g2) = ob[hh][q];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Module A for the BF16 path, from the symbol grid to the first LayerNorm in
 // one token-resident kernel (method section, Module A; Appendix, one-step
 // algorithm):
@@ -935,6 +1120,19 @@ hipError_t launch_mlp3_bf16(const GemmArgs& g, const Mat& W1, const float* b1, c
     return mlp3_t<128, 1, 8, 2, 4, true, 1>(g, W1.b16, b1, W2.b16, F, s);
   }
   return mlp3_t<256, 1, 8, 2, 3, false>(g, W1.b16, b1, W2.b16, F, s);
+}
+
+bool user_qkv_attn_ok(int d, int heads) { return d == 256 && heads * 32 == d; }
+
+// QKV projection + user attention for BF16 at d = 256, head width 32: O (BF16
+// [T][d]) from XN; groups from c.ugrp32.
+hipError_t launch_user_qkv_attn(const StepCtx& c, const void* XN, const Mat& Wqkv, const float* bqkv, void* O,
+                                int d, int heads, hipStream_t s) {
+  if (c.total_ugrp32 == 0) return hipSuccess;
+  if (!user_qkv_attn_ok(d, heads) || !c.ugrp32 || !Wqkv.b16) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_user_qkv_attn<256>), dim3((c.total_ugrp32 + 7) / 8), dim3(512), 0, s, c, (const bf16*)XN,
+                     Wqkv.b16, bqkv, (bf16*)O);
+  return hipGetLastError();
 }
 
 bool embed_gate3_ok(int d) { return d == 128; }

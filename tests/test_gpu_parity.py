@@ -62,6 +62,11 @@ CASES = [
     (7, 36, 1, 128, 8),
     (9, 20, 1, 64, 2),
     (16, 24, 1, 64, 4),
+    # 32-slot user groups of the d = 256 path: floor(32/K) columns of K rows,
+    # padding slots at K = 3, 7 and a part-filled last group at n = 100, 40
+    (3, 100, 1, 256, 8),
+    (7, 40, 1, 256, 8),
+    (16, 24, 1, 256, 8),
 ]
 
 
@@ -333,12 +338,15 @@ def test_every_gemm_tile_teacher_forced(K, n, L, d, h):
 
 
 @pytest.mark.parametrize("K,n,L,d,h", [(4, 128, 2, 128, 8), (3, 44, 2, 64, 4), (7, 36, 1, 192, 6),
-                                       (5, 64, 1, 128, 2), (1, 100, 1, 64, 4)])
+                                       (5, 64, 1, 128, 2), (1, 100, 1, 64, 4), (8, 64, 2, 256, 8),
+                                       (5, 72, 1, 256, 8)])
 def test_fused_blocks_match_separate_kernels(K, n, L, d, h):
-    """The fused attention block (QKV, attention, output projection, residual
-    and LayerNorm in one kernel) rounds at the same points as the separate
-    GEMM / attention kernels, so the two BF16 paths agree far inside the BF16
-    tolerance; both are also held to that tolerance against the oracle."""
+    """The fused kernels (attention blocks with QKV, attention, output
+    projection, residual and LayerNorm; at d = 256 the QKV projection with the
+    user attention; the embedding with Module A) round at the same points as
+    the separate GEMM / attention kernels, so the two BF16 paths agree far
+    inside the BF16 tolerance; both are also held to that tolerance against
+    the oracle."""
     torch = torch_cuda()
     P = lib()
     cfg = synth.ModelCfg(L, d, h, n_max=max(n, 64))
