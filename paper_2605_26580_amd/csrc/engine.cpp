@@ -454,7 +454,10 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
       TIMED("gemm_o_row", oproj(g, L.Wo_r));
     }
     if (!fused_ln) TIMED("layernorm", ln(L.ln2_g, L.ln2_b));
-    if (blk_user) {
+    if (prec == kBF16 && r.use_blocks && user_block_tr_ok(d, m.heads)) {
+      // BF16, head width 16: the user-attention sublayer token-resident (whole-column groups per wave)
+      TIMED("user_block", launch_user_block_tr(c, k.XN, L, L.ln3_g, L.ln3_b, k.R, d, m.heads, s));
+    } else if (blk_user) {
       TIMED("attn_block_user", launch_attn_block(c, true, k.XN, L, L.ln3_g, L.ln3_b, k.R, d, m.heads, s));
     } else {
       if (prec == kBF16 && r.use_blocks && user_qkv_attn_ok(d, m.heads)) {

@@ -819,6 +819,196 @@ void k_user_qkv_attn(StepCtx c, const bf16* __restrict__ XN, const bf16* __restr
 }
 
 // ---------------------------------------------------------------------------
+// The whole user-attention sublayer for the BF16 path at head width 16
+// (d = 128): QKV projection, softmax attention of each token over the K
+// tokens of its slot, output projection, bias, residual and the next
+// LayerNorm, token-resident.  A wave owns one 32-slot group of whole columns
+// as in k_user_qkv_attn; the weights go through LDS one head pair at a time:
+// the pair's Q, K and V rows (three 32-row MFMA blocks, rows 16 e + j of a
+// block = feature j of head 2p + e) and the pair's 32 columns of W_o.  Per
+// head the score MFMA takes the 16 features of that head (registers
+// 8e .. 8e + 7 of the Q and K blocks).  V is projected transposed (the same
+// MFMA with its operands swapped: lane l then holds feature l%32 for 16
+// keys, in exactly the key order of P's registers), so it is the A operand
+// of O^T = V^T P^T as it stands; that MFMA takes both heads' V rows and the
+// head keeps its half.  The pair's O block feeds the output projection at
+// once (acc2 += W_o[:, pair] O_pair), so O never leaves registers.  Four
+// waves (128 tokens) per workgroup in 74 KB of LDS: two workgroups per CU.
+// HBM traffic per token: XN and R in, R and XN out.
+template <int D>
+struct UBSmem {
+  static constexpr int RB1 = D * 2 + 16;               // bytes per stored Wqkv row
+  static constexpr int RB2 = 32 * 2 + 16;              // bytes per stored W_o row (the pair's 32 columns)
+  static constexpr size_t w1 = (size_t)96 * RB1;
+  static constexpr size_t w2 = (size_t)D * RB2;
+  static constexpr size_t w1a = (w1 + 15) / 16 * 16;
+  static constexpr size_t w2a = (w2 + 15) / 16 * 16;
+  static constexpr size_t buf = w1a + w2a;
+  static constexpr size_t vec = (size_t)8 * D * 4;     // bqkv [3D], then the epilogue vectors [5D]
+  static constexpr size_t bytes = 2 * buf + vec;
+  static_assert(bytes <= 80 * 1024, "two workgroups per CU");
+};
+
+template <int D, int NW>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_user_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const float* __restrict__ bqkv,
+                     const bf16* __restrict__ Wo) {
+  using S = UBSmem<D>;
+  constexpr int RB1 = S::RB1, RB2 = S::RB2, KS = D / 16, NP = D / 32, OBK = D / 32, NTHR = NW * 64;
+  constexpr int N1 = (int)((S::w1 + 1023) / 1024), N2 = (int)((S::w2 + 1023) / 1024), NPW = (N1 + N2 + NW - 1) / NW;
+  __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
+  float* sbias = (float*)(smem + 2 * S::buf);
+  float* sv = sbias + 3 * D;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
+
+  // ---- this lane's slot of the wave's group
+  const int gi = blockIdx.x * NW + wave;
+  int tok = -1, K = 1;
+  if (gi < c.total_ugrp32) {
+    const int bi = c.ugrp32[2 * gi], c0 = c.ugrp32[2 * gi + 1];
+    const DevBin& b = c.bins[bi];
+    K = b.K;
+    const int C = 32 / K, cl = l32 / K, k = l32 - cl * K;
+    if (l32 < C * K && c0 + cl < b.n) tok = b.tok_off + k * b.n + c0 + cl;
+  }
+  const unsigned long long vmask = __ballot(tok >= 0);
+  unsigned okbits = 0;                               // register r of S^T: key slot 8(r/4) + 4 g2 + r%4
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int kr = 8 * (r >> 2) + 4 * g2 + (r & 3);
+    if (((vmask >> kr) & 1ull) && kr / K == l32 / K) okbits |= 1u << r;
+  }
+
+  // head pair p -> LDS: Wqkv rows (j / 32) D + 32 p + j % 32, W_o columns 32 p .. + 32
+  auto dma = [&](int p, int buf) {
+    char* base = smem + buf * S::buf;
+#pragma unroll
+    for (int k = 0; k < NPW; ++k) {
+      const int u = wave + k * NW;                    // uniform over the wave
+      if (u >= N1 + N2) break;
+      const bool first = u < N1;
+      const int pos = (first ? u : u - N1) * 1024 + lane * 16;
+      const int rb = first ? RB1 : RB2;
+      const int j = pos / rb, o = pos - j * rb;
+      const bool data = o < rb - 16;                   // else a pad (copy something in bounds)
+      const int jj = data ? j : 0;
+      const bf16* src = first ? Wqkv + (long)((jj >> 5) * D + 32 * p + (jj & 31)) * D + (data ? o / 2 : 0)
+                              : Wo + (long)jj * D + 32 * p + (data ? o / 2 : 0);
+      char* dst = base + (first ? 0 : (int)S::w1a) + (pos - lane * 16);
+      if (pos < (first ? (int)S::w1 : (int)S::w2))
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+    }
+  };
+  for (int i = tid; i < 3 * D; i += NTHR) sbias[i] = bqkv[i];
+  m3_stage_vectors<D>(sv, g, false, tid, NTHR);
+  const bf16* __restrict__ A = (const bf16*)g.A;
+  bf16x8 xf[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s)
+    xf[s] = tok >= 0 ? *(const bf16x8*)(A + (long)tok * D + 16 * s + 8 * g2) : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+  dma(0, 0);
+  __syncthreads();                                    // vectors staged, pair 0 in LDS
+
+  const float scale = 1.4426950408889634f / 4.0f;     // log2(e) / sqrt(16)
+  f32x16 acc2[OBK][1];
+#pragma unroll
+  for (int b = 0; b < OBK; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc2[b][0][r] = 0.f;
+#pragma unroll 1
+  for (int p = 0; p < NP; ++p) {
+    // buffer (p + 1) & 1 was last read in iteration p - 1, before its closing barrier
+    if (p + 1 < NP) dma(p + 1, (p + 1) & 1);
+    const char* s1 = smem + (p & 1) * S::buf;
+    const char* s2 = s1 + S::w1a;
+    // Q, K: register r holds pair feature 8(r/4) + 4 g2 + r%4 of token l%32;
+    // V^T: register r holds token 8(r/4) + 4 g2 + r%4, feature l%32
+    f32x16 aq, ak, av;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) aq[r] = ak[r] = av[r] = 0.f;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const bf16x8 wq = *(const bf16x8*)(s1 + l32 * RB1 + (2 * s + g2) * 16);
+      const bf16x8 wk = *(const bf16x8*)(s1 + (32 + l32) * RB1 + (2 * s + g2) * 16);
+      const bf16x8 wv = *(const bf16x8*)(s1 + (64 + l32) * RB1 + (2 * s + g2) * 16);
+      aq = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wq, xf[s], aq, 0, 0, 0);
+      ak = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wk, xf[s], ak, 0, 0, 0);
+      av = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xf[s], wv, av, 0, 0, 0);
+    }
+    // + bias, BF16; registers 8e .. 8e + 7 of Q and K are head 2p + e
+    bf16x8 qf[2], kf[2], vf[2];
+    const float bv = sbias[2 * D + 32 * p + l32];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int f = 32 * p + 8 * q + 4 * g2;
+      const f32x4 bq = *(const f32x4*)&sbias[f];
+      const f32x4 bk = *(const f32x4*)&sbias[D + f];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 4 * q + i;
+        qf[r >> 3][r & 7] = (bf16)(aq[r] + bq[i]);
+        kf[r >> 3][r & 7] = (bf16)(ak[r] + bk[i]);
+        vf[r >> 3][r & 7] = (bf16)(av[r] + bv);
+      }
+    }
+    f32x16 ob;                                         // O of the pair, pair features as Q's
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      f32x16 st;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) st[r] = 0.f;
+      st = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kf[e], qf[e], st, 0, 0, 0);
+      float mx = -INFINITY;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        st[r] = ((okbits >> r) & 1u) ? st[r] : -INFINITY;
+        mx = fmaxf(mx, st[r]);
+      }
+      mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+      // a padding query has no valid key (mx = -inf): p = 0 for it
+      const float mxs = mx == -INFINITY ? 0.f : -mx * scale;
+      float ps = 0.f;
+      bf16x8 pf[2];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float pv = __builtin_amdgcn_exp2f(fmaf(st[r], scale, mxs));
+        ps += pv;
+        pf[r >> 3][r & 7] = (bf16)pv;
+      }
+      ps += __shfl_xor(ps, 32, 64);
+      f32x16 o;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) o[r] = 0.f;
+      o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vf[0], pf[0], o, 0, 0, 0);
+      o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vf[1], pf[1], o, 0, 0, 0);
+      const float inv = ps > 0.f ? 1.0f / ps : 0.f;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) ob[8 * e + r] = o[8 * e + r] * inv;
+    }
+    // output projection of the pair: acc2[b] += W_o[32 b + row][32 p + k] O[k],
+    // the k order of O's registers (16 s + 4 g2 + j, 16 s + 8 + 4 g2 + j - 4)
+    // on both operands
+    bf16x8 of[2];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) of[r >> 3][r & 7] = (bf16)ob[r];
+#pragma unroll
+    for (int b = 0; b < OBK; ++b)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const char* wr = s2 + (32 * b + l32) * RB2;
+        const bf16x4 a0 = *(const bf16x4*)(wr + (16 * s + 4 * g2) * 2);
+        const bf16x4 a1 = *(const bf16x4*)(wr + (16 * s + 8 + 4 * g2) * 2);
+        const bf16x8 w = bf16x8{a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+        acc2[b][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, of[s], acc2[b][0], 0, 0, 0);
+      }
+    // pair p + 1 complete in every wave (this wave's only memory operations in
+    // flight are its part of that DMA)
+    if (p + 1 < NP) m3_wait_barrier(0);
+  }
+  m3_residual_epilogue<D, 1, false>(acc2, tok >= 0 ? (long)tok : g.M, g, g2, sv);
+}
+
+// ---------------------------------------------------------------------------
 // Module A for the BF16 path, from the symbol grid to the first LayerNorm in
 // one token-resident kernel (method section, Module A; Appendix, one-step
 // algorithm):
@@ -1120,6 +1310,30 @@ hipError_t launch_mlp3_bf16(const GemmArgs& g, const Mat& W1, const float* b1, c
     return mlp3_t<128, 1, 8, 2, 4, true, 1>(g, W1.b16, b1, W2.b16, F, s);
   }
   return mlp3_t<256, 1, 8, 2, 3, false>(g, W1.b16, b1, W2.b16, F, s);
+}
+
+bool user_block_tr_ok(int d, int heads) { return d == 128 && heads * 16 == d; }
+
+// The user-attention sublayer for BF16 at d = 128, head width 16: R += O W_o^T
+// + b_o with O the user attention of the QKV projection of XN, then the next
+// LayerNorm of R into XN (in place).  Groups from c.ugrp32.
+hipError_t launch_user_block_tr(const StepCtx& c, void* XN, const DevLayer& L, const float* ln_g, const float* ln_b,
+                                float* R, int d, int heads, hipStream_t s) {
+  if (c.total_ugrp32 == 0) return hipSuccess;
+  if (!user_block_tr_ok(d, heads) || !c.ugrp32 || !L.Wqkv_u.b16 || !L.Wo_u.b16) return hipErrorInvalidValue;
+  GemmArgs g{};
+  g.M = c.total_tokens;
+  g.N = d;
+  g.Kd = d;
+  g.A = XN;
+  g.out = XN;
+  g.bias = L.bo_u;
+  g.R = R;
+  g.ln_g = ln_g;
+  g.ln_b = ln_b;
+  hipLaunchKernelGGL((k_user_block_tr<128, 4>), dim3((c.total_ugrp32 + 3) / 4), dim3(256), 0, s, c, g,
+                     L.Wqkv_u.b16, L.bqkv_u, L.Wo_u.b16);
+  return hipGetLastError();
 }
 
 bool user_qkv_attn_ok(int d, int heads) { return d == 256 && heads * 32 == d; }
