@@ -649,8 +649,9 @@ void k_oproj3(GemmArgs g, const bf16* __restrict__ W) {
 //                 the head dimension on both sides;
 //   softmax       exp2, masked to the query's column; a lane holds 16 keys
 //                 of its query, lane l ^ 32 the other 16;
-//   O^T = V^T P^T two MFMAs; V passes through a per-wave LDS tile to become
-//                 the A operand, read with the keys in P's register order.
+//   O^T = V^T P^T two MFMAs; V is projected transposed (the projection MFMA
+//                 with its operands swapped), which leaves it as the A
+//                 operand with the keys in P's register order.
 // Only XN is read and only O is written: 4d bytes per token, against 16d for
 // a separate projection and attention kernel.
 template <int D>
@@ -659,10 +660,8 @@ struct UQSmem {
   static constexpr int CR = 96;                      // Q, K and V rows of one head
   static constexpr size_t w = (size_t)CR * RB;
   static constexpr size_t wa = (w + 15) / 16 * 16;
-  static constexpr int LDT = 40;                     // V^T tile row: 32 keys + pad (bf16)
-  static constexpr size_t vt = (size_t)8 * 32 * LDT * 2;
   static constexpr size_t bias = (size_t)3 * D * 4;
-  static constexpr size_t bytes = 2 * wa + vt + bias;
+  static constexpr size_t bytes = 2 * wa + bias;
   static_assert(bytes <= 160 * 1024, "LDS");
 };
 
@@ -671,12 +670,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_user_qkv_attn(StepCtx c, const bf16* __restrict__ XN, const bf16* __restrict__ W,
                      const float* __restrict__ bqkv, bf16* __restrict__ O) {
   using S = UQSmem<D>;
-  constexpr int RB = S::RB, LDT = S::LDT, KS = D / 16, HEADS = D / 32;
+  constexpr int RB = S::RB, KS = D / 16, HEADS = D / 32;
   constexpr int NB = (int)((S::w + 1023) / 1024), NPW = (NB + 7) / 8;
   static_assert(HEADS % 4 == 0, "heads in batches of four");
   __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
-  bf16* sVt = (bf16*)(smem + 2 * S::wa);
-  float* sbias = (float*)(smem + 2 * S::wa + S::vt);
+  float* sbias = (float*)(smem + 2 * S::wa);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
 
   // ---- this lane's slot of the wave's group
@@ -722,7 +720,6 @@ void k_user_qkv_attn(StepCtx c, const bf16* __restrict__ XN, const bf16* __restr
   __syncthreads();                                  // bias staged, chunk 0 in LDS
 
   const float scale = 1.4426950408889634f / sqrtf(32.0f);
-  bf16* tvt = sVt + wave * 32 * LDT;
   // O of HB heads at a time; each batch is stored right after a closing
   // barrier, so its stores overlap the next head's work and are complete by
   // the barrier after it
@@ -734,32 +731,35 @@ void k_user_qkv_attn(StepCtx c, const bf16* __restrict__ XN, const bf16* __restr
     // buffer (h + 1) & 1 was last read in iteration h - 1, before its closing barrier
     if (h + 1 < HEADS) dma(h + 1, (h + 1) & 1);
     const char* sw = smem + (h & 1) * S::wa;
-    f32x16 acc[3];
+    // Q, K: register r holds head feature 8(r/4) + 4 g2 + r%4 of token l%32;
+    // V^T (operands swapped): register r holds token 8(r/4) + 4 g2 + r%4,
+    // feature l%32 -- the A operand of O^T = V^T P^T as it stands
+    f32x16 aq, ak, av;
 #pragma unroll
-    for (int cb = 0; cb < 3; ++cb)
+    for (int r = 0; r < 16; ++r) aq[r] = ak[r] = av[r] = 0.f;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[cb][r] = 0.f;
-#pragma unroll
-    for (int s = 0; s < KS; ++s)
-#pragma unroll
-      for (int cb = 0; cb < 3; ++cb) {
-        const bf16x8 a = *(const bf16x8*)(sw + (32 * cb + l32) * RB + (2 * s + g2) * 16);
-        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, xf[s], acc[cb], 0, 0, 0);
-      }
-    // + bias, BF16; register r holds feature 8(r/4) + 4 g2 + r%4 of the head
-    bf16x8 qf[2], kf[2];
+    for (int s = 0; s < KS; ++s) {
+      const bf16x8 wq = *(const bf16x8*)(sw + l32 * RB + (2 * s + g2) * 16);
+      const bf16x8 wk = *(const bf16x8*)(sw + (32 + l32) * RB + (2 * s + g2) * 16);
+      const bf16x8 wv = *(const bf16x8*)(sw + (64 + l32) * RB + (2 * s + g2) * 16);
+      aq = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wq, xf[s], aq, 0, 0, 0);
+      ak = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wk, xf[s], ak, 0, 0, 0);
+      av = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xf[s], wv, av, 0, 0, 0);
+    }
+    // + bias, BF16
+    bf16x8 qf[2], kf[2], vf[2];
+    const float bv = sbias[2 * D + h * 32 + l32];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int f = h * 32 + 8 * q + 4 * g2;
       const f32x4 bq = *(const f32x4*)&sbias[f];
       const f32x4 bk = *(const f32x4*)&sbias[D + f];
-      const f32x4 bv = *(const f32x4*)&sbias[2 * D + f];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int r = 4 * q + i;
-        qf[r >> 3][r & 7] = (bf16)(acc[0][r] + bq[i]);
-        kf[r >> 3][r & 7] = (bf16)(acc[1][r] + bk[i]);
-        tvt[(8 * q + 4 * g2 + i) * LDT + l32] = (bf16)(acc[2][r] + bv[i]);
+        qf[r >> 3][r & 7] = (bf16)(aq[r] + bq[i]);
+        kf[r >> 3][r & 7] = (bf16)(ak[r] + bk[i]);
+        vf[r >> 3][r & 7] = (bf16)(av[r] + bv);
       }
     }
     // S^T = K Q^T: lane l holds query l%32, register r key slot 8(r/4) + 4 g2 + r%4
@@ -786,16 +786,6 @@ void k_user_qkv_attn(StepCtx c, const bf16* __restrict__ XN, const bf16* __restr
       pf[r >> 3][r & 7] = (bf16)p;
     }
     ps += __shfl_xor(ps, 32, 64);
-    // V^T fragments in P's key order: element j of k-step s is key
-    // 16 s + 4 g2 + j (j < 4) or 16 s + 8 + 4 g2 + j - 4
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // this wave's V^T writes are in LDS
-    bf16x8 vf[2];
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const bf16x4 a0 = *(const bf16x4*)&tvt[l32 * LDT + 16 * s + 4 * g2];
-      const bf16x4 a1 = *(const bf16x4*)&tvt[l32 * LDT + 16 * s + 8 + 4 * g2];
-      vf[s] = bf16x8{a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
-    }
     f32x16 o;
 #pragma unroll
     for (int r = 0; r < 16; ++r) o[r] = 0.f;
