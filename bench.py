@@ -98,6 +98,7 @@ def algorithmic(model, n, K, es: int):
         "attn_row": 4 * n * d, "attn_user": 4 * K * d,
         "attn_block_row": 8 * d * d + 4 * n * d, "attn_block_user": 8 * d * d + 4 * K * d,
         "gate_fused": 6 * d * d, "embed_gate": 6 * d * d, "user_block": 8 * d * d + 4 * K * d,
+        "row_block": 8 * d * d + 4 * n * d,
         "qkv_attn_user": 6 * d * d + 4 * K * d,
     }
     # minimum bytes: inputs read once, outputs written once; residual updates read and
@@ -112,7 +113,7 @@ def algorithmic(model, n, K, es: int):
         "layernorm": 4 * d + d * es,
         # fused attention sublayer: XN in, FP32 residual read and written, next XN out
         "attn_block_row": 2 * d * es + 8 * d, "attn_block_user": 2 * d * es + 8 * d,
-        "user_block": 2 * d * es + 8 * d,
+        "user_block": 2 * d * es + 8 * d, "row_block": 2 * d * es + 8 * d,
         # QKV projection + user attention: XN in, O out
         "qkv_attn_user": 2 * d * es,
         # gate MLP: [Z ; e] in, residual stream and e read, residual and first XN written

@@ -439,7 +439,10 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
   for (int l = 0; l < m.n_layers; ++l) {
     const DevLayer& L = m.layer[l];
     if (!fused_ln) TIMED("layernorm", ln(L.ln1_g, L.ln1_b));
-    if (blk_row) {
+    if (prec == kBF16 && r.use_blocks && row_block_tr_ok(d, m.heads, c.max_n)) {
+      // BF16, head width 16, n <= 128: the row-attention sublayer token-resident (one row per workgroup)
+      TIMED("row_block", launch_row_block_tr(c, k.XN, L, L.ln2_g, L.ln2_b, k.R, d, m.heads, s));
+    } else if (blk_row) {
       // BF16: QKV projection, row attention, output projection, residual and LN2 in one kernel
       TIMED("attn_block_row", launch_attn_block(c, false, k.XN, L, L.ln2_g, L.ln2_b, k.R, d, m.heads, s));
     } else {

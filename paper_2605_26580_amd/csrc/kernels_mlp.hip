@@ -999,6 +999,225 @@ void k_user_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const
 }
 
 // ---------------------------------------------------------------------------
+// The row-attention sublayer for the BF16 path at head width 16 (d = 128,
+// rows of n <= 128 tokens), token-resident: QKV projection, softmax
+// attention of each token over the n tokens of its row, output projection,
+// bias, residual and the next LayerNorm.  A workgroup of four waves owns one
+// row (wave w: slots 32 w .. 32 w + 31); each wave keeps its XN rows in
+// registers and walks the head pairs as k_user_block_tr does.  Per pair the
+// waves publish their K block (key-major) and V^T block (projected
+// transposed) to LDS, then every wave runs its 32 queries over the row's key
+// blocks with an online softmax (S^T = K Q^T from the shared K rows, O^T +=
+// V^T P^T from the shared V^T rows, both in P's key order), and feeds the
+// pair's O to the output projection.  The pair's Wqkv rows and W_o columns
+// sit in one LDS buffer each; each DMA is issued as soon as every wave is
+// done with the buffer it refills (Wqkv after the K/V publication, W_o after
+// the output projection), so it lands behind the attention or the next
+// projection.  59 KB of LDS: two workgroups per CU.
+template <int D>
+struct RBSmem {
+  static constexpr int RB1 = D * 2 + 16;               // bytes per stored Wqkv row
+  static constexpr int RB2 = 32 * 2 + 16;              // bytes per stored W_o row (the pair's 32 columns)
+  static constexpr size_t w1 = (size_t)96 * RB1;
+  static constexpr size_t w2 = (size_t)D * RB2;
+  static constexpr size_t w1a = (w1 + 15) / 16 * 16;
+  static constexpr size_t w2a = (w2 + 15) / 16 * 16;
+  static constexpr int LDK = 32 + 8;                   // K row: the pair's 32 features + pad (bf16)
+  static constexpr int LDV = 128 + 8;                  // V^T row: 128 keys + pad (bf16)
+  static constexpr size_t k = (size_t)128 * LDK * 2;
+  static constexpr size_t vt = (size_t)32 * LDV * 2;
+  static constexpr size_t vec = (size_t)8 * D * 4;     // bqkv [3D], then the epilogue vectors [5D]
+  static constexpr size_t bytes = w1a + w2a + k + vt + vec;
+  static_assert(bytes <= 80 * 1024, "two workgroups per CU");
+};
+
+template <int D>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_row_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const float* __restrict__ bqkv,
+                    const bf16* __restrict__ Wo) {
+  using S = RBSmem<D>;
+  constexpr int RB1 = S::RB1, RB2 = S::RB2, LDK = S::LDK, LDV = S::LDV;
+  constexpr int KS = D / 16, NP = D / 32, OBK = D / 32;
+  constexpr int N1 = (int)((S::w1 + 1023) / 1024), N2 = (int)((S::w2 + 1023) / 1024);
+  constexpr int NP1 = (N1 + 3) / 4, NP2 = (N2 + 3) / 4;
+  __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
+  char* sw1 = smem;
+  char* sw2 = smem + S::w1a;
+  bf16* sK = (bf16*)(smem + S::w1a + S::w2a);
+  bf16* sVt = (bf16*)(smem + S::w1a + S::w2a + S::k);
+  float* sbias = (float*)(smem + S::w1a + S::w2a + S::k + S::vt);
+  float* sv = sbias + 3 * D;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
+
+  const int row = blockIdx.x;
+  const DevBin& b = c.bins[c.row_bin[row]];
+  if (b.st->phase == kDone) return;                 // whole workgroup, before any barrier
+  const int n = b.n, slot = 32 * wave + l32;
+  const int tok = slot < n ? b.tok_off + (row - b.row_off) * n + slot : -1;
+  const int nkb = (n + 31) / 32;                    // key blocks holding a token
+
+  // DMA blocks of this wave (uniform counts for the partial waits)
+  const int nw1 = N1 / 4 + (wave < N1 % 4 ? 1 : 0), nw2 = N2 / 4 + (wave < N2 % 4 ? 1 : 0);
+  auto dma_qkv = [&](int p) {
+#pragma unroll
+    for (int k = 0; k < NP1; ++k) {
+      const int u = wave + 4 * k;
+      if (u >= N1) break;
+      const int pos = u * 1024 + lane * 16, j = pos / RB1, o = pos - j * RB1;
+      const bool data = o < RB1 - 16;
+      const int jj = data ? j : 0;
+      const bf16* src = Wqkv + (long)((jj >> 5) * D + 32 * p + (jj & 31)) * D + (data ? o / 2 : 0);
+      if (pos < (int)S::w1)
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(sw1 + u * 1024), 16, 0, 0);
+    }
+  };
+  auto dma_o = [&](int p) {
+#pragma unroll
+    for (int k = 0; k < NP2; ++k) {
+      const int u = wave + 4 * k;
+      if (u >= N2) break;
+      const int pos = u * 1024 + lane * 16, j = pos / RB2, o = pos - j * RB2;
+      const bool data = o < RB2 - 16;
+      const bf16* src = Wo + (long)(data ? j : 0) * D + 32 * p + (data ? o / 2 : 0);
+      if (pos < (int)S::w2)
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(sw2 + u * 1024), 16, 0, 0);
+    }
+  };
+  for (int i = tid; i < 3 * D; i += 256) sbias[i] = bqkv[i];
+  m3_stage_vectors<D>(sv, g, false, tid, 256);
+  const bf16* __restrict__ A = (const bf16*)g.A;
+  bf16x8 xf[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s)
+    xf[s] = tok >= 0 ? *(const bf16x8*)(A + (long)tok * D + 16 * s + 8 * g2) : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+  dma_qkv(0);
+  dma_o(0);
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // staged vectors written (visible after the first barrier)
+  const float scale = 1.4426950408889634f / 4.0f;   // log2(e) / sqrt(16)
+  f32x16 acc2[OBK][1];
+#pragma unroll
+  for (int ob = 0; ob < OBK; ++ob)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc2[ob][0][r] = 0.f;
+
+#pragma unroll 1
+  for (int p = 0; p < NP; ++p) {
+    // Wqkv of pair p in LDS (issued before W_o of pair p, which may still be in flight)
+    m3_wait_barrier(nw2);
+    f32x16 aq, ak, av;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) aq[r] = ak[r] = av[r] = 0.f;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const bf16x8 wq = *(const bf16x8*)(sw1 + l32 * RB1 + (2 * s + g2) * 16);
+      const bf16x8 wk = *(const bf16x8*)(sw1 + (32 + l32) * RB1 + (2 * s + g2) * 16);
+      const bf16x8 wv = *(const bf16x8*)(sw1 + (64 + l32) * RB1 + (2 * s + g2) * 16);
+      aq = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wq, xf[s], aq, 0, 0, 0);
+      ak = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wk, xf[s], ak, 0, 0, 0);
+      av = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xf[s], wv, av, 0, 0, 0);
+    }
+    // + bias, BF16: Q stays in registers (registers 8e .. 8e + 7 = head 2p + e);
+    // K (key-major) and V^T (feature-major) are published for the whole row
+    bf16x8 qf[2];
+    const float bv = sbias[2 * D + 32 * p + l32];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int f = 32 * p + 8 * q + 4 * g2;
+      const f32x4 bq = *(const f32x4*)&sbias[f];
+      const f32x4 bk = *(const f32x4*)&sbias[D + f];
+      bf16x4 kq, vq;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        qf[q >> 1][4 * (q & 1) + i] = (bf16)(aq[4 * q + i] + bq[i]);
+        kq[i] = (bf16)(ak[4 * q + i] + bk[i]);
+        vq[i] = (bf16)(av[4 * q + i] + bv);
+      }
+      *(bf16x4*)&sK[slot * LDK + 8 * q + 4 * g2] = kq;
+      *(bf16x4*)&sVt[l32 * LDV + 32 * wave + 8 * q + 4 * g2] = vq;
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();                   // K, V^T of the row published; Wqkv buffer free
+    asm volatile("" ::: "memory");
+    if (p + 1 < NP) dma_qkv(p + 1);
+
+    f32x16 ob;                                       // O of the pair, pair features as Q's
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      float m = -INFINITY, ls = 0.f;
+      f32x16 o;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) o[r] = 0.f;
+#pragma unroll 1
+      for (int kb = 0; kb < nkb; ++kb) {
+        const bf16* kr = &sK[(32 * kb + l32) * LDK + 16 * e + 4 * g2];
+        const bf16x4 k0 = *(const bf16x4*)kr, k1 = *(const bf16x4*)(kr + 8);
+        const bf16x8 kfr = bf16x8{k0[0], k0[1], k0[2], k0[3], k1[0], k1[1], k1[2], k1[3]};
+        f32x16 st;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) st[r] = 0.f;
+        st = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kfr, qf[e], st, 0, 0, 0);
+        // register r: key 32 kb + 8(r/4) + 4 g2 + r%4
+        float mb = -INFINITY;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          if (32 * kb + 8 * (r >> 2) + 4 * g2 + (r & 3) >= n) st[r] = -INFINITY;
+          mb = fmaxf(mb, st[r]);
+        }
+        mb = fmaxf(mb, __shfl_xor(mb, 32, 64));
+        const float mn = fmaxf(m, mb);              // finite: key block kb holds a token
+        const float corr = __builtin_amdgcn_exp2f((m - mn) * scale);
+        ls *= corr;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) o[r] *= corr;
+        const float mns = -mn * scale;
+        bf16x8 pf[2];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const float pv = __builtin_amdgcn_exp2f(fmaf(st[r], scale, mns));
+          ls += pv;
+          pf[r >> 3][r & 7] = (bf16)pv;
+        }
+        m = mn;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const bf16* vr = &sVt[l32 * LDV + 32 * kb + 16 * s + 4 * g2];
+          const bf16x4 v0 = *(const bf16x4*)vr, v1 = *(const bf16x4*)(vr + 8);
+          const bf16x8 vfr = bf16x8{v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
+          o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vfr, pf[s], o, 0, 0, 0);
+        }
+      }
+      ls += __shfl_xor(ls, 32, 64);
+      const float inv = 1.0f / ls;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) ob[8 * e + r] = o[8 * e + r] * inv;
+    }
+    // W_o of pair p in LDS (the Wqkv DMA of pair p + 1, issued after it, may
+    // be in flight); every wave is done with K and V^T of this pair
+    m3_wait_barrier(p + 1 < NP ? nw1 : 0);
+    bf16x8 of[2];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) of[r >> 3][r & 7] = (bf16)ob[r];
+#pragma unroll
+    for (int bo = 0; bo < OBK; ++bo)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const char* wr = sw2 + (32 * bo + l32) * RB2;
+        const bf16x4 a0 = *(const bf16x4*)(wr + (16 * s + 4 * g2) * 2);
+        const bf16x4 a1 = *(const bf16x4*)(wr + (16 * s + 8 + 4 * g2) * 2);
+        const bf16x8 w = bf16x8{a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+        acc2[bo][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, of[s], acc2[bo][0], 0, 0, 0);
+      }
+    if (p + 1 < NP) {
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      __builtin_amdgcn_s_barrier();                 // every wave is done with W_o of pair p
+      asm volatile("" ::: "memory");
+      dma_o(p + 1);
+    }
+  }
+  m3_residual_epilogue<D, 1, false>(acc2, tok >= 0 ? (long)tok : g.M, g, g2, sv);
+}
+
+// ---------------------------------------------------------------------------
 // Module A for the BF16 path, from the symbol grid to the first LayerNorm in
 // one token-resident kernel (method section, Module A; Appendix, one-step
 // algorithm):
@@ -1300,6 +1519,31 @@ hipError_t launch_mlp3_bf16(const GemmArgs& g, const Mat& W1, const float* b1, c
     return mlp3_t<128, 1, 8, 2, 4, true, 1>(g, W1.b16, b1, W2.b16, F, s);
   }
   return mlp3_t<256, 1, 8, 2, 3, false>(g, W1.b16, b1, W2.b16, F, s);
+}
+
+bool row_block_tr_ok(int d, int heads, int max_n) { return d == 128 && heads * 16 == d && max_n <= 128; }
+
+// The row-attention sublayer for BF16 at d = 128, head width 16, rows of at
+// most 128 tokens: R += O W_o^T + b_o with O the row attention of the QKV
+// projection of XN, then the next LayerNorm of R into XN (in place).  One
+// workgroup per row.
+hipError_t launch_row_block_tr(const StepCtx& c, void* XN, const DevLayer& L, const float* ln_g, const float* ln_b,
+                               float* R, int d, int heads, hipStream_t s) {
+  if (c.total_rows == 0) return hipSuccess;
+  if (!row_block_tr_ok(d, heads, c.max_n) || !L.Wqkv_r.b16 || !L.Wo_r.b16) return hipErrorInvalidValue;
+  GemmArgs g{};
+  g.M = c.total_tokens;
+  g.N = d;
+  g.Kd = d;
+  g.A = XN;
+  g.out = XN;
+  g.bias = L.bo_r;
+  g.R = R;
+  g.ln_g = ln_g;
+  g.ln_b = ln_b;
+  hipLaunchKernelGGL((k_row_block_tr<128>), dim3(c.total_rows), dim3(256), 0, s, c, g, L.Wqkv_r.b16, L.bqkv_r,
+                     L.Wo_r.b16);
+  return hipGetLastError();
 }
 
 bool user_block_tr_ok(int d, int heads) { return d == 128 && heads * 16 == d; }
