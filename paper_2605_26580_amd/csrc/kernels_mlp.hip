@@ -1156,20 +1156,30 @@ void k_row_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const 
 #pragma unroll
         for (int r = 0; r < 16; ++r) st[r] = 0.f;
         st = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kfr, qf[e], st, 0, 0, 0);
-        // register r: key 32 kb + 8(r/4) + 4 g2 + r%4
+        // register r: key 32 kb + 8(r/4) + 4 g2 + r%4; only the last block can
+        // hold keys past n (a uniform branch)
+        if (32 * kb + 32 > n) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r)
+            if (32 * kb + 8 * (r >> 2) + 4 * g2 + (r & 3) >= n) st[r] = -INFINITY;
+        }
         float mb = -INFINITY;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          if (32 * kb + 8 * (r >> 2) + 4 * g2 + (r & 3) >= n) st[r] = -INFINITY;
-          mb = fmaxf(mb, st[r]);
-        }
+        for (int r = 0; r < 16; ++r) mb = fmaxf(mb, st[r]);
         mb = fmaxf(mb, __shfl_xor(mb, 32, 64));
-        const float mn = fmaxf(m, mb);              // finite: key block kb holds a token
-        const float corr = __builtin_amdgcn_exp2f((m - mn) * scale);
-        ls *= corr;
+        // the running max m moves (and o, ls are rescaled) only when some
+        // query's block max exceeds it by more than 8 / scale: until then
+        // every p is at most 2^8, which FP32 sums and BF16 P carry exactly
+        // as well; the first block always sets m (finite: it holds a token)
+        if (__ballot(mb > m + 8.0f / scale) != 0ull) {   // wave-uniform
+          const float mn = fmaxf(m, mb);
+          const float corr = __builtin_amdgcn_exp2f((m - mn) * scale);
+          ls *= corr;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) o[r] *= corr;
-        const float mns = -mn * scale;
+          for (int r = 0; r < 16; ++r) o[r] *= corr;
+          m = mn;
+        }
+        const float mns = -m * scale;
         bf16x8 pf[2];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
@@ -1177,7 +1187,6 @@ void k_row_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const 
           ls += pv;
           pf[r >> 3][r & 7] = (bf16)pv;
         }
-        m = mn;
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
           const bf16* vr = &sVt[l32 * LDV + 32 * kb + 16 * s + 4 * g2];
