@@ -99,7 +99,7 @@ def algorithmic(model, n, K, es: int):
         "attn_block_row": 8 * d * d + 4 * n * d, "attn_block_user": 8 * d * d + 4 * K * d,
         "gate_fused": 6 * d * d, "embed_gate": 6 * d * d, "user_block": 8 * d * d + 4 * K * d,
         "row_block": 8 * d * d + 4 * n * d,
-        "qkv_attn_user": 6 * d * d + 4 * K * d,
+        "qkv_attn_user": 6 * d * d + 4 * K * d, "qkv_attn_row": 6 * d * d + 4 * n * d,
     }
     # minimum bytes: inputs read once, outputs written once; residual updates read and
     # write the FP32 stream and (BF16) write the next LayerNorm's compute-type copy
@@ -115,7 +115,7 @@ def algorithmic(model, n, K, es: int):
         "attn_block_row": 2 * d * es + 8 * d, "attn_block_user": 2 * d * es + 8 * d,
         "user_block": 2 * d * es + 8 * d, "row_block": 2 * d * es + 8 * d,
         # QKV projection + user attention: XN in, O out
-        "qkv_attn_user": 2 * d * es,
+        "qkv_attn_user": 2 * d * es, "qkv_attn_row": 2 * d * es,
         # gate MLP: [Z ; e] in, residual stream and e read, residual and first XN written
         "gate_fused": 3 * d * es + 12 * d,
         # embedding + Module A + first LayerNorm: the symbol in (the weights and the

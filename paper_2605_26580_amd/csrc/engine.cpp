@@ -446,11 +446,16 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
       // BF16: QKV projection, row attention, output projection, residual and LN2 in one kernel
       TIMED("attn_block_row", launch_attn_block(c, false, k.XN, L, L.ln2_g, L.ln2_b, k.R, d, m.heads, s));
     } else {
-      g = GemmArgs{}; g.M = T;
-      g.N = 3 * d; g.Kd = d; g.A = k.XN; g.bias = L.bqkv_r; g.out = k.QKV;
-      TIMED("gemm_qkv_row", qkv(g, L.Wqkv_r));
-      if (prec == kF32) TIMED("attn_row", launch_row_attn(c, prec, k.QKV, k.O, d, m.heads, c.max_n, s));
-      else TIMED("attn_row", launch_row_attn_mfma(c, k.QKV, k.O, d, m.heads, c.max_n, s));
+      if (prec == kBF16 && r.use_blocks && row_qkv_attn_ok(d, m.heads, c.max_n)) {
+        // BF16, head width 32, n <= 256: QKV projection and row attention in one kernel
+        TIMED("qkv_attn_row", launch_row_qkv_attn(c, k.XN, L.Wqkv_r, L.bqkv_r, k.O, d, m.heads, s));
+      } else {
+        g = GemmArgs{}; g.M = T;
+        g.N = 3 * d; g.Kd = d; g.A = k.XN; g.bias = L.bqkv_r; g.out = k.QKV;
+        TIMED("gemm_qkv_row", qkv(g, L.Wqkv_r));
+        if (prec == kF32) TIMED("attn_row", launch_row_attn(c, prec, k.QKV, k.O, d, m.heads, c.max_n, s));
+        else TIMED("attn_row", launch_row_attn_mfma(c, k.QKV, k.O, d, m.heads, c.max_n, s));
+      }
       g = GemmArgs{}; g.M = T;
       g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_r; g.R = k.R;
       next_ln(g, L.ln2_g, L.ln2_b);

@@ -1227,6 +1227,193 @@ void k_row_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const 
 }
 
 // ---------------------------------------------------------------------------
+// QKV projection + row attention for the BF16 path at head width 32
+// (d = 256, rows of n <= 256 tokens): a workgroup of eight waves owns one
+// row (wave w: slots 32 w .. 32 w + 31) and walks the heads; weight chunk h
+// holds head h's Q, K and V rows (96 rows, double-buffered DMA).  Per head
+// each wave projects its 32 tokens (V transposed, as in k_user_qkv_attn),
+// keeps Q in registers and publishes its K block (key-major) and V^T block to
+// LDS; then every wave runs its queries over the row's 32-key blocks with the
+// online softmax of k_row_block_tr (lazy rescale).  O is written in BF16,
+// four heads at a time right after a barrier; the output projection,
+// residual and LayerNorm follow in k_oproj3.  HBM traffic: XN in, O out.
+template <int D>
+struct RQSmem {
+  static constexpr int RB = D * 2 + 16;                // bytes per stored weight row
+  static constexpr size_t w = (size_t)96 * RB;
+  static constexpr size_t wa = (w + 15) / 16 * 16;
+  static constexpr int LDK = 32 + 8;                   // K row: the head's 32 features + pad (bf16)
+  static constexpr int LDV = 256 + 8;                  // V^T row: 256 keys + pad (bf16)
+  static constexpr size_t k = (size_t)256 * LDK * 2;
+  static constexpr size_t vt = (size_t)32 * LDV * 2;
+  static constexpr size_t bias = (size_t)3 * D * 4;
+  static constexpr size_t bytes = 2 * wa + k + vt + bias;
+  static_assert(bytes <= 160 * 1024, "LDS");
+};
+
+template <int D>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_row_qkv_attn(StepCtx c, const bf16* __restrict__ XN, const bf16* __restrict__ W,
+                    const float* __restrict__ bqkv, bf16* __restrict__ O) {
+  using S = RQSmem<D>;
+  constexpr int RB = S::RB, LDK = S::LDK, LDV = S::LDV, KS = D / 16, HEADS = D / 32;
+  constexpr int NB = (int)((S::w + 1023) / 1024), NPW = (NB + 7) / 8;
+  static_assert(HEADS % 4 == 0, "heads in batches of four");
+  __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
+  bf16* sK = (bf16*)(smem + 2 * S::wa);
+  bf16* sVt = (bf16*)(smem + 2 * S::wa + S::k);
+  float* sbias = (float*)(smem + 2 * S::wa + S::k + S::vt);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
+
+  const int row = blockIdx.x;
+  const DevBin& b = c.bins[c.row_bin[row]];
+  if (b.st->phase == kDone) return;                 // whole workgroup, before any barrier
+  const int n = b.n, slot = 32 * wave + l32;
+  const int tok = slot < n ? b.tok_off + (row - b.row_off) * n + slot : -1;
+  const int nkb = (n + 31) / 32;                    // key blocks holding a token
+
+  auto dma = [&](int h, int buf) {
+    char* base = smem + buf * S::wa;
+#pragma unroll
+    for (int k = 0; k < NPW; ++k) {
+      const int u = wave + k * 8;                   // uniform over the wave
+      if (u >= NB) break;
+      const int pos = u * 1024 + lane * 16, j = pos / RB, o = pos - j * RB;
+      const bool data = o < RB - 16;                 // else a pad (copy something in bounds)
+      const int jj = data ? j : 0;
+      const bf16* src = W + (long)((jj >> 5) * D + h * 32 + (jj & 31)) * D + (data ? o / 2 : 0);
+      if (pos < (int)S::w)
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(base + u * 1024), 16, 0, 0);
+    }
+  };
+  for (int i = tid; i < 3 * D; i += 512) sbias[i] = bqkv[i];
+  bf16x8 xf[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s)
+    xf[s] = tok >= 0 ? *(const bf16x8*)(XN + (long)tok * D + 16 * s + 8 * g2) : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+  dma(0, 0);
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // staged bias written (visible after the first barrier)
+
+  const float scale = 1.4426950408889634f / sqrtf(32.0f);
+  constexpr int HB = 4;
+  bf16x4 ob[HB][4];
+  bf16* orow = O + (long)(tok >= 0 ? tok : 0) * D;
+#pragma unroll
+  for (int h = 0; h < HEADS; ++h) {
+    // chunk h in LDS; every wave is done with the previous head's K, V^T and
+    // with the buffer the next DMA refills; the previous batch's O stores
+    // are complete too
+    m3_wait_barrier(0);
+    if (h % HB == 0 && h > 0 && tok >= 0) {
+#pragma unroll
+      for (int hh = 0; hh < HB; ++hh)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *(bf16x4*)(orow + (h - HB + hh) * 32 + 8 * q + 4 * g2) = ob[hh][q];
+    }
+    if (h + 1 < HEADS) dma(h + 1, (h + 1) & 1);
+    const char* sw = smem + (h & 1) * S::wa;
+    f32x16 aq, ak, av;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) aq[r] = ak[r] = av[r] = 0.f;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const bf16x8 wq = *(const bf16x8*)(sw + l32 * RB + (2 * s + g2) * 16);
+      const bf16x8 wk = *(const bf16x8*)(sw + (32 + l32) * RB + (2 * s + g2) * 16);
+      const bf16x8 wv = *(const bf16x8*)(sw + (64 + l32) * RB + (2 * s + g2) * 16);
+      aq = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wq, xf[s], aq, 0, 0, 0);
+      ak = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wk, xf[s], ak, 0, 0, 0);
+      av = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xf[s], wv, av, 0, 0, 0);
+    }
+    bf16x8 qf[2];
+    const float bv = sbias[2 * D + h * 32 + l32];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int f = h * 32 + 8 * q + 4 * g2;
+      const f32x4 bq = *(const f32x4*)&sbias[f];
+      const f32x4 bk = *(const f32x4*)&sbias[D + f];
+      bf16x4 kq, vq;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        qf[q >> 1][4 * (q & 1) + i] = (bf16)(aq[4 * q + i] + bq[i]);
+        kq[i] = (bf16)(ak[4 * q + i] + bk[i]);
+        vq[i] = (bf16)(av[4 * q + i] + bv);
+      }
+      *(bf16x4*)&sK[slot * LDK + 8 * q + 4 * g2] = kq;
+      *(bf16x4*)&sVt[l32 * LDV + 32 * wave + 8 * q + 4 * g2] = vq;
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();                   // the row's K and V^T published
+    asm volatile("" ::: "memory");
+
+    float m = -INFINITY, ls = 0.f;
+    f32x16 o;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) o[r] = 0.f;
+#pragma unroll 1
+    for (int kb = 0; kb < nkb; ++kb) {
+      f32x16 st;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) st[r] = 0.f;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const bf16* kr = &sK[(32 * kb + l32) * LDK + 16 * s + 4 * g2];
+        const bf16x4 k0 = *(const bf16x4*)kr, k1 = *(const bf16x4*)(kr + 8);
+        const bf16x8 kfr = bf16x8{k0[0], k0[1], k0[2], k0[3], k1[0], k1[1], k1[2], k1[3]};
+        st = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kfr, qf[s], st, 0, 0, 0);
+      }
+      // register r: key 32 kb + 8(r/4) + 4 g2 + r%4; only the last block can
+      // hold keys past n (a uniform branch)
+      if (32 * kb + 32 > n) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          if (32 * kb + 8 * (r >> 2) + 4 * g2 + (r & 3) >= n) st[r] = -INFINITY;
+      }
+      float mb = -INFINITY;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) mb = fmaxf(mb, st[r]);
+      mb = fmaxf(mb, __shfl_xor(mb, 32, 64));
+      // lazy rescale (see k_row_block_tr): m moves only when some query's
+      // block max exceeds it by more than 8 / scale; the first block sets it
+      if (__ballot(mb > m + 8.0f / scale) != 0ull) {   // wave-uniform
+        const float mn = fmaxf(m, mb);
+        const float corr = __builtin_amdgcn_exp2f((m - mn) * scale);
+        ls *= corr;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) o[r] *= corr;
+        m = mn;
+      }
+      const float mns = -m * scale;
+      bf16x8 pf[2];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float pv = __builtin_amdgcn_exp2f(fmaf(st[r], scale, mns));
+        ls += pv;
+        pf[r >> 3][r & 7] = (bf16)pv;
+      }
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const bf16* vr = &sVt[l32 * LDV + 32 * kb + 16 * s + 4 * g2];
+        const bf16x4 v0 = *(const bf16x4*)vr, v1 = *(const bf16x4*)(vr + 8);
+        const bf16x8 vfr = bf16x8{v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
+        o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vfr, pf[s], o, 0, 0, 0);
+      }
+    }
+    ls += __shfl_xor(ls, 32, 64);
+    const float inv = 1.0f / ls;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      ob[h % HB][q] = bf16x4{(bf16)(o[4 * q] * inv), (bf16)(o[4 * q + 1] * inv), (bf16)(o[4 * q + 2] * inv),
+                             (bf16)(o[4 * q + 3] * inv)};
+  }
+  if (tok >= 0) {
+#pragma unroll
+    for (int hh = 0; hh < HB; ++hh)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) *(bf16x4*)(orow + (HEADS - HB + hh) * 32 + 8 * q + 4 * g2) = ob[hh][q];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Module A for the BF16 path, from the symbol grid to the first LayerNorm in
 // one token-resident kernel (method section, Module A; Appendix, one-step
 // algorithm):
@@ -1528,6 +1715,19 @@ hipError_t launch_mlp3_bf16(const GemmArgs& g, const Mat& W1, const float* b1, c
     return mlp3_t<128, 1, 8, 2, 4, true, 1>(g, W1.b16, b1, W2.b16, F, s);
   }
   return mlp3_t<256, 1, 8, 2, 3, false>(g, W1.b16, b1, W2.b16, F, s);
+}
+
+bool row_qkv_attn_ok(int d, int heads, int max_n) { return d == 256 && heads * 32 == d && max_n <= 256; }
+
+// QKV projection + row attention for BF16 at d = 256, head width 32, rows of
+// at most 256 tokens: O (BF16 [T][d]) from XN.  One workgroup per row.
+hipError_t launch_row_qkv_attn(const StepCtx& c, const void* XN, const Mat& Wqkv, const float* bqkv, void* O, int d,
+                               int heads, hipStream_t s) {
+  if (c.total_rows == 0) return hipSuccess;
+  if (!row_qkv_attn_ok(d, heads, c.max_n) || !Wqkv.b16) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_row_qkv_attn<256>), dim3(c.total_rows), dim3(512), 0, s, c, (const bf16*)XN, Wqkv.b16, bqkv,
+                     (bf16*)O);
+  return hipGetLastError();
 }
 
 bool row_block_tr_ok(int d, int heads, int max_n) { return d == 128 && heads * 16 == d && max_n <= 128; }
