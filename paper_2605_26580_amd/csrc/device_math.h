@@ -14,7 +14,7 @@ namespace cider {
 // VALU operations and the two hardware transcendentals (2^x, 1/x); the FP32
 // plain path keeps the erf form.
 __device__ __forceinline__ float gelu_f(float x) {
-  const float xc = fminf(fmaxf(x, -10.0f), 10.0f);
+  const float xc = __builtin_amdgcn_fmed3f(x, -10.0f, 10.0f);   // clamp, one v_med3_f32
   const float s = xc * xc;
   const float f = xc * fmaf(fmaf(0.0010142630f, s, -0.10677572f), s, -2.3011212f);
   return x * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(f));
