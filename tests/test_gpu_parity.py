@@ -62,6 +62,11 @@ CASES = [
     (7, 36, 1, 128, 8),
     (9, 20, 1, 64, 2),
     (16, 24, 1, 64, 4),
+    # token-resident sublayers at d = 128 (head width 16): a row shorter than
+    # one 32-key block, user groups of 3 columns x 9 rows, a row of 100
+    # tokens ending in a part-filled key block
+    (9, 20, 1, 128, 8),
+    (2, 100, 1, 128, 8),
     # 32-slot user groups of the d = 256 path: floor(32/K) columns of K rows,
     # padding slots at K = 3, 7 and a part-filled last group at n = 100, 40
     (3, 100, 1, 256, 8),

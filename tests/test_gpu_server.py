@@ -27,11 +27,14 @@ def _server(P, wh, steps, max_slots, max_tokens, max_queue=64, opts=None):
     return h
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_served_equals_alone(prec):
+@pytest.mark.parametrize("prec,d,h", [("fp32", 64, 4), ("bf16", 64, 4), ("bf16", 128, 8)])
+def test_served_equals_alone(prec, d, h):
+    """Requests admitted into a running batch decode exactly as they do alone
+    (at d = 128 the BF16 path runs the token-resident kernels, whose tile and
+    group tables are rebuilt whenever the resident set changes)."""
     torch = torch_cuda()
     P = lib()
-    cfg = synth.ModelCfg(2, 64, 4, n_max=128)
+    cfg = synth.ModelCfg(2, d, h, n_max=128)
     wh, _ = weights_handle(cfg, seed=41)
     opts = P.cider_opts_default(precision=P.CIDER_FP32 if prec == "fp32" else P.CIDER_BF16, remask=1)
     rng = np.random.default_rng(7)
@@ -42,7 +45,7 @@ def test_served_equals_alone(prec):
         code = code_of(n, 1000 + n)
         b = synth.make_bins(code, K, 1, float(rng.uniform(2, 6)), seed=900 + i)
         reqs.append((K, n, code, np.ascontiguousarray(b.y[0]), float(b.sigma2[0])))
-    say(f"server {prec}: 24 requests, 5 slots")
+    say(f"server {prec} d={d}: 24 requests, 5 slots")
     srv = _server(P, wh, 8, max_slots=5, max_tokens=5 * 6 * 128, opts=opts)
     L = P.abi.lib()
     outs, ids = [], []
