@@ -402,6 +402,7 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
   // BF16: fused attention blocks where the shapes allow (row attention needs n <= 128)
   const bool blk_row = prec == kBF16 && r.use_blocks && attn_block_ok(d, m.heads, c.max_n, false);
   const bool blk_user = prec == kBF16 && r.use_blocks && attn_block_ok(d, m.heads, c.max_n, true);
+  const bool user_mlp = prec == kBF16 && r.use_blocks && user_mlp_tr_ok(d, m.heads, F);
   GemmArgs g{};
   g.M = T;
   // BF16 at d = 128: embedding, Module A and the first LayerNorm in one kernel
@@ -462,7 +463,9 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
       TIMED("gemm_o_row", oproj(g, L.Wo_r));
     }
     if (!fused_ln) TIMED("layernorm", ln(L.ln2_g, L.ln2_b));
-    if (prec == kBF16 && r.use_blocks && user_block_tr_ok(d, m.heads)) {
+    if (user_mlp) {
+      // the user-attention sublayer runs with the MLP below, in one kernel
+    } else if (prec == kBF16 && r.use_blocks && user_block_tr_ok(d, m.heads)) {
       // BF16, head width 16: the user-attention sublayer token-resident (whole-column groups per wave)
       TIMED("user_block", launch_user_block_tr(c, k.XN, L, L.ln3_g, L.ln3_b, k.R, d, m.heads, s));
     } else if (blk_user) {
@@ -498,6 +501,9 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
         g.A = k.XN8;
         g.a_scale = k.xscale;
         TIMED("mlp_fused", launch_mlp_fp8(g, L.W1, L.b1, L.W2, F, s));
+      } else if (user_mlp) {
+        // BF16, d = 128, head width 16: user-attention sublayer + MLP, token-resident, one kernel
+        TIMED("user_mlp", launch_user_mlp_tr(c, k.XN, L, g, d, m.heads, F, s));
       } else if (mlp3_ok(d, F)) {
         // token-resident MLP: 256 tokens per workgroup, weights streamed once per tile
         TIMED("mlp_fused", launch_mlp3_bf16(g, L.W1, L.b1, L.W2, F, s));

@@ -1414,6 +1414,434 @@ void k_row_qkv_attn(StepCtx c, const bf16* __restrict__ XN, const bf16* __restri
 }
 
 // ---------------------------------------------------------------------------
+// The user-attention sublayer and the MLP of one layer in one kernel (BF16,
+// d = 128, head width 16): a wave owns a 32-slot group of whole columns (as
+// in k_user_block_tr) for both sublayers, so the residual stream and the
+// LayerNorm output between them never leave registers.
+//   user:  R1 = R + W_o Attn(Wqkv XN) + b_o, X1 = LN_3(R1)      (registers)
+//   MLP:   R2 = R1 + W2 GELU(W1 X1 + b1) + b2, then the next LayerNorm of R2
+//          into XN (or, after the last layer, the final LayerNorm and the
+//          symbol projection into lbar)
+// X1 stays in the output-accumulator layout: k-step s of the up projection
+// takes registers 8(s%2) .. 8(s%2) + 7 of block s/2, which hold features
+// 16 s + 4 g2 + j and 16 s + 8 + 4 g2 + j - 4; the W1 fragments are read
+// from LDS in that order (two 8-byte reads).  Weights go through one LDS
+// region: the user sublayer's pair buffers (Wqkv rows refilled after every
+// wave's projection, W_o columns after every wave's output projection),
+// then the MLP's chunk ring.  HBM traffic per token: XN and R in, R and XN
+// out, for two sublayers.
+template <int D, int NBUF, int MAXF>
+struct UMSmem {
+  using U = UBSmem<D>;
+  using M = M3Smem<D, NBUF, MAXF>;
+  static constexpr size_t wu = U::w1a + U::w2a;            // user sublayer: Wqkv rows | W_o columns of a pair
+  static constexpr size_t wm = NBUF * M::buf;              // MLP chunk ring
+  static constexpr size_t w = wu > wm ? wu : wm;
+  static constexpr size_t vec = (size_t)(3 * D + 3 * D + MAXF + 5 * D) * 4;   // bqkv, (b_o, LN3), b1, epilogue
+  static constexpr size_t bytes = w + vec;
+  static_assert(bytes <= 80 * 1024, "two workgroups per CU");
+};
+
+struct UserMlpArgs {
+  const bf16* Wqkv;
+  const float* bqkv;
+  const bf16* Wo;
+  const float* bo;
+  const float* ln3_g;
+  const float* ln3_b;
+  const bf16* W1;
+  const float* b1;
+  const bf16* W2;
+  int F;
+  GemmArgs g;   // A = out = XN, R, bias = b2, next LayerNorm (or final LayerNorm + proj_w / proj_out)
+};
+
+// The residual stream of the wave's tokens is final in acc2 (register layout
+// as in m3_residual_epilogue, TB = 1): write it to R, then the next
+// LayerNorm into g.out or (PROJ) the final LayerNorm and the 2-way
+// projection into g.proj_out.
+template <int D, bool PROJ>
+__device__ __forceinline__ void m3_epilogue_final(f32x16 (&acc2)[D / 32][1], int tok, const GemmArgs& g, int g2,
+                                                  const float* sv) {
+  constexpr int OBK = D / 32;
+  const float* slg = sv + D;
+  const float* slb = sv + 2 * D;
+  const bool tv = tok >= 0;
+  float* Rrow = g.R + (long)(tv ? tok : 0) * D;
+  float sum = 0.f;
+#pragma unroll
+  for (int b = 0; b < OBK; ++b)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int f = 32 * b + 8 * q + 4 * g2;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sum += acc2[b][0][4 * q + i];
+      if (tv)
+        *(f32x4*)(Rrow + f) = f32x4{acc2[b][0][4 * q], acc2[b][0][4 * q + 1], acc2[b][0][4 * q + 2],
+                                    acc2[b][0][4 * q + 3]};
+    }
+  sum += __shfl_xor(sum, 32, 64);
+  const float mean = sum / (float)D;
+  float qv = 0.f;
+#pragma unroll
+  for (int b = 0; b < OBK; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float dv = acc2[b][0][r] - mean;
+      qv = fmaf(dv, dv, qv);
+    }
+  qv += __shfl_xor(qv, 32, 64);
+  const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
+  if (!PROJ) {
+    if (tv) {
+      bf16* xo = (bf16*)g.out + (long)tok * D;
+#pragma unroll
+      for (int b = 0; b < OBK; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int f = 32 * b + 8 * q + 4 * g2;
+          const f32x4 lg = *(const f32x4*)&slg[f];
+          const f32x4 lb = *(const f32x4*)&slb[f];
+          bf16x4 h;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) h[i] = (bf16)((acc2[b][0][4 * q + i] - mean) * rstd * lg[i] + lb[i]);
+          *(bf16x4*)(xo + f) = h;
+        }
+    }
+  } else {
+    const float* sp0 = sv + 3 * D;
+    const float* sp1 = sv + 4 * D;
+    float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+    for (int b = 0; b < OBK; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int f = 32 * b + 8 * q + 4 * g2;
+        const f32x4 lg = *(const f32x4*)&slg[f];
+        const f32x4 lb = *(const f32x4*)&slb[f];
+        const f32x4 w0 = *(const f32x4*)&sp0[f];
+        const f32x4 w1 = *(const f32x4*)&sp1[f];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float hv = (acc2[b][0][4 * q + i] - mean) * rstd * lg[i] + lb[i];
+          a0 = fmaf(hv, w0[i], a0);
+          a1 = fmaf(hv, w1[i], a1);
+        }
+      }
+    a0 += __shfl_xor(a0, 32, 64);
+    a1 += __shfl_xor(a1, 32, 64);
+    if (tv && g2 == 0) {
+      g.proj_out[2 * (long)tok] = a0;
+      g.proj_out[2 * (long)tok + 1] = a1;
+    }
+  }
+}
+
+template <int D, int NW, int NBUF, int MAXF, bool PROJ>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_user_mlp_tr(StepCtx c, UserMlpArgs a) {
+  using S = UMSmem<D, NBUF, MAXF>;
+  using U = UBSmem<D>;
+  using M = typename S::M;
+  constexpr int RB1 = U::RB1, RB2 = U::RB2, KS = D / 16, NP = D / 32, OBK = D / 32, NTHR = NW * 64;
+  constexpr int U1 = (int)((U::w1 + 1023) / 1024), U2 = (int)((U::w2 + 1023) / 1024);
+  constexpr int MRB1 = M::RB1, MRB2 = M::RB2;
+  constexpr int N1 = (int)((M::w1 + 1023) / 1024), N2 = (int)((M::w2 + 1023) / 1024);
+  __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
+  char* su1 = smem;                                 // user: Wqkv rows of the pair
+  char* su2 = smem + U::w1a;                        // user: W_o columns of the pair
+  float* sbias = (float*)(smem + S::w);             // bqkv [3D]
+  float* svu = sbias + 3 * D;                       // b_o, LN3 gain, LN3 bias
+  float* sb1 = svu + 3 * D;                         // b1 [MAXF]
+  float* svm = sb1 + MAXF;                          // b2, next LayerNorm, projection rows
+  const GemmArgs& g = a.g;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
+  const int F = a.F, nch = F / kM3FCH;
+
+  // ---- this lane's slot of the wave's group
+  const int gi = blockIdx.x * NW + wave;
+  int tok = -1, K = 1;
+  if (gi < c.total_ugrp32) {
+    const int bi = c.ugrp32[2 * gi], c0 = c.ugrp32[2 * gi + 1];
+    const DevBin& b = c.bins[bi];
+    K = b.K;
+    const int C = 32 / K, cl = l32 / K, k = l32 - cl * K;
+    if (l32 < C * K && c0 + cl < b.n) tok = b.tok_off + k * b.n + c0 + cl;
+  }
+  const unsigned long long vmask = __ballot(tok >= 0);
+  unsigned okbits = 0;                               // register r of S^T: key slot 8(r/4) + 4 g2 + r%4
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int kr = 8 * (r >> 2) + 4 * g2 + (r & 3);
+    if (((vmask >> kr) & 1ull) && kr / K == l32 / K) okbits |= 1u << r;
+  }
+
+  // ---- user-sublayer weights of head pair p (per-wave DMA counts uniform)
+  const int nu1 = U1 / NW + (wave < U1 % NW ? 1 : 0), nu2 = U2 / NW + (wave < U2 % NW ? 1 : 0);
+  auto dma_qkv = [&](int p) {
+#pragma unroll
+    for (int k = 0; k < (U1 + NW - 1) / NW; ++k) {
+      const int u = wave + NW * k;
+      if (u >= U1) break;
+      const int pos = u * 1024 + lane * 16, j = pos / RB1, o = pos - j * RB1;
+      const bool data = o < RB1 - 16;
+      const int jj = data ? j : 0;
+      const bf16* src = a.Wqkv + (long)((jj >> 5) * D + 32 * p + (jj & 31)) * D + (data ? o / 2 : 0);
+      if (pos < (int)U::w1)
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(su1 + u * 1024), 16, 0, 0);
+    }
+  };
+  auto dma_o = [&](int p) {
+#pragma unroll
+    for (int k = 0; k < (U2 + NW - 1) / NW; ++k) {
+      const int u = wave + NW * k;
+      if (u >= U2) break;
+      const int pos = u * 1024 + lane * 16, j = pos / RB2, o = pos - j * RB2;
+      const bool data = o < RB2 - 16;
+      const bf16* src = a.Wo + (long)(data ? j : 0) * D + 32 * p + (data ? o / 2 : 0);
+      if (pos < (int)U::w2)
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(su2 + u * 1024), 16, 0, 0);
+    }
+  };
+  // ---- MLP chunk c -> ring buffer
+  const int nwm = (N1 + N2) / NW + (wave < (N1 + N2) % NW ? 1 : 0);
+  auto dma_m = [&](int ch, int buf) {
+    const int c0 = ch * kM3FCH;
+    char* base = smem + buf * M::buf;
+#pragma unroll
+    for (int k = 0; k < (N1 + N2 + NW - 1) / NW; ++k) {
+      const int u = wave + NW * k;
+      if (u >= N1 + N2) break;
+      const bool first = u < N1;
+      const int pos = (first ? u : u - N1) * 1024 + lane * 16;
+      const int rb = first ? MRB1 : MRB2;
+      const int j = pos / rb, o = pos - j * rb;
+      const bool data = o < rb - 16;
+      const bf16* src;
+      if (first) src = a.W1 + (long)(c0 + m3_sigma(data ? j : 0)) * D + (data ? o / 2 : 0);
+      else src = a.W2 + (long)(data ? j : 0) * F + c0 + (data ? o / 2 : 0);
+      char* dst = base + (first ? 0 : (int)M::w1a) + (pos - lane * 16);
+      if (pos < (first ? (int)M::w1 : (int)M::w2))
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+    }
+  };
+
+  for (int i = tid; i < 3 * D; i += NTHR) sbias[i] = a.bqkv[i];
+  for (int i = tid; i < D; i += NTHR) {
+    svu[i] = a.bo[i];
+    svu[D + i] = a.ln3_g[i];
+    svu[2 * D + i] = a.ln3_b[i];
+  }
+  for (int i = tid; i < F; i += NTHR) sb1[i] = a.b1[i];
+  m3_stage_vectors<D>(svm, g, PROJ, tid, NTHR);
+  const bf16* __restrict__ XN = (const bf16*)g.A;
+  bf16x8 xf[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s)
+    xf[s] = tok >= 0 ? *(const bf16x8*)(XN + (long)tok * D + 16 * s + 8 * g2) : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+  dma_qkv(0);
+  dma_o(0);
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // staged vectors written (visible after the first barrier)
+
+  // ================= user sublayer (see k_user_block_tr) =================
+  const float scale = 1.4426950408889634f / 4.0f;     // log2(e) / sqrt(16)
+  f32x16 acc2[OBK][1];
+#pragma unroll
+  for (int ob = 0; ob < OBK; ++ob)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc2[ob][0][r] = 0.f;
+#pragma unroll 1
+  for (int p = 0; p < NP; ++p) {
+    m3_wait_barrier(nu2);                            // Wqkv of pair p in LDS (W_o of p may be in flight)
+    f32x16 aq, ak, av;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) aq[r] = ak[r] = av[r] = 0.f;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const bf16x8 wq = *(const bf16x8*)(su1 + l32 * RB1 + (2 * s + g2) * 16);
+      const bf16x8 wk = *(const bf16x8*)(su1 + (32 + l32) * RB1 + (2 * s + g2) * 16);
+      const bf16x8 wv = *(const bf16x8*)(su1 + (64 + l32) * RB1 + (2 * s + g2) * 16);
+      aq = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wq, xf[s], aq, 0, 0, 0);
+      ak = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wk, xf[s], ak, 0, 0, 0);
+      av = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xf[s], wv, av, 0, 0, 0);
+    }
+    bf16x8 qf[2], kf[2], vf[2];
+    const float bv = sbias[2 * D + 32 * p + l32];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int f = 32 * p + 8 * q + 4 * g2;
+      const f32x4 bq = *(const f32x4*)&sbias[f];
+      const f32x4 bk = *(const f32x4*)&sbias[D + f];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 4 * q + i;
+        qf[r >> 3][r & 7] = (bf16)(aq[r] + bq[i]);
+        kf[r >> 3][r & 7] = (bf16)(ak[r] + bk[i]);
+        vf[r >> 3][r & 7] = (bf16)(av[r] + bv);
+      }
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();                   // every wave is done with the Wqkv buffer
+    asm volatile("" ::: "memory");
+    if (p + 1 < NP) dma_qkv(p + 1);
+    f32x16 ob;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      f32x16 st;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) st[r] = 0.f;
+      st = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kf[e], qf[e], st, 0, 0, 0);
+      float mx = -INFINITY;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        st[r] = ((okbits >> r) & 1u) ? st[r] : -INFINITY;
+        mx = fmaxf(mx, st[r]);
+      }
+      mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+      const float mxs = mx == -INFINITY ? 0.f : -mx * scale;   // a padding query has no valid key
+      float ps = 0.f;
+      bf16x8 pf[2];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float pv = __builtin_amdgcn_exp2f(fmaf(st[r], scale, mxs));
+        ps += pv;
+        pf[r >> 3][r & 7] = (bf16)pv;
+      }
+      ps += __shfl_xor(ps, 32, 64);
+      f32x16 o;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) o[r] = 0.f;
+      o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vf[0], pf[0], o, 0, 0, 0);
+      o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vf[1], pf[1], o, 0, 0, 0);
+      const float inv = ps > 0.f ? 1.0f / ps : 0.f;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) ob[8 * e + r] = o[8 * e + r] * inv;
+    }
+    // W_o of pair p in LDS (the Wqkv DMA of pair p + 1 may be in flight)
+    m3_wait_barrier(p + 1 < NP ? nu1 : 0);
+    bf16x8 of[2];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) of[r >> 3][r & 7] = (bf16)ob[r];
+#pragma unroll
+    for (int bo = 0; bo < OBK; ++bo)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const char* wr = su2 + (32 * bo + l32) * RB2;
+        const bf16x4 a0 = *(const bf16x4*)(wr + (16 * s + 4 * g2) * 2);
+        const bf16x4 a1 = *(const bf16x4*)(wr + (16 * s + 8 + 4 * g2) * 2);
+        const bf16x8 w = bf16x8{a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+        acc2[bo][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, of[s], acc2[bo][0], 0, 0, 0);
+      }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();                   // every wave is done with the W_o buffer
+    asm volatile("" ::: "memory");
+    if (p + 1 < NP) dma_o(p + 1);
+  }
+  // the user weights are dead: the MLP ring takes the region
+  const int pre = min(NBUF - 1, nch);
+  for (int ch = 0; ch < pre; ++ch) dma_m(ch, ch);
+
+  // ---- R1 = R + acc2 + b_o in place, X1 = LN3(R1) as the up projection's B
+  // operand; acc2 then starts the MLP at R1 + b2, so the down projection
+  // accumulates the final residual directly
+  bf16x8 x1[KS];
+  {
+    const bool tv = tok >= 0;
+    const float* Rrow = g.R + (long)(tv ? tok : 0) * D;
+    float sum = 0.f;
+#pragma unroll
+    for (int b = 0; b < OBK; ++b) {
+      f32x4 rr[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        rr[q] = tv ? *(const f32x4*)(Rrow + 32 * b + 8 * q + 4 * g2) : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f32x4 bias = *(const f32x4*)&svu[32 * b + 8 * q + 4 * g2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float res = rr[q][i] + (acc2[b][0][4 * q + i] + bias[i]);
+          acc2[b][0][4 * q + i] = res;
+          sum += res;
+        }
+      }
+      // finish this block before the next block's loads (bounds the registers in flight)
+      asm volatile("" : "+v"(acc2[b][0]), "+v"(sum)::"memory");
+    }
+    sum += __shfl_xor(sum, 32, 64);
+    const float mean = sum / (float)D;
+    float qv = 0.f;
+#pragma unroll
+    for (int b = 0; b < OBK; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float dv = acc2[b][0][r] - mean;
+        qv = fmaf(dv, dv, qv);
+      }
+    qv += __shfl_xor(qv, 32, 64);
+    const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
+    // k-step s of the up projection: registers 8(s%2) .. 8(s%2) + 7 of block s/2
+#pragma unroll
+    for (int b = 0; b < OBK; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int f = 32 * b + 8 * q + 4 * g2;
+        const f32x4 lg = *(const f32x4*)&svu[D + f];
+        const f32x4 lb = *(const f32x4*)&svu[2 * D + f];
+        const f32x4 b2 = *(const f32x4*)&svm[f];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          x1[2 * b + (q >> 1)][4 * (q & 1) + i] = (bf16)((acc2[b][0][4 * q + i] - mean) * rstd * lg[i] + lb[i]);
+          acc2[b][0][4 * q + i] += b2[i];
+        }
+        if (q & 1) asm volatile("" : "+v"(x1[2 * b + (q >> 1)]), "+v"(acc2[b][0])::"memory");
+      }
+  }
+
+  // ================= MLP (one chunk of 32 hidden units at a time) =================
+  m3_wait_barrier(nwm * max(0, pre - 1));           // chunk 0 in LDS
+#pragma unroll 1
+  for (int ch = 0; ch < nch; ++ch) {
+    // buffer (ch + NBUF - 1) % NBUF was last read in iteration ch - 1, before its closing barrier
+    if (ch + NBUF - 1 < nch) dma_m(ch + NBUF - 1, (ch + NBUF - 1) % NBUF);
+    const char* s1 = smem + (ch % NBUF) * M::buf;
+    const char* s2 = s1 + M::w1a;
+    const float* sb = sb1 + ch * kM3FCH;
+    f32x16 acc1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const f32x4 bq = *(const f32x4*)&sb[16 * (q >> 1) + 8 * g2 + 4 * (q & 1)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc1[4 * q + i] = bq[i];
+    }
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      // W1 k-values in X1's order: 16 s + 4 g2 + j, then 16 s + 8 + 4 g2 + j
+      const char* wr = s1 + l32 * MRB1;
+      const bf16x4 a0 = *(const bf16x4*)(wr + (16 * s + 4 * g2) * 2);
+      const bf16x4 a1 = *(const bf16x4*)(wr + (16 * s + 8 + 4 * g2) * 2);
+      const bf16x8 w = bf16x8{a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, x1[s], acc1, 0, 0, 0);
+    }
+    bf16x8 hf[2];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) hf[q >> 1][4 * (q & 1) + i] = (bf16)gelu_f(acc1[4 * q + i]);
+#pragma unroll
+    for (int b = 0; b < OBK; ++b)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const bf16x8 w = *(const bf16x8*)(s2 + (32 * b + l32) * MRB2 + (2 * s + g2) * 16);
+        acc2[b][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, hf[s], acc2[b][0], 0, 0, 0);
+      }
+    // chunk ch + 1 complete in every wave: later chunks (at most NBUF - 2) may be in flight
+    if (ch + 1 < nch) m3_wait_barrier(nwm * (min(ch + NBUF - 1, nch - 1) - (ch + 1)));
+  }
+  m3_epilogue_final<D, PROJ>(acc2, tok, g, g2, svm);
+}
+
+// ---------------------------------------------------------------------------
 // Module A for the BF16 path, from the symbol grid to the first LayerNorm in
 // one token-resident kernel (method section, Module A; Appendix, one-step
 // algorithm):
@@ -1715,6 +2143,29 @@ hipError_t launch_mlp3_bf16(const GemmArgs& g, const Mat& W1, const float* b1, c
     return mlp3_t<128, 1, 8, 2, 4, true, 1>(g, W1.b16, b1, W2.b16, F, s);
   }
   return mlp3_t<256, 1, 8, 2, 3, false>(g, W1.b16, b1, W2.b16, F, s);
+}
+
+bool user_mlp_tr_ok(int d, int heads, int F) { return d == 128 && heads * 16 == d && F % kM3FCH == 0 && F >= 64 && F <= 512; }
+
+// The user-attention sublayer and the MLP of one layer (BF16, d = 128, head
+// width 16, hidden width <= 512): R and XN in, R and XN (or, with
+// g.proj_out set, lbar) out.  Groups from c.ugrp32.
+hipError_t launch_user_mlp_tr(const StepCtx& c, void* XN, const DevLayer& L, const GemmArgs& g2, int d, int heads,
+                              int F, hipStream_t s) {
+  if (c.total_ugrp32 == 0) return hipSuccess;
+  if (!user_mlp_tr_ok(d, heads, F) || !c.ugrp32 || !L.Wqkv_u.b16 || !L.Wo_u.b16 || !L.W1.b16 || !L.W2.b16)
+    return hipErrorInvalidValue;
+  UserMlpArgs a{};
+  a.Wqkv = L.Wqkv_u.b16; a.bqkv = L.bqkv_u; a.Wo = L.Wo_u.b16; a.bo = L.bo_u;
+  a.ln3_g = L.ln3_g; a.ln3_b = L.ln3_b;
+  a.W1 = L.W1.b16; a.b1 = L.b1; a.W2 = L.W2.b16; a.F = F;
+  a.g = g2;
+  a.g.A = XN;
+  a.g.M = c.total_tokens;
+  const dim3 grid((c.total_ugrp32 + 3) / 4), block(256);
+  if (g2.proj_out) hipLaunchKernelGGL((k_user_mlp_tr<128, 4, 3, 512, true>), grid, block, 0, s, c, a);
+  else hipLaunchKernelGGL((k_user_mlp_tr<128, 4, 3, 512, false>), grid, block, 0, s, c, a);
+  return hipGetLastError();
 }
 
 bool row_qkv_attn_ok(int d, int heads, int max_n) { return d == 256 && heads * 32 == d && max_n <= 256; }
