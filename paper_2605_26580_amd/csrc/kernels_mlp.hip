@@ -1022,8 +1022,11 @@ struct RBSmem {
   static constexpr size_t w2 = (size_t)D * RB2;
   static constexpr size_t w1a = (w1 + 15) / 16 * 16;
   static constexpr size_t w2a = (w2 + 15) / 16 * 16;
-  static constexpr int LDK = 32 + 8;                   // K row: the pair's 32 features + pad (bf16)
-  static constexpr int LDV = 128 + 8;                  // V^T row: 128 keys + pad (bf16)
+  // tile pitches of 18 and 66 dwords: the 8-byte accesses of 32 lanes to 32
+  // consecutive rows then cover all 64 banks once (a pitch that is a
+  // multiple of 4 dwords puts rows l and l + 16 on the same banks)
+  static constexpr int LDK = 32 + 4;                   // K row: the pair's 32 features + pad (bf16)
+  static constexpr int LDV = 128 + 4;                  // V^T row: 128 keys + pad (bf16)
   static constexpr size_t k = (size_t)128 * LDK * 2;
   static constexpr size_t vt = (size_t)32 * LDV * 2;
   static constexpr size_t vec = (size_t)8 * D * 4;     // bqkv [3D], then the epilogue vectors [5D]
@@ -1242,8 +1245,9 @@ struct RQSmem {
   static constexpr int RB = D * 2 + 16;                // bytes per stored weight row
   static constexpr size_t w = (size_t)96 * RB;
   static constexpr size_t wa = (w + 15) / 16 * 16;
-  static constexpr int LDK = 32 + 8;                   // K row: the head's 32 features + pad (bf16)
-  static constexpr int LDV = 256 + 8;                  // V^T row: 256 keys + pad (bf16)
+  // tile pitches of 18 and 130 dwords (see RBSmem)
+  static constexpr int LDK = 32 + 4;                   // K row: the head's 32 features + pad (bf16)
+  static constexpr int LDV = 256 + 4;                  // V^T row: 256 keys + pad (bf16)
   static constexpr size_t k = (size_t)256 * LDK * 2;
   static constexpr size_t vt = (size_t)32 * LDV * 2;
   static constexpr size_t bias = (size_t)3 * D * 4;
