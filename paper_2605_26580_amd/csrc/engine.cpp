@@ -403,6 +403,10 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
   const bool blk_row = prec == kBF16 && r.use_blocks && attn_block_ok(d, m.heads, c.max_n, false);
   const bool blk_user = prec == kBF16 && r.use_blocks && attn_block_ok(d, m.heads, c.max_n, true);
   const bool user_mlp = prec == kBF16 && r.use_blocks && user_mlp_tr_ok(d, m.heads, F);
+  // d = 256: the user-attention output projection runs with the MLP (needs the fused
+  // QKV + user attention, which leaves O in k.O)
+  const bool oproj_mlp = prec == kBF16 && r.use_blocks && !user_mlp && user_qkv_attn_ok(d, m.heads) &&
+                         oproj_mlp3_ok(d, F);
   GemmArgs g{};
   g.M = T;
   // BF16 at d = 128: embedding, Module A and the first LayerNorm in one kernel
@@ -481,10 +485,12 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
         if (prec == kF32) TIMED("attn_user", launch_user_attn(c, prec, k.QKV, k.O, d, m.heads, s));
         else TIMED("attn_user", launch_user_attn_mfma(c, k.QKV, k.O, d, m.heads, s));
       }
-      g = GemmArgs{}; g.M = T;
-      g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_u; g.R = k.R;
-      next_ln(g, L.ln3_g, L.ln3_b);
-      TIMED("gemm_o_user", oproj(g, L.Wo_u));
+      if (!oproj_mlp) {
+        g = GemmArgs{}; g.M = T;
+        g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_u; g.R = k.R;
+        next_ln(g, L.ln3_g, L.ln3_b);
+        TIMED("gemm_o_user", oproj(g, L.Wo_u));
+      }
     }
     if (!fused_ln) TIMED("layernorm", ln(L.ln3_g, L.ln3_b));
     if (fused_ln) {
@@ -504,6 +510,10 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
       } else if (user_mlp) {
         // BF16, d = 128, head width 16: user-attention sublayer + MLP, token-resident, one kernel
         TIMED("user_mlp", launch_user_mlp_tr(c, k.XN, L, g, d, m.heads, F, s));
+      } else if (oproj_mlp) {
+        // BF16, d = 256: the user sublayer's output projection + MLP in one kernel (O in, R and XN out)
+        g.A = k.O;
+        TIMED("oproj_mlp", launch_oproj_mlp3_bf16(g, L.Wo_u, L.bo_u, L.ln3_g, L.ln3_b, L.W1, L.b1, L.W2, F, s));
       } else if (mlp3_ok(d, F)) {
         // token-resident MLP: 256 tokens per workgroup, weights streamed once per tile
         TIMED("mlp_fused", launch_mlp3_bf16(g, L.W1, L.b1, L.W2, F, s));

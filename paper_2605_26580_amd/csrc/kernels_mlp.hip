@@ -1846,6 +1846,234 @@ void k_user_mlp_tr(StepCtx c, UserMlpArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// The output projection of an attention sublayer and the MLP that follows,
+// in one token-resident kernel (BF16, d = 256): the residual stream and the
+// LayerNorm output between them stay in registers.
+//   R1 = R + O W_o^T + b_o,  X1 = LN(R1)                    (registers)
+//   R2 = R1 + W2 GELU(W1 X1 + b1) + b2, then the next LayerNorm of R2 into XN
+//   (or, after the last layer, the final LayerNorm and the projection)
+// The output projection is k_oproj3's (W_o columns in 128-wide chunks through
+// LDS, O fragments read one chunk ahead); X1 stays in the output
+// accumulator's layout and the W1 fragments are read in that order (as in
+// k_user_mlp_tr); the MLP accumulator starts at R1 + b2.  The weight buffers
+// of the two phases share one LDS region.  HBM traffic per token: O, R in;
+// R, XN out (12d bytes against 24d for the two kernels).
+template <int D, int NBUF, int MAXF>
+struct OMSmem {
+  using O = O3Smem<D, 128>;
+  using M = M3Smem<D, NBUF, MAXF>;
+  static constexpr size_t wo = 2 * O::wa;
+  static constexpr size_t wm = NBUF * M::buf;
+  static constexpr size_t w = wo > wm ? wo : wm;
+  static constexpr size_t vec = (size_t)(3 * D + MAXF + 5 * D) * 4;   // (b_o, LN), b1, epilogue vectors
+  static constexpr size_t bytes = w + vec;
+  static_assert(bytes <= 160 * 1024, "LDS");
+};
+
+template <int D, int NBUF, int MAXF, bool PROJ>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_oproj_mlp3(GemmArgs g, const bf16* __restrict__ Wo, const float* __restrict__ bo, const float* __restrict__ lnx_g,
+                  const float* __restrict__ lnx_b, const bf16* __restrict__ W1, const float* __restrict__ b1,
+                  const bf16* __restrict__ W2, int F) {
+  constexpr int KCH = 128;
+  using S = OMSmem<D, NBUF, MAXF>;
+  using O = typename S::O;
+  using M = typename S::M;
+  constexpr int NW = 8, RB = O::RB, OBK = D / 32, NCH = O::NCH, KSC = KCH / 16, KS = D / 16;
+  constexpr int NB = (int)(O::wa / 1024), NPW = (NB + NW - 1) / NW;
+  constexpr int MRB1 = M::RB1, MRB2 = M::RB2;
+  constexpr int N1 = (int)((M::w1 + 1023) / 1024), N2 = (int)((M::w2 + 1023) / 1024);
+  __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
+  float* svo = (float*)(smem + S::w);               // b_o, LN gain, LN bias
+  float* sb1 = svo + 3 * D;                         // b1 [MAXF]
+  float* svm = sb1 + MAXF;                          // b2, next LayerNorm, projection rows
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
+  const long tok0 = (long)blockIdx.x * kM3BM + wave * 32 + l32;
+  const bool tv = tok0 < g.M;
+  const int tok = tv ? (int)tok0 : -1;
+  const int nch = F / kM3FCH;
+  const bf16* __restrict__ A = (const bf16*)g.A;
+
+  auto dma_o = [&](int c, int buf) {
+    char* base = smem + buf * O::wa;
+#pragma unroll
+    for (int k = 0; k < NPW; ++k) {
+      const int u = wave + k * NW;
+      if (u >= NB) break;
+      const int pos = u * 1024 + lane * 16, j = pos / RB, o = pos - j * RB;
+      const bool data = o < RB - 16;
+      const bf16* src = Wo + (long)(data ? j : 0) * D + c * KCH + (data ? o / 2 : 0);
+      if (pos < (int)O::w)
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(base + u * 1024), 16, 0, 0);
+    }
+  };
+  auto afrag = [&](int c, bf16x8 (&f)[KSC]) {
+#pragma unroll
+    for (int s = 0; s < KSC; ++s)
+      f[s] = tv ? *(const bf16x8*)(A + tok0 * D + c * KCH + 16 * s + 8 * g2) : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+  };
+  const int nwm = (N1 + N2) / NW + (wave < (N1 + N2) % NW ? 1 : 0);
+  auto dma_m = [&](int ch, int buf) {
+    const int c0 = ch * kM3FCH;
+    char* base = smem + buf * M::buf;
+#pragma unroll
+    for (int k = 0; k < (N1 + N2 + NW - 1) / NW; ++k) {
+      const int u = wave + NW * k;
+      if (u >= N1 + N2) break;
+      const bool first = u < N1;
+      const int pos = (first ? u : u - N1) * 1024 + lane * 16;
+      const int rb = first ? MRB1 : MRB2;
+      const int j = pos / rb, o = pos - j * rb;
+      const bool data = o < rb - 16;
+      const bf16* src;
+      if (first) src = W1 + (long)(c0 + m3_sigma(data ? j : 0)) * D + (data ? o / 2 : 0);
+      else src = W2 + (long)(data ? j : 0) * F + c0 + (data ? o / 2 : 0);
+      char* dst = base + (first ? 0 : (int)M::w1a) + (pos - lane * 16);
+      if (pos < (first ? (int)M::w1 : (int)M::w2))
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+    }
+  };
+
+  for (int i = tid; i < D; i += 512) {
+    svo[i] = bo[i];
+    svo[D + i] = lnx_g[i];
+    svo[2 * D + i] = lnx_b[i];
+  }
+  for (int i = tid; i < F; i += 512) sb1[i] = b1[i];
+  m3_stage_vectors<D>(svm, g, PROJ, tid, 512);
+
+  // ================= output projection (see k_oproj3) =================
+  f32x16 acc2[OBK][1];
+#pragma unroll
+  for (int b = 0; b < OBK; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc2[b][0][r] = 0.f;
+  bf16x8 fa[KSC], fn[KSC];
+  afrag(0, fa);
+  dma_o(0, 0);
+  __syncthreads();
+#pragma unroll 1
+  for (int c = 0; c < NCH; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < NCH) {
+      dma_o(c + 1, buf ^ 1);
+      afrag(c + 1, fn);
+    }
+    const char* sw = smem + buf * O::wa;
+#pragma unroll
+    for (int s = 0; s < KSC; ++s)
+#pragma unroll
+      for (int b = 0; b < OBK; ++b) {
+        const bf16x8 w = *(const bf16x8*)(sw + (32 * b + l32) * RB + (2 * s + g2) * 16);
+        acc2[b][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, fa[s], acc2[b][0], 0, 0, 0);
+      }
+    if (c + 1 < NCH) {
+#pragma unroll
+      for (int s = 0; s < KSC; ++s) fa[s] = fn[s];
+    }
+    __syncthreads();                                // every wave is done with this buffer
+  }
+  // the W_o buffers are dead: the MLP ring takes the region
+  const int pre = min(NBUF - 1, nch);
+  for (int ch = 0; ch < pre; ++ch) dma_m(ch, ch);
+
+  // ---- R1 = R + acc2 + b_o in place, X1 = LN(R1) in the accumulator layout,
+  // then acc2 = R1 + b2
+  bf16x8 x1[KS];
+  {
+    const float* Rrow = g.R + (long)(tv ? tok0 : 0) * D;
+    float sum = 0.f;
+#pragma unroll
+    for (int b = 0; b < OBK; ++b) {
+      f32x4 rr[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        rr[q] = tv ? *(const f32x4*)(Rrow + 32 * b + 8 * q + 4 * g2) : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f32x4 bias = *(const f32x4*)&svo[32 * b + 8 * q + 4 * g2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float res = rr[q][i] + (acc2[b][0][4 * q + i] + bias[i]);
+          acc2[b][0][4 * q + i] = res;
+          sum += res;
+        }
+      }
+      asm volatile("" : "+v"(acc2[b][0]), "+v"(sum)::"memory");   // bounds the loads in flight
+    }
+    sum += __shfl_xor(sum, 32, 64);
+    const float mean = sum / (float)D;
+    float qv = 0.f;
+#pragma unroll
+    for (int b = 0; b < OBK; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float dv = acc2[b][0][r] - mean;
+        qv = fmaf(dv, dv, qv);
+      }
+    qv += __shfl_xor(qv, 32, 64);
+    const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
+#pragma unroll
+    for (int b = 0; b < OBK; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int f = 32 * b + 8 * q + 4 * g2;
+        const f32x4 lg = *(const f32x4*)&svo[D + f];
+        const f32x4 lb = *(const f32x4*)&svo[2 * D + f];
+        const f32x4 b2 = *(const f32x4*)&svm[f];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          x1[2 * b + (q >> 1)][4 * (q & 1) + i] = (bf16)((acc2[b][0][4 * q + i] - mean) * rstd * lg[i] + lb[i]);
+          acc2[b][0][4 * q + i] += b2[i];
+        }
+        if (q & 1) asm volatile("" : "+v"(x1[2 * b + (q >> 1)]), "+v"(acc2[b][0])::"memory");
+      }
+  }
+
+  // ================= MLP (one chunk of 32 hidden units at a time) =================
+  m3_wait_barrier(nwm * max(0, pre - 1));           // chunk 0 in LDS
+#pragma unroll 1
+  for (int ch = 0; ch < nch; ++ch) {
+    // buffer (ch + NBUF - 1) % NBUF was last read in iteration ch - 1, before its closing barrier
+    if (ch + NBUF - 1 < nch) dma_m(ch + NBUF - 1, (ch + NBUF - 1) % NBUF);
+    const char* s1 = smem + (ch % NBUF) * M::buf;
+    const char* s2 = s1 + M::w1a;
+    const float* sb = sb1 + ch * kM3FCH;
+    f32x16 acc1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const f32x4 bq = *(const f32x4*)&sb[16 * (q >> 1) + 8 * g2 + 4 * (q & 1)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc1[4 * q + i] = bq[i];
+    }
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      // W1 k-values in X1's order: 16 s + 4 g2 + j, then 16 s + 8 + 4 g2 + j
+      const char* wr = s1 + l32 * MRB1;
+      const bf16x4 a0 = *(const bf16x4*)(wr + (16 * s + 4 * g2) * 2);
+      const bf16x4 a1 = *(const bf16x4*)(wr + (16 * s + 8 + 4 * g2) * 2);
+      const bf16x8 w = bf16x8{a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, x1[s], acc1, 0, 0, 0);
+    }
+    bf16x8 hf[2];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) hf[q >> 1][4 * (q & 1) + i] = (bf16)gelu_f(acc1[4 * q + i]);
+#pragma unroll
+    for (int b = 0; b < OBK; ++b)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const bf16x8 w = *(const bf16x8*)(s2 + (32 * b + l32) * MRB2 + (2 * s + g2) * 16);
+        acc2[b][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, hf[s], acc2[b][0], 0, 0, 0);
+      }
+    // chunk ch + 1 complete in every wave: later chunks (at most NBUF - 2) may be in flight
+    if (ch + 1 < nch) m3_wait_barrier(nwm * (min(ch + NBUF - 1, nch - 1) - (ch + 1)));
+  }
+  m3_epilogue_final<D, PROJ>(acc2, tok, g, g2, svm);
+}
+
+// ---------------------------------------------------------------------------
 // Module A for the BF16 path, from the symbol grid to the first LayerNorm in
 // one token-resident kernel (method section, Module A; Appendix, one-step
 // algorithm):
@@ -2147,6 +2375,26 @@ hipError_t launch_mlp3_bf16(const GemmArgs& g, const Mat& W1, const float* b1, c
     return mlp3_t<128, 1, 8, 2, 4, true, 1>(g, W1.b16, b1, W2.b16, F, s);
   }
   return mlp3_t<256, 1, 8, 2, 3, false>(g, W1.b16, b1, W2.b16, F, s);
+}
+
+bool oproj_mlp3_ok(int d, int F) { return d == 256 && F % kM3FCH == 0 && F >= 64 && F <= 1024; }
+
+// R += O W_o^T + b_o, X = LN(R) with (lnx_g, lnx_b), then the MLP on X into R
+// with the next LayerNorm (g.ln_g / g.ln_b into g.out) or the final
+// projection (g.proj_w / g.proj_out).  BF16, d = 256.  g.A = O, g.bias = b2.
+hipError_t launch_oproj_mlp3_bf16(const GemmArgs& g, const Mat& Wo, const float* bo, const float* lnx_g,
+                                  const float* lnx_b, const Mat& W1, const float* b1, const Mat& W2, int F,
+                                  hipStream_t s) {
+  if (g.M == 0) return hipSuccess;
+  if (!oproj_mlp3_ok(g.N, F) || !g.ln_g || !Wo.b16 || !W1.b16 || !W2.b16) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((g.M + kM3BM - 1) / kM3BM)), block(512);
+  if (g.proj_out)
+    hipLaunchKernelGGL((k_oproj_mlp3<256, 3, 1024, true>), grid, block, 0, s, g, Wo.b16, bo, lnx_g, lnx_b, W1.b16, b1,
+                       W2.b16, F);
+  else
+    hipLaunchKernelGGL((k_oproj_mlp3<256, 3, 1024, false>), grid, block, 0, s, g, Wo.b16, bo, lnx_g, lnx_b, W1.b16,
+                       b1, W2.b16, F);
+  return hipGetLastError();
 }
 
 bool user_mlp_tr_ok(int d, int heads, int F) { return d == 128 && heads * 16 == d && F % kM3FCH == 0 && F >= 64 && F <= 512; }
