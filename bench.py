@@ -98,7 +98,7 @@ def algorithmic(model, n, K, es: int):
         "attn_row": 4 * n * d, "attn_user": 4 * K * d,
         "attn_block_row": 8 * d * d + 4 * n * d, "attn_block_user": 8 * d * d + 4 * K * d,
         "gate_fused": 6 * d * d, "embed_gate": 6 * d * d, "user_block": 8 * d * d + 4 * K * d, "user_mlp": 8 * d * d + 4 * K * d + 4 * d * F,
-        "oproj_mlp": 2 * d * d + 4 * d * F,
+        "oproj_mlp": 2 * d * d + 4 * d * F, "oproj_user_attn": 8 * d * d + 4 * K * d,
         "row_block": 8 * d * d + 4 * n * d,
         "qkv_attn_user": 6 * d * d + 4 * K * d, "qkv_attn_row": 6 * d * d + 4 * n * d,
     }
@@ -119,6 +119,8 @@ def algorithmic(model, n, K, es: int):
         "user_mlp": 2 * d * es + 8 * d,
         # output projection + MLP: O and R in, R and XN out
         "oproj_mlp": 2 * d * es + 8 * d,
+        # row output projection + user QKV + attention: O_row, R in; R, O_user out
+        "oproj_user_attn": 2 * d * es + 8 * d,
         # QKV projection + user attention: XN in, O out
         "qkv_attn_user": 2 * d * es, "qkv_attn_row": 2 * d * es,
         # gate MLP: [Z ; e] in, residual stream and e read, residual and first XN written

@@ -178,6 +178,10 @@ hipError_t launch_mlp3_bf16(const GemmArgs& g, const Mat& W1, const float* b1, c
 bool attn_block_ok(int d, int heads, int max_n, bool user);
 hipError_t launch_attn_block(const StepCtx& c, bool user, void* XN, const DevLayer& L, const float* ln_g,
                              const float* ln_b, float* R, int d, int heads, hipStream_t s);
+bool oproj_user_attn_ok(int d, int heads);
+hipError_t launch_oproj_user_attn(const StepCtx& c, const void* Orow, const Mat& Wo, const float* bo,
+                                  const float* ln_g, const float* ln_b, float* R, const Mat& Wqkv, const float* bqkv,
+                                  void* O, int d, int heads, hipStream_t s);
 bool oproj_mlp3_ok(int d, int F);
 hipError_t launch_oproj_mlp3_bf16(const GemmArgs& g, const Mat& Wo, const float* bo, const float* lnx_g,
                                   const float* lnx_b, const Mat& W1, const float* b1, const Mat& W2, int F,

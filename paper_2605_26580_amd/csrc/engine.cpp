@@ -407,6 +407,11 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
   // QKV + user attention, which leaves O in k.O)
   const bool oproj_mlp = prec == kBF16 && r.use_blocks && !user_mlp && user_qkv_attn_ok(d, m.heads) &&
                          oproj_mlp3_ok(d, F);
+  // d = 256 with the unfused row sublayer (which leaves O in k.O): its output projection runs
+  // with the user sublayer's QKV projection and attention
+  const bool oproj_user = prec == kBF16 && r.use_blocks && !row_block_tr_ok(d, m.heads, c.max_n) && !blk_row &&
+                          !user_mlp && !user_block_tr_ok(d, m.heads) && !blk_user &&
+                          oproj_user_attn_ok(d, m.heads);
   GemmArgs g{};
   g.M = T;
   // BF16 at d = 128: embedding, Module A and the first LayerNorm in one kernel
@@ -461,10 +466,12 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
         if (prec == kF32) TIMED("attn_row", launch_row_attn(c, prec, k.QKV, k.O, d, m.heads, c.max_n, s));
         else TIMED("attn_row", launch_row_attn_mfma(c, k.QKV, k.O, d, m.heads, c.max_n, s));
       }
-      g = GemmArgs{}; g.M = T;
-      g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_r; g.R = k.R;
-      next_ln(g, L.ln2_g, L.ln2_b);
-      TIMED("gemm_o_row", oproj(g, L.Wo_r));
+      if (!oproj_user) {
+        g = GemmArgs{}; g.M = T;
+        g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_r; g.R = k.R;
+        next_ln(g, L.ln2_g, L.ln2_b);
+        TIMED("gemm_o_row", oproj(g, L.Wo_r));
+      }
     }
     if (!fused_ln) TIMED("layernorm", ln(L.ln2_g, L.ln2_b));
     if (user_mlp) {
@@ -475,7 +482,12 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
     } else if (blk_user) {
       TIMED("attn_block_user", launch_attn_block(c, true, k.XN, L, L.ln3_g, L.ln3_b, k.R, d, m.heads, s));
     } else {
-      if (prec == kBF16 && r.use_blocks && user_qkv_attn_ok(d, m.heads)) {
+      if (oproj_user) {
+        // BF16, d = 256: the row sublayer's output projection (O in k.O, R updated) with the user
+        // sublayer's QKV projection and attention, O_user back into k.O
+        TIMED("oproj_user_attn", launch_oproj_user_attn(c, k.O, L.Wo_r, L.bo_r, L.ln2_g, L.ln2_b, k.R, L.Wqkv_u,
+                                                         L.bqkv_u, k.O, d, m.heads, s));
+      } else if (prec == kBF16 && r.use_blocks && user_qkv_attn_ok(d, m.heads)) {
         // BF16, head width 32: QKV projection and user attention in one kernel
         TIMED("qkv_attn_user", launch_user_qkv_attn(c, k.XN, L.Wqkv_u, L.bqkv_u, k.O, d, m.heads, s));
       } else {
