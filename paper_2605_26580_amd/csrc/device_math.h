@@ -28,4 +28,17 @@ __device__ __forceinline__ float sigmoid_f(float v) {
   return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-v * 1.4426950408889634f));
 }
 
+// Reductions across the two halves of a wave (lanes l and l ^ 32) without a
+// trip through LDS: v_permlane32_swap, applied to x in both operands, returns
+// in every lane the low half's x (first result) and the high half's x (second
+// result) of that lane's position, so both halves get the same value.
+__device__ __forceinline__ float xhalf_max(float x) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+__device__ __forceinline__ float xhalf_sum(float x) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
 }  // namespace cider

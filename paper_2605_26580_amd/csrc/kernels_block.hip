@@ -25,6 +25,7 @@
 // other operand is read with the same assignment, so each MFMA still forms
 // the full dot product.
 #include "cider_internal.h"
+#include "device_math.h"
 
 namespace cider {
 
@@ -199,10 +200,11 @@ __global__ __launch_bounds__(NT * 4) __attribute__((amdgpu_waves_per_eu(USER && 
     const float scale = 1.4426950408889634f / sqrtf((float)DH);
     float kbias[4] = {0.f, 0.f, 0.f, 0.f};       // user attention: -inf off the query's column
     if (USER) {
+      const int col_lo = (l16 / K) * K;          // key slots of this lane's column
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int jk = g4 * 4 + r;
-        const bool ok = sTok[wave * 16 + jk] >= 0 && jk / K == l16 / K;
+        const bool ok = sTok[wave * 16 + jk] >= 0 && (unsigned)(jk - col_lo) < (unsigned)K;
         kbias[r] = ok ? 0.f : -INFINITY;
       }
     }
@@ -242,7 +244,7 @@ __global__ __launch_bounds__(NT * 4) __attribute__((amdgpu_waves_per_eu(USER && 
 #pragma unroll
           for (int r = 0; r < 4; ++r) mx = fmaxf(mx, st[kt][r]);
         mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
-        mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+        mx = xhalf_max(mx);
         const float mxs = -mx * scale;
         float ps = 0.f;
 #pragma unroll
@@ -254,7 +256,7 @@ __global__ __launch_bounds__(NT * 4) __attribute__((amdgpu_waves_per_eu(USER && 
             ps += p;
           }
         ps += __shfl_xor(ps, 16, 64);
-        ps += __shfl_xor(ps, 32, 64);
+        ps = xhalf_sum(ps);
         lsum = ps;
 #pragma unroll
         for (int u = 0; u < NW / 2; ++u) {
@@ -285,7 +287,7 @@ __global__ __launch_bounds__(NT * 4) __attribute__((amdgpu_waves_per_eu(USER && 
           mx = fmaxf(mx, a[r]);
         }
         mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
-        mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+        mx = xhalf_max(mx);
         // a padding query slot has no valid key (mx = -inf): p = 0 for it
         const float mxs = mx == -INFINITY ? 0.f : -mx * scale;
         float ps = 0.f;
@@ -296,7 +298,7 @@ __global__ __launch_bounds__(NT * 4) __attribute__((amdgpu_waves_per_eu(USER && 
           ps += p;
         }
         ps += __shfl_xor(ps, 16, 64);
-        ps += __shfl_xor(ps, 32, 64);
+        ps = xhalf_sum(ps);
         lsum = ps;
         const bf16x4 fp = to_bf16x4(a);
 #pragma unroll
@@ -352,7 +354,7 @@ __global__ __launch_bounds__(NT * 4) __attribute__((amdgpu_waves_per_eu(USER && 
     sum += (res[0] + res[1]) + (res[2] + res[3]);
   }
   sum += __shfl_xor(sum, 16, 64);
-  sum += __shfl_xor(sum, 32, 64);
+  sum = xhalf_sum(sum);
   const float mean = sum / (float)D;
   float q = 0.f;
 #pragma unroll
@@ -363,7 +365,7 @@ __global__ __launch_bounds__(NT * 4) __attribute__((amdgpu_waves_per_eu(USER && 
       q = fmaf(dv, dv, q);
     }
   q += __shfl_xor(q, 16, 64);
-  q += __shfl_xor(q, 32, 64);
+  q = xhalf_sum(q);
   const float rstd = 1.0f / sqrtf(q / (float)D + 1e-5f);
   if (tv) {
     bf16* xrow = XN + (long)tok * D;
@@ -446,10 +448,11 @@ __global__ __launch_bounds__(64) void k_user_attn_mfma(StepCtx c, const bf16* __
   const long tq = slot_tok(l16);                  // this lane's query row and key row
   const bool qv = tq >= 0;
   float kbias[4];
+  const int col_lo = (l16 / K) * K;               // key slots of this lane's column
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int jk = g4 * 4 + r;
-    kbias[r] = (slot_tok(jk) >= 0 && jk / K == l16 / K) ? 0.f : -INFINITY;
+    kbias[r] = (slot_tok(jk) >= 0 && (unsigned)(jk - col_lo) < (unsigned)K) ? 0.f : -INFINITY;
   }
   const float scale = 1.4426950408889634f / sqrtf((float)DH);
   const bf16* qrow = QKV + (qv ? tq : 0) * ld;
@@ -476,7 +479,7 @@ __global__ __launch_bounds__(64) void k_user_attn_mfma(StepCtx c, const bf16* __
       mx = fmaxf(mx, a[r]);
     }
     mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
-    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+    mx = xhalf_max(mx);
     const float mxs = mx == -INFINITY ? 0.f : -mx * scale;
     float ps = 0.f;
 #pragma unroll
@@ -485,7 +488,7 @@ __global__ __launch_bounds__(64) void k_user_attn_mfma(StepCtx c, const bf16* __
       ps += a[r];
     }
     ps += __shfl_xor(ps, 16, 64);
-    ps += __shfl_xor(ps, 32, 64);
+    ps = xhalf_sum(ps);
     const float inv = ps > 0.f ? 1.0f / ps : 0.f;
     const bf16x4 fp = to_bf16x4(a);
 #pragma unroll

@@ -1092,7 +1092,7 @@ __global__ __launch_bounds__(256) void k_row_attn_mfma(StepCtx c, const bf16* __
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) bmax = fmaxf(bmax, st[t][rr]);
       bmax = fmaxf(bmax, __shfl_xor(bmax, 16, 64));
-      bmax = fmaxf(bmax, __shfl_xor(bmax, 32, 64));
+      bmax = xhalf_max(bmax);
       // running max kept in scaled units: p = 2^(scale s - m), one FMA and one v_exp_f32
       const float mnew = fmaxf(mrun, bmax * scale);
       const float corr = __builtin_amdgcn_exp2f(mrun - mnew);
@@ -1106,7 +1106,7 @@ __global__ __launch_bounds__(256) void k_row_attn_mfma(StepCtx c, const bf16* __
           psum += pv;
         }
       psum += __shfl_xor(psum, 16, 64);
-      psum += __shfl_xor(psum, 32, 64);
+      psum = xhalf_sum(psum);
       lsum = lsum * corr + psum;
       mrun = mnew;
 #pragma unroll

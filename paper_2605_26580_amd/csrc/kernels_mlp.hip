@@ -175,7 +175,7 @@ __device__ __forceinline__ void m3_residual_epilogue(f32x16 (&acc2)[D / 32][TB],
           }
       }
     }
-    sum += __shfl_xor(sum, 32, 64);
+    sum = xhalf_sum(sum);
     const float mean = sum / (float)D;
     float qv = 0.f;
 #pragma unroll
@@ -185,7 +185,7 @@ __device__ __forceinline__ void m3_residual_epilogue(f32x16 (&acc2)[D / 32][TB],
         const float dv = acc2[b][t][r] - mean;
         qv = fmaf(dv, dv, qv);
       }
-    qv += __shfl_xor(qv, 32, 64);
+    qv = xhalf_sum(qv);
     const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
     if (!PROJ) {
       if (tv) {
@@ -223,8 +223,8 @@ __device__ __forceinline__ void m3_residual_epilogue(f32x16 (&acc2)[D / 32][TB],
             a1 = fmaf(hv, w1[i], a1);
           }
         }
-      a0 += __shfl_xor(a0, 32, 64);
-      a1 += __shfl_xor(a1, 32, 64);
+      a0 = xhalf_sum(a0);
+      a1 = xhalf_sum(a1);
       if (tv && g2 == 0) {
         g.proj_out[2 * tok] = a0;
         g.proj_out[2 * tok + 1] = a1;
@@ -691,10 +691,11 @@ void k_user_qkv_attn(StepCtx c, const bf16* __restrict__ XN, const bf16* __restr
   // 8(r/4) + 4 g2 + r%4; valid slot in the query's column
   const unsigned long long vmask = __ballot(tok >= 0);
   unsigned okbits = 0;
+  const int col_lo = (l32 / K) * K;                 // key slots of this lane's column: col_lo .. col_lo + K - 1
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int kr = 8 * (r >> 2) + 4 * g2 + (r & 3);
-    if (((vmask >> kr) & 1ull) && kr / K == l32 / K) okbits |= 1u << r;
+    if (((vmask >> kr) & 1ull) && (unsigned)(kr - col_lo) < (unsigned)K) okbits |= 1u << r;
   }
 
   auto dma = [&](int h, int buf) {
@@ -774,7 +775,7 @@ void k_user_qkv_attn(StepCtx c, const bf16* __restrict__ XN, const bf16* __restr
       st[r] = ((okbits >> r) & 1u) ? st[r] : -INFINITY;
       mx = fmaxf(mx, st[r]);
     }
-    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+    mx = xhalf_max(mx);
     // a padding query has no valid key (mx = -inf): p = 0 for it
     const float mxs = mx == -INFINITY ? 0.f : -mx * scale;
     float ps = 0.f;
@@ -785,7 +786,7 @@ void k_user_qkv_attn(StepCtx c, const bf16* __restrict__ XN, const bf16* __restr
       ps += p;
       pf[r >> 3][r & 7] = (bf16)p;
     }
-    ps += __shfl_xor(ps, 32, 64);
+    ps = xhalf_sum(ps);
     f32x16 o;
 #pragma unroll
     for (int r = 0; r < 16; ++r) o[r] = 0.f;
@@ -863,10 +864,11 @@ void k_user_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const
   }
   const unsigned long long vmask = __ballot(tok >= 0);
   unsigned okbits = 0;                               // register r of S^T: key slot 8(r/4) + 4 g2 + r%4
+  const int col_lo = (l32 / K) * K;                 // key slots of this lane's column: col_lo .. col_lo + K - 1
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int kr = 8 * (r >> 2) + 4 * g2 + (r & 3);
-    if (((vmask >> kr) & 1ull) && kr / K == l32 / K) okbits |= 1u << r;
+    if (((vmask >> kr) & 1ull) && (unsigned)(kr - col_lo) < (unsigned)K) okbits |= 1u << r;
   }
 
   // head pair p -> LDS: Wqkv rows (j / 32) D + 32 p + j % 32, W_o columns 32 p .. + 32
@@ -954,7 +956,7 @@ void k_user_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const
         st[r] = ((okbits >> r) & 1u) ? st[r] : -INFINITY;
         mx = fmaxf(mx, st[r]);
       }
-      mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+      mx = xhalf_max(mx);
       // a padding query has no valid key (mx = -inf): p = 0 for it
       const float mxs = mx == -INFINITY ? 0.f : -mx * scale;
       float ps = 0.f;
@@ -965,7 +967,7 @@ void k_user_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const
         ps += pv;
         pf[r >> 3][r & 7] = (bf16)pv;
       }
-      ps += __shfl_xor(ps, 32, 64);
+      ps = xhalf_sum(ps);
       f32x16 o;
 #pragma unroll
       for (int r = 0; r < 16; ++r) o[r] = 0.f;
@@ -1169,7 +1171,7 @@ void k_row_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const 
         float mb = -INFINITY;
 #pragma unroll
         for (int r = 0; r < 16; ++r) mb = fmaxf(mb, st[r]);
-        mb = fmaxf(mb, __shfl_xor(mb, 32, 64));
+        mb = xhalf_max(mb);
         // the running max m moves (and o, ls are rescaled) only when some
         // query's block max exceeds it by more than 8 / scale: until then
         // every p is at most 2^8, which FP32 sums and BF16 P carry exactly
@@ -1198,7 +1200,7 @@ void k_row_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const 
           o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vfr, pf[s], o, 0, 0, 0);
         }
       }
-      ls += __shfl_xor(ls, 32, 64);
+      ls = xhalf_sum(ls);
       const float inv = 1.0f / ls;
 #pragma unroll
       for (int r = 0; r < 8; ++r) ob[8 * e + r] = o[8 * e + r] * inv;
@@ -1375,7 +1377,7 @@ void k_row_qkv_attn(StepCtx c, const bf16* __restrict__ XN, const bf16* __restri
       float mb = -INFINITY;
 #pragma unroll
       for (int r = 0; r < 16; ++r) mb = fmaxf(mb, st[r]);
-      mb = fmaxf(mb, __shfl_xor(mb, 32, 64));
+      mb = xhalf_max(mb);
       // lazy rescale (see k_row_block_tr): m moves only when some query's
       // block max exceeds it by more than 8 / scale; the first block sets it
       if (__ballot(mb > m + 8.0f / scale) != 0ull) {   // wave-uniform
@@ -1402,7 +1404,7 @@ void k_row_qkv_attn(StepCtx c, const bf16* __restrict__ XN, const bf16* __restri
         o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vfr, pf[s], o, 0, 0, 0);
       }
     }
-    ls += __shfl_xor(ls, 32, 64);
+    ls = xhalf_sum(ls);
     const float inv = 1.0f / ls;
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -1484,7 +1486,7 @@ __device__ __forceinline__ void m3_epilogue_final(f32x16 (&acc2)[D / 32][1], int
         *(f32x4*)(Rrow + f) = f32x4{acc2[b][0][4 * q], acc2[b][0][4 * q + 1], acc2[b][0][4 * q + 2],
                                     acc2[b][0][4 * q + 3]};
     }
-  sum += __shfl_xor(sum, 32, 64);
+  sum = xhalf_sum(sum);
   const float mean = sum / (float)D;
   float qv = 0.f;
 #pragma unroll
@@ -1494,7 +1496,7 @@ __device__ __forceinline__ void m3_epilogue_final(f32x16 (&acc2)[D / 32][1], int
       const float dv = acc2[b][0][r] - mean;
       qv = fmaf(dv, dv, qv);
     }
-  qv += __shfl_xor(qv, 32, 64);
+  qv = xhalf_sum(qv);
   const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
   if (!PROJ) {
     if (tv) {
@@ -1532,8 +1534,8 @@ __device__ __forceinline__ void m3_epilogue_final(f32x16 (&acc2)[D / 32][1], int
           a1 = fmaf(hv, w1[i], a1);
         }
       }
-    a0 += __shfl_xor(a0, 32, 64);
-    a1 += __shfl_xor(a1, 32, 64);
+    a0 = xhalf_sum(a0);
+    a1 = xhalf_sum(a1);
     if (tv && g2 == 0) {
       g.proj_out[2 * (long)tok] = a0;
       g.proj_out[2 * (long)tok + 1] = a1;
@@ -1574,10 +1576,11 @@ void k_user_mlp_tr(StepCtx c, UserMlpArgs a) {
   }
   const unsigned long long vmask = __ballot(tok >= 0);
   unsigned okbits = 0;                               // register r of S^T: key slot 8(r/4) + 4 g2 + r%4
+  const int col_lo = (l32 / K) * K;                 // key slots of this lane's column: col_lo .. col_lo + K - 1
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int kr = 8 * (r >> 2) + 4 * g2 + (r & 3);
-    if (((vmask >> kr) & 1ull) && kr / K == l32 / K) okbits |= 1u << r;
+    if (((vmask >> kr) & 1ull) && (unsigned)(kr - col_lo) < (unsigned)K) okbits |= 1u << r;
   }
 
   // ---- user-sublayer weights of head pair p (per-wave DMA counts uniform)
@@ -1701,7 +1704,7 @@ void k_user_mlp_tr(StepCtx c, UserMlpArgs a) {
         st[r] = ((okbits >> r) & 1u) ? st[r] : -INFINITY;
         mx = fmaxf(mx, st[r]);
       }
-      mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+      mx = xhalf_max(mx);
       const float mxs = mx == -INFINITY ? 0.f : -mx * scale;   // a padding query has no valid key
       float ps = 0.f;
       bf16x8 pf[2];
@@ -1711,7 +1714,7 @@ void k_user_mlp_tr(StepCtx c, UserMlpArgs a) {
         ps += pv;
         pf[r >> 3][r & 7] = (bf16)pv;
       }
-      ps += __shfl_xor(ps, 32, 64);
+      ps = xhalf_sum(ps);
       f32x16 o;
 #pragma unroll
       for (int r = 0; r < 16; ++r) o[r] = 0.f;
@@ -1772,7 +1775,7 @@ void k_user_mlp_tr(StepCtx c, UserMlpArgs a) {
       // finish this block before the next block's loads (bounds the registers in flight)
       asm volatile("" : "+v"(acc2[b][0]), "+v"(sum)::"memory");
     }
-    sum += __shfl_xor(sum, 32, 64);
+    sum = xhalf_sum(sum);
     const float mean = sum / (float)D;
     float qv = 0.f;
 #pragma unroll
@@ -1782,7 +1785,7 @@ void k_user_mlp_tr(StepCtx c, UserMlpArgs a) {
         const float dv = acc2[b][0][r] - mean;
         qv = fmaf(dv, dv, qv);
       }
-    qv += __shfl_xor(qv, 32, 64);
+    qv = xhalf_sum(qv);
     const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
     // k-step s of the up projection: registers 8(s%2) .. 8(s%2) + 7 of block s/2
 #pragma unroll
@@ -2001,7 +2004,7 @@ void k_oproj_mlp3(GemmArgs g, const bf16* __restrict__ Wo, const float* __restri
       }
       asm volatile("" : "+v"(acc2[b][0]), "+v"(sum)::"memory");   // bounds the loads in flight
     }
-    sum += __shfl_xor(sum, 32, 64);
+    sum = xhalf_sum(sum);
     const float mean = sum / (float)D;
     float qv = 0.f;
 #pragma unroll
@@ -2011,7 +2014,7 @@ void k_oproj_mlp3(GemmArgs g, const bf16* __restrict__ Wo, const float* __restri
         const float dv = acc2[b][0][r] - mean;
         qv = fmaf(dv, dv, qv);
       }
-    qv += __shfl_xor(qv, 32, 64);
+    qv = xhalf_sum(qv);
     const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
 #pragma unroll
     for (int b = 0; b < OBK; ++b)
@@ -2127,10 +2130,11 @@ void k_oproj_user_attn(StepCtx c, const bf16* __restrict__ Orow, const bf16* __r
   }
   const unsigned long long vmask = __ballot(tok >= 0);
   unsigned okbits = 0;                               // register r of S^T: key slot 8(r/4) + 4 g2 + r%4
+  const int col_lo = (l32 / K) * K;                 // key slots of this lane's column: col_lo .. col_lo + K - 1
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int kr = 8 * (r >> 2) + 4 * g2 + (r & 3);
-    if (((vmask >> kr) & 1ull) && kr / K == l32 / K) okbits |= 1u << r;
+    if (((vmask >> kr) & 1ull) && (unsigned)(kr - col_lo) < (unsigned)K) okbits |= 1u << r;
   }
   const bool tv = tok >= 0;
 
@@ -2234,7 +2238,7 @@ void k_oproj_user_attn(StepCtx c, const bf16* __restrict__ Orow, const bf16* __r
       }
       asm volatile("" : "+v"(acc2[b]), "+v"(sum)::"memory");   // bounds the loads in flight
     }
-    sum += __shfl_xor(sum, 32, 64);
+    sum = xhalf_sum(sum);
     const float mean = sum / (float)D;
     float qv = 0.f;
 #pragma unroll
@@ -2244,7 +2248,7 @@ void k_oproj_user_attn(StepCtx c, const bf16* __restrict__ Orow, const bf16* __r
         const float dv = acc2[b][r] - mean;
         qv = fmaf(dv, dv, qv);
       }
-    qv += __shfl_xor(qv, 32, 64);
+    qv = xhalf_sum(qv);
     const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
 #pragma unroll
     for (int b = 0; b < OBK; ++b)
@@ -2320,7 +2324,7 @@ void k_oproj_user_attn(StepCtx c, const bf16* __restrict__ Orow, const bf16* __r
       st[r] = ((okbits >> r) & 1u) ? st[r] : -INFINITY;
       mx = fmaxf(mx, st[r]);
     }
-    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+    mx = xhalf_max(mx);
     const float mxs = mx == -INFINITY ? 0.f : -mx * scale;   // a padding query has no valid key
     float ps = 0.f;
     bf16x8 pf[2];
@@ -2330,7 +2334,7 @@ void k_oproj_user_attn(StepCtx c, const bf16* __restrict__ Orow, const bf16* __r
       ps += p;
       pf[r >> 3][r & 7] = (bf16)p;
     }
-    ps += __shfl_xor(ps, 32, 64);
+    ps = xhalf_sum(ps);
     f32x16 o;
 #pragma unroll
     for (int r = 0; r < 16; ++r) o[r] = 0.f;
@@ -2570,7 +2574,7 @@ void k_embed_gate3(StepCtx c, EmbedW m, EmbedGateArgs a, int ntiles) {
           *(f32x4*)(Rrow + f) = f32x4{acc2[ob][4 * q], acc2[ob][4 * q + 1], acc2[ob][4 * q + 2], acc2[ob][4 * q + 3]};
         asm volatile("" ::: "memory");            // bound the loads in flight
       }
-    sum += __shfl_xor(sum, 32, 64);
+    sum = xhalf_sum(sum);
     const float mean = sum / (float)D;
     float qv = 0.f;
 #pragma unroll
@@ -2580,7 +2584,7 @@ void k_embed_gate3(StepCtx c, EmbedW m, EmbedGateArgs a, int ntiles) {
         const float dv = acc2[ob][r] - mean;
         qv = fmaf(dv, dv, qv);
       }
-    qv += __shfl_xor(qv, 32, 64);
+    qv = xhalf_sum(qv);
     const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
     if (tv) {
       bf16* xo = a.XN + tok * D;
