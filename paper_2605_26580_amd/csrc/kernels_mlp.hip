@@ -1887,7 +1887,11 @@ void k_oproj_mlp3(GemmArgs g, const bf16* __restrict__ Wo, const float* __restri
   constexpr int MRB1 = M::RB1, MRB2 = M::RB2;
   constexpr int N1 = (int)((M::w1 + 1023) / 1024), N2 = (int)((M::w2 + 1023) / 1024);
   __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
-  float* svo = (float*)(smem + S::w);               // b_o, LN gain, LN bias
+  // the vectors sit at the start of LDS, where one base register plus an
+  // immediate offset reaches each of them; the weight buffers follow
+  static_assert(S::vec % 1024 == 0, "weight region 1 KB aligned");
+  char* const wreg = smem + S::vec;
+  float* svo = (float*)smem;                        // b_o, LN gain, LN bias
   float* sb1 = svo + 3 * D;                         // b1 [MAXF]
   float* svm = sb1 + MAXF;                          // b2, next LayerNorm, projection rows
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
@@ -1898,7 +1902,7 @@ void k_oproj_mlp3(GemmArgs g, const bf16* __restrict__ Wo, const float* __restri
   const bf16* __restrict__ A = (const bf16*)g.A;
 
   auto dma_o = [&](int c, int buf) {
-    char* base = smem + buf * O::wa;
+    char* base = wreg + buf * O::wa;
 #pragma unroll
     for (int k = 0; k < NPW; ++k) {
       const int u = wave + k * NW;
@@ -1918,7 +1922,7 @@ void k_oproj_mlp3(GemmArgs g, const bf16* __restrict__ Wo, const float* __restri
   const int nwm = (N1 + N2) / NW + (wave < (N1 + N2) % NW ? 1 : 0);
   auto dma_m = [&](int ch, int buf) {
     const int c0 = ch * kM3FCH;
-    char* base = smem + buf * M::buf;
+    char* base = wreg + buf * M::buf;
 #pragma unroll
     for (int k = 0; k < (N1 + N2 + NW - 1) / NW; ++k) {
       const int u = wave + NW * k;
@@ -1962,7 +1966,7 @@ void k_oproj_mlp3(GemmArgs g, const bf16* __restrict__ Wo, const float* __restri
       dma_o(c + 1, buf ^ 1);
       afrag(c + 1, fn);
     }
-    const char* sw = smem + buf * O::wa;
+    const char* sw = wreg + buf * O::wa;
 #pragma unroll
     for (int s = 0; s < KSC; ++s)
 #pragma unroll
@@ -2039,7 +2043,7 @@ void k_oproj_mlp3(GemmArgs g, const bf16* __restrict__ Wo, const float* __restri
   for (int ch = 0; ch < nch; ++ch) {
     // buffer (ch + NBUF - 1) % NBUF was last read in iteration ch - 1, before its closing barrier
     if (ch + NBUF - 1 < nch) dma_m(ch + NBUF - 1, (ch + NBUF - 1) % NBUF);
-    const char* s1 = smem + (ch % NBUF) * M::buf;
+    const char* s1 = wreg + (ch % NBUF) * M::buf;
     const char* s2 = s1 + M::w1a;
     const float* sb = sb1 + ch * kM3FCH;
     f32x16 acc1;
@@ -2114,7 +2118,11 @@ void k_oproj_user_attn(StepCtx c, const bf16* __restrict__ Orow, const bf16* __r
   constexpr int RB = U::RB, KS = D / 16, HEADS = D / 32;
   constexpr int NB = (int)((U::w + 1023) / 1024), NPW = (NB + 7) / 8;
   __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
-  float* sbias = (float*)(smem + S::w);             // bqkv [3D]
+  // the vectors sit at the start of LDS, where one base register plus an
+  // immediate offset reaches each of them; the weight buffers follow
+  static_assert(S::vec % 1024 == 0, "weight region 1 KB aligned");
+  char* const wreg = smem + S::vec;
+  float* sbias = (float*)smem;                      // bqkv [3D]
   float* svo = sbias + 3 * D;                       // b_o, LN2 gain, LN2 bias
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
 
@@ -2139,7 +2147,7 @@ void k_oproj_user_attn(StepCtx c, const bf16* __restrict__ Orow, const bf16* __r
   const bool tv = tok >= 0;
 
   auto dma_o = [&](int cc, int buf) {
-    char* base = smem + buf * OS::wa;
+    char* base = wreg + buf * OS::wa;
 #pragma unroll
     for (int k = 0; k < NPWO; ++k) {
       const int u = wave + k * 8;
@@ -2157,7 +2165,7 @@ void k_oproj_user_attn(StepCtx c, const bf16* __restrict__ Orow, const bf16* __r
       f[s] = tv ? *(const bf16x8*)(Orow + (long)tok * D + cc * KCH + 16 * s + 8 * g2) : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
   };
   auto dma = [&](int h, int buf) {
-    char* base = smem + buf * U::wa;
+    char* base = wreg + buf * U::wa;
 #pragma unroll
     for (int k = 0; k < NPW; ++k) {
       const int u = wave + k * 8;                   // uniform over the wave
@@ -2195,7 +2203,7 @@ void k_oproj_user_attn(StepCtx c, const bf16* __restrict__ Orow, const bf16* __r
         dma_o(cc + 1, buf ^ 1);
         afrag(cc + 1, fn);
       }
-      const char* sw = smem + buf * OS::wa;
+      const char* sw = wreg + buf * OS::wa;
 #pragma unroll
       for (int s = 0; s < KSC; ++s)
 #pragma unroll
@@ -2285,7 +2293,7 @@ void k_oproj_user_attn(StepCtx c, const bf16* __restrict__ Orow, const bf16* __r
         for (int q = 0; q < 4; ++q) *(bf16x4*)(orow + (h - HB + hh) * 32 + 8 * q + 4 * g2) = ob[hh][q];
     }
     if (h + 1 < HEADS) dma(h + 1, (h + 1) & 1);
-    const char* sw = smem + (h & 1) * U::wa;
+    const char* sw = wreg + (h & 1) * U::wa;
     f32x16 aq, ak, av;
 #pragma unroll
     for (int r = 0; r < 16; ++r) aq[r] = ak[r] = av[r] = 0.f;
