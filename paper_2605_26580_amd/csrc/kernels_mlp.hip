@@ -1031,8 +1031,9 @@ struct RBSmem {
   static constexpr int LDV = 128 + 4;                  // V^T row: 128 keys + pad (bf16)
   static constexpr size_t k = (size_t)128 * LDK * 2;
   static constexpr size_t vt = (size_t)32 * LDV * 2;
+  static constexpr size_t ones = (size_t)128 * 2 + 16;  // a V^T row of ones: P's row sums on the MFMA
   static constexpr size_t vec = (size_t)8 * D * 4;     // bqkv [3D], then the epilogue vectors [5D]
-  static constexpr size_t bytes = w1a + w2a + k + vt + vec;
+  static constexpr size_t bytes = w1a + w2a + k + vt + ones + vec;
   static_assert(bytes <= 80 * 1024, "two workgroups per CU");
 };
 
@@ -1050,7 +1051,8 @@ void k_row_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const 
   char* sw2 = smem + S::w1a;
   bf16* sK = (bf16*)(smem + S::w1a + S::w2a);
   bf16* sVt = (bf16*)(smem + S::w1a + S::w2a + S::k);
-  float* sbias = (float*)(smem + S::w1a + S::w2a + S::k + S::vt);
+  bf16* sOnes = (bf16*)(smem + S::w1a + S::w2a + S::k + S::vt);
+  float* sbias = (float*)(smem + S::w1a + S::w2a + S::k + S::vt + S::ones);
   float* sv = sbias + 3 * D;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
 
@@ -1089,6 +1091,7 @@ void k_row_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const 
     }
   };
   for (int i = tid; i < 3 * D; i += 256) sbias[i] = bqkv[i];
+  if (tid < 128) sOnes[tid] = (bf16)1.0f;
   m3_stage_vectors<D>(sv, g, false, tid, 256);
   const bf16* __restrict__ A = (const bf16*)g.A;
   bf16x8 xf[KS];
@@ -1148,7 +1151,11 @@ void k_row_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const 
     f32x16 ob;                                       // O of the pair, pair features as Q's
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      float m = -INFINITY, ls = 0.f;
+      // the PV product spans the pair's 32 features; the 16 rows of the other
+      // head take the ones row instead of V^T, so that those output rows hold
+      // the softmax denominator (the sum of the BF16 P that the product used)
+      const bf16* vrow = (l32 >> 4) == e ? &sVt[l32 * LDV] : sOnes;
+      float m = -INFINITY;
       f32x16 o;
 #pragma unroll
       for (int r = 0; r < 16; ++r) o[r] = 0.f;
@@ -1179,7 +1186,6 @@ void k_row_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const 
         if (__ballot(mb > m + 8.0f / scale) != 0ull) {   // wave-uniform
           const float mn = fmaxf(m, mb);
           const float corr = __builtin_amdgcn_exp2f((m - mn) * scale);
-          ls *= corr;
 #pragma unroll
           for (int r = 0; r < 16; ++r) o[r] *= corr;
           m = mn;
@@ -1187,21 +1193,16 @@ void k_row_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const 
         const float mns = -m * scale;
         bf16x8 pf[2];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const float pv = __builtin_amdgcn_exp2f(fmaf(st[r], scale, mns));
-          ls += pv;
-          pf[r >> 3][r & 7] = (bf16)pv;
-        }
+        for (int r = 0; r < 16; ++r) pf[r >> 3][r & 7] = (bf16)__builtin_amdgcn_exp2f(fmaf(st[r], scale, mns));
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
-          const bf16* vr = &sVt[l32 * LDV + 32 * kb + 16 * s + 4 * g2];
+          const bf16* vr = vrow + 32 * kb + 16 * s + 4 * g2;
           const bf16x4 v0 = *(const bf16x4*)vr, v1 = *(const bf16x4*)(vr + 8);
           const bf16x8 vfr = bf16x8{v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
           o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vfr, pf[s], o, 0, 0, 0);
         }
       }
-      ls = xhalf_sum(ls);
-      const float inv = 1.0f / ls;
+      const float inv = 1.0f / o[8 * (1 - e)];     // a ones row of V^T: the denominator
 #pragma unroll
       for (int r = 0; r < 8; ++r) ob[8 * e + r] = o[8 * e + r] * inv;
     }
