@@ -111,6 +111,7 @@ struct DevModel {
   int n_layers, d, heads, mlp_mult, n_max;
   const float *E, *P, *u, *W, *v, *bg1, *bg2, *lnf_g, *lnf_b;
   Mat Wg1, Wg2;
+  const float* ug;      // [2][d]: Wg1[:, d:2d] v_a, the gate's e input folded into two vectors
   DevLayer layer[64];
 };
 
@@ -214,9 +215,12 @@ struct EmbedGateArgs {
   const float* p;       // [slots][2] per-slot beliefs
   float* R;             // [T][d] FP32 residual stream (out)
   bf16* XN;             // [T][d] LayerNorm output (out)
+  const float* ug;      // [2][d]: Wg1's e half times v_a (d = 256 kernel)
 };
 bool embed_gate3_ok(int d);
 hipError_t launch_embed_gate3(const StepCtx& c, const EmbedW& m, const EmbedGateArgs& a, hipStream_t s);
+bool embed_gate_z_ok(int d);
+hipError_t launch_embed_gate_z(const StepCtx& c, const EmbedW& m, const EmbedGateArgs& a, hipStream_t s);
 hipError_t launch_gate_bf16(const GemmArgs& g, const Mat& Wg1, const float* bg1, const Mat& Wg2, hipStream_t s);
 hipError_t launch_gemm_fp8(const GemmArgs& g, const Mat& W, hipStream_t s);
 hipError_t launch_mlp_fp8(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s);

@@ -415,15 +415,16 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
   GemmArgs g{};
   g.M = T;
   // BF16 at d = 128: embedding, Module A and the first LayerNorm in one kernel
-  const bool embed_gate = prec == kBF16 && r.use_blocks && fused_ln && embed_gate3_ok(d);
+  const bool embed_gate = prec == kBF16 && r.use_blocks && fused_ln && (embed_gate3_ok(d) || embed_gate_z_ok(d));
   if (!embed_gate) TIMED("embed_demix", launch_embed_demix(c, w->ew, k, prec, s));
   // gate MLP: H1 = GELU([Z ; e] Wg1^T + bg1); R = g Z + (1 - g) e, g = sigmoid(H1 Wg2^T + bg2)
   if (embed_gate) {
     EmbedGateArgs ea{};
     ea.Wg1 = m.Wg1.b16; ea.bg1 = m.bg1; ea.Wg2 = m.Wg2.b16; ea.bg2 = m.bg2;
     ea.ln_g = m.layer[0].ln1_g; ea.ln_b = m.layer[0].ln1_b;
-    ea.p = k.p; ea.R = k.R; ea.XN = (bf16*)k.XN;
-    TIMED("embed_gate", launch_embed_gate3(c, w->ew, ea, s));
+    ea.p = k.p; ea.R = k.R; ea.XN = (bf16*)k.XN; ea.ug = m.ug;
+    if (embed_gate_z_ok(d)) TIMED("embed_gate", launch_embed_gate_z(c, w->ew, ea, s));
+    else TIMED("embed_gate", launch_embed_gate3(c, w->ew, ea, s));
   } else if (prec == kBF16 && d == 256) {
     // d = 256: the gate MLP as two token-resident kernels (the fused form's
     // [Z ; e] rows and output accumulators exceed the register file)
@@ -968,13 +969,16 @@ int cider_weights_create(const cider_model_cfg* cfg, const float* blob, size_t n
     return CIDER_OK;
   };
   DevModel& m = w->dm;
+  size_t off_v = 0, off_wg1 = 0;
   m.n_layers = cfg->n_layers; m.d = d; m.heads = cfg->heads; m.mlp_mult = cfg->mlp_mult; m.n_max = cfg->n_max;
   int rc = 0;
   m.E = vec(3 * (size_t)d);
   m.P = vec((size_t)cfg->n_max * d);
   m.u = vec(d);
   m.W = vec(2 * (size_t)d);
+  off_v = off;
   m.v = vec(2 * (size_t)d);
+  off_wg1 = off;
   if ((rc = mat(d, 2 * d, &m.Wg1))) goto bad;
   m.bg1 = vec(d);
   if ((rc = mat(d, d, &m.Wg2))) goto bad;
@@ -1000,6 +1004,26 @@ int cider_weights_create(const cider_model_cfg* cfg, const float* blob, size_t n
   m.lnf_g = vec(d);
   m.lnf_b = vec(d);
   if (off != n_floats) { rc = fail(CIDER_EINVAL, "internal layout mismatch"); goto bad; }
+  {
+    // the gate's e input is a combination of the two rows v_a, so its share of
+    // the first gate layer folds into ug[a] = Wg1[:, d:2d] v_a (FP64 sums)
+    std::vector<float> hug(2 * (size_t)d);
+    for (int a = 0; a < 2; ++a)
+      for (int j = 0; j < d; ++j) {
+        double acc = 0.0;
+        for (int i = 0; i < d; ++i)
+          acc += (double)blob[off_wg1 + (size_t)j * 2 * d + d + i] * (double)blob[off_v + (size_t)a * d + i];
+        hug[(size_t)a * d + j] = (float)acc;
+      }
+    void* dug = nullptr;
+    if (hipMalloc(&dug, hug.size() * 4) != hipSuccess) { rc = fail(CIDER_ENOMEM, "weights hipMalloc"); goto bad; }
+    w->allocs.push_back(dug);
+    if (hipMemcpy(dug, hug.data(), hug.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+      rc = fail(CIDER_EDEVICE, "weights copy");
+      goto bad;
+    }
+    m.ug = (const float*)dug;
+  }
   w->ew = EmbedW{d, m.E, m.P, m.u, m.W, m.v, m.lnf_g, m.lnf_b};
   *out = w;
   return CIDER_OK;

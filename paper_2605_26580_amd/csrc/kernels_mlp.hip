@@ -2614,6 +2614,248 @@ void k_embed_gate3(StepCtx c, EmbedW m, EmbedGateArgs a, int ntiles) {
   if (!weights_ready) __syncthreads();            // no tile: drain the DMA before the workgroup ends
 }
 
+// ---------------------------------------------------------------------------
+// Embedding, Module A and the first LayerNorm for the BF16 path at d = 256, in
+// one token-resident kernel.  The gate's input [Z ; e] has e = c0 v_0 + c1 v_1
+// (Q = 2: a per-token combination of two fixed vectors), so its
+// up-projection is Wg1_Z Z + c0 (Wg1_e v_0) + c1 (Wg1_e v_1), with the two
+// products Wg1_e v_a formed once per weight set (exact in real arithmetic;
+// here they enter in FP32 where the two-kernel form rounds e to BF16).  What
+// remains is a d -> d -> d MLP on Z, run as the MLP chunk ring (rows of Wg1_Z
+// and columns of Wg2, 32 hidden units per chunk, through LDS), with the
+// sigmoid gate, the blend R = g Z + (1 - g) e and the first LayerNorm in the
+// epilogue.  Reads the symbols, the per-slot beliefs and the tables; writes R
+// (FP32) and XN (BF16).
+template <int D>
+struct EGZSmem {
+  static constexpr int NBUF = 3;
+  using M = M3Smem<D, NBUF, D>;
+  // E[3], u, v[2], Wg1_e v_a [2], bg1, bg2, LN gain / bias, <E[x], w_a>: at
+  // the start of LDS (one register base plus immediate offsets)
+  static constexpr size_t vec = ((size_t)12 * D * 4 + 8 * 4 + 1023) / 1024 * 1024;
+  static constexpr size_t bytes = vec + NBUF * M::buf;
+  static_assert(bytes <= 160 * 1024, "LDS");
+};
+
+template <int D>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_embed_gate_z(StepCtx c, EmbedW m, EmbedGateArgs a) {
+  using S = EGZSmem<D>;
+  using M = typename S::M;
+  constexpr int NW = 8, NBUF = S::NBUF, NCH = D / kM3FCH, OBK = D / 32, KZ = D / 16;
+  constexpr int MRB1 = M::RB1, MRB2 = M::RB2;
+  constexpr int N1 = (int)((M::w1 + 1023) / 1024), N2 = (int)((M::w2 + 1023) / 1024);
+  static_assert(NCH > NBUF - 1, "the prefetch covers chunks 0 .. NBUF - 2");
+  static_assert(S::vec % 1024 == 0, "weight region 1 KB aligned");
+  __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
+  char* const wreg = smem + S::vec;               // the chunk ring
+  float* sE = (float*)smem;                       // [3][D]
+  float* su = sE + 3 * D;
+  float* sv = su + D;                             // [2][D]
+  float* sug = sv + 2 * D;                        // [2][D]: Wg1_e v_a
+  float* sbg1 = sug + 2 * D;
+  float* sbg2 = sbg1 + D;
+  float* slg = sbg2 + D;
+  float* slb = slg + D;
+  float* sEW = slb + D;                           // [3][2]: <E[x], w_a>
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
+
+  for (int i = tid; i < 3 * D; i += 512) sE[i] = m.E[i];
+  for (int i = tid; i < D; i += 512) {
+    su[i] = m.u[i];
+    sv[i] = m.v[i];
+    sv[D + i] = m.v[D + i];
+    sug[i] = a.ug[i];
+    sug[D + i] = a.ug[D + i];
+    sbg1[i] = a.bg1[i];
+    sbg2[i] = a.bg2[i];
+    slg[i] = a.ln_g[i];
+    slb[i] = a.ln_b[i];
+  }
+  if (wave < 6) {
+    const int x = wave >> 1, al = wave & 1;
+    float acc = 0.f;
+    for (int i = lane; i < D; i += 64) acc = fmaf(m.E[x * D + i], m.W[al * D + i], acc);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) sEW[wave] = acc;
+  }
+  __syncthreads();
+
+  // ---- chunk ch of the gate MLP -> ring buffer: rows 32 ch + sigma(j) of
+  // Wg1's Z half (row stride 2d) and columns 32 ch .. + 32 of Wg2
+  const int nwm = (N1 + N2) / NW + (wave < (N1 + N2) % NW ? 1 : 0);
+  auto dma_m = [&](int ch, int buf) {
+    const int c0 = ch * kM3FCH;
+    char* base = wreg + buf * M::buf;
+#pragma unroll
+    for (int k = 0; k < (N1 + N2 + NW - 1) / NW; ++k) {
+      const int u = wave + NW * k;
+      if (u >= N1 + N2) break;
+      const bool first = u < N1;
+      const int pos = (first ? u : u - N1) * 1024 + lane * 16;
+      const int rb = first ? MRB1 : MRB2;
+      const int j = pos / rb, o = pos - j * rb;
+      const bool data = o < rb - 16;                 // else a pad (copy something in bounds)
+      const bf16* src;
+      if (first) src = a.Wg1 + (long)(c0 + m3_sigma(data ? j : 0)) * (2 * D) + (data ? o / 2 : 0);
+      else src = a.Wg2 + (long)(data ? j : 0) * D + c0 + (data ? o / 2 : 0);
+      char* dst = base + (first ? 0 : (int)M::w1a) + (pos - lane * 16);
+      if (pos < (first ? (int)M::w1 : (int)M::w2))
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+    }
+  };
+  for (int ch = 0; ch < NBUF - 1; ++ch) dma_m(ch, ch);
+
+  // ---- this lane's token: its bin, row k, slot l, symbol, mask ratio and
+  // the demixing coefficients r[k, a] p[l, a]
+  const float inv_tau = 1.0f / c.tau;
+  const long tok = (long)blockIdx.x * kM3BM + wave * 32 + l32;
+  const bool tv = tok < c.total_tokens;
+  const long tq = tv ? tok : c.total_tokens - 1;
+  int b = c.tile_bin[blockIdx.x];
+  while (b + 1 < c.num_bins && tq >= c.bins[b + 1].tok_off) ++b;
+  const DevBin* bp = &c.bins[b];
+  const int K = bp->K, n = bp->n;
+  const int rel = (int)(tq - bp->tok_off), k = rel / n, l = rel - k * n;
+  const float gamma = c.gamma_override >= 0.f ? c.gamma_override : (float)bp->st->masked / (float)(K * n);
+  const uint8_t* Xc = bp->X + l;
+  const int x = min((int)Xc[k * n], kMask);
+  float mx0 = -INFINITY, mx1 = -INFINITY;
+  for (int kk = 0; kk < K; ++kk) {
+    const int xk = min((int)Xc[kk * n], kMask);
+    mx0 = fmaxf(mx0, sEW[2 * xk] * inv_tau);
+    mx1 = fmaxf(mx1, sEW[2 * xk + 1] * inv_tau);
+  }
+  float den0 = 0.f, den1 = 0.f;
+  for (int kk = 0; kk < K; ++kk) {
+    const int xk = min((int)Xc[kk * n], kMask);
+    den0 += expf(sEW[2 * xk] * inv_tau - mx0);
+    den1 += expf(sEW[2 * xk + 1] * inv_tau - mx1);
+  }
+  const int slot = bp->slot_off + l;
+  const float c0 = expf(sEW[2 * x] * inv_tau - mx0) / den0 * a.p[2 * slot];
+  const float c1 = expf(sEW[2 * x + 1] * inv_tau - mx1) / den1 * a.p[2 * slot + 1];
+  const float* Pl = m.P + (long)l * D;
+  const float* Ex = sE + x * D;
+
+  // ---- Z in the B-operand layout: k-step s holds features 16 s + 8 g2 + 0..7
+  bf16x8 xf[KZ];
+#pragma unroll
+  for (int s = 0; s < KZ; ++s) {
+    const int f = 16 * s + 8 * g2;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const f32x4 pq = *(const f32x4*)(Pl + f + 4 * h);
+      const f32x4 eq = *(const f32x4*)(Ex + f + 4 * h);
+      const f32x4 uq = *(const f32x4*)(su + f + 4 * h);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) xf[s][4 * h + i] = (bf16)((eq[i] + pq[i]) + gamma * uq[i]);
+    }
+    asm volatile("" : "+v"(xf[s])::"memory");      // bounds the loads in flight
+  }
+
+  // ---- gate MLP over Z: up (d -> d, + c0 Wg1_e v_0 + c1 Wg1_e v_1, GELU), down (d -> d)
+  f32x16 acc2[OBK];
+#pragma unroll
+  for (int ob = 0; ob < OBK; ++ob)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc2[ob][r] = 0.f;
+  m3_wait_barrier(nwm * (NBUF - 2));              // chunk 0 in LDS
+#pragma unroll 1
+  for (int ch = 0; ch < NCH; ++ch) {
+    // buffer (ch + NBUF - 1) % NBUF was last read in iteration ch - 1, before its closing barrier
+    if (ch + NBUF - 1 < NCH) dma_m(ch + NBUF - 1, (ch + NBUF - 1) % NBUF);
+    const char* s1 = wreg + (ch % NBUF) * M::buf;
+    const char* s2 = s1 + M::w1a;
+    f32x16 acc1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int f = ch * kM3FCH + 16 * (q >> 1) + 8 * g2 + 4 * (q & 1);
+      const f32x4 bq = *(const f32x4*)&sbg1[f];
+      const f32x4 u0 = *(const f32x4*)&sug[f];
+      const f32x4 u1 = *(const f32x4*)&sug[D + f];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc1[4 * q + i] = bq[i] + (c0 * u0[i] + c1 * u1[i]);
+    }
+#pragma unroll
+    for (int s = 0; s < KZ; ++s) {
+      const bf16x8 w = *(const bf16x8*)(s1 + l32 * MRB1 + (2 * s + g2) * 16);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, xf[s], acc1, 0, 0, 0);
+    }
+    bf16x8 hf[2];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) hf[q >> 1][4 * (q & 1) + i] = (bf16)gelu_f(acc1[4 * q + i]);
+#pragma unroll
+    for (int ob = 0; ob < OBK; ++ob)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const bf16x8 w = *(const bf16x8*)(s2 + (32 * ob + l32) * MRB2 + (2 * s + g2) * 16);
+        acc2[ob] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, hf[s], acc2[ob], 0, 0, 0);
+      }
+    // chunk ch + 1 complete in every wave: later chunks (at most NBUF - 2) may be in flight
+    if (ch + 1 < NCH) m3_wait_barrier(nwm * (min(ch + NBUF - 1, NCH - 1) - (ch + 1)));
+  }
+
+  // ---- blend R = g Z + (1 - g) e, then the first LayerNorm.  Lane l holds
+  // output features 32 ob + 8 q + 4 g2 + i of its token in register 4 q + i.
+  float* Rrow = a.R + tq * D;
+  float sum = 0.f;
+#pragma unroll
+  for (int ob = 0; ob < OBK; ++ob)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int f = 32 * ob + 8 * q + 4 * g2;
+      const f32x4 pq = *(const f32x4*)(Pl + f);
+      const f32x4 eq = *(const f32x4*)(Ex + f);
+      const f32x4 uq = *(const f32x4*)(su + f);
+      const f32x4 v0 = *(const f32x4*)(sv + f);
+      const f32x4 v1 = *(const f32x4*)(sv + D + f);
+      const f32x4 bq = *(const f32x4*)(sbg2 + f);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float z = (eq[i] + pq[i]) + gamma * uq[i];
+        const float e = c0 * v0[i] + c1 * v1[i];
+        const float gt = sigmoid_f(acc2[ob][4 * q + i] + bq[i]);
+        const float res = gt * z + (1.0f - gt) * e;
+        acc2[ob][4 * q + i] = res;
+        sum += res;
+      }
+      if (tv)
+        *(f32x4*)(Rrow + f) = f32x4{acc2[ob][4 * q], acc2[ob][4 * q + 1], acc2[ob][4 * q + 2], acc2[ob][4 * q + 3]};
+      asm volatile("" ::: "memory");              // bounds the loads in flight
+    }
+  sum = xhalf_sum(sum);
+  const float mean = sum / (float)D;
+  float qv = 0.f;
+#pragma unroll
+  for (int ob = 0; ob < OBK; ++ob)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float dv = acc2[ob][r] - mean;
+      qv = fmaf(dv, dv, qv);
+    }
+  qv = xhalf_sum(qv);
+  const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
+  if (tv) {
+    bf16* xo = a.XN + tok * D;
+#pragma unroll
+    for (int ob = 0; ob < OBK; ++ob)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int f = 32 * ob + 8 * q + 4 * g2;
+        const f32x4 lg = *(const f32x4*)(slg + f);
+        const f32x4 lb = *(const f32x4*)(slb + f);
+        bf16x4 h;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) h[i] = (bf16)((acc2[ob][4 * q + i] - mean) * rstd * lg[i] + lb[i]);
+        *(bf16x4*)(xo + f) = h;
+      }
+  }
+}
+
 }  // namespace
 
 // out = XN W^T + b (BF16), N a multiple of 32.
@@ -2813,6 +3055,18 @@ hipError_t launch_embed_gate3(const StepCtx& c, const EmbedW& m, const EmbedGate
     return hipErrorInvalidValue;
   const int grid = std::min(ntiles, std::max(ncu, 1));
   hipLaunchKernelGGL((k_embed_gate3<128>), dim3(grid), dim3(512), 0, s, c, m, a, ntiles);
+  return hipGetLastError();
+}
+
+bool embed_gate_z_ok(int d) { return d == 256; }
+
+// Embedding, Module A and the first LayerNorm for the BF16 path (d = 256):
+// writes R (FP32) and XN (BF16) of every token of the batch.
+hipError_t launch_embed_gate_z(const StepCtx& c, const EmbedW& m, const EmbedGateArgs& a, hipStream_t s) {
+  if (c.total_tokens == 0) return hipSuccess;
+  if (!embed_gate_z_ok(m.d) || !c.tile_bin || !a.Wg1 || !a.Wg2 || !a.ug) return hipErrorInvalidValue;
+  const int ntiles = (int)((c.total_tokens + kM3BM - 1) / kM3BM);
+  hipLaunchKernelGGL((k_embed_gate_z<256>), dim3(ntiles), dim3(512), 0, s, c, m, a);
   return hipGetLastError();
 }
 
