@@ -2374,14 +2374,16 @@ void k_oproj_user_attn(StepCtx c, const bf16* __restrict__ Orow, const bf16* __r
 // The rows of one slot differ only in E[x]: P[l] + gamma u is common to them
 // and cancels in the softmax over rows, so r[k, a] is the softmax over the
 // slot's rows of <E[x_k], w_a> / tau, six table values (three symbols, two
-// logits) that each workgroup computes once.  Each lane forms Z and e of its
-// token in registers, straight in the B-operand layout of the up MFMAs, and
-// again in the output layout for the blend: neither reaches HBM.  The whole
-// gate MLP (Wg1: d x 2d, Wg2: d x d) is DMA'd into LDS once per workgroup;
-// a workgroup then walks 256-token tiles.
+// logits) that each workgroup computes once.  Each lane forms Z of its token
+// in registers, straight in the B-operand layout of the up MFMAs, and Z and
+// e again in the output layout for the blend: neither reaches HBM.  Since
+// e = c0 v_0 + c1 v_1, the up projection's e half is c0 (Wg1_e v_0) +
+// c1 (Wg1_e v_1), two vectors formed once per weight set, so only Wg1's Z
+// half (d x d) and Wg2 (d x d) are DMA'd into LDS, once per workgroup; a
+// workgroup then walks 256-token tiles.
 template <int D>
 struct EG3Smem {
-  static constexpr int DIN = 2 * D;
+  static constexpr int DIN = D;                          // the Z half of Wg1's columns
   static constexpr int NCH = D / kM3FCH;                 // the gate's hidden width is d
   static constexpr int RB1 = DIN * 2 + 16;
   static constexpr int RB2 = kM3FCH * 2 + 16;
@@ -2390,9 +2392,10 @@ struct EG3Smem {
   static constexpr size_t w1a = (w1 + 1023) / 1024 * 1024;
   static constexpr size_t w2a = (w2 + 1023) / 1024 * 1024;
   static constexpr size_t buf = w1a + w2a;
-  // E[3], u, v[2], bg1, bg2, LN gain / bias, <E[x], w_a>: at the start of
-  // LDS, so that every vector address is a register base + an immediate
-  static constexpr size_t vec = ((size_t)11 * D * 4 + 8 * 4 + 1023) / 1024 * 1024;
+  // E[3], u, v[2], Wg1_e v_a [2], bg1, bg2, LN gain / bias, <E[x], w_a>: at
+  // the start of LDS, so that every vector address is a register base + an
+  // immediate
+  static constexpr size_t vec = ((size_t)13 * D * 4 + 8 * 4 + 1023) / 1024 * 1024;
   static constexpr size_t bytes = vec + NCH * buf;
   static_assert(bytes <= 160 * 1024, "LDS");
 };
@@ -2410,7 +2413,8 @@ void k_embed_gate3(StepCtx c, EmbedW m, EmbedGateArgs a, int ntiles) {
   float* sE = (float*)smem;                       // [3][D]
   float* su = sE + 3 * D;
   float* sv = su + D;                             // [2][D]
-  float* sbg1 = sv + 2 * D;
+  float* sug = sv + 2 * D;                        // [2][D]: Wg1_e v_a
+  float* sbg1 = sug + 2 * D;
   float* sbg2 = sbg1 + D;
   float* slg = sbg2 + D;
   float* slb = slg + D;
@@ -2422,6 +2426,8 @@ void k_embed_gate3(StepCtx c, EmbedW m, EmbedGateArgs a, int ntiles) {
     su[i] = m.u[i];
     sv[i] = m.v[i];
     sv[D + i] = m.v[D + i];
+    sug[i] = a.ug[i];
+    sug[D + i] = a.ug[D + i];
     sbg1[i] = a.bg1[i];
     sbg2[i] = a.bg2[i];
     slg[i] = a.ln_g[i];
@@ -2437,8 +2443,8 @@ void k_embed_gate3(StepCtx c, EmbedW m, EmbedGateArgs a, int ntiles) {
   }
   __syncthreads();
   // the whole gate MLP -> LDS, 1 KB blocks spread over the waves; chunk ch
-  // holds hidden units 32 ch + sigma(j) of Wg1 (rows padded to RB1 bytes)
-  // and columns 32 ch .. + 32 of Wg2 (rows padded to RB2 bytes)
+  // holds hidden units 32 ch + sigma(j) of Wg1's Z half (rows padded to RB1
+  // bytes) and columns 32 ch .. + 32 of Wg2 (rows padded to RB2 bytes)
   for (int u = wave; u < NB; u += 8) {
     const int ch = u / (N1 + N2), v = u - ch * (N1 + N2);
     const bool first = v < N1;
@@ -2447,7 +2453,7 @@ void k_embed_gate3(StepCtx c, EmbedW m, EmbedGateArgs a, int ntiles) {
     const int j = pos / rb, o = pos - j * rb;
     const bool data = o < rb - 16;                 // else a pad (copy something in bounds)
     const bf16* src;
-    if (first) src = a.Wg1 + (long)(ch * kM3FCH + m3_sigma(data ? j : 0)) * DIN + (data ? o / 2 : 0);
+    if (first) src = a.Wg1 + (long)(ch * kM3FCH + m3_sigma(data ? j : 0)) * (2 * D) + (data ? o / 2 : 0);
     else src = a.Wg2 + (long)(data ? j : 0) * D + ch * kM3FCH + (data ? o / 2 : 0);
     char* dst = wsm + ch * S::buf + (first ? 0 : (int)S::w1a) + (pos - lane * 16);
     if (pos < (first ? (int)S::w1 : (int)S::w2))
@@ -2491,9 +2497,10 @@ void k_embed_gate3(StepCtx c, EmbedW m, EmbedGateArgs a, int ntiles) {
     const float* Pl = m.P + (long)l * D;
     const float* Ex = sE + x * D;
 
-    // ---- [Z ; e] in the B-operand layout: k-step s holds input features
-    // 16 s + 8 g2 + 0..7 (Z for s < d/16, e after)
-    bf16x8 xf[KS1];
+    // ---- Z in the B-operand layout: k-step s holds features 16 s + 8 g2 + 0..7
+    // (e = c0 v_0 + c1 v_1 enters the up projection as c0 Wg1_e v_0 + c1 Wg1_e v_1)
+    static_assert(KS1 == KZ, "the up projection reads Z only");
+    bf16x8 xf[KZ];
 #pragma unroll
     for (int s = 0; s < KZ; ++s) {
       const int f = 16 * s + 8 * g2;
@@ -2502,24 +2509,20 @@ void k_embed_gate3(StepCtx c, EmbedW m, EmbedGateArgs a, int ntiles) {
         const f32x4 pq = *(const f32x4*)(Pl + f + 4 * h);
         const f32x4 eq = *(const f32x4*)(Ex + f + 4 * h);
         const f32x4 uq = *(const f32x4*)(su + f + 4 * h);
-        const f32x4 v0 = *(const f32x4*)(sv + f + 4 * h);
-        const f32x4 v1 = *(const f32x4*)(sv + D + f + 4 * h);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          xf[s][4 * h + i] = (bf16)((eq[i] + pq[i]) + gamma * uq[i]);
-          xf[KZ + s][4 * h + i] = (bf16)(c0 * v0[i] + c1 * v1[i]);
-        }
+        for (int i = 0; i < 4; ++i) xf[s][4 * h + i] = (bf16)((eq[i] + pq[i]) + gamma * uq[i]);
       }
       // finish these fragments before the next loads, so that the loaded
       // vectors die here (bounds the registers in flight)
-      asm volatile("" : "+v"(xf[s]), "+v"(xf[KZ + s])::"memory");
+      asm volatile("" : "+v"(xf[s])::"memory");
     }
     if (!weights_ready) {
       __syncthreads();                            // every wave's weight DMA complete
       weights_ready = true;
     }
 
-    // ---- gate MLP: up (2d -> d, GELU), down (d -> d), all weights in LDS
+    // ---- gate MLP: up (d -> d, + c0 Wg1_e v_0 + c1 Wg1_e v_1, GELU), down
+    // (d -> d), all weights in LDS
     f32x16 acc2[OBK];
 #pragma unroll
     for (int ob = 0; ob < OBK; ++ob)
@@ -2532,9 +2535,12 @@ void k_embed_gate3(StepCtx c, EmbedW m, EmbedGateArgs a, int ntiles) {
       f32x16 acc1;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const f32x4 bq = *(const f32x4*)&sbg1[ch * kM3FCH + 16 * (q >> 1) + 8 * g2 + 4 * (q & 1)];
+        const int f = ch * kM3FCH + 16 * (q >> 1) + 8 * g2 + 4 * (q & 1);
+        const f32x4 bq = *(const f32x4*)&sbg1[f];
+        const f32x4 u0 = *(const f32x4*)&sug[f];
+        const f32x4 u1 = *(const f32x4*)&sug[D + f];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc1[4 * q + i] = bq[i];
+        for (int i = 0; i < 4; ++i) acc1[4 * q + i] = bq[i] + (c0 * u0[i] + c1 * u1[i]);
       }
 #pragma unroll
       for (int s = 0; s < KS1; ++s) {
@@ -3048,7 +3054,7 @@ bool embed_gate3_ok(int d) { return d == 128; }
 // writes R (FP32) and XN (BF16) of every token of the batch.
 hipError_t launch_embed_gate3(const StepCtx& c, const EmbedW& m, const EmbedGateArgs& a, hipStream_t s) {
   if (c.total_tokens == 0) return hipSuccess;
-  if (!embed_gate3_ok(m.d) || !c.tile_bin || !a.Wg1 || !a.Wg2) return hipErrorInvalidValue;
+  if (!embed_gate3_ok(m.d) || !c.tile_bin || !a.Wg1 || !a.Wg2 || !a.ug) return hipErrorInvalidValue;
   const int ntiles = (int)((c.total_tokens + kM3BM - 1) / kM3BM);
   int dev = 0, ncu = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
