@@ -414,7 +414,7 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
                           oproj_user_attn_ok(d, m.heads);
   GemmArgs g{};
   g.M = T;
-  // BF16 at d = 128: embedding, Module A and the first LayerNorm in one kernel
+  // BF16 at d = 128 and 256: embedding, Module A and the first LayerNorm in one kernel
   const bool embed_gate = prec == kBF16 && r.use_blocks && fused_ln && (embed_gate3_ok(d) || embed_gate_z_ok(d));
   if (!embed_gate) TIMED("embed_demix", launch_embed_demix(c, w->ew, k, prec, s));
   // gate MLP: H1 = GELU([Z ; e] Wg1^T + bg1); R = g Z + (1 - g) e, g = sigmoid(H1 Wg2^T + bg2)
@@ -426,8 +426,8 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
     if (embed_gate_z_ok(d)) TIMED("embed_gate", launch_embed_gate_z(c, w->ew, ea, s));
     else TIMED("embed_gate", launch_embed_gate3(c, w->ew, ea, s));
   } else if (prec == kBF16 && d == 256) {
-    // d = 256: the gate MLP as two token-resident kernels (the fused form's
-    // [Z ; e] rows and output accumulators exceed the register file)
+    // d = 256 without the fused blocks: the gate MLP on [Z ; e] as two
+    // token-resident kernels
     g.N = d; g.Kd = 2 * d; g.A = k.ZE; g.bias = m.bg1; g.out = k.H1;
     TIMED("gate1", launch_proj3_bf16(g, m.Wg1, s, true));
     g = GemmArgs{}; g.M = T;
