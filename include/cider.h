@@ -212,6 +212,25 @@ int cider_step_debug(const uint8_t* X_in, uint8_t* X_out, const float* y, float 
 int cider_evidence(const float* y, float sigma2, int32_t K, int32_t n, float* out_S, float* out_p,
                    void* stream);
 
+/* ---- slot-wise AMP-MMSE detector (the non-binary evidence front end) ------
+ * Appendix, slot-wise AMP-MMSE detector and sensing-matrix construction.  For
+ * each slot: Y = A U + noise in C^{n_s}, A[j][a] = exp(-2 pi i R_j a / Q) /
+ * sqrt(n_s) (rows R_j of the Q-point DFT), a Bernoulli-Gaussian prior
+ * (1 - rho) delta_0 + rho CN(0, su2) on each U_a.  Runs `iters` AMP
+ * iterations with the MMSE denoiser and its Onsager correction (effective
+ * noise nu = ||residual||^2 / n_s) and writes S[slot][a] = log Pr(U_a != 0 |
+ * Y) from the final pseudo-observation, FP32.
+ *   y      device float [slots][n_s][2]: Y, real and imaginary parts
+ *   rows   device int32 [slots][n_s]: DFT row indices (taken modulo Q)
+ *   out_S  device float [slots][Q]
+ * 1 <= n_s <= 64, 2 <= Q <= 64, 0 <= slots < 2^31, 0 <= iters <= 10000,
+ * 0 < rho < 1, su2 > 0.  The caller owns every buffer; the call is enqueued
+ * on `stream` (a hipStream_t, NULL = default) and does not synchronise.
+ * CIDER_EINVAL for bad sizes, parameters or NULL pointers (nothing
+ * enqueued), CIDER_EDEVICE if the launch fails. */
+int cider_amp_evidence(const float* y, const int32_t* rows, int64_t slots, int32_t n_s, int32_t Q, float rho,
+                       float su2, int32_t iters, float* out_S, void* stream);
+
 /* ---- serving: continuous batching of arriving bins ---------------------- */
 typedef struct cider_server cider_server;
 

@@ -24,7 +24,7 @@ CIDER_MASK = 2
 EXPORTS = [
     "cider_opts_default", "cider_weights_blob_floats", "cider_weights_create", "cider_weights_destroy",
     "cider_code_create", "cider_code_destroy", "cider_workspace_size", "cider_decode",
-    "cider_decode_batch", "cider_step_debug", "cider_evidence", "cider_server_create",
+    "cider_decode_batch", "cider_step_debug", "cider_evidence", "cider_amp_evidence", "cider_server_create",
     "cider_server_submit", "cider_server_poll", "cider_server_drain", "cider_server_destroy",
     "cider_strerror", "cider_last_error", "cider_profile_read", "cider_tuning_read",
 ]
@@ -108,6 +108,7 @@ def lib() -> C.CDLL:
     L.cider_step_debug.argtypes = [vp, vp, vp, f32, vp, i32, i32, vp, f32, i32, i32,
                                    C.POINTER(cider_opts), vp, vp, vp, vp]
     L.cider_evidence.argtypes = [vp, f32, i32, i32, vp, vp, vp]
+    L.cider_amp_evidence.argtypes = [vp, vp, C.c_int64, i32, i32, f32, f32, i32, vp, vp]
     L.cider_server_create.argtypes = [C.POINTER(cider_server_cfg), C.POINTER(vp)]
     L.cider_server_submit.argtypes = [vp, vp, f32, vp, i32, i32, vp, C.POINTER(C.c_uint64)]
     L.cider_server_poll.argtypes = [vp, C.POINTER(cider_result), i32, C.POINTER(i32)]
@@ -121,9 +122,9 @@ def lib() -> C.CDLL:
     L.cider_last_error.argtypes = []
     L.cider_last_error.restype = C.c_char_p
     for name in ("cider_weights_create", "cider_code_create", "cider_workspace_size", "cider_decode",
-                 "cider_decode_batch", "cider_step_debug", "cider_evidence", "cider_server_create",
-                 "cider_server_submit", "cider_server_poll", "cider_server_drain", "cider_profile_read",
-                 "cider_tuning_read"):
+                 "cider_decode_batch", "cider_step_debug", "cider_evidence", "cider_amp_evidence",
+                 "cider_server_create", "cider_server_submit", "cider_server_poll", "cider_server_drain",
+                 "cider_profile_read", "cider_tuning_read"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -260,6 +261,14 @@ def cider_step_debug(X_in, X_out, y, sigma2: float, code: Code, K: int, n: int, 
                                  float(gamma), int(reveal_count), int(first),
                                  C.byref(opts) if opts is not None else None, _ptr(out_lbar), _ptr(out_logits),
                                  _ptr(out_z), _stream(stream)), "cider_step_debug")
+
+
+def cider_amp_evidence(y, rows, slots: int, n_s: int, Q: int, rho: float, su2: float, iters: int, out_S,
+                       stream=None) -> None:
+    """Slot-wise AMP-MMSE evidence: y float32 [slots][n_s][2], rows int32
+    [slots][n_s], out_S float32 [slots][Q], all device tensors."""
+    check(lib().cider_amp_evidence(_ptr(y), _ptr(rows), int(slots), int(n_s), int(Q), float(rho), float(su2),
+                                   int(iters), _ptr(out_S), _stream(stream)), "cider_amp_evidence")
 
 
 def cider_evidence(y, sigma2: float, K: int, n: int, out_S=None, out_p=None, stream=None) -> None:

@@ -219,6 +219,17 @@ struct EmbedGateArgs {
 };
 bool embed_gate3_ok(int d);
 hipError_t launch_embed_gate3(const StepCtx& c, const EmbedW& m, const EmbedGateArgs& a, hipStream_t s);
+// Slot-wise AMP-MMSE detector (kernels_amp.hip).
+struct AmpArgs {
+  const float* y;        // [slots][ns][2]
+  const int32_t* rows;   // [slots][ns]
+  long slots;
+  int ns, Q;
+  float rho, su2;
+  int iters;
+  float* S;              // [slots][Q]
+};
+hipError_t launch_amp_evidence(const AmpArgs& g, hipStream_t s);
 bool embed_gate_z_ok(int d);
 hipError_t launch_embed_gate_z(const StepCtx& c, const EmbedW& m, const EmbedGateArgs& a, hipStream_t s);
 hipError_t launch_gate_bf16(const GemmArgs& g, const Mat& Wg1, const float* bg1, const Mat& Wg2, hipStream_t s);

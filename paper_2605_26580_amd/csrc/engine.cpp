@@ -1183,6 +1183,20 @@ int cider_step_debug(const uint8_t* X_in, uint8_t* X_out, const float* y, float 
   return CIDER_OK;
 }
 
+int cider_amp_evidence(const float* y, const int32_t* rows, int64_t slots, int32_t n_s, int32_t Q, float rho,
+                       float su2, int32_t iters, float* out_S, void* stream) {
+  if (slots < 0 || slots >= ((int64_t)1 << 31) || n_s < 1 || n_s > 64 || Q < 2 || Q > 64 || iters < 0 ||
+      iters > 10000 || !(rho > 0.f && rho < 1.f) || !(su2 > 0.f) || !std::isfinite(su2))
+    return fail(CIDER_EINVAL, "bad AMP arguments");
+  if (slots > 0 && (!y || !rows || !out_S)) return fail(CIDER_EINVAL, "null AMP buffer");
+  AmpArgs g{};
+  g.y = y; g.rows = rows; g.slots = (long)slots; g.ns = n_s; g.Q = Q;
+  g.rho = rho; g.su2 = su2; g.iters = iters; g.S = out_S;
+  const hipError_t err = launch_amp_evidence(g, (hipStream_t)stream);
+  if (err != hipSuccess) return hip_fail(err, "cider_amp_evidence");
+  return CIDER_OK;
+}
+
 int cider_evidence(const float* y, float sigma2, int32_t K, int32_t n, float* out_S, float* out_p, void* stream) {
   if (!y || K < 1 || K > CIDER_MAX_K || n < 1 || n > CIDER_MAX_N || !(sigma2 > 0.f))
     return fail(CIDER_EINVAL, "bad evidence arguments");

@@ -55,3 +55,18 @@ def test_bad_model_and_code_rejected_on_cpu():
         P.Code(8, 1, np.array([0, 3]), np.array([2, 1, 3]))                      # not ascending
     assert "invalid" in P.cider_strerror(P.abi.CIDER_EINVAL)
 
+
+
+def test_amp_arguments_rejected_on_cpu():
+    """cider_amp_evidence validates before any device work (no GPU needed)."""
+    import paper_2605_26580_amd as P
+    bad = [dict(n_s=0), dict(n_s=65), dict(Q=1), dict(Q=65), dict(iters=-1), dict(rho=0.0), dict(rho=1.0),
+           dict(su2=0.0), dict(slots=-1)]
+    for kw in bad:
+        args = dict(slots=4, n_s=24, Q=64, rho=0.03, su2=2.0, iters=20)
+        args.update(kw)
+        rc = P.abi.lib().cider_amp_evidence(None, None, args["slots"], args["n_s"], args["Q"], args["rho"],
+                                            args["su2"], args["iters"], None, None)
+        assert rc == -1, kw
+    # valid sizes but missing buffers
+    assert P.abi.lib().cider_amp_evidence(None, None, 4, 24, 64, 0.03, 2.0, 20, None, None) == -1
