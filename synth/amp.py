@@ -43,23 +43,24 @@ def make_amp_slots(frames: int, L: int, Q: int, n_s: int, K: int, payload_bits: 
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
     levels = np.atleast_1d(np.asarray(ebn0_db, dtype=np.float64))
     S = frames * L
-    rows = np.empty((S, n_s), dtype=np.int32)
+    # n_s distinct rows per slot: the first n_s of a uniform random permutation
     if shared_rows:
-        rows[:] = np.sort(rng.choice(Q, size=n_s, replace=False))[None, :]
+        rows = np.repeat(np.sort(np.argsort(rng.random(Q))[:n_s])[None, :], S, axis=0).astype(np.int32)
     else:
-        for s in range(S):
-            rows[s] = np.sort(rng.choice(Q, size=n_s, replace=False))
-    counts = np.zeros((S, Q), dtype=np.int32)
+        rows = np.sort(np.argsort(rng.random((S, Q)), axis=1)[:, :n_s], axis=1).astype(np.int32)
     idx = rng.integers(0, Q, size=(S, K))
+    counts = np.zeros((S, Q), dtype=np.int32)
     for k in range(K):
         np.add.at(counts, (np.arange(S), idx[:, k]), 1)
     eb = np.repeat(levels[np.arange(frames) % len(levels)], L)
     p_sym = np.array([p_sym_of(e, payload_bits, L) for e in eb])
-    # channel: A_l U_l with A_l[j, a] = exp(-2 pi i R_l[j] a / Q) / sqrt(n_s)
-    a = np.arange(Q)
-    A = np.exp(-2j * np.pi * (rows[:, :, None].astype(np.float64) * a[None, None, :]) / Q) / np.sqrt(n_s)
-    U = np.sqrt(p_sym)[:, None] * counts.astype(np.float64)
-    noise = (rng.standard_normal((S, n_s)) + 1j * rng.standard_normal((S, n_s))) * np.sqrt(sigma2 / 2.0)
-    Y = np.einsum("sja,sa->sj", A, U) + noise
+    # channel: A_l U_l = sqrt(P_sym) sum_k column idx_k of A_l, with
+    # A_l[j, a] = exp(-2 pi i R_l[j] a / Q) / sqrt(n_s)
+    Y = np.zeros((S, n_s), dtype=np.complex128)
+    for k in range(K):
+        ph = (rows.astype(np.int64) * idx[:, k:k + 1]) % Q
+        Y += np.exp(-2j * np.pi * ph / Q)
+    Y *= np.sqrt(p_sym)[:, None] / np.sqrt(n_s)
+    Y += (rng.standard_normal((S, n_s)) + 1j * rng.standard_normal((S, n_s))) * np.sqrt(sigma2 / 2.0)
     y = np.stack([Y.real, Y.imag], axis=-1).astype(np.float32)
     return AmpSlots(rows=rows, y=y, counts=counts, p_sym=p_sym, ebn0_db=eb)
