@@ -54,10 +54,43 @@ __device__ __forceinline__ Activity activity(float t, float lodds0, float delta)
   return a;
 }
 
+// The value of lane l ^ d (d a power of two below 64).
+__device__ __forceinline__ float2 xor_lane(float2 v, int lane, int d) {
+  if (d == 32) {
+    const auto rx = __builtin_amdgcn_permlane32_swap(__float_as_uint(v.x), __float_as_uint(v.x), false, false);
+    const auto ry = __builtin_amdgcn_permlane32_swap(__float_as_uint(v.y), __float_as_uint(v.y), false, false);
+    const bool hi = lane & 32;                    // the partner sits in the other half
+    return make_float2(__uint_as_float(hi ? rx[0] : rx[1]), __uint_as_float(hi ? ry[0] : ry[1]));
+  }
+  return make_float2(__shfl_xor(v.x, d, 64), __shfl_xor(v.y, d, 64));
+}
+
+// 64-point DFT across the wave, one value per lane, radix-2 decimation in
+// frequency: X[k] = sum_n x[n] w^(+-nk), w = exp(-2 pi i / 64), the sign
+// negative for the forward transform.  Lane n ends with X[bitrev6(n)].
+// twd[s]: this lane's twiddle w^e of the stage of span d = 32 >> s, e =
+// (lane mod d) * 32 / d.
+__device__ __forceinline__ float2 fft64(float2 x, int lane, const float2 (&twd)[6], bool inverse) {
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const int d = 32 >> s;
+    const float2 y = xor_lane(x, lane, d);
+    const float2 w = make_float2(twd[s].x, inverse ? -twd[s].y : twd[s].y);
+    if (lane & d) {                               // (a - b) w, this lane holding b
+      const float tx = y.x - x.x, ty = y.y - x.y;
+      x = make_float2(tx * w.x - ty * w.y, tx * w.y + ty * w.x);
+    } else {                                      // a + b
+      x = make_float2(x.x + y.x, x.y + y.y);
+    }
+  }
+  return x;
+}
+
 __global__ __launch_bounds__(64 * kAmpWaves) void k_amp_evidence(AmpArgs g) {
   __shared__ float2 tw[64];                       // w^k = exp(-2 pi i k / Q)
   __shared__ float2 vec[kAmpWaves][64];           // the wave's broadcast vector
   __shared__ int srow[kAmpWaves][64];             // the slot's DFT rows
+  __shared__ float sx[kAmpWaves][64], sy[kAmpWaves][64];   // Q = 64: the scattered residual
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int Q = g.Q, ns = g.ns;
   if (tid < Q) {
@@ -79,15 +112,45 @@ __global__ __launch_bounds__(64 * kAmpWaves) void k_amp_evidence(AmpArgs g) {
   }
   srow[wave][lane] = rj;
   const float lrho = logf(g.rho) - log1pf(-g.rho), su2 = g.su2;
+  // Q = 64: both products as 64-point FFTs across the wave (the partial DFT is
+  // rows R of the full one): A U_hat = FFT(U_hat) at rows R, A^H Y_res = the
+  // inverse FFT of Y_res scattered to rows R (repeated rows add up)
+  const bool fft = Q == 64;
+  const int brev = (int)(__builtin_bitreverse32((unsigned)lane) >> 26);
+  float2 twd[6];
+#pragma unroll
+  for (int s6 = 0; s6 < 6; ++s6) {
+    const int d = 32 >> s6;
+    twd[s6] = fft ? tw[(lane & (d - 1)) * (32 / d)] : make_float2(1.f, 0.f);
+  }
   float2 res = y, uh = make_float2(0.f, 0.f), R = make_float2(0.f, 0.f);
   float nu = 1.f;
   for (int it = 0;; ++it) {
     // nu and R = U_hat + A^H Y_res (lane a; conj(A[j][a]) = conj(w^{(R_j a) mod Q}) / sqrt(n_s))
     nu = wave_sum64(res.x * res.x + res.y * res.y) / (float)ns;
+    float2 acc = make_float2(0.f, 0.f);
+    if (fft) {
+      sx[wave][lane] = 0.f;
+      sy[wave][lane] = 0.f;
+      __builtin_amdgcn_wave_barrier();
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      if (mj) {
+        atomicAdd(&sx[wave][rj], res.x);
+        atomicAdd(&sy[wave][rj], res.y);
+      }
+      __builtin_amdgcn_wave_barrier();
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      const float2 V = fft64(make_float2(sx[wave][lane], sy[wave][lane]), lane, twd, true);
+      vec[wave][brev] = V;                        // natural order
+      __builtin_amdgcn_wave_barrier();
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      acc = vec[wave][lane];
+      __builtin_amdgcn_wave_barrier();            // read before the next write of vec
+      asm volatile("" ::: "memory");
+    } else {
     vec[wave][lane] = res;
     __builtin_amdgcn_wave_barrier();
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    float2 acc = make_float2(0.f, 0.f);
     if (ma) {
       for (int j = 0; j < ns; ++j) {
         const float2 v = vec[wave][j];
@@ -95,6 +158,7 @@ __global__ __launch_bounds__(64 * kAmpWaves) void k_amp_evidence(AmpArgs g) {
         acc.x = fmaf(w.x, v.x, fmaf(w.y, v.y, acc.x));
         acc.y = fmaf(w.x, v.y, fmaf(-w.y, v.x, acc.y));
       }
+    }
     }
     R = make_float2(uh.x + acc.x * inv_sqrt_ns, uh.y + acc.y * inv_sqrt_ns);
     if (it == g.iters) break;
@@ -109,10 +173,17 @@ __global__ __launch_bounds__(64 * kAmpWaves) void k_amp_evidence(AmpArgs g) {
     // Y_res' = Y - A U_hat' + Y_res D / n_s (lane j; A[j][a] = w^{(R_j a) mod Q} / sqrt(n_s))
     __builtin_amdgcn_wave_barrier();              // every lane has read the residual row
     asm volatile("" ::: "memory");
+    float2 au = make_float2(0.f, 0.f);
+    if (fft) {
+      const float2 X = fft64(un, lane, twd, false);
+      vec[wave][brev] = X;                        // natural order
+      __builtin_amdgcn_wave_barrier();
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      if (mj) au = vec[wave][rj];
+    } else {
     vec[wave][lane] = un;
     __builtin_amdgcn_wave_barrier();
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    float2 au = make_float2(0.f, 0.f);
     if (mj) {
       for (int a = 0; a < Q; ++a) {
         const float2 v = vec[wave][a];
@@ -120,6 +191,7 @@ __global__ __launch_bounds__(64 * kAmpWaves) void k_amp_evidence(AmpArgs g) {
         au.x = fmaf(w.x, v.x, fmaf(-w.y, v.y, au.x));
         au.y = fmaf(w.x, v.y, fmaf(w.y, v.x, au.y));
       }
+    }
     }
     const float c = D / (float)ns;
     res = mj ? make_float2(y.x - au.x * inv_sqrt_ns + res.x * c, y.y - au.y * inv_sqrt_ns + res.y * c)

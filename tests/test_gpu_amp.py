@@ -65,3 +65,17 @@ def test_rows_are_taken_modulo_q():
 
 def test_no_slots_is_a_no_op():
     assert _run(np.zeros((0, 24, 2), np.float32), np.zeros((0, 24), np.int32), 64, 0.03, 2.0, 20).shape == (0, 64)
+
+
+@pytest.mark.parametrize("Q", [64, 48])
+def test_repeated_rows_match_oracle(Q):
+    """Rows drawn with replacement: A has repeated rows (the Q = 64 FFT path
+    sums the residual entries that land on the same row)."""
+    rng = np.random.default_rng(21)
+    S, n_s = 30, 24
+    rows = rng.integers(0, Q, size=(S, n_s)).astype(np.int32)
+    y = rng.standard_normal((S, n_s, 2)).astype(np.float32) * 2.0
+    say(f"AMP repeated rows Q={Q}")
+    got = _run(y, rows, Q, 2 / Q, 3.0, 20)
+    ref = amp_evidence_batch(y, rows, Q, 2 / Q, 3.0, 20)
+    assert rel_err(got, ref) <= TOL
