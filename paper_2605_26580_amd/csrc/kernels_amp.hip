@@ -27,11 +27,6 @@ namespace {
 
 constexpr int kAmpWaves = 4;
 
-__device__ __forceinline__ float wave_sum64(float v) {
-#pragma unroll
-  for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return xhalf_sum(v);
-}
 
 // x mod Q for 0 <= x < 2^22: the quotient from a float reciprocal with half a
 // unit of headroom, so that no rounding of x / Q lands on the wrong integer.
@@ -54,15 +49,72 @@ __device__ __forceinline__ Activity activity(float t, float lodds0, float delta)
   return a;
 }
 
-// The value of lane l ^ d (d a power of two below 64).
-__device__ __forceinline__ float2 xor_lane(float2 v, int lane, int d) {
-  if (d == 32) {
-    const auto rx = __builtin_amdgcn_permlane32_swap(__float_as_uint(v.x), __float_as_uint(v.x), false, false);
-    const auto ry = __builtin_amdgcn_permlane32_swap(__float_as_uint(v.y), __float_as_uint(v.y), false, false);
-    const bool hi = lane & 32;                    // the partner sits in the other half
-    return make_float2(__uint_as_float(hi ? rx[0] : rx[1]), __uint_as_float(hi ? ry[0] : ry[1]));
+// DPP lane moves within 16-lane rows (gfx9 encodings): quad_perm [1,0,3,2]
+// = xor 1, [2,3,0,1] = xor 2, [3,2,1,0] = xor 3; row_half_mirror = xor 7
+// within 8 lanes; row_mirror = xor 15 within 16.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ __forceinline__ float2 dpp2(float2 v) {
+  return make_float2(dpp<CTRL>(v.x), dpp<CTRL>(v.y));
+}
+
+// Sum over the wave, every lane ending with the same value: butterflies at
+// distances 1, 2, 4, 8 (DPP; each step adds a lane and its partner, so both
+// compute the same sum), then the row and half-wave swaps.
+__device__ __forceinline__ float wave_sum64(float v) {
+  v += dpp<0xb1>(v);
+  v += dpp<0x4e>(v);
+  v += dpp<0x141>(dpp<0x1b>(v));
+  v += dpp<0x140>(dpp<0x141>(v));
+  const unsigned a = __float_as_uint(v);
+  const auto r = __builtin_amdgcn_permlane16_swap(a, a, false, false);
+  v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  return xhalf_sum(v);
+}
+
+// The value of lane l ^ D, without LDS: DPP below 16, the row and half-wave
+// swaps (v_permlane16_swap / v_permlane32_swap: applied to a value in both
+// operands they return, in every lane, the value of the even and of the odd
+// row / half at that position) at 16 and 32.
+template <int D>
+__device__ __forceinline__ float2 xor_lane(float2 v, int lane) {
+  if constexpr (D == 1) {
+    return dpp2<0xb1>(v);
+  } else if constexpr (D == 2) {
+    return dpp2<0x4e>(v);
+  } else if constexpr (D == 4) {
+    return dpp2<0x141>(dpp2<0x1b>(v));            // (x ^ 3) ^ 7
+  } else if constexpr (D == 8) {
+    return dpp2<0x140>(dpp2<0x141>(v));           // (x ^ 7) ^ 15
+  } else {
+    static_assert(D == 16 || D == 32, "lane distance");
+    unsigned ax = __float_as_uint(v.x), ay = __float_as_uint(v.y);
+    if constexpr (D == 16) {
+      const auto rx = __builtin_amdgcn_permlane16_swap(ax, ax, false, false);
+      const auto ry = __builtin_amdgcn_permlane16_swap(ay, ay, false, false);
+      const bool odd = lane & 16;
+      return make_float2(__uint_as_float(odd ? rx[0] : rx[1]), __uint_as_float(odd ? ry[0] : ry[1]));
+    } else {
+      const auto rx = __builtin_amdgcn_permlane32_swap(ax, ax, false, false);
+      const auto ry = __builtin_amdgcn_permlane32_swap(ay, ay, false, false);
+      const bool hi = lane & 32;
+      return make_float2(__uint_as_float(hi ? rx[0] : rx[1]), __uint_as_float(hi ? ry[0] : ry[1]));
+    }
   }
-  return make_float2(__shfl_xor(v.x, d, 64), __shfl_xor(v.y, d, 64));
+}
+
+template <int S>
+__device__ __forceinline__ float2 butterfly(float2 x, int lane, float2 w) {
+  constexpr int d = 32 >> S;
+  const float2 y = xor_lane<d>(x, lane);
+  if (lane & d) {                                 // (a - b) w, this lane holding b
+    const float tx = y.x - x.x, ty = y.y - x.y;
+    return make_float2(tx * w.x - ty * w.y, tx * w.y + ty * w.x);
+  }
+  return make_float2(x.x + y.x, x.y + y.y);      // a + b
 }
 
 // 64-point DFT across the wave, one value per lane, radix-2 decimation in
@@ -71,18 +123,13 @@ __device__ __forceinline__ float2 xor_lane(float2 v, int lane, int d) {
 // twd[s]: this lane's twiddle w^e of the stage of span d = 32 >> s, e =
 // (lane mod d) * 32 / d.
 __device__ __forceinline__ float2 fft64(float2 x, int lane, const float2 (&twd)[6], bool inverse) {
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    const int d = 32 >> s;
-    const float2 y = xor_lane(x, lane, d);
-    const float2 w = make_float2(twd[s].x, inverse ? -twd[s].y : twd[s].y);
-    if (lane & d) {                               // (a - b) w, this lane holding b
-      const float tx = y.x - x.x, ty = y.y - x.y;
-      x = make_float2(tx * w.x - ty * w.y, tx * w.y + ty * w.x);
-    } else {                                      // a + b
-      x = make_float2(x.x + y.x, x.y + y.y);
-    }
-  }
+  auto tw_s = [&](int s) { return make_float2(twd[s].x, inverse ? -twd[s].y : twd[s].y); };
+  x = butterfly<0>(x, lane, tw_s(0));
+  x = butterfly<1>(x, lane, tw_s(1));
+  x = butterfly<2>(x, lane, tw_s(2));
+  x = butterfly<3>(x, lane, tw_s(3));
+  x = butterfly<4>(x, lane, tw_s(4));
+  x = butterfly<5>(x, lane, tw_s(5));
   return x;
 }
 
