@@ -45,6 +45,10 @@ class DecodeOpts:
     tau_max: float = 1.0           # inference temperature at the first refinement step
     tau_min: float = 1.0           # ... at the last; the remask confidence uses it
     parity: bool = True
+    # PRISM-style head instead of the fixed criterion: row_conf(den output) -> [K]
+    # confidences, remasked while below phi[s] after pass s, at most len(phi) rounds
+    row_conf: Optional[Callable] = None
+    phi: tuple = (0.96, 0.90, 0.85)
 
 
 @dataclass
@@ -114,10 +118,20 @@ def decode_grid(K: int, n: int, code, den: Callable, T: int, opts: DecodeOpts,
     while True:
         out = den(X, float((X == MASK).sum()) / float(K * n))
         fin = out["logits"] if isinstance(out, dict) else out
-        syn, q, low = row_status(X, fin, code, opts.remask_thr, opts.tau_min)
-        finals.append({"logits": fin, "low": low.copy(), "q": q, "syn": syn,
-                       "gap_q": float(np.min(np.abs(q - opts.remask_thr))) if opts.remask else float("inf")})
-        if not opts.remask or rounds >= opts.remask_max_rounds or not low.any():
+        if opts.row_conf is None:
+            syn, q, low = row_status(X, fin, code, opts.remask_thr, opts.tau_min)
+            finals.append({"logits": fin, "low": low.copy(), "q": q, "syn": syn,
+                           "gap_q": float(np.min(np.abs(q - opts.remask_thr))) if opts.remask else float("inf")})
+            max_rounds = opts.remask_max_rounds
+        else:
+            max_rounds = len(opts.phi)
+            q = opts.row_conf(out)
+            thr = opts.phi[rounds] if rounds < max_rounds else -np.inf
+            low = q < thr
+            finals.append({"logits": fin, "low": low.copy(), "q": q, "syn": None,
+                           "gap_q": float(np.min(np.abs(q - thr))) if opts.remask and rounds < max_rounds
+                           else float("inf")})
+        if not opts.remask or rounds >= max_rounds or not low.any():
             break
         X[low, :] = MASK
         T_rm = max(1, int(math.floor(T * int(low.sum()) / K)))

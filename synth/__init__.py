@@ -11,14 +11,14 @@ so that the same seed yields the same bytes on every machine.
 """
 from .code import LdpcCode, regular_ldpc, nullspace_gf2, rank_gf2
 from .channel import ebn0_to_sigma2, make_bins, make_ragged_bins, BinBatch, RaggedBin
-from .weights import ModelCfg, weight_layout, make_weights, unpack_weights
+from .weights import ModelCfg, weight_layout, make_weights, unpack_weights, make_quality_head
 from .configs import WORKLOADS, Workload, workload
 from .amp import AmpSlots, make_amp_slots, p_sym_of
 
 __all__ = [
     "LdpcCode", "regular_ldpc", "nullspace_gf2", "rank_gf2",
     "ebn0_to_sigma2", "make_bins", "make_ragged_bins", "BinBatch", "RaggedBin",
-    "ModelCfg", "weight_layout", "make_weights", "unpack_weights",
+    "ModelCfg", "weight_layout", "make_weights", "unpack_weights", "make_quality_head",
     "WORKLOADS", "Workload", "workload",
     "AmpSlots", "make_amp_slots", "p_sym_of",
 ]

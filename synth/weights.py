@@ -109,3 +109,15 @@ def unpack_weights(blob: np.ndarray, cfg: ModelCfg, dtype=np.float64) -> Dict[st
         out[name] = flat[off:off + cnt].astype(dtype).reshape(shape)
         off += cnt
     return out
+
+
+def make_quality_head(d: int, H: int, seed: int, std: float = 0.05, b2: float = 2.0) -> np.ndarray:
+    """Seeded parameters of a per-token quality head (untrained): flat FP32
+    [W1 (H x d), b1 (H), LayerNorm gain (H), LayerNorm bias (H), w2 (H), b2]."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    W1 = rng.standard_normal((H, d)) * std
+    b1 = rng.standard_normal(H) * std
+    g = 1.0 + rng.standard_normal(H) * std
+    b = rng.standard_normal(H) * std
+    w2 = rng.standard_normal(H) * 0.5
+    return np.concatenate([W1.ravel(), b1, g, b, w2, [b2]]).astype(np.float32)
