@@ -126,6 +126,21 @@ typedef struct {
                               /*    0: separate GEMM / attention kernels       */
   void*   workspace;          /* device scratch owned by the caller, or NULL   */
   size_t  workspace_bytes;    /* size of `workspace`; see cider_workspace_size */
+  /* PRISM-style quality head (Appendix, PRISM-style quality head and
+   * remasking plug-in) as the remask criterion, in place of the syndrome /
+   * confidence test above.  NULL [default]: not used.  Else a device FP32
+   * vector owned by the caller, live until the decode completes: W1 [H][d]
+   * row-major, b1 [H], LayerNorm gain [H], LayerNorm bias [H], w2 [H], b2;
+   * per token omega = sigmoid(w2 . GELU(LN(W1 LN_f(Z) + b1)) + b2) at the
+   * final pass, a row's confidence is its mean omega, and after pass s the
+   * rows below remask_phi[s] are remasked, for at most remask_stages rounds
+   * (remask_max_rounds and remask_thr are then unused; remask must be 1,
+   * else CIDER_EINVAL; d > 1024 gives CIDER_EUNSUPPORTED).  The syndrome
+   * still sets out_row_valid. */
+  const float* qhead;
+  int32_t qhead_hidden;       /* H, 1..64                                  [0] */
+  int32_t remask_stages;      /* number of thresholds, 1..4                [3] */
+  float   remask_phi[4];      /* thresholds            [0.96, 0.90, 0.85, 0]   */
 } cider_opts;
 
 typedef struct cider_weights cider_weights;

@@ -49,7 +49,9 @@ class cider_opts(C.Structure):
                 ("tau_max", C.c_float), ("tau_min", C.c_float),
                 ("autotune", C.c_int32), ("profile", C.c_int32), ("fused_blocks", C.c_int32),
                 ("workspace", C.c_void_p),
-                ("workspace_bytes", C.c_size_t)]
+                ("workspace_bytes", C.c_size_t),
+                ("qhead", C.c_void_p), ("qhead_hidden", C.c_int32), ("remask_stages", C.c_int32),
+                ("remask_phi", C.c_float * 4)]
 
 
 class cider_bin(C.Structure):
@@ -89,6 +91,10 @@ def lib() -> C.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library {LIB_PATH} is not built; run paper_2605_26580_amd.build.build()")
+    # torch first: the library then binds to the HIP runtime torch has already
+    # loaded, so the process holds one runtime.  Loaded the other way round,
+    # two runtimes end up in the process and the second to start sees no device.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp, i32, f32 = C.c_void_p, C.c_int32, C.c_float
     L.cider_opts_default.argtypes = [C.POINTER(cider_opts)]
@@ -161,6 +167,10 @@ def cider_opts_default(**overrides) -> cider_opts:
     for k, v in overrides.items():
         if not hasattr(o, k):
             raise AttributeError(k)
+        if k == "remask_phi":
+            v = (C.c_float * 4)(*(list(v) + [0.0] * (4 - len(v))))
+        elif k == "qhead" and v is not None and not isinstance(v, int):
+            v = _ptr(v)
         setattr(o, k, v)
     return o
 

@@ -80,6 +80,10 @@ struct StepCtx {
   int first_verbatim;       // first-reveal step reveals every slot's selected site
   float remask_thr, tau, eta, lam_max, lam_min;
   float q_inv_tau;          // 1 / tau_min: temperature of the remask confidence
+  const float* qhead;       // quality-head parameters (NULL: syndrome / confidence criterion)
+  int qh_hidden;
+  float phi[4];             // per-round thresholds of the quality head
+  const float* qw;          // per-token head output omega [T] (written for bins in their final pass)
   float gamma_override;     // >= 0: mask-ratio input for every bin (teacher-forced step)
   int reveal_override;      // >= 0: reveal this many sites instead of the schedule's count
   int first_override;       // first-reveal flag used with reveal_override
@@ -130,6 +134,7 @@ struct Work {
   float* ascale;   // [T]        per-token FP8 activation scales (FP8 only)
   float* lbar;     // [T][2]     logits before Module B
   float* logits;   // [T][2]     logits after Module B
+  float* qw;       // [T]        quality-head omega (final passes)
   float* p;        // [slots][2] per-slot beliefs
   float* S;        // [slots][2] per-slot log evidence
 };
@@ -142,6 +147,8 @@ hipError_t launch_embed_demix(const StepCtx& c, const EmbedW& m, const Work& w, 
 hipError_t launch_final_proj(const StepCtx& c, const EmbedW& m, const Work& w, hipStream_t s);
 hipError_t launch_module_b(const StepCtx& c, const Work& w, hipStream_t s);
 hipError_t launch_step_tail(const StepCtx& c, const Work& w, hipStream_t s);
+// PRISM-style quality head: omega per token from the final residual into c.qw.
+hipError_t launch_quality_head(const StepCtx& c, const EmbedW& m, const Work& w, hipStream_t s);
 
 // GEMM: out = epi(pro(A) W^T + bias).  A rows are tokens.
 enum Pro : int { kProNone = 0, kProLN = 1 };

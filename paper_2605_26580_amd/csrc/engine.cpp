@@ -193,7 +193,7 @@ struct Layout {
   int num_bins = 0;
   long total_tokens = 0;
   int total_slots = 0, total_rows = 0, max_n = 0, total_ugrp = 0;
-  size_t off_ugrp = 0, off_ugrp32 = 0, off_tile = 0, off_R, off_E, off_ZE, off_H1, off_QKV, off_O, off_HID, off_lbar, off_logits, off_p, off_S,
+  size_t off_ugrp = 0, off_ugrp32 = 0, off_tile = 0, off_R, off_E, off_ZE, off_H1, off_QKV, off_O, off_HID, off_lbar, off_logits, off_qw, off_p, off_S,
       off_bins, off_state, off_slot, off_row, off_X, off_XN, off_XN8, off_xscale, total;
 };
 
@@ -219,6 +219,7 @@ Layout plan_layout(const cider_model_cfg& cfg, int num_bins, long T, int slots, 
   L.off_HID = take(T * F * es);
   L.off_lbar = take(T * 2 * 4);
   L.off_logits = take(T * 2 * 4);
+  L.off_qw = take(T * 4);
   L.off_p = take((size_t)slots * 2 * 4);
   L.off_S = take((size_t)slots * 2 * 4);
   L.off_bins = take((size_t)num_bins * sizeof(DevBin));
@@ -611,6 +612,7 @@ int autotune_forward(cider_weights* w, const Run& r, hipStream_t s) {
 int enqueue_step(cider_weights* w, const Run& r, hipStream_t s) {
   int rc = enqueue_forward(w, r, s);
   if (rc) return rc;
+  if (r.ctx.qhead) TIMED("quality_head", launch_quality_head(r.ctx, w->ew, r.work, s));
   TIMED("step_tail", launch_step_tail(r.ctx, r.work, s));
   return CIDER_OK;
 }
@@ -673,10 +675,18 @@ int check_opts(const cider_opts& o) {
     return fail(CIDER_EINVAL, "tau, lam_max, lam_min must be > 0 and eta >= 0");
   if (o.first_reveal < 0 || o.first_reveal > 2) return fail(CIDER_EINVAL, "first_reveal must be 0, 1 or 2");
   if (!(o.tau_max > 0.f) || !(o.tau_min > 0.f)) return fail(CIDER_EINVAL, "tau_max and tau_min must be > 0");
+  if (o.qhead) {
+    if (!o.remask) return fail(CIDER_EINVAL, "the quality head is a remask criterion: remask must be 1");
+    if (o.qhead_hidden < 1 || o.qhead_hidden > 64) return fail(CIDER_EINVAL, "qhead_hidden must be 1..64");
+    if (o.remask_stages < 1 || o.remask_stages > 4) return fail(CIDER_EINVAL, "remask_stages must be 1..4");
+    for (int i = 0; i < o.remask_stages; ++i)
+      if (!std::isfinite(o.remask_phi[i])) return fail(CIDER_EINVAL, "remask_phi must be finite");
+  }
   return CIDER_OK;
 }
 
 int check_prec(const cider_weights* w, const cider_opts& o) {
+  if (o.qhead && w->cfg.d > 1024) return fail(CIDER_EUNSUPPORTED, "the quality head needs d <= 1024");
   if (o.precision == CIDER_FP8 && (w->cfg.d % 128 != 0 || (w->cfg.mlp_mult * w->cfg.d) % 64 != 0))
     return fail(CIDER_EUNSUPPORTED, "FP8 needs d to be a multiple of 128");
   return CIDER_OK;
@@ -797,6 +807,10 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
   c.remask_thr = o.remask_thr;
   c.first_verbatim = o.first_reveal == 2;
   c.q_inv_tau = 1.0f / o.tau_min;
+  c.qhead = o.qhead;
+  c.qh_hidden = o.qhead_hidden;
+  for (int i = 0; i < 4; ++i) c.phi[i] = o.remask_phi[i];
+  if (o.qhead) c.max_rounds = o.remask_stages;
   c.tau = o.tau;
   c.eta = o.eta;
   c.lam_max = o.lam_max;
@@ -818,6 +832,8 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
   k.ascale = nullptr;
   k.lbar = (float*)(base + L.off_lbar);
   k.logits = (float*)(base + L.off_logits);
+  k.qw = (float*)(base + L.off_qw);
+  c.qw = k.qw;
   k.p = (float*)(base + L.off_p);
   k.S = (float*)(base + L.off_S);
   r->prec = o.precision;
@@ -857,10 +873,12 @@ int decode_impl(cider_weights* w, const std::vector<BinIn>& bins, int steps, con
   // initial pass: steps reveal steps + the final pass
   rc = run_steps(w, r, steps + 1, graph, s);
   if (rc) return rc;
-  if (o.remask && o.remask_max_rounds > 0) {
+  // remask rounds: the quality head's stages, else remask_max_rounds
+  const int rounds = o.qhead ? o.remask_stages : o.remask_max_rounds;
+  if (o.remask && rounds > 0) {
     const BinState* dst = (const BinState*)((const char*)r.ctx.bins - L.off_bins + L.off_state);
     std::vector<BinState> hst(bins.size());
-    for (int round = 0; round < o.remask_max_rounds; ++round) {
+    for (int round = 0; round < rounds; ++round) {
       HIPCHK(hipMemcpyAsync(hst.data(), dst, hst.size() * sizeof(BinState), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       bool busy = false;
@@ -896,6 +914,13 @@ void cider_opts_default(cider_opts* o) {
   o->lam_min = 1e-6f;
   o->tau_max = 1.0f;
   o->tau_min = 1.0f;
+  o->qhead = nullptr;
+  o->qhead_hidden = 0;
+  o->remask_stages = 3;
+  o->remask_phi[0] = 0.96f;
+  o->remask_phi[1] = 0.90f;
+  o->remask_phi[2] = 0.85f;
+  o->remask_phi[3] = 0.0f;
   o->autotune = 1;
   o->profile = 0;
   o->fused_blocks = 1;

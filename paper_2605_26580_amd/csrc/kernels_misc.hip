@@ -503,10 +503,16 @@ __global__ __launch_bounds__(kTailThreads) void k_step_tail(StepCtx c, const flo
   }
   if (wave < K) {
     float acc = 0.f;
-    for (int l = lane; l < n; l += 64) {
-      int site = wave * n + l;
-      float mg = fabsf(lg[2 * site] - lg[2 * site + 1]);
-      acc += 1.0f / (1.0f + expf(-mg * c.q_inv_tau));
+    if (c.qhead) {
+      // quality head: the row's mean omega
+      const float* qrow = c.qw + (size_t)b.tok_off + (size_t)wave * n;
+      for (int l = lane; l < n; l += 64) acc += qrow[l];
+    } else {
+      for (int l = lane; l < n; l += 64) {
+        int site = wave * n + l;
+        float mg = fabsf(lg[2 * site] - lg[2 * site + 1]);
+        acc += 1.0f / (1.0f + expf(-mg * c.q_inv_tau));
+      }
     }
     acc = wave_sum(acc);
     if (lane == 0) s_q[wave] = acc / (float)n;
@@ -514,8 +520,15 @@ __global__ __launch_bounds__(kTailThreads) void k_step_tail(StepCtx c, const flo
   __syncthreads();
   if (tid == 0) {
     int low = 0;
-    for (int k = 0; k < K; ++k)
-      if (s_syn[k] || s_q[k] < c.remask_thr) low |= 1 << k;
+    if (c.qhead) {
+      // after final pass s (s = rounds already run) the threshold is phi_s
+      const float thr = c.phi[min(st.round, 3)];
+      for (int k = 0; k < K; ++k)
+        if (s_q[k] < thr) low |= 1 << k;
+    } else {
+      for (int k = 0; k < K; ++k)
+        if (s_syn[k] || s_q[k] < c.remask_thr) low |= 1 << k;
+    }
     s_low = low;
   }
   __syncthreads();
@@ -570,6 +583,94 @@ __global__ __launch_bounds__(kTailThreads) void k_step_tail(StepCtx c, const flo
     st.phase = kDone;
     *b.st = st;
   }
+}
+
+// PRISM-style quality head (Appendix, PRISM-style quality head and remasking
+// plug-in), for the tokens of every bin in its final pass: from the final
+// residual Z, Zhat = LN_f(Z), h = W1 Zhat + b1 (H hidden units), and
+// omega = sigmoid(w2 . GELU(LN_H(h)) + b2), LN_H with its own gain and bias.
+// One wave per token, FP32: the token's d features sit d / 64 per lane, each
+// hidden unit is a wave reduction and then lives in lane j < H.  The head is
+// read from HBM / L2 per token (H d floats); it is a plug-in that runs once
+// per final pass, beside the L layers of the forward pass.
+// psi = [W1 (H x d, row-major) | b1 | gain | bias | w2 | b2].
+constexpr int kQhWaves = 4;
+constexpr int kQhMaxNC = 16;   // d <= 1024
+
+__global__ __launch_bounds__(64 * kQhWaves) void k_quality_head(StepCtx c, EmbedW m, const float* __restrict__ R,
+                                                               float* __restrict__ qw) {
+  const DevBin& b = c.bins[blockIdx.x];
+  if (b.st->phase != kFinal) return;
+  const int d = m.d, H = c.qh_hidden;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tot = b.K * b.n;
+  const float* W1 = c.qhead;
+  const float* b1 = W1 + (size_t)H * d;
+  const float* hg = b1 + H;
+  const float* hb = hg + H;
+  const float* w2 = hb + H;
+  const float b2 = w2[H];
+  const bool act = lane < H;
+  const float b1j = act ? b1[lane] : 0.f, hgj = act ? hg[lane] : 0.f, hbj = act ? hb[lane] : 0.f;
+  const float w2j = act ? w2[lane] : 0.f;
+  for (int i = blockIdx.y * kQhWaves + wave; i < tot; i += gridDim.y * kQhWaves) {
+    const size_t tok = (size_t)b.tok_off + i;
+    const float* z = R + tok * d;
+    float zh[kQhMaxNC];
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < kQhMaxNC; ++q) {
+      const int col = lane + 64 * q;
+      zh[q] = col < d ? z[col] : 0.f;
+      s += zh[q];
+    }
+    const float mean = wave_sum(s) / (float)d;
+    float v = 0.f;
+#pragma unroll
+    for (int q = 0; q < kQhMaxNC; ++q) {
+      const int col = lane + 64 * q;
+      const float t = col < d ? zh[q] - mean : 0.f;
+      v = fmaf(t, t, v);
+    }
+    const float rstd = rsqrtf(wave_sum(v) / (float)d + 1e-5f);
+#pragma unroll
+    for (int q = 0; q < kQhMaxNC; ++q) {
+      const int col = lane + 64 * q;
+      zh[q] = col < d ? (zh[q] - mean) * rstd * m.lnf_g[col] + m.lnf_b[col] : 0.f;
+    }
+    float hj = 0.f;
+    for (int j = 0; j < H; ++j) {
+      const float* wr = W1 + (size_t)j * d;
+      float a = 0.f;
+#pragma unroll
+      for (int q = 0; q < kQhMaxNC; ++q) {
+        const int col = lane + 64 * q;
+        if (col < d) a = fmaf(wr[col], zh[q], a);
+      }
+      a = wave_sum(a);
+      if (lane == j) hj = a + b1j;
+    }
+    const float hm = wave_sum(act ? hj : 0.f) / (float)H;
+    const float dv = act ? hj - hm : 0.f;
+    const float hr = rsqrtf(wave_sum(dv * dv) / (float)H + 1e-5f);
+    float o = 0.f;
+    if (act) {
+      const float x = dv * hr * hgj + hbj;
+      o = w2j * (0.5f * x * (1.0f + erff(x * 0.70710678118654752f)));
+    }
+    o = wave_sum(o) + b2;
+    if (lane == 0) qw[tok] = 1.0f / (1.0f + expf(-o));
+  }
+}
+
+hipError_t launch_quality_head(const StepCtx& c, const EmbedW& m, const Work& w, hipStream_t s) {
+  if (!c.qhead || c.qh_hidden < 1 || c.qh_hidden > 64 || m.d < 1 || m.d > 64 * kQhMaxNC) return hipErrorInvalidValue;
+  // one workgroup row per bin (grid x); along y enough workgroups for the largest grid
+  // (kMaxK rows of max_n slots), at most 32
+  const int need = (kMaxK * c.max_n + kQhWaves - 1) / kQhWaves;
+  const int gx = need < 32 ? need : 32;
+  hipLaunchKernelGGL(k_quality_head, dim3(c.num_bins, gx), dim3(64 * kQhWaves), 0, s, c, m, w.R, w.qw);
+  return hipGetLastError();
 }
 
 hipError_t launch_step_tail(const StepCtx& c, const Work& w, hipStream_t s) {

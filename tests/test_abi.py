@@ -34,6 +34,10 @@ def test_opts_defaults():
     assert o.remask == 0 and o.remask_max_rounds == 2 and abs(o.remask_thr - 0.9) < 1e-7
     assert o.tau == 1.0 and o.eta == 1.0 and o.lam_max == 20.0 and abs(o.lam_min - 1e-6) < 1e-12
     assert o.tau_max == 1.0 and o.tau_min == 1.0 and o.fused_blocks == 1 and o.autotune == 1
+    assert not o.qhead and o.qhead_hidden == 0 and o.remask_stages == 3
+    assert np.allclose(list(o.remask_phi), [0.96, 0.90, 0.85, 0.0])
+    o = P.cider_opts_default(remask_phi=(0.5, 0.25))
+    assert np.allclose(list(o.remask_phi), [0.5, 0.25, 0.0, 0.0])
 
 
 @pytest.mark.parametrize("L,d,h", [(2, 64, 4), (4, 128, 8), (6, 256, 8), (8, 384, 12)])
