@@ -14,6 +14,7 @@ from .channel import ebn0_to_sigma2, make_bins, make_ragged_bins, BinBatch, Ragg
 from .weights import ModelCfg, weight_layout, make_weights, unpack_weights, make_quality_head
 from .configs import WORKLOADS, Workload, workload
 from .amp import AmpSlots, make_amp_slots, p_sym_of
+from .binning import ProtocolFrame, make_protocol_frames
 
 __all__ = [
     "LdpcCode", "regular_ldpc", "nullspace_gf2", "rank_gf2",
@@ -21,4 +22,5 @@ __all__ = [
     "ModelCfg", "weight_layout", "make_weights", "unpack_weights", "make_quality_head",
     "WORKLOADS", "Workload", "workload",
     "AmpSlots", "make_amp_slots", "p_sym_of",
+    "ProtocolFrame", "make_protocol_frames",
 ]
