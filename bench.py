@@ -13,6 +13,7 @@ accumulation.  Prints one JSON line.
     python bench.py --workload c4                      (4096 ragged bins, one packed pass)
     python bench.py --workload c5 --load 0.5,0.9       (served: Poisson arrivals)
     python bench.py --workload amp                     (AMP-MMSE slot detector, 4096 frames)
+    python bench.py --workload protocol                (stochastic binning: 160 frames, 100 users, 25 bins)
 """
 from __future__ import annotations
 
@@ -281,8 +282,16 @@ def run_batched(args, wl, P, torch):
     wh = P.Weights(P.make_cfg(cfg.n_layers, cfg.d, cfg.heads, cfg.mlp_mult, cfg.n_max), blob)
     if ragged:
         codes = {n: synth.regular_ldpc(n, seed=1000 + n) for n in wl.ragged_n}
-        rb = synth.make_ragged_bins(codes, args.bins or wl.batch, wl.ragged_K, wl.ragged_n, wl.ebn0_range,
-                                    wl.bin_seed)
+        if wl.binning:
+            # every decodable bin of the frames, in one packed call (as decode_frames issues it)
+            K_tot, zeta, K_max = wl.binning
+            frames = synth.make_protocol_frames(codes[wl.ragged_n[0]], args.bins or wl.batch, K_tot, zeta, K_max,
+                                                wl.ebn0_range, wl.bin_seed)
+            rb = [b for fr in frames for _, b in fr.bins]
+            erased = sum(len(fr.overflow) for fr in frames)
+        else:
+            rb = synth.make_ragged_bins(codes, args.bins or wl.batch, wl.ragged_K, wl.ragged_n, wl.ebn0_range,
+                                        wl.bin_seed)
         handles = {n: P.Code(c.n, c.m, c.row_ptr, c.col_idx) for n, c in codes.items()}
         shapes = [(b.K, b.n) for b in rb]
         ys = [torch.from_numpy(b.y).to(dev) for b in rb]
@@ -304,6 +313,13 @@ def run_batched(args, wl, P, torch):
     prec = {"bf16": P.CIDER_BF16, "fp32": P.CIDER_FP32, "fp8": P.CIDER_FP8}[args.precision]
     kind = args.precision
     ro = dict(remask=int(wl.remask), remask_thr=wl.remask_thr, remask_max_rounds=wl.remask_max_rounds)
+    if args.qhead:
+        # quality head as the remask criterion: a seeded head that is always sure
+        # (b2 = +30, no row remasked), so the run costs the head's evaluation at
+        # every final pass and nothing more
+        psi = synth.make_quality_head(cfg.d, args.qhead, seed=7, b2=30.0)
+        qbuf = torch.from_numpy(psi).to(dev)
+        ro = dict(remask=1, qhead=qbuf, qhead_hidden=args.qhead)
     opts = P.cider_opts_default(precision=prec, use_graph=1, **ro)
     blist = [{"y": ys[i], "sigma2": s2[i], "code": chs[i], "K": shapes[i][0], "n": shapes[i][1],
               "out_symbols": outs[i]} for i in range(B)]
@@ -376,7 +392,21 @@ def run_batched(args, wl, P, torch):
         "speedup_vs_fp32_plain": round(value / plain_value, 2) if plain_value else None,
         "roofline": roof, "kernels": kernel_table, "tuning": tuning,
     }
-    if ragged:
+    if args.qhead:
+        res["quality_head"] = {"hidden": args.qhead, "b2": 30.0, "remask": "head criterion, no row below phi"}
+    if wl.binning:
+        K_tot, zeta, K_max = wl.binning
+        nf = len(frames)
+        res["users_per_s"] = round(nf * K_tot * args.steps / total, 1)
+        res["config"] = {"workload": f"{wl.name}: {nf} frames of K_tot={K_tot} users, uniform preamble choice over "
+                                     f"zeta={zeta} bins, bins with K_chi > {K_max} erased ({erased} of {nf * zeta}), "
+                                     f"the other {B} bins (K_chi 1..{K_max}) decoded in one packed pass per step; "
+                                     f"(3,6)-regular binary LDPC n={wl.ragged_n[0]}, Eb/N0 uniform "
+                                     f"{list(wl.ebn0_range)} dB, L={cfg.n_layers} d={cfg.d} h={cfg.heads} "
+                                     f"seeded N(0,0.02) weights, T={wl.T}",
+                         "frames": nf, "bins_per_batch": B, "erased_bins": erased, "tokens": tokens, "T": wl.T,
+                         "remask": wl.remask}
+    elif ragged:
         res["config"] = {"workload": f"{wl.name}: {B} bins, K uniform {list(wl.ragged_K)}, n uniform "
                                      f"{list(wl.ragged_n)} (3,6)-regular binary LDPC, Eb/N0 uniform "
                                      f"{list(wl.ebn0_range)} dB, L={cfg.n_layers} d={cfg.d} h={cfg.heads} "
@@ -498,6 +528,7 @@ def main():
     ap.add_argument("--cpu-bins", type=int, default=16)
     ap.add_argument("--plain-bins", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--qhead", type=int, default=0, help="quality head with this many hidden units as the remask criterion")
     ap.add_argument("--calib-copy", action="store_true", help="end with a 256 MiB device copy (counter calibration)")
     ap.add_argument("--load", default="0.5,0.9")
     ap.add_argument("--duration", type=float, default=15.0)

@@ -32,6 +32,7 @@ class Workload:
     ragged_K: Optional[Tuple[int, ...]] = None
     ragged_n: Optional[Tuple[int, ...]] = None
     ebn0_range: Optional[Tuple[float, float]] = None
+    binning: Optional[Tuple[int, int, int]] = None   # (K_tot, zeta, K_max): batch counts frames
 
 
 WORKLOADS: Dict[str, Workload] = {
@@ -50,6 +51,12 @@ WORKLOADS: Dict[str, Workload] = {
                    ebn0_db=(4.0,), code_seed=1000, weight_seed=15, bin_seed=105,
                    remask=True, ragged_K=tuple(range(2, 17)), ragged_n=(128, 256, 512, 1024),
                    ebn0_range=(2.0, 6.0)),
+    # stochastic-binning traffic: frames of K_tot = 100 users over zeta = 25 preamble
+    # bins, bank up to K_max = 8 (overflow bins erased); c4's model, n = 256
+    "protocol": Workload("protocol", K=8, n=256, model=ModelCfg(6, 256, 8), T=32, batch=160,
+                         ebn0_db=(4.0,), code_seed=1256, weight_seed=13, bin_seed=106,
+                         ragged_K=tuple(range(1, 9)), ragged_n=(256,), ebn0_range=(2.0, 6.0),
+                         binning=(100, 25, 8)),
 }
 
 
