@@ -126,3 +126,34 @@ def test_teacher_forced_step_at_workload_size(name):
         e_log = rel_err(logits.cpu().numpy(), ref["logits"])
         print(f"  err lbar={e_lbar:.2e} logits={e_log:.2e}")
         assert e_lbar <= tol and e_log <= tol, (e_lbar, e_log)
+
+
+def test_quality_head_control_flow_at_c3_size():
+    """The quality head as the remask criterion over c3's whole batch (512
+    bins, 1.05 M tokens, the benchmark's launch configuration): a head that
+    is always sure equals the decode without remasking, and one that always
+    doubts equals the fixed criterion with a threshold above 1, bit for bit."""
+    torch = torch_cuda()
+    P = lib()
+    wl, wh, _, items = _workload_batch("c3")
+    code = items[0][2]
+    ch = P.Code(code.n, code.m, code.row_ptr, code.col_idx)
+    ys = [torch.from_numpy(np.ascontiguousarray(y)).cuda() for *_, y, _ in items]
+    H = 16
+
+    def run(opts):
+        outs = [torch.full((K, n), 9, dtype=torch.uint8, device="cuda") for K, n, *_ in items]
+        valid = [torch.zeros(K, dtype=torch.uint8, device="cuda") for K, *_ in items]
+        P.cider_decode_batch([{"y": ys[i], "sigma2": items[i][4], "code": ch, "K": items[i][0], "n": items[i][1],
+                               "out_symbols": outs[i], "out_row_valid": valid[i]} for i in range(len(items))],
+                             wh, wl.T, opts)
+        torch.cuda.synchronize()
+        return np.stack([o.cpu().numpy() for o in outs]), np.stack([v.cpu().numpy() for v in valid])
+
+    base = dict(precision=P.CIDER_BF16, use_graph=1)
+    for b2, ref_opts in ((30.0, dict(remask=0)), (-30.0, dict(remask=1, remask_thr=2.0, remask_max_rounds=1))):
+        psi = torch.from_numpy(synth.make_quality_head(wl.model.d, H, seed=7, b2=b2)).cuda()
+        say(f"c3 full batch with the quality head, b2={b2}")
+        got = run(P.cider_opts_default(remask=1, qhead=psi, qhead_hidden=H, remask_stages=1, **base))
+        ref = run(P.cider_opts_default(**ref_opts, **base))
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), b2
