@@ -590,22 +590,33 @@ __global__ __launch_bounds__(kTailThreads) void k_step_tail(StepCtx c, const flo
 // residual Z, Zhat = LN_f(Z), h = W1 Zhat + b1 (H hidden units), and
 // omega = sigmoid(w2 . GELU(LN_H(h)) + b2), LN_H with its own gain and bias.
 // One wave per token, FP32: the token's d features sit d / 64 per lane, each
-// hidden unit is a wave reduction and then lives in lane j < H.  The head is
-// read from HBM / L2 per token (H d floats); it is a plug-in that runs once
-// per final pass, beside the L layers of the forward pass.
+// hidden unit is a wave reduction and then lives in lane j < H.  With STAGE
+// the workgroup copies W1 (H d floats, at most 64 KB) into LDS once and its
+// waves read it from there for every token they take; otherwise W1 is read
+// from L2 per token.  It is a plug-in that runs once per final pass, beside
+// the L layers of the forward pass.
 // psi = [W1 (H x d, row-major) | b1 | gain | bias | w2 | b2].
 constexpr int kQhWaves = 4;
 constexpr int kQhMaxNC = 16;   // d <= 1024
 
+template <bool STAGE>
 __global__ __launch_bounds__(64 * kQhWaves) void k_quality_head(StepCtx c, EmbedW m, const float* __restrict__ R,
                                                                float* __restrict__ qw) {
+  extern __shared__ float sW1[];        // STAGE: W1 [H][d]
   const DevBin& b = c.bins[blockIdx.x];
-  if (b.st->phase != kFinal) return;
+  if (b.st->phase != kFinal) return;    // the same for every wave of the workgroup
   const int d = m.d, H = c.qh_hidden;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tot = b.K * b.n;
-  const float* W1 = c.qhead;
-  const float* b1 = W1 + (size_t)H * d;
+  const float* W1g = c.qhead;
+  if (STAGE) {
+    const int nw = H * d;               // a multiple of 64 (d is)
+    for (int i = 4 * (int)threadIdx.x; i < nw; i += 4 * 64 * kQhWaves)
+      *(float4*)&sW1[i] = *(const float4*)&W1g[i];
+    __syncthreads();
+  }
+  const float* W1 = STAGE ? sW1 : W1g;
+  const float* b1 = W1g + (size_t)H * d;
   const float* hg = b1 + H;
   const float* hb = hg + H;
   const float* w2 = hb + H;
@@ -669,7 +680,11 @@ hipError_t launch_quality_head(const StepCtx& c, const EmbedW& m, const Work& w,
   // (kMaxK rows of max_n slots), at most 32
   const int need = (kMaxK * c.max_n + kQhWaves - 1) / kQhWaves;
   const int gx = need < 32 ? need : 32;
-  hipLaunchKernelGGL(k_quality_head, dim3(c.num_bins, gx), dim3(64 * kQhWaves), 0, s, c, m, w.R, w.qw);
+  const size_t wbytes = (size_t)c.qh_hidden * m.d * sizeof(float);
+  if (wbytes <= 65536 && (m.d % 64) == 0 && ((uintptr_t)c.qhead % 16) == 0)
+    hipLaunchKernelGGL(k_quality_head<true>, dim3(c.num_bins, gx), dim3(64 * kQhWaves), wbytes, s, c, m, w.R, w.qw);
+  else
+    hipLaunchKernelGGL(k_quality_head<false>, dim3(c.num_bins, gx), dim3(64 * kQhWaves), 0, s, c, m, w.R, w.qw);
   return hipGetLastError();
 }
 
