@@ -1,0 +1,44 @@
+"""Host bookkeeping of decode_frames (stochastic-binning front end), on the
+CPU: which bins are erased, skipped or sent, and in what packed order.  The
+library call is replaced by a recorder, so no device is touched."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2605_26580_amd as P
+from paper_2605_26580_amd import protocol
+
+
+def test_decode_frames_erases_overflow_and_packs_the_rest(monkeypatch):
+    calls = []
+    monkeypatch.setattr(protocol.abi, "cider_decode_batch",
+                        lambda bins, w, steps, opts, stream=None: calls.append((bins, steps)))
+    n, K_max = 16, 3
+    loads = [np.array([0, 2, 4, 1]), np.array([3, 0, 0, 5])]
+    frames = [{"loads": L, "payload": {chi: (torch.full((n,), float(f * 10 + chi)), 0.5)
+                                       for chi, K in enumerate(L) if 1 <= K <= K_max}}
+              for f, L in enumerate(loads)]
+    res = protocol.decode_frames(frames, code="code", n=n, w="weights", steps=7, K_max=K_max)
+    assert [r["erased"] for r in res] == [[2], [3]]
+    assert [sorted(r["decoded"]) for r in res] == [[1, 3], [0]]
+    assert len(calls) == 1 and calls[0][1] == 7
+    bins = calls[0][0]
+    # frame-major, bin-index order; outputs sized K x n
+    assert [(int(b["y"][0]), b["K"]) for b in bins] == [(1, 2), (3, 1), (10, 3)]
+    for b, (f, chi) in zip(bins, [(0, 1), (0, 3), (1, 0)]):
+        sym, valid = res[f]["decoded"][chi]
+        assert b["out_symbols"] is sym and b["out_row_valid"] is valid
+        assert tuple(sym.shape) == (b["K"], n) and tuple(valid.shape) == (b["K"],)
+        assert b["n"] == n and b["sigma2"] == 0.5 and b["code"] == "code"
+
+
+def test_decode_frames_with_nothing_decodable_makes_no_call(monkeypatch):
+    calls = []
+    monkeypatch.setattr(protocol.abi, "cider_decode_batch", lambda *a, **k: calls.append(a))
+    res = protocol.decode_frames([{"loads": np.array([0, 9]), "payload": {}}], "code", 8, "w", 4, K_max=8)
+    assert res == [{"decoded": {}, "erased": [1]}] and calls == []
+
+
+def test_decode_frames_rejects_a_bank_beyond_the_library():
+    with pytest.raises(ValueError):
+        P.decode_frames([], "code", 8, "w", 4, K_max=17)
