@@ -10,7 +10,7 @@
   paths: a head that is always sure (b2 = +30) never remasks, so the decode
   equals the one without remasking; a head that always doubts (b2 = -30)
   remasks every row after every stage, as the fixed criterion does with a
-  threshold above 1 and as many rounds; in FP32 and in BF16 (fused blocks);
+  threshold above 1 and as many rounds; in FP32, BF16 (fused blocks) and FP8;
 - options that do not describe a head are rejected before any launch.
 """
 import numpy as np
@@ -100,7 +100,7 @@ def test_quality_head_fp32_matches_oracle():
     assert safe >= B // 3 and partial >= 1
 
 
-@pytest.mark.parametrize("prec,d,h", [("fp32", 64, 4), ("bf16", 128, 8)])
+@pytest.mark.parametrize("prec,d,h", [("fp32", 64, 4), ("bf16", 128, 8), ("fp8", 128, 8)])
 def test_quality_head_extremes(prec, d, h):
     P = lib()
     K, n, T, B, H = 4, 64, 8, 6, 8
