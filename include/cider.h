@@ -246,6 +246,27 @@ int cider_evidence(const float* y, float sigma2, int32_t K, int32_t n, float* ou
 int cider_amp_evidence(const float* y, const int32_t* rows, int64_t slots, int32_t n_s, int32_t Q, float rho,
                        float su2, int32_t iters, float* out_S, void* stream);
 
+/* Check-node update of the GF(64) parity layer (Appendix, Q-ary LDPC code
+ * over F_Q; FFT-BP's Walsh-Hadamard check update).  For every check
+ * sum_i alpha_i x_i = 0 (row j of H, edges row_ptr[j] .. row_ptr[j+1]-1 in
+ * CSR order) and every edge o of it, writes the message to the variable of
+ * edge o: m_o(a) proportional to the probability, under the other edges'
+ * distributions, that their weighted sum equals alpha_o a; normalised, FP32.
+ * Field: GF(2^6) in polynomial basis with primitive polynomial x^6 + x + 1,
+ * symbol index = the element's coefficient bits.
+ *   p_edge   device float [edges][64]: variable-to-check distribution of each edge
+ *   row_ptr  device int32 [checks + 1], row_ptr[0] = 0, row_ptr[checks] = edges
+ *   coef     device uint8 [edges]: the edge's coefficient alpha, 1..63
+ *   out_msg  device float [edges][64]
+ * Check degrees 1..32.  A row whose bounds fall outside 0..edges or whose
+ * degree is outside 1..32 is left unwritten (no access outside the
+ * buffers); a zero coefficient gives unspecified values.  The caller owns
+ * every buffer; the call is enqueued on `stream` and does not synchronise.
+ * CIDER_EINVAL for negative or too large sizes or NULL buffers (nothing
+ * enqueued), CIDER_EDEVICE if the launch fails. */
+int cider_gf64_check_update(const float* p_edge, const int32_t* row_ptr, const uint8_t* coef, int64_t checks,
+                            int64_t edges, float* out_msg, void* stream);
+
 /* ---- serving: continuous batching of arriving bins ---------------------- */
 typedef struct cider_server cider_server;
 

@@ -1,7 +1,7 @@
 """FP64 oracle pieces of the non-binary (GF(2^m), Q = 2^m) parity layer
 (Q-ary LDPC code; FFT-BP's check update; the coefficient action Pi_alpha of
 the latent Module B).  Test infrastructure only: the HIP library never
-imports or calls it, and no GPU kernel for the non-binary path exists yet.
+imports or calls it.
 
 Readings where the text leaves a choice:
 - the field is GF(2^m) in polynomial basis with a fixed primitive

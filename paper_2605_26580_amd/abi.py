@@ -24,7 +24,7 @@ CIDER_MASK = 2
 EXPORTS = [
     "cider_opts_default", "cider_weights_blob_floats", "cider_weights_create", "cider_weights_destroy",
     "cider_code_create", "cider_code_destroy", "cider_workspace_size", "cider_decode",
-    "cider_decode_batch", "cider_step_debug", "cider_evidence", "cider_amp_evidence", "cider_server_create",
+    "cider_decode_batch", "cider_step_debug", "cider_evidence", "cider_amp_evidence", "cider_gf64_check_update", "cider_server_create",
     "cider_server_submit", "cider_server_poll", "cider_server_drain", "cider_server_destroy",
     "cider_strerror", "cider_last_error", "cider_profile_read", "cider_tuning_read",
 ]
@@ -115,6 +115,7 @@ def lib() -> C.CDLL:
                                    C.POINTER(cider_opts), vp, vp, vp, vp]
     L.cider_evidence.argtypes = [vp, f32, i32, i32, vp, vp, vp]
     L.cider_amp_evidence.argtypes = [vp, vp, C.c_int64, i32, i32, f32, f32, i32, vp, vp]
+    L.cider_gf64_check_update.argtypes = [vp, vp, vp, C.c_int64, C.c_int64, vp, vp]
     L.cider_server_create.argtypes = [C.POINTER(cider_server_cfg), C.POINTER(vp)]
     L.cider_server_submit.argtypes = [vp, vp, f32, vp, i32, i32, vp, C.POINTER(C.c_uint64)]
     L.cider_server_poll.argtypes = [vp, C.POINTER(cider_result), i32, C.POINTER(i32)]
@@ -128,7 +129,7 @@ def lib() -> C.CDLL:
     L.cider_last_error.argtypes = []
     L.cider_last_error.restype = C.c_char_p
     for name in ("cider_weights_create", "cider_code_create", "cider_workspace_size", "cider_decode",
-                 "cider_decode_batch", "cider_step_debug", "cider_evidence", "cider_amp_evidence",
+                 "cider_decode_batch", "cider_step_debug", "cider_evidence", "cider_amp_evidence", "cider_gf64_check_update",
                  "cider_server_create", "cider_server_submit", "cider_server_poll", "cider_server_drain",
                  "cider_profile_read", "cider_tuning_read"):
         getattr(L, name).restype = C.c_int
@@ -271,6 +272,11 @@ def cider_step_debug(X_in, X_out, y, sigma2: float, code: Code, K: int, n: int, 
                                  float(gamma), int(reveal_count), int(first),
                                  C.byref(opts) if opts is not None else None, _ptr(out_lbar), _ptr(out_logits),
                                  _ptr(out_z), _stream(stream)), "cider_step_debug")
+
+
+def cider_gf64_check_update(p_edge, row_ptr, coef, checks: int, edges: int, out_msg, stream=None) -> None:
+    check(lib().cider_gf64_check_update(_ptr(p_edge), _ptr(row_ptr), _ptr(coef), int(checks), int(edges),
+                                        _ptr(out_msg), _stream(stream)), "cider_gf64_check_update")
 
 
 def cider_amp_evidence(y, rows, slots: int, n_s: int, Q: int, rho: float, su2: float, iters: int, out_S,

@@ -139,6 +139,16 @@ struct Work {
   float* S;        // [slots][2] per-slot log evidence
 };
 
+// GF(64) check-node update: per-edge distributions in, per-edge messages out.
+struct GfCheckArgs {
+  const float* p;          // [edges][64] variable-to-check distributions, CSR edge order
+  const int32_t* row_ptr;  // [checks + 1]
+  const uint8_t* coef;     // [edges] nonzero GF(64) coefficients
+  long checks, edges;
+  float* out;              // [edges][64] check-to-variable messages
+};
+hipError_t launch_gf64_check(const GfCheckArgs& g, hipStream_t s);
+
 // ---- launchers (kernels_*.hip) --------------------------------------------
 hipError_t launch_evidence(const StepCtx& c, float* S, float* p, hipStream_t s);
 hipError_t launch_init_bins(const StepCtx& c, int T, int first_reveal, hipStream_t s);

@@ -1222,6 +1222,18 @@ int cider_amp_evidence(const float* y, const int32_t* rows, int64_t slots, int32
   return CIDER_OK;
 }
 
+int cider_gf64_check_update(const float* p_edge, const int32_t* row_ptr, const uint8_t* coef, int64_t checks,
+                            int64_t edges, float* out_msg, void* stream) {
+  if (checks < 0 || edges < 0 || checks >= ((int64_t)1 << 31) || edges >= ((int64_t)1 << 31))
+    return fail(CIDER_EINVAL, "bad GF(64) check-update sizes");
+  if (checks > 0 && (!p_edge || !row_ptr || !coef || !out_msg)) return fail(CIDER_EINVAL, "null GF(64) buffer");
+  GfCheckArgs g{};
+  g.p = p_edge; g.row_ptr = row_ptr; g.coef = coef; g.checks = (long)checks; g.edges = (long)edges; g.out = out_msg;
+  const hipError_t err = launch_gf64_check(g, (hipStream_t)stream);
+  if (err != hipSuccess) return hip_fail(err, "cider_gf64_check_update");
+  return CIDER_OK;
+}
+
 int cider_evidence(const float* y, float sigma2, int32_t K, int32_t n, float* out_S, float* out_p, void* stream) {
   if (!y || K < 1 || K > CIDER_MAX_K || n < 1 || n > CIDER_MAX_N || !(sigma2 > 0.f))
     return fail(CIDER_EINVAL, "bad evidence arguments");

@@ -74,3 +74,14 @@ def test_amp_arguments_rejected_on_cpu():
         assert rc == -1, kw
     # valid sizes but missing buffers
     assert P.abi.lib().cider_amp_evidence(None, None, 4, 24, 64, 0.03, 2.0, 20, None, None) == -1
+
+
+def test_gf64_check_update_arguments_rejected_on_cpu():
+    """cider_gf64_check_update validates sizes and buffers before any device work."""
+    import paper_2605_26580_amd as P
+    L = P.abi.lib()
+    assert L.cider_gf64_check_update(None, None, None, -1, 0, None, None) == -1
+    assert L.cider_gf64_check_update(None, None, None, 0, -1, None, None) == -1
+    assert L.cider_gf64_check_update(None, None, None, 1 << 31, 10, None, None) == -1
+    assert L.cider_gf64_check_update(None, None, None, 4, 12, None, None) == -1      # null buffers
+    assert L.cider_gf64_check_update(None, None, None, 0, 0, None, None) == 0        # nothing to do
