@@ -160,7 +160,7 @@ typedef struct {
 } cider_bin;
 
 /* Fills `opts` with the defaults listed above. */
-void cider_opts_default(cider_opts* opts);
+void cider_opts_default(cider_opts* opts);   /* opts: host, not NULL */
 
 /* Number of floats a weights blob for `cfg` holds (layout below), or 0 if cfg
  * is invalid.  Blob layout, all row-major FP32, a linear map is y = x W^T + b:
@@ -174,14 +174,25 @@ void cider_opts_default(cider_opts* opts);
  * head h uses rows h*d/heads .. (h+1)*d/heads - 1 of each block. */
 size_t cider_weights_blob_floats(const cider_model_cfg* cfg);
 
-/* Uploads a host FP32 blob to the current device and prepares the FP32, BF16
- * and FP8 copies of every matrix.  Synchronous.  `n_floats` must equal
- * cider_weights_blob_floats(cfg). */
+/* The denoiser's parameters: the embedding table E (two symbols and the
+ * mask token), the shared symbol projection W, the evidence embeddings v_a
+ * and the gate MLP of Module A (Appendix, CIDER architecture: latent
+ * parameterisation and slot-competition demixing; method section, Module A
+ * equations), the L pre-LN blocks the workload defines, and the final
+ * LayerNorm feeding the logit projection.
+ * Uploads a host FP32 blob (read during the call only) to the current
+ * device and prepares the FP32, BF16 and FP8 copies of every matrix.
+ * Synchronous.  `n_floats` must equal cider_weights_blob_floats(cfg), else
+ * CIDER_EINVAL; an invalid cfg is CIDER_EINVAL, a failed device allocation
+ * CIDER_ENOMEM.  *out is owned by the caller until cider_weights_destroy. */
 int cider_weights_create(const cider_model_cfg* cfg, const float* host_blob, size_t n_floats,
                          cider_weights** out);
 void cider_weights_destroy(cider_weights* w);
 
-/* Binary parity-check matrix H (m checks x n slots) given as host CSR:
+/* The shared code's parity-check matrix, which the parity-aware decoder is
+ * given (Appendix, Q-ary LDPC code: H over F_Q with its Tanner graph, taken
+ * here at Q = 2; multiuser-code families and parity-check metadata).
+ * Binary H (m checks x n slots) given as host CSR (read during the call):
  * row_ptr[m+1], col_idx[row_ptr[m]] with ascending, distinct column indices
  * in [0, n).  Rows may have any degree up to 32; every slot may appear in
  * at most 32 checks.  Copied to the device; synchronous. */
@@ -190,12 +201,18 @@ int cider_code_create(int32_t n, int32_t m, const int32_t* row_ptr, const int32_
 void cider_code_destroy(cider_code* code);
 
 /* Bytes of caller workspace a batch of `num_bins` bins with `total_tokens`
- * = sum of K*n and `total_slots` = sum of n needs under `opts`. */
+ * = sum of K*n and `total_slots` = sum of n needs under `opts`: the
+ * per-token residual stream and activations of one denoiser forward plus the
+ * per-bin grid, logit and schedule state of the refinement loop (method
+ * section, refinement loop).  Writes *bytes; CIDER_EINVAL for NULL or
+ * negative arguments.  No device work. */
 int cider_workspace_size(const cider_weights* w, int32_t num_bins, int64_t total_tokens,
                          int64_t total_slots, const cider_opts* opts, size_t* bytes);
 
-/* Decodes one bin (problem statement: evidence from y, then S -> unordered
- * K x n grid).  y: device [n] FP32; out_symbols: device [K][n] uint8.
+/* Decodes one bin: evidence from y, then the map from evidence S to an
+ * unordered K x n grid (Appendix, multiuser decoding objective and
+ * set-valued output), computed by the refinement loop of the method section
+ * with the final pass and remasking of the inference appendix.  y: device [n] FP32; out_symbols: device [K][n] uint8.
  * steps = T of the initial pass, 1 <= steps <= K*n.  opts may be NULL for the
  * defaults.  Returns after enqueueing, except that with remasking on the
  * call synchronises `stream` once per remask round to learn whether any bin
@@ -205,12 +222,21 @@ int cider_decode(const float* y, float sigma2, const cider_code* code, int32_t K
                  const cider_opts* opts, void* stream);
 
 /* Decodes `num_bins` independent bins of possibly different K, n and code in
- * one packed pass per step.  The result of every bin is bit-identical to
- * decoding it alone with cider_decode and the same opts. */
+ * one packed pass per step.  Bins share no state: each preamble bin of the
+ * random-access protocol is decoded on its own (Appendix, protocol-level
+ * scalability: per-bin decoding), so a batch is only a launch-level grouping
+ * of cider_decode calls.  bins: host array [num_bins] (read during the
+ * call); its device buffers follow cider_decode's rules.  The result of
+ * every bin is bit-identical to decoding it alone with cider_decode and the
+ * same opts.  CIDER_EINVAL if any bin fails cider_decode's checks (nothing
+ * enqueued). */
 int cider_decode_batch(int32_t num_bins, const cider_bin* bins, const cider_weights* w,
                        int32_t steps, const cider_opts* opts, void* stream);
 
-/* Test entry point: one teacher-forced denoiser step on a given grid.
+/* Test entry point: one refinement step (method section, refinement loop:
+ * denoiser forward with Modules A and B, then the confidence-ranked reveal
+ * of the masked-diffusion inference appendix) on a given grid, teacher
+ * forced: the caller supplies the grid instead of the previous step.
  * X_in: device [K][n] uint8 in {0,1,2}; gamma: mask-ratio input.
  * Writes out_lbar (logits before Module B) and out_logits (after), device
  * [K][n][2] FP32, either may be NULL; out_z: device [K][n][d] FP32 residual
@@ -222,8 +248,12 @@ int cider_step_debug(const uint8_t* X_in, uint8_t* X_out, const float* y, float 
                      float gamma, int32_t reveal_count, int32_t first, const cider_opts* opts,
                      float* out_lbar, float* out_logits, float* out_z, void* stream);
 
-/* Per-slot evidence alone: out_S and out_p device [n][2] FP32 (either may be
- * NULL).  S[l,a] = log Pr(symbol a present at slot l | y_l), p = softmax_a S. */
+/* Per-slot evidence alone (Appendix, per-slot channel model and symbol-level
+ * soft evidence): out_S and out_p device [n][2] FP32 (either may be NULL).
+ * S[l,a] = log Pr(symbol a present at slot l | y_l), exact over the number
+ * of users sending bit 1; p = softmax_a S.  y: device [n] FP32.
+ * CIDER_EINVAL for K outside 1..CIDER_MAX_K, n outside 1..CIDER_MAX_N,
+ * sigma2 <= 0 or a NULL y. */
 int cider_evidence(const float* y, float sigma2, int32_t K, int32_t n, float* out_S, float* out_p,
                    void* stream);
 
@@ -290,7 +320,10 @@ typedef struct {
   double   t_done;
 } cider_result;
 
-/* Creates a server with its own HIP stream and worker thread on the current
+/* Continuous batching of arriving bins, each decoded as cider_decode would
+ * decode it alone (Appendix, protocol-level scalability: bins arrive from
+ * the preamble stage and are decoded independently).
+ * Creates a server with its own HIP stream and worker thread on the current
  * device.  Resident bins advance one refinement step per iteration; a newly
  * admitted bin joins at its own step 1 while others are mid-decode. */
 int cider_server_create(const cider_server_cfg* cfg, cider_server** out);
@@ -306,7 +339,8 @@ int cider_server_poll(cider_server* s, cider_result* out, int32_t max, int32_t* 
 int cider_server_drain(cider_server* s);
 void cider_server_destroy(cider_server* s);
 
-/* Per-kernel timings gathered by decode calls made with opts->profile = 1 on
+/* Introspection (no step of the method): per-kernel timings gathered by
+ * decode calls made with opts->profile = 1 on
  * this weights handle.  Synchronises the device.  Kernels are named by their
  * role in the step (e.g. "gemm_mlp_up", "attn_row", "step_tail").  `reset`
  * clears the accumulated figures after reading. */
@@ -318,7 +352,8 @@ typedef struct {
 int cider_profile_read(const cider_weights* w, cider_kernel_stat* out, int32_t max, int32_t* n_out,
                        int32_t reset);
 
-/* The GEMM tile shapes the autotuner chose on this weights handle: one entry
+/* Introspection (no step of the method): the GEMM tile shapes the autotuner
+ * chose on this weights handle: one entry
  * per (role, N, Kd, token-count bucket 2^bucket) with the tile index and the
  * best measured launch time.  Tile indices are those of the library's GEMM
  * (0 = the default shape). */

@@ -18,7 +18,7 @@ LIB = os.path.join(PKG, "libcider.so")
 OBJDIR = os.path.join(PKG, "_build")
 
 SOURCES = ["engine.cpp", "kernels_misc.hip", "kernels_gemm.hip", "kernels_attn.hip", "kernels_fast.hip",
-           "kernels_block.hip", "kernels_mlp.hip", "kernels_amp.hip", "kernels_gf.hip", "server.cpp"]
+           "kernels_block.hip", "kernels_mlp.hip", "kernels_amp.hip", "kernels_gf.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-x", "hip", "-ffp-contract=off",
@@ -49,7 +49,10 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False) -> str:
     """Compile every source and link libcider.so; returns the library path."""
     os.makedirs(OBJDIR, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    missing = [s for s in SOURCES if not os.path.exists(os.path.join(CSRC, s))]
+    if missing:
+        raise RuntimeError(f"missing sources: {missing}")
+    srcs = list(SOURCES)
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"

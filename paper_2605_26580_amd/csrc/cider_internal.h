@@ -75,7 +75,8 @@ struct StepCtx {
   int total_ugrp;
   int total_ugrp32;
   long total_tokens;
-  int max_n;                // largest n in the batch
+  int max_n;                // largest n in the batch (in the launch's rows, for row launches)
+  int row_first;            // first row of a row launch (rows row_first .. row_first + total_rows - 1)
   int schedule, remask, max_rounds, final_argmax;
   int first_verbatim;       // first-reveal step reveals every slot's selected site
   float remask_thr, tau, eta, lam_max, lam_min;

@@ -22,15 +22,23 @@ using namespace cider;
 
 namespace {
 
-thread_local std::string g_err;
+// Last error of the calling thread, kept in a fixed buffer so that reporting
+// an error never allocates.
+thread_local char g_err[512];
 
-int fail(int code, const std::string& msg) {
-  g_err = msg;
+void set_err(const char* what, const char* detail = nullptr) {
+  std::snprintf(g_err, sizeof(g_err), "%s%s%s", what, detail ? ": " : "", detail ? detail : "");
+}
+
+int fail(int code, const char* msg) {
+  set_err(msg);
   return code;
 }
 
+int fail(int code, const std::string& msg) { return fail(code, msg.c_str()); }
+
 int hip_fail(hipError_t e, const char* what) {
-  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  set_err(what, hipGetErrorString(e));
   return CIDER_EDEVICE;
 }
 
@@ -153,26 +161,41 @@ namespace {
 // then, for the initial pass (j = 0, T steps over K n sites) and for every
 // remask pass over j rows (T_rm = max(1, floor(T j / K)) steps over j n
 // sites), the cumulative number of sites revealed after each step.
-std::vector<int> schedule_table(int K, int n, int T, int kind) {
-  std::vector<int> off(K + 1), len(K + 1), data;
+// Emits the table's ints in order through put(int).
+template <class Put>
+void schedule_emit(int K, int n, int T, int kind, Put put) {
+  auto pass_T = [&](int j) { return (j == 0) ? T : std::max(1, (int)((long)T * j / K)); };
+  int off = 0;
   for (int j = 0; j <= K; ++j) {
-    int Tp = (j == 0) ? T : std::max(1, (int)((long)T * j / K));
-    long Nm = (long)(j == 0 ? K : j) * n;
-    off[j] = (int)data.size();
-    len[j] = Tp;
+    put(off);
+    off += pass_T(j);
+  }
+  for (int j = 0; j <= K; ++j) put(pass_T(j));
+  for (int j = 0; j <= K; ++j) {
+    const int Tp = pass_T(j);
+    const long Nm = (long)(j == 0 ? K : j) * n;
     for (int t = 1; t <= Tp; ++t) {
       long R;
       if (kind == CIDER_SCHED_COSINE)
         R = (long)std::floor(0.5 * (1.0 - std::cos(M_PI * (double)t / (double)Tp)) * (double)Nm);
       else
         R = (long)t * Nm / Tp;
-      data.push_back((int)R);
+      put((int)R);
     }
   }
+}
+
+// Number of ints in the table of a K-row bin with T initial steps.
+long schedule_ints(int K, int T) {
+  long total = 2L * (K + 1);
+  for (int j = 0; j <= K; ++j) total += (j == 0) ? T : std::max(1, (int)((long)T * j / K));
+  return total;
+}
+
+std::vector<int> schedule_table(int K, int n, int T, int kind) {
   std::vector<int> out;
-  out.insert(out.end(), off.begin(), off.end());
-  out.insert(out.end(), len.begin(), len.end());
-  out.insert(out.end(), data.begin(), data.end());
+  out.reserve(schedule_ints(K, T));
+  schedule_emit(K, n, T, kind, [&](int v) { out.push_back(v); });
   return out;
 }
 
@@ -269,12 +292,34 @@ int ensure_pinned(cider_weights* w, size_t need) {
   return CIDER_OK;
 }
 
+// Row-sublayer path a bin of n slots takes.  Bins are packed path by path,
+// so the rows (and tokens) of one path are contiguous and each path runs as
+// its own launches: a bin's kernels depend on its own shape only, never on
+// the other bins it is batched with.
+enum RowPath : int { kRowGeneral = 0, kRowBlockTr = 1, kRowAttnBlock = 2, kRowQkvAttn = 3, kRowPaths = 4 };
+
+int row_path(const cider_model_cfg& m, int prec, bool use_blocks, int n) {
+  if (prec != kBF16 || !use_blocks) return kRowGeneral;
+  if (row_block_tr_ok(m.d, m.heads, n)) return kRowBlockTr;
+  if (attn_block_ok(m.d, m.heads, n, false)) return kRowAttnBlock;
+  if (row_qkv_attn_ok(m.d, m.heads, n)) return kRowQkvAttn;
+  return kRowGeneral;
+}
+
+// The rows and tokens of one row path inside the packed batch.
+struct RowSeg {
+  int path, row0, rows, max_n;
+  long tok0, toks;
+};
+
 struct Run {
   StepCtx ctx{};
   Work work{};
   int prec = 0;
   int forced_tile = -1;   // >= 0: every GEMM uses this tile (tests)
   bool use_blocks = true; // fused attention blocks where the shapes allow
+  RowSeg seg[kRowPaths]{};
+  int nseg = 0;
 };
 
 // Brackets a launch with events when profiling is on.
@@ -378,12 +423,14 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
   // epilogue (set ln_g / ln_b / out); FP32 runs it as its own kernel.
   const bool fused_ln = prec != kF32;
   const bool f8 = prec == kFP8;
-  auto next_ln = [&](GemmArgs& g, const float* gg, const float* bb) {
+  const size_t es = esize(prec);
+  // LayerNorm epilogue into XN (or XN8 and its scales) for the tokens from tok0 on
+  auto next_ln = [&](GemmArgs& g, const float* gg, const float* bb, long tok0 = 0) {
     if (!fused_ln) return;
     g.ln_g = gg;
     g.ln_b = bb;
-    if (f8) { g.out = k.XN8; g.out_scale = k.xscale; }
-    else g.out = k.XN;
+    if (f8) { g.out = k.XN8 + tok0 * d; g.out_scale = k.xscale + tok0; }
+    else g.out = (char*)k.XN + tok0 * d * es;
   };
   // the GEMMs fed by a LayerNorm (QKV, MLP up) read XN8 with its per-token
   // scale in FP8, the others stay BF16
@@ -393,15 +440,14 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
   auto oproj = [&](const GemmArgs& g, const Mat& W) -> hipError_t {
     return p3 ? launch_oproj3_bf16(g, W, s) : gemm(kEpiResid, g, W);
   };
-  auto qkv = [&](GemmArgs& g, const Mat& W) -> hipError_t {
+  auto qkv = [&](GemmArgs& g, const Mat& W, long tok0 = 0) -> hipError_t {
     if (p3) return launch_proj3_bf16(g, W, s);
     if (!f8) return gemm(kEpiStore, g, W);
-    g.A = k.XN8;
-    g.a_scale = k.xscale;
+    g.A = k.XN8 + tok0 * d;
+    g.a_scale = k.xscale + tok0;
     return launch_gemm_fp8(g, W, s);
   };
-  // BF16: fused attention blocks where the shapes allow (row attention needs n <= 128)
-  const bool blk_row = prec == kBF16 && r.use_blocks && attn_block_ok(d, m.heads, c.max_n, false);
+  // BF16: fused attention blocks where the shapes allow (the row variant is a row path)
   const bool blk_user = prec == kBF16 && r.use_blocks && attn_block_ok(d, m.heads, c.max_n, true);
   const bool user_mlp = prec == kBF16 && r.use_blocks && user_mlp_tr_ok(d, m.heads, F);
   // d = 256: the user-attention output projection runs with the MLP (needs the fused
@@ -410,9 +456,10 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
                          oproj_mlp3_ok(d, F);
   // d = 256 with the unfused row sublayer (which leaves O in k.O): its output projection runs
   // with the user sublayer's QKV projection and attention
-  const bool oproj_user = prec == kBF16 && r.use_blocks && !row_block_tr_ok(d, m.heads, c.max_n) && !blk_row &&
-                          !user_mlp && !user_block_tr_ok(d, m.heads) && !blk_user &&
-                          oproj_user_attn_ok(d, m.heads);
+  // (only where no row can take a sublayer-complete row path, whatever its length)
+  const bool oproj_user = prec == kBF16 && r.use_blocks && !row_block_tr_ok(d, m.heads, 1) &&
+                          !attn_block_ok(d, m.heads, 1, false) && !user_mlp && !user_block_tr_ok(d, m.heads) &&
+                          !blk_user && oproj_user_attn_ok(d, m.heads);
   GemmArgs g{};
   g.M = T;
   // BF16 at d = 128 and 256: embedding, Module A and the first LayerNorm in one kernel
@@ -451,27 +498,39 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
   for (int l = 0; l < m.n_layers; ++l) {
     const DevLayer& L = m.layer[l];
     if (!fused_ln) TIMED("layernorm", ln(L.ln1_g, L.ln1_b));
-    if (prec == kBF16 && r.use_blocks && row_block_tr_ok(d, m.heads, c.max_n)) {
-      // BF16, head width 16, n <= 128: the row-attention sublayer token-resident (one row per workgroup)
-      TIMED("row_block", launch_row_block_tr(c, k.XN, L, L.ln2_g, L.ln2_b, k.R, d, m.heads, s));
-    } else if (blk_row) {
-      // BF16: QKV projection, row attention, output projection, residual and LN2 in one kernel
-      TIMED("attn_block_row", launch_attn_block(c, false, k.XN, L, L.ln2_g, L.ln2_b, k.R, d, m.heads, s));
-    } else {
-      if (prec == kBF16 && r.use_blocks && row_qkv_attn_ok(d, m.heads, c.max_n)) {
+    // the row sublayer, one launch sequence per row path (rows and tokens of a path are contiguous)
+    for (int si = 0; si < r.nseg; ++si) {
+      const RowSeg& sg = r.seg[si];
+      StepCtx sc = c;
+      sc.row_first = sg.row0;
+      sc.total_rows = sg.rows;
+      sc.max_n = sg.max_n;
+      if (sg.path == kRowBlockTr) {
+        // BF16, head width 16, n <= 128: the row-attention sublayer token-resident (one row per workgroup)
+        TIMED("row_block", launch_row_block_tr(sc, k.XN, L, L.ln2_g, L.ln2_b, k.R, d, m.heads, s));
+        continue;
+      }
+      if (sg.path == kRowAttnBlock) {
+        // BF16: QKV projection, row attention, output projection, residual and LN2 in one kernel
+        TIMED("attn_block_row", launch_attn_block(sc, false, k.XN, L, L.ln2_g, L.ln2_b, k.R, d, m.heads, s));
+        continue;
+      }
+      if (sg.path == kRowQkvAttn) {
         // BF16, head width 32, n <= 256: QKV projection and row attention in one kernel
-        TIMED("qkv_attn_row", launch_row_qkv_attn(c, k.XN, L.Wqkv_r, L.bqkv_r, k.O, d, m.heads, s));
+        TIMED("qkv_attn_row", launch_row_qkv_attn(sc, k.XN, L.Wqkv_r, L.bqkv_r, k.O, d, m.heads, s));
       } else {
-        g = GemmArgs{}; g.M = T;
-        g.N = 3 * d; g.Kd = d; g.A = k.XN; g.bias = L.bqkv_r; g.out = k.QKV;
-        TIMED("gemm_qkv_row", qkv(g, L.Wqkv_r));
-        if (prec == kF32) TIMED("attn_row", launch_row_attn(c, prec, k.QKV, k.O, d, m.heads, c.max_n, s));
-        else TIMED("attn_row", launch_row_attn_mfma(c, k.QKV, k.O, d, m.heads, c.max_n, s));
+        // token-wise projections over the path's tokens; the attention indexes tokens absolutely
+        g = GemmArgs{}; g.M = sg.toks;
+        g.N = 3 * d; g.Kd = d; g.A = (char*)k.XN + sg.tok0 * d * es; g.bias = L.bqkv_r;
+        g.out = (char*)k.QKV + sg.tok0 * 3 * d * es;
+        TIMED("gemm_qkv_row", qkv(g, L.Wqkv_r, sg.tok0));
+        if (prec == kF32) TIMED("attn_row", launch_row_attn(sc, prec, k.QKV, k.O, d, m.heads, sg.max_n, s));
+        else TIMED("attn_row", launch_row_attn_mfma(sc, k.QKV, k.O, d, m.heads, sg.max_n, s));
       }
       if (!oproj_user) {
-        g = GemmArgs{}; g.M = T;
-        g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_r; g.R = k.R;
-        next_ln(g, L.ln2_g, L.ln2_b);
+        g = GemmArgs{}; g.M = sg.toks;
+        g.N = d; g.Kd = d; g.A = (char*)k.O + sg.tok0 * d * es; g.bias = L.bo_r; g.R = k.R + sg.tok0 * d;
+        next_ln(g, L.ln2_g, L.ln2_b, sg.tok0);
         TIMED("gemm_o_row", oproj(g, L.Wo_r));
       }
     }
@@ -705,86 +764,10 @@ int check_bin(const cider_weights* w, const BinIn& b, int steps) {
   return CIDER_OK;
 }
 
-// Lays out a batch in the workspace and uploads its metadata; fills `r`.
-int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const cider_opts& o,
-            hipStream_t s, Run* r, Layout* Lout, bool init_grids) {
-  const int B = (int)bins.size();
-  long T = 0;
-  int slots = 0, rows = 0, max_n = 0;
-  for (const BinIn& b : bins) {
-    T += (long)b.K * b.n;
-    slots += b.n;
-    rows += b.K;
-    max_n = std::max(max_n, b.n);
-  }
-  Layout L = plan_layout(w->cfg, B, T, slots, rows, o.precision);
-  L.max_n = max_n;
-  char* base = nullptr;
-  int rc = ensure_ws(w, o, L.total, &base);
-  if (rc) return rc;
-  int ngrp = 0, ngrp32 = 0;
-  for (const BinIn& b : bins) {
-    ngrp += (b.n + ugrp_cols(b.K) - 1) / ugrp_cols(b.K);
-    ngrp32 += (b.n + 32 / b.K - 1) / (32 / b.K);
-  }
-  const int ntile = (int)((T + 255) / 256);
-  size_t meta = B * sizeof(DevBin) + (size_t)(slots + rows) * 4 + (size_t)ngrp * 2 * 4 + (size_t)ntile * 4 +
-                (size_t)ngrp32 * 2 * 4;
-  rc = ensure_pinned(w, meta);
-  if (rc) return rc;
-  DevBin* hb = (DevBin*)w->pinned;
-  int* hslot = (int*)((char*)w->pinned + B * sizeof(DevBin));
-  int* hrow = hslot + slots;
-  int* hgrp = hrow + rows;
-  int* htile = hgrp + 2 * (size_t)ngrp;
-  int* hgrp32 = htile + ntile;
-  int go32 = 0;
-  int go = 0;
-  long tok = 0;
-  int so = 0, ro = 0;
-  for (int i = 0; i < B; ++i) {
-    const BinIn& b = bins[i];
-    int* sched = nullptr;
-    rc = get_sched(w, b.K, b.n, steps, o.schedule, &sched);
-    if (rc) return rc;
-    DevBin db{};
-    db.tok_off = (int)tok;
-    db.K = b.K; db.n = b.n; db.m = b.code->m;
-    db.slot_off = so; db.row_off = ro;
-    db.row_ptr = b.code->d_row_ptr; db.col_idx = b.code->d_col_idx;
-    db.var_ptr = b.code->d_var_ptr; db.var_edge = b.code->d_var_edge;
-    db.sched = sched;
-    db.y = b.y; db.sigma2 = b.sigma2;
-    db.X = b.X ? b.X : (uint8_t*)(base + L.off_X) + tok;
-    db.out_sym = b.out_sym; db.out_logits = b.out_logits; db.out_valid = b.out_valid;
-    db.st = b.st ? b.st : (BinState*)(base + L.off_state) + i;
-    hb[i] = db;
-    for (int l = 0; l < b.n; ++l) hslot[so + l] = i;
-    for (int k = 0; k < b.K; ++k) hrow[ro + k] = i;
-    for (int l0 = 0; l0 < b.n; l0 += ugrp_cols(b.K)) {
-      hgrp[2 * go] = i;
-      hgrp[2 * go + 1] = l0;
-      ++go;
-    }
-    for (long t0 = (tok + 255) / 256 * 256; t0 < tok + (long)b.K * b.n; t0 += 256) htile[t0 / 256] = i;
-    for (int l0 = 0; l0 < b.n; l0 += 32 / b.K) {
-      hgrp32[2 * go32] = i;
-      hgrp32[2 * go32 + 1] = l0;
-      ++go32;
-    }
-    tok += (long)b.K * b.n;
-    so += b.n;
-    ro += b.K;
-  }
-  if (T > (long)INT32_MAX) return fail(CIDER_EINVAL, "batch too large");
-  HIPCHK(hipMemcpyAsync(base + L.off_bins, hb, B * sizeof(DevBin), hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(base + L.off_slot, hslot, (size_t)slots * 4, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(base + L.off_row, hrow, (size_t)rows * 4, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(base + L.off_ugrp, hgrp, (size_t)ngrp * 2 * 4, hipMemcpyHostToDevice, s));
-  if (ntile) HIPCHK(hipMemcpyAsync(base + L.off_tile, htile, (size_t)ntile * 4, hipMemcpyHostToDevice, s));
-  if (ngrp32) HIPCHK(hipMemcpyAsync(base + L.off_ugrp32, hgrp32, (size_t)ngrp32 * 2 * 4, hipMemcpyHostToDevice, s));
-  HIPCHK(hipEventRecord(w->meta_done, s));
-
+// Points a Run's step context and work buffers at a laid-out workspace
+// whose per-bin metadata (bins, slot / row / group / tile maps) is in place.
+void fill_run(Run* r, const Layout& L, char* base, const cider_opts& o, int B, long T, int slots, int rows,
+              int max_n, int ngrp, int ngrp32) {
   StepCtx& c = r->ctx;
   c = StepCtx{};
   c.num_bins = B;
@@ -837,6 +820,108 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
   k.p = (float*)(base + L.off_p);
   k.S = (float*)(base + L.off_S);
   r->prec = o.precision;
+}
+
+// Lays out a batch in the workspace and uploads its metadata; fills `r`.
+int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const cider_opts& o,
+            hipStream_t s, Run* r, Layout* Lout, bool init_grids) {
+  const int B = (int)bins.size();
+  long T = 0;
+  int slots = 0, rows = 0, max_n = 0;
+  for (const BinIn& b : bins) {
+    T += (long)b.K * b.n;
+    slots += b.n;
+    rows += b.K;
+    max_n = std::max(max_n, b.n);
+  }
+  Layout L = plan_layout(w->cfg, B, T, slots, rows, o.precision);
+  L.max_n = max_n;
+  char* base = nullptr;
+  int rc = ensure_ws(w, o, L.total, &base);
+  if (rc) return rc;
+  int ngrp = 0, ngrp32 = 0;
+  for (const BinIn& b : bins) {
+    ngrp += (b.n + ugrp_cols(b.K) - 1) / ugrp_cols(b.K);
+    ngrp32 += (b.n + 32 / b.K - 1) / (32 / b.K);
+  }
+  const int ntile = (int)((T + 255) / 256);
+  size_t meta = B * sizeof(DevBin) + (size_t)(slots + rows) * 4 + (size_t)ngrp * 2 * 4 + (size_t)ntile * 4 +
+                (size_t)ngrp32 * 2 * 4;
+  rc = ensure_pinned(w, meta);
+  if (rc) return rc;
+  DevBin* hb = (DevBin*)w->pinned;
+  int* hslot = (int*)((char*)w->pinned + B * sizeof(DevBin));
+  int* hrow = hslot + slots;
+  int* hgrp = hrow + rows;
+  int* htile = hgrp + 2 * (size_t)ngrp;
+  int* hgrp32 = htile + ntile;
+  int go32 = 0;
+  int go = 0;
+  long tok = 0;
+  int so = 0, ro = 0;
+  // pack the bins path by path (stable within a path)
+  std::vector<int> path_of(B), ord(B);
+  for (int i = 0; i < B; ++i) {
+    path_of[i] = row_path(w->cfg, o.precision, o.fused_blocks != 0, bins[i].n);
+    ord[i] = i;
+  }
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return path_of[x] < path_of[y]; });
+  r->nseg = 0;
+  for (int i = 0; i < B; ++i) {
+    const BinIn& b = bins[ord[i]];
+    const int pth = path_of[ord[i]];
+    if (r->nseg == 0 || r->seg[r->nseg - 1].path != pth) {
+      RowSeg& sg = r->seg[r->nseg++];
+      sg = RowSeg{pth, ro, 0, 0, tok, 0};
+    }
+    RowSeg& sg = r->seg[r->nseg - 1];
+    sg.rows += b.K;
+    sg.toks += (long)b.K * b.n;
+    sg.max_n = std::max(sg.max_n, b.n);
+    int* sched = nullptr;
+    rc = get_sched(w, b.K, b.n, steps, o.schedule, &sched);
+    if (rc) return rc;
+    DevBin db{};
+    db.tok_off = (int)tok;
+    db.K = b.K; db.n = b.n; db.m = b.code->m;
+    db.slot_off = so; db.row_off = ro;
+    db.row_ptr = b.code->d_row_ptr; db.col_idx = b.code->d_col_idx;
+    db.var_ptr = b.code->d_var_ptr; db.var_edge = b.code->d_var_edge;
+    db.sched = sched;
+    db.y = b.y; db.sigma2 = b.sigma2;
+    db.X = b.X ? b.X : (uint8_t*)(base + L.off_X) + tok;
+    db.out_sym = b.out_sym; db.out_logits = b.out_logits; db.out_valid = b.out_valid;
+    db.st = b.st ? b.st : (BinState*)(base + L.off_state) + i;
+    hb[i] = db;
+    for (int l = 0; l < b.n; ++l) hslot[so + l] = i;
+    for (int k = 0; k < b.K; ++k) hrow[ro + k] = i;
+    for (int l0 = 0; l0 < b.n; l0 += ugrp_cols(b.K)) {
+      hgrp[2 * go] = i;
+      hgrp[2 * go + 1] = l0;
+      ++go;
+    }
+    for (long t0 = (tok + 255) / 256 * 256; t0 < tok + (long)b.K * b.n; t0 += 256) htile[t0 / 256] = i;
+    for (int l0 = 0; l0 < b.n; l0 += 32 / b.K) {
+      hgrp32[2 * go32] = i;
+      hgrp32[2 * go32 + 1] = l0;
+      ++go32;
+    }
+    tok += (long)b.K * b.n;
+    so += b.n;
+    ro += b.K;
+  }
+  if (T > (long)INT32_MAX) return fail(CIDER_EINVAL, "batch too large");
+  HIPCHK(hipMemcpyAsync(base + L.off_bins, hb, B * sizeof(DevBin), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(base + L.off_slot, hslot, (size_t)slots * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(base + L.off_row, hrow, (size_t)rows * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(base + L.off_ugrp, hgrp, (size_t)ngrp * 2 * 4, hipMemcpyHostToDevice, s));
+  if (ntile) HIPCHK(hipMemcpyAsync(base + L.off_tile, htile, (size_t)ntile * 4, hipMemcpyHostToDevice, s));
+  if (ngrp32) HIPCHK(hipMemcpyAsync(base + L.off_ugrp32, hgrp32, (size_t)ngrp32 * 2 * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hipEventRecord(w->meta_done, s));
+
+  fill_run(r, L, base, o, B, T, slots, rows, max_n, ngrp, ngrp32);
+  const StepCtx& c = r->ctx;
+  const Work& k = r->work;
   HIPCHK(launch_evidence(c, k.S, k.p, s));
   if (init_grids) {
     HIPCHK(launch_init_bins(c, steps, o.first_reveal, s));
@@ -940,7 +1025,7 @@ const char* cider_strerror(int st) {
   }
 }
 
-const char* cider_last_error(void) { return g_err.c_str(); }
+const char* cider_last_error(void) { return g_err; }
 
 size_t cider_weights_blob_floats(const cider_model_cfg* cfg) {
   std::string why;
@@ -1462,7 +1547,7 @@ void server_loop(cider_server* S) {
       hipMemcpyAsync(&S->h_states[order[j]], S->slots[order[j]].st, sizeof(BinState), hipMemcpyDeviceToHost,
                      S->stream);
     hipError_t e = hipStreamSynchronize(S->stream);
-    if (e != hipSuccess) { g_err = hipGetErrorString(e); fail_all(CIDER_EDEVICE); break; }
+    if (e != hipSuccess) { set_err(hipGetErrorString(e)); fail_all(CIDER_EDEVICE); break; }
     for (size_t j = 0; j < order.size(); ++j) {
       Slot& sl = S->slots[order[j]];
       const BinState& st = S->h_states[order[j]];

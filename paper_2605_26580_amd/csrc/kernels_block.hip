@@ -82,7 +82,7 @@ __global__ __launch_bounds__(NT * 4) __attribute__((amdgpu_waves_per_eu(USER && 
     bi = c.ugrp[2 * blockIdx.x];
     l0 = c.ugrp[2 * blockIdx.x + 1];
   } else {
-    bi = c.row_bin[blockIdx.x];
+    bi = c.row_bin[c.row_first + blockIdx.x];
   }
   const DevBin& b = c.bins[bi];
   if (b.st->phase == kDone) return;            // whole workgroup, before any barrier
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(NT * 4) __attribute__((amdgpu_waves_per_eu(USER && 
       const int t = tid >> 4, j = tid & 15, col = l0 + t * cpt + j / K;
       if (j < cpt * K && col < n) tok = b.tok_off + (j % K) * n + col;
     } else if (tid < n) {
-      tok = b.tok_off + (blockIdx.x - b.row_off) * n + tid;
+      tok = b.tok_off + (c.row_first + (int)blockIdx.x - b.row_off) * n + tid;
     }
     sTok[tid] = tok;
   }

@@ -1019,7 +1019,7 @@ __global__ __launch_bounds__(256) void k_row_attn_mfma(StepCtx c, const bf16* __
   typedef __bf16 qv_t __attribute__((__vector_size__(QE * sizeof(__bf16))));
   extern __shared__ __attribute__((aligned(16))) char smem_attn[];
   const int lb = xcd_logical((int)blockIdx.x, (int)gridDim.x);
-  const int r = lb / heads, h = lb - (lb / heads) * heads;
+  const int r = c.row_first + lb / heads, h = lb - (lb / heads) * heads;
   const DevBin& b = c.bins[c.row_bin[r]];
   if (b.st->phase == kDone) return;
   const int n = b.n, k = r - b.row_off;

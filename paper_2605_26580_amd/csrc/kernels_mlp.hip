@@ -1056,7 +1056,7 @@ void k_row_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const 
   float* sv = sbias + 3 * D;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
 
-  const int row = blockIdx.x;
+  const int row = c.row_first + (int)blockIdx.x;
   const DevBin& b = c.bins[c.row_bin[row]];
   if (b.st->phase == kDone) return;                 // whole workgroup, before any barrier
   const int n = b.n, slot = 32 * wave + l32;
@@ -1272,7 +1272,7 @@ void k_row_qkv_attn(StepCtx c, const bf16* __restrict__ XN, const bf16* __restri
   float* sbias = (float*)(smem + 2 * S::wa + S::k + S::vt);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
 
-  const int row = blockIdx.x;
+  const int row = c.row_first + (int)blockIdx.x;
   const DevBin& b = c.bins[c.row_bin[row]];
   if (b.st->phase == kDone) return;                 // whole workgroup, before any barrier
   const int n = b.n, slot = 32 * wave + l32;

@@ -19,7 +19,7 @@ import synth
 from oracle.denoiser import denoise
 from oracle.evidence import evidence
 
-from gpu_common import TOL, lib, rel_err, say, torch_cuda
+from gpu_common import TOL, code_handle, code_of, lib, rel_err, say, torch_cuda, valid_selection, weights_handle
 
 pytestmark = pytest.mark.gpu
 
@@ -126,6 +126,94 @@ def test_teacher_forced_step_at_workload_size(name):
         e_log = rel_err(logits.cpu().numpy(), ref["logits"])
         print(f"  err lbar={e_lbar:.2e} logits={e_log:.2e}")
         assert e_lbar <= tol and e_log <= tol, (e_lbar, e_log)
+        valid_selection(Xin, Xo.cpu().numpy(), ref["logits"], r, 0, slack=2 * tol * max(1.0, float(np.abs(ref["logits"]).max())))
+
+
+# (K, n, workload whose model runs): rows longer than every sublayer-complete
+# row kernel (n = 512 at d = 256 takes the QKV projection + LDS-resident row
+# attention), and the d = 384, 12-head model of the served workload up to its
+# largest bin (16 x 1024 = 16,384 tokens)
+LARGE = [(8, 512, "c4"), (4, 512, "c5"), (16, 1024, "c5")]
+
+
+@pytest.mark.parametrize("K,n,name", LARGE)
+def test_teacher_forced_step_at_large_shapes(K, n, name):
+    torch = torch_cuda()
+    P = lib()
+    wl = synth.workload(name)
+    cfg = wl.model
+    wh, w = weights_handle(cfg, wl.weight_seed)
+    code = code_of(n, 1000 + n)
+    ch = code_handle(code)
+    b = synth.make_bins(code, K, 1, 4.0, seed=K * 1000 + n)
+    y, s2 = b.y[0], float(b.sigma2[0])
+    _, p = evidence(y.astype(np.float64), s2, K)
+    rng = np.random.default_rng(K + n)
+    opts = P.cider_opts_default(precision=P.CIDER_BF16)
+    tol = TOL["bf16"]
+    yd = torch.from_numpy(np.ascontiguousarray(y)).cuda()
+    for frac, first in ((1.0, 1), (0.5, 0)):
+        Xin = rng.integers(0, 2, size=(K, n)).astype(np.uint8)
+        Xin[rng.random((K, n)) < frac] = 2
+        gamma = float((Xin == 2).mean())
+        say(f"teacher-forced BF16 K={K} n={n} L={cfg.n_layers} d={cfg.d} h={cfg.heads} mask={frac} first={first}")
+        ref = denoise(Xin, p, code, w, cfg.n_layers, cfg.heads, gamma)
+        lbar = torch.zeros(K, n, 2, dtype=torch.float32, device="cuda")
+        logits = torch.zeros_like(lbar)
+        Xo = torch.zeros(K, n, dtype=torch.uint8, device="cuda")
+        ncand = n if first else int((Xin == 2).sum())
+        r = max(1, ncand // 3)
+        P.cider_step_debug(torch.from_numpy(Xin).cuda(), Xo, yd, s2, ch, K, n, wh, gamma, r, first, opts,
+                           out_lbar=lbar, out_logits=logits)
+        torch.cuda.synchronize()
+        e_lbar = rel_err(lbar.cpu().numpy(), ref["lbar"])
+        e_log = rel_err(logits.cpu().numpy(), ref["logits"])
+        print(f"  err lbar={e_lbar:.2e} logits={e_log:.2e}")
+        assert e_lbar <= tol and e_log <= tol, (e_lbar, e_log)
+        valid_selection(Xin, Xo.cpu().numpy(), ref["logits"], r, first,
+                        slack=2 * tol * max(1.0, float(np.abs(ref["logits"]).max())))
+
+
+# bins on both sides of every row-path boundary: n <= 128 (token-resident row
+# sublayer at d = 128) beside longer rows, n <= 256 (fused QKV + row attention
+# at d = 256) beside n = 512
+MIXES = [("c2", [(4, 64), (2, 256), (3, 128), (1, 96)]), ("c4", [(4, 256), (2, 512), (8, 64), (3, 128)])]
+
+
+@pytest.mark.parametrize("name,shapes", MIXES)
+def test_batch_mix_across_row_paths_equals_alone_bitwise(name, shapes):
+    """Logits, symbols and row-valid flags of every bin are bit-identical in
+    the mixed batch and alone: a bin's kernels depend on its own shape only."""
+    torch = torch_cuda()
+    P = lib()
+    wl = synth.workload(name)
+    wh, _ = weights_handle(wl.model, wl.weight_seed)
+    items = []
+    for i, (K, n) in enumerate(shapes):
+        code = code_of(n, 1000 + n)
+        b = synth.make_bins(code, K, 1, 3.0 + i, seed=300 + i)
+        items.append((K, n, code_handle(code), torch.from_numpy(np.ascontiguousarray(b.y[0])).cuda(),
+                      float(b.sigma2[0])))
+    opts = P.cider_opts_default(precision=P.CIDER_BF16, use_graph=1)
+    T = 8
+
+    def run(sel):
+        outs = {i: (torch.full((items[i][0], items[i][1]), 9, dtype=torch.uint8, device="cuda"),
+                    torch.zeros(items[i][0], items[i][1], 2, dtype=torch.float32, device="cuda"),
+                    torch.zeros(items[i][0], dtype=torch.uint8, device="cuda")) for i in sel}
+        P.cider_decode_batch([{"y": items[i][3], "sigma2": items[i][4], "code": items[i][2], "K": items[i][0],
+                               "n": items[i][1], "out_symbols": outs[i][0], "out_logits": outs[i][1],
+                               "out_row_valid": outs[i][2]} for i in sel], wh, T, opts)
+        torch.cuda.synchronize()
+        return outs
+
+    say(f"batch mix {name}: shapes {shapes}, BF16, graph replay")
+    mixed = run(list(range(len(items))))
+    for i, (K, n, *_) in enumerate(items):
+        say(f"  {name} bin {i} (K={K}, n={n}) alone")
+        alone = run([i])[i]
+        for a, m, what in zip(alone, mixed[i], ("symbols", "logits", "row-valid")):
+            assert torch.equal(a, m), f"bin {i} (K={K}, n={n}): {what} differ between the mix and alone"
 
 
 def test_quality_head_control_flow_at_c3_size():

@@ -4,8 +4,6 @@ C ABI: every outgoing message of checks of degree 1..32 with random nonzero
 coefficients and random input distributions, within the FP32 tolerance;
 rows the kernel must skip (empty, or reaching past the edge count) are left
 unwritten."""
-import time
-
 import numpy as np
 import pytest
 
@@ -64,24 +62,3 @@ def test_gf64_malformed_rows_left_unwritten():
     assert np.all(got[2:] == -7.0)
     ref0 = gf.check_message_wht([p[1].astype(np.float64)], [int(coef[1])], int(coef[0]))
     assert np.max(np.abs(got[0] - ref0)) <= TOL["fp32"]
-
-
-def test_gf64_check_update_throughput():
-    """Timing only: 2^17 checks of degree 6 (786,432 edges, 201 MB in + 201 MB out)."""
-    torch = torch_cuda()
-    P = lib()
-    C, dc = 1 << 17, 6
-    row_ptr, coef, p = _random_check_set([dc] * C, 7)
-    E = C * dc
-    dp, dr, dcf = (torch.from_numpy(x).cuda() for x in (p, row_ptr, coef))
-    out = torch.empty((E, 64), dtype=torch.float32, device="cuda")
-    say(f"gf64 check update timing: {C} checks of degree {dc}")
-    P.cider_gf64_check_update(dp, dr, dcf, C, E, out)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(10):
-        P.cider_gf64_check_update(dp, dr, dcf, C, E, out)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / 10
-    print(f"  {dt * 1e3:.3f} ms per call, {E / dt / 1e6:.1f} M edges/s, {2 * E * 256 / dt / 1e9:.0f} GB/s of edge data")
-    assert np.isfinite(out[:4].cpu().numpy()).all()
