@@ -142,7 +142,17 @@ def run_amp(args):
     value = S_slots * args.steps / (t1 - t0)
     # one launch per call: the kernel's own average duration from the events
     avg_ms = float(np.mean(lat))
-    flop = S_slots * (iters * 16 + 8) * Q * n_s        # two complex products per iteration, one more at the end
+    # operations the kernel performs: at Q = 64 each partial-DFT product is a
+    # 64-point radix-2 FFT across the wave (per lane and stage one complex add
+    # or subtract-and-twiddle, 5 FLOP on average), plus the MMSE denoiser (about
+    # 20 FLOP per coordinate, a transcendental counted as one) and the residual,
+    # Onsager and noise-estimate updates (9 FLOP per measurement); other Q take
+    # the two dense complex products (8 Q n_s FLOP each)
+    if Q == 64:
+        fft = 5 * Q * 6
+        flop = S_slots * (iters * (2 * fft + 20 * Q + 9 * n_s) + fft + 20 * Q)
+    else:
+        flop = S_slots * (iters * 16 + 8) * Q * n_s
     ach = flop / (avg_ms * 1e-3) / 1e12
     res = {"metric": "AMP-MMSE slot evidence/sec (non-binary detector front end)", "value": round(value, 1),
            "unit": "slots/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -406,6 +416,7 @@ def run_batched(args, wl, P, torch):
     B = len(shapes)
     tokens = sum(K * n for K, n in shapes)
     outs = [torch.zeros(K, n, dtype=torch.uint8, device=dev) for K, n in shapes]
+    rounds = torch.zeros(len(shapes), dtype=torch.int32, device=dev)
     prec = {"bf16": P.CIDER_BF16, "fp32": P.CIDER_FP32, "fp8": P.CIDER_FP8}[args.precision]
     kind = args.precision
     ro = dict(remask=int(wl.remask), remask_thr=wl.remask_thr, remask_max_rounds=wl.remask_max_rounds)
@@ -418,7 +429,7 @@ def run_batched(args, wl, P, torch):
         ro = dict(remask=1, qhead=qbuf, qhead_hidden=args.qhead)
     opts = P.cider_opts_default(precision=prec, use_graph=1, **ro)
     blist = [{"y": ys[i], "sigma2": s2[i], "code": chs[i], "K": shapes[i][0], "n": shapes[i][1],
-              "out_symbols": outs[i]} for i in range(B)]
+              "out_symbols": outs[i], "out_rounds": rounds[i:i + 1]} for i in range(B)]
     stream = torch.cuda.Stream()
     log(f"{wl.name}: {B} bins, {tokens} tokens, L={cfg.n_layers} d={cfg.d} h={cfg.heads} T={wl.T} "
         f"remask={wl.remask} {kind}, warmup {args.warmup}, steps {args.steps}")
@@ -441,6 +452,7 @@ def run_batched(args, wl, P, torch):
     total = t1 - t0
     value = B * args.steps / total
     gpu_X = [o.cpu().numpy() for o in outs]
+    rounds_hist = {int(k): int(v) for k, v in zip(*np.unique(rounds.cpu().numpy(), return_counts=True))}
     log(f"{value:.1f} bins/s")
 
     # plain FP32 per-bin path on a subset of the same bins (the comparison baseline)
@@ -486,6 +498,9 @@ def run_batched(args, wl, P, torch):
         "fp32_plain": ({"value": round(plain_value, 3), "unit": "bins/s", "bins": nplain,
                         "path": "cider_decode per bin, FP32, eager launches"} if plain_value else None),
         "speedup_vs_fp32_plain": round(value / plain_value, 2) if plain_value else None,
+        "latency_scope": "per bin: every bin of a batch is submitted with it and completes with it, so a bin's "
+                         "latency is its batch's decode time (HIP events on the decode stream)",
+        "remask_rounds": rounds_hist if wl.remask or args.qhead else None,
         "roofline": roof, "kernels": kernel_table, "tuning": tuning,
     }
     if args.qhead:
@@ -515,6 +530,84 @@ def run_batched(args, wl, P, torch):
                                      + (", remasking on" if wl.remask else ""),
                          "bins_per_batch": B, "K": wl.K, "n": wl.n, "T": wl.T, "remask": wl.remask}
     return res, gpu_X, plain_X
+
+
+def _c2_weights(P, wl):
+    import synth
+    cfg = wl.model
+    blob = synth.make_weights(cfg, wl.weight_seed)
+    return cfg, P.Weights(P.make_cfg(cfg.n_layers, cfg.d, cfg.heads, cfg.mlp_mult, cfg.n_max), blob)
+
+
+def clopper_pearson(k, n, alpha=0.05):
+    """Exact two-sided (1 - alpha) interval of a binomial proportion k / n."""
+    from scipy.stats import beta
+    lo = 0.0 if k == 0 else float(beta.ppf(alpha / 2, k, n - k + 1))
+    hi = 1.0 if k == n else float(beta.ppf(1 - alpha / 2, k + 1, n - k))
+    return lo, hi
+
+
+def stored_grid_agreement(P, torch, wh, wl):
+    """Bit-exact agreement of whole c2 decodes with the FP64 oracle's grids
+    stored in tests/golden/c2_oracle_grids.npz (3072 bins, written by a script
+    that calls only the oracle): BF16 in the timed configuration (256 bins per
+    call, graph replay) and the plain FP32 path (one call per bin, eager)."""
+    import synth
+    path = os.path.join(ROOT, "tests", "golden", "c2_oracle_grids.npz")
+    if wl.name != "c2" or not os.path.exists(path):
+        return None
+    g = np.load(path)
+    shape = tuple(int(v) for v in g["shape"])
+    X = np.unpackbits(g["X_packed"], axis=-1, count=shape[-1]).reshape(shape)
+    B, K, n = shape
+    code = synth.regular_ldpc(wl.n, seed=wl.code_seed)
+    bins = synth.make_bins(code, wl.K, B, wl.ebn0_db, wl.bin_seed)
+    if float(np.sum(bins.y, dtype=np.float64)) != float(g["y_sum"][0]):
+        log("stored grids do not match the generated inputs; agreement not measured")
+        return None
+    ch = P.Code(code.n, code.m, code.row_ptr, code.col_idx)
+    y = torch.from_numpy(bins.y).cuda()
+    runs = {}
+    out = torch.full((B, K, n), 9, dtype=torch.uint8, device="cuda")
+    o = P.cider_opts_default(precision=P.CIDER_BF16, use_graph=1)
+    for b0 in range(0, B, 256):
+        P.cider_decode_batch([{"y": y[b], "sigma2": float(bins.sigma2[b]), "code": ch, "K": K, "n": n,
+                               "out_symbols": out[b]} for b in range(b0, min(B, b0 + 256))], wh, wl.T, o)
+    torch.cuda.synchronize()
+    runs["bf16_batched"] = out.cpu().numpy()
+    log(f"stored-grid agreement: {B} bins BF16 batched done; FP32 plain, one call per bin")
+    out.fill_(9)
+    o = P.cider_opts_default(precision=P.CIDER_FP32, use_graph=0)
+    for b in range(B):
+        P.cider_decode(y[b], float(bins.sigma2[b]), ch, K, n, wh, wl.T, out[b], o)
+        if b % 1024 == 1023:
+            torch.cuda.synchronize()
+            log(f"  fp32 plain {b + 1}/{B}")
+    torch.cuda.synchronize()
+    runs["fp32_plain"] = out.cpu().numpy()
+    res = {"bins": B, "source": "tests/golden/c2_oracle_grids.npz (FP64 oracle, exact grid equality)"}
+    for name, got in runs.items():
+        same = np.array([np.array_equal(got[b], X[b]) for b in range(B)])
+        lo, hi = clopper_pearson(int(same.sum()), B)
+        res[name] = {"bin_match": round(float(same.mean()), 5), "ci95": [round(lo, 5), round(hi, 5)],
+                     "symbol_match": round(float(np.mean(got == X)), 5)}
+    mg = g["min_gap"]
+    res["oracle_min_decision_gap"] = {f"q{q:g}": float(np.quantile(mg, q / 100)) for q in (0.1, 1, 10, 50)}
+    return res
+
+
+def c3_subrecord(args, P, torch):
+    """c3 (K=8, n=256, d=256, L=6, T=32, remasking on, 512 bins) timed in the
+    same run: bins/s, the dominant kernel against the MFMA peak, rounds."""
+    import copy
+    import synth
+    a = copy.copy(args)
+    a.workload, a.steps, a.warmup, a.bins, a.plain_bins, a.qhead = "c3", 2, 1, 0, 0, 0
+    r3, _, _ = run_batched(a, synth.workload("c3"), P, torch)
+    top = dict(list(r3["kernels"].items())[:4])
+    return {"value": r3["value"], "unit": "bins/s", "steps": a.steps, "ms_per_step": r3["ms_per_step"],
+            "symbols_per_s": r3["symbols_per_s"], "remask_rounds": r3["remask_rounds"], "roofline": r3["roofline"],
+            "kernels": top, "workload": r3["config"]["workload"]}
 
 
 def run_served(args, wl, P, torch):
@@ -599,6 +692,25 @@ def run_served(args, wl, P, torch):
         loads.append(dict(run(f * capacity, args.duration), load=f))
     main = loads[-1] if loads else cap
     toks = float(np.mean([b.K * b.n for b in pool]))
+    # the dominant kernel of the served model: one profiled packed decode of the
+    # first 32 bins of the pool (HIP events around every launch)
+    sample = pool[:32]
+    so = P.cider_opts_default(precision=P.CIDER_BF16, profile=1, remask=int(wl.remask), remask_thr=wl.remask_thr,
+                              remask_max_rounds=wl.remask_max_rounds)
+    souts = [torch.zeros(b.K, b.n, dtype=torch.uint8, device="cuda") for b in sample]
+    sy = [torch.from_numpy(np.ascontiguousarray(b.y)).cuda() for b in sample]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        P.cider_profile_read(wh, reset=True)
+        P.cider_decode_batch([{"y": sy[i], "sigma2": b.sigma2, "code": handles[b.n], "K": b.K, "n": b.n,
+                               "out_symbols": souts[i]} for i, b in enumerate(sample)], wh, wl.T, so, stream=stream)
+        stream.synchronize()
+    prof = P.cider_profile_read(wh, reset=True)
+    stoks = sum(b.K * b.n for b in sample)
+    roof = roofline(prof, cfg, stoks / sum(b.K for b in sample), stoks / sum(b.n for b in sample), stoks, "bf16",
+                    wl.name)
+    if roof:
+        roof["sample"] = f"one packed decode of the first {len(sample)} bins of the served pool ({stoks} tokens)"
     return {
         "metric": METRIC, "value": main["throughput"], "unit": "bins/s", "n_gpus": 1, "steps": len(loads),
         "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -609,7 +721,8 @@ def run_served(args, wl, P, torch):
                                f"d={cfg.d} h={cfg.heads}, T={wl.T}, remasking on; offered load as a fraction of "
                                f"the measured capacity (the workload's 20k bins/s is far beyond one GPU)",
                    "max_slots": args.max_slots, "max_tokens": args.max_tokens},
-        "capacity_probe": cap, "loads": loads, "roofline": None, "cpu_baseline": None,
+        "capacity_probe": cap, "loads": loads, "roofline": roof, "cpu_baseline": None,
+        "latency_scope": "per bin: completion minus submission of each admitted request",
     }
 
 
@@ -624,6 +737,7 @@ def main():
     ap.add_argument("--cpu-bins", type=int, default=16)
     ap.add_argument("--plain-bins", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="c2: skip the stored-grid agreement and the c3 record")
     ap.add_argument("--qhead", type=int, default=0, help="quality head with this many hidden units as the remask criterion")
     ap.add_argument("--calib-copy", action="store_true", help="end with a 256 MiB device copy (counter calibration)")
     ap.add_argument("--load", default="0.5,0.9")
@@ -651,7 +765,7 @@ def main():
 
     # CPU baseline first, before the GPU is initialised (spawned workers)
     cpu, oracle_out = None, {}
-    if not args.no_cpu and not served:
+    if not args.no_cpu:
         workers = max(1, min(args.cpu_bins, os.cpu_count() or 1, 16))
         if wl.ragged_K is None and wl.name in ("c1", "c2"):
             log(f"oracle cpu baseline: {args.cpu_bins} bins on {workers} workers")
@@ -664,7 +778,7 @@ def main():
                              f"{sum(r[2] for r in out):.1f} s CPU"}
         else:
             K = wl.K if wl.ragged_K is None else int(np.median(wl.ragged_K))
-            n = wl.n if wl.ragged_K is None else int(np.median(wl.ragged_n))
+            n = wl.n if wl.ragged_K is None else int(wl.ragged_n[len(wl.ragged_n) // 2])
             code_seed = wl.code_seed if wl.ragged_K is None else 1000 + n
             log(f"oracle cpu baseline: one denoiser forward of a K={K} n={n} bin on {workers} workers")
             out, wall = _pool(_oracle_step_worker, [(K, n, wl.model, wl.weight_seed, code_seed)] * workers, workers)
@@ -680,6 +794,7 @@ def main():
     torch.cuda.set_device(0)
     if served:
         res = run_served(args, wl, P, torch)
+        res["cpu_baseline"] = cpu
     else:
         res, gpu_X, plain_X = run_batched(args, wl, P, torch)
         res["cpu_baseline"] = cpu
@@ -691,6 +806,10 @@ def main():
             pbm = sum(np.array_equal(plain_X[b], oracle_out[b]) for b in pb)
             res["oracle_match"] = {"bins": len(ob), "bin_match": round(bm / len(ob), 4), "symbol_match": round(sm, 5),
                                    "fp32_plain_bin_match": round(pbm / len(pb), 4) if pb else None}
+        if wl.name == "c2" and not args.bins and not args.no_extra:
+            _, wh2 = _c2_weights(P, wl)
+            res["stored_grid_agreement"] = stored_grid_agreement(P, torch, wh2, wl)
+            res["c3"] = c3_subrecord(args, P, torch)
     if args.calib_copy:
         x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
         yb = torch.empty_like(x)

@@ -157,6 +157,7 @@ typedef struct {
   float*            out_logits;    /* device [K][n][2] FP32 logits of the last   */
                                    /* final pass, or NULL                        */
   uint8_t*          out_row_valid; /* device [K]: 1 iff H x_k = 0, or NULL       */
+  int32_t*          out_rounds;    /* device [1]: remask rounds run, or NULL     */
 } cider_bin;
 
 /* Fills `opts` with the defaults listed above. */

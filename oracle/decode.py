@@ -141,7 +141,7 @@ def decode_grid(K: int, n: int, code, den: Callable, T: int, opts: DecodeOpts,
     if opts.final_argmax:
         Xout = np.where(fin[..., 0] >= fin[..., 1], 0, 1).astype(np.uint8)
     valid = (~syndrome(Xout, code).any(axis=1)).astype(np.uint8)
-    gaps = [min(s["gaps"].values()) for s in steps] + [f["gap_q"] for f in finals]
+    gaps = [min(s["gaps"][k] for k in ("cut", "sel", "slot")) for s in steps] + [f["gap_q"] for f in finals]
     return DecodeResult(X=Xout, final_logits=fin, row_valid=valid, rounds=rounds, steps=steps,
                         finals=finals, min_gap=float(min(gaps)) if gaps else float("inf"))
 

@@ -79,18 +79,54 @@ def margins(logits: np.ndarray) -> np.ndarray:
     return np.abs(logits[..., 0] - logits[..., 1])
 
 
+def _boundary_gap(vals, scales, i):
+    """Distance from a tie of the decision between positions i (kept) and
+    i + 1 (dropped) of the descending values `vals`: their difference; or,
+    when they are equal -- identical user rows, whose logits are
+    bit-identical in any precision and whose order the index tie-break fixes
+    -- the distance from the tied value to the nearest distinct value on
+    either side, since only a value crossing the tied group changes the
+    outcome.  Returns (gap, relative gap, tied); the relative gap divides by 4
+    max(1, |logits|) of the two sites compared (inf when nothing competes)."""
+    inf = float("inf")
+    v, w = vals[i], vals[i + 1]
+    if v > w:
+        return float(v - w), float(v - w) / (4.0 * max(scales[i], scales[i + 1])), False
+    gap, rel = inf, inf
+    up = np.nonzero(vals[:i] > v)[0]
+    if up.size:
+        j = up[-1]
+        gap = float(vals[j] - v)
+        rel = gap / (4.0 * max(scales[j], scales[i]))
+    down = np.nonzero(vals[i + 1:] < v)[0]
+    if down.size:
+        j = i + 1 + down[0]
+        g = float(v - vals[j])
+        if g < gap:
+            gap = g
+        rel = min(rel, g / (4.0 * max(scales[j], scales[i])))
+    return gap, rel, True
+
+
 def reveal(X: np.ndarray, logits: np.ndarray, r: int, first_reveal: bool) -> Dict:
     """Reveal up to r masked sites of X [K][n] in place; returns selection info.
 
-    'gaps' reports how far each integer decision in this step sits from a tie:
-    cut (r-th minus (r+1)-th candidate margin), sel (smallest selected margin,
-    i.e. the argmax decision) and slot (first-reveal best-minus-second row).
+    'gaps' reports how far each integer decision in this step sits from a
+    tie: cut (between the r-th and the (r+1)-th candidate), sel (smallest
+    selected margin, i.e. the argmax decision) and slot (first-reveal choice
+    of a slot's row), each through _boundary_gap, which looks past ties
+    between identical rows ('ties' counts them).  The r-prefixed entries put
+    each gap against the logits it is made of: a margin difference of two
+    sites over 4 max(1, |logits of both sites|), an argmax margin over
+    2 max(1, |its two logits|) -- the gap a relative logit error of that
+    size, max |dL| / max(1, |L|), can close at most.
     """
     K, n = X.shape
     c = margins(logits)
+    scale = np.maximum(1.0, np.abs(logits).max(axis=-1))
     masked = X == MASK
     inf = float("inf")
-    gaps = {"cut": inf, "sel": inf, "slot": inf}
+    gaps = {"cut": inf, "sel": inf, "slot": inf, "rcut": inf, "rsel": inf, "rslot": inf, "ties": 0}
     if first_reveal:
         cm = np.where(masked, c, -np.inf)
         cand = []
@@ -99,9 +135,13 @@ def reveal(X: np.ndarray, logits: np.ndarray, r: int, first_reveal: bool) -> Dic
                 continue
             k = int(np.argmax(cm[:, l]))           # first maximum -> smallest k
             cand.append((k, l))
-            col = np.sort(cm[:, l][masked[:, l]])[::-1]
-            if col.size > 1:
-                gaps["slot"] = min(gaps["slot"], float(col[0] - col[1]))
+            ks = np.nonzero(masked[:, l])[0]
+            if ks.size > 1:
+                o = ks[np.argsort(-cm[ks, l], kind="stable")]
+                g, rg, tied = _boundary_gap(cm[o, l], scale[o, l], 0)
+                gaps["slot"] = min(gaps["slot"], g)
+                gaps["rslot"] = min(gaps["rslot"], rg)
+                gaps["ties"] += int(tied)
     else:
         ks, ls = np.nonzero(masked)
         cand = list(zip(ks.tolist(), ls.tolist()))
@@ -112,9 +152,13 @@ def reveal(X: np.ndarray, logits: np.ndarray, r: int, first_reveal: bool) -> Dic
     order = np.lexsort((flat, -cvals))             # by margin desc, then flat index asc
     take = order[:min(r, len(cand))]
     if len(cand) > r:
-        gaps["cut"] = float(cvals[order[r - 1]] - cvals[order[r]])
+        sc = np.array([scale[cand[i]] for i in order])
+        g, rg, tied = _boundary_gap(cvals[order], sc, r - 1)
+        gaps["cut"], gaps["rcut"] = g, rg
+        gaps["ties"] += int(tied)
     sel = [cand[i] for i in take]
     gaps["sel"] = float(min(cvals[i] for i in take))
+    gaps["rsel"] = float(min(cvals[i] / (2.0 * scale[cand[i]]) for i in take))
     for k, l in sel:
         X[k, l] = 0 if logits[k, l, 0] >= logits[k, l, 1] else 1
     return {"selected": sel, "gaps": gaps}

@@ -57,7 +57,7 @@ class cider_opts(C.Structure):
 class cider_bin(C.Structure):
     _fields_ = [("y", C.c_void_p), ("sigma2", C.c_float), ("code", C.c_void_p), ("K", C.c_int32),
                 ("n", C.c_int32), ("out_symbols", C.c_void_p), ("out_logits", C.c_void_p),
-                ("out_row_valid", C.c_void_p)]
+                ("out_row_valid", C.c_void_p), ("out_rounds", C.c_void_p)]
 
 
 class cider_kernel_stat(C.Structure):
@@ -256,11 +256,13 @@ def cider_decode(y, sigma2: float, code: Code, K: int, n: int, w: Weights, steps
 
 def cider_decode_batch(bins: Sequence[dict], w: Weights, steps: int, opts: Optional[cider_opts] = None,
                        stream=None) -> None:
-    """bins: dicts with y, sigma2, code, K, n, out_symbols and optional out_logits, out_row_valid."""
+    """bins: dicts with y, sigma2, code, K, n, out_symbols and optional out_logits, out_row_valid,
+    out_rounds."""
     arr = (cider_bin * len(bins))()
     for i, b in enumerate(bins):
         arr[i] = cider_bin(_ptr(b["y"]), float(b["sigma2"]), b["code"].handle, int(b["K"]), int(b["n"]),
-                           _ptr(b["out_symbols"]), _ptr(b.get("out_logits")), _ptr(b.get("out_row_valid")))
+                           _ptr(b["out_symbols"]), _ptr(b.get("out_logits")), _ptr(b.get("out_row_valid")),
+                           _ptr(b.get("out_rounds")))
     check(lib().cider_decode_batch(len(bins), arr, w.handle, steps, C.byref(opts) if opts is not None else None,
                                    _stream(stream)), "cider_decode_batch")
 

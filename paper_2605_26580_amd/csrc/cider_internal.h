@@ -58,6 +58,7 @@ struct DevBin {
   uint8_t* out_sym;     // [K][n]
   float* out_logits;    // [K][n][2] or null
   uint8_t* out_valid;   // [K] or null
+  int32_t* out_rounds;  // [1] remask rounds run, or null
   BinState* st;
 };
 

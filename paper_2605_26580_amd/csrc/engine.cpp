@@ -721,6 +721,7 @@ struct BinIn {
   uint8_t* out_sym;
   float* out_logits;
   uint8_t* out_valid;
+  int32_t* out_rounds = nullptr;
   uint8_t* X = nullptr;     // persistent grid (serving); null: workspace
   BinState* st = nullptr;   // persistent state (serving); null: workspace
 };
@@ -890,7 +891,7 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
     db.sched = sched;
     db.y = b.y; db.sigma2 = b.sigma2;
     db.X = b.X ? b.X : (uint8_t*)(base + L.off_X) + tok;
-    db.out_sym = b.out_sym; db.out_logits = b.out_logits; db.out_valid = b.out_valid;
+    db.out_sym = b.out_sym; db.out_logits = b.out_logits; db.out_valid = b.out_valid; db.out_rounds = b.out_rounds;
     db.st = b.st ? b.st : (BinState*)(base + L.off_state) + i;
     hb[i] = db;
     for (int l = 0; l < b.n; ++l) hslot[so + l] = i;
@@ -1243,7 +1244,7 @@ int cider_decode_batch(int32_t num_bins, const cider_bin* bins, const cider_weig
   v.reserve(num_bins);
   for (int i = 0; i < num_bins; ++i)
     v.push_back(BinIn{bins[i].y, bins[i].sigma2, bins[i].code, bins[i].K, bins[i].n, bins[i].out_symbols,
-                      bins[i].out_logits, bins[i].out_row_valid});
+                      bins[i].out_logits, bins[i].out_row_valid, bins[i].out_rounds});
   return decode_impl(const_cast<cider_weights*>(w), v, steps, o, (hipStream_t)stream);
 }
 

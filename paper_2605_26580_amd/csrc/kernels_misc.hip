@@ -582,6 +582,7 @@ __global__ __launch_bounds__(kTailThreads) void k_step_tail(StepCtx c, const flo
     st.valid_rows = valid;
     st.phase = kDone;
     *b.st = st;
+    if (b.out_rounds) *b.out_rounds = st.round;
   }
 }
 

@@ -11,7 +11,12 @@ reveal cut (r-th minus (r+1)-th candidate margin), the argmax of each
 revealed site (its margin) and the first-reveal row choice (best minus
 second margin of a slot).  An exact zero is a structural tie -- identical
 user rows, which carry bit-identical logits in any precision -- and is
-counted apart from the nonzero gaps.
+counted apart (zero_ties); the gap of such a decision is measured past the
+tied group, to the nearest distinct value.  min_rel_gap puts each nonzero gap against
+the logits it is made of (a margin difference of two sites over 4 max(1, |L|)
+of both sites, an argmax margin over 2 max(1, |L|) of its site): a GPU decode
+whose logits are within that relative error, max |dL| / max(1, |L|), of the
+oracle's takes every decision the same way.
 
     python tests/golden/make_c2_oracle_grids.py [--bins 3072] [--workers 8]
 """
@@ -51,9 +56,10 @@ def _one(b: int):
                    wl.T, DecodeOpts())
     g = {key: [s["gaps"][key] for s in r.steps] for key in ("cut", "sel", "slot")}
     nz = [v for vals in g.values() for v in vals if 0.0 < v < np.inf]
-    ties = sum(1 for vals in g.values() for v in vals if v == 0.0)
+    ties = sum(s["gaps"]["ties"] for s in r.steps)
     mins = [min([v for v in g[key] if v > 0.0], default=np.inf) for key in ("cut", "sel", "slot")]
-    return r.X, min(nz, default=np.inf), mins, ties
+    rel = min(s["gaps"][key] for s in r.steps for key in ("rcut", "rsel", "rslot"))
+    return r.X, min(nz, default=np.inf), mins, ties, rel
 
 
 def main() -> None:
@@ -72,6 +78,7 @@ def main() -> None:
         min_gap=np.array([r[1] for r in res]), min_cut=np.array([r[2][0] for r in res]),
         min_sel=np.array([r[2][1] for r in res]), min_slot=np.array([r[2][2] for r in res]),
         zero_ties=np.array([r[3] for r in res], dtype=np.int32),
+        min_rel_gap=np.array([r[4] for r in res]),
         y_sum=np.array([float(np.sum(_ctx["bins"].y, dtype=np.float64))]))
     print(f"wrote {OUT}: {a.bins} bins in {time.time() - t0:.0f} s on {a.workers} workers")
 

@@ -176,7 +176,7 @@ def _free_running(prec, K, n, L, d, h, T, B, remask=False, schedule="linear", fi
 def _gaps(res):
     out = []
     for s in res.steps:
-        out += [g for g in s["gaps"].values()]
+        out += [s["gaps"][k] for k in ("cut", "sel", "slot")]
     out += [f["gap_q"] for f in res.finals]
     return out
 

@@ -58,7 +58,7 @@ def _head(d, H, std, b2):
 def _gaps(res):
     out = []
     for s in res.steps:
-        out += list(s["gaps"].values())
+        out += [s["gaps"][k] for k in ("cut", "sel", "slot")]
     out += [f["gap_q"] for f in res.finals]
     return out
 

@@ -298,3 +298,31 @@ def test_remask_confidence_at_tau_min():
         _, q, _ = row_status(X, fin, code, 0.9, tau)
         want = 0.5 * (1 / (1 + math.exp(-2.0 / tau)) + 0.5)
         assert abs(q[0] - want) < 1e-15
+
+
+def test_relative_gaps_put_each_decision_against_its_logits():
+    """Three masked sites with margins 3, 2.5 and 0.5 (logits up to 10):
+    revealing one leaves the cut 3 - 2.5 = 0.5 between sites of largest
+    |L| 10 and 4, so rcut = 0.5 / (4 * 10); the revealed site's argmax
+    margin 3 over its logits (10, 7) gives rsel = 3 / (2 * 10)."""
+    from oracle.schedule import reveal
+    X = np.full((1, 3), 2, dtype=np.uint8)
+    logits = np.array([[[10.0, 7.0], [1.5, 4.0], [0.25, -0.25]]])
+    info = reveal(X, logits, 1, False)
+    assert info["selected"] == [(0, 0)] and X[0, 0] == 0
+    assert info["gaps"]["cut"] == pytest.approx(0.5) and info["gaps"]["rcut"] == pytest.approx(0.5 / 40.0)
+    assert info["gaps"]["sel"] == pytest.approx(3.0) and info["gaps"]["rsel"] == pytest.approx(3.0 / 20.0)
+
+
+def test_a_tie_between_identical_rows_measures_the_gap_past_it():
+    """Rows 1 and 2 identical (margin 2 at slot 0), row 0 margin 2.3, row 3
+    margin 1.9: revealing two sites takes row 0 and, by index, row 1; the
+    decision turns only if row 3 crosses the tied pair (gap 0.1) or the
+    tied pair crosses row 0 (gap 0.3), so cut = 0.1 and one tie is counted."""
+    from oracle.schedule import reveal
+    X = np.full((4, 1), 2, dtype=np.uint8)
+    logits = np.array([[[2.3, 0.0]], [[2.0, 0.0]], [[2.0, 0.0]], [[1.9, 0.0]]])
+    info = reveal(X, logits, 2, False)
+    assert info["selected"] == [(0, 0), (1, 0)]
+    assert info["gaps"]["cut"] == pytest.approx(0.1) and info["gaps"]["ties"] == 1
+    assert info["gaps"]["rcut"] == pytest.approx(0.1 / (4 * 2.0))
