@@ -18,11 +18,12 @@ Modules
     quality   -- the PRISM-style quality head and its row confidences
     protocol  -- stochastic binning: bin loads, overflow, frame-level errors
     gf        -- GF(2^m) arithmetic, Pi_alpha and the non-binary check message
+    qary      -- the decode over a Q-ary LDPC code (Q-symbol Modules A and B, reveal)
 
 Parity status: every function is pinned by tests under tests/ (closed forms,
 brute force, library special cases, invariants) except the end-to-end
 decode on random weights, whose free-running output has no value in the
 paper to match; there the HIP library is compared with this oracle.
 """
-from . import evidence, denoiser, parity, schedule, decode, metrics, brute, amp, quality, protocol, gf  # noqa: F401
+from . import evidence, denoiser, parity, schedule, decode, metrics, brute, amp, quality, protocol, gf, qary  # noqa: F401
 from .decode import DecodeOpts, decode_bin  # noqa: F401

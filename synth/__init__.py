@@ -15,6 +15,7 @@ from .weights import ModelCfg, weight_layout, make_weights, unpack_weights, make
 from .configs import WORKLOADS, Workload, workload
 from .amp import AmpSlots, make_amp_slots, p_sym_of
 from .binning import ProtocolFrame, make_protocol_frames
+from .qary import QaryCode, QaryFrames, qary_ldpc, make_qary_frames
 
 __all__ = [
     "LdpcCode", "regular_ldpc", "nullspace_gf2", "rank_gf2",
@@ -23,4 +24,5 @@ __all__ = [
     "WORKLOADS", "Workload", "workload",
     "AmpSlots", "make_amp_slots", "p_sym_of",
     "ProtocolFrame", "make_protocol_frames",
+    "QaryCode", "QaryFrames", "qary_ldpc", "make_qary_frames",
 ]

@@ -12,7 +12,7 @@ Data only: the channel is synthesised here, the detector is not.
 from __future__ import annotations
 
 from dataclasses import dataclass
-from typing import Sequence
+from typing import Optional, Sequence
 
 import numpy as np
 
@@ -33,13 +33,14 @@ def p_sym_of(ebn0_db: float, payload_bits: int, L: int) -> float:
 
 def make_amp_slots(frames: int, L: int, Q: int, n_s: int, K: int, payload_bits: int,
                    ebn0_db: Sequence[float] | float, seed: int, sigma2: float = 1.0,
-                   shared_rows: bool = False) -> AmpSlots:
+                   shared_rows: bool = False, idx: Optional[np.ndarray] = None) -> AmpSlots:
     """``frames`` frames of L slots each (S = frames * L slots, frame-major).
 
     Every frame draws its K users' signature indices independently and
     uniformly per slot, and its Eb/N0 from ``ebn0_db`` in turn.  The DFT rows
     of each slot are n_s distinct indices drawn uniformly (one set for all
-    slots when ``shared_rows``)."""
+    slots when ``shared_rows``).  ``idx`` [S][K], if given, fixes the users'
+    symbols instead (codeword symbols of a coded frame)."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
     levels = np.atleast_1d(np.asarray(ebn0_db, dtype=np.float64))
     S = frames * L
@@ -48,7 +49,9 @@ def make_amp_slots(frames: int, L: int, Q: int, n_s: int, K: int, payload_bits: 
         rows = np.repeat(np.sort(np.argsort(rng.random(Q))[:n_s])[None, :], S, axis=0).astype(np.int32)
     else:
         rows = np.sort(np.argsort(rng.random((S, Q)), axis=1)[:, :n_s], axis=1).astype(np.int32)
-    idx = rng.integers(0, Q, size=(S, K))
+    if idx is None:
+        idx = rng.integers(0, Q, size=(S, K))
+    idx = np.asarray(idx, dtype=np.int64)
     counts = np.zeros((S, Q), dtype=np.int32)
     for k in range(K):
         np.add.at(counts, (np.arange(S), idx[:, k]), 1)
