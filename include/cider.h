@@ -222,6 +222,29 @@ int cider_decode(const float* y, float sigma2, const cider_code* code, int32_t K
                  const cider_weights* w, int32_t steps, uint8_t* out_symbols,
                  const cider_opts* opts, void* stream);
 
+/* Allocation-free variant of cider_decode, for callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, rules and result as cider_decode (bit-identical
+ * symbols), but the call allocates nothing, on the device or on the host:
+ * its workspace, per-bin metadata and reveal-schedule table live in a
+ * library-owned device array of CIDER_NOALLOC_SCRATCH_BYTES per GPU, held
+ * from the first call on that GPU until the process ends.  Launches are
+ * eager (opts->use_graph is ignored: a graph would allocate) and no tile is
+ * autotuned (a tile tuned earlier on the weights handle, or forced with
+ * autotune >= 2, is used).  Every call on a GPU shares that GPU's array, which
+ * keeps the last call's contents: calls that overlap on one GPU (any stream,
+ * any thread) race and must be serialised by the caller.
+ * CIDER_EINVAL, before anything is enqueued, when the bin's workspace exceeds
+ * the array (roughly K*n*d*(30 + 6*mlp_mult) bytes at BF16 must fit in
+ * 64 MiB: every bin of K*n <= 4096 tokens at d = 256), when
+ * opts->workspace is set, or when opts->profile = 1 (timing events allocate);
+ * otherwise as cider_decode.  With remasking on, the call synchronises
+ * `stream` once per remask round, as cider_decode does. */
+#define CIDER_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int cider_decode_noalloc(const float* y, float sigma2, const cider_code* code, int32_t K, int32_t n,
+                         const cider_weights* w, int32_t steps, uint8_t* out_symbols,
+                         const cider_opts* opts, void* stream);
+
 /* Decodes `num_bins` independent bins of possibly different K, n and code in
  * one packed pass per step.  Bins share no state: each preamble bin of the
  * random-access protocol is decoded on its own (Appendix, protocol-level

@@ -24,7 +24,7 @@ CIDER_MASK = 2
 EXPORTS = [
     "cider_opts_default", "cider_weights_blob_floats", "cider_weights_create", "cider_weights_destroy",
     "cider_code_create", "cider_code_destroy", "cider_workspace_size", "cider_decode",
-    "cider_decode_batch", "cider_step_debug", "cider_evidence", "cider_amp_evidence", "cider_gf64_check_update", "cider_server_create",
+    "cider_decode_batch", "cider_decode_noalloc", "cider_step_debug", "cider_evidence", "cider_amp_evidence", "cider_gf64_check_update", "cider_server_create",
     "cider_server_submit", "cider_server_poll", "cider_server_drain", "cider_server_destroy",
     "cider_strerror", "cider_last_error", "cider_profile_read", "cider_tuning_read",
 ]
@@ -110,6 +110,7 @@ def lib() -> C.CDLL:
     L.cider_workspace_size.argtypes = [vp, i32, C.c_int64, C.c_int64, C.POINTER(cider_opts),
                                        C.POINTER(C.c_size_t)]
     L.cider_decode.argtypes = [vp, f32, vp, i32, i32, vp, i32, vp, C.POINTER(cider_opts), vp]
+    L.cider_decode_noalloc.argtypes = [vp, f32, vp, i32, i32, vp, i32, vp, C.POINTER(cider_opts), vp]
     L.cider_decode_batch.argtypes = [i32, C.POINTER(cider_bin), vp, i32, C.POINTER(cider_opts), vp]
     L.cider_step_debug.argtypes = [vp, vp, vp, f32, vp, i32, i32, vp, f32, i32, i32,
                                    C.POINTER(cider_opts), vp, vp, vp, vp]
@@ -129,7 +130,7 @@ def lib() -> C.CDLL:
     L.cider_last_error.argtypes = []
     L.cider_last_error.restype = C.c_char_p
     for name in ("cider_weights_create", "cider_code_create", "cider_workspace_size", "cider_decode",
-                 "cider_decode_batch", "cider_step_debug", "cider_evidence", "cider_amp_evidence", "cider_gf64_check_update",
+                 "cider_decode_batch", "cider_decode_noalloc", "cider_step_debug", "cider_evidence", "cider_amp_evidence", "cider_gf64_check_update",
                  "cider_server_create", "cider_server_submit", "cider_server_poll", "cider_server_drain",
                  "cider_profile_read", "cider_tuning_read"):
         getattr(L, name).restype = C.c_int
@@ -252,6 +253,13 @@ def cider_decode(y, sigma2: float, code: Code, K: int, n: int, w: Weights, steps
                  opts: Optional[cider_opts] = None, stream=None) -> None:
     check(lib().cider_decode(_ptr(y), float(sigma2), code.handle, K, n, w.handle, steps, _ptr(out_symbols),
                              C.byref(opts) if opts is not None else None, _stream(stream)), "cider_decode")
+
+
+def cider_decode_noalloc(y, sigma2: float, code: Code, K: int, n: int, w: Weights, steps: int, out_symbols,
+                         opts: Optional[cider_opts] = None, stream=None) -> None:
+    check(lib().cider_decode_noalloc(_ptr(y), float(sigma2), code.handle, K, n, w.handle, steps,
+                                     _ptr(out_symbols), C.byref(opts) if opts is not None else None,
+                                     _stream(stream)), "cider_decode_noalloc")
 
 
 def cider_decode_batch(bins: Sequence[dict], w: Weights, steps: int, opts: Optional[cider_opts] = None,

@@ -978,6 +978,180 @@ int decode_impl(cider_weights* w, const std::vector<BinIn>& bins, int steps, con
   return CIDER_OK;
 }
 
+// ---- decoding without allocation ----------------------------------------
+// For callers that cannot allocate (HIP graph capture, tight serving loops):
+// a single-bin decode whose workspace, per-bin metadata and reveal-schedule
+// table live in the file-scope device array `scratch` (one copy per GPU, held
+// until the process ends) instead of memory the library allocates.  Metadata
+// reaches the device through kernel arguments, never through host staging
+// buffers, so nothing on the host is allocated either.  Every call on a GPU
+// shares that GPU's array: calls that overlap on one GPU race.
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_at[kMaxDevices] = {};
+
+struct SingleBinMeta {
+  DevBin db;
+  int K, n, ngrp, cols, ngrp32, cols32, ntile;
+};
+
+// Writes the packed-batch maps of a batch that holds one bin: every slot,
+// row and tile belongs to bin 0; user groups start every `cols` columns.
+__global__ void k_single_bin_meta(SingleBinMeta a, DevBin* bins, int* slot, int* row, int* grp, int* tile,
+                                  int* grp32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) bins[0] = a.db;
+  if (i < a.n) slot[i] = 0;
+  if (i < a.K) row[i] = 0;
+  if (i < a.ngrp) {
+    grp[2 * i] = 0;
+    grp[2 * i + 1] = i * a.cols;
+  }
+  if (i < a.ntile) tile[i] = 0;
+  if (i < a.ngrp32) {
+    grp32[2 * i] = 0;
+    grp32[2 * i + 1] = i * a.cols32;
+  }
+}
+
+constexpr int kChunkInts = 240;
+struct IntChunk {
+  int v[kChunkInts];
+  int count;
+};
+
+__global__ void k_put_ints(IntChunk c, int* dst) {
+  const int i = threadIdx.x;
+  if (i < c.count) dst[i] = c.v[i];
+}
+
+// Streams ints to device memory in kernel-argument chunks.
+struct ChunkWriter {
+  IntChunk c{};
+  int* dst;
+  hipStream_t s;
+  hipError_t err = hipSuccess;
+  long written = 0;
+  void put(int v) {
+    c.v[c.count++] = v;
+    if (c.count == kChunkInts) flush();
+  }
+  void flush() {
+    if (c.count && err == hipSuccess) {
+      hipLaunchKernelGGL(k_put_ints, dim3(1), dim3(256), 0, s, c, dst + written);
+      err = hipGetLastError();
+    }
+    written += c.count;
+    c.count = 0;
+  }
+};
+
+}  // namespace
+
+// The scratch array.  In host code its name stands for the host-side shadow,
+// not a device address: kernels get the address looked up per device below.
+static __device__ __align__(256) char scratch[CIDER_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+// Device address of this device's copy of `scratch`; the device must be current.
+int scratch_base(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(CIDER_EUNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_at[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_at[dev] = (char*)p;
+  }
+  *out = g_scratch_at[dev];
+  return CIDER_OK;
+}
+
+int decode_noalloc_impl(cider_weights* w, const BinIn& b, int steps, const cider_opts& o, hipStream_t s) {
+  int rc = check_opts(o);
+  if (rc) return rc;
+  rc = check_prec(w, o);
+  if (rc) return rc;
+  rc = check_bin(w, b, steps);
+  if (rc) return rc;
+  if (o.profile) return fail(CIDER_EINVAL, "profile = 1 creates timing events: not available without allocation");
+  if (o.workspace) return fail(CIDER_EINVAL, "the allocation-free decode uses its own scratch: workspace must be NULL");
+  const long T = (long)b.K * b.n;
+  Layout L = plan_layout(w->cfg, 1, T, b.n, b.K, o.precision);
+  L.max_n = b.n;
+  const size_t sched_at = L.total;
+  const size_t need = align_up(sched_at + (size_t)schedule_ints(b.K, steps) * sizeof(int), 256);
+  if (need > CIDER_NOALLOC_SCRATCH_BYTES) {
+    char msg[160];
+    std::snprintf(msg, sizeof(msg), "bin needs %zu bytes of scratch, the allocation-free decode has %zu", need,
+                  (size_t)CIDER_NOALLOC_SCRATCH_BYTES);
+    return fail(CIDER_EINVAL, msg);
+  }
+  std::lock_guard<std::mutex> lock(w->mu);
+  HIPCHK(hipSetDevice(w->device));
+  char* base = nullptr;
+  rc = scratch_base(w->device, &base);
+  if (rc) return rc;
+  w->prof_on = false;
+
+  SingleBinMeta a{};
+  a.K = b.K;
+  a.n = b.n;
+  a.cols = ugrp_cols(b.K);
+  a.ngrp = (b.n + a.cols - 1) / a.cols;
+  a.cols32 = 32 / b.K;
+  a.ngrp32 = (b.n + a.cols32 - 1) / a.cols32;
+  a.ntile = (int)((T + 255) / 256);
+  DevBin& db = a.db;
+  db.tok_off = 0;
+  db.K = b.K; db.n = b.n; db.m = b.code->m;
+  db.slot_off = 0; db.row_off = 0;
+  db.row_ptr = b.code->d_row_ptr; db.col_idx = b.code->d_col_idx;
+  db.var_ptr = b.code->d_var_ptr; db.var_edge = b.code->d_var_edge;
+  db.sched = (const int*)(base + sched_at);
+  db.y = b.y; db.sigma2 = b.sigma2;
+  db.X = (uint8_t*)(base + L.off_X);
+  db.out_sym = b.out_sym; db.out_logits = b.out_logits; db.out_valid = b.out_valid; db.out_rounds = b.out_rounds;
+  db.st = (BinState*)(base + L.off_state);
+  const int span = std::max({a.n, a.K, a.ngrp, a.ntile, a.ngrp32, 1});
+  hipLaunchKernelGGL(k_single_bin_meta, dim3((span + 255) / 256), dim3(256), 0, s, a, (DevBin*)(base + L.off_bins),
+                     (int*)(base + L.off_slot), (int*)(base + L.off_row), (int*)(base + L.off_ugrp),
+                     (int*)(base + L.off_tile), (int*)(base + L.off_ugrp32));
+  HIPCHK(hipGetLastError());
+  ChunkWriter cw;
+  cw.dst = (int*)(base + sched_at);
+  cw.s = s;
+  schedule_emit(b.K, b.n, steps, o.schedule, [&](int v) { cw.put(v); });
+  cw.flush();
+  HIPCHK(cw.err);
+
+  Run r;
+  r.nseg = 1;
+  r.seg[0] = RowSeg{row_path(w->cfg, o.precision, o.fused_blocks != 0, b.n), 0, b.K, b.n, 0, T};
+  fill_run(&r, L, base, o, 1, T, b.n, b.K, b.n, a.ngrp, a.ngrp32);
+  HIPCHK(launch_evidence(r.ctx, r.work.S, r.work.p, s));
+  HIPCHK(launch_init_bins(r.ctx, steps, o.first_reveal, s));
+  if (o.autotune >= 2) r.forced_tile = o.autotune - 2;
+  r.use_blocks = o.fused_blocks != 0;
+  // eager launches: instantiating a graph would allocate
+  rc = run_steps(w, r, steps + 1, false, s);
+  if (rc) return rc;
+  const int rounds = o.qhead ? o.remask_stages : o.remask_max_rounds;
+  if (o.remask && rounds > 0) {
+    BinState st{};
+    for (int round = 0; round < rounds; ++round) {
+      HIPCHK(hipMemcpyAsync(&st, base + L.off_state, sizeof(BinState), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (st.phase == kDone) break;
+      rc = run_steps(w, r, steps + 1, false, s);
+      if (rc) return rc;
+    }
+  }
+  return CIDER_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1232,6 +1406,16 @@ int cider_decode(const float* y, float sigma2, const cider_code* code, int32_t K
   if (opts) o = *opts; else cider_opts_default(&o);
   std::vector<BinIn> bins{BinIn{y, sigma2, code, K, n, out_symbols, nullptr, nullptr}};
   return decode_impl(const_cast<cider_weights*>(w), bins, steps, o, (hipStream_t)stream);
+}
+
+int cider_decode_noalloc(const float* y, float sigma2, const cider_code* code, int32_t K, int32_t n,
+                         const cider_weights* w, int32_t steps, uint8_t* out_symbols, const cider_opts* opts,
+                         void* stream) {
+  if (!w) return fail(CIDER_EINVAL, "null weights");
+  cider_opts o;
+  if (opts) o = *opts; else cider_opts_default(&o);
+  const BinIn b{y, sigma2, code, K, n, out_symbols, nullptr, nullptr};
+  return decode_noalloc_impl(const_cast<cider_weights*>(w), b, steps, o, (hipStream_t)stream);
 }
 
 int cider_decode_batch(int32_t num_bins, const cider_bin* bins, const cider_weights* w, int32_t steps,
