@@ -385,7 +385,7 @@ def run_batched(args, wl, P, torch):
     cfg = wl.model
     ragged = wl.ragged_K is not None
     blob = synth.make_weights(cfg, wl.weight_seed)
-    wh = P.Weights(P.make_cfg(cfg.n_layers, cfg.d, cfg.heads, cfg.mlp_mult, cfg.n_max), blob)
+    wh = P.Weights(P.make_cfg(cfg.n_layers, cfg.d, cfg.heads, cfg.mlp_mult, cfg.n_max, cfg.q), blob)
     if ragged:
         codes = {n: synth.regular_ldpc(n, seed=1000 + n) for n in wl.ragged_n}
         if wl.binning:
@@ -536,7 +536,7 @@ def _c2_weights(P, wl):
     import synth
     cfg = wl.model
     blob = synth.make_weights(cfg, wl.weight_seed)
-    return cfg, P.Weights(P.make_cfg(cfg.n_layers, cfg.d, cfg.heads, cfg.mlp_mult, cfg.n_max), blob)
+    return cfg, P.Weights(P.make_cfg(cfg.n_layers, cfg.d, cfg.heads, cfg.mlp_mult, cfg.n_max, cfg.q), blob)
 
 
 def clopper_pearson(k, n, alpha=0.05):
@@ -617,7 +617,7 @@ def run_served(args, wl, P, torch):
     import synth
     cfg = wl.model
     blob = synth.make_weights(cfg, wl.weight_seed)
-    wh = P.Weights(P.make_cfg(cfg.n_layers, cfg.d, cfg.heads, cfg.mlp_mult, cfg.n_max), blob)
+    wh = P.Weights(P.make_cfg(cfg.n_layers, cfg.d, cfg.heads, cfg.mlp_mult, cfg.n_max, cfg.q), blob)
     codes = {n: synth.regular_ldpc(n, seed=1000 + n) for n in wl.ragged_n}
     handles = {n: P.Code(c.n, c.m, c.row_ptr, c.col_idx) for n, c in codes.items()}
     pool = synth.make_ragged_bins(codes, args.bins or 512, wl.ragged_K, wl.ragged_n, wl.ebn0_range, wl.bin_seed)

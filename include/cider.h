@@ -79,6 +79,8 @@ typedef struct {
   int32_t heads;
   int32_t mlp_mult;   /* MLP hidden width = mlp_mult * d (the workloads use 4) */
   int32_t n_max;      /* rows of the positional table P                      */
+  int32_t q;          /* symbols Q: 0 or 2 = the binary path (cider_decode);  */
+                      /* 4, 8, 16, 32 or 64 = GF(Q) codes (cider_decode_q_batch) */
 } cider_model_cfg;
 
 /* Decoding options; cider_opts_default() fills the values in brackets. */
@@ -164,8 +166,9 @@ typedef struct {
 void cider_opts_default(cider_opts* opts);   /* opts: host, not NULL */
 
 /* Number of floats a weights blob for `cfg` holds (layout below), or 0 if cfg
- * is invalid.  Blob layout, all row-major FP32, a linear map is y = x W^T + b:
- *   E[3][d] (row 2 = mask token), P[n_max][d], u[d], W[2][d], v[2][d],
+ * is invalid.  Blob layout, all row-major FP32, a linear map is y = x W^T + b,
+ * Q = cfg->q (2 when 0):
+ *   E[Q+1][d] (row Q = mask token), P[n_max][d], u[d], W[Q][d], v[Q][d],
  *   Wg1[d][2d], bg1[d], Wg2[d][d], bg2[d],
  *   per layer: ln1_g[d] ln1_b[d] Wqkv_r[3d][d] bqkv_r[3d] Wo_r[d][d] bo_r[d]
  *              ln2_g[d] ln2_b[d] Wqkv_u[3d][d] bqkv_u[3d] Wo_u[d][d] bo_u[d]
@@ -200,6 +203,16 @@ void cider_weights_destroy(cider_weights* w);
 int cider_code_create(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* col_idx,
                       cider_code** out);
 void cider_code_destroy(cider_code* code);
+
+/* A parity-check matrix over GF(Q), Q = 2^q_bits, 2 <= q_bits <= 6 (Appendix,
+ * Q-ary LDPC code: H in F_Q^{P x L} with i.i.d. nonzero coefficients on its
+ * Tanner-graph edges).  CSR as in cider_code_create plus coef[row_ptr[m]],
+ * the nonzero coefficient H[j, l] of each edge; field in polynomial basis
+ * with primitive polynomial x^2+x+1, x^3+x+1, x^4+x+1, x^5+x^2+1 or x^6+x+1,
+ * symbol index = the element's coefficient bits.  Check degrees 1..16.
+ * Host arrays, read during the call; synchronous. */
+int cider_code_create_q(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* col_idx,
+                        const uint8_t* coef, int32_t q_bits, cider_code** out);
 
 /* Bytes of caller workspace a batch of `num_bins` bins with `total_tokens`
  * = sum of K*n and `total_slots` = sum of n needs under `opts`: the
@@ -256,6 +269,46 @@ int cider_decode_noalloc(const float* y, float sigma2, const cider_code* code, i
  * enqueued). */
 int cider_decode_batch(int32_t num_bins, const cider_bin* bins, const cider_weights* w,
                        int32_t steps, const cider_opts* opts, void* stream);
+
+/* ---- GF(Q) codes: the paper's main setting ------------------------------
+ * Decoding over a Q-ary LDPC code from the slot-wise evidence S[l][a] =
+ * log Pr(symbol a present at slot l | Y_l) (Appendix, per-slot channel model
+ * and symbol-level soft evidence; cider_amp_evidence computes it), with the
+ * Q-symbol forms of the method: embedding table E[Q+1] (row Q = mask),
+ * Module A over the Q symbols with p = softmax_a S, Module B's extrinsic
+ * check messages from the exact check-to-variable rule over GF(Q) (the
+ * other edges' weighted sum, applied through each edge's coefficient)
+ * added to the logits as eta times their centred logarithm, and a reveal
+ * ranked by the confidence max_a softmax(L / tau_t)_a at the annealed
+ * temperature (masked-diffusion inference appendix).  The grid holds
+ * symbols 0..Q-1 and Q = mask.  The weights need cfg.q == Q and every code
+ * q_bits == log2 Q.  Precision FP32 or BF16; remasking, the quality head and
+ * final_argmax are CIDER_EUNSUPPORTED on this path. */
+typedef struct {
+  const float*      S;             /* device [n][Q] FP32 log evidence            */
+  const cider_code* code;          /* cider_code_create_q, code->n == n          */
+  int32_t           K;             /* users, 1..CIDER_MAX_K                      */
+  int32_t           n;             /* slots, 1..min(n_max, CIDER_MAX_N)          */
+  uint8_t*          out_symbols;   /* device [K][n], values 0..Q-1               */
+  float*            out_logits;    /* device [K][n][Q] last final-pass logits,   */
+                                   /* or NULL                                    */
+  uint8_t*          out_row_valid; /* device [K]: 1 iff H x_k = 0 over GF(Q)     */
+} cider_qbin;
+
+/* Decodes `num_bins` independent bins over GF(Q) codes in one packed pass
+ * per step, like cider_decode_batch: each bin's result is the same as
+ * decoding it alone.  bins: host array (read during the call). */
+int cider_decode_q_batch(int32_t num_bins, const cider_qbin* bins, const cider_weights* w,
+                         int32_t steps, const cider_opts* opts, void* stream);
+
+/* Teacher-forced GF(Q) step, as cider_step_debug: X_in device [K][n] in
+ * 0..Q (Q = mask); out_lbar / out_logits device [K][n][Q] (either NULL);
+ * X_out, if not NULL, receives X_in with `reveal_count` sites revealed by the
+ * confidence ranking at temperature opts->tau_max (first-reveal if `first`). */
+int cider_step_debug_q(const uint8_t* X_in, uint8_t* X_out, const float* S, const cider_code* code,
+                       int32_t K, int32_t n, const cider_weights* w, float gamma, int32_t reveal_count,
+                       int32_t first, const cider_opts* opts, float* out_lbar, float* out_logits,
+                       void* stream);
 
 /* Test entry point: one refinement step (method section, refinement loop:
  * denoiser forward with Modules A and B, then the confidence-ranked reveal

@@ -80,13 +80,10 @@ def site_dists(lbar: np.ndarray, X: np.ndarray, Q: int, lam_max: float) -> np.nd
 
 
 def xor_convolve(a: np.ndarray, b: np.ndarray) -> np.ndarray:
-    """Distribution of x ^ y for independent x ~ a, y ~ b: out[c] = sum_x a[x] b[x ^ c]."""
-    Q = a.shape[0]
-    out = np.zeros(Q)
-    for c in range(Q):
-        for x in range(Q):
-            out[c] += a[x] * b[x ^ c]
-    return out
+    """Distribution of x ^ y for independent x ~ a, y ~ b: out[c] = sum_x a[x] b[x ^ c]
+    (the sum over x as one matrix-vector product with the table b[x ^ c])."""
+    idx = np.arange(a.shape[0])
+    return a @ np.asarray(b)[np.bitwise_xor.outer(idx, idx)]
 
 
 def check_message(q_in: List[np.ndarray], alphas_in: List[int], alpha_out: int, m: int) -> np.ndarray:

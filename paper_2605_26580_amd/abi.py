@@ -27,6 +27,7 @@ EXPORTS = [
     "cider_decode_batch", "cider_decode_noalloc", "cider_step_debug", "cider_evidence", "cider_amp_evidence", "cider_gf64_check_update", "cider_server_create",
     "cider_server_submit", "cider_server_poll", "cider_server_drain", "cider_server_destroy",
     "cider_strerror", "cider_last_error", "cider_profile_read", "cider_tuning_read",
+    "cider_code_create_q", "cider_decode_q_batch", "cider_step_debug_q",
 ]
 
 
@@ -38,7 +39,7 @@ class CiderError(RuntimeError):
 
 class cider_model_cfg(C.Structure):
     _fields_ = [("n_layers", C.c_int32), ("d", C.c_int32), ("heads", C.c_int32),
-                ("mlp_mult", C.c_int32), ("n_max", C.c_int32)]
+                ("mlp_mult", C.c_int32), ("n_max", C.c_int32), ("q", C.c_int32)]
 
 
 class cider_opts(C.Structure):
@@ -58,6 +59,11 @@ class cider_bin(C.Structure):
     _fields_ = [("y", C.c_void_p), ("sigma2", C.c_float), ("code", C.c_void_p), ("K", C.c_int32),
                 ("n", C.c_int32), ("out_symbols", C.c_void_p), ("out_logits", C.c_void_p),
                 ("out_row_valid", C.c_void_p), ("out_rounds", C.c_void_p)]
+
+
+class cider_qbin(C.Structure):
+    _fields_ = [("S", C.c_void_p), ("code", C.c_void_p), ("K", C.c_int32), ("n", C.c_int32),
+                ("out_symbols", C.c_void_p), ("out_logits", C.c_void_p), ("out_row_valid", C.c_void_p)]
 
 
 class cider_kernel_stat(C.Structure):
@@ -106,6 +112,10 @@ def lib() -> C.CDLL:
     L.cider_weights_destroy.restype = None
     L.cider_code_create.argtypes = [i32, i32, vp, vp, C.POINTER(vp)]
     L.cider_code_destroy.argtypes = [vp]
+    L.cider_code_create_q.argtypes = [i32, i32, vp, vp, vp, i32, C.POINTER(vp)]
+    L.cider_decode_q_batch.argtypes = [i32, C.POINTER(cider_qbin), vp, i32, C.POINTER(cider_opts), vp]
+    L.cider_step_debug_q.argtypes = [vp, vp, vp, vp, i32, i32, vp, f32, i32, i32, C.POINTER(cider_opts),
+                                     vp, vp, vp]
     L.cider_code_destroy.restype = None
     L.cider_workspace_size.argtypes = [vp, i32, C.c_int64, C.c_int64, C.POINTER(cider_opts),
                                        C.POINTER(C.c_size_t)]
@@ -177,8 +187,8 @@ def cider_opts_default(**overrides) -> cider_opts:
     return o
 
 
-def make_cfg(n_layers: int, d: int, heads: int, mlp_mult: int = 4, n_max: int = 1024) -> cider_model_cfg:
-    return cider_model_cfg(n_layers, d, heads, mlp_mult, n_max)
+def make_cfg(n_layers: int, d: int, heads: int, mlp_mult: int = 4, n_max: int = 1024, q: int = 0) -> cider_model_cfg:
+    return cider_model_cfg(n_layers, d, heads, mlp_mult, n_max, q)
 
 
 def cider_weights_blob_floats(cfg: cider_model_cfg) -> int:
@@ -238,6 +248,43 @@ class Code:
 
 def cider_code_create(n: int, m: int, row_ptr, col_idx) -> Code:
     return Code(n, m, row_ptr, col_idx)
+
+
+class CodeQ(Code):
+    """Owns a cider_code handle of a GF(2^q_bits) code (CSR plus edge coefficients)."""
+
+    def __init__(self, n: int, m: int, row_ptr: np.ndarray, col_idx: np.ndarray, coef: np.ndarray, q_bits: int):
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        cf = np.ascontiguousarray(coef, dtype=np.uint8)
+        h = C.c_void_p()
+        check(lib().cider_code_create_q(int(n), int(m), rp.ctypes.data, ci.ctypes.data, cf.ctypes.data,
+                                        int(q_bits), C.byref(h)), "cider_code_create_q")
+        self.n, self.m, self.q_bits = int(n), int(m), int(q_bits)
+        self.handle = h
+
+
+def cider_code_create_q(n: int, m: int, row_ptr, col_idx, coef, q_bits: int) -> CodeQ:
+    return CodeQ(n, m, row_ptr, col_idx, coef, q_bits)
+
+
+def cider_decode_q_batch(bins: Sequence[dict], w: Weights, steps: int, opts: Optional[cider_opts] = None,
+                         stream=None) -> None:
+    """bins: dicts with S, code, K, n, out_symbols and optional out_logits, out_row_valid."""
+    arr = (cider_qbin * len(bins))()
+    for i, b in enumerate(bins):
+        arr[i] = cider_qbin(_ptr(b["S"]), b["code"].handle, int(b["K"]), int(b["n"]), _ptr(b["out_symbols"]),
+                            _ptr(b.get("out_logits")), _ptr(b.get("out_row_valid")))
+    check(lib().cider_decode_q_batch(len(bins), arr, w.handle, steps, C.byref(opts) if opts is not None else None,
+                                     _stream(stream)), "cider_decode_q_batch")
+
+
+def cider_step_debug_q(X_in, X_out, S, code: Code, K: int, n: int, w: Weights, gamma: float, reveal_count: int,
+                       first: int, opts: Optional[cider_opts] = None, out_lbar=None, out_logits=None,
+                       stream=None) -> None:
+    check(lib().cider_step_debug_q(_ptr(X_in), _ptr(X_out), _ptr(S), code.handle, K, n, w.handle, float(gamma),
+                                   int(reveal_count), int(first), C.byref(opts) if opts is not None else None,
+                                   _ptr(out_lbar), _ptr(out_logits), _stream(stream)), "cider_step_debug_q")
 
 
 def cider_workspace_size(w: Weights, num_bins: int, total_tokens: int, total_slots: int,

@@ -60,6 +60,11 @@ struct DevBin {
   uint8_t* out_valid;   // [K] or null
   int32_t* out_rounds;  // [1] remask rounds run, or null
   BinState* st;
+  // GF(Q) path (null / 0 on the binary path)
+  const float* S;       // [n][Q] log evidence
+  const uint8_t* coef;  // [nnz] coefficient of each edge of H
+  int q_bits;           // Q = 2^q_bits
+  int msg_off;          // first check message of the bin in StepCtx::msg, in units of Q floats
 };
 
 // Everything a refinement step needs besides the weights.
@@ -86,6 +91,12 @@ struct StepCtx {
   int qh_hidden;
   float phi[4];             // per-round thresholds of the quality head
   const float* qw;          // per-token head output omega [T] (written for bins in their final pass)
+  // symbols: 2 on the binary path, Q = 2^m on the GF(Q) path (grid value `mask` = masked)
+  int q, mask;
+  float tau_max, tau_min;   // inference temperature, annealed over a pass (GF(Q) ranking)
+  float* msg;               // GF(Q) Module B: per row and edge, the centred log check message [Q]
+  unsigned* rank;           // GF(Q) reveal: per token, confidence rank (larger = more confident)
+  uint8_t* sym;             // GF(Q) reveal: per token, argmax symbol
   float gamma_override;     // >= 0: mask-ratio input for every bin (teacher-forced step)
   int reveal_override;      // >= 0: reveal this many sites instead of the schedule's count
   int first_override;       // first-reveal flag used with reveal_override
@@ -111,10 +122,11 @@ struct DevLayer {
 struct EmbedW {
   int d;
   const float *E, *P, *u, *W, *v, *lnf_g, *lnf_b;
+  int q;                // symbols: E has q + 1 rows, W and v q rows
 };
 
 struct DevModel {
-  int n_layers, d, heads, mlp_mult, n_max;
+  int n_layers, d, heads, mlp_mult, n_max, q;
   const float *E, *P, *u, *W, *v, *bg1, *bg2, *lnf_g, *lnf_b;
   Mat Wg1, Wg2;
   const float* ug;      // [2][d]: Wg1[:, d:2d] v_a, the gate's e input folded into two vectors
@@ -140,6 +152,19 @@ struct Work {
   float* p;        // [slots][2] per-slot beliefs
   float* S;        // [slots][2] per-slot log evidence
 };
+
+// ---- GF(Q) path (kernels_qary.hip) ---------------------------------------
+constexpr int kQaryMaxDeg = 16;   // check degree bound of the GF(Q) Module B
+// p = softmax_a S per slot ([slots][Q])
+hipError_t launch_evidence_q(const StepCtx& c, float* p, hipStream_t s);
+// embedding + Module A over Q symbols: R = Z, Ebuf = e, ZE = [Z ; e]
+hipError_t launch_embed_demix_q(const StepCtx& c, const EmbedW& m, const Work& w, int prec, hipStream_t s);
+// lbar[t][a] = <LN_f(R[t]), w_a>, a < Q
+hipError_t launch_final_proj_q(const StepCtx& c, const EmbedW& m, const Work& w, hipStream_t s);
+// Module B over GF(Q): check messages into c.msg, then logits = lbar + eta sum
+hipError_t launch_module_b_q(const StepCtx& c, const Work& w, int max_checks, hipStream_t s);
+// reveal keys: per token confidence rank at the pass's temperature and argmax symbol
+hipError_t launch_site_key_q(const StepCtx& c, const Work& w, hipStream_t s);
 
 // GF(64) check-node update: per-edge distributions in, per-edge messages out.
 struct GfCheckArgs {

@@ -88,12 +88,17 @@ bool cfg_ok(const cider_model_cfg* c, std::string* why) {
   if (dh != 16 && dh != 32 && dh != 64) { *why = "d/heads must be 16, 32 or 64"; return false; }
   if (c->mlp_mult < 1 || c->mlp_mult * c->d > 2048) { *why = "mlp_mult*d must be <= 2048"; return false; }
   if (c->n_max < 1 || c->n_max > CIDER_MAX_N) { *why = "n_max must be 1..1024"; return false; }
+  if (!(c->q == 0 || c->q == 2 || c->q == 4 || c->q == 8 || c->q == 16 || c->q == 32 || c->q == 64)) {
+    *why = "q must be 0 or 2 (binary) or 4, 8, 16, 32, 64";
+    return false;
+  }
   return true;
 }
 
 size_t blob_floats(const cider_model_cfg* c) {
   size_t d = c->d, F = (size_t)c->mlp_mult * c->d;
-  size_t head = 3 * d + (size_t)c->n_max * d + d + 2 * d + 2 * d + d * 2 * d + d + d * d + d;
+  const size_t Q = c->q > 2 ? (size_t)c->q : 2;
+  size_t head = (Q + 1) * d + (size_t)c->n_max * d + d + Q * d + Q * d + d * 2 * d + d + d * d + d;
   size_t per = 2 * d + 3 * d * d + 3 * d + d * d + d + 2 * d + 3 * d * d + 3 * d + d * d + d + 2 * d +
                F * d + F + d * F + d;
   return head + per * c->n_layers + 2 * d;
@@ -104,6 +109,8 @@ size_t blob_floats(const cider_model_cfg* c) {
 // ---------------------------------------------------------------------------
 struct cider_code {
   int n = 0, m = 0, nnz = 0, device = 0;
+  int q_bits = 0;              // 0: binary code; m: GF(2^m) coefficients in d_coef
+  uint8_t* d_coef = nullptr;
   int* d_row_ptr = nullptr;
   int* d_col_idx = nullptr;
   int* d_var_ptr = nullptr;
@@ -214,21 +221,25 @@ int get_sched(cider_weights* w, int K, int n, int T, int kind, int** out) {
 
 struct Layout {
   int num_bins = 0;
+  int q = 2;              // symbols of the model (2: binary path)
   long total_tokens = 0;
   int total_slots = 0, total_rows = 0, max_n = 0, total_ugrp = 0;
   size_t off_ugrp = 0, off_ugrp32 = 0, off_tile = 0, off_R, off_E, off_ZE, off_H1, off_QKV, off_O, off_HID, off_lbar, off_logits, off_qw, off_p, off_S,
-      off_bins, off_state, off_slot, off_row, off_X, off_XN, off_XN8, off_xscale, total;
+      off_bins, off_state, off_slot, off_row, off_X, off_XN, off_XN8, off_xscale, off_msg, off_rank, off_sym, total;
 };
 
 size_t esize(int prec) { return prec == CIDER_FP32 ? 4 : 2; }
 
-Layout plan_layout(const cider_model_cfg& cfg, int num_bins, long T, int slots, int rows, int prec) {
+// msg: GF(Q) check messages (sum over bins of K nnz), in units of Q floats.
+Layout plan_layout(const cider_model_cfg& cfg, int num_bins, long T, int slots, int rows, int prec, long msg = 0) {
   Layout L;
   L.num_bins = num_bins;
   L.total_tokens = T;
   L.total_slots = slots;
   L.total_rows = rows;
   size_t d = cfg.d, F = (size_t)cfg.mlp_mult * cfg.d, es = esize(prec), o = 0;
+  const size_t Q = cfg.q > 2 ? (size_t)cfg.q : 2;
+  L.q = (int)Q;
   auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
   L.off_R = take(T * d * 4);
   L.off_E = take(T * d * 4);
@@ -240,11 +251,14 @@ Layout plan_layout(const cider_model_cfg& cfg, int num_bins, long T, int slots, 
   L.off_QKV = take(T * 3 * d * es);
   L.off_O = take(T * d * es);
   L.off_HID = take(T * F * es);
-  L.off_lbar = take(T * 2 * 4);
-  L.off_logits = take(T * 2 * 4);
+  L.off_lbar = take(T * Q * 4);
+  L.off_logits = take(T * Q * 4);
   L.off_qw = take(T * 4);
-  L.off_p = take((size_t)slots * 2 * 4);
-  L.off_S = take((size_t)slots * 2 * 4);
+  L.off_p = take((size_t)slots * Q * 4);
+  L.off_S = take((size_t)slots * Q * 4);
+  L.off_msg = take(Q > 2 ? (size_t)msg * Q * 4 : 0);
+  L.off_rank = take(Q > 2 ? T * 4 : 0);
+  L.off_sym = take(Q > 2 ? T : 0);
   L.off_bins = take((size_t)num_bins * sizeof(DevBin));
   L.off_state = take((size_t)num_bins * sizeof(BinState));
   L.off_slot = take((size_t)slots * 4);
@@ -320,6 +334,7 @@ struct Run {
   bool use_blocks = true; // fused attention blocks where the shapes allow
   RowSeg seg[kRowPaths]{};
   int nseg = 0;
+  int max_checks = 0;     // most checks of a bin's code (GF(Q) Module B grid)
 };
 
 // Brackets a launch with events when profiling is on.
@@ -463,8 +478,11 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
   GemmArgs g{};
   g.M = T;
   // BF16 at d = 128 and 256: embedding, Module A and the first LayerNorm in one kernel
-  const bool embed_gate = prec == kBF16 && r.use_blocks && fused_ln && (embed_gate3_ok(d) || embed_gate_z_ok(d));
-  if (!embed_gate) TIMED("embed_demix", launch_embed_demix(c, w->ew, k, prec, s));
+  const bool qary = m.q > 2;
+  const bool embed_gate = !qary && prec == kBF16 && r.use_blocks && fused_ln &&
+                          (embed_gate3_ok(d) || embed_gate_z_ok(d));
+  if (qary) TIMED("embed_demix", launch_embed_demix_q(c, w->ew, k, prec, s));
+  else if (!embed_gate) TIMED("embed_demix", launch_embed_demix(c, w->ew, k, prec, s));
   // gate MLP: H1 = GELU([Z ; e] Wg1^T + bg1); R = g Z + (1 - g) e, g = sigmoid(H1 Wg2^T + bg2)
   if (embed_gate) {
     EmbedGateArgs ea{};
@@ -572,6 +590,10 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
       g.N = d; g.Kd = d; g.A = k.XN; g.bias = L.b2; g.R = k.R;
       if (l + 1 < m.n_layers) {
         next_ln(g, m.layer[l + 1].ln1_g, m.layer[l + 1].ln1_b);
+      } else if (qary) {
+        // GF(Q): the Q-way projection runs as its own kernel on R; the epilogue's
+        // LayerNorm output is not read
+        next_ln(g, m.lnf_g, m.lnf_b);
       } else {
         // last block: final LayerNorm and symbol projection in the epilogue
         g.ln_g = m.lnf_g; g.ln_b = m.lnf_b; g.proj_w = m.W; g.proj_out = k.lbar;
@@ -603,6 +625,11 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
       g.N = d; g.Kd = F; g.A = k.HID; g.bias = L.b2; g.R = k.R;
       TIMED("gemm_mlp_down", gemm(kEpiResid, g, L.W2));
     }
+  }
+  if (qary) {
+    TIMED("final_proj", launch_final_proj_q(c, w->ew, k, s));
+    TIMED("module_b", launch_module_b_q(c, k, r.max_checks, s));
+    return CIDER_OK;
   }
   if (!fused_ln) TIMED("final_proj", launch_final_proj(c, w->ew, k, s));
   TIMED("module_b", launch_module_b(c, k, s));
@@ -672,6 +699,7 @@ int enqueue_step(cider_weights* w, const Run& r, hipStream_t s) {
   int rc = enqueue_forward(w, r, s);
   if (rc) return rc;
   if (r.ctx.qhead) TIMED("quality_head", launch_quality_head(r.ctx, w->ew, r.work, s));
+  if (r.ctx.q > 2) TIMED("site_key", launch_site_key_q(r.ctx, r.work, s));
   TIMED("step_tail", launch_step_tail(r.ctx, r.work, s));
   return CIDER_OK;
 }
@@ -724,6 +752,7 @@ struct BinIn {
   int32_t* out_rounds = nullptr;
   uint8_t* X = nullptr;     // persistent grid (serving); null: workspace
   BinState* st = nullptr;   // persistent state (serving); null: workspace
+  const float* S = nullptr; // GF(Q) path: device [n][Q] log evidence (y is null)
 };
 
 int check_opts(const cider_opts& o) {
@@ -746,6 +775,11 @@ int check_opts(const cider_opts& o) {
 }
 
 int check_prec(const cider_weights* w, const cider_opts& o) {
+  if (w->cfg.q > 2) {
+    if (o.precision == CIDER_FP8) return fail(CIDER_EUNSUPPORTED, "GF(Q) decoding runs in FP32 or BF16");
+    if (o.remask || o.qhead) return fail(CIDER_EUNSUPPORTED, "GF(Q) decoding has no remasking");
+    if (o.final_argmax) return fail(CIDER_EUNSUPPORTED, "GF(Q) decoding outputs the held-fixed grid");
+  }
   if (o.qhead && w->cfg.d > 1024) return fail(CIDER_EUNSUPPORTED, "the quality head needs d <= 1024");
   if (o.precision == CIDER_FP8 && (w->cfg.d % 128 != 0 || (w->cfg.mlp_mult * w->cfg.d) % 64 != 0))
     return fail(CIDER_EUNSUPPORTED, "FP8 needs d to be a multiple of 128");
@@ -753,14 +787,21 @@ int check_prec(const cider_weights* w, const cider_opts& o) {
 }
 
 int check_bin(const cider_weights* w, const BinIn& b, int steps) {
-  if (!b.y || !b.code || !b.out_sym) return fail(CIDER_EINVAL, "null y, code or out_symbols");
+  const bool qary = w->cfg.q > 2;
+  if (!(qary ? b.S : b.y) || !b.code || !b.out_sym)
+    return fail(CIDER_EINVAL, qary ? "null S, code or out_symbols" : "null y, code or out_symbols");
+  if (qary != (b.S != nullptr))
+    return fail(CIDER_EINVAL, qary ? "weights for GF(Q) codes need GF(Q) bins (cider_decode_q_batch)"
+                                   : "binary weights need binary bins (cider_decode, cider_decode_batch)");
+  if (qary ? (b.code->q_bits == 0 || (1 << b.code->q_bits) != w->cfg.q) : b.code->q_bits != 0)
+    return fail(CIDER_EINVAL, "the code's field does not match the weights' symbol count");
   if (row_attn_mfma_lds(b.n, w->cfg.d / w->cfg.heads) > 160 * 1024)
     return fail(CIDER_EUNSUPPORTED, "n * d/heads too large for LDS-resident row attention (n*dh*4 <= 160 KB)");
   if (b.K < 1 || b.K > CIDER_MAX_K) return fail(CIDER_EINVAL, "K must be 1..16");
   if (b.n < 1 || b.n > std::min(w->cfg.n_max, CIDER_MAX_N)) return fail(CIDER_EINVAL, "n out of range for the model");
   if (b.code->n != b.n) return fail(CIDER_EINVAL, "code length != n");
   if (b.code->device != w->device) return fail(CIDER_EINVAL, "code and weights live on different devices");
-  if (!(b.sigma2 > 0.f) || !std::isfinite(b.sigma2)) return fail(CIDER_EINVAL, "sigma2 must be > 0");
+  if (!qary && (!(b.sigma2 > 0.f) || !std::isfinite(b.sigma2))) return fail(CIDER_EINVAL, "sigma2 must be > 0");
   if (steps < 1 || (long)steps > (long)b.K * b.n) return fail(CIDER_EINVAL, "steps must be 1..K*n");
   return CIDER_OK;
 }
@@ -802,6 +843,13 @@ void fill_run(Run* r, const Layout& L, char* base, const cider_opts& o, int B, l
   c.gamma_override = -1.f;
   c.reveal_override = -1;
   c.first_override = 0;
+  c.q = L.q;
+  c.mask = c.q > 2 ? c.q : kMask;
+  c.tau_max = o.tau_max;
+  c.tau_min = o.tau_min;
+  c.msg = c.q > 2 ? (float*)(base + L.off_msg) : nullptr;
+  c.rank = c.q > 2 ? (unsigned*)(base + L.off_rank) : nullptr;
+  c.sym = c.q > 2 ? (uint8_t*)(base + L.off_sym) : nullptr;
   Work& k = r->work;
   k.R = (float*)(base + L.off_R);
   k.Ebuf = (float*)(base + L.off_E);
@@ -827,15 +875,18 @@ void fill_run(Run* r, const Layout& L, char* base, const cider_opts& o, int B, l
 int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const cider_opts& o,
             hipStream_t s, Run* r, Layout* Lout, bool init_grids) {
   const int B = (int)bins.size();
-  long T = 0;
+  long T = 0, msg = 0;
   int slots = 0, rows = 0, max_n = 0;
+  r->max_checks = 0;
   for (const BinIn& b : bins) {
     T += (long)b.K * b.n;
     slots += b.n;
     rows += b.K;
     max_n = std::max(max_n, b.n);
+    msg += (long)b.K * b.code->nnz;
+    r->max_checks = std::max(r->max_checks, b.code->m);
   }
-  Layout L = plan_layout(w->cfg, B, T, slots, rows, o.precision);
+  Layout L = plan_layout(w->cfg, B, T, slots, rows, o.precision, msg);
   L.max_n = max_n;
   char* base = nullptr;
   int rc = ensure_ws(w, o, L.total, &base);
@@ -858,7 +909,7 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
   int* hgrp32 = htile + ntile;
   int go32 = 0;
   int go = 0;
-  long tok = 0;
+  long tok = 0, mo = 0;
   int so = 0, ro = 0;
   // pack the bins path by path (stable within a path)
   std::vector<int> path_of(B), ord(B);
@@ -893,6 +944,11 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
     db.X = b.X ? b.X : (uint8_t*)(base + L.off_X) + tok;
     db.out_sym = b.out_sym; db.out_logits = b.out_logits; db.out_valid = b.out_valid; db.out_rounds = b.out_rounds;
     db.st = b.st ? b.st : (BinState*)(base + L.off_state) + i;
+    db.S = b.S;
+    db.coef = b.code->d_coef;
+    db.q_bits = b.code->q_bits;
+    db.msg_off = (int)mo;
+    mo += (long)b.K * b.code->nnz;
     hb[i] = db;
     for (int l = 0; l < b.n; ++l) hslot[so + l] = i;
     for (int k = 0; k < b.K; ++k) hrow[ro + k] = i;
@@ -923,7 +979,8 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
   fill_run(r, L, base, o, B, T, slots, rows, max_n, ngrp, ngrp32);
   const StepCtx& c = r->ctx;
   const Work& k = r->work;
-  HIPCHK(launch_evidence(c, k.S, k.p, s));
+  if (c.q > 2) HIPCHK(launch_evidence_q(c, k.p, s));
+  else HIPCHK(launch_evidence(c, k.S, k.p, s));
   if (init_grids) {
     HIPCHK(launch_init_bins(c, steps, o.first_reveal, s));
   }
@@ -1256,13 +1313,14 @@ int cider_weights_create(const cider_model_cfg* cfg, const float* blob, size_t n
   DevModel& m = w->dm;
   size_t off_v = 0, off_wg1 = 0;
   m.n_layers = cfg->n_layers; m.d = d; m.heads = cfg->heads; m.mlp_mult = cfg->mlp_mult; m.n_max = cfg->n_max;
+  m.q = cfg->q > 2 ? cfg->q : 2;
   int rc = 0;
-  m.E = vec(3 * (size_t)d);
+  m.E = vec((size_t)(m.q + 1) * d);
   m.P = vec((size_t)cfg->n_max * d);
   m.u = vec(d);
-  m.W = vec(2 * (size_t)d);
+  m.W = vec((size_t)m.q * d);
   off_v = off;
-  m.v = vec(2 * (size_t)d);
+  m.v = vec((size_t)m.q * d);
   off_wg1 = off;
   if ((rc = mat(d, 2 * d, &m.Wg1))) goto bad;
   m.bg1 = vec(d);
@@ -1289,7 +1347,7 @@ int cider_weights_create(const cider_model_cfg* cfg, const float* blob, size_t n
   m.lnf_g = vec(d);
   m.lnf_b = vec(d);
   if (off != n_floats) { rc = fail(CIDER_EINVAL, "internal layout mismatch"); goto bad; }
-  {
+  if (m.q == 2) {
     // the gate's e input is a combination of the two rows v_a, so its share of
     // the first gate layer folds into ug[a] = Wg1[:, d:2d] v_a (FP64 sums)
     std::vector<float> hug(2 * (size_t)d);
@@ -1309,7 +1367,7 @@ int cider_weights_create(const cider_model_cfg* cfg, const float* blob, size_t n
     }
     m.ug = (const float*)dug;
   }
-  w->ew = EmbedW{d, m.E, m.P, m.u, m.W, m.v, m.lnf_g, m.lnf_b};
+  w->ew = EmbedW{d, m.E, m.P, m.u, m.W, m.v, m.lnf_g, m.lnf_b, m.q};
   *out = w;
   return CIDER_OK;
 bad:
@@ -1384,7 +1442,33 @@ void cider_code_destroy(cider_code* c) {
   hipFree(c->d_col_idx);
   hipFree(c->d_var_ptr);
   hipFree(c->d_var_edge);
+  hipFree(c->d_coef);
   delete c;
+}
+
+int cider_code_create_q(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* col_idx, const uint8_t* coef,
+                        int32_t q_bits, cider_code** out) {
+  if (!out) return fail(CIDER_EINVAL, "null out");
+  *out = nullptr;
+  if (q_bits < 2 || q_bits > 6 || !coef || !row_ptr) return fail(CIDER_EINVAL, "q_bits must be 2..6 with coefficients");
+  if (m < 1 || m > 4 * CIDER_MAX_N || row_ptr[0] != 0) return fail(CIDER_EINVAL, "bad code sizes");
+  for (int j = 0; j < m; ++j)
+    if (row_ptr[j + 1] - row_ptr[j] > kQaryMaxDeg) return fail(CIDER_EINVAL, "GF(Q) check degree must be 1..16");
+  const int nnz = row_ptr[m];
+  for (int e = 0; e < nnz; ++e)
+    if (coef[e] < 1 || coef[e] >= (1 << q_bits)) return fail(CIDER_EINVAL, "coefficients must be nonzero field elements");
+  cider_code* c = nullptr;
+  int rc = cider_code_create(n, m, row_ptr, col_idx, &c);
+  if (rc) return rc;
+  hipError_t e = hipMalloc(&c->d_coef, (size_t)nnz);
+  if (e == hipSuccess) e = hipMemcpy(c->d_coef, coef, (size_t)nnz, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    cider_code_destroy(c);
+    return hip_fail(e, "cider_code_create_q");
+  }
+  c->q_bits = q_bits;
+  *out = c;
+  return CIDER_OK;
 }
 
 int cider_workspace_size(const cider_weights* w, int32_t num_bins, int64_t total_tokens, int64_t total_slots,
@@ -1430,6 +1514,70 @@ int cider_decode_batch(int32_t num_bins, const cider_bin* bins, const cider_weig
     v.push_back(BinIn{bins[i].y, bins[i].sigma2, bins[i].code, bins[i].K, bins[i].n, bins[i].out_symbols,
                       bins[i].out_logits, bins[i].out_row_valid, bins[i].out_rounds});
   return decode_impl(const_cast<cider_weights*>(w), v, steps, o, (hipStream_t)stream);
+}
+
+int cider_decode_q_batch(int32_t num_bins, const cider_qbin* bins, const cider_weights* w, int32_t steps,
+                         const cider_opts* opts, void* stream) {
+  if (!w) return fail(CIDER_EINVAL, "null weights");
+  if (num_bins < 0 || (num_bins > 0 && !bins)) return fail(CIDER_EINVAL, "bad bin list");
+  cider_opts o;
+  if (opts) o = *opts; else cider_opts_default(&o);
+  std::vector<BinIn> v;
+  v.reserve(num_bins);
+  for (int i = 0; i < num_bins; ++i) {
+    BinIn b{nullptr, 1.0f, bins[i].code, bins[i].K, bins[i].n, bins[i].out_symbols, bins[i].out_logits,
+            bins[i].out_row_valid};
+    b.S = bins[i].S;
+    v.push_back(b);
+  }
+  return decode_impl(const_cast<cider_weights*>(w), v, steps, o, (hipStream_t)stream);
+}
+
+int cider_step_debug_q(const uint8_t* X_in, uint8_t* X_out, const float* S, const cider_code* code, int32_t K,
+                       int32_t n, const cider_weights* wc, float gamma, int32_t reveal_count, int32_t first,
+                       const cider_opts* opts, float* out_lbar, float* out_logits, void* stream) {
+  if (!wc || !X_in) return fail(CIDER_EINVAL, "null weights or X_in");
+  cider_weights* w = const_cast<cider_weights*>(wc);
+  cider_opts o;
+  if (opts) o = *opts; else cider_opts_default(&o);
+  int rc = check_opts(o);
+  if (rc) return rc;
+  rc = check_prec(w, o);
+  if (rc) return rc;
+  uint8_t dummy = 0;
+  BinIn b{nullptr, 1.0f, code, K, n, &dummy, nullptr, nullptr};
+  b.S = S;
+  rc = check_bin(w, b, 1);
+  if (rc) return rc;
+  if (reveal_count < 0 || reveal_count > K * n) return fail(CIDER_EINVAL, "reveal_count out of range");
+  if (!(gamma >= 0.f && gamma <= 1.f)) return fail(CIDER_EINVAL, "gamma must be in [0, 1]");
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(w->mu);
+  HIPCHK(hipSetDevice(w->device));
+  Run r;
+  Layout L;
+  std::vector<BinIn> bins{b};
+  rc = prepare(w, bins, 1, o, s, &r, &L, true);
+  if (rc) return rc;
+  char* base = (char*)r.ctx.bins - L.off_bins;
+  uint8_t* Xw = (uint8_t*)(base + L.off_X);
+  HIPCHK(hipMemcpyAsync(Xw, X_in, (size_t)K * n, hipMemcpyDeviceToDevice, s));
+  if (o.autotune >= 2) r.forced_tile = o.autotune - 2;
+  r.use_blocks = o.fused_blocks != 0;
+  r.ctx.gamma_override = gamma;
+  r.ctx.reveal_override = reveal_count;
+  r.ctx.first_override = first ? 1 : 0;
+  rc = enqueue_forward(w, r, s);
+  if (rc) return rc;
+  const size_t T = (size_t)K * n, Q = (size_t)w->cfg.q;
+  if (out_lbar) HIPCHK(hipMemcpyAsync(out_lbar, r.work.lbar, T * Q * 4, hipMemcpyDeviceToDevice, s));
+  if (out_logits) HIPCHK(hipMemcpyAsync(out_logits, r.work.logits, T * Q * 4, hipMemcpyDeviceToDevice, s));
+  if (X_out) {
+    HIPCHK(launch_site_key_q(r.ctx, r.work, s));
+    HIPCHK(launch_step_tail(r.ctx, r.work, s));
+    HIPCHK(hipMemcpyAsync(X_out, Xw, T, hipMemcpyDeviceToDevice, s));
+  }
+  return CIDER_OK;
 }
 
 int cider_step_debug(const uint8_t* X_in, uint8_t* X_out, const float* y, float sigma2, const cider_code* code,

@@ -79,7 +79,7 @@ hipError_t launch_evidence(const StepCtx& c, float* S, float* p, hipStream_t s) 
 __global__ void k_init_bins(StepCtx c, int T, int first_reveal) {
   const DevBin& b = c.bins[blockIdx.x];
   int tot = b.K * b.n;
-  for (int i = threadIdx.x; i < tot; i += blockDim.x) b.X[i] = (uint8_t)kMask;
+  for (int i = threadIdx.x; i < tot; i += blockDim.x) b.X[i] = (uint8_t)c.mask;
   if (threadIdx.x == 0) {
     BinState st = {};
     st.phase = kReveal;
@@ -348,11 +348,26 @@ hipError_t launch_module_b(const StepCtx& c, const Work& w, hipStream_t s) {
 constexpr int kTailThreads = 1024;
 constexpr int kKeysPerThread = (kMaxK * kMaxN) / kTailThreads;
 
+// Product in GF(2^m), polynomial basis, primitive polynomial of degree m
+// (x^2+x+1, x^3+x+1, x^4+x+1, x^5+x^2+1, x^6+x+1).
+__device__ __forceinline__ int gf_mul_q(int a, int b, int m) {
+  const int poly = m == 2 ? 0x7 : m == 3 ? 0xB : m == 4 ? 0x13 : m == 5 ? 0x25 : 0x43;
+  int r = 0;
+  for (int i = 0; i < m; ++i) {
+    if (b & 1) r ^= a;
+    b >>= 1;
+    a <<= 1;
+    if (a >> m) a ^= poly;
+  }
+  return r;
+}
+
 __device__ __forceinline__ unsigned long long site_key(float margin, int flat) {
   return ((unsigned long long)__float_as_uint(margin) << 32) |
          (unsigned long long)(0xFFFFFFFFu - (unsigned)flat);
 }
 
+template <bool QARY>
 __global__ __launch_bounds__(kTailThreads) void k_step_tail(StepCtx c, const float* logits) {
   __shared__ unsigned s_hist[256];
   __shared__ int s_wsum[4];
@@ -366,7 +381,16 @@ __global__ __launch_bounds__(kTailThreads) void k_step_tail(StepCtx c, const flo
   BinState st = *b.st;
   if (st.phase == kDone) return;
   const int K = b.K, n = b.n, tot = K * n, tid = threadIdx.x;
-  const float* lg = logits + 2 * (size_t)b.tok_off;
+  const int Q = QARY ? c.q : 2;
+  const float* lg = logits + (size_t)Q * b.tok_off;
+  // reveal key: confidence (margin bits, or the GF(Q) rank) over the complemented flat index
+  auto key_of = [&](int site) -> unsigned long long {
+    if constexpr (QARY)
+      return ((unsigned long long)c.rank[(size_t)b.tok_off + site] << 32) |
+             (unsigned long long)(0xFFFFFFFFu - (unsigned)site);
+    else
+      return site_key(fabsf(lg[2 * site] - lg[2 * site + 1]), site);
+  };
 
   if (st.phase == kReveal) {
     const int* hdr = b.sched;
@@ -376,7 +400,7 @@ __global__ __launch_bounds__(kTailThreads) void k_step_tail(StepCtx c, const flo
     bool first;
     if (c.reveal_override >= 0) {
       int masked = 0;
-      for (int site = tid; site < tot; site += kTailThreads) masked += b.X[site] == kMask;
+      for (int site = tid; site < tot; site += kTailThreads) masked += b.X[site] == c.mask;
       if (tid == 0) s_cnt = 0;
       __syncthreads();
       if (masked) atomicAdd(&s_cnt, masked);
@@ -401,8 +425,8 @@ __global__ __launch_bounds__(kTailThreads) void k_step_tail(StepCtx c, const flo
         unsigned long long best = 0ull;
         for (int k = 0; k < K; ++k) {
           int site = k * n + tid;
-          if (b.X[site] == kMask) {
-            unsigned long long kk = site_key(fabsf(lg[2 * site] - lg[2 * site + 1]), site);
+          if (b.X[site] == c.mask) {
+            unsigned long long kk = key_of(site);
             if (kk > best) best = kk;
           }
         }
@@ -412,8 +436,8 @@ __global__ __launch_bounds__(kTailThreads) void k_step_tail(StepCtx c, const flo
 #pragma unroll
       for (int i = 0; i < kKeysPerThread; ++i) {
         int site = tid + i * kTailThreads;
-        if (site < tot && b.X[site] == kMask)
-          keys[i] = site_key(fabsf(lg[2 * site] - lg[2 * site + 1]), site);
+        if (site < tot && b.X[site] == c.mask)
+          keys[i] = key_of(site);
       }
     }
     if (tid == 0) s_cnt = 0;
@@ -477,7 +501,10 @@ __global__ __launch_bounds__(kTailThreads) void k_step_tail(StepCtx c, const flo
       unsigned long long kk = keys[i];
       if (kk != 0ull && kk >= thr) {
         int site = (int)(0xFFFFFFFFu - (unsigned)(kk & 0xFFFFFFFFull));
-        b.X[site] = (lg[2 * site] >= lg[2 * site + 1]) ? 0 : 1;
+        if constexpr (QARY)
+          b.X[site] = c.sym[(size_t)b.tok_off + site];
+        else
+          b.X[site] = (lg[2 * site] >= lg[2 * site + 1]) ? 0 : 1;
       }
     }
     __syncthreads();
@@ -498,10 +525,15 @@ __global__ __launch_bounds__(kTailThreads) void k_step_tail(StepCtx c, const flo
   for (int idx = tid; idx < K * b.m; idx += kTailThreads) {
     int k = idx / b.m, j = idx - k * b.m;
     int par = 0;
-    for (int e = b.row_ptr[j]; e < b.row_ptr[j + 1]; ++e) par ^= b.X[k * n + b.col_idx[e]];
-    if (par & 1) atomicOr(&s_syn[k], 1);
+    for (int e = b.row_ptr[j]; e < b.row_ptr[j + 1]; ++e) {
+      if constexpr (QARY)
+        par ^= gf_mul_q(b.coef[e], b.X[k * n + b.col_idx[e]], b.q_bits);
+      else
+        par ^= b.X[k * n + b.col_idx[e]];
+    }
+    if (QARY ? par != 0 : (par & 1)) atomicOr(&s_syn[k], 1);
   }
-  if (wave < K) {
+  if (!QARY && wave < K) {
     float acc = 0.f;
     if (c.qhead) {
       // quality head: the row's mean omega
@@ -517,6 +549,7 @@ __global__ __launch_bounds__(kTailThreads) void k_step_tail(StepCtx c, const flo
     acc = wave_sum(acc);
     if (lane == 0) s_q[wave] = acc / (float)n;
   }
+  if (QARY && tid < kMaxK) s_q[tid] = 1.0f;
   __syncthreads();
   if (tid == 0) {
     int low = 0;
@@ -535,7 +568,7 @@ __global__ __launch_bounds__(kTailThreads) void k_step_tail(StepCtx c, const flo
   const int low = s_low;
   if (c.remask && st.round < c.max_rounds && low != 0) {
     for (int site = tid; site < tot; site += kTailThreads)
-      if ((low >> (site / n)) & 1) b.X[site] = kMask;
+      if ((low >> (site / n)) & 1) b.X[site] = (uint8_t)c.mask;
     if (tid == 0) {
       int j = __popc(low);
       st.phase = kReveal;
@@ -554,16 +587,14 @@ __global__ __launch_bounds__(kTailThreads) void k_step_tail(StepCtx c, const flo
   }
   // done: output grid, logits and row validity
   for (int site = tid; site < tot; site += kTailThreads) {
-    uint8_t x = c.final_argmax ? (uint8_t)((lg[2 * site] >= lg[2 * site + 1]) ? 0 : 1) : b.X[site];
+    uint8_t x = (!QARY && c.final_argmax) ? (uint8_t)((lg[2 * site] >= lg[2 * site + 1]) ? 0 : 1) : b.X[site];
     b.out_sym[site] = x;
-    if (c.final_argmax) b.X[site] = x;
-    if (b.out_logits) {
-      b.out_logits[2 * site] = lg[2 * site];
-      b.out_logits[2 * site + 1] = lg[2 * site + 1];
-    }
+    if (!QARY && c.final_argmax) b.X[site] = x;
+    if (b.out_logits)
+      for (int a = 0; a < Q; ++a) b.out_logits[(size_t)Q * site + a] = lg[(size_t)Q * site + a];
   }
   __syncthreads();
-  if (c.final_argmax) {
+  if (!QARY && c.final_argmax) {
     if (tid < kMaxK) s_syn[tid] = 0;
     __syncthreads();
     for (int idx = tid; idx < K * b.m; idx += kTailThreads) {
@@ -690,7 +721,10 @@ hipError_t launch_quality_head(const StepCtx& c, const EmbedW& m, const Work& w,
 }
 
 hipError_t launch_step_tail(const StepCtx& c, const Work& w, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_tail, dim3(c.num_bins), dim3(kTailThreads), 0, s, c, w.logits);
+  if (c.q > 2)
+    hipLaunchKernelGGL(k_step_tail<true>, dim3(c.num_bins), dim3(kTailThreads), 0, s, c, w.logits);
+  else
+    hipLaunchKernelGGL(k_step_tail<false>, dim3(c.num_bins), dim3(kTailThreads), 0, s, c, w.logits);
   return hipGetLastError();
 }
 

@@ -57,7 +57,7 @@ def weights_handle(cfg: synth.ModelCfg, seed: int, bias_std=0.0, ln_std=0.0):
     key = ("w", cfg, seed, bias_std, ln_std)
     if key not in _handles:
         blob = synth.make_weights(cfg, seed, bias_std=bias_std, ln_std=ln_std)
-        _handles[key] = (P.Weights(P.make_cfg(cfg.n_layers, cfg.d, cfg.heads, cfg.mlp_mult, cfg.n_max), blob),
+        _handles[key] = (P.Weights(P.make_cfg(cfg.n_layers, cfg.d, cfg.heads, cfg.mlp_mult, cfg.n_max, cfg.q), blob),
                          synth.unpack_weights(blob, cfg))
     return _handles[key]
 

@@ -40,11 +40,23 @@ def test_opts_defaults():
     assert np.allclose(list(o.remask_phi), [0.5, 0.25, 0.0, 0.0])
 
 
-@pytest.mark.parametrize("L,d,h", [(2, 64, 4), (4, 128, 8), (6, 256, 8), (8, 384, 12)])
-def test_blob_size_agrees_with_generator(L, d, h):
+@pytest.mark.parametrize("L,d,h,q", [(2, 64, 4, 2), (4, 128, 8, 2), (6, 256, 8, 2), (8, 384, 12, 2), (4, 128, 4, 64),
+                                     (1, 64, 4, 8)])
+def test_blob_size_agrees_with_generator(L, d, h, q):
     import paper_2605_26580_amd as P
-    cfg = synth.ModelCfg(L, d, h)
-    assert P.cider_weights_blob_floats(P.make_cfg(L, d, h)) == synth.weights.blob_size(cfg)
+    cfg = synth.ModelCfg(L, d, h, q=q)
+    assert P.cider_weights_blob_floats(P.make_cfg(L, d, h, q=q)) == synth.weights.blob_size(cfg)
+
+
+def test_bad_q_rejected_on_cpu():
+    import paper_2605_26580_amd as P
+    assert P.cider_weights_blob_floats(P.make_cfg(2, 64, 4, q=3)) == 0
+    assert P.cider_weights_blob_floats(P.make_cfg(2, 64, 4, q=128)) == 0
+    with pytest.raises(P.CiderError) as e:                                      # zero coefficient
+        P.CodeQ(4, 1, np.array([0, 3]), np.array([0, 1, 2]), np.array([1, 0, 5]), 3)
+    assert e.value.status == P.abi.CIDER_EINVAL
+    with pytest.raises(P.CiderError):                                           # degree above 16
+        P.CodeQ(32, 1, np.array([0, 17]), np.arange(17), np.ones(17), 3)
 
 
 def test_bad_model_and_code_rejected_on_cpu():

@@ -44,7 +44,7 @@ def _workload_batch(name):
     wl = synth.workload(name)
     cfg = wl.model
     blob = synth.make_weights(cfg, wl.weight_seed)
-    wh = P.Weights(P.make_cfg(cfg.n_layers, cfg.d, cfg.heads, cfg.mlp_mult, cfg.n_max), blob)
+    wh = P.Weights(P.make_cfg(cfg.n_layers, cfg.d, cfg.heads, cfg.mlp_mult, cfg.n_max, cfg.q), blob)
     w = synth.unpack_weights(blob, cfg)
     items = []
     if wl.ragged_K is not None:
