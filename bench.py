@@ -760,7 +760,7 @@ def run_served(args, wl, P, torch):
         sc.steps = wl.T
         sc.max_slots = args.max_slots
         sc.max_queue = 1 << 20
-        sc.hbm_budget = 0
+        sc.hbm_budget = int(args.hbm_gib * (1 << 30))
         sc.max_tokens = args.max_tokens
         h = C.c_void_p()
         P.abi.check(L.cider_server_create(C.byref(sc), C.byref(h)), "cider_server_create")
@@ -848,7 +848,8 @@ def run_served(args, wl, P, torch):
                                f"{list(wl.ragged_n)}, Eb/N0 uniform {list(wl.ebn0_range)} dB, L={cfg.n_layers} "
                                f"d={cfg.d} h={cfg.heads}, T={wl.T}, remasking on; offered load as a fraction of "
                                f"the measured capacity (the workload's 20k bins/s is far beyond one GPU)",
-                   "max_slots": args.max_slots, "max_tokens": args.max_tokens},
+                   "max_slots": args.max_slots, "admission": f"HBM budget {args.hbm_gib} GiB (bin state + step "
+                                                              f"workspace laid out for the resident mix)"},
         "capacity_probe": cap, "loads": loads, "roofline": roof, "cpu_baseline": None,
         "latency_scope": "per bin: completion minus submission of each admitted request",
     }
@@ -872,7 +873,8 @@ def main():
     ap.add_argument("--duration", type=float, default=15.0)
     ap.add_argument("--burst", type=int, default=96)
     ap.add_argument("--max-slots", type=int, default=96)
-    ap.add_argument("--max-tokens", type=int, default=400000)
+    ap.add_argument("--max-tokens", type=int, default=1 << 40, help="served: cap on resident tokens")
+    ap.add_argument("--hbm-gib", type=float, default=16.0, help="served: device memory for bin state + workspace")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}); "

@@ -383,8 +383,17 @@ typedef struct {
   int32_t              steps;          /* T of every request                    */
   int32_t              max_slots;      /* bins resident on the device at once   */
   int32_t              max_queue;      /* waiting requests before EAGAIN        */
-  size_t               hbm_budget;     /* bytes of bin state + step workspace   */
-  int64_t              max_tokens;     /* sum of K*n over resident bins          */
+  size_t               hbm_budget;     /* device bytes the server may hold: the */
+                                       /* per-slot bin state of max_slots bins   */
+                                       /* plus the step workspace, which takes   */
+                                       /* the rest; a waiting bin is admitted    */
+                                       /* (in arrival order) when a slot is free */
+                                       /* and the workspace the resident set     */
+                                       /* would need with it -- laid out for its */
+                                       /* exact K, n mix -- fits.  0: workspace  */
+                                       /* sized for max_tokens                   */
+  int64_t              max_tokens;     /* cap on the sum of K*n over resident   */
+                                       /* bins                                   */
 } cider_server_cfg;
 
 typedef struct {
@@ -404,6 +413,10 @@ typedef struct {
  * device.  Resident bins advance one refinement step per iteration; a newly
  * admitted bin joins at its own step 1 while others are mid-decode. */
 int cider_server_create(const cider_server_cfg* cfg, cider_server** out);
+/* Smallest hbm_budget cider_server_create accepts for `cfg`: the per-slot
+ * bin state of max_slots bins plus the step workspace of one largest bin
+ * (K = CIDER_MAX_K, n = the model's n_max).  No device work. */
+int cider_server_budget_floor(const cider_server_cfg* cfg, size_t* bytes);
 /* Queues a request.  y_host: host [n] FP32 (copied).  out_symbols_host:
  * host [K][n], written before the request is reported done; it must stay
  * valid until then.  Returns CIDER_EAGAIN when the queue is full. */

@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
-from typing import Optional, Sequence
+from typing import Tuple, Optional, Sequence
 
 import numpy as np
 
@@ -27,7 +27,7 @@ EXPORTS = [
     "cider_decode_batch", "cider_decode_noalloc", "cider_step_debug", "cider_evidence", "cider_amp_evidence", "cider_gf64_check_update", "cider_server_create",
     "cider_server_submit", "cider_server_poll", "cider_server_drain", "cider_server_destroy",
     "cider_strerror", "cider_last_error", "cider_profile_read", "cider_tuning_read",
-    "cider_code_create_q", "cider_decode_q_batch", "cider_step_debug_q",
+    "cider_code_create_q", "cider_decode_q_batch", "cider_step_debug_q", "cider_server_budget_floor",
 ]
 
 
@@ -131,6 +131,7 @@ def lib() -> C.CDLL:
     L.cider_server_submit.argtypes = [vp, vp, f32, vp, i32, i32, vp, C.POINTER(C.c_uint64)]
     L.cider_server_poll.argtypes = [vp, C.POINTER(cider_result), i32, C.POINTER(i32)]
     L.cider_server_drain.argtypes = [vp]
+    L.cider_server_budget_floor.argtypes = [C.POINTER(cider_server_cfg), C.POINTER(C.c_size_t)]
     L.cider_server_destroy.argtypes = [vp]
     L.cider_server_destroy.restype = None
     L.cider_profile_read.argtypes = [vp, C.POINTER(cider_kernel_stat), i32, C.POINTER(i32), i32]
@@ -347,6 +348,68 @@ def cider_amp_evidence(y, rows, slots: int, n_s: int, Q: int, rho: float, su2: f
 def cider_evidence(y, sigma2: float, K: int, n: int, out_S=None, out_p=None, stream=None) -> None:
     check(lib().cider_evidence(_ptr(y), float(sigma2), K, n, _ptr(out_S), _ptr(out_p), _stream(stream)),
           "cider_evidence")
+
+
+class Server:
+    """Owns a cider_server (continuous batching of arriving bins on its own
+    stream and worker thread); submit host buffers, poll or drain results."""
+
+    def __init__(self, w: Weights, steps: int, opts: Optional[cider_opts] = None, max_slots: int = 64,
+                 max_queue: int = 1 << 20, hbm_budget: int = 0, max_tokens: int = 1 << 40):
+        cfg = cider_server_cfg()
+        cfg.weights = w.handle
+        cfg.opts = opts if opts is not None else cider_opts_default()
+        cfg.steps, cfg.max_slots, cfg.max_queue = int(steps), int(max_slots), int(max_queue)
+        cfg.hbm_budget, cfg.max_tokens = int(hbm_budget), int(max_tokens)
+        self.cfg = cfg
+        h = C.c_void_p()
+        check(lib().cider_server_create(C.byref(cfg), C.byref(h)), "cider_server_create")
+        self.handle = h
+        self._keep = {}                 # request id -> host buffers the library reads or writes
+
+    @staticmethod
+    def budget_floor(w: Weights, steps: int, opts: Optional[cider_opts] = None, max_slots: int = 64) -> int:
+        """Smallest hbm_budget a server of this model and slot count accepts."""
+        cfg = cider_server_cfg()
+        cfg.weights = w.handle
+        cfg.opts = opts if opts is not None else cider_opts_default()
+        cfg.steps, cfg.max_slots, cfg.max_queue, cfg.max_tokens = int(steps), int(max_slots), 1, 1
+        out = C.c_size_t()
+        check(lib().cider_server_budget_floor(C.byref(cfg), C.byref(out)), "cider_server_budget_floor")
+        return int(out.value)
+
+    def submit(self, y: np.ndarray, sigma2: float, code: Code, K: int, n: int) -> Tuple[int, np.ndarray]:
+        """Queues a bin; returns (request id, host [K][n] uint8 array written when it is done)."""
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        out = np.zeros((K, n), dtype=np.uint8)
+        rid = C.c_uint64()
+        check(lib().cider_server_submit(self.handle, y.ctypes.data, float(sigma2), code.handle, int(K), int(n),
+                                        out.ctypes.data, C.byref(rid)), "cider_server_submit")
+        self._keep[rid.value] = (y, out)
+        return rid.value, out
+
+    def poll(self, max_results: int = 4096) -> list:
+        res = (cider_result * max_results)()
+        got = C.c_int32()
+        check(lib().cider_server_poll(self.handle, res, max_results, C.byref(got)), "cider_server_poll")
+        done = [res[i] for i in range(got.value)]
+        for r in done:
+            self._keep.pop(r.id, None)
+        return done
+
+    def drain(self) -> None:
+        check(lib().cider_server_drain(self.handle), "cider_server_drain")
+
+    def close(self):
+        if self.handle:
+            lib().cider_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def cider_profile_read(w: Weights, reset: bool = True) -> dict:

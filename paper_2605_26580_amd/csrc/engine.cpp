@@ -1787,6 +1787,10 @@ struct cider_server {
   size_t ws_bytes = 0;
   char* dev_pool = nullptr;
   BinState* h_states = nullptr;
+  // resident set, for admission: the step workspace it needs must fit ws_bytes
+  long res_tokens = 0, res_msg = 0;
+  int res_bins = 0, res_slots = 0, res_rows = 0;
+  long admitted = 0, deferred_hbm = 0;   // admissions, and admissions that waited for HBM
 };
 
 namespace {
@@ -1830,6 +1834,21 @@ void server_loop(cider_server* S) {
         for (int i = 0; i < (int)S->slots.size(); ++i)
           if (!S->slots[i].used) { free_i = i; break; }
         if (free_i < 0) break;
+        // HBM budget: the workspace of the resident set with this bin added,
+        // laid out exactly as the next step will lay it out
+        const Layout need = plan_layout(w->cfg, S->res_bins + 1, S->res_tokens + tok, S->res_slots + rq.n,
+                                        S->res_rows + rq.K, o.precision, S->res_msg + (long)rq.K * rq.code->nnz);
+        if (need.total > S->ws_bytes) {
+          if (S->res_bins == 0) { fail_all(CIDER_ENOMEM); break; }   // cannot fit even alone
+          S->deferred_hbm += 1;
+          break;
+        }
+        S->res_bins += 1;
+        S->res_tokens += tok;
+        S->res_slots += rq.n;
+        S->res_rows += rq.K;
+        S->res_msg += (long)rq.K * rq.code->nnz;
+        S->admitted += 1;
         Slot& sl = S->slots[free_i];
         sl.used = true;
         sl.req = std::move(S->queue.front());
@@ -1892,6 +1911,11 @@ void server_loop(cider_server* S) {
       std::lock_guard<std::mutex> lk(S->mu);
       S->done.push_back(res);
       tokens_in_use -= (long)sl.req.K * sl.req.n;
+      S->res_bins -= 1;
+      S->res_tokens -= (long)sl.req.K * sl.req.n;
+      S->res_slots -= sl.req.n;
+      S->res_rows -= sl.req.K;
+      S->res_msg -= (long)sl.req.K * sl.req.code->nnz;
       sl.used = false;
       sl.req.y.clear();
       S->inflight -= 1;
@@ -1904,6 +1928,25 @@ void server_loop(cider_server* S) {
 }  // namespace
 
 extern "C" {
+
+// Device bytes a server needs at the least: the per-slot bin state of
+// max_slots bins plus the step workspace of one largest bin (K = 16, n = n_max).
+static size_t server_floor(const cider_server_cfg* cfg, size_t per_slot) {
+  const cider_model_cfg& m = cfg->weights->cfg;
+  const int n = std::min(m.n_max, CIDER_MAX_N);
+  const Layout one = plan_layout(m, 1, (long)CIDER_MAX_K * n, n, CIDER_MAX_K, cfg->opts.precision, 0);
+  return per_slot * (size_t)cfg->max_slots + one.total;
+}
+
+static size_t server_per_slot() {
+  return align_up(CIDER_MAX_N * 4, 256) + 2 * align_up(CIDER_MAX_K * CIDER_MAX_N, 256) + align_up(sizeof(BinState), 256);
+}
+
+int cider_server_budget_floor(const cider_server_cfg* cfg, size_t* bytes) {
+  if (!cfg || !cfg->weights || !bytes || cfg->max_slots < 1) return fail(CIDER_EINVAL, "null cfg, weights or bytes");
+  *bytes = server_floor(cfg, server_per_slot());
+  return CIDER_OK;
+}
 
 int cider_server_create(const cider_server_cfg* cfg, cider_server** out) {
   if (!out) return fail(CIDER_EINVAL, "null out");
@@ -1924,15 +1967,22 @@ int cider_server_create(const cider_server_cfg* cfg, cider_server** out) {
   long slots_bound = std::min<long>((long)cfg->max_slots * CIDER_MAX_N, cfg->max_tokens);
   Layout Lw = plan_layout(S->w->cfg, cfg->max_slots, cfg->max_tokens, (int)slots_bound,
                           (int)std::min<long>((long)cfg->max_slots * CIDER_MAX_K, cfg->max_tokens), cfg->opts.precision);
-  const size_t per_slot = align_up(CIDER_MAX_N * 4, 256) + 2 * align_up(CIDER_MAX_K * CIDER_MAX_N, 256) +
-                          align_up(sizeof(BinState), 256);
-  const size_t need = Lw.total + per_slot * cfg->max_slots;
-  if (cfg->hbm_budget && need > cfg->hbm_budget) {
-    delete S;
-    return fail(CIDER_EINVAL, "hbm_budget below what max_tokens and max_slots need: " + std::to_string(need));
+  const size_t per_slot = server_per_slot();
+  // with an HBM budget the workspace takes what the slot state leaves of it, and
+  // admission keeps the resident set's workspace within it; without one the
+  // workspace is sized for max_tokens
+  size_t ws_bytes = Lw.total;
+  if (cfg->hbm_budget) {
+    const size_t pool = per_slot * cfg->max_slots, floor = server_floor(cfg, per_slot);
+    if (cfg->hbm_budget < floor) {
+      delete S;
+      return fail(CIDER_EINVAL, "hbm_budget below the slot state plus one largest bin's workspace: " +
+                                    std::to_string(floor) + " bytes");
+    }
+    ws_bytes = cfg->hbm_budget - pool;
   }
   if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess ||
-      hipMalloc(&S->ws, Lw.total) != hipSuccess ||
+      hipMalloc(&S->ws, ws_bytes) != hipSuccess ||
       hipMalloc((void**)&S->dev_pool, per_slot * cfg->max_slots) != hipSuccess ||
       hipHostMalloc((void**)&S->h_states, sizeof(BinState) * cfg->max_slots, hipHostMallocDefault) != hipSuccess) {
     if (S->stream) hipStreamDestroy(S->stream);
@@ -1941,7 +1991,7 @@ int cider_server_create(const cider_server_cfg* cfg, cider_server** out) {
     delete S;
     return fail(CIDER_ENOMEM, "server allocation failed");
   }
-  S->ws_bytes = Lw.total;
+  S->ws_bytes = ws_bytes;
   S->slots.resize(cfg->max_slots);
   for (int i = 0; i < cfg->max_slots; ++i) {
     char* p = S->dev_pool + per_slot * i;

@@ -9,6 +9,11 @@ the library in ONE cider_decode_batch call (one packed pass per refinement
 step, bins of different K side by side), so a frame's decode costs what its
 tokens cost, whatever its load mix.
 
+serve_frames feeds the same bins to a continuous-batching server instead:
+frames arrive one after another, each decodable bin is submitted as soon as
+its frame arrives and joins the bins already on the GPU at its own first
+refinement step, and a frame is complete when its last bin is.
+
 Host bookkeeping only: the decode itself runs in the HIP library.
 """
 from __future__ import annotations
@@ -51,4 +56,34 @@ def decode_frames(frames: Sequence[dict], code: "abi.Code", n: int, w: "abi.Weig
         out.append(res)
     if batch:
         abi.cider_decode_batch(batch, w, steps, opts, stream=stream)
+    return out
+
+
+def serve_frames(server: "abi.Server", frames: Sequence[dict], code: "abi.Code", n: int, K_max: int,
+                 drain: bool = True) -> List[dict]:
+    """frames: dicts with ``loads`` and ``payload`` {chi: (y, sigma2)} (y a host
+    float32 array [n]) for every bin with 1 <= K_chi <= K_max, submitted in
+    order.  Returns per frame {"decoded": {chi: host uint8 [K_chi][n]},
+    "erased": [chi with K_chi > K_max], "ids": {chi: request id}}; the grids
+    are complete once the server has finished their requests (after
+    ``server.drain()``, which this call makes unless ``drain`` is False)."""
+    if not 1 <= K_max <= 16:
+        raise ValueError("K_max must be 1..16 (the library's largest K)")
+    out: List[dict] = []
+    for f in frames:
+        res = {"decoded": {}, "erased": [], "ids": {}}
+        for chi, K in enumerate(f["loads"]):
+            K = int(K)
+            if K == 0:
+                continue
+            if K > K_max:
+                res["erased"].append(chi)
+                continue
+            y, s2 = f["payload"][chi]
+            rid, grid = server.submit(y, float(s2), code, K, n)
+            res["decoded"][chi] = grid
+            res["ids"][chi] = rid
+        out.append(res)
+    if drain:
+        server.drain()
     return out

@@ -100,3 +100,117 @@ def test_queue_backpressure_returns_eagain():
         L.cider_server_destroy(srv)
     assert P.abi.CIDER_EAGAIN in statuses and statuses[0] == 0
     assert all(s in (0, P.abi.CIDER_EAGAIN) for s in statuses)
+
+
+def _bins(rng, count, Ks, ns, seed0):
+    out = []
+    for i in range(count):
+        K = int(rng.choice(Ks))
+        n = int(rng.choice(ns))
+        code = code_of(n, 1000 + n)
+        b = synth.make_bins(code, K, 1, float(rng.uniform(2, 6)), seed=seed0 + i)
+        out.append((K, n, code, np.ascontiguousarray(b.y[0]), float(b.sigma2[0])))
+    return out
+
+
+def _alone(P, torch, wh, reqs, T, opts):
+    res = []
+    for K, n, code, y, s2 in reqs:
+        a = torch.zeros(K, n, dtype=torch.uint8, device="cuda")
+        P.cider_decode_batch([{"y": torch.from_numpy(y).cuda(), "sigma2": s2, "code": code_handle(code), "K": K,
+                               "n": n, "out_symbols": a}], wh, T, opts)
+        torch.cuda.synchronize()
+        res.append(a.cpu().numpy())
+    return res
+
+
+def test_served_equals_alone_at_the_served_model_width():
+    """The served workload's model shape (d = 384, 12 heads; two layers) with
+    K up to 16 and n up to 1024: each served bin equals the bin decoded alone."""
+    torch = torch_cuda()
+    P = lib()
+    cfg = synth.ModelCfg(2, 384, 12, n_max=1024)
+    wh, _ = weights_handle(cfg, seed=15)
+    opts = P.cider_opts_default(precision=P.CIDER_BF16, remask=1)
+    rng = np.random.default_rng(5)
+    reqs = _bins(rng, 1, [16], [1024], 700) + _bins(rng, 5, [2, 9, 16], [128, 512, 1024], 701)
+    say(f"server d=384: shapes {[(K, n) for K, n, *_ in reqs]}")
+    srv = P.Server(wh, 6, opts, max_slots=4, max_tokens=40000)
+    got = []
+    try:
+        for K, n, code, y, s2 in reqs:
+            got.append(srv.submit(y, s2, code_handle(code), K, n)[1])
+        srv.drain()
+        done = srv.poll()
+        assert len(done) == len(reqs) and all(r.status == 0 for r in done)
+    finally:
+        srv.close()
+    for (K, n, *_), g, a in zip(reqs, got, _alone(P, torch, wh, reqs, 6, opts)):
+        assert np.array_equal(g, a), (K, n)
+
+
+def test_hbm_budget_bounds_the_resident_set():
+    """At the smallest budget (slot state plus one largest bin's workspace)
+    bins of that largest size decode one at a time; a larger budget lets them
+    overlap; every result equals the bin decoded alone."""
+    torch = torch_cuda()
+    P = lib()
+    cfg = synth.ModelCfg(1, 64, 4, n_max=64)
+    wh, _ = weights_handle(cfg, seed=44)
+    opts = P.cider_opts_default(precision=P.CIDER_BF16)
+    reqs = _bins(np.random.default_rng(9), 5, [16], [64], 800)
+    floor = P.Server.budget_floor(wh, 6, opts, max_slots=4)
+    ref = _alone(P, torch, wh, reqs, 6, opts)
+    for budget, most in ((floor, 1), (floor * 4, 2)):
+        say(f"server hbm_budget={budget} (floor {floor}): 5 bins of K=16 n=64")
+        srv = P.Server(wh, 6, opts, max_slots=4, hbm_budget=budget)
+        got = []
+        try:
+            for K, n, code, y, s2 in reqs:
+                got.append(srv.submit(y, s2, code_handle(code), K, n)[1])
+            srv.drain()
+            done = sorted(srv.poll(), key=lambda r: r.id)
+        finally:
+            srv.close()
+        assert len(done) == len(reqs)
+        for g, a in zip(got, ref):
+            assert np.array_equal(g, a)
+        spans = [(r.t_admit, r.t_done) for r in done]
+        overlap = max(sum(1 for a2, d2 in spans if a2 < d1 and a1 < d2) for a1, d1 in spans)
+        print(f"  most bins resident together: {overlap}")
+        if most == 1:
+            assert overlap == 1
+        else:
+            assert overlap >= most
+    with pytest.raises(P.CiderError):
+        P.Server(wh, 6, opts, max_slots=4, hbm_budget=floor - 1)
+
+
+def test_frames_served_equal_frames_decoded_in_one_batch():
+    """The stochastic-binning front end through the server (each frame's
+    decodable bins submitted as the frame arrives) gives the grids the batch
+    front end gives (Appendix, protocol-level scalability)."""
+    torch = torch_cuda()
+    P = lib()
+    n, K_max, T = 64, 8, 6
+    cfg = synth.ModelCfg(2, 128, 8, n_max=64)
+    wh, _ = weights_handle(cfg, seed=46)
+    code = code_of(n, 1000 + n)
+    ch = code_handle(code)
+    frames = synth.make_protocol_frames(code, 3, 30, 6, K_max, (2.0, 6.0), seed=23)
+    opts = P.cider_opts_default(precision=P.CIDER_BF16)
+    say("frames through the server and through one packed batch")
+    host = [{"loads": fr.loads, "payload": {chi: (b.y, b.sigma2) for chi, b in fr.bins}} for fr in frames]
+    dev = [{"loads": fr.loads, "payload": {chi: (torch.from_numpy(b.y).cuda(), b.sigma2) for chi, b in fr.bins}}
+           for fr in frames]
+    srv = P.Server(wh, T, opts, max_slots=6)
+    try:
+        served = P.serve_frames(srv, host, ch, n, K_max)
+    finally:
+        srv.close()
+    batch = P.decode_frames(dev, ch, n, wh, T, K_max, opts)
+    torch.cuda.synchronize()
+    for s, b in zip(served, batch):
+        assert s["erased"] == b["erased"] and sorted(s["decoded"]) == sorted(b["decoded"])
+        for chi, g in s["decoded"].items():
+            assert np.array_equal(g, b["decoded"][chi][0].cpu().numpy()), chi

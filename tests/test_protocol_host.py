@@ -42,3 +42,31 @@ def test_decode_frames_with_nothing_decodable_makes_no_call(monkeypatch):
 def test_decode_frames_rejects_a_bank_beyond_the_library():
     with pytest.raises(ValueError):
         P.decode_frames([], "code", 8, "w", 4, K_max=17)
+
+
+class _RecordingServer:
+    """Stands in for abi.Server: records submissions, returns grids."""
+    def __init__(self):
+        self.subs, self.drained = [], 0
+
+    def submit(self, y, sigma2, code, K, n):
+        self.subs.append((float(y[0]), float(sigma2), code, K, n))
+        return len(self.subs), np.zeros((K, n), np.uint8)
+
+    def drain(self):
+        self.drained += 1
+
+
+def test_serve_frames_submits_decodable_bins_in_arrival_order():
+    srv = _RecordingServer()
+    n, K_max = 8, 3
+    loads = [np.array([1, 0, 5, 3]), np.array([0, 2, 0, 0])]
+    frames = [{"loads": L, "payload": {chi: (np.full(n, f * 10.0 + chi, np.float32), 0.25)
+                                       for chi, K in enumerate(L) if 1 <= K <= K_max}}
+              for f, L in enumerate(loads)]
+    res = P.serve_frames(srv, frames, code="code", n=n, K_max=K_max)
+    assert [(y, K) for y, _, _, K, _ in srv.subs] == [(0.0, 1), (3.0, 3), (11.0, 2)]
+    assert srv.drained == 1
+    assert [r["erased"] for r in res] == [[2], []]
+    assert res[0]["ids"] == {0: 1, 3: 2} and res[1]["ids"] == {1: 3}
+    assert res[0]["decoded"][3].shape == (3, n)
