@@ -17,7 +17,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libcider.so")
 
 CIDER_OK, CIDER_EINVAL, CIDER_ENOMEM, CIDER_EDEVICE, CIDER_EUNSUPPORTED, CIDER_EAGAIN = 0, -1, -2, -3, -4, -5
-CIDER_FP32, CIDER_BF16, CIDER_FP8 = 0, 1, 2
+CIDER_FP32, CIDER_BF16, CIDER_FP8, CIDER_FP64 = 0, 1, 2, 3
 CIDER_SCHED_LINEAR, CIDER_SCHED_COSINE = 0, 1
 CIDER_MASK = 2
 
@@ -355,7 +355,7 @@ class Server:
     stream and worker thread); submit host buffers, poll or drain results."""
 
     def __init__(self, w: Weights, steps: int, opts: Optional[cider_opts] = None, max_slots: int = 64,
-                 max_queue: int = 1 << 20, hbm_budget: int = 0, max_tokens: int = 1 << 40):
+                 max_queue: int = 1 << 20, hbm_budget: int = 0, max_tokens: int = 1 << 18):
         cfg = cider_server_cfg()
         cfg.weights = w.handle
         cfg.opts = opts if opts is not None else cider_opts_default()

@@ -19,7 +19,7 @@ OBJDIR = os.path.join(PKG, "_build")
 
 SOURCES = ["engine.cpp", "kernels_misc.hip", "kernels_gemm.hip", "kernels_attn.hip", "kernels_fast.hip",
            "kernels_block.hip", "kernels_mlp.hip", "kernels_amp.hip", "kernels_gf.hip",
-           "kernels_qary.hip"]
+           "kernels_qary.hip", "kernels_f64.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-x", "hip", "-ffp-contract=off",

@@ -153,6 +153,42 @@ struct Work {
   float* S;        // [slots][2] per-slot log evidence
 };
 
+// ---- FP64 precision mode (kernels_f64.hip) --------------------------------
+constexpr int kFP64 = 3;
+struct DevLayer64 {
+  const double *ln1_g, *ln1_b, *Wqkv_r, *bqkv_r, *Wo_r, *bo_r;
+  const double *ln2_g, *ln2_b, *Wqkv_u, *bqkv_u, *Wo_u, *bo_u;
+  const double *ln3_g, *ln3_b, *W1, *b1, *W2, *b2;
+};
+// Double copies of every parameter of the model.
+struct DevModel64 {
+  const double *E, *P, *u, *W, *v, *Wg1, *bg1, *Wg2, *bg2, *lnf_g, *lnf_b;
+  DevLayer64 layer[64];
+};
+// out = epi(A W^T + bias) in double: Store / GELU into out, residual add into
+// R, or the gate blend R = g R + (1 - g) E with g = sigmoid(.).
+struct Gemm64 {
+  long M;
+  int N, Kd;
+  const double* A;
+  const double* bias;
+  double* out;
+  double* R;
+  const double* E;
+};
+hipError_t launch_evidence64(const StepCtx& c, double* p, hipStream_t s);
+hipError_t launch_embed_demix64(const StepCtx& c, const DevModel64& m, int d, double* R, double* E, double* ZE,
+                                const double* p, hipStream_t s);
+hipError_t launch_gemm64(int epi, const Gemm64& g, const double* W, hipStream_t s);
+hipError_t launch_layernorm64(long T, int d, const double* R, const double* g, const double* b, double* out,
+                              hipStream_t s);
+hipError_t launch_row_attn64(const StepCtx& c, const double* QKV, double* O, int d, int heads, int max_n,
+                             hipStream_t s);
+hipError_t launch_user_attn64(const StepCtx& c, const double* QKV, double* O, int d, int heads, hipStream_t s);
+hipError_t launch_final_proj64(long T, int d, const DevModel64& m, const double* R, double* lbar, hipStream_t s);
+hipError_t launch_module_b64(const StepCtx& c, const double* lbar, double* logits, hipStream_t s);
+hipError_t launch_step_tail64(const StepCtx& c, const double* logits, hipStream_t s);
+
 // ---- GF(Q) path (kernels_qary.hip) ---------------------------------------
 constexpr int kQaryMaxDeg = 16;   // check degree bound of the GF(Q) Module B
 // p = softmax_a S per slot ([slots][Q])

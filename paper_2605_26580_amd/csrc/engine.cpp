@@ -32,6 +32,9 @@ void set_err(const char* what, const char* detail = nullptr) {
 
 int fail(int code, const char* msg) {
   set_err(msg);
+  // a refused allocation leaves HIP's last-error state set; clear it so that
+  // the next launch's error check does not report it again
+  if (code == CIDER_ENOMEM) (void)hipGetLastError();
   return code;
 }
 
@@ -151,6 +154,7 @@ struct cider_weights {
   int device = 0;
   std::vector<void*> allocs;
   DevModel dm{};
+  DevModel64 dm64{};            // double copies (FP64 precision mode)
   EmbedW ew{};
   std::mutex mu;
   void* ws = nullptr;
@@ -228,7 +232,7 @@ struct Layout {
       off_bins, off_state, off_slot, off_row, off_X, off_XN, off_XN8, off_xscale, off_msg, off_rank, off_sym, total;
 };
 
-size_t esize(int prec) { return prec == CIDER_FP32 ? 4 : 2; }
+size_t esize(int prec) { return prec == kFP64 ? 8 : prec == CIDER_FP32 ? 4 : 2; }
 
 // msg: GF(Q) check messages (sum over bins of K nnz), in units of Q floats.
 Layout plan_layout(const cider_model_cfg& cfg, int num_bins, long T, int slots, int rows, int prec, long msg = 0) {
@@ -241,8 +245,9 @@ Layout plan_layout(const cider_model_cfg& cfg, int num_bins, long T, int slots, 
   const size_t Q = cfg.q > 2 ? (size_t)cfg.q : 2;
   L.q = (int)Q;
   auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
-  L.off_R = take(T * d * 4);
-  L.off_E = take(T * d * 4);
+  const size_t fs = prec == kFP64 ? 8 : 4;   // the FP32 buffers hold doubles in the FP64 mode
+  L.off_R = take(T * d * fs);
+  L.off_E = take(T * d * fs);
   L.off_ZE = take(T * 2 * d * es);
   L.off_H1 = take(T * d * es);
   L.off_XN = take(T * d * es);
@@ -251,11 +256,11 @@ Layout plan_layout(const cider_model_cfg& cfg, int num_bins, long T, int slots, 
   L.off_QKV = take(T * 3 * d * es);
   L.off_O = take(T * d * es);
   L.off_HID = take(T * F * es);
-  L.off_lbar = take(T * Q * 4);
-  L.off_logits = take(T * Q * 4);
+  L.off_lbar = take(T * Q * fs);
+  L.off_logits = take(T * Q * fs);
   L.off_qw = take(T * 4);
-  L.off_p = take((size_t)slots * Q * 4);
-  L.off_S = take((size_t)slots * Q * 4);
+  L.off_p = take((size_t)slots * Q * fs);
+  L.off_S = take((size_t)slots * Q * fs);
   L.off_msg = take(Q > 2 ? (size_t)msg * Q * 4 : 0);
   L.off_rank = take(Q > 2 ? T * 4 : 0);
   L.off_sym = take(Q > 2 ? T : 0);
@@ -417,7 +422,51 @@ int tune_gemm(cider_weights* w, const char* role, int epi, const GemmArgs& g, co
 // One denoiser forward over every bin of the batch, then Module B.
 // GEMM operands are in the compute type (BF16 on the fast path), LayerNorms
 // write a normalised copy XN, and the residual stream R stays FP32.
+// The FP64 mode: the plain sequence of kernels in double (embedding and
+// Module A, the gate GEMMs, per layer LayerNorm + QKV GEMM + attention +
+// output GEMM twice and LayerNorm + MLP GEMMs, final projection, Module B).
+int enqueue_forward64(cider_weights* w, const Run& r, hipStream_t s) {
+  const DevModel64& M = w->dm64;
+  const StepCtx& c = r.ctx;
+  const Work& k = r.work;
+  const long T = c.total_tokens;
+  const int d = w->cfg.d, F = w->cfg.mlp_mult * w->cfg.d, h = w->cfg.heads;
+  double* R = (double*)k.R;
+  double* E = (double*)k.Ebuf;
+  double* ZE = (double*)k.ZE;
+  double* H1 = (double*)k.H1;
+  double* XN = (double*)k.XN;
+  double* QKV = (double*)k.QKV;
+  double* O = (double*)k.O;
+  double* HID = (double*)k.HID;
+  auto gemm = [&](int epi, int N, int Kd, const double* A, const double* bias, double* out, const double* W) {
+    Gemm64 g{T, N, Kd, A, bias, out, R, E};
+    return launch_gemm64(epi, g, W, s);
+  };
+  TIMED("embed_demix", launch_embed_demix64(c, M, d, R, E, ZE, (const double*)k.p, s));
+  TIMED("gemm_gate1", gemm(kEpiGelu, d, 2 * d, ZE, M.bg1, H1, M.Wg1));
+  TIMED("gemm_gate2", gemm(kEpiGate, d, d, H1, M.bg2, nullptr, M.Wg2));
+  for (int l = 0; l < w->cfg.n_layers; ++l) {
+    const DevLayer64& L = M.layer[l];
+    TIMED("layernorm", launch_layernorm64(T, d, R, L.ln1_g, L.ln1_b, XN, s));
+    TIMED("gemm_qkv_row", gemm(kEpiStore, 3 * d, d, XN, L.bqkv_r, QKV, L.Wqkv_r));
+    TIMED("attn_row", launch_row_attn64(c, QKV, O, d, h, c.max_n, s));
+    TIMED("gemm_o_row", gemm(kEpiResid, d, d, O, L.bo_r, nullptr, L.Wo_r));
+    TIMED("layernorm", launch_layernorm64(T, d, R, L.ln2_g, L.ln2_b, XN, s));
+    TIMED("gemm_qkv_user", gemm(kEpiStore, 3 * d, d, XN, L.bqkv_u, QKV, L.Wqkv_u));
+    TIMED("attn_user", launch_user_attn64(c, QKV, O, d, h, s));
+    TIMED("gemm_o_user", gemm(kEpiResid, d, d, O, L.bo_u, nullptr, L.Wo_u));
+    TIMED("layernorm", launch_layernorm64(T, d, R, L.ln3_g, L.ln3_b, XN, s));
+    TIMED("gemm_mlp_up", gemm(kEpiGelu, F, d, XN, L.b1, HID, L.W1));
+    TIMED("gemm_mlp_down", gemm(kEpiResid, d, F, HID, L.b2, nullptr, L.W2));
+  }
+  TIMED("final_proj", launch_final_proj64(T, d, M, R, (double*)k.lbar, s));
+  TIMED("module_b", launch_module_b64(c, (const double*)k.lbar, (double*)k.logits, s));
+  return CIDER_OK;
+}
+
 int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
+  if (r.prec == kFP64) return enqueue_forward64(w, r, s);
   const DevModel& m = w->dm;
   const StepCtx& c = r.ctx;
   const Work& k = r.work;
@@ -668,7 +717,7 @@ int tune_mlp(cider_weights* w, const GemmArgs& g, const DevLayer& L, int F, hipS
 
 // Tunes every GEMM shape of the forward for this batch size (BF16 only).
 int autotune_forward(cider_weights* w, const Run& r, hipStream_t s) {
-  if (r.prec == kF32) return CIDER_OK;
+  if (r.prec == kF32 || r.prec == kFP64) return CIDER_OK;
   const DevModel& m = w->dm;
   const Work& k = r.work;
   const long T = r.ctx.total_tokens;
@@ -700,7 +749,8 @@ int enqueue_step(cider_weights* w, const Run& r, hipStream_t s) {
   if (rc) return rc;
   if (r.ctx.qhead) TIMED("quality_head", launch_quality_head(r.ctx, w->ew, r.work, s));
   if (r.ctx.q > 2) TIMED("site_key", launch_site_key_q(r.ctx, r.work, s));
-  TIMED("step_tail", launch_step_tail(r.ctx, r.work, s));
+  if (r.prec == kFP64) TIMED("step_tail", launch_step_tail64(r.ctx, (const double*)r.work.logits, s));
+  else TIMED("step_tail", launch_step_tail(r.ctx, r.work, s));
   return CIDER_OK;
 }
 
@@ -756,7 +806,7 @@ struct BinIn {
 };
 
 int check_opts(const cider_opts& o) {
-  if (o.precision < 0 || o.precision > 2) return fail(CIDER_EINVAL, "precision must be 0..2");
+  if (o.precision < 0 || o.precision > 3) return fail(CIDER_EINVAL, "precision must be 0..3");
   if (o.schedule != CIDER_SCHED_LINEAR && o.schedule != CIDER_SCHED_COSINE)
     return fail(CIDER_EINVAL, "unknown schedule");
   if (o.remask_max_rounds < 0 || o.remask_max_rounds > 16) return fail(CIDER_EINVAL, "remask_max_rounds 0..16");
@@ -775,6 +825,8 @@ int check_opts(const cider_opts& o) {
 }
 
 int check_prec(const cider_weights* w, const cider_opts& o) {
+  if (o.precision == kFP64 && (w->cfg.q > 2 || o.qhead))
+    return fail(CIDER_EUNSUPPORTED, "the FP64 mode covers the binary path without the quality head");
   if (w->cfg.q > 2) {
     if (o.precision == CIDER_FP8) return fail(CIDER_EUNSUPPORTED, "GF(Q) decoding runs in FP32 or BF16");
     if (o.remask || o.qhead) return fail(CIDER_EUNSUPPORTED, "GF(Q) decoding has no remasking");
@@ -980,6 +1032,7 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
   const StepCtx& c = r->ctx;
   const Work& k = r->work;
   if (c.q > 2) HIPCHK(launch_evidence_q(c, k.p, s));
+  else if (o.precision == kFP64) HIPCHK(launch_evidence64(c, (double*)k.p, s));
   else HIPCHK(launch_evidence(c, k.S, k.p, s));
   if (init_grids) {
     HIPCHK(launch_init_bins(c, steps, o.first_reveal, s));
@@ -1368,6 +1421,32 @@ int cider_weights_create(const cider_model_cfg* cfg, const float* blob, size_t n
     m.ug = (const float*)dug;
   }
   w->ew = EmbedW{d, m.E, m.P, m.u, m.W, m.v, m.lnf_g, m.lnf_b, m.q};
+  {
+    // double copies for the FP64 mode, at the FP32 blob's offsets
+    std::vector<double> h64(blob, blob + n_floats);
+    double* d64 = nullptr;
+    if (hipMalloc(&d64, n_floats * 8) != hipSuccess) { rc = fail(CIDER_ENOMEM, "weights hipMalloc"); goto bad; }
+    w->allocs.push_back(d64);
+    if (hipMemcpy(d64, h64.data(), n_floats * 8, hipMemcpyHostToDevice) != hipSuccess) {
+      rc = fail(CIDER_EDEVICE, "weights copy");
+      goto bad;
+    }
+    auto to64 = [&](const float* p) { return (const double*)(d64 + (p - dblob)); };
+    DevModel64& M = w->dm64;
+    M.E = to64(m.E); M.P = to64(m.P); M.u = to64(m.u); M.W = to64(m.W); M.v = to64(m.v);
+    M.Wg1 = to64(m.Wg1.f32); M.bg1 = to64(m.bg1); M.Wg2 = to64(m.Wg2.f32); M.bg2 = to64(m.bg2);
+    M.lnf_g = to64(m.lnf_g); M.lnf_b = to64(m.lnf_b);
+    for (int l = 0; l < cfg->n_layers; ++l) {
+      const DevLayer& L = m.layer[l];
+      DevLayer64& X = M.layer[l];
+      X.ln1_g = to64(L.ln1_g); X.ln1_b = to64(L.ln1_b); X.Wqkv_r = to64(L.Wqkv_r.f32); X.bqkv_r = to64(L.bqkv_r);
+      X.Wo_r = to64(L.Wo_r.f32); X.bo_r = to64(L.bo_r);
+      X.ln2_g = to64(L.ln2_g); X.ln2_b = to64(L.ln2_b); X.Wqkv_u = to64(L.Wqkv_u.f32); X.bqkv_u = to64(L.bqkv_u);
+      X.Wo_u = to64(L.Wo_u.f32); X.bo_u = to64(L.bo_u);
+      X.ln3_g = to64(L.ln3_g); X.ln3_b = to64(L.ln3_b); X.W1 = to64(L.W1.f32); X.b1 = to64(L.b1);
+      X.W2 = to64(L.W2.f32); X.b2 = to64(L.b2);
+    }
+  }
   *out = w;
   return CIDER_OK;
 bad:
@@ -1615,12 +1694,13 @@ int cider_step_debug(const uint8_t* X_in, uint8_t* X_out, const float* y, float 
   r.ctx.first_override = first ? 1 : 0;
   rc = enqueue_forward(w, r, s);
   if (rc) return rc;
-  const size_t T = (size_t)K * n;
-  if (out_lbar) HIPCHK(hipMemcpyAsync(out_lbar, r.work.lbar, T * 8, hipMemcpyDeviceToDevice, s));
-  if (out_logits) HIPCHK(hipMemcpyAsync(out_logits, r.work.logits, T * 8, hipMemcpyDeviceToDevice, s));
-  if (out_z) HIPCHK(hipMemcpyAsync(out_z, r.work.R, T * w->cfg.d * 4, hipMemcpyDeviceToDevice, s));
+  const size_t T = (size_t)K * n, fs = o.precision == kFP64 ? 8 : 4;
+  if (out_lbar) HIPCHK(hipMemcpyAsync(out_lbar, r.work.lbar, T * 2 * fs, hipMemcpyDeviceToDevice, s));
+  if (out_logits) HIPCHK(hipMemcpyAsync(out_logits, r.work.logits, T * 2 * fs, hipMemcpyDeviceToDevice, s));
+  if (out_z) HIPCHK(hipMemcpyAsync(out_z, r.work.R, T * w->cfg.d * fs, hipMemcpyDeviceToDevice, s));
   if (X_out) {
-    HIPCHK(launch_step_tail(r.ctx, r.work, s));
+    if (o.precision == kFP64) HIPCHK(launch_step_tail64(r.ctx, (const double*)r.work.logits, s));
+    else HIPCHK(launch_step_tail(r.ctx, r.work, s));
     HIPCHK(hipMemcpyAsync(X_out, Xw, T, hipMemcpyDeviceToDevice, s));
   }
   return CIDER_OK;

@@ -63,7 +63,8 @@ def _logit_error(prec, wl, cfg, wh, w, code, ch, bins):
     of eight bins at four mask fractions."""
     torch = torch_cuda()
     P = lib()
-    opts = P.cider_opts_default(precision=prec_id(prec))
+    opts = P.cider_opts_default(precision=P.CIDER_FP64 if prec == "fp64" else prec_id(prec))
+    fdt = torch.float64 if prec == "fp64" else torch.float32
     rng = np.random.default_rng(2024)
     K, n = wl.K, wl.n
     err = 0.0
@@ -73,9 +74,9 @@ def _logit_error(prec, wl, cfg, wh, w, code, ch, bins):
         for frac in (1.0, 0.75, 0.5, 0.25):
             X = rng.integers(0, 2, size=(K, n)).astype(np.uint8)
             X[rng.random((K, n)) < frac] = 2
-            gamma = float((X == 2).mean())
+            gamma = float(np.float32((X == 2).mean()))
             ref = denoise(X, p, code, w, cfg.n_layers, cfg.heads, gamma)["logits"]
-            lg = torch.zeros(K, n, 2, dtype=torch.float32, device="cuda")
+            lg = torch.zeros(K, n, 2, dtype=fdt, device="cuda")
             P.cider_step_debug(torch.from_numpy(X).cuda(), None, torch.from_numpy(y).cuda(), s2, ch, K, n, wh,
                                gamma, 0, 0, opts, out_logits=lg)
             torch.cuda.synchronize()
@@ -136,3 +137,23 @@ def test_c2_fp32_plain_agreement_over_stored_oracle_grids():
     torch.cuda.synchronize()
     same, decidable = _report("fp32 plain", out.cpu().numpy(), X, rel_gap, err)
     assert decidable.sum() >= B // 2, "FP32 should resolve most bins' decisions"
+
+
+def test_c2_fp64_batched_agreement_over_stored_oracle_grids():
+    """The FP64 mode in the benchmark's launch configuration: every stored bin
+    is decidable at its error, and every one must equal the oracle's grid."""
+    torch = torch_cuda()
+    P = lib()
+    wl, cfg, wh, w, code, ch, bins, X, rel_gap = _setup()
+    B, K, n = X.shape
+    err = _logit_error("fp64", wl, cfg, wh, w, code, ch, bins)
+    say(f"c2 FP64 batched over {B} stored oracle grids, 256 bins per call, graph replay")
+    opts = P.cider_opts_default(precision=P.CIDER_FP64, use_graph=1)
+    y = torch.from_numpy(bins.y).cuda()
+    out = torch.full((B, K, n), 9, dtype=torch.uint8, device="cuda")
+    for b0 in range(0, B, 256):
+        P.cider_decode_batch([{"y": y[b], "sigma2": float(bins.sigma2[b]), "code": ch, "K": K, "n": n,
+                               "out_symbols": out[b]} for b in range(b0, min(B, b0 + 256))], wh, wl.T, opts)
+    torch.cuda.synchronize()
+    same, decidable = _report("fp64 batched", out.cpu().numpy(), X, rel_gap, err)
+    assert decidable.all() and same.all()

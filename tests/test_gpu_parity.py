@@ -432,3 +432,45 @@ def test_fp8_rejects_narrow_models():
 def test_free_running_fp8_reports_match():
     match, safe, B = _free_running("fp8", 4, 128, 2, 128, 8, 16, 8, min_gap=1.0)
     print(f"  fp8 exact-grid bins {match}/{B}")
+
+
+@pytest.mark.parametrize("K,n,L,d,h", [(2, 32, 2, 64, 4), (4, 128, 2, 128, 8), (3, 100, 1, 256, 8),
+                                       (9, 20, 1, 128, 8), (2, 128, 1, 384, 12)])
+def test_teacher_forced_step_fp64(K, n, L, d, h):
+    """The FP64 mode's step: logits before and after Module B and the residual
+    stream within 1e-11 of the oracle relative to max(1, |oracle|) (double
+    rounding in a different summation order), and the reveal equal to the
+    oracle's wherever its decisions are farther than 1e-9 from a tie."""
+    torch = torch_cuda()
+    P = lib()
+    cfg = synth.ModelCfg(L, d, h, n_max=max(n, 64))
+    wh, w = weights_handle(cfg, seed=21 + L + d, bias_std=0.02, ln_std=0.05)
+    code = code_of(n, 1000 + n)
+    ch = code_handle(code)
+    bins = synth.make_bins(code, K, 1, 4.0, seed=5 + K)
+    y, s2 = bins.y[0], float(bins.sigma2[0])
+    _, p = evidence(y.astype(np.float64), s2, K)
+    rng = np.random.default_rng(K * 7 + n)
+    opts = P.cider_opts_default(precision=P.CIDER_FP64)
+    for frac in (1.0, 0.6, 0.1):
+        X = rng.integers(0, 2, size=(K, n)).astype(np.uint8)
+        X[rng.random((K, n)) < frac] = 2
+        gamma = float(np.float32((X == 2).mean()))          # the step's gamma input is FP32
+        ref = denoise(X, p, code, w, L, h, gamma)
+        say(f"teacher-forced fp64 K={K} n={n} L={L} d={d} h={h} mask={frac}")
+        lbar = torch.zeros(K, n, 2, dtype=torch.float64, device="cuda")
+        logits = torch.zeros_like(lbar)
+        z = torch.zeros(K, n, d, dtype=torch.float64, device="cuda")
+        Xo = torch.zeros(K, n, dtype=torch.uint8, device="cuda")
+        r = max(1, int((X == 2).sum()) // 3)
+        first = 1 if frac == 1.0 else 0
+        P.cider_step_debug(_dev(X), Xo, _dev(y), s2, ch, K, n, wh, gamma, r, first, opts,
+                           out_lbar=lbar, out_logits=logits, out_z=z)
+        torch.cuda.synchronize()
+        e = [rel_err(t.cpu().numpy(), ref[k]) for t, k in ((lbar, "lbar"), (logits, "logits"), (z, "z"))]
+        print(f"  err lbar={e[0]:.2e} logits={e[1]:.2e} z={e[2]:.2e}")
+        assert max(e) <= 1e-11, e
+        Xr = X.copy()
+        info = oracle_reveal(Xr, ref["logits"], r, bool(first))
+        if min(info["gaps"][k] for k in ("cut", "sel", "slot")) > 1e-9:
+            assert np.array_equal(Xo.cpu().numpy(), Xr)
