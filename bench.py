@@ -35,7 +35,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "decoded bins/sec + p99 latency, BF16 batched vs FP32 plain, >=99.9% oracle symbol match"
-PEAK = {"bf16": 2500.0, "fp32": 157.3, "fp8": 5000.0}   # dense TFLOP/s, MI355X published
+PEAK = {"bf16": 2500.0, "fp32": 157.3, "fp8": 5000.0, "fp64": 78.6}   # dense TFLOP/s, MI355X published
 HBM_PEAK = 8000.0                                        # GB/s
 
 
@@ -301,6 +301,9 @@ def run_tiny64(args):
     """GF(64) decoding at the paper's Tiny scale: AMP-MMSE evidence and the
     refinement loop for a batch of frames; value = decoded frames (bins) per second."""
     t = TINY64
+    if args.precision not in ("bf16", "fp32"):
+        raise SystemExit("the GF(Q) decoder runs in bf16 or fp32")
+    kind = args.precision
     frames = args.bins or 4096
     Q, n, K = 1 << t["q_bits"], t["n"], t["K"]
     cpu, oracle_X = None, {}
@@ -328,7 +331,7 @@ def run_tiny64(args):
     rows = torch.from_numpy(sl.rows).cuda()
     S = torch.empty(frames * n, Q, dtype=torch.float32, device="cuda")
     out = torch.zeros(frames, K, n, dtype=torch.uint8, device="cuda")
-    prec = {"bf16": P.CIDER_BF16, "fp32": P.CIDER_FP32}[args.precision if args.precision != "fp8" else "bf16"]
+    prec = {"bf16": P.CIDER_BF16, "fp32": P.CIDER_FP32}[kind]
     opts = P.cider_opts_default(precision=prec, use_graph=1)
     blist = [{"S": S[f * n:(f + 1) * n], "code": ch, "K": K, "n": n, "out_symbols": out[f]} for f in range(frames)]
     stream = torch.cuda.Stream()
@@ -364,11 +367,11 @@ def run_tiny64(args):
     kernels = {k: {"launches": v[0], "avg_ms": round(v[1] / v[0], 4), "total_ms": round(v[1], 3)}
                for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
     tokens = frames * K * n
-    roof = roofline(prof, cfg, n, K, tokens, args.precision if args.precision != "fp8" else "bf16", "tiny64")
+    roof = roofline(prof, cfg, n, K, tokens, kind, "tiny64")
     res = {"metric": "decoded bins/sec, GF(64) Tiny scale (AMP-MMSE evidence + CIDER refinement)",
            "value": round(value, 1), "unit": "bins/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round((t1 - t0) / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": args.precision if args.precision != "fp8" else "bf16", "data": "synthetic",
+           "vs_baseline": None, "dtype": kind, "data": "synthetic",
            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
            "latency_scope": "per bin: the frames of a batch are submitted and complete together",
            "symbols_per_s": round(value * K * n, 1),
@@ -477,7 +480,7 @@ def _measured_traffic(workload: str, kernel: str):
 
 
 def roofline(prof, model, n, K, tokens, kind, workload):
-    per_tok, flop_role, byte_role = algorithmic(model, n, K, 4 if kind == "fp32" else 2)
+    per_tok, flop_role, byte_role = algorithmic(model, n, K, {"fp32": 4, "fp64": 8}.get(kind, 2))
     if kind == "fp8":   # the LayerNorm-fed GEMMs read 1-byte activations
         d = model.d
         byte_role["gemm_qkv_row"] = byte_role["gemm_qkv_user"] = d + 3 * d * 2 + 4
@@ -492,8 +495,8 @@ def roofline(prof, model, n, K, tokens, kind, workload):
     # the denoiser's dense contractions are the path's bound: the dominant kernel is
     # reported as GEMM FLOP/s against the dense MFMA peak of its operand type, with
     # its algorithmic HBM rate beside it
-    if kind == "fp32" and dom_name.startswith("attn"):
-        bound, peak, unit = "alu", PEAK["fp32"], "TFLOP/s"
+    if kind in ("fp32", "fp64") and dom_name.startswith("attn"):
+        bound, peak, unit = "alu", PEAK[kind], "TFLOP/s"
     else:
         bound, peak, unit = "mfma", PEAK[kind], "TFLOP/s"
     ach = fl / secs / 1e12
@@ -545,7 +548,7 @@ def run_batched(args, wl, P, torch):
     tokens = sum(K * n for K, n in shapes)
     outs = [torch.zeros(K, n, dtype=torch.uint8, device=dev) for K, n in shapes]
     rounds = torch.zeros(len(shapes), dtype=torch.int32, device=dev)
-    prec = {"bf16": P.CIDER_BF16, "fp32": P.CIDER_FP32, "fp8": P.CIDER_FP8}[args.precision]
+    prec = {"bf16": P.CIDER_BF16, "fp32": P.CIDER_FP32, "fp8": P.CIDER_FP8, "fp64": P.CIDER_FP64}[args.precision]
     kind = args.precision
     ro = dict(remask=int(wl.remask), remask_thr=wl.remask_thr, remask_max_rounds=wl.remask_max_rounds)
     if args.qhead:
@@ -876,7 +879,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2")
-    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp8"])
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp8", "fp64"])
     ap.add_argument("--bins", type=int, default=0, help="override the batch size")
     ap.add_argument("--cpu-bins", type=int, default=16)
     ap.add_argument("--plain-bins", type=int, default=32)

@@ -111,6 +111,7 @@ __global__ __launch_bounds__(256) void k_embed_demix64(StepCtx c, DevModel64 m, 
 // thread a 4 x 4 block (rows ty + 16 i, columns tx + 16 j), k in slices of 16
 // staged in LDS; every element sums its k terms in ascending order.
 constexpr int GB = 64, GK = 16;
+constexpr bool kGemm64Mfma = true;   // the matrix-core GEMM below; false: the FMA tile
 
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm64(Gemm64 g, const double* __restrict__ W) {
@@ -164,6 +165,70 @@ __global__ __launch_bounds__(256) void k_gemm64(Gemm64 g, const double* __restri
       }
     }
   }
+}
+
+// The same GEMM on the matrix cores: four waves in a 2 x 2 arrangement, a
+// wave a 32 x 32 sub-tile of 2 x 2 v_mfma_f64_16x16x4 blocks (lane l supplies
+// A[l % 16][k0 + l / 16] and B[k0 + l / 16][l % 16] and holds rows
+// l / 16 + 4 r, column l % 16 of a block's result: the double-precision
+// instruction interleaves its result rows); k in slices of 16 in LDS.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm64_mfma(Gemm64 g, const double* __restrict__ W) {
+  __shared__ double As[GB][GK + 1];
+  __shared__ double Bs[GB][GK + 1];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+  const long m0 = (long)blockIdx.x * GB;
+  const int n0 = blockIdx.y * GB;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < g.Kd; k0 += GK) {
+    for (int idx = tid; idx < GB * GK; idx += 256) {
+      const int r = idx / GK, kk = idx - r * GK;
+      const long gm = m0 + r;
+      As[r][kk] = gm < g.M ? g.A[gm * g.Kd + k0 + kk] : 0.0;
+      Bs[r][kk] = W[(long)(n0 + r) * g.Kd + k0 + kk];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < GK / 4; ++st)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const double a = As[wr * 32 + i * 16 + (lane & 15)][st * 4 + (lane >> 4)];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const double bv = Bs[wc * 32 + j * 16 + (lane & 15)][st * 4 + (lane >> 4)];
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[i][j], 0, 0, 0);
+        }
+      }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wc * 32 + j * 16 + (lane & 15);
+      const double bias = g.bias ? g.bias[col] : 0.0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long row = m0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
+        if (row >= g.M) continue;
+        const double v = acc[i][j][r] + bias;
+        const long o = row * g.N + col;
+        if (EPI == kEpiStore) g.out[o] = v;
+        else if (EPI == kEpiGelu) g.out[o] = gelu64(v);
+        else if (EPI == kEpiResid) g.R[o] = g.R[o] + v;
+        else {
+          const double gt = 1.0 / (1.0 + exp(-v));
+          g.R[o] = gt * g.R[o] + (1.0 - gt) * g.E[o];
+        }
+      }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -656,10 +721,17 @@ hipError_t launch_gemm64(int epi, const Gemm64& g, const double* W, hipStream_t 
   if (g.M == 0) return hipSuccess;
   if (g.N % GB != 0 || g.Kd % GK != 0) return hipErrorInvalidValue;
   dim3 grid((unsigned)((g.M + GB - 1) / GB), (unsigned)(g.N / GB)), block(256);
-  if (epi == kEpiStore) hipLaunchKernelGGL(k_gemm64<kEpiStore>, grid, block, 0, s, g, W);
-  else if (epi == kEpiGelu) hipLaunchKernelGGL(k_gemm64<kEpiGelu>, grid, block, 0, s, g, W);
-  else if (epi == kEpiResid) hipLaunchKernelGGL(k_gemm64<kEpiResid>, grid, block, 0, s, g, W);
-  else hipLaunchKernelGGL(k_gemm64<kEpiGate>, grid, block, 0, s, g, W);
+  if (kGemm64Mfma) {
+    if (epi == kEpiStore) hipLaunchKernelGGL(k_gemm64_mfma<kEpiStore>, grid, block, 0, s, g, W);
+    else if (epi == kEpiGelu) hipLaunchKernelGGL(k_gemm64_mfma<kEpiGelu>, grid, block, 0, s, g, W);
+    else if (epi == kEpiResid) hipLaunchKernelGGL(k_gemm64_mfma<kEpiResid>, grid, block, 0, s, g, W);
+    else hipLaunchKernelGGL(k_gemm64_mfma<kEpiGate>, grid, block, 0, s, g, W);
+  } else {
+    if (epi == kEpiStore) hipLaunchKernelGGL(k_gemm64<kEpiStore>, grid, block, 0, s, g, W);
+    else if (epi == kEpiGelu) hipLaunchKernelGGL(k_gemm64<kEpiGelu>, grid, block, 0, s, g, W);
+    else if (epi == kEpiResid) hipLaunchKernelGGL(k_gemm64<kEpiResid>, grid, block, 0, s, g, W);
+    else hipLaunchKernelGGL(k_gemm64<kEpiGate>, grid, block, 0, s, g, W);
+  }
   return hipGetLastError();
 }
 
