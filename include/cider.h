@@ -448,11 +448,14 @@ typedef struct {
 int cider_profile_read(const cider_weights* w, cider_kernel_stat* out, int32_t max, int32_t* n_out,
                        int32_t reset);
 
-/* Introspection (no step of the method): the GEMM tile shapes the autotuner
- * chose on this weights handle: one entry
- * per (role, N, Kd, token-count bucket 2^bucket) with the tile index and the
- * best measured launch time.  Tile indices are those of the library's GEMM
- * (0 = the default shape). */
+/* Introspection (no step of the method): the GEMM tile shapes and the
+ * token-resident kernel variants the autotuner chose on this weights handle:
+ * one entry per (role, N, Kd, token-count bucket 2^bucket) with the tile
+ * index and the best measured launch time.  GEMM roles: tile indices are
+ * those of the library's GEMM (0 = the default shape).  Roles "user_mlp_tr"
+ * and "oproj_mlp3" (the fused sublayer + MLP kernels): n is d, kd the hidden
+ * width, tile the variant (0 = the default; variants change the waves per
+ * workgroup or the weight-ring depth, never a result). */
 typedef struct {
   char    role[24];
   int32_t n, kd, bucket, tile;

@@ -421,7 +421,9 @@ def cider_profile_read(w: Weights, reset: bool = True) -> dict:
 
 
 def cider_tuning_read(w: Weights) -> list:
-    """[(role, N, Kd, bucket, tile, best_ms, default_ms)] chosen by the GEMM autotuner."""
+    """[(role, N, Kd, bucket, tile, best_ms, default_ms)] chosen by the autotuner
+    (GEMM tile shapes; for the fused kernels' roles N = d, Kd = hidden width and
+    tile = variant)."""
     arr = (cider_tuning_entry * 128)()
     n = C.c_int32()
     check(lib().cider_tuning_read(w.handle, arr, 128, C.byref(n)), "cider_tuning_read")

@@ -266,10 +266,12 @@ hipError_t launch_oproj_user_attn(const StepCtx& c, const void* Orow, const Mat&
 bool oproj_mlp3_ok(int d, int F);
 hipError_t launch_oproj_mlp3_bf16(const GemmArgs& g, const Mat& Wo, const float* bo, const float* lnx_g,
                                   const float* lnx_b, const Mat& W1, const float* b1, const Mat& W2, int F,
-                                  hipStream_t s);
+                                  hipStream_t s, int variant = 0);
+int oproj_mlp3_variants();
 bool user_mlp_tr_ok(int d, int heads, int F);
 hipError_t launch_user_mlp_tr(const StepCtx& c, void* XN, const DevLayer& L, const GemmArgs& g2, int d, int heads,
-                              int F, hipStream_t s);
+                              int F, hipStream_t s, int variant = 0);
+int user_mlp_tr_variants();
 bool row_qkv_attn_ok(int d, int heads, int max_n);
 hipError_t launch_row_qkv_attn(const StepCtx& c, const void* XN, const Mat& Wqkv, const float* bqkv, void* O, int d,
                                int heads, hipStream_t s);

@@ -368,7 +368,9 @@ struct Timed {
     HIPCHK(expr);                     \
   } while (0)
 
-constexpr int kMlpKey = 100;   // tuning-table key of the fused MLP
+constexpr int kMlpKey = 100;       // tuning-table keys: the fused MLP,
+constexpr int kOprojMlpKey = 101;  // the d = 256 output projection + MLP,
+constexpr int kUserMlpKey = 102;   // the d = 128 user sublayer + MLP
 
 int bucket_of(long M) {
   int b = 0;
@@ -384,6 +386,46 @@ TuneKey tune_key(int epi, const GemmArgs& g) {
 int tile_for(cider_weights* w, int epi, const GemmArgs& g) {
   auto it = w->tune.find(tune_key(epi, g));
   return it == w->tune.end() ? 0 : it->second.tile;
+}
+
+// The variant of a token-resident kernel (key kOprojMlpKey / kUserMlpKey)
+// for this batch: forced (tests), tuned earlier, or 0.
+int variant_for(cider_weights* w, const Run& r, int key, int d, int F, long T, int count) {
+  if (r.forced_tile >= 0) return r.forced_tile < count ? r.forced_tile : 0;
+  auto it = w->tune.find(TuneKey{key, 0, d, F, bucket_of(T)});
+  return it == w->tune.end() ? 0 : it->second.tile;
+}
+
+// Times each variant of a token-resident kernel on the live buffers (3
+// launches each, best of them) and records the fastest.  The kernels rewrite
+// R and XN in place, which the next forward recomputes from the embedding.
+template <class Launch>
+int tune_variants(cider_weights* w, const char* role, const TuneKey& key, int count, Launch launch, hipStream_t s) {
+  if (w->tune.count(key)) return CIDER_OK;
+  hipEvent_t a, b;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  double best = 1e30, dflt = 0;
+  int best_t = 0;
+  for (int t = 0; t < count; ++t) {
+    if (launch(t) != hipSuccess) { (void)hipGetLastError(); continue; }
+    double tmin = 1e30;
+    for (int rep = 0; rep < 3; ++rep) {
+      HIPCHK(hipEventRecord(a, s));
+      HIPCHK(launch(t));
+      HIPCHK(hipEventRecord(b, s));
+      HIPCHK(hipEventSynchronize(b));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, a, b));
+      tmin = std::min(tmin, (double)ms);
+    }
+    if (t == 0) dflt = tmin;
+    if (tmin < best) { best = tmin; best_t = t; }
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  w->tune[key] = TuneVal{best_t, best, dflt, role};
+  return CIDER_OK;
 }
 
 // Times every tile shape of one GEMM on the live buffers (3 launches each,
@@ -653,11 +695,13 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
         TIMED("mlp_fused", launch_mlp_fp8(g, L.W1, L.b1, L.W2, F, s));
       } else if (user_mlp) {
         // BF16, d = 128, head width 16: user-attention sublayer + MLP, token-resident, one kernel
-        TIMED("user_mlp", launch_user_mlp_tr(c, k.XN, L, g, d, m.heads, F, s));
+        const int v = variant_for(w, r, kUserMlpKey, d, F, T, user_mlp_tr_variants());
+        TIMED("user_mlp", launch_user_mlp_tr(c, k.XN, L, g, d, m.heads, F, s, v));
       } else if (oproj_mlp) {
         // BF16, d = 256: the user sublayer's output projection + MLP in one kernel (O in, R and XN out)
         g.A = k.O;
-        TIMED("oproj_mlp", launch_oproj_mlp3_bf16(g, L.Wo_u, L.bo_u, L.ln3_g, L.ln3_b, L.W1, L.b1, L.W2, F, s));
+        const int v = variant_for(w, r, kOprojMlpKey, d, F, T, oproj_mlp3_variants());
+        TIMED("oproj_mlp", launch_oproj_mlp3_bf16(g, L.Wo_u, L.bo_u, L.ln3_g, L.ln3_b, L.W1, L.b1, L.W2, F, s, v));
       } else if (mlp3_ok(d, F)) {
         // token-resident MLP: 256 tokens per workgroup, weights streamed once per tile
         TIMED("mlp_fused", launch_mlp3_bf16(g, L.W1, L.b1, L.W2, F, s));
@@ -740,6 +784,28 @@ int autotune_forward(cider_weights* w, const Run& r, hipStream_t s) {
     g = GemmArgs{}; g.M = T; g.N = d; g.Kd = d; g.A = k.XN; g.bias = L.b2; g.R = k.R;
     g.ln_g = L.ln1_g; g.ln_b = L.ln1_b; g.out = k.XN;
     if ((rc = tune_mlp(w, g, L, F, s))) return rc;
+  }
+  // the token-resident kernels with variants (the same choice as the forward's)
+  const bool user_mlp = r.prec == kBF16 && r.use_blocks && user_mlp_tr_ok(d, m.heads, F);
+  const bool oproj_mlp = r.prec == kBF16 && r.use_blocks && !user_mlp && user_qkv_attn_ok(d, m.heads) &&
+                         oproj_mlp3_ok(d, F);
+  g = GemmArgs{}; g.M = T; g.N = d; g.Kd = d; g.A = k.XN; g.bias = L.b2; g.R = k.R;
+  g.ln_g = L.ln1_g; g.ln_b = L.ln1_b; g.out = k.XN;
+  if (user_mlp) {
+    const StepCtx& c = r.ctx;
+    auto launch = [&](int v) { return launch_user_mlp_tr(c, k.XN, L, g, d, m.heads, F, s, v); };
+    if ((rc = tune_variants(w, "user_mlp_tr", TuneKey{kUserMlpKey, 0, d, F, bucket_of(T)}, user_mlp_tr_variants(),
+                            launch, s)))
+      return rc;
+  }
+  if (oproj_mlp) {
+    g.A = k.O;
+    auto launch = [&](int v) {
+      return launch_oproj_mlp3_bf16(g, L.Wo_u, L.bo_u, L.ln3_g, L.ln3_b, L.W1, L.b1, L.W2, F, s, v);
+    };
+    if ((rc = tune_variants(w, "oproj_mlp3", TuneKey{kOprojMlpKey, 0, d, F, bucket_of(T)}, oproj_mlp3_variants(),
+                            launch, s)))
+      return rc;
   }
   return CIDER_OK;
 }

@@ -1446,7 +1446,7 @@ struct UMSmem {
   static constexpr size_t w = wu > wm ? wu : wm;
   static constexpr size_t vec = (size_t)(3 * D + 3 * D + MAXF + 5 * D) * 4;   // bqkv, (b_o, LN3), b1, epilogue
   static constexpr size_t bytes = w + vec;
-  static_assert(bytes <= 80 * 1024, "two workgroups per CU");
+  static_assert(bytes <= 160 * 1024, "LDS");
 };
 
 struct UserMlpArgs {
@@ -1548,6 +1548,8 @@ template <int D, int NW, int NBUF, int MAXF, bool PROJ>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_user_mlp_tr(StepCtx c, UserMlpArgs a) {
   using S = UMSmem<D, NBUF, MAXF>;
+  // two waves per SIMD: two 4-wave workgroups per CU, or one 8-wave workgroup
+  static_assert(NW == 8 || S::bytes <= 80 * 1024, "two workgroups per CU");
   using U = UBSmem<D>;
   using M = typename S::M;
   constexpr int RB1 = U::RB1, RB2 = U::RB2, KS = D / 16, NP = D / 32, OBK = D / 32, NTHR = NW * 64;
@@ -2937,18 +2939,27 @@ bool oproj_mlp3_ok(int d, int F) { return d == 256 && F % kM3FCH == 0 && F >= 64
 // projection (g.proj_w / g.proj_out).  BF16, d = 256.  g.A = O, g.bias = b2.
 hipError_t launch_oproj_mlp3_bf16(const GemmArgs& g, const Mat& Wo, const float* bo, const float* lnx_g,
                                   const float* lnx_b, const Mat& W1, const float* b1, const Mat& W2, int F,
-                                  hipStream_t s) {
+                                  hipStream_t s, int variant) {
   if (g.M == 0) return hipSuccess;
   if (!oproj_mlp3_ok(g.N, F) || !g.ln_g || !Wo.b16 || !W1.b16 || !W2.b16) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((g.M + kM3BM - 1) / kM3BM)), block(512);
-  if (g.proj_out)
-    hipLaunchKernelGGL((k_oproj_mlp3<256, 3, 1024, true>), grid, block, 0, s, g, Wo.b16, bo, lnx_g, lnx_b, W1.b16, b1,
-                       W2.b16, F);
-  else
-    hipLaunchKernelGGL((k_oproj_mlp3<256, 3, 1024, false>), grid, block, 0, s, g, Wo.b16, bo, lnx_g, lnx_b, W1.b16,
-                       b1, W2.b16, F);
+#define CIDER_OM(NB)                                                                                              \
+  if (g.proj_out)                                                                                                 \
+    hipLaunchKernelGGL((k_oproj_mlp3<256, NB, 1024, true>), grid, block, 0, s, g, Wo.b16, bo, lnx_g, lnx_b,        \
+                       W1.b16, b1, W2.b16, F);                                                                    \
+  else                                                                                                            \
+    hipLaunchKernelGGL((k_oproj_mlp3<256, NB, 1024, false>), grid, block, 0, s, g, Wo.b16, bo, lnx_g, lnx_b,       \
+                       W1.b16, b1, W2.b16, F);
+  // variants differ only in the depth of the MLP weight-chunk ring (3, 4 or 2
+  // chunks in flight); every element's arithmetic is the same
+  if (variant == 1) { CIDER_OM(4) }
+  else if (variant == 2) { CIDER_OM(2) }
+  else { CIDER_OM(3) }
+#undef CIDER_OM
   return hipGetLastError();
 }
+
+int oproj_mlp3_variants() { return 3; }
 
 bool user_mlp_tr_ok(int d, int heads, int F) { return d == 128 && heads * 16 == d && F % kM3FCH == 0 && F >= 64 && F <= 512; }
 
@@ -2956,7 +2967,7 @@ bool user_mlp_tr_ok(int d, int heads, int F) { return d == 128 && heads * 16 == 
 // width 16, hidden width <= 512): R and XN in, R and XN (or, with
 // g.proj_out set, lbar) out.  Groups from c.ugrp32.
 hipError_t launch_user_mlp_tr(const StepCtx& c, void* XN, const DevLayer& L, const GemmArgs& g2, int d, int heads,
-                              int F, hipStream_t s) {
+                              int F, hipStream_t s, int variant) {
   if (c.total_ugrp32 == 0) return hipSuccess;
   if (!user_mlp_tr_ok(d, heads, F) || !c.ugrp32 || !L.Wqkv_u.b16 || !L.Wo_u.b16 || !L.W1.b16 || !L.W2.b16)
     return hipErrorInvalidValue;
@@ -2967,11 +2978,24 @@ hipError_t launch_user_mlp_tr(const StepCtx& c, void* XN, const DevLayer& L, con
   a.g = g2;
   a.g.A = XN;
   a.g.M = c.total_tokens;
-  const dim3 grid((c.total_ugrp32 + 3) / 4), block(256);
-  if (g2.proj_out) hipLaunchKernelGGL((k_user_mlp_tr<128, 4, 3, 512, true>), grid, block, 0, s, c, a);
-  else hipLaunchKernelGGL((k_user_mlp_tr<128, 4, 3, 512, false>), grid, block, 0, s, c, a);
+#define CIDER_UM(NW, NB)                                                                                     \
+  {                                                                                                          \
+    const dim3 grid((c.total_ugrp32 + NW - 1) / NW), block(NW * 64);                                        \
+    if (g2.proj_out) hipLaunchKernelGGL((k_user_mlp_tr<128, NW, NB, 512, true>), grid, block, 0, s, c, a);   \
+    else hipLaunchKernelGGL((k_user_mlp_tr<128, NW, NB, 512, false>), grid, block, 0, s, c, a);              \
+  }
+  // variants: waves per workgroup (4: two workgroups per CU; 8: one, which
+  // halves the weight traffic per token) and the depth of the MLP chunk ring;
+  // each wave's arithmetic on its own 32 tokens is the same in all of them
+  if (variant == 1) CIDER_UM(8, 3)
+  else if (variant == 2) CIDER_UM(8, 4)
+  else if (variant == 3) CIDER_UM(4, 2)
+  else CIDER_UM(4, 3)
+#undef CIDER_UM
   return hipGetLastError();
 }
+
+int user_mlp_tr_variants() { return 4; }
 
 bool row_qkv_attn_ok(int d, int heads, int max_n) { return d == 256 && heads * 32 == d && max_n <= 256; }
 

@@ -385,8 +385,8 @@ def test_fused_blocks_match_separate_kernels(K, n, L, d, h):
 
 
 def test_every_gemm_tile_gives_identical_decodes():
-    """Tile shapes change only the work split, never an element's accumulation
-    order, so the autotuner cannot change a result."""
+    """Tile shapes and kernel variants change only the work split, never an
+    element's accumulation order, so the autotuner cannot change a result."""
     torch = torch_cuda()
     P = lib()
     for (K, n, L, d, h) in [(4, 128, 2, 128, 8), (3, 64, 1, 256, 8), (2, 64, 1, 384, 12)]:
@@ -409,10 +409,15 @@ def test_every_gemm_tile_gives_identical_decodes():
                 ref = (out.clone(), lg.clone())
             else:
                 assert torch.equal(out, ref[0]) and torch.equal(lg, ref[1]), mode
-        if d not in (128, 256):
-            # d <= 192 runs fused attention blocks, and d in {128, 256} the
-            # token-resident projections and MLP: none has tile shapes to tune
-            assert len(P.cider_tuning_read(wh)) > 0
+        roles = {t[0] for t in P.cider_tuning_read(wh)}
+        if d == 128:
+            # the user sublayer + MLP kernel's variants (forced tiles 0-3 above)
+            assert "user_mlp_tr" in roles, roles
+        elif d == 256:
+            # the output projection + MLP kernel's variants (forced tiles 0-2 above)
+            assert "oproj_mlp3" in roles, roles
+        else:
+            assert len(roles) > 0
 
 
 def test_fp8_rejects_narrow_models():
