@@ -86,6 +86,24 @@ __device__ __forceinline__ void m3_wait_barrier(int n) {
   }
 }
 
+// A run of N MFMAs whose A operands come from LDS, with each fragment read
+// PF MFMAs ahead of its use (the scheduling barrier keeps that order, so each
+// MFMA waits only for its own fragment, not for a read issued just before
+// it).  ld(i) returns fragment i; op(i, w) issues MFMA i.
+template <int N, int PF, class Ld, class Op>
+__device__ __forceinline__ void mfma_pipe(Ld ld, Op op) {
+  bf16x8 w[PF];
+#pragma unroll
+  for (int i = 0; i < PF; ++i)
+    if (i < N) w[i] = ld(i);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    op(i, w[i % PF]);
+    if (i + PF < N) w[i % PF] = ld(i + PF);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 // Row j of the stored W1 chunk holds hidden unit sigma(j) of the chunk.
 __device__ __forceinline__ int m3_sigma(int j) {
   const int q = j >> 3, g = (j >> 2) & 1, i = j & 3;
@@ -1544,7 +1562,7 @@ __device__ __forceinline__ void m3_epilogue_final(f32x16 (&acc2)[D / 32][1], int
   }
 }
 
-template <int D, int NW, int NBUF, int MAXF, bool PROJ>
+template <int D, int NW, int NBUF, int MAXF, bool PROJ, int PF>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_user_mlp_tr(StepCtx c, UserMlpArgs a) {
   using S = UMSmem<D, NBUF, MAXF>;
@@ -1824,27 +1842,25 @@ void k_user_mlp_tr(StepCtx c, UserMlpArgs a) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) acc1[4 * q + i] = bq[i];
     }
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      // W1 k-values in X1's order: 16 s + 4 g2 + j, then 16 s + 8 + 4 g2 + j
-      const char* wr = s1 + l32 * MRB1;
-      const bf16x4 a0 = *(const bf16x4*)(wr + (16 * s + 4 * g2) * 2);
-      const bf16x4 a1 = *(const bf16x4*)(wr + (16 * s + 8 + 4 * g2) * 2);
-      const bf16x8 w = bf16x8{a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, x1[s], acc1, 0, 0, 0);
-    }
+    // W1 k-values in X1's order: 16 s + 4 g2 + j, then 16 s + 8 + 4 g2 + j
+    const char* wr = s1 + l32 * MRB1;
+    mfma_pipe<KS, PF>(
+        [&](int s) {
+          const bf16x4 a0 = *(const bf16x4*)(wr + (16 * s + 4 * g2) * 2);
+          const bf16x4 a1 = *(const bf16x4*)(wr + (16 * s + 8 + 4 * g2) * 2);
+          return bf16x8{a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+        },
+        [&](int s, const bf16x8& w) { acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, x1[s], acc1, 0, 0, 0); });
     bf16x8 hf[2];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int i = 0; i < 4; ++i) hf[q >> 1][4 * (q & 1) + i] = (bf16)gelu_f(acc1[4 * q + i]);
-#pragma unroll
-    for (int b = 0; b < OBK; ++b)
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const bf16x8 w = *(const bf16x8*)(s2 + (32 * b + l32) * MRB2 + (2 * s + g2) * 16);
-        acc2[b][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, hf[s], acc2[b][0], 0, 0, 0);
-      }
+    mfma_pipe<2 * OBK, PF>(
+        [&](int j) { return *(const bf16x8*)(s2 + (32 * (j >> 1) + l32) * MRB2 + (2 * (j & 1) + g2) * 16); },
+        [&](int j, const bf16x8& w) {
+          acc2[j >> 1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, hf[j & 1], acc2[j >> 1][0], 0, 0, 0);
+        });
     // chunk ch + 1 complete in every wave: later chunks (at most NBUF - 2) may be in flight
     if (ch + 1 < nch) m3_wait_barrier(nwm * (min(ch + NBUF - 1, nch - 1) - (ch + 1)));
   }
@@ -1876,7 +1892,7 @@ struct OMSmem {
   static_assert(bytes <= 160 * 1024, "LDS");
 };
 
-template <int D, int NBUF, int MAXF, bool PROJ>
+template <int D, int NBUF, int MAXF, bool PROJ, int PF>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_oproj_mlp3(GemmArgs g, const bf16* __restrict__ Wo, const float* __restrict__ bo, const float* __restrict__ lnx_g,
                   const float* __restrict__ lnx_b, const bf16* __restrict__ W1, const float* __restrict__ b1,
@@ -1970,21 +1986,21 @@ void k_oproj_mlp3(GemmArgs g, const bf16* __restrict__ Wo, const float* __restri
       afrag(c + 1, fn);
     }
     const char* sw = wreg + buf * O::wa;
-#pragma unroll
-    for (int s = 0; s < KSC; ++s)
-#pragma unroll
-      for (int b = 0; b < OBK; ++b) {
-        const bf16x8 w = *(const bf16x8*)(sw + (32 * b + l32) * RB + (2 * s + g2) * 16);
-        acc2[b][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, fa[s], acc2[b][0], 0, 0, 0);
-      }
+    mfma_pipe<KSC * OBK, PF>(
+        [&](int i) { return *(const bf16x8*)(sw + (32 * (i % OBK) + l32) * RB + (2 * (i / OBK) + g2) * 16); },
+        [&](int i, const bf16x8& w) {
+          acc2[i % OBK][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, fa[i / OBK], acc2[i % OBK][0], 0, 0, 0);
+        });
     if (c + 1 < NCH) {
 #pragma unroll
       for (int s = 0; s < KSC; ++s) fa[s] = fn[s];
     }
     __syncthreads();                                // every wave is done with this buffer
   }
-  // the W_o buffers are dead: the MLP ring takes the region
-  const int pre = min(NBUF - 1, nch);
+  // the W_o buffers are dead: the MLP ring takes the region (chunks prefetched
+  // DIST ahead)
+  constexpr int DIST = NBUF - 1;
+  const int pre = min(DIST, nch);
   for (int ch = 0; ch < pre; ++ch) dma_m(ch, ch);
 
   // ---- R1 = R + acc2 + b_o in place, X1 = LN(R1) in the accumulator layout,
@@ -2041,44 +2057,53 @@ void k_oproj_mlp3(GemmArgs g, const bf16* __restrict__ Wo, const float* __restri
   }
 
   // ================= MLP (one chunk of 32 hidden units at a time) =================
-  m3_wait_barrier(nwm * max(0, pre - 1));           // chunk 0 in LDS
-#pragma unroll 1
-  for (int ch = 0; ch < nch; ++ch) {
-    // buffer (ch + NBUF - 1) % NBUF was last read in iteration ch - 1, before its closing barrier
-    if (ch + NBUF - 1 < nch) dma_m(ch + NBUF - 1, (ch + NBUF - 1) % NBUF);
+  // up: acc1 = b1 + W1 X1 for the chunk's 32 hidden units
+  auto up = [&](int ch, f32x16& acc1) {
     const char* s1 = wreg + (ch % NBUF) * M::buf;
-    const char* s2 = s1 + M::w1a;
     const float* sb = sb1 + ch * kM3FCH;
-    f32x16 acc1;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const f32x4 bq = *(const f32x4*)&sb[16 * (q >> 1) + 8 * g2 + 4 * (q & 1)];
 #pragma unroll
       for (int i = 0; i < 4; ++i) acc1[4 * q + i] = bq[i];
     }
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      // W1 k-values in X1's order: 16 s + 4 g2 + j, then 16 s + 8 + 4 g2 + j
-      const char* wr = s1 + l32 * MRB1;
-      const bf16x4 a0 = *(const bf16x4*)(wr + (16 * s + 4 * g2) * 2);
-      const bf16x4 a1 = *(const bf16x4*)(wr + (16 * s + 8 + 4 * g2) * 2);
-      const bf16x8 w = bf16x8{a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, x1[s], acc1, 0, 0, 0);
-    }
-    bf16x8 hf[2];
+    // W1 k-values in X1's order: 16 s + 4 g2 + j, then 16 s + 8 + 4 g2 + j
+    const char* wr = s1 + l32 * MRB1;
+    mfma_pipe<KS, PF>(
+        [&](int s) {
+          const bf16x4 a0 = *(const bf16x4*)(wr + (16 * s + 4 * g2) * 2);
+          const bf16x4 a1 = *(const bf16x4*)(wr + (16 * s + 8 + 4 * g2) * 2);
+          return bf16x8{a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+        },
+        [&](int s, const bf16x8& w) { acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, x1[s], acc1, 0, 0, 0); });
+  };
+  auto gelu = [&](const f32x16& acc1, bf16x8 (&hf)[2]) {
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int i = 0; i < 4; ++i) hf[q >> 1][4 * (q & 1) + i] = (bf16)gelu_f(acc1[4 * q + i]);
-#pragma unroll
-    for (int b = 0; b < OBK; ++b)
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const bf16x8 w = *(const bf16x8*)(s2 + (32 * b + l32) * MRB2 + (2 * s + g2) * 16);
-        acc2[b][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, hf[s], acc2[b][0], 0, 0, 0);
-      }
-    // chunk ch + 1 complete in every wave: later chunks (at most NBUF - 2) may be in flight
-    if (ch + 1 < nch) m3_wait_barrier(nwm * (min(ch + NBUF - 1, nch - 1) - (ch + 1)));
+  };
+  // down: acc2 += W2 GELU(.) over the chunk
+  auto down = [&](int ch, const bf16x8 (&hf)[2]) {
+    const char* s2 = wreg + (ch % NBUF) * M::buf + M::w1a;
+    mfma_pipe<2 * OBK, PF>(
+        [&](int j) { return *(const bf16x8*)(s2 + (32 * (j >> 1) + l32) * MRB2 + (2 * (j & 1) + g2) * 16); },
+        [&](int j, const bf16x8& w) {
+          acc2[j >> 1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, hf[j & 1], acc2[j >> 1][0], 0, 0, 0);
+        });
+  };
+  m3_wait_barrier(nwm * max(0, pre - 1));           // chunk 0 in LDS
+#pragma unroll 1
+  for (int ch = 0; ch < nch; ++ch) {
+    // buffer (ch + DIST) % NBUF was last read in iteration ch - 1, before its closing barrier
+    if (ch + DIST < nch) dma_m(ch + DIST, (ch + DIST) % NBUF);
+    f32x16 acc1;
+    bf16x8 hf[2];
+    up(ch, acc1);
+    gelu(acc1, hf);
+    down(ch, hf);
+    // chunk ch + 1 complete in every wave: later chunks (at most DIST - 1) may be in flight
+    if (ch + 1 < nch) m3_wait_barrier(nwm * (min(ch + DIST, nch - 1) - (ch + 1)));
   }
   m3_epilogue_final<D, PROJ>(acc2, tok, g, g2, svm);
 }
@@ -2943,23 +2968,26 @@ hipError_t launch_oproj_mlp3_bf16(const GemmArgs& g, const Mat& Wo, const float*
   if (g.M == 0) return hipSuccess;
   if (!oproj_mlp3_ok(g.N, F) || !g.ln_g || !Wo.b16 || !W1.b16 || !W2.b16) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((g.M + kM3BM - 1) / kM3BM)), block(512);
-#define CIDER_OM(NB)                                                                                              \
+#define CIDER_OM(NB, PF)                                                                                          \
   if (g.proj_out)                                                                                                 \
-    hipLaunchKernelGGL((k_oproj_mlp3<256, NB, 1024, true>), grid, block, 0, s, g, Wo.b16, bo, lnx_g, lnx_b,        \
+    hipLaunchKernelGGL((k_oproj_mlp3<256, NB, 1024, true, PF>), grid, block, 0, s, g, Wo.b16, bo, lnx_g, lnx_b,    \
                        W1.b16, b1, W2.b16, F);                                                                    \
   else                                                                                                            \
-    hipLaunchKernelGGL((k_oproj_mlp3<256, NB, 1024, false>), grid, block, 0, s, g, Wo.b16, bo, lnx_g, lnx_b,       \
+    hipLaunchKernelGGL((k_oproj_mlp3<256, NB, 1024, false, PF>), grid, block, 0, s, g, Wo.b16, bo, lnx_g, lnx_b,   \
                        W1.b16, b1, W2.b16, F);
-  // variants differ only in the depth of the MLP weight-chunk ring (3, 4 or 2
-  // chunks in flight); every element's arithmetic is the same
-  if (variant == 1) { CIDER_OM(4) }
-  else if (variant == 2) { CIDER_OM(2) }
-  else { CIDER_OM(3) }
+  // variants differ in the depth of the MLP weight-chunk ring (2, 3 or 4
+  // buffers) and in how many weight fragments each wave keeps in flight
+  // ahead of its MFMAs; every element's arithmetic is the same
+  if (variant == 1) { CIDER_OM(3, 3) }
+  else if (variant == 2) { CIDER_OM(2, 2) }
+  else if (variant == 3) { CIDER_OM(2, 4) }
+  else if (variant == 4) { CIDER_OM(4, 3) }
+  else { CIDER_OM(2, 3) }
 #undef CIDER_OM
   return hipGetLastError();
 }
 
-int oproj_mlp3_variants() { return 3; }
+int oproj_mlp3_variants() { return 5; }
 
 bool user_mlp_tr_ok(int d, int heads, int F) { return d == 128 && heads * 16 == d && F % kM3FCH == 0 && F >= 64 && F <= 512; }
 
@@ -2978,24 +3006,26 @@ hipError_t launch_user_mlp_tr(const StepCtx& c, void* XN, const DevLayer& L, con
   a.g = g2;
   a.g.A = XN;
   a.g.M = c.total_tokens;
-#define CIDER_UM(NW, NB)                                                                                     \
-  {                                                                                                          \
-    const dim3 grid((c.total_ugrp32 + NW - 1) / NW), block(NW * 64);                                        \
-    if (g2.proj_out) hipLaunchKernelGGL((k_user_mlp_tr<128, NW, NB, 512, true>), grid, block, 0, s, c, a);   \
-    else hipLaunchKernelGGL((k_user_mlp_tr<128, NW, NB, 512, false>), grid, block, 0, s, c, a);              \
+#define CIDER_UM(NW, NB, PF)                                                                                   \
+  {                                                                                                            \
+    const dim3 grid((c.total_ugrp32 + NW - 1) / NW), block(NW * 64);                                          \
+    if (g2.proj_out) hipLaunchKernelGGL((k_user_mlp_tr<128, NW, NB, 512, true, PF>), grid, block, 0, s, c, a); \
+    else hipLaunchKernelGGL((k_user_mlp_tr<128, NW, NB, 512, false, PF>), grid, block, 0, s, c, a);            \
   }
   // variants: waves per workgroup (4: two workgroups per CU; 8: one, which
-  // halves the weight traffic per token) and the depth of the MLP chunk ring;
-  // each wave's arithmetic on its own 32 tokens is the same in all of them
-  if (variant == 1) CIDER_UM(8, 3)
-  else if (variant == 2) CIDER_UM(8, 4)
-  else if (variant == 3) CIDER_UM(4, 2)
-  else CIDER_UM(4, 3)
+  // halves the weight traffic per token), the depth of the MLP chunk ring and
+  // the MLP weight fragments each wave keeps in flight; each wave's arithmetic
+  // on its own 32 tokens is the same in all of them
+  if (variant == 1) CIDER_UM(4, 3, 3)
+  else if (variant == 2) CIDER_UM(4, 2, 2)
+  else if (variant == 3) CIDER_UM(4, 2, 4)
+  else if (variant == 4) CIDER_UM(8, 3, 3)
+  else CIDER_UM(4, 2, 3)
 #undef CIDER_UM
   return hipGetLastError();
 }
 
-int user_mlp_tr_variants() { return 4; }
+int user_mlp_tr_variants() { return 5; }
 
 bool row_qkv_attn_ok(int d, int heads, int max_n) { return d == 256 && heads * 32 == d && max_n <= 256; }
 

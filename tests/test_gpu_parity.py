@@ -397,7 +397,7 @@ def test_every_gemm_tile_gives_identical_decodes():
         bins = synth.make_bins(code, K, 6, 4.0, seed=60 + d)
         y = _dev(bins.y)
         ref = None
-        for mode in (0, 1, 2, 3, 4, 5):
+        for mode in (0, 1, 2, 3, 4, 5, 6):
             say(f"tiles d={d} autotune={mode}")
             opts = P.cider_opts_default(precision=P.CIDER_BF16, autotune=mode)
             out = torch.zeros(6, K, n, dtype=torch.uint8, device="cuda")
