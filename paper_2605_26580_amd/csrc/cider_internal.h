@@ -184,7 +184,8 @@ hipError_t launch_layernorm64(long T, int d, const double* R, const double* g, c
                               hipStream_t s);
 hipError_t launch_row_attn64(const StepCtx& c, const double* QKV, double* O, int d, int heads, int max_n,
                              hipStream_t s);
-hipError_t launch_user_attn64(const StepCtx& c, const double* QKV, double* O, int d, int heads, hipStream_t s);
+hipError_t launch_user_attn64(const StepCtx& c, const double* QKV, double* O, int d, int heads, int max_K,
+                              hipStream_t s);
 hipError_t launch_final_proj64(long T, int d, const DevModel64& m, const double* R, double* lbar, hipStream_t s);
 hipError_t launch_module_b64(const StepCtx& c, const double* lbar, double* logits, hipStream_t s);
 hipError_t launch_step_tail64(const StepCtx& c, const double* logits, hipStream_t s);

@@ -340,6 +340,7 @@ struct Run {
   RowSeg seg[kRowPaths]{};
   int nseg = 0;
   int max_checks = 0;     // most checks of a bin's code (GF(Q) Module B grid)
+  int max_K = kMaxK;      // most users of a bin (sizes the FP64 user-attention grid)
 };
 
 // Brackets a launch with events when profiling is on.
@@ -496,7 +497,7 @@ int enqueue_forward64(cider_weights* w, const Run& r, hipStream_t s) {
     TIMED("gemm_o_row", gemm(kEpiResid, d, d, O, L.bo_r, nullptr, L.Wo_r));
     TIMED("layernorm", launch_layernorm64(T, d, R, L.ln2_g, L.ln2_b, XN, s));
     TIMED("gemm_qkv_user", gemm(kEpiStore, 3 * d, d, XN, L.bqkv_u, QKV, L.Wqkv_u));
-    TIMED("attn_user", launch_user_attn64(c, QKV, O, d, h, s));
+    TIMED("attn_user", launch_user_attn64(c, QKV, O, d, h, r.max_K, s));
     TIMED("gemm_o_user", gemm(kEpiResid, d, d, O, L.bo_u, nullptr, L.Wo_u));
     TIMED("layernorm", launch_layernorm64(T, d, R, L.ln3_g, L.ln3_b, XN, s));
     TIMED("gemm_mlp_up", gemm(kEpiGelu, F, d, XN, L.b1, HID, L.W1));
@@ -996,7 +997,9 @@ int prepare(cider_weights* w, const std::vector<BinIn>& bins, int steps, const c
   long T = 0, msg = 0;
   int slots = 0, rows = 0, max_n = 0;
   r->max_checks = 0;
+  r->max_K = 1;
   for (const BinIn& b : bins) {
+    r->max_K = std::max(r->max_K, b.K);
     T += (long)b.K * b.n;
     slots += b.n;
     rows += b.K;

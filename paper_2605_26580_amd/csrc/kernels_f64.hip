@@ -325,40 +325,154 @@ __global__ __launch_bounds__(kQ64) void k_row_attn64(StepCtx c, const double* __
   }
 }
 
-// User attention (as k_user_attn): one thread per (slot, head, query row).
+// Row attention on the matrix cores: one wave per 16 queries of a (row,
+// head), four waves per workgroup.  Per tile of 16 keys the wave forms
+// S^T = K Q^T with v_mfma_f64_16x16x4 (lane l then holds the scores of
+// keys l / 16 + 4 r for query l % 16), keeps an online softmax per query
+// (maximum across the four lane groups of a column), and accumulates
+// O^T = V^T P^T, whose B operand for k-step s is exactly the lane's
+// probability r = s.  Keys and values pass through LDS 32 at a time.
+constexpr bool kRowAttn64Mfma = true;
+
+template <int DH>
+__global__ __launch_bounds__(256) void k_row_attn64_mfma(StepCtx c, const double* __restrict__ QKV,
+                                                         double* __restrict__ O, int d, int heads) {
+  constexpr int KT = 32, NS = DH / 4, NT = DH / 16;
+  __shared__ double sK[KT][DH + 1];
+  __shared__ double sV[KT][DH + 1];
+  const int item = blockIdx.x;
+  const int r = c.row_first + item / heads, h = item % heads;
+  const DevBin& b = c.bins[c.row_bin[r]];
+  if (b.st->phase == kDone) return;
+  const int n = b.n, k = r - b.row_off;
+  const int qb = blockIdx.y * 64;
+  if (qb >= n) return;
+  const long tok0 = (long)b.tok_off + (long)k * n;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, qi = lane & 15, g = lane >> 4;
+  const int q = qb + wave * 16 + qi;
+  const bool qv = q < n;
+  const double scale = 1.0 / sqrt((double)DH);
+  double qf[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) qf[s] = qv ? QKV[(tok0 + q) * 3 * d + h * DH + 4 * s + g] : 0.0;
+  f64x4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+  double mrun = -INFINITY, lpart = 0.0;
+  for (int j0 = 0; j0 < n; j0 += KT) {
+    const int nk = min(KT, n - j0);
+    for (int idx = tid; idx < KT * DH; idx += 256) {
+      const int jj = idx / DH, ii = idx - jj * DH;
+      double kv = 0.0, vv = 0.0;
+      if (jj < nk) {
+        const double* base = QKV + (tok0 + j0 + jj) * 3 * d + h * DH + ii;
+        kv = base[d];
+        vv = base[2 * d];
+      }
+      sK[jj][ii] = kv;
+      sV[jj][ii] = vv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < KT / 16; ++t) {
+      if (t * 16 >= nk) break;                          // uniform over the workgroup
+      f64x4 st = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        st = __builtin_amdgcn_mfma_f64_16x16x4f64(sK[t * 16 + qi][4 * s + g], qf[s], st, 0, 0, 0);
+      double p[4], tmax = -INFINITY;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int key = j0 + t * 16 + g + 4 * rr;
+        p[rr] = key < n ? st[rr] * scale : -INFINITY;
+        tmax = fmax(tmax, p[rr]);
+      }
+      tmax = fmax(tmax, __shfl_xor(tmax, 16));
+      tmax = fmax(tmax, __shfl_xor(tmax, 32));
+      const double mnew = fmax(mrun, tmax);
+      const double corr = exp(mrun - mnew);             // 0 on the first tile
+      lpart *= corr;
+#pragma unroll
+      for (int u = 0; u < NT; ++u)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) acc[u][rr] *= corr;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        p[rr] = exp(p[rr] - mnew);
+        lpart += p[rr];
+      }
+      mrun = mnew;
+#pragma unroll
+      for (int u = 0; u < NT; ++u)
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(sV[t * 16 + 4 * s + g][u * 16 + qi], p[s], acc[u], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double lsum = lpart + __shfl_xor(lpart, 16);
+  lsum += __shfl_xor(lsum, 32);
+  if (qv) {
+#pragma unroll
+    for (int u = 0; u < NT; ++u)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) O[(tok0 + q) * d + h * DH + u * 16 + g + 4 * rr] = acc[u][rr] / lsum;
+  }
+}
+
+// User attention (as k_user_attn): DH consecutive lanes per (slot, head,
+// query row), lane i holding feature i, max_K query rows per (slot, head).
+// Scores are summed across the group's lanes and broadcast from its first
+// lane, so every lane applies the same softmax; loads and stores are whole
+// head rows.  DH divides 64, so a group never straddles a wave.
 template <int DH>
 __global__ __launch_bounds__(256) void k_user_attn64(StepCtx c, const double* __restrict__ QKV,
-                                                     double* __restrict__ O, int d, int heads) {
+                                                     double* __restrict__ O, int d, int heads, int max_K) {
   const long item = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long per_slot = (long)heads * kMaxK;
-  const long s = item / per_slot;
-  if (s >= c.total_slots) return;
-  const int rem = (int)(item - s * per_slot);
-  const int h = rem / kMaxK, kq = rem - h * kMaxK;
-  const DevBin& b = c.bins[c.slot_bin[s]];
-  if (kq >= b.K || b.st->phase == kDone) return;
-  const int n = b.n, l = (int)(s - b.slot_off), K = b.K;
-  const long tq = (long)b.tok_off + (long)kq * n + l;
+  const int i = (int)(item % DH);
+  const long grp = item / DH;
+  const long per_slot = (long)heads * max_K;
+  const long s = grp / per_slot;
+  bool live = s < c.total_slots;
+  int h = 0, kq = 0, n = 1, K = 1;
+  long tok_l = 0;                                    // token of user 0 at this slot
+  if (live) {
+    const int rem = (int)(grp - s * per_slot);
+    h = rem / max_K;
+    kq = rem - h * max_K;
+    const DevBin& b = c.bins[c.slot_bin[s]];
+    live = kq < b.K && b.st->phase != kDone;
+    n = b.n;
+    K = b.K;
+    tok_l = (long)b.tok_off + (s - b.slot_off);
+  }
+  if (!live) K = 0;                                  // uniform per group: no score, no store
+  const int lead = (int)(threadIdx.x & 63) & ~(DH - 1);
   const double scale = 1.0 / sqrt((double)DH);
+  const double qv = live ? QKV[(tok_l + (long)kq * n) * 3 * d + h * DH + i] : 0.0;
   double sc[kMaxK];
   double mx = -INFINITY;
-  for (int j = 0; j < K; ++j) {
-    const long tk = (long)b.tok_off + (long)j * n + l;
-    double a = 0.0;
-    for (int i = 0; i < DH; ++i) a = fma(QKV[tq * 3 * d + h * DH + i], QKV[tk * 3 * d + d + h * DH + i], a);
-    sc[j] = a * scale;
-    mx = fmax(mx, sc[j]);
+#pragma unroll
+  for (int j = 0; j < kMaxK; ++j) {
+    if (j < K) {
+      double a = qv * QKV[(tok_l + (long)j * n) * 3 * d + d + h * DH + i];
+#pragma unroll
+      for (int off = DH / 2; off >= 1; off >>= 1) a += __shfl_xor(a, off);
+      a = __shfl(a, lead);
+      sc[j] = a * scale;
+      mx = fmax(mx, sc[j]);
+    }
   }
-  double lsum = 0.0;
-  for (int j = 0; j < K; ++j) {
-    sc[j] = exp(sc[j] - mx);
-    lsum += sc[j];
+  double lsum = 0.0, o = 0.0;
+#pragma unroll
+  for (int j = 0; j < kMaxK; ++j) {
+    if (j < K) {
+      sc[j] = exp(sc[j] - mx);
+      lsum += sc[j];
+      o = fma(sc[j], QKV[(tok_l + (long)j * n) * 3 * d + 2 * d + h * DH + i], o);
+    }
   }
-  for (int i = 0; i < DH; ++i) {
-    double o = 0.0;
-    for (int j = 0; j < K; ++j) o = fma(sc[j], QKV[((long)b.tok_off + (long)j * n + l) * 3 * d + 2 * d + h * DH + i], o);
-    O[tq * d + h * DH + i] = o / lsum;
-  }
+  if (live) O[(tok_l + (long)kq * n) * d + h * DH + i] = o / lsum;
 }
 
 // ---------------------------------------------------------------------------
@@ -745,8 +859,16 @@ hipError_t launch_layernorm64(long T, int d, const double* R, const double* g, c
 hipError_t launch_row_attn64(const StepCtx& c, const double* QKV, double* O, int d, int heads, int max_n,
                              hipStream_t s) {
   if (c.total_rows == 0) return hipSuccess;
-  dim3 grid((unsigned)(c.total_rows * heads), (unsigned)((max_n + kQ64 - 1) / kQ64)), block(kQ64);
   const int dh = d / heads;
+  if (kRowAttn64Mfma) {
+    dim3 grid((unsigned)(c.total_rows * heads), (unsigned)((max_n + 63) / 64)), block(256);
+    if (dh == 16) hipLaunchKernelGGL(k_row_attn64_mfma<16>, grid, block, 0, s, c, QKV, O, d, heads);
+    else if (dh == 32) hipLaunchKernelGGL(k_row_attn64_mfma<32>, grid, block, 0, s, c, QKV, O, d, heads);
+    else if (dh == 64) hipLaunchKernelGGL(k_row_attn64_mfma<64>, grid, block, 0, s, c, QKV, O, d, heads);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
+  dim3 grid((unsigned)(c.total_rows * heads), (unsigned)((max_n + kQ64 - 1) / kQ64)), block(kQ64);
   if (dh == 16) hipLaunchKernelGGL(k_row_attn64<16>, grid, block, 0, s, c, QKV, O, d, heads);
   else if (dh == 32) hipLaunchKernelGGL(k_row_attn64<32>, grid, block, 0, s, c, QKV, O, d, heads);
   else if (dh == 64) hipLaunchKernelGGL(k_row_attn64<64>, grid, block, 0, s, c, QKV, O, d, heads);
@@ -754,14 +876,16 @@ hipError_t launch_row_attn64(const StepCtx& c, const double* QKV, double* O, int
   return hipGetLastError();
 }
 
-hipError_t launch_user_attn64(const StepCtx& c, const double* QKV, double* O, int d, int heads, hipStream_t s) {
+hipError_t launch_user_attn64(const StepCtx& c, const double* QKV, double* O, int d, int heads, int max_K,
+                              hipStream_t s) {
   if (c.total_slots == 0) return hipSuccess;
-  const long items = (long)c.total_slots * heads * kMaxK;
-  dim3 grid((unsigned)((items + 255) / 256)), block(256);
+  if (max_K < 1 || max_K > kMaxK) return hipErrorInvalidValue;
   const int dh = d / heads;
-  if (dh == 16) hipLaunchKernelGGL(k_user_attn64<16>, grid, block, 0, s, c, QKV, O, d, heads);
-  else if (dh == 32) hipLaunchKernelGGL(k_user_attn64<32>, grid, block, 0, s, c, QKV, O, d, heads);
-  else if (dh == 64) hipLaunchKernelGGL(k_user_attn64<64>, grid, block, 0, s, c, QKV, O, d, heads);
+  const long items = (long)c.total_slots * heads * max_K * dh;
+  dim3 grid((unsigned)((items + 255) / 256)), block(256);
+  if (dh == 16) hipLaunchKernelGGL(k_user_attn64<16>, grid, block, 0, s, c, QKV, O, d, heads, max_K);
+  else if (dh == 32) hipLaunchKernelGGL(k_user_attn64<32>, grid, block, 0, s, c, QKV, O, d, heads, max_K);
+  else if (dh == 64) hipLaunchKernelGGL(k_user_attn64<64>, grid, block, 0, s, c, QKV, O, d, heads, max_K);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
