@@ -249,8 +249,10 @@ hipError_t launch_layernorm(int prec, long T, int d, const float* R, const float
 hipError_t launch_gemm_bf16(int epi, const GemmArgs& g, const Mat& W, hipStream_t s, int tile);
 int gemm_tile_count(int epi, int N, bool ln);
 hipError_t launch_mlp_bf16(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s,
-                           int tile);
+                           int tile, void* hid);
 int mlp_tile_count(int D);
+int mlp_default_tile(int D);
+int gemm_default_tile(int epi, int N, bool ln);
 bool gate_fusable(int d);
 bool mlp3_ok(int d, int F);
 bool proj3_ok(int d);

@@ -385,8 +385,10 @@ TuneKey tune_key(int epi, const GemmArgs& g) {
 }
 
 int tile_for(cider_weights* w, int epi, const GemmArgs& g) {
-  auto it = w->tune.find(tune_key(epi, g));
-  return it == w->tune.end() ? 0 : it->second.tile;
+  const TuneKey key = tune_key(epi, g);
+  auto it = w->tune.find(key);
+  if (it != w->tune.end()) return it->second.tile;
+  return epi == kMlpKey ? mlp_default_tile(g.N) : gemm_default_tile(epi, g.N, key.ln != 0);
 }
 
 // The variant of a token-resident kernel (key kOprojMlpKey / kUserMlpKey)
@@ -709,7 +711,7 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
       } else {
         int mt = tile_for(w, kMlpKey, g);
         if (r.forced_tile >= 0) mt = r.forced_tile < mlp_tile_count(d) ? r.forced_tile : 0;
-        TIMED("mlp_fused", launch_mlp_bf16(g, L.W1, L.b1, L.W2, F, s, mt));
+        TIMED("mlp_fused", launch_mlp_bf16(g, L.W1, L.b1, L.W2, F, s, mt, k.HID));
       }
     } else {
       g = GemmArgs{}; g.M = T;
@@ -730,7 +732,7 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
   return CIDER_OK;
 }
 
-int tune_mlp(cider_weights* w, const GemmArgs& g, const DevLayer& L, int F, hipStream_t s) {
+int tune_mlp(cider_weights* w, const GemmArgs& g, const DevLayer& L, int F, void* hid, hipStream_t s) {
   TuneKey key = tune_key(kMlpKey, g);
   if (w->tune.count(key)) return CIDER_OK;
   const int cand = mlp_tile_count(g.N);
@@ -740,11 +742,11 @@ int tune_mlp(cider_weights* w, const GemmArgs& g, const DevLayer& L, int F, hipS
   double best = 1e30, dflt = 0;
   int best_t = 0;
   for (int t = 0; t < cand; ++t) {
-    if (launch_mlp_bf16(g, L.W1, L.b1, L.W2, F, s, t) != hipSuccess) { (void)hipGetLastError(); continue; }
+    if (launch_mlp_bf16(g, L.W1, L.b1, L.W2, F, s, t, hid) != hipSuccess) { (void)hipGetLastError(); continue; }
     double tmin = 1e30;
     for (int rep = 0; rep < 3; ++rep) {
       HIPCHK(hipEventRecord(a, s));
-      HIPCHK(launch_mlp_bf16(g, L.W1, L.b1, L.W2, F, s, t));
+      HIPCHK(launch_mlp_bf16(g, L.W1, L.b1, L.W2, F, s, t, hid));
       HIPCHK(hipEventRecord(b, s));
       HIPCHK(hipEventSynchronize(b));
       float ms = 0.f;
@@ -784,7 +786,7 @@ int autotune_forward(cider_weights* w, const Run& r, hipStream_t s) {
   if (r.prec == kBF16 && !mlp3_ok(d, F)) {
     g = GemmArgs{}; g.M = T; g.N = d; g.Kd = d; g.A = k.XN; g.bias = L.b2; g.R = k.R;
     g.ln_g = L.ln1_g; g.ln_b = L.ln1_b; g.out = k.XN;
-    if ((rc = tune_mlp(w, g, L, F, s))) return rc;
+    if ((rc = tune_mlp(w, g, L, F, k.HID, s))) return rc;
   }
   // the token-resident kernels with variants (the same choice as the forward's)
   const bool user_mlp = r.prec == kBF16 && r.use_blocks && user_mlp_tr_ok(d, m.heads, F);

@@ -107,7 +107,8 @@ namespace {
 
 constexpr int GPAD = 8;
 
-enum : int { kEpiResidLN = 4, kEpiGateLN = 5, kEpiResidLN8 = 6, kEpiGateLN8 = 7, kEpiResidProj = 8 };
+enum : int { kEpiResidLN = 4, kEpiGateLN = 5, kEpiResidLN8 = 6, kEpiGateLN8 = 7, kEpiResidProj = 8,
+             kEpiGeluB0 = 9 };   // GELU with the accumulators started at the bias (the fused MLP's up order)
 
 typedef int i32x8 __attribute__((__vector_size__(8 * sizeof(int))));
 typedef int i32x4 __attribute__((__vector_size__(4 * sizeof(int))));
@@ -133,7 +134,7 @@ __device__ __forceinline__ void row_pass(const float* sC, long m0, int n0, const
   constexpr int GPL = (CG + LPR - 1) / LPR;      // column groups per lane
   constexpr int NIT = BM / (4 * RPI);            // passes per wave
   constexpr int CH = (NIT * GPL <= 16) ? NIT : (16 / GPL > 0 ? 16 / GPL : 1);
-  constexpr bool RES = EPI != kEpiStore && EPI != kEpiGelu;
+  constexpr bool RES = EPI != kEpiStore && EPI != kEpiGelu && EPI != kEpiGeluB0;
   constexpr bool GATE = EPI == kEpiGate || EPI == kEpiGateLN || EPI == kEpiGateLN8;
   constexpr bool F8OUT = EPI == kEpiResidLN8 || EPI == kEpiGateLN8;
   constexpr bool PROJ = EPI == kEpiResidProj;   // final LayerNorm + symbol projection
@@ -174,7 +175,7 @@ __device__ __forceinline__ void row_pass(const float* sC, long m0, int n0, const
         if (cg >= CG || !mv) continue;
         f32x4 v = vv[it][u];
         if (!RES) {
-          if (EPI == kEpiGelu) {
+          if (EPI == kEpiGelu || EPI == kEpiGeluB0) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) v[r] = gelu_f(v[r]);
           }
@@ -286,6 +287,104 @@ __device__ __forceinline__ void row_pass(const float* sC, long m0, int n0, const
   }
 }
 
+// The LayerNorm of the residual row pass as a kernel of its own, over R as
+// the plain residual GEMM left it: the same lanes per row, the same column
+// groups per lane and the same order of every sum and shuffle as row_pass
+// (EPI = ResidLN, BN = N), so XN is bit-identical to the fused epilogue's.
+// Lets a LayerNorm-fed residual GEMM run with the plain tiles, whose weight
+// traffic per token is far lower than a full-row tile's when N is large.
+template <int BN, bool PROJ>
+__global__ __launch_bounds__(256) void k_ln_rows(GemmArgs g) {
+  constexpr int CG = BN / 4;
+  constexpr int LPR = CG <= 16 ? 16 : (CG <= 32 ? 32 : 64);
+  constexpr int RPI = 64 / LPR;
+  constexpr int GPL = (CG + LPR - 1) / LPR;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, grp = lane / LPR, cl = lane % LPR;
+  const long m = ((long)blockIdx.x * 4 + wave) * RPI + grp;
+  const bool mv = m < g.M;
+  f32x4 vv[GPL];
+  float sum = 0.f;
+#pragma unroll
+  for (int u = 0; u < GPL; ++u) {
+    const int cg = cl + u * LPR;
+    if (cg >= CG || !mv) continue;
+    vv[u] = *(const f32x4*)(g.R + m * BN + cg * 4);
+    sum += (vv[u][0] + vv[u][1]) + (vv[u][2] + vv[u][3]);
+  }
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+  const float mean = sum / (float)BN;
+  float q = 0.f;
+#pragma unroll
+  for (int u = 0; u < GPL; ++u) {
+    const int cg = cl + u * LPR;
+    if (cg >= CG || !mv) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float dv = vv[u][r] - mean;
+      q = fmaf(dv, dv, q);
+    }
+  }
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
+  const float rstd = 1.0f / sqrtf(q / (float)BN + 1e-5f);
+  if (PROJ) {
+    // the final LayerNorm and the two-way symbol projection (row_pass's PROJ)
+    float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+    for (int u = 0; u < GPL; ++u) {
+      const int cg = cl + u * LPR;
+      if (cg >= CG || !mv) continue;
+      const int c = cg * 4;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float hv = (vv[u][r] - mean) * rstd * g.ln_g[c + r] + g.ln_b[c + r];
+        a0 = fmaf(hv, g.proj_w[c + r], a0);
+        a1 = fmaf(hv, g.proj_w[BN + c + r], a1);
+      }
+    }
+#pragma unroll
+    for (int o = LPR / 2; o > 0; o >>= 1) {
+      a0 += __shfl_xor(a0, o, 64);
+      a1 += __shfl_xor(a1, o, 64);
+    }
+    if (cl == 0 && mv) {
+      g.proj_out[2 * m] = a0;
+      g.proj_out[2 * m + 1] = a1;
+    }
+    return;
+  }
+  bf16* __restrict__ Og = (bf16*)g.out;
+#pragma unroll
+  for (int u = 0; u < GPL; ++u) {
+    const int cg = cl + u * LPR;
+    if (cg >= CG || !mv) continue;
+    const int c = cg * 4;
+    bf16x4 h;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h[r] = (bf16)((vv[u][r] - mean) * rstd * g.ln_g[c + r] + g.ln_b[c + r]);
+    *(bf16x4*)(Og + m * BN + c) = h;
+  }
+}
+
+hipError_t launch_ln_rows(const GemmArgs& g, hipStream_t s) {
+  const int rpb = 4 * (64 / ((g.N / 4) <= 16 ? 16 : ((g.N / 4) <= 32 ? 32 : 64)));   // rows per workgroup
+  dim3 grid((unsigned)((g.M + rpb - 1) / rpb)), block(256);
+  const bool pj = g.proj_out != nullptr;
+#define CIDER_LNR(N)                                                               \
+  case N:                                                                          \
+    if (pj) hipLaunchKernelGGL((k_ln_rows<N, true>), grid, block, 0, s, g);        \
+    else hipLaunchKernelGGL((k_ln_rows<N, false>), grid, block, 0, s, g);          \
+    break;
+  switch (g.N) {
+    CIDER_LNR(64) CIDER_LNR(128) CIDER_LNR(192) CIDER_LNR(256)
+    CIDER_LNR(320) CIDER_LNR(384) CIDER_LNR(448) CIDER_LNR(512)
+    default: return hipErrorInvalidValue;
+  }
+#undef CIDER_LNR
+  return hipGetLastError();
+}
+
 // Workgroups of 4 waves that LDS lets share a CU: the register budget the
 // compiler may use without lowering occupancy below what LDS already sets.
 constexpr int lds_waves(size_t bytes) {
@@ -342,11 +441,19 @@ void k_gemm_bf16(GemmArgs g, const bf16* __restrict__ W) {
     }
   };
 
+  // B0: the accumulators start at the bias (columns wn + 16 i + 4 (lane/16) + r)
+  constexpr bool B0 = EPI == kEpiGeluB0;
   f32x4 acc[TI][TJ];
 #pragma unroll
-  for (int i = 0; i < TI; ++i)
+  for (int i = 0; i < TI; ++i) {
+    f32x4 a0 = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (B0 && g.bias) {
+      const int nl = n0 + wn + i * 16 + (lane >> 4) * 4;
+      a0 = f32x4{g.bias[nl], g.bias[nl + 1], g.bias[nl + 2], g.bias[nl + 3]};
+    }
 #pragma unroll
-    for (int j = 0; j < TJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < TJ; ++j) acc[i][j] = a0;
+  }
 
   const int nk = Kd / BK;
   fetch(0);
@@ -379,7 +486,7 @@ void k_gemm_bf16(GemmArgs g, const bf16* __restrict__ W) {
   for (int i = 0; i < TI; ++i) {
     const int nl = wn + i * 16 + (lane >> 4) * 4;
     f32x4 bias = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (g.bias) {
+    if (g.bias && !B0) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) bias[r] = g.bias[n0 + nl + r];
     }
@@ -400,6 +507,7 @@ hipError_t gemm_bf16_t(int epi, const GemmArgs& g, const bf16* W, hipStream_t s)
   switch (epi) {
     case kEpiStore: hipLaunchKernelGGL((k_gemm_bf16<BM, BN, BK, kEpiStore>), grid, block, 0, s, g, W); break;
     case kEpiGelu: hipLaunchKernelGGL((k_gemm_bf16<BM, BN, BK, kEpiGelu>), grid, block, 0, s, g, W); break;
+    case kEpiGeluB0: hipLaunchKernelGGL((k_gemm_bf16<BM, BN, BK, kEpiGeluB0>), grid, block, 0, s, g, W); break;
     case kEpiResid: hipLaunchKernelGGL((k_gemm_bf16<BM, BN, BK, kEpiResid>), grid, block, 0, s, g, W); break;
     case kEpiGate: hipLaunchKernelGGL((k_gemm_bf16<BM, BN, BK, kEpiGate>), grid, block, 0, s, g, W); break;
     case kEpiResidLN: hipLaunchKernelGGL((k_gemm_bf16<BM, BN, BK, kEpiResidLN>), grid, block, 0, s, g, W); break;
@@ -418,10 +526,22 @@ hipError_t gemm_bf16_t(int epi, const GemmArgs& g, const bf16* W, hipStream_t s)
 // LayerNorm always spans the full row, so the choice never changes a result;
 // the autotuner picks among them by measured time.
 //   plain epilogues : 0 = 128x128, 1 = 64x128, 2 = 128x64, 3 = 64x64 (BM x BN)
-//   LayerNorm fused : BN = N, 0 = BM 128 (N <= 128) or 64, 1 = BM 64, 2 = BM 32
+//   LayerNorm fused : BN = N, 0 = BM 128 (N <= 128) or 64, 1 = BM 64, 2 = BM 32;
+//                     for a residual GEMM with a BF16 LayerNorm output, then
+//                     the plain tiles followed by k_ln_rows (same result)
+static int ln_fused_tiles(int N) { return N <= 128 ? 3 : 2; }
+static int plain_tiles(int N) { return (N % 128 == 0) ? 4 : 2; }
 int gemm_tile_count(int epi, int N, bool ln) {
-  if (ln) return N <= 128 ? 3 : 2;
-  return (N % 128 == 0) ? 4 : 2;
+  if (ln) return ln_fused_tiles(N) + (epi == kEpiResid ? plain_tiles(N) : 0);
+  return plain_tiles(N);
+}
+
+// The tile used before (or without) tuning: a full-row tile re-streams the
+// whole weight matrix for every 32-64 tokens, which at N >= 320 costs more
+// than the split form's extra pass over R (measured at d = 384: 0.38 against
+// 0.75 ms per output projection).
+int gemm_default_tile(int epi, int N, bool ln) {
+  return (ln && epi == kEpiResid && N >= 320 && N % 64 == 0 && N <= 512) ? ln_fused_tiles(N) : 0;
 }
 
 // epi: Store, Gelu, Resid, Gate; with ln_g set (Resid / Gate) the next
@@ -430,6 +550,19 @@ hipError_t launch_gemm_bf16(int epi, const GemmArgs& g, const Mat& W, hipStream_
   if (g.M == 0) return hipSuccess;
   if (g.Kd % 64 != 0) return hipErrorInvalidValue;
   const bool ln = (epi == kEpiResid || epi == kEpiGate) && g.ln_g != nullptr;
+  if (ln && tile >= ln_fused_tiles(g.N)) {
+    if (epi != kEpiResid || g.out_scale || g.proj_out || g.N % 64 != 0 || g.N > 512) {
+      tile = 0;                                   // no split form: the default fused tile
+    } else {
+      // residual GEMM with a plain tile, then the row LayerNorm over R
+      GemmArgs gr = g;
+      gr.ln_g = gr.ln_b = nullptr;
+      gr.out = nullptr;
+      const hipError_t e = launch_gemm_bf16(kEpiResid, gr, W, s, tile - ln_fused_tiles(g.N));
+      if (e != hipSuccess) return e;
+      return launch_ln_rows(g, s);
+    }
+  }
   if (ln) {
     const bool f8 = g.out_scale != nullptr;
     const int e = epi == kEpiResid ? (f8 ? kEpiResidLN8 : kEpiResidLN) : (f8 ? kEpiGateLN8 : kEpiGateLN);
@@ -661,14 +794,44 @@ hipError_t gate_t(const GemmArgs& g, const bf16* W1, const float* b1, const bf16
 // Fused-MLP tile shapes (BM tokens, FCH hidden columns per chunk).  The
 // hidden dimension is always consumed in 32-wide MFMA steps from 0 up, so every
 // shape gives the same result; the autotuner picks by time.
-int mlp_tile_count(int D) { return D == 128 ? 4 : (D == 64 || D == 256 ? 2 : 1); }
+// Fused tiles per width, then two split forms: the up projection as a GEMM
+// whose accumulators start at b1 (the fused kernel's order) with GELU into
+// the hidden buffer, the down projection as a plain residual GEMM (128- or
+// 64-token tiles) and the row LayerNorm (or final LayerNorm and projection)
+// after it -- bit-identical to the fused kernel, with the weights streamed
+// per 128 tokens instead of per 32-64.
+static int mlp_fused_tiles(int D) { return D == 128 ? 4 : (D == 64 || D == 256 ? 2 : 1); }
+int mlp_tile_count(int D) { return mlp_fused_tiles(D) + 2; }
+// Widths whose fused kernel runs 32-token tiles start on the split form
+// (measured at d = 384: 1.39 against 2.86 ms per MLP).
+int mlp_default_tile(int D) { return D >= 320 ? mlp_fused_tiles(D) : 0; }
 
 // R += W2 GELU(W1 XN + b1) + b2 (g.A = XN, g.bias = b2, g.R = R, and with
 // g.ln_g set the next LayerNorm into g.out).
 hipError_t launch_mlp_bf16(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s,
-                           int tile) {
+                           int tile, void* hid) {
   if (g.M == 0) return hipSuccess;
   const bool ln = g.ln_g != nullptr;
+  if (tile >= mlp_fused_tiles(g.N)) {
+    const int sp = tile - mlp_fused_tiles(g.N);
+    if (!hid || !ln || g.out_scale || F % 128 != 0 || g.N % 64 != 0 || g.N > 512 || g.Kd != g.N) {
+      tile = 0;                                   // no split form: the default fused tile
+    } else {
+      GemmArgs gu{};
+      gu.M = g.M; gu.N = F; gu.Kd = g.N; gu.A = g.A; gu.bias = b1; gu.out = hid;
+      hipError_t e = gemm_bf16_t<128, 128, 64>(kEpiGeluB0, gu, W1.b16, s);
+      if (e != hipSuccess) return e;
+      GemmArgs gd = g;
+      gd.A = hid; gd.Kd = F;
+      gd.ln_g = gd.ln_b = nullptr; gd.out = nullptr; gd.proj_w = nullptr; gd.proj_out = nullptr;
+      if (g.N % 128 == 0) e = sp == 0 ? gemm_bf16_t<128, 128, 64>(kEpiResid, gd, W2.b16, s)
+                                      : gemm_bf16_t<64, 128, 64>(kEpiResid, gd, W2.b16, s);
+      else e = sp == 0 ? gemm_bf16_t<128, 64, 64>(kEpiResid, gd, W2.b16, s)
+                       : gemm_bf16_t<64, 64, 64>(kEpiResid, gd, W2.b16, s);
+      if (e != hipSuccess) return e;
+      return launch_ln_rows(g, s);
+    }
+  }
   switch (g.N) {
     case 64:
       if (tile == 1) return mlp_t<32, 64, 64>(ln, g, W1.b16, b1, W2.b16, F, s);
@@ -997,17 +1160,21 @@ hipError_t launch_mlp_fp8(const GemmArgs& g, const Mat& W1, const float* b1, con
 }
 
 // ---------------------------------------------------------------------------
-// Row attention on MFMA.  One workgroup per (row, head): the row's keys K
-// [key][dh] and transposed values V^T [dh][key] for that head are loaded into
-// LDS once (n * dh * 4 bytes <= 128 KB), then each wave takes 16-query tiles
-// and streams the resident keys 64 at a time:
+// Row attention on MFMA, streaming the keys.  One workgroup per (row, head,
+// block of 64 QT queries); each wave owns QT tiles of 16 queries.  The row's
+// keys and values pass through LDS 64 at a time (K [key][dh] and V^T
+// [dh][key] of the chunk; the next chunk is read into registers while the
+// current one is used), and for each of its query tiles a wave forms
 //   S^T = K Q^T       (A = keys from LDS, B = the tile's queries)
 //   O^T += V^T P^T    (A = values from LDS, B = probabilities)
 // so a lane keeps one query (lane % 16): its running max, its sum and its
-// output columns; the online-softmax rescale is applied in FP32.
+// output columns; the online-softmax rescale is applied in FP32.  LDS does
+// not grow with n, so several workgroups share a CU at any row length; each
+// query sees the keys in the same 64-key blocks from 0 up.
 namespace {
 
-constexpr int AKB = 64;   // keys per MFMA block
+constexpr int AKB = 64;   // keys per MFMA block (and per LDS chunk)
+constexpr int AQT = 2;    // query tiles of 16 per wave
 
 template <int DH>
 __global__ __launch_bounds__(256) void k_row_attn_mfma(StepCtx c, const bf16* __restrict__ QKV, bf16* __restrict__ O,
@@ -1015,68 +1182,90 @@ __global__ __launch_bounds__(256) void k_row_attn_mfma(StepCtx c, const bf16* __
   constexpr int DT = DH / 16;                    // output column blocks
   constexpr int QE = (DH == 16) ? 4 : 8;         // dh elements per lane per MFMA
   constexpr int QS = (DH == 64) ? 2 : 1;         // MFMA k-steps over dh
-  constexpr int LDK = DH + 8;
+  constexpr int LDK = DH + 8, LDV = AKB + 8;
+  constexpr int NPC = AKB * DH / 8;              // 8-element pieces of K (and of V) per chunk
+  constexpr int CPT = (NPC + 255) / 256;         // per thread
   typedef __bf16 qv_t __attribute__((__vector_size__(QE * sizeof(__bf16))));
-  extern __shared__ __attribute__((aligned(16))) char smem_attn[];
+  __shared__ __attribute__((aligned(16))) bf16 sK[AKB * LDK];
+  __shared__ __attribute__((aligned(16))) bf16 sVt[DH * LDV];
   const int lb = xcd_logical((int)blockIdx.x, (int)gridDim.x);
   const int r = c.row_first + lb / heads, h = lb - (lb / heads) * heads;
   const DevBin& b = c.bins[c.row_bin[r]];
   if (b.st->phase == kDone) return;
   const int n = b.n, k = r - b.row_off;
-  const int nkp = (n + AKB - 1) / AKB * AKB;     // keys padded to whole blocks
-  const int LDV = nkp + 8;
-  bf16* sK = (bf16*)smem_attn;                   // [nkp][LDK]
-  bf16* sVt = sK + nkp * LDK;                    // [DH][LDV]
+  const int qb = blockIdx.y * (64 * AQT);
+  if (qb >= n) return;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const long tok0 = (long)b.tok_off + (long)k * n;
   const long ld = 3L * d;
   // scores are scaled by log2(e)/sqrt(dh) so the softmax uses exp2 (one v_exp_f32)
   const float scale = 1.4426950408889634f / sqrtf((float)DH);
 
-  for (int idx = tid; idx < nkp * (DH / 8); idx += 256) {
-    const int key = idx / (DH / 8), c8 = (idx - key * (DH / 8)) * 8;
-    bf16x8 kv = bf16x8{0, 0, 0, 0, 0, 0, 0, 0}, vv = kv;
-    if (key < n) {
-      const bf16* base = QKV + (tok0 + key) * ld + h * DH + c8;
-      kv = *(const bf16x8*)(base + d);
-      vv = *(const bf16x8*)(base + 2 * d);
-    }
-    *(bf16x8*)&sK[key * LDK + c8] = kv;
+  bf16x8 pk[CPT], pv[CPT];
+  auto fetch = [&](int j0) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) sVt[(c8 + e) * LDV + key] = vv[e];
-  }
-  __syncthreads();
-
-  for (int q0 = wave * 16; q0 < n; q0 += 64) {
-    const int q = q0 + (lane & 15);
-    const bool qvalid = q < n;
-    qv_t fq[QS];
-#pragma unroll
-    for (int s = 0; s < QS; ++s) {
-      if (qvalid) {
-        fq[s] = *(const qv_t*)(QKV + (tok0 + q) * ld + h * DH + s * 32 + (lane >> 4) * QE);
-      } else {
-#pragma unroll
-        for (int e = 0; e < QE; ++e) fq[s][e] = (bf16)0.f;
+    for (int i = 0; i < CPT; ++i) {
+      const int idx = tid + i * 256, key = idx / (DH / 8), c8 = (idx - key * (DH / 8)) * 8;
+      pk[i] = pv[i] = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+      if (idx < NPC && j0 + key < n) {
+        const bf16* base = QKV + (tok0 + j0 + key) * ld + h * DH + c8;
+        pk[i] = *(const bf16x8*)(base + d);
+        pv[i] = *(const bf16x8*)(base + 2 * d);
       }
     }
-    float mrun = -INFINITY, lsum = 0.f;
-    f32x4 oacc[DT];
+  };
+  auto stash = [&]() {
 #pragma unroll
-    for (int t = 0; t < DT; ++t) oacc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int j0 = 0; j0 < n; j0 += AKB) {
+    for (int i = 0; i < CPT; ++i) {
+      const int idx = tid + i * 256, key = idx / (DH / 8), c8 = (idx - key * (DH / 8)) * 8;
+      if (idx >= NPC) continue;
+      *(bf16x8*)&sK[key * LDK + c8] = pk[i];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) sVt[(c8 + e) * LDV + key] = pv[i][e];
+    }
+  };
+
+  qv_t fq[AQT][QS];
+  float mrun[AQT], lsum[AQT];
+  f32x4 oacc[AQT][DT];
+#pragma unroll
+  for (int a = 0; a < AQT; ++a) {
+    const int q = qb + (wave * AQT + a) * 16 + (lane & 15);
+#pragma unroll
+    for (int s = 0; s < QS; ++s) {
+      if (q < n) {
+        fq[a][s] = *(const qv_t*)(QKV + (tok0 + q) * ld + h * DH + s * 32 + (lane >> 4) * QE);
+      } else {
+#pragma unroll
+        for (int e = 0; e < QE; ++e) fq[a][s][e] = (bf16)0.f;
+      }
+    }
+    mrun[a] = -INFINITY;
+    lsum[a] = 0.f;
+#pragma unroll
+    for (int t = 0; t < DT; ++t) oacc[a][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+
+  fetch(0);
+  for (int j0 = 0; j0 < n; j0 += AKB) {
+    stash();
+    __syncthreads();
+    if (j0 + AKB < n) fetch(j0 + AKB);
+#pragma unroll
+    for (int a = 0; a < AQT; ++a) {
+      if (qb + (wave * AQT + a) * 16 >= n) continue;   // the tile holds no query (uniform per wave)
       // scores of 64 keys: lane holds keys j0 + 16 t + 4 (lane/16) + rr of its query
       f32x4 st[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        f32x4 a = f32x4{0.f, 0.f, 0.f, 0.f};
+        f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < QS; ++s) {
-          const qv_t fk = *(const qv_t*)&sK[(j0 + t * 16 + (lane & 15)) * LDK + s * 32 + (lane >> 4) * QE];
-          if constexpr (DH == 16) a = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fk, fq[s], a, 0, 0, 0);
-          else a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fk, fq[s], a, 0, 0, 0);
+          const qv_t fk = *(const qv_t*)&sK[(t * 16 + (lane & 15)) * LDK + s * 32 + (lane >> 4) * QE];
+          if constexpr (DH == 16) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fk, fq[a][s], acc, 0, 0, 0);
+          else acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fk, fq[a][s], acc, 0, 0, 0);
         }
-        st[t] = a;
+        st[t] = acc;
       }
       // raw scores; keys past n (only in the last block) get -inf
       if (j0 + AKB > n) {
@@ -1094,23 +1283,23 @@ __global__ __launch_bounds__(256) void k_row_attn_mfma(StepCtx c, const bf16* __
       bmax = fmaxf(bmax, __shfl_xor(bmax, 16, 64));
       bmax = xhalf_max(bmax);
       // running max kept in scaled units: p = 2^(scale s - m), one FMA and one v_exp_f32
-      const float mnew = fmaxf(mrun, bmax * scale);
-      const float corr = __builtin_amdgcn_exp2f(mrun - mnew);
+      const float mnew = fmaxf(mrun[a], bmax * scale);
+      const float corr = __builtin_amdgcn_exp2f(mrun[a] - mnew);
       float psum = 0.f;
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-          const float pv = __builtin_amdgcn_exp2f(fmaf(st[t][rr], scale, -mnew));
-          st[t][rr] = pv;
-          psum += pv;
+          const float p = __builtin_amdgcn_exp2f(fmaf(st[t][rr], scale, -mnew));
+          st[t][rr] = p;
+          psum += p;
         }
       psum += __shfl_xor(psum, 16, 64);
       psum = xhalf_sum(psum);
-      lsum = lsum * corr + psum;
-      mrun = mnew;
+      lsum[a] = lsum[a] * corr + psum;
+      mrun[a] = mnew;
 #pragma unroll
-      for (int t = 0; t < DT; ++t) oacc[t] = oacc[t] * corr;
+      for (int t = 0; t < DT; ++t) oacc[a][t] = oacc[a][t] * corr;
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         bf16x8 fp;
@@ -1121,19 +1310,24 @@ __global__ __launch_bounds__(256) void k_row_attn_mfma(StepCtx c, const bf16* __
         }
 #pragma unroll
         for (int t = 0; t < DT; ++t) {
-          const bf16* vrow = &sVt[(t * 16 + (lane & 15)) * LDV + j0];
+          const bf16* vrow = &sVt[(t * 16 + (lane & 15)) * LDV];
           const bf16x4 v0 = *(const bf16x4*)(vrow + (2 * u) * 16 + (lane >> 4) * 4);
           const bf16x4 v1 = *(const bf16x4*)(vrow + (2 * u + 1) * 16 + (lane >> 4) * 4);
           bf16x8 fv = {v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
-          oacc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fv, fp, oacc[t], 0, 0, 0);
+          oacc[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fv, fp, oacc[a][t], 0, 0, 0);
         }
       }
     }
-    if (qvalid) {
-      const float inv = 1.0f / lsum;
+    __syncthreads();                              // every wave is done with this chunk
+  }
+#pragma unroll
+  for (int a = 0; a < AQT; ++a) {
+    const int q = qb + (wave * AQT + a) * 16 + (lane & 15);
+    if (q < n) {
+      const float inv = 1.0f / lsum[a];
 #pragma unroll
       for (int t = 0; t < DT; ++t) {
-        const f32x4 v = oacc[t] * inv;
+        const f32x4 v = oacc[a][t] * inv;
         bf16x4 hv = {(bf16)v[0], (bf16)v[1], (bf16)v[2], (bf16)v[3]};
         *(bf16x4*)(O + (tok0 + q) * d + h * DH + t * 16 + (lane >> 4) * 4) = hv;
       }
@@ -1143,31 +1337,20 @@ __global__ __launch_bounds__(256) void k_row_attn_mfma(StepCtx c, const bf16* __
 
 }  // namespace
 
+// LDS of the row attention: one 64-key chunk of K and V^T, whatever n is.
 size_t row_attn_mfma_lds(int max_n, int dh) {
-  const int nkp = (max_n + AKB - 1) / AKB * AKB;
-  return (size_t)nkp * (dh + 8) * 2 + (size_t)dh * (nkp + 8) * 2;
+  (void)max_n;
+  return (size_t)AKB * (dh + 8) * 2 + (size_t)dh * (AKB + 8) * 2;
 }
 
 hipError_t launch_row_attn_mfma(const StepCtx& c, const void* QKV, void* O, int d, int heads, int max_n,
                                 hipStream_t s) {
   if (c.total_rows == 0) return hipSuccess;
   const int dh = d / heads;
-  const size_t lds = row_attn_mfma_lds(max_n, dh);
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
-  dim3 grid((unsigned)(c.total_rows * heads)), block(256);
-  // raise the dynamic-LDS limit once per instance (idempotent; allowed while capturing)
-  static bool attr_set[3] = {false, false, false};
-  const int which = dh == 16 ? 0 : (dh == 32 ? 1 : 2);
-  if (!attr_set[which]) {
-    const void* fn = dh == 16 ? (const void*)k_row_attn_mfma<16>
-                              : (dh == 32 ? (const void*)k_row_attn_mfma<32> : (const void*)k_row_attn_mfma<64>);
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr_set[which] = true;
-  }
-  if (dh == 16) hipLaunchKernelGGL((k_row_attn_mfma<16>), grid, block, lds, s, c, (const bf16*)QKV, (bf16*)O, d, heads);
-  else if (dh == 32) hipLaunchKernelGGL((k_row_attn_mfma<32>), grid, block, lds, s, c, (const bf16*)QKV, (bf16*)O, d, heads);
-  else if (dh == 64) hipLaunchKernelGGL((k_row_attn_mfma<64>), grid, block, lds, s, c, (const bf16*)QKV, (bf16*)O, d, heads);
+  dim3 grid((unsigned)(c.total_rows * heads), (unsigned)((max_n + 64 * AQT - 1) / (64 * AQT))), block(256);
+  if (dh == 16) hipLaunchKernelGGL((k_row_attn_mfma<16>), grid, block, 0, s, c, (const bf16*)QKV, (bf16*)O, d, heads);
+  else if (dh == 32) hipLaunchKernelGGL((k_row_attn_mfma<32>), grid, block, 0, s, c, (const bf16*)QKV, (bf16*)O, d, heads);
+  else if (dh == 64) hipLaunchKernelGGL((k_row_attn_mfma<64>), grid, block, 0, s, c, (const bf16*)QKV, (bf16*)O, d, heads);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
