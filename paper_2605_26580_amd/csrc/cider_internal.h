@@ -255,6 +255,7 @@ int mlp_default_tile(int D);
 int gemm_default_tile(int epi, int N, bool ln);
 bool gate_fusable(int d);
 bool mlp3_ok(int d, int F);
+bool qkv3_ok(int d);
 bool proj3_ok(int d);
 hipError_t launch_proj3_bf16(const GemmArgs& g, const Mat& W, hipStream_t s, bool gelu = false);
 hipError_t launch_oproj3_bf16(const GemmArgs& g, const Mat& W, hipStream_t s, bool gate = false);

@@ -550,7 +550,7 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
     return p3 ? launch_oproj3_bf16(g, W, s) : gemm(kEpiResid, g, W);
   };
   auto qkv = [&](GemmArgs& g, const Mat& W, long tok0 = 0) -> hipError_t {
-    if (p3) return launch_proj3_bf16(g, W, s);
+    if (prec == kBF16 && qkv3_ok(d)) return launch_proj3_bf16(g, W, s);
     if (!f8) return gemm(kEpiStore, g, W);
     g.A = k.XN8 + tok0 * d;
     g.a_scale = k.xscale + tok0;
@@ -777,8 +777,10 @@ int autotune_forward(cider_weights* w, const Run& r, hipStream_t s) {
   const bool blocks = r.prec == kBF16 && r.use_blocks && attn_block_ok(d, m.heads, r.ctx.max_n, false) &&
                       attn_block_ok(d, m.heads, r.ctx.max_n, true);
   if (!blocks && !(r.prec == kBF16 && proj3_ok(d))) {
-    g = GemmArgs{}; g.M = T; g.N = 3 * d; g.Kd = d; g.A = k.XN; g.bias = L.bqkv_r; g.out = k.QKV;
-    if ((rc = tune_gemm(w, "gemm_qkv", kEpiStore, g, L.Wqkv_r, s))) return rc;
+    if (!(r.prec == kBF16 && qkv3_ok(d))) {
+      g = GemmArgs{}; g.M = T; g.N = 3 * d; g.Kd = d; g.A = k.XN; g.bias = L.bqkv_r; g.out = k.QKV;
+      if ((rc = tune_gemm(w, "gemm_qkv", kEpiStore, g, L.Wqkv_r, s))) return rc;
+    }
     g = GemmArgs{}; g.M = T; g.N = d; g.Kd = d; g.A = k.O; g.bias = L.bo_r; g.R = k.R;
     g.ln_g = L.ln2_g; g.ln_b = L.ln2_b; g.out = k.XN;
     if ((rc = tune_gemm(w, "gemm_o_ln", kEpiResid, g, L.Wo_r, s))) return rc;

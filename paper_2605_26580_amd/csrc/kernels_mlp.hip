@@ -2894,7 +2894,7 @@ void k_embed_gate_z(StepCtx c, EmbedW m, EmbedGateArgs a) {
 // out = XN W^T + b (BF16), N a multiple of 32.
 hipError_t launch_proj3_bf16(const GemmArgs& g, const Mat& W, hipStream_t s, bool gelu) {
   if (g.M == 0) return hipSuccess;
-  if (!(g.Kd == 128 || g.Kd == 256 || g.Kd == 512) || g.N % 32 != 0 || g.N <= 0 || g.N > 1536)
+  if (!(g.Kd == 128 || g.Kd == 256 || g.Kd == 384 || g.Kd == 512) || g.N % 32 != 0 || g.N <= 0 || g.N > 1536)
     return hipErrorInvalidValue;
   dim3 grid((unsigned)((g.M + kM3BM - 1) / kM3BM)), block(512);
 #define CIDER_P3(KD, CHB, WPE)                                                                     \
@@ -2903,8 +2903,8 @@ hipError_t launch_proj3_bf16(const GemmArgs& g, const Mat& W, hipStream_t s, boo
     else hipLaunchKernelGGL((k_proj3<KD, CHB, WPE, false>), grid, block, 0, s, g, W.b16);          \
     return hipGetLastError();                                                                      \
   }
-  CIDER_P3(128, 4, 2) CIDER_P3(128, 1, 4) CIDER_P3(256, 2, 4) CIDER_P3(256, 1, 4) CIDER_P3(512, 2, 2)
-  CIDER_P3(512, 1, 2)
+  CIDER_P3(128, 4, 2) CIDER_P3(128, 1, 4) CIDER_P3(256, 2, 4) CIDER_P3(256, 1, 4) CIDER_P3(384, 2, 2)
+  CIDER_P3(384, 1, 2) CIDER_P3(512, 2, 2) CIDER_P3(512, 1, 2)
 #undef CIDER_P3
   return hipErrorInvalidValue;
 }
@@ -2926,6 +2926,9 @@ hipError_t launch_oproj3_bf16(const GemmArgs& g, const Mat& W, hipStream_t s, bo
 }
 
 bool proj3_ok(int d) { return d == 128 || d == 256; }
+
+// The token-resident QKV projection (input width d, 3d outputs).
+bool qkv3_ok(int d) { return d == 128 || d == 256 || d == 384 || d == 512; }
 
 bool mlp3_ok(int d, int F) { return (d == 128 || d == 256) && F % kM3FCH == 0 && F >= kM3FCH && F <= kM3MaxF; }
 
