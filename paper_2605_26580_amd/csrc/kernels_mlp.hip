@@ -110,6 +110,55 @@ __device__ __forceinline__ int m3_sigma(int j) {
   return 16 * (q >> 1) + 8 * g + 4 * (q & 1) + i;
 }
 
+// One wave's share of the LDS DMA of an MLP weight chunk: rows sigma(0..31)
+// of the chunk of W1 (row stride ld1) and the chunk's 32 columns of W2 (row
+// stride ld2), as 1 KB blocks of 16 bytes per lane (rows padded to RB1 / RB2
+// bytes; a pad lane copies something in bounds).  The per-lane source
+// offsets relative to the chunk's first hidden unit are formed once (-1: the
+// lane's bytes lie past its region), so a chunk costs one address add per
+// block instead of a division by the row pitch.
+template <int NW, int N1, int N2, int RB1, int RB2, int W1B, int W2B, int W1A, bool CACHE = true>
+struct M3ChunkDma {
+  static constexpr int KM = (N1 + N2 + NW - 1) / NW;
+  int off[CACHE ? KM : 1];
+  int ld1_, ld2_, wave_, lane_;
+  // offset of block k's lane within its chunk (constant divisors: the region
+  // test is uniform across the wave)
+  __device__ __forceinline__ int offset(int k) const {
+    const int u = wave_ + NW * k;
+    if (u < N1) {
+      const int pos = u * 1024 + lane_ * 16, j = pos / RB1, o = pos - j * RB1;
+      const bool data = o < RB1 - 16;
+      return pos < W1B ? m3_sigma(data ? j : 0) * ld1_ + (data ? o / 2 : 0) : -1;
+    }
+    const int pos = (u - N1) * 1024 + lane_ * 16, j = pos / RB2, o = pos - j * RB2;
+    const bool data = o < RB2 - 16;
+    return pos < W2B ? (data ? j : 0) * ld2_ + (data ? o / 2 : 0) : -1;
+  }
+  __device__ __forceinline__ void init(int wave, int lane, int ld1, int ld2) {
+    ld1_ = ld1;
+    ld2_ = ld2;
+    wave_ = wave;
+    lane_ = lane;
+    if (CACHE) {
+#pragma unroll
+      for (int k = 0; k < KM; ++k) off[CACHE ? k : 0] = (wave + NW * k < N1 + N2) ? offset(k) : -1;
+    }
+  }
+  __device__ __forceinline__ void issue(const bf16* W1, const bf16* W2, int c0, char* base) const {
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+      const int u = wave_ + NW * k;
+      if (u >= N1 + N2) break;
+      const bool first = u < N1;
+      const int o = CACHE ? off[CACHE ? k : 0] : offset(k);
+      const bf16* src = first ? W1 + (long)c0 * ld1_ + o : W2 + c0 + o;
+      char* dst = base + (first ? u * 1024 : W1A + (u - N1) * 1024);
+      if (o >= 0) __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+    }
+  }
+};
+
 // Per-feature vectors of the residual epilogue, staged in LDS at kernel
 // start: bias [D], LayerNorm gain [D] and bias [D], and with the final
 // projection its two rows [2][D].  Reading them from LDS keeps the
@@ -1633,26 +1682,9 @@ void k_user_mlp_tr(StepCtx c, UserMlpArgs a) {
   };
   // ---- MLP chunk c -> ring buffer
   const int nwm = (N1 + N2) / NW + (wave < (N1 + N2) % NW ? 1 : 0);
-  auto dma_m = [&](int ch, int buf) {
-    const int c0 = ch * kM3FCH;
-    char* base = smem + buf * M::buf;
-#pragma unroll
-    for (int k = 0; k < (N1 + N2 + NW - 1) / NW; ++k) {
-      const int u = wave + NW * k;
-      if (u >= N1 + N2) break;
-      const bool first = u < N1;
-      const int pos = (first ? u : u - N1) * 1024 + lane * 16;
-      const int rb = first ? MRB1 : MRB2;
-      const int j = pos / rb, o = pos - j * rb;
-      const bool data = o < rb - 16;
-      const bf16* src;
-      if (first) src = a.W1 + (long)(c0 + m3_sigma(data ? j : 0)) * D + (data ? o / 2 : 0);
-      else src = a.W2 + (long)(data ? j : 0) * F + c0 + (data ? o / 2 : 0);
-      char* dst = base + (first ? 0 : (int)M::w1a) + (pos - lane * 16);
-      if (pos < (first ? (int)M::w1 : (int)M::w2))
-        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
-    }
-  };
+  M3ChunkDma<NW, N1, N2, MRB1, MRB2, (int)M::w1, (int)M::w2, (int)M::w1a> mdma;
+  mdma.init(wave, lane, D, F);
+  auto dma_m = [&](int ch, int buf) { mdma.issue(a.W1, a.W2, ch * kM3FCH, smem + buf * M::buf); };
 
   for (int i = tid; i < 3 * D; i += NTHR) sbias[i] = a.bqkv[i];
   for (int i = tid; i < D; i += NTHR) {
@@ -1939,26 +1971,10 @@ void k_oproj_mlp3(GemmArgs g, const bf16* __restrict__ Wo, const float* __restri
       f[s] = tv ? *(const bf16x8*)(A + tok0 * D + c * KCH + 16 * s + 8 * g2) : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
   };
   const int nwm = (N1 + N2) / NW + (wave < (N1 + N2) % NW ? 1 : 0);
-  auto dma_m = [&](int ch, int buf) {
-    const int c0 = ch * kM3FCH;
-    char* base = wreg + buf * M::buf;
-#pragma unroll
-    for (int k = 0; k < (N1 + N2 + NW - 1) / NW; ++k) {
-      const int u = wave + NW * k;
-      if (u >= N1 + N2) break;
-      const bool first = u < N1;
-      const int pos = (first ? u : u - N1) * 1024 + lane * 16;
-      const int rb = first ? MRB1 : MRB2;
-      const int j = pos / rb, o = pos - j * rb;
-      const bool data = o < rb - 16;
-      const bf16* src;
-      if (first) src = W1 + (long)(c0 + m3_sigma(data ? j : 0)) * D + (data ? o / 2 : 0);
-      else src = W2 + (long)(data ? j : 0) * F + c0 + (data ? o / 2 : 0);
-      char* dst = base + (first ? 0 : (int)M::w1a) + (pos - lane * 16);
-      if (pos < (first ? (int)M::w1 : (int)M::w2))
-        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
-    }
-  };
+  // offsets formed per chunk here: the kernel has no registers to keep them
+  M3ChunkDma<NW, N1, N2, MRB1, MRB2, (int)M::w1, (int)M::w2, (int)M::w1a, false> mdma;
+  mdma.init(wave, lane, D, F);
+  auto dma_m = [&](int ch, int buf) { mdma.issue(W1, W2, ch * kM3FCH, wreg + buf * M::buf); };
 
   for (int i = tid; i < D; i += 512) {
     svo[i] = bo[i];
@@ -2718,26 +2734,9 @@ void k_embed_gate_z(StepCtx c, EmbedW m, EmbedGateArgs a) {
   // ---- chunk ch of the gate MLP -> ring buffer: rows 32 ch + sigma(j) of
   // Wg1's Z half (row stride 2d) and columns 32 ch .. + 32 of Wg2
   const int nwm = (N1 + N2) / NW + (wave < (N1 + N2) % NW ? 1 : 0);
-  auto dma_m = [&](int ch, int buf) {
-    const int c0 = ch * kM3FCH;
-    char* base = wreg + buf * M::buf;
-#pragma unroll
-    for (int k = 0; k < (N1 + N2 + NW - 1) / NW; ++k) {
-      const int u = wave + NW * k;
-      if (u >= N1 + N2) break;
-      const bool first = u < N1;
-      const int pos = (first ? u : u - N1) * 1024 + lane * 16;
-      const int rb = first ? MRB1 : MRB2;
-      const int j = pos / rb, o = pos - j * rb;
-      const bool data = o < rb - 16;                 // else a pad (copy something in bounds)
-      const bf16* src;
-      if (first) src = a.Wg1 + (long)(c0 + m3_sigma(data ? j : 0)) * (2 * D) + (data ? o / 2 : 0);
-      else src = a.Wg2 + (long)(data ? j : 0) * D + c0 + (data ? o / 2 : 0);
-      char* dst = base + (first ? 0 : (int)M::w1a) + (pos - lane * 16);
-      if (pos < (first ? (int)M::w1 : (int)M::w2))
-        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
-    }
-  };
+  M3ChunkDma<NW, N1, N2, MRB1, MRB2, (int)M::w1, (int)M::w2, (int)M::w1a> mdma;
+  mdma.init(wave, lane, 2 * D, D);
+  auto dma_m = [&](int ch, int buf) { mdma.issue(a.Wg1, a.Wg2, ch * kM3FCH, wreg + buf * M::buf); };
   for (int ch = 0; ch < NBUF - 1; ++ch) dma_m(ch, ch);
 
   // ---- this lane's token: its bin, row k, slot l, symbol, mask ratio and
