@@ -497,6 +497,13 @@ def roofline(prof, model, n, K, tokens, kind, workload):
     # its algorithmic HBM rate beside it
     if kind in ("fp32", "fp64") and dom_name.startswith("attn"):
         bound, peak, unit = "alu", PEAK[kind], "TFLOP/s"
+    elif kind == "fp8" and dom_name == "oproj_mlp":
+        # the token-resident d = 256 kernel runs only its MLP up projection in
+        # e4m3: the peak is the time-weighted blend of the two MFMA rates
+        d, F = model.d, model.d_ff
+        f8 = 2 * d * F
+        b16 = flop_role[dom_name] - f8
+        bound, peak, unit = "mfma", round(flop_role[dom_name] / (f8 / PEAK["fp8"] + b16 / PEAK["bf16"]), 1), "TFLOP/s"
     else:
         bound, peak, unit = "mfma", PEAK[kind], "TFLOP/s"
     ach = fl / secs / 1e12

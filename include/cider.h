@@ -60,8 +60,11 @@ extern "C" {
 enum cider_precision {
   CIDER_FP32 = 0,   /* every contraction in FP32 (MFMA 16x16x4 f32)            */
   CIDER_BF16 = 1,   /* GEMM/attention operands BF16, FP32 accumulate           */
-  CIDER_FP8  = 2,   /* GEMM operands OCP e4m3 with per-tensor weight scale and */
-                    /* per-token activation scale, FP32 accumulate             */
+  CIDER_FP8  = 2,   /* LayerNorm-fed GEMM operands OCP e4m3 with per-tensor    */
+                    /* weight scale and per-token activation scale, FP32       */
+                    /* accumulate; at d = 256 (head width 32, binary codes,    */
+                    /* fused blocks on) the BF16 token-resident kernels run    */
+                    /* with only the MLP up projection in e4m3                 */
   CIDER_FP64 = 3    /* every value in double, from the evidence to the reveal  */
                     /* keys (binary path, no quality head): the integer        */
                     /* decisions of a decode come out as an FP64 reference's   */

@@ -108,6 +108,7 @@ struct Mat {
   const bf16* b16 = nullptr;
   const uint8_t* f8 = nullptr;
   float f8_scale = 1.f;   // W ~= f8_scale * fp8(W)
+  const uint8_t* f8p = nullptr;   // W1 only: f8 with each row's columns reordered for the token-resident up projection
   int rows = 0, cols = 0;
 };
 
@@ -270,7 +271,7 @@ hipError_t launch_oproj_user_attn(const StepCtx& c, const void* Orow, const Mat&
 bool oproj_mlp3_ok(int d, int F);
 hipError_t launch_oproj_mlp3_bf16(const GemmArgs& g, const Mat& Wo, const float* bo, const float* lnx_g,
                                   const float* lnx_b, const Mat& W1, const float* b1, const Mat& W2, int F,
-                                  hipStream_t s, int variant = 0);
+                                  hipStream_t s, int variant = 0, bool f8_up = false);
 int oproj_mlp3_variants();
 bool user_mlp_tr_ok(int d, int heads, int F);
 hipError_t launch_user_mlp_tr(const StepCtx& c, void* XN, const DevLayer& L, const GemmArgs& g2, int d, int heads,

@@ -317,7 +317,18 @@ int ensure_pinned(cider_weights* w, size_t need) {
 // the other bins it is batched with.
 enum RowPath : int { kRowGeneral = 0, kRowBlockTr = 1, kRowAttnBlock = 2, kRowQkvAttn = 3, kRowPaths = 4 };
 
+// FP8 at d = 256 runs the BF16 token-resident kernels, with the MLP up
+// projection of the output projection + MLP kernel in e4m3: the precision
+// the kernel choice follows.
+bool fp8_tr_ok(const cider_model_cfg& m) {
+  return m.q <= 2 && user_qkv_attn_ok(m.d, m.heads) && oproj_mlp3_ok(m.d, m.mlp_mult * m.d);
+}
+int choice_prec(const cider_model_cfg& m, int prec, bool use_blocks) {
+  return (prec == kFP8 && use_blocks && fp8_tr_ok(m)) ? kBF16 : prec;
+}
+
 int row_path(const cider_model_cfg& m, int prec, bool use_blocks, int n) {
+  prec = choice_prec(m, prec, use_blocks);
   if (prec != kBF16 || !use_blocks) return kRowGeneral;
   if (row_block_tr_ok(m.d, m.heads, n)) return kRowBlockTr;
   if (attn_block_ok(m.d, m.heads, n, false)) return kRowAttnBlock;
@@ -515,7 +526,10 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
   const DevModel& m = w->dm;
   const StepCtx& c = r.ctx;
   const Work& k = r.work;
-  const int prec = r.prec;
+  // FP8 on the d = 256 token-resident path: BF16 kernels, the MLP up
+  // projection in e4m3
+  const int prec = choice_prec(w->cfg, r.prec, r.use_blocks);
+  const bool f8_up = prec != r.prec;
   const long T = c.total_tokens;
   const int d = m.d, F = m.mlp_mult * m.d;
   auto gemm = [&](int epi, const GemmArgs& g, const Mat& W) -> hipError_t {
@@ -704,7 +718,7 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
         // BF16, d = 256: the user sublayer's output projection + MLP in one kernel (O in, R and XN out)
         g.A = k.O;
         const int v = variant_for(w, r, kOprojMlpKey, d, F, T, oproj_mlp3_variants());
-        TIMED("oproj_mlp", launch_oproj_mlp3_bf16(g, L.Wo_u, L.bo_u, L.ln3_g, L.ln3_b, L.W1, L.b1, L.W2, F, s, v));
+        TIMED("oproj_mlp", launch_oproj_mlp3_bf16(g, L.Wo_u, L.bo_u, L.ln3_g, L.ln3_b, L.W1, L.b1, L.W2, F, s, v, f8_up));
       } else if (mlp3_ok(d, F)) {
         // token-resident MLP: 256 tokens per workgroup, weights streamed once per tile
         TIMED("mlp_fused", launch_mlp3_bf16(g, L.W1, L.b1, L.W2, F, s));
@@ -765,6 +779,9 @@ int tune_mlp(cider_weights* w, const GemmArgs& g, const DevLayer& L, int F, void
 // Tunes every GEMM shape of the forward for this batch size (BF16 only).
 int autotune_forward(cider_weights* w, const Run& r, hipStream_t s) {
   if (r.prec == kF32 || r.prec == kFP64) return CIDER_OK;
+  // FP8 at d = 256 takes the BF16 kernels (its up projection has no variants)
+  const int prec = choice_prec(w->cfg, r.prec, r.use_blocks);
+  const bool f8_up = prec != r.prec;
   const DevModel& m = w->dm;
   const Work& k = r.work;
   const long T = r.ctx.total_tokens;
@@ -774,10 +791,10 @@ int autotune_forward(cider_weights* w, const Run& r, hipStream_t s) {
   GemmArgs g{};
   // the separate QKV / output-projection GEMMs run only where a fused
   // attention block does not
-  const bool blocks = r.prec == kBF16 && r.use_blocks && attn_block_ok(d, m.heads, r.ctx.max_n, false) &&
+  const bool blocks = prec == kBF16 && r.use_blocks && attn_block_ok(d, m.heads, r.ctx.max_n, false) &&
                       attn_block_ok(d, m.heads, r.ctx.max_n, true);
-  if (!blocks && !(r.prec == kBF16 && proj3_ok(d))) {
-    if (!(r.prec == kBF16 && qkv3_ok(d))) {
+  if (!blocks && !(prec == kBF16 && proj3_ok(d))) {
+    if (!(prec == kBF16 && qkv3_ok(d))) {
       g = GemmArgs{}; g.M = T; g.N = 3 * d; g.Kd = d; g.A = k.XN; g.bias = L.bqkv_r; g.out = k.QKV;
       if ((rc = tune_gemm(w, "gemm_qkv", kEpiStore, g, L.Wqkv_r, s))) return rc;
     }
@@ -785,14 +802,14 @@ int autotune_forward(cider_weights* w, const Run& r, hipStream_t s) {
     g.ln_g = L.ln2_g; g.ln_b = L.ln2_b; g.out = k.XN;
     if ((rc = tune_gemm(w, "gemm_o_ln", kEpiResid, g, L.Wo_r, s))) return rc;
   }
-  if (r.prec == kBF16 && !mlp3_ok(d, F)) {
+  if (prec == kBF16 && !mlp3_ok(d, F)) {
     g = GemmArgs{}; g.M = T; g.N = d; g.Kd = d; g.A = k.XN; g.bias = L.b2; g.R = k.R;
     g.ln_g = L.ln1_g; g.ln_b = L.ln1_b; g.out = k.XN;
     if ((rc = tune_mlp(w, g, L, F, k.HID, s))) return rc;
   }
   // the token-resident kernels with variants (the same choice as the forward's)
-  const bool user_mlp = r.prec == kBF16 && r.use_blocks && user_mlp_tr_ok(d, m.heads, F);
-  const bool oproj_mlp = r.prec == kBF16 && r.use_blocks && !user_mlp && user_qkv_attn_ok(d, m.heads) &&
+  const bool user_mlp = prec == kBF16 && r.use_blocks && user_mlp_tr_ok(d, m.heads, F);
+  const bool oproj_mlp = prec == kBF16 && r.use_blocks && !user_mlp && user_qkv_attn_ok(d, m.heads) &&
                          oproj_mlp3_ok(d, F);
   g = GemmArgs{}; g.M = T; g.N = d; g.Kd = d; g.A = k.XN; g.bias = L.b2; g.R = k.R;
   g.ln_g = L.ln1_g; g.ln_b = L.ln1_b; g.out = k.XN;
@@ -803,7 +820,7 @@ int autotune_forward(cider_weights* w, const Run& r, hipStream_t s) {
                             launch, s)))
       return rc;
   }
-  if (oproj_mlp) {
+  if (oproj_mlp && !f8_up) {
     g.A = k.O;
     auto launch = [&](int v) {
       return launch_oproj_mlp3_bf16(g, L.Wo_u, L.bo_u, L.ln3_g, L.ln3_b, L.W1, L.b1, L.W2, F, s, v);
@@ -1465,7 +1482,33 @@ int cider_weights_create(const cider_model_cfg* cfg, const float* blob, size_t n
     if ((rc = mat(d, d, &L.Wo_u))) goto bad;
     L.bo_u = vec(d);
     L.ln3_g = vec(d); L.ln3_b = vec(d);
-    if ((rc = mat(F, d, &L.W1))) goto bad;
+    {
+      const size_t off_w1 = off;
+      if ((rc = mat(F, d, &L.W1))) goto bad;
+      if (d % 64 == 0) {
+        // e4m3 copy of W1 for the token-resident FP8 up projection: in each
+        // 64-column block, position 32 h + 8 s + e holds column
+        // 16 s + 8 (e / 4) + 4 h + e % 4 (the order of a lane's X1 bytes)
+        std::vector<uint8_t> p8((size_t)F * d);
+        for (int row = 0; row < F; ++row)
+          for (int t = 0; t < d / 64; ++t)
+            for (int h = 0; h < 2; ++h)
+              for (int sb = 0; sb < 4; ++sb)
+                for (int e = 0; e < 8; ++e) {
+                  const int col = 64 * t + 16 * sb + 8 * (e >> 2) + 4 * h + (e & 3);
+                  p8[(size_t)row * d + 64 * t + 32 * h + 8 * sb + e] =
+                      f32_to_e4m3(blob[off_w1 + (size_t)row * d + col] / L.W1.f8_scale);
+                }
+        void* dp = nullptr;
+        if (hipMalloc(&dp, p8.size()) != hipSuccess) { rc = fail(CIDER_ENOMEM, "weights hipMalloc"); goto bad; }
+        w->allocs.push_back(dp);
+        if (hipMemcpy(dp, p8.data(), p8.size(), hipMemcpyHostToDevice) != hipSuccess) {
+          rc = fail(CIDER_EDEVICE, "weights upload");
+          goto bad;
+        }
+        L.W1.f8p = (const uint8_t*)dp;
+      }
+    }
     L.b1 = vec(F);
     if ((rc = mat(d, F, &L.W2))) goto bad;
     L.b2 = vec(d);

@@ -35,6 +35,7 @@ namespace cider {
 namespace {
 
 typedef float f32x16 __attribute__((__vector_size__(16 * sizeof(float))));
+typedef int i32x8 __attribute__((__vector_size__(8 * sizeof(int))));
 
 constexpr int kM3BM = 256;                        // tokens per workgroup
 constexpr int kM3FCH = 32;                        // hidden units per chunk
@@ -117,7 +118,7 @@ __device__ __forceinline__ int m3_sigma(int j) {
 // offsets relative to the chunk's first hidden unit are formed once (-1: the
 // lane's bytes lie past its region), so a chunk costs one address add per
 // block instead of a division by the row pitch.
-template <int NW, int N1, int N2, int RB1, int RB2, int W1B, int W2B, int W1A, bool CACHE = true>
+template <int NW, int N1, int N2, int RB1, int RB2, int W1B, int W2B, int W1A, bool CACHE = true, int ES1 = 2>
 struct M3ChunkDma {
   static constexpr int KM = (N1 + N2 + NW - 1) / NW;
   int off[CACHE ? KM : 1];
@@ -129,7 +130,7 @@ struct M3ChunkDma {
     if (u < N1) {
       const int pos = u * 1024 + lane_ * 16, j = pos / RB1, o = pos - j * RB1;
       const bool data = o < RB1 - 16;
-      return pos < W1B ? m3_sigma(data ? j : 0) * ld1_ + (data ? o / 2 : 0) : -1;
+      return pos < W1B ? m3_sigma(data ? j : 0) * ld1_ + (data ? o / ES1 : 0) : -1;
     }
     const int pos = (u - N1) * 1024 + lane_ * 16, j = pos / RB2, o = pos - j * RB2;
     const bool data = o < RB2 - 16;
@@ -145,14 +146,15 @@ struct M3ChunkDma {
       for (int k = 0; k < KM; ++k) off[CACHE ? k : 0] = (wave + NW * k < N1 + N2) ? offset(k) : -1;
     }
   }
-  __device__ __forceinline__ void issue(const bf16* W1, const bf16* W2, int c0, char* base) const {
+  // W1 holds ES1-byte elements (BF16, or e4m3 for the FP8 up projection)
+  __device__ __forceinline__ void issue(const void* W1, const bf16* W2, int c0, char* base) const {
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
       const int u = wave_ + NW * k;
       if (u >= N1 + N2) break;
       const bool first = u < N1;
       const int o = CACHE ? off[CACHE ? k : 0] : offset(k);
-      const bf16* src = first ? W1 + (long)c0 * ld1_ + o : W2 + c0 + o;
+      const void* src = first ? (const void*)((const char*)W1 + ((long)c0 * ld1_ + o) * ES1) : (const void*)(W2 + c0 + o);
       char* dst = base + (first ? u * 1024 : W1A + (u - N1) * 1024);
       if (o >= 0) __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
     }
@@ -1924,11 +1926,19 @@ struct OMSmem {
   static_assert(bytes <= 160 * 1024, "LDS");
 };
 
-template <int D, int NBUF, int MAXF, bool PROJ, int PF>
+// F8: the MLP up projection in e4m3 (v_mfma_scale_f32_32x32x64_f8f6f4, unit
+// block scales): X1 is quantised per token (amax / 448) straight from the
+// LayerNorm, and W1q is the e4m3 copy of W1 (per-tensor scale w1s) with each
+// row's columns reordered so that a lane's 32 bytes of a 64-wide k step are
+// contiguous: row position 64 t + 32 h + 8 s + e holds feature
+// 16 (4 t + s) + 8 (e / 4) + 4 h + e % 4, the feature a lane of half h
+// holds in byte 8 s + e of its X1 fragment t.  The result has the BF16 up
+// projection's layout, so the GELU and the down projection are unchanged.
+template <int D, int NBUF, int MAXF, bool PROJ, int PF, bool F8 = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_oproj_mlp3(GemmArgs g, const bf16* __restrict__ Wo, const float* __restrict__ bo, const float* __restrict__ lnx_g,
                   const float* __restrict__ lnx_b, const bf16* __restrict__ W1, const float* __restrict__ b1,
-                  const bf16* __restrict__ W2, int F) {
+                  const bf16* __restrict__ W2, int F, const uint8_t* __restrict__ W1q, float w1s) {
   constexpr int KCH = 128;
   using S = OMSmem<D, NBUF, MAXF>;
   using O = typename S::O;
@@ -1970,11 +1980,19 @@ void k_oproj_mlp3(GemmArgs g, const bf16* __restrict__ Wo, const float* __restri
     for (int s = 0; s < KSC; ++s)
       f[s] = tv ? *(const bf16x8*)(A + tok0 * D + c * KCH + 16 * s + 8 * g2) : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
   };
-  const int nwm = (N1 + N2) / NW + (wave < (N1 + N2) % NW ? 1 : 0);
-  // offsets formed per chunk here: the kernel has no registers to keep them
-  M3ChunkDma<NW, N1, N2, MRB1, MRB2, (int)M::w1, (int)M::w2, (int)M::w1a, false> mdma;
+  // offsets formed per chunk here: the kernel has no registers to keep them.
+  // With F8 the W1 rows are D e4m3 bytes (pitch RB1Q), the first of the
+  // BF16 W1 region's bytes
+  constexpr int RB1Q = D + 16, W1Q = 32 * RB1Q, N1Q = (W1Q + 1023) / 1024;
+  static_assert(W1Q <= (int)M::w1a, "e4m3 W1 chunk fits the BF16 one's region");
+  M3ChunkDma<NW, F8 ? N1Q : N1, N2, F8 ? RB1Q : MRB1, MRB2, F8 ? W1Q : (int)M::w1, (int)M::w2, (int)M::w1a, false,
+             F8 ? 1 : 2> mdma;
   mdma.init(wave, lane, D, F);
-  auto dma_m = [&](int ch, int buf) { mdma.issue(W1, W2, ch * kM3FCH, wreg + buf * M::buf); };
+  auto dma_m = [&](int ch, int buf) {
+    mdma.issue(F8 ? (const void*)W1q : (const void*)W1, W2, ch * kM3FCH, wreg + buf * M::buf);
+  };
+  constexpr int NM = (F8 ? N1Q : N1) + N2;          // DMA blocks of a chunk
+  const int nwm = NM / NW + (wave < NM % NW ? 1 : 0);
 
   for (int i = tid; i < D; i += 512) {
     svo[i] = bo[i];
@@ -2019,9 +2037,11 @@ void k_oproj_mlp3(GemmArgs g, const bf16* __restrict__ Wo, const float* __restri
   const int pre = min(DIST, nch);
   for (int ch = 0; ch < pre; ++ch) dma_m(ch, ch);
 
-  // ---- R1 = R + acc2 + b_o in place, X1 = LN(R1) in the accumulator layout,
-  // then acc2 = R1 + b2
+  // ---- R1 = R + acc2 + b_o in place, X1 = LN(R1) in the accumulator layout
+  // (BF16, or e4m3 fragments with the token's scale), then acc2 = R1 + b2
   bf16x8 x1[KS];
+  i32x8 xq[F8 ? D / 64 : 1];
+  float xsc = 1.f;
   {
     const float* Rrow = g.R + (long)(tv ? tok0 : 0) * D;
     float sum = 0.f;
@@ -2056,20 +2076,44 @@ void k_oproj_mlp3(GemmArgs g, const bf16* __restrict__ Wo, const float* __restri
     qv = xhalf_sum(qv);
     const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
 #pragma unroll
-    for (int b = 0; b < OBK; ++b)
+      for (int b = 0; b < OBK; ++b)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int f = 32 * b + 8 * q + 4 * g2;
-        const f32x4 lg = *(const f32x4*)&svo[D + f];
-        const f32x4 lb = *(const f32x4*)&svo[2 * D + f];
-        const f32x4 b2 = *(const f32x4*)&svm[f];
+        for (int q = 0; q < 4; ++q) {
+          const int f = 32 * b + 8 * q + 4 * g2;
+          const f32x4 lg = *(const f32x4*)&svo[D + f];
+          const f32x4 lb = *(const f32x4*)&svo[2 * D + f];
+          const f32x4 b2 = *(const f32x4*)&svm[f];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          x1[2 * b + (q >> 1)][4 * (q & 1) + i] = (bf16)((acc2[b][0][4 * q + i] - mean) * rstd * lg[i] + lb[i]);
-          acc2[b][0][4 * q + i] += b2[i];
+          for (int i = 0; i < 4; ++i) {
+            x1[2 * b + (q >> 1)][4 * (q & 1) + i] = (bf16)((acc2[b][0][4 * q + i] - mean) * rstd * lg[i] + lb[i]);
+            acc2[b][0][4 * q + i] += b2[i];
+          }
+          if (q & 1) asm volatile("" : "+v"(x1[2 * b + (q >> 1)]), "+v"(acc2[b][0])::"memory");
         }
-        if (q & 1) asm volatile("" : "+v"(x1[2 * b + (q >> 1)]), "+v"(acc2[b][0])::"memory");
-      }
+    if constexpr (F8) {
+      // e4m3 fragments of X1 with the token's scale amax / 448 (amax over the
+      // two lanes of the token); value e of x1[s] is byte 8 (s % 4) + e of
+      // fragment s / 4
+      float amax = 0.f;
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) amax = fmaxf(amax, fabsf((float)x1[s][e]));
+      amax = xhalf_max(amax);
+      xsc = amax > 0.f ? amax / 448.0f : 1.0f;
+      const float inv = 1.0f / xsc;
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          float hq[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) hq[i] = fminf(fmaxf((float)x1[s][4 * h + i] * inv, -448.f), 448.f);
+          int pk = __builtin_amdgcn_cvt_pk_fp8_f32(hq[0], hq[1], 0, false);
+          pk = __builtin_amdgcn_cvt_pk_fp8_f32(hq[2], hq[3], pk, true);
+          xq[s >> 2][2 * (s & 3) + h] = pk;
+        }
+    }
   }
 
   // ================= MLP (one chunk of 32 hidden units at a time) =================
@@ -2077,6 +2121,26 @@ void k_oproj_mlp3(GemmArgs g, const bf16* __restrict__ Wo, const float* __restri
   auto up = [&](int ch, f32x16& acc1) {
     const char* s1 = wreg + (ch % NBUF) * M::buf;
     const float* sb = sb1 + ch * kM3FCH;
+    if constexpr (F8) {
+      // acc1 = b1 + (scale of X1 x w1s) (W1q X1q) over D / 64 steps of 64
+      f32x16 a;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) a[r] = 0.f;
+      const char* wr = s1 + l32 * RB1Q + 32 * g2;
+#pragma unroll
+      for (int t = 0; t < D / 64; ++t) {
+        const i32x8 wa = *(const i32x8*)(wr + 64 * t);
+        a = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(wa, xq[t], a, 0, 0, 0, 127, 0, 127);
+      }
+      const float sc = xsc * w1s;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f32x4 bq = *(const f32x4*)&sb[16 * (q >> 1) + 8 * g2 + 4 * (q & 1)];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc1[4 * q + i] = a[4 * q + i] * sc + bq[i];
+      }
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const f32x4 bq = *(const f32x4*)&sb[16 * (q >> 1) + 8 * g2 + 4 * (q & 1)];
@@ -2966,17 +3030,28 @@ bool oproj_mlp3_ok(int d, int F) { return d == 256 && F % kM3FCH == 0 && F >= 64
 // projection (g.proj_w / g.proj_out).  BF16, d = 256.  g.A = O, g.bias = b2.
 hipError_t launch_oproj_mlp3_bf16(const GemmArgs& g, const Mat& Wo, const float* bo, const float* lnx_g,
                                   const float* lnx_b, const Mat& W1, const float* b1, const Mat& W2, int F,
-                                  hipStream_t s, int variant) {
+                                  hipStream_t s, int variant, bool f8_up) {
   if (g.M == 0) return hipSuccess;
   if (!oproj_mlp3_ok(g.N, F) || !g.ln_g || !Wo.b16 || !W1.b16 || !W2.b16) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((g.M + kM3BM - 1) / kM3BM)), block(512);
 #define CIDER_OM(NB, PF)                                                                                          \
   if (g.proj_out)                                                                                                 \
     hipLaunchKernelGGL((k_oproj_mlp3<256, NB, 1024, true, PF>), grid, block, 0, s, g, Wo.b16, bo, lnx_g, lnx_b,    \
-                       W1.b16, b1, W2.b16, F);                                                                    \
+                       W1.b16, b1, W2.b16, F, nullptr, 1.f);                                                      \
   else                                                                                                            \
     hipLaunchKernelGGL((k_oproj_mlp3<256, NB, 1024, false, PF>), grid, block, 0, s, g, Wo.b16, bo, lnx_g, lnx_b,   \
-                       W1.b16, b1, W2.b16, F);
+                       W1.b16, b1, W2.b16, F, nullptr, 1.f);
+  if (f8_up) {
+    // the up projection in e4m3 (W1.f8p, the reordered copy)
+    if (!W1.f8p) return hipErrorInvalidValue;
+    if (g.proj_out)
+      hipLaunchKernelGGL((k_oproj_mlp3<256, 2, 1024, true, 3, true>), grid, block, 0, s, g, Wo.b16, bo, lnx_g, lnx_b,
+                         W1.b16, b1, W2.b16, F, W1.f8p, W1.f8_scale);
+    else
+      hipLaunchKernelGGL((k_oproj_mlp3<256, 2, 1024, false, 3, true>), grid, block, 0, s, g, Wo.b16, bo, lnx_g, lnx_b,
+                         W1.b16, b1, W2.b16, F, W1.f8p, W1.f8_scale);
+    return hipGetLastError();
+  }
   // variants differ in the depth of the MLP weight-chunk ring (2, 3 or 4
   // buffers) and in how many weight fragments each wave keeps in flight
   // ahead of its MFMAs; every element's arithmetic is the same
