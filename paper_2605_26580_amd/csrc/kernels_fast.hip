@@ -532,7 +532,7 @@ hipError_t gemm_bf16_t(int epi, const GemmArgs& g, const bf16* W, hipStream_t s)
 static int ln_fused_tiles(int N) { return N <= 128 ? 3 : 2; }
 static int plain_tiles(int N) { return (N % 128 == 0) ? 4 : 2; }
 int gemm_tile_count(int epi, int N, bool ln) {
-  if (ln) return ln_fused_tiles(N) + (epi == kEpiResid ? plain_tiles(N) : 0);
+  if (ln) return ln_fused_tiles(N) + ((epi == kEpiResid || epi == kEpiGate) ? plain_tiles(N) : 0);
   return plain_tiles(N);
 }
 
@@ -541,7 +541,7 @@ int gemm_tile_count(int epi, int N, bool ln) {
 // than the split form's extra pass over R (measured at d = 384: 0.38 against
 // 0.75 ms per output projection).
 int gemm_default_tile(int epi, int N, bool ln) {
-  return (ln && epi == kEpiResid && N >= 320 && N % 64 == 0 && N <= 512) ? ln_fused_tiles(N) : 0;
+  return (ln && (epi == kEpiResid || epi == kEpiGate) && N >= 320 && N % 64 == 0 && N <= 512) ? ln_fused_tiles(N) : 0;
 }
 
 // epi: Store, Gelu, Resid, Gate; with ln_g set (Resid / Gate) the next
@@ -551,14 +551,14 @@ hipError_t launch_gemm_bf16(int epi, const GemmArgs& g, const Mat& W, hipStream_
   if (g.Kd % 64 != 0) return hipErrorInvalidValue;
   const bool ln = (epi == kEpiResid || epi == kEpiGate) && g.ln_g != nullptr;
   if (ln && tile >= ln_fused_tiles(g.N)) {
-    if (epi != kEpiResid || g.out_scale || g.proj_out || g.N % 64 != 0 || g.N > 512) {
+    if ((epi != kEpiResid && epi != kEpiGate) || g.out_scale || g.proj_out || g.N % 64 != 0 || g.N > 512) {
       tile = 0;                                   // no split form: the default fused tile
     } else {
-      // residual GEMM with a plain tile, then the row LayerNorm over R
+      // residual (or gate-blend) GEMM with a plain tile, then the row LayerNorm over R
       GemmArgs gr = g;
       gr.ln_g = gr.ln_b = nullptr;
       gr.out = nullptr;
-      const hipError_t e = launch_gemm_bf16(kEpiResid, gr, W, s, tile - ln_fused_tiles(g.N));
+      const hipError_t e = launch_gemm_bf16(epi, gr, W, s, tile - ln_fused_tiles(g.N));
       if (e != hipSuccess) return e;
       return launch_ln_rows(g, s);
     }
@@ -870,7 +870,9 @@ hipError_t launch_gate_bf16(const GemmArgs& g, const Mat& Wg1, const float* bg1,
 }
 
 // d = 512 would need 172 KB of LDS for the [Z ; e] tile and one W_g1 chunk.
-bool gate_fusable(int d) { return d <= 448 && d % 64 == 0; }
+// At d >= 320 the fused gate's 32-token tiles re-stream both gate matrices
+// per tile; the two GEMMs (with the split LayerNorm) stream them per 128.
+bool gate_fusable(int d) { return d <= 256 && d % 64 == 0; }
 
 // ---------------------------------------------------------------------------
 // FP8 (OCP e4m3) token GEMMs fed by a LayerNorm: out = A W^T with A = XN8
