@@ -96,8 +96,11 @@ def test_full_batch_equals_sampled_bins_alone(name):
         assert np.array_equal(va.cpu().numpy(), V[i])
 
 
-@pytest.mark.parametrize("name", ["c2", "c3"])
-def test_teacher_forced_step_at_workload_size(name):
+@pytest.mark.parametrize("name,prec", [("c2", "bf16"), ("c3", "bf16"), ("c3", "fp8")])
+def test_teacher_forced_step_at_workload_size(name, prec):
+    """One teacher-forced step of a sampled bin at the workload's model, K and
+    n; with FP8 at c3 this runs the token-resident kernels with the e4m3 MLP
+    up projection over 2,048 tokens."""
     torch = torch_cuda()
     P = lib()
     wl, wh, w, items = _workload_batch(name)
@@ -106,14 +109,14 @@ def test_teacher_forced_step_at_workload_size(name):
     ch = P.Code(code.n, code.m, code.row_ptr, code.col_idx)
     _, p = evidence(y.astype(np.float64), s2, K)
     rng = np.random.default_rng(7)
-    opts = P.cider_opts_default(precision=P.CIDER_BF16)
-    tol = TOL["bf16"]
+    opts = P.cider_opts_default(precision={"bf16": P.CIDER_BF16, "fp8": P.CIDER_FP8}[prec])
+    tol = TOL[prec]
     yd = torch.from_numpy(np.ascontiguousarray(y)).cuda()
     for frac in (1.0, 0.5):
         Xin = rng.integers(0, 2, size=(K, n)).astype(np.uint8)
         Xin[rng.random((K, n)) < frac] = 2
         gamma = float((Xin == 2).mean())
-        say(f"teacher-forced BF16 at {name} size: K={K} n={n} L={cfg.n_layers} d={cfg.d} mask={frac}")
+        say(f"teacher-forced {prec} at {name} size: K={K} n={n} L={cfg.n_layers} d={cfg.d} mask={frac}")
         ref = denoise(Xin, p, code, w, cfg.n_layers, cfg.heads, gamma)
         lbar = torch.zeros(K, n, 2, dtype=torch.float32, device="cuda")
         logits = torch.zeros_like(lbar)
