@@ -273,6 +273,8 @@ hipError_t launch_oproj_mlp3_bf16(const GemmArgs& g, const Mat& Wo, const float*
                                   const float* lnx_b, const Mat& W1, const float* b1, const Mat& W2, int F,
                                   hipStream_t s, int variant = 0, bool f8_up = false);
 int oproj_mlp3_variants();
+bool mlp16_ok(int d, int F);
+hipError_t launch_mlp16_bf16(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s);
 bool user_mlp_tr_ok(int d, int heads, int F);
 hipError_t launch_user_mlp_tr(const StepCtx& c, void* XN, const DevLayer& L, const GemmArgs& g2, int d, int heads,
                               int F, hipStream_t s, int variant = 0);

@@ -722,6 +722,9 @@ int enqueue_forward(cider_weights* w, const Run& r, hipStream_t s) {
       } else if (mlp3_ok(d, F)) {
         // token-resident MLP: 256 tokens per workgroup, weights streamed once per tile
         TIMED("mlp_fused", launch_mlp3_bf16(g, L.W1, L.b1, L.W2, F, s));
+      } else if (prec == kBF16 && mlp16_ok(d, F)) {
+        // d = 384: token-resident MLP with 16 tokens per wave, 128 per workgroup
+        TIMED("mlp_fused", launch_mlp16_bf16(g, L.W1, L.b1, L.W2, F, s));
       } else {
         int mt = tile_for(w, kMlpKey, g);
         if (r.forced_tile >= 0) mt = r.forced_tile < mlp_tile_count(d) ? r.forced_tile : 0;
@@ -802,7 +805,7 @@ int autotune_forward(cider_weights* w, const Run& r, hipStream_t s) {
     g.ln_g = L.ln2_g; g.ln_b = L.ln2_b; g.out = k.XN;
     if ((rc = tune_gemm(w, "gemm_o_ln", kEpiResid, g, L.Wo_r, s))) return rc;
   }
-  if (prec == kBF16 && !mlp3_ok(d, F)) {
+  if (prec == kBF16 && !mlp3_ok(d, F) && !mlp16_ok(d, F)) {
     g = GemmArgs{}; g.M = T; g.N = d; g.Kd = d; g.A = k.XN; g.bias = L.b2; g.R = k.R;
     g.ln_g = L.ln1_g; g.ln_b = L.ln1_b; g.out = k.XN;
     if ((rc = tune_mlp(w, g, L, F, k.HID, s))) return rc;

@@ -3008,6 +3008,195 @@ hipError_t launch_mlp3_bf16(const GemmArgs& g, const Mat& W1, const float* b1, c
   return mlp3_t<256, 1, 8, 2, 3, false>(g, W1.b16, b1, W2.b16, F, s);
 }
 
+// ---------------------------------------------------------------------------
+// Token-resident MLP for wide models (BF16, d = 384): 16 tokens per wave on
+// MFMA 16 x 16 x 32, so that the d outputs of a wave's tokens (d / 4
+// accumulators per lane) and its XN fragments (d / 8 registers) fit two waves
+// per SIMD.  R += W2 GELU(W1 XN + b1) + b2, then the next LayerNorm into
+// g.out (or, PROJ, the final LayerNorm and the 2-way projection).
+//   up    acc1[u] (hidden 16 u + 4 (l/16) + r of token l % 16) starts at b1;
+//         A = W1 rows of the chunk (natural order), B = XN[token][32 s + 8 (l/16) ..]
+//   down  B = GELU of the lane's 8 hidden units: k-slot 8 (l/16) + e holds
+//         hidden 4 (l/16) + e (e < 4) or 16 + 4 (l/16) + e - 4, and the A
+//         operand reads W2's chunk columns in that order (two 8-byte halves)
+// Weights go through LDS one chunk of 32 hidden units at a time, two
+// buffers, the next chunk's DMA issued before the current one's MFMAs.
+namespace {
+
+template <int D, int MAXF>
+struct M16Smem {
+  static constexpr int RB1 = D * 2 + 16;          // W1 row pitch (bytes)
+  static constexpr int RB2 = 32 * 2 + 16;         // W2 chunk row pitch
+  static constexpr size_t w1 = (size_t)32 * RB1;
+  static constexpr size_t w2 = (size_t)D * RB2;
+  static constexpr size_t w1a = (w1 + 15) / 16 * 16;
+  static constexpr size_t buf = (w1a + w2 + 1023) / 1024 * 1024;
+  // b1, then b2, LN gain and bias, projection rows; the weights from a 1 KB boundary
+  static constexpr size_t vec = ((size_t)(MAXF + 5 * D) * 4 + 1023) / 1024 * 1024;
+  static constexpr size_t bytes = vec + 2 * buf;
+  static_assert(bytes <= 160 * 1024, "LDS");
+};
+
+template <int D, int MAXF, bool PROJ>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_mlp16(GemmArgs g, const bf16* __restrict__ W1, const float* __restrict__ b1, const bf16* __restrict__ W2,
+             int F) {
+  using S = M16Smem<D, MAXF>;
+  constexpr int NW = 8, KS = D / 32, OT = D / 16, RB1 = S::RB1, RB2 = S::RB2;
+  constexpr int N1 = (int)((S::w1 + 1023) / 1024), N2 = (int)((S::w2 + 1023) / 1024), NM = N1 + N2;
+  __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
+  float* sb1 = (float*)smem;
+  float* sv = sb1 + MAXF;                           // b2, LN gain, LN bias, projection rows
+  char* const wreg = smem + S::vec;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g4 = lane >> 4, l16 = lane & 15;
+  const long tok0 = (long)blockIdx.x * (NW * 16) + wave * 16 + l16;
+  const bool tv = tok0 < g.M;
+  const long tok = tv ? tok0 : 0;
+  const int nch = F / 32;
+  const bf16* __restrict__ A = (const bf16*)g.A;
+
+  auto dma = [&](int ch, int buf) {
+    const int c0 = ch * 32;
+    char* base = wreg + buf * S::buf;
+#pragma unroll
+    for (int k = 0; k < (NM + NW - 1) / NW; ++k) {
+      const int u = wave + NW * k;
+      if (u >= NM) break;
+      if (u < N1) {
+        const int pos = u * 1024 + lane * 16, j = pos / RB1, o = pos - j * RB1;
+        const bool data = o < RB1 - 16;
+        const bf16* src = W1 + (long)(c0 + (data ? j : 0)) * D + (data ? o / 2 : 0);
+        if (pos < (int)S::w1)
+          __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(base + u * 1024), 16, 0, 0);
+      } else {
+        const int pos = (u - N1) * 1024 + lane * 16, j = pos / RB2, o = pos - j * RB2;
+        const bool data = o < RB2 - 16;
+        const bf16* src = W2 + (long)(data ? j : 0) * F + c0 + (data ? o / 2 : 0);
+        if (pos < (int)S::w2)
+          __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(base + S::w1a + (u - N1) * 1024),
+                                           16, 0, 0);
+      }
+    }
+  };
+  for (int i = tid; i < F; i += NW * 64) sb1[i] = b1[i];
+  m3_stage_vectors<D>(sv, g, PROJ, tid, NW * 64);
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // staged vectors written (visible after the first barrier)
+  dma(0, 0);
+  bf16x8 xf[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s)
+    xf[s] = tv ? *(const bf16x8*)(A + tok * D + 32 * s + 8 * g4) : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+  f32x4 acc2[OT];
+#pragma unroll
+  for (int t = 0; t < OT; ++t) acc2[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  m3_wait_barrier(0);                               // chunk 0 and the vectors in LDS
+
+#pragma unroll 1
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nch) dma(ch + 1, buf ^ 1);         // its last readers passed the previous barrier
+    const char* s1 = wreg + buf * S::buf;
+    const char* s2 = s1 + S::w1a;
+    f32x4 acc1[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) acc1[u] = *(const f32x4*)&sb1[ch * 32 + 16 * u + 4 * g4];
+    mfma_pipe<2 * KS, 3>(
+        [&](int i) { return *(const bf16x8*)(s1 + (16 * (i & 1) + l16) * RB1 + (32 * (i >> 1) + 8 * g4) * 2); },
+        [&](int i, const bf16x8& w) {
+          acc1[i & 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xf[i >> 1], acc1[i & 1], 0, 0, 0);
+        });
+    bf16x8 hf;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      hf[r] = (bf16)gelu_f(acc1[0][r]);
+      hf[4 + r] = (bf16)gelu_f(acc1[1][r]);
+    }
+    mfma_pipe<OT, 3>(
+        [&](int t) {
+          const char* wr = s2 + (16 * t + l16) * RB2;
+          const bf16x4 a0 = *(const bf16x4*)(wr + 8 * g4);
+          const bf16x4 a1 = *(const bf16x4*)(wr + 32 + 8 * g4);
+          return bf16x8{a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+        },
+        [&](int t, const bf16x8& w) { acc2[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, hf, acc2[t], 0, 0, 0); });
+    // chunk ch + 1 complete in every wave, and every wave done with buffer buf
+    if (ch + 1 < nch) m3_wait_barrier(0);
+  }
+
+  // ---- R += acc2 + b2, then the next LayerNorm (or the final one and the projection).
+  // Lane l holds features 16 t + 4 (l/16) + r of token l % 16; four lanes per token.
+  const float* slg = sv + D;
+  const float* slb = sv + 2 * D;
+  float* Rrow = g.R + tok * D;
+  float sum = 0.f;
+#pragma unroll
+  for (int t = 0; t < OT; ++t) {
+    const int f = 16 * t + 4 * g4;
+    const f32x4 rr = tv ? *(const f32x4*)(Rrow + f) : f32x4{0.f, 0.f, 0.f, 0.f};
+    const f32x4 bb = *(const f32x4*)&sv[f];
+    const f32x4 res = rr + (acc2[t] + bb);
+    acc2[t] = res;
+    sum += (res[0] + res[1]) + (res[2] + res[3]);
+    if (tv) *(f32x4*)(Rrow + f) = res;
+    if ((t & 3) == 3) asm volatile("" ::: "memory");   // bounds the loads in flight
+  }
+  sum += __shfl_xor(sum, 16, 64);
+  sum += __shfl_xor(sum, 32, 64);
+  const float mean = sum / (float)D;
+  float qv = 0.f;
+#pragma unroll
+  for (int t = 0; t < OT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float dv = acc2[t][r] - mean;
+      qv = fmaf(dv, dv, qv);
+    }
+  qv += __shfl_xor(qv, 16, 64);
+  qv += __shfl_xor(qv, 32, 64);
+  const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
+  if (!PROJ) {
+    bf16* xo = (bf16*)g.out + tok * D;
+#pragma unroll
+    for (int t = 0; t < OT; ++t) {
+      const int f = 16 * t + 4 * g4;
+      const f32x4 lg = *(const f32x4*)&slg[f];
+      const f32x4 lb = *(const f32x4*)&slb[f];
+      bf16x4 h;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h[r] = (bf16)((acc2[t][r] - mean) * rstd * lg[r] + lb[r]);
+      if (tv) *(bf16x4*)(xo + f) = h;
+    }
+  } else {
+    const float* sp0 = sv + 3 * D;
+    const float* sp1 = sv + 4 * D;
+    float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+    for (int t = 0; t < OT; ++t) {
+      const int f = 16 * t + 4 * g4;
+      const f32x4 lg = *(const f32x4*)&slg[f];
+      const f32x4 lb = *(const f32x4*)&slb[f];
+      const f32x4 w0 = *(const f32x4*)&sp0[f];
+      const f32x4 w1 = *(const f32x4*)&sp1[f];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float hv = (acc2[t][r] - mean) * rstd * lg[r] + lb[r];
+        a0 = fmaf(hv, w0[r], a0);
+        a1 = fmaf(hv, w1[r], a1);
+      }
+    }
+    a0 += __shfl_xor(a0, 16, 64);
+    a0 += __shfl_xor(a0, 32, 64);
+    a1 += __shfl_xor(a1, 16, 64);
+    a1 += __shfl_xor(a1, 32, 64);
+    if (tv && g4 == 0) {
+      g.proj_out[2 * tok] = a0;
+      g.proj_out[2 * tok + 1] = a1;
+    }
+  }
+}
+
+}  // namespace
+
 bool oproj_user_attn_ok(int d, int heads) { return d == 256 && heads * 32 == d; }
 
 // R += O_row W_o^T + b_o (the row sublayer's output projection), then the
@@ -3065,6 +3254,21 @@ hipError_t launch_oproj_mlp3_bf16(const GemmArgs& g, const Mat& Wo, const float*
 }
 
 int oproj_mlp3_variants() { return 5; }
+
+bool mlp16_ok(int d, int F) { return d == 384 && F % 32 == 0 && F >= 64 && F <= 1536; }
+
+// R += W2 GELU(W1 XN + b1) + b2 for the d = 384 model, 16 tokens per wave,
+// with the next LayerNorm (g.ln_g / g.out) or the final LayerNorm and the
+// projection (g.proj_out).
+hipError_t launch_mlp16_bf16(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s) {
+  if (g.M == 0) return hipSuccess;
+  if (!mlp16_ok(g.N, F) || g.Kd != g.N || !g.ln_g || !g.R || !W1.b16 || !W2.b16 || (!g.proj_out && !g.out))
+    return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((g.M + 127) / 128)), block(512);
+  if (g.proj_out) hipLaunchKernelGGL((k_mlp16<384, 1536, true>), grid, block, 0, s, g, W1.b16, b1, W2.b16, F);
+  else hipLaunchKernelGGL((k_mlp16<384, 1536, false>), grid, block, 0, s, g, W1.b16, b1, W2.b16, F);
+  return hipGetLastError();
+}
 
 bool user_mlp_tr_ok(int d, int heads, int F) { return d == 128 && heads * 16 == d && F % kM3FCH == 0 && F >= 64 && F <= 512; }
 
