@@ -72,6 +72,12 @@ CASES = [
     (3, 100, 1, 256, 8),
     (7, 40, 1, 256, 8),
     (16, 24, 1, 256, 8),
+    # widths of the split forms (plain-tile GEMM + row LayerNorm, the MLP as
+    # an up GEMM from b1 + residual GEMM + row LayerNorm or final projection)
+    # and the token-resident QKV projection at input width 512
+    (2, 64, 1, 320, 10),
+    (3, 40, 1, 448, 14),
+    (2, 36, 1, 512, 16),
 ]
 
 
@@ -389,7 +395,7 @@ def test_every_gemm_tile_gives_identical_decodes():
     element's accumulation order, so the autotuner cannot change a result."""
     torch = torch_cuda()
     P = lib()
-    for (K, n, L, d, h) in [(4, 128, 2, 128, 8), (3, 64, 1, 256, 8), (2, 64, 1, 384, 12)]:
+    for (K, n, L, d, h) in [(4, 128, 2, 128, 8), (3, 64, 1, 256, 8), (2, 64, 1, 384, 12), (2, 64, 1, 320, 10)]:
         cfg = synth.ModelCfg(L, d, h, n_max=128)
         wh, _ = weights_handle(cfg, seed=51 + d, bias_std=0.02, ln_std=0.05)
         code = code_of(n, 1000 + n)
