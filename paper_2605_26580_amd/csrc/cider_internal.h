@@ -109,6 +109,10 @@ struct Mat {
   const uint8_t* f8 = nullptr;
   float f8_scale = 1.f;   // W ~= f8_scale * fp8(W)
   const uint8_t* f8p = nullptr;   // W1 only: f8 with each row's columns reordered for the token-resident up projection
+  // BF16 with each row's columns reordered within every 16-column block as
+  // 0-3, 8-11, 4-7, 12-15: the k order of an operand held in the 32 x 32
+  // accumulator layout, so that a lane's 8 k-values are one 16-byte read
+  const bf16* b16k = nullptr;
   int rows = 0, cols = 0;
 };
 

@@ -1453,6 +1453,18 @@ int cider_weights_create(const cider_model_cfg* cfg, const float* blob, size_t n
     HIPCHK(hipMemcpy(d8, h8.data(), cnt, hipMemcpyHostToDevice));
     M->f8 = (const uint8_t*)d8;
     M->f8_scale = sc;
+    if (cols % 16 == 0) {
+      // k-ordered BF16 copy (see Mat::b16k)
+      static const int kperm[16] = {0, 1, 2, 3, 8, 9, 10, 11, 4, 5, 6, 7, 12, 13, 14, 15};
+      std::vector<uint16_t> hk(cnt);
+      for (int r = 0; r < rows; ++r)
+        for (int c = 0; c < cols; ++c) hk[(size_t)r * cols + c] = hb[(size_t)r * cols + (c & ~15) + kperm[c & 15]];
+      void* dk = nullptr;
+      if (hipMalloc(&dk, cnt * 2) != hipSuccess) return fail(CIDER_ENOMEM, "weights hipMalloc");
+      w->allocs.push_back(dk);
+      HIPCHK(hipMemcpy(dk, hk.data(), cnt * 2, hipMemcpyHostToDevice));
+      M->b16k = (const bf16*)dk;
+    }
     off += cnt;
     return CIDER_OK;
   };

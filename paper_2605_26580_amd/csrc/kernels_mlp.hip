@@ -1057,9 +1057,7 @@ void k_user_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         const char* wr = s2 + (32 * b + l32) * RB2;
-        const bf16x4 a0 = *(const bf16x4*)(wr + (16 * s + 4 * g2) * 2);
-        const bf16x4 a1 = *(const bf16x4*)(wr + (16 * s + 8 + 4 * g2) * 2);
-        const bf16x8 w = bf16x8{a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+        const bf16x8 w = *(const bf16x8*)(wr + (16 * s + 8 * g2) * 2);   // k-ordered rows
         acc2[b][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, of[s], acc2[b][0], 0, 0, 0);
       }
     // pair p + 1 complete in every wave (this wave's only memory operations in
@@ -1286,9 +1284,7 @@ void k_row_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const 
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         const char* wr = sw2 + (32 * bo + l32) * RB2;
-        const bf16x4 a0 = *(const bf16x4*)(wr + (16 * s + 4 * g2) * 2);
-        const bf16x4 a1 = *(const bf16x4*)(wr + (16 * s + 8 + 4 * g2) * 2);
-        const bf16x8 w = bf16x8{a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+        const bf16x8 w = *(const bf16x8*)(wr + (16 * s + 8 * g2) * 2);   // k-ordered rows
         acc2[bo][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, of[s], acc2[bo][0], 0, 0, 0);
       }
     if (p + 1 < NP) {
@@ -1789,9 +1785,7 @@ void k_user_mlp_tr(StepCtx c, UserMlpArgs a) {
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         const char* wr = su2 + (32 * bo + l32) * RB2;
-        const bf16x4 a0 = *(const bf16x4*)(wr + (16 * s + 4 * g2) * 2);
-        const bf16x4 a1 = *(const bf16x4*)(wr + (16 * s + 8 + 4 * g2) * 2);
-        const bf16x8 w = bf16x8{a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+        const bf16x8 w = *(const bf16x8*)(wr + (16 * s + 8 * g2) * 2);   // k-ordered rows
         acc2[bo][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, of[s], acc2[bo][0], 0, 0, 0);
       }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
@@ -1876,13 +1870,12 @@ void k_user_mlp_tr(StepCtx c, UserMlpArgs a) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) acc1[4 * q + i] = bq[i];
     }
-    // W1 k-values in X1's order: 16 s + 4 g2 + j, then 16 s + 8 + 4 g2 + j
+    // W1 k-values in X1's order (16 s + 4 g2 + j, then 16 s + 8 + 4 g2 + j):
+    // the k-ordered copy holds them contiguously
     const char* wr = s1 + l32 * MRB1;
     mfma_pipe<KS, PF>(
         [&](int s) {
-          const bf16x4 a0 = *(const bf16x4*)(wr + (16 * s + 4 * g2) * 2);
-          const bf16x4 a1 = *(const bf16x4*)(wr + (16 * s + 8 + 4 * g2) * 2);
-          return bf16x8{a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+          return *(const bf16x8*)(wr + (16 * s + 8 * g2) * 2);   // k-ordered rows
         },
         [&](int s, const bf16x8& w) { acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, x1[s], acc1, 0, 0, 0); });
     bf16x8 hf[2];
@@ -2147,13 +2140,12 @@ void k_oproj_mlp3(GemmArgs g, const bf16* __restrict__ Wo, const float* __restri
 #pragma unroll
       for (int i = 0; i < 4; ++i) acc1[4 * q + i] = bq[i];
     }
-    // W1 k-values in X1's order: 16 s + 4 g2 + j, then 16 s + 8 + 4 g2 + j
+    // W1 k-values in X1's order (16 s + 4 g2 + j, then 16 s + 8 + 4 g2 + j):
+    // the k-ordered copy holds them contiguously
     const char* wr = s1 + l32 * MRB1;
     mfma_pipe<KS, PF>(
         [&](int s) {
-          const bf16x4 a0 = *(const bf16x4*)(wr + (16 * s + 4 * g2) * 2);
-          const bf16x4 a1 = *(const bf16x4*)(wr + (16 * s + 8 + 4 * g2) * 2);
-          return bf16x8{a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+          return *(const bf16x8*)(wr + (16 * s + 8 * g2) * 2);   // k-ordered rows
         },
         [&](int s, const bf16x8& w) { acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, x1[s], acc1, 0, 0, 0); });
   };
@@ -2385,10 +2377,8 @@ void k_oproj_user_attn(StepCtx c, const bf16* __restrict__ Orow, const bf16* __r
   constexpr int HB = 2;                             // heads per O store batch (registers)
   bf16x4 ob[HB][4];
   bf16* orow = O + (long)(tv ? tok : 0) * D;
-  auto wfrag = [&](const char* rowp, int s) {      // weight k-values in X2's order
-    const bf16x4 a0 = *(const bf16x4*)(rowp + (16 * s + 4 * g2) * 2);
-    const bf16x4 a1 = *(const bf16x4*)(rowp + (16 * s + 8 + 4 * g2) * 2);
-    return bf16x8{a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+  auto wfrag = [&](const char* rowp, int s) {      // weight k-values in X2's order (k-ordered rows)
+    return *(const bf16x8*)(rowp + (16 * s + 8 * g2) * 2);
   };
 #pragma unroll
   for (int h = 0; h < HEADS; ++h) {
@@ -3206,9 +3196,10 @@ hipError_t launch_oproj_user_attn(const StepCtx& c, const void* Orow, const Mat&
                                   const float* ln_g, const float* ln_b, float* R, const Mat& Wqkv, const float* bqkv,
                                   void* O, int d, int heads, hipStream_t s) {
   if (c.total_ugrp32 == 0) return hipSuccess;
-  if (!oproj_user_attn_ok(d, heads) || !c.ugrp32 || !Wo.b16 || !Wqkv.b16) return hipErrorInvalidValue;
+  if (!oproj_user_attn_ok(d, heads) || !c.ugrp32 || !Wo.b16 || !Wqkv.b16k) return hipErrorInvalidValue;
+  // the user QKV projection multiplies X2 held in the accumulator layout: Wqkv's k-ordered copy
   hipLaunchKernelGGL((k_oproj_user_attn<256>), dim3((c.total_ugrp32 + 7) / 8), dim3(512), 0, s, c,
-                     (const bf16*)Orow, Wo.b16, bo, ln_g, ln_b, R, Wqkv.b16, bqkv, (bf16*)O);
+                     (const bf16*)Orow, Wo.b16, bo, ln_g, ln_b, R, Wqkv.b16k, bqkv, (bf16*)O);
   return hipGetLastError();
 }
 
@@ -3221,24 +3212,24 @@ hipError_t launch_oproj_mlp3_bf16(const GemmArgs& g, const Mat& Wo, const float*
                                   const float* lnx_b, const Mat& W1, const float* b1, const Mat& W2, int F,
                                   hipStream_t s, int variant, bool f8_up) {
   if (g.M == 0) return hipSuccess;
-  if (!oproj_mlp3_ok(g.N, F) || !g.ln_g || !Wo.b16 || !W1.b16 || !W2.b16) return hipErrorInvalidValue;
+  if (!oproj_mlp3_ok(g.N, F) || !g.ln_g || !Wo.b16 || !W1.b16k || !W2.b16) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((g.M + kM3BM - 1) / kM3BM)), block(512);
 #define CIDER_OM(NB, PF)                                                                                          \
   if (g.proj_out)                                                                                                 \
     hipLaunchKernelGGL((k_oproj_mlp3<256, NB, 1024, true, PF>), grid, block, 0, s, g, Wo.b16, bo, lnx_g, lnx_b,    \
-                       W1.b16, b1, W2.b16, F, nullptr, 1.f);                                                      \
+                       W1.b16k, b1, W2.b16, F, nullptr, 1.f);                                                      \
   else                                                                                                            \
     hipLaunchKernelGGL((k_oproj_mlp3<256, NB, 1024, false, PF>), grid, block, 0, s, g, Wo.b16, bo, lnx_g, lnx_b,   \
-                       W1.b16, b1, W2.b16, F, nullptr, 1.f);
+                       W1.b16k, b1, W2.b16, F, nullptr, 1.f);
   if (f8_up) {
     // the up projection in e4m3 (W1.f8p, the reordered copy)
     if (!W1.f8p) return hipErrorInvalidValue;
     if (g.proj_out)
       hipLaunchKernelGGL((k_oproj_mlp3<256, 2, 1024, true, 3, true>), grid, block, 0, s, g, Wo.b16, bo, lnx_g, lnx_b,
-                         W1.b16, b1, W2.b16, F, W1.f8p, W1.f8_scale);
+                         W1.b16k, b1, W2.b16, F, W1.f8p, W1.f8_scale);
     else
       hipLaunchKernelGGL((k_oproj_mlp3<256, 2, 1024, false, 3, true>), grid, block, 0, s, g, Wo.b16, bo, lnx_g, lnx_b,
-                         W1.b16, b1, W2.b16, F, W1.f8p, W1.f8_scale);
+                         W1.b16k, b1, W2.b16, F, W1.f8p, W1.f8_scale);
     return hipGetLastError();
   }
   // variants differ in the depth of the MLP weight-chunk ring (2, 3 or 4
@@ -3278,12 +3269,13 @@ bool user_mlp_tr_ok(int d, int heads, int F) { return d == 128 && heads * 16 == 
 hipError_t launch_user_mlp_tr(const StepCtx& c, void* XN, const DevLayer& L, const GemmArgs& g2, int d, int heads,
                               int F, hipStream_t s, int variant) {
   if (c.total_ugrp32 == 0) return hipSuccess;
-  if (!user_mlp_tr_ok(d, heads, F) || !c.ugrp32 || !L.Wqkv_u.b16 || !L.Wo_u.b16 || !L.W1.b16 || !L.W2.b16)
+  if (!user_mlp_tr_ok(d, heads, F) || !c.ugrp32 || !L.Wqkv_u.b16 || !L.Wo_u.b16k || !L.W1.b16k || !L.W2.b16)
     return hipErrorInvalidValue;
   UserMlpArgs a{};
-  a.Wqkv = L.Wqkv_u.b16; a.bqkv = L.bqkv_u; a.Wo = L.Wo_u.b16; a.bo = L.bo_u;
+  // W_o and W1 multiply operands held in the accumulator layout: their k-ordered copies
+  a.Wqkv = L.Wqkv_u.b16; a.bqkv = L.bqkv_u; a.Wo = L.Wo_u.b16k; a.bo = L.bo_u;
   a.ln3_g = L.ln3_g; a.ln3_b = L.ln3_b;
-  a.W1 = L.W1.b16; a.b1 = L.b1; a.W2 = L.W2.b16; a.F = F;
+  a.W1 = L.W1.b16k; a.b1 = L.b1; a.W2 = L.W2.b16; a.F = F;
   a.g = g2;
   a.g.A = XN;
   a.g.M = c.total_tokens;
@@ -3330,7 +3322,7 @@ bool row_block_tr_ok(int d, int heads, int max_n) { return d == 128 && heads * 1
 hipError_t launch_row_block_tr(const StepCtx& c, void* XN, const DevLayer& L, const float* ln_g, const float* ln_b,
                                float* R, int d, int heads, hipStream_t s) {
   if (c.total_rows == 0) return hipSuccess;
-  if (!row_block_tr_ok(d, heads, c.max_n) || !L.Wqkv_r.b16 || !L.Wo_r.b16) return hipErrorInvalidValue;
+  if (!row_block_tr_ok(d, heads, c.max_n) || !L.Wqkv_r.b16 || !L.Wo_r.b16k) return hipErrorInvalidValue;
   GemmArgs g{};
   g.M = c.total_tokens;
   g.N = d;
@@ -3342,7 +3334,7 @@ hipError_t launch_row_block_tr(const StepCtx& c, void* XN, const DevLayer& L, co
   g.ln_g = ln_g;
   g.ln_b = ln_b;
   hipLaunchKernelGGL((k_row_block_tr<128>), dim3(c.total_rows), dim3(256), 0, s, c, g, L.Wqkv_r.b16, L.bqkv_r,
-                     L.Wo_r.b16);
+                     L.Wo_r.b16k);   // W_o k-ordered (its operand is in the accumulator layout)
   return hipGetLastError();
 }
 
@@ -3354,7 +3346,7 @@ bool user_block_tr_ok(int d, int heads) { return d == 128 && heads * 16 == d; }
 hipError_t launch_user_block_tr(const StepCtx& c, void* XN, const DevLayer& L, const float* ln_g, const float* ln_b,
                                 float* R, int d, int heads, hipStream_t s) {
   if (c.total_ugrp32 == 0) return hipSuccess;
-  if (!user_block_tr_ok(d, heads) || !c.ugrp32 || !L.Wqkv_u.b16 || !L.Wo_u.b16) return hipErrorInvalidValue;
+  if (!user_block_tr_ok(d, heads) || !c.ugrp32 || !L.Wqkv_u.b16 || !L.Wo_u.b16k) return hipErrorInvalidValue;
   GemmArgs g{};
   g.M = c.total_tokens;
   g.N = d;
@@ -3366,7 +3358,7 @@ hipError_t launch_user_block_tr(const StepCtx& c, void* XN, const DevLayer& L, c
   g.ln_g = ln_g;
   g.ln_b = ln_b;
   hipLaunchKernelGGL((k_user_block_tr<128, 4>), dim3((c.total_ugrp32 + 3) / 4), dim3(256), 0, s, c, g,
-                     L.Wqkv_u.b16, L.bqkv_u, L.Wo_u.b16);
+                     L.Wqkv_u.b16, L.bqkv_u, L.Wo_u.b16k);   // W_o k-ordered
   return hipGetLastError();
 }
 
