@@ -2492,7 +2492,7 @@ struct EG3Smem {
   // E[3], u, v[2], Wg1_e v_a [2], bg1, bg2, LN gain / bias, <E[x], w_a>: at
   // the start of LDS, so that every vector address is a register base + an
   // immediate
-  static constexpr size_t vec = ((size_t)13 * D * 4 + 8 * 4 + 1023) / 1024 * 1024;
+  static constexpr size_t vec = ((size_t)(13 * D + 12) * 4 + 8 * 4 + 1023) / 1024 * 1024;
   static constexpr size_t bytes = vec + NCH * buf;
   static_assert(bytes <= 160 * 1024, "LDS");
 };
@@ -2507,8 +2507,12 @@ void k_embed_gate3(StepCtx c, EmbedW m, EmbedGateArgs a, int ntiles) {
   __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
   char* wsm = smem + S::vec;                      // the weight chunks
-  float* sE = (float*)smem;                       // [3][D]
-  float* su = sE + 3 * D;
+  // E's three rows at a pitch of D + 4 floats: lanes of different symbols
+  // read their row at the same feature, which a pitch of D (a multiple of
+  // the bank count) would put on the same banks
+  constexpr int EP = D + 4;
+  float* sE = (float*)smem;                       // [3][EP]
+  float* su = sE + 3 * EP;
   float* sv = su + D;                             // [2][D]
   float* sug = sv + 2 * D;                        // [2][D]: Wg1_e v_a
   float* sbg1 = sug + 2 * D;
@@ -2518,7 +2522,7 @@ void k_embed_gate3(StepCtx c, EmbedW m, EmbedGateArgs a, int ntiles) {
   float* sEW = slb + D;                           // [3][2]: <E[x], w_a>
 
   // small vectors first: their loads complete before the weight DMA is issued
-  for (int i = tid; i < 3 * D; i += 512) sE[i] = m.E[i];
+  for (int i = tid; i < 3 * D; i += 512) sE[(i / D) * EP + i % D] = m.E[i];
   for (int i = tid; i < D; i += 512) {
     su[i] = m.u[i];
     sv[i] = m.v[i];
@@ -2592,7 +2596,7 @@ void k_embed_gate3(StepCtx c, EmbedW m, EmbedGateArgs a, int ntiles) {
     const float c0 = expf(sEW[2 * x] * inv_tau - mx0) / den0 * a.p[2 * slot];
     const float c1 = expf(sEW[2 * x + 1] * inv_tau - mx1) / den1 * a.p[2 * slot + 1];
     const float* Pl = m.P + (long)l * D;
-    const float* Ex = sE + x * D;
+    const float* Ex = sE + x * EP;
 
     // ---- Z in the B-operand layout: k-step s holds features 16 s + 8 g2 + 0..7
     // (e = c0 v_0 + c1 v_1 enters the up projection as c0 Wg1_e v_0 + c1 Wg1_e v_1)
@@ -2735,7 +2739,7 @@ struct EGZSmem {
   using M = M3Smem<D, NBUF, D>;
   // E[3], u, v[2], Wg1_e v_a [2], bg1, bg2, LN gain / bias, <E[x], w_a>: at
   // the start of LDS (one register base plus immediate offsets)
-  static constexpr size_t vec = ((size_t)12 * D * 4 + 8 * 4 + 1023) / 1024 * 1024;
+  static constexpr size_t vec = ((size_t)(12 * D + 12) * 4 + 8 * 4 + 1023) / 1024 * 1024;
   static constexpr size_t bytes = vec + NBUF * M::buf;
   static_assert(bytes <= 160 * 1024, "LDS");
 };
@@ -2752,8 +2756,12 @@ void k_embed_gate_z(StepCtx c, EmbedW m, EmbedGateArgs a) {
   static_assert(S::vec % 1024 == 0, "weight region 1 KB aligned");
   __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
   char* const wreg = smem + S::vec;               // the chunk ring
-  float* sE = (float*)smem;                       // [3][D]
-  float* su = sE + 3 * D;
+  // E's three rows at a pitch of D + 4 floats: lanes of different symbols
+  // read their row at the same feature, which a pitch of D (a multiple of
+  // the bank count) would put on the same banks
+  constexpr int EP = D + 4;
+  float* sE = (float*)smem;                       // [3][EP]
+  float* su = sE + 3 * EP;
   float* sv = su + D;                             // [2][D]
   float* sug = sv + 2 * D;                        // [2][D]: Wg1_e v_a
   float* sbg1 = sug + 2 * D;
@@ -2763,7 +2771,7 @@ void k_embed_gate_z(StepCtx c, EmbedW m, EmbedGateArgs a) {
   float* sEW = slb + D;                           // [3][2]: <E[x], w_a>
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
 
-  for (int i = tid; i < 3 * D; i += 512) sE[i] = m.E[i];
+  for (int i = tid; i < 3 * D; i += 512) sE[(i / D) * EP + i % D] = m.E[i];
   for (int i = tid; i < D; i += 512) {
     su[i] = m.u[i];
     sv[i] = m.v[i];
@@ -2823,7 +2831,7 @@ void k_embed_gate_z(StepCtx c, EmbedW m, EmbedGateArgs a) {
   const float c0 = expf(sEW[2 * x] * inv_tau - mx0) / den0 * a.p[2 * slot];
   const float c1 = expf(sEW[2 * x + 1] * inv_tau - mx1) / den1 * a.p[2 * slot + 1];
   const float* Pl = m.P + (long)l * D;
-  const float* Ex = sE + x * D;
+  const float* Ex = sE + x * EP;
 
   // ---- Z in the B-operand layout: k-step s holds features 16 s + 8 g2 + 0..7
   bf16x8 xf[KZ];
