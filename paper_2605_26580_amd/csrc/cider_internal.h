@@ -113,6 +113,9 @@ struct Mat {
   // 0-3, 8-11, 4-7, 12-15: the k order of an operand held in the 32 x 32
   // accumulator layout, so that a lane's 8 k-values are one 16-byte read
   const bf16* b16k = nullptr;
+  // BF16 in MFMA-fragment order for the four-wave output projection + MLP
+  // kernel (W_o, W1 and W2 of the d = 256 model; om4_fragment_copy)
+  const bf16* b16f = nullptr;
   int rows = 0, cols = 0;
 };
 
@@ -277,6 +280,7 @@ hipError_t launch_oproj_mlp3_bf16(const GemmArgs& g, const Mat& Wo, const float*
                                   const float* lnx_b, const Mat& W1, const float* b1, const Mat& W2, int F,
                                   hipStream_t s, int variant = 0, bool f8_up = false);
 int oproj_mlp3_variants();
+void om4_fragment_copy(int role, int d, int F, const float* src, uint16_t* dst, uint16_t (*to_bf16)(float));
 bool mlp16_ok(int d, int F);
 hipError_t launch_mlp16_bf16(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s);
 bool user_mlp_tr_ok(int d, int heads, int F);

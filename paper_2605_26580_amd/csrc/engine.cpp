@@ -1494,6 +1494,7 @@ int cider_weights_create(const cider_model_cfg* cfg, const float* blob, size_t n
     L.ln2_g = vec(d); L.ln2_b = vec(d);
     if ((rc = mat(3 * d, d, &L.Wqkv_u))) goto bad;
     L.bqkv_u = vec(3 * (size_t)d);
+    const size_t off_wou = off;
     if ((rc = mat(d, d, &L.Wo_u))) goto bad;
     L.bo_u = vec(d);
     L.ln3_g = vec(d); L.ln3_b = vec(d);
@@ -1525,7 +1526,30 @@ int cider_weights_create(const cider_model_cfg* cfg, const float* blob, size_t n
       }
     }
     L.b1 = vec(F);
-    if ((rc = mat(d, F, &L.W2))) goto bad;
+    {
+      const size_t off_w1 = off - (size_t)F - (size_t)F * d, off_w2 = off;
+      if ((rc = mat(d, F, &L.W2))) goto bad;
+      if (oproj_mlp3_ok(d, F)) {
+        // fragment-major copies of W_o, W1 and W2 for the four-wave output
+        // projection + MLP kernel
+        const Mat* ms[3] = {&L.Wo_u, &L.W1, &L.W2};
+        const size_t offs[3] = {off_wou, off_w1, off_w2};
+        Mat* dstm[3] = {&L.Wo_u, &L.W1, &L.W2};
+        for (int role = 0; role < 3; ++role) {
+          const size_t cnt = (size_t)ms[role]->rows * ms[role]->cols;
+          std::vector<uint16_t> hf(cnt);
+          om4_fragment_copy(role, d, F, blob + offs[role], hf.data(), f32_to_bf16_bits);
+          void* df = nullptr;
+          if (hipMalloc(&df, cnt * 2) != hipSuccess) { rc = fail(CIDER_ENOMEM, "weights hipMalloc"); goto bad; }
+          w->allocs.push_back(df);
+          if (hipMemcpy(df, hf.data(), cnt * 2, hipMemcpyHostToDevice) != hipSuccess) {
+            rc = fail(CIDER_EDEVICE, "weights upload");
+            goto bad;
+          }
+          dstm[role]->b16f = (const bf16*)df;
+        }
+      }
+    }
     L.b2 = vec(d);
   }
   m.lnf_g = vec(d);

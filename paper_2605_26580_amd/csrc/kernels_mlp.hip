@@ -2181,6 +2181,204 @@ void k_oproj_mlp3(GemmArgs g, const bf16* __restrict__ Wo, const float* __restri
 }
 
 // ---------------------------------------------------------------------------
+// k_oproj_mlp4: the computation of k_oproj_mlp3 (same MFMA sequence for every
+// output element, so the same bits) in workgroups of four waves and 128
+// tokens whose LDS fits twice in a CU (76 KB at d = 256).  Two workgroups per
+// CU let one workgroup's loads of O and R and its stores of R and XN, which
+// a CU moves at its own limited rate, run while the other computes.  The
+// weights come from fragment-major copies (Mat::b16f): each MFMA A-operand
+// fragment is 1 KB, lane l's 16 bytes at 16 l, so a chunk is one contiguous
+// run of 1 KB DMA blocks and every LDS read is a conflict-free 1 KB read
+// with the fragment index in the instruction's offset; nothing is padded.
+// W_o goes through LDS in chunks of 64 k-columns (32 fragments), the MLP in
+// chunks of 32 hidden units (16 W1 fragments, then 16 W2 fragments), each
+// double-buffered in one 64 KB region.
+template <int D, int MAXF>
+struct OM4Smem {
+  static constexpr int KCH = 64;
+  static constexpr size_t wo = (size_t)D * KCH * 2;            // a W_o chunk: D rows x 64 k
+  static constexpr size_t wm = (size_t)2 * kM3FCH * D * 2;     // an MLP chunk: W1 (32 x D) and W2 (D x 32)
+  static constexpr size_t buf = wo > wm ? wo : wm;
+  static constexpr size_t vec = ((size_t)(3 * D + MAXF + 5 * D) * 4 + 1023) / 1024 * 1024;
+  static constexpr size_t bytes = vec + 2 * buf;
+  static_assert(bytes <= 80 * 1024, "two workgroups per CU");
+};
+
+template <int D, int MAXF, bool PROJ, int PF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_oproj_mlp4(GemmArgs g, const bf16* __restrict__ Wof, const float* __restrict__ bo,
+                  const float* __restrict__ lnx_g, const float* __restrict__ lnx_b, const bf16* __restrict__ W1f,
+                  const float* __restrict__ b1, const bf16* __restrict__ W2f, int F) {
+  using S = OM4Smem<D, MAXF>;
+  constexpr int NW = 4, KCH = S::KCH, NCH = D / KCH, KSC = KCH / 16, OBK = D / 32, KS = D / 16;
+  constexpr int NBO = (int)(S::wo / 1024), NB1 = KS, NB2 = 2 * OBK;   // 1 KB fragments per chunk
+  static_assert(NBO % NW == 0 && (NB1 + NB2) % NW == 0 && NB1 % NW == 0, "DMA blocks split evenly over the waves");
+  constexpr int TPW = NW * 32;                      // tokens per workgroup
+  __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
+  float* svo = (float*)smem;                        // b_o, LN gain, LN bias
+  float* sb1 = svo + 3 * D;                         // b1 [MAXF]
+  float* svm = sb1 + MAXF;                          // b2, next LayerNorm, projection rows
+  char* const wreg = smem + S::vec;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
+  const long tok0 = (long)blockIdx.x * TPW + wave * 32 + l32;
+  const bool tv = tok0 < g.M;
+  const int tok = tv ? (int)tok0 : -1;
+  const int nch = F / kM3FCH;
+  const bf16* __restrict__ A = (const bf16*)g.A;
+
+  // chunk c of W_o: fragments c * NBO .. c * NBO + NBO - 1 of the copy
+  auto dma_o = [&](int c, int buf) {
+#pragma unroll
+    for (int k = 0; k < NBO / NW; ++k) {
+      const int u = wave + NW * k;
+      __builtin_amdgcn_global_load_lds(Wof + ((long)c * NBO + u) * 512 + lane * 8,
+                                       (__attribute__((address_space(3))) void*)(wreg + buf * S::buf + u * 1024), 16, 0, 0);
+    }
+  };
+  // MLP chunk ch: its NB1 W1 fragments, then its NB2 W2 fragments
+  auto dma_m = [&](int ch, int buf) {
+#pragma unroll
+    for (int k = 0; k < (NB1 + NB2) / NW; ++k) {
+      const int u = wave + NW * k;
+      const bf16* src = u < NB1 ? W1f + ((long)ch * NB1 + u) * 512 : W2f + ((long)ch * NB2 + (u - NB1)) * 512;
+      __builtin_amdgcn_global_load_lds(src + lane * 8,
+                                       (__attribute__((address_space(3))) void*)(wreg + buf * S::buf + u * 1024), 16, 0, 0);
+    }
+  };
+  auto afrag = [&](int c, bf16x8 (&f)[KSC]) {
+#pragma unroll
+    for (int s = 0; s < KSC; ++s)
+      f[s] = tv ? *(const bf16x8*)(A + tok0 * D + c * KCH + 16 * s + 8 * g2) : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+  };
+
+  for (int i = tid; i < D; i += NW * 64) {
+    svo[i] = bo[i];
+    svo[D + i] = lnx_g[i];
+    svo[2 * D + i] = lnx_b[i];
+  }
+  for (int i = tid; i < F; i += NW * 64) sb1[i] = b1[i];
+  m3_stage_vectors<D>(svm, g, PROJ, tid, NW * 64);
+
+  // ================= output projection =================
+  f32x16 acc2[OBK][1];
+#pragma unroll
+  for (int b = 0; b < OBK; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc2[b][0][r] = 0.f;
+  bf16x8 fa[KSC], fn[KSC];
+  afrag(0, fa);
+  dma_o(0, 0);
+  __syncthreads();
+#pragma unroll 1
+  for (int c = 0; c < NCH; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < NCH) {
+      dma_o(c + 1, buf ^ 1);
+      afrag(c + 1, fn);
+    }
+    const char* sw = wreg + buf * S::buf + lane * 16;
+    // fragment i: output block i % OBK, k-step i / OBK of the chunk
+    mfma_pipe<KSC * OBK, PF>(
+        [&](int i) { return *(const bf16x8*)(sw + i * 1024); },
+        [&](int i, const bf16x8& w) {
+          acc2[i % OBK][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, fa[i / OBK], acc2[i % OBK][0], 0, 0, 0);
+        });
+    if (c + 1 < NCH) {
+#pragma unroll
+      for (int s = 0; s < KSC; ++s) fa[s] = fn[s];
+    }
+    __syncthreads();                                // every wave is done with this buffer
+  }
+  dma_m(0, 0);
+
+  // ---- R1 = R + acc2 + b_o in place, X1 = LN(R1) in the accumulator layout, then acc2 = R1 + b2
+  bf16x8 x1[KS];
+  {
+    const float* Rrow = g.R + (long)(tv ? tok0 : 0) * D;
+    float sum = 0.f;
+#pragma unroll
+    for (int b = 0; b < OBK; ++b) {
+      f32x4 rr[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        rr[q] = tv ? *(const f32x4*)(Rrow + 32 * b + 8 * q + 4 * g2) : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f32x4 bias = *(const f32x4*)&svo[32 * b + 8 * q + 4 * g2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float res = rr[q][i] + (acc2[b][0][4 * q + i] + bias[i]);
+          acc2[b][0][4 * q + i] = res;
+          sum += res;
+        }
+      }
+      asm volatile("" : "+v"(acc2[b][0]), "+v"(sum)::"memory");   // bounds the loads in flight
+    }
+    sum = xhalf_sum(sum);
+    const float mean = sum / (float)D;
+    float qv = 0.f;
+#pragma unroll
+    for (int b = 0; b < OBK; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float dv = acc2[b][0][r] - mean;
+        qv = fmaf(dv, dv, qv);
+      }
+    qv = xhalf_sum(qv);
+    const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
+#pragma unroll
+    for (int b = 0; b < OBK; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int f = 32 * b + 8 * q + 4 * g2;
+        const f32x4 lg = *(const f32x4*)&svo[D + f];
+        const f32x4 lb = *(const f32x4*)&svo[2 * D + f];
+        const f32x4 b2 = *(const f32x4*)&svm[f];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          x1[2 * b + (q >> 1)][4 * (q & 1) + i] = (bf16)((acc2[b][0][4 * q + i] - mean) * rstd * lg[i] + lb[i]);
+          acc2[b][0][4 * q + i] += b2[i];
+        }
+        if (q & 1) asm volatile("" : "+v"(x1[2 * b + (q >> 1)]), "+v"(acc2[b][0])::"memory");
+      }
+  }
+
+  // ================= MLP (one chunk of 32 hidden units at a time) =================
+  m3_wait_barrier(0);                               // chunk 0 in LDS
+#pragma unroll 1
+  for (int ch = 0; ch < nch; ++ch) {
+    // the other buffer was last read in iteration ch - 1, before its closing barrier
+    if (ch + 1 < nch) dma_m(ch + 1, (ch + 1) & 1);
+    const char* s1 = wreg + (ch & 1) * S::buf + lane * 16;
+    const float* sb = sb1 + ch * kM3FCH;
+    // up: acc1 = b1 + W1 X1 for the chunk's 32 hidden units (W1 fragments in X1's k order)
+    f32x16 acc1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const f32x4 bq = *(const f32x4*)&sb[16 * (q >> 1) + 8 * g2 + 4 * (q & 1)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc1[4 * q + i] = bq[i];
+    }
+    mfma_pipe<KS, PF>([&](int s) { return *(const bf16x8*)(s1 + s * 1024); },
+                      [&](int s, const bf16x8& w) { acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, x1[s], acc1, 0, 0, 0); });
+    bf16x8 hf[2];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) hf[q >> 1][4 * (q & 1) + i] = (bf16)gelu_f(acc1[4 * q + i]);
+    // down: acc2 += W2 GELU(.) over the chunk; fragment j: output block j / 2, k-step j % 2
+    mfma_pipe<NB2, PF>(
+        [&](int j) { return *(const bf16x8*)(s1 + (NB1 + j) * 1024); },
+        [&](int j, const bf16x8& w) {
+          acc2[j >> 1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, hf[j & 1], acc2[j >> 1][0], 0, 0, 0);
+        });
+    // chunk ch + 1 complete in every wave, and every wave done with buffer ch & 1
+    if (ch + 1 < nch) m3_wait_barrier(0);
+  }
+  m3_epilogue_final<D, PROJ>(acc2, tok, g, g2, svm);
+}
+
+// ---------------------------------------------------------------------------
 // The row sublayer's output projection followed by the user sublayer's QKV
 // projection and attention (BF16, d = 256, head width 32), in one kernel per
 // 32-slot user group (the output projection is per token, so it runs on the
@@ -3242,7 +3440,20 @@ hipError_t launch_oproj_mlp3_bf16(const GemmArgs& g, const Mat& Wo, const float*
   }
   // variants differ in the depth of the MLP weight-chunk ring (2, 3 or 4
   // buffers) and in how many weight fragments each wave keeps in flight
-  // ahead of its MFMAs; every element's arithmetic is the same
+  // ahead of its MFMAs, and variant 5 is the four-wave k_oproj_mlp4; every
+  // element's arithmetic is the same
+  if (variant == 5) {
+    // four-wave workgroups, two per CU, on the fragment-major weight copies
+    if (!Wo.b16f || !W1.b16f || !W2.b16f || F > 1024) return hipErrorInvalidValue;
+    const dim3 grid4((unsigned)((g.M + 127) / 128)), block4(256);
+    if (g.proj_out)
+      hipLaunchKernelGGL((k_oproj_mlp4<256, 1024, true, 3>), grid4, block4, 0, s, g, Wo.b16f, bo, lnx_g, lnx_b, W1.b16f,
+                         b1, W2.b16f, F);
+    else
+      hipLaunchKernelGGL((k_oproj_mlp4<256, 1024, false, 3>), grid4, block4, 0, s, g, Wo.b16f, bo, lnx_g, lnx_b,
+                         W1.b16f, b1, W2.b16f, F);
+    return hipGetLastError();
+  }
   if (variant == 1) { CIDER_OM(3, 3) }
   else if (variant == 2) { CIDER_OM(2, 2) }
   else if (variant == 3) { CIDER_OM(2, 4) }
@@ -3252,7 +3463,44 @@ hipError_t launch_oproj_mlp3_bf16(const GemmArgs& g, const Mat& Wo, const float*
   return hipGetLastError();
 }
 
-int oproj_mlp3_variants() { return 5; }
+int oproj_mlp3_variants() { return 6; }
+
+// The fragment-major copies k_oproj_mlp4 reads (see there): fragment f is
+// elements 512 f .. 512 f + 511, lane l's eight at 8 l, lane l = 32 g2 + l32.
+//   role 0, W_o [d][d]: f = (d / 32) (4 c + s) + b -> row 32 b + l32, columns
+//     64 c + 16 s + 8 g2 + e (chunk c of 64 columns, k-step s, block b)
+//   role 1, W1 [F][d]: f = (d / 16) ch + s -> row 32 ch + sigma(l32), the
+//     k-ordered columns 16 s + 8 g2 + e (the order of X1's accumulator layout)
+//   role 2, W2 [d][F]: f = (d / 16) ch + 2 b + ks -> row 32 b + l32, columns
+//     32 ch + 16 ks + 8 g2 + e
+void om4_fragment_copy(int role, int d, int F, const float* src, uint16_t* dst, uint16_t (*to_bf16)(float)) {
+  static const int kperm[16] = {0, 1, 2, 3, 8, 9, 10, 11, 4, 5, 6, 7, 12, 13, 14, 15};
+  const int rows = role == 1 ? F : d, cols = role == 2 ? F : d;
+  const size_t nfrag = (size_t)rows * cols / 512;
+  const int obk = d / 32, ks = d / 16;
+  for (size_t f = 0; f < nfrag; ++f)
+    for (int l = 0; l < 64; ++l)
+      for (int e = 0; e < 8; ++e) {
+        const int g2 = l >> 5, l32 = l & 31;
+        int r, c;
+        if (role == 0) {
+          const int cs = (int)(f / obk), b = (int)(f % obk);
+          r = 32 * b + l32;
+          c = 16 * cs + 8 * g2 + e;                 // 16 (4 c + s) = 64 c + 16 s
+        } else if (role == 1) {
+          const int ch = (int)(f / ks), s = (int)(f % ks);
+          const int q = l32 >> 3, g = (l32 >> 2) & 1, i = l32 & 3;
+          r = 32 * ch + 16 * (q >> 1) + 8 * g + 4 * (q & 1) + i;   // sigma(l32)
+          const int kc = 16 * s + 8 * g2 + e;
+          c = (kc & ~15) + kperm[kc & 15];
+        } else {
+          const int ch = (int)(f / (2 * obk)), j = (int)(f % (2 * obk));
+          r = 32 * (j >> 1) + l32;
+          c = 32 * ch + 16 * (j & 1) + 8 * g2 + e;
+        }
+        dst[f * 512 + (size_t)l * 8 + e] = to_bf16(src[(size_t)r * cols + c]);
+      }
+}
 
 bool mlp16_ok(int d, int F) { return d == 384 && F % 32 == 0 && F >= 64 && F <= 1536; }
 
