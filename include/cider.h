@@ -458,7 +458,8 @@ int cider_profile_read(const cider_weights* w, cider_kernel_stat* out, int32_t m
  * those of the library's GEMM (0 = the default shape).  Roles "user_mlp_tr"
  * and "oproj_mlp3" (the fused sublayer + MLP kernels): n is d, kd the hidden
  * width, tile the variant (0 = the default; variants change the waves per
- * workgroup or the weight-ring depth, never a result). */
+ * workgroup, the weights' layout in LDS, the weight-ring depth or the
+ * fragment prefetch depth, never a result). */
 typedef struct {
   char    role[24];
   int32_t n, kd, bucket, tile;

@@ -3438,32 +3438,37 @@ hipError_t launch_oproj_mlp3_bf16(const GemmArgs& g, const Mat& Wo, const float*
                          W1.b16k, b1, W2.b16, F, W1.f8p, W1.f8_scale);
     return hipGetLastError();
   }
-  // variants differ in the depth of the MLP weight-chunk ring (2, 3 or 4
-  // buffers) and in how many weight fragments each wave keeps in flight
-  // ahead of its MFMAs, and variant 5 is the four-wave k_oproj_mlp4; every
-  // element's arithmetic is the same
-  if (variant == 5) {
-    // four-wave workgroups, two per CU, on the fragment-major weight copies
+  // Variants 0-2: the four-wave k_oproj_mlp4 (two workgroups per CU, on the
+  // fragment-major weight copies) with 3, 2 or 4 weight fragments in flight
+  // ahead of its MFMAs; variants 3-7: the eight-wave k_oproj_mlp3 with MLP
+  // weight-chunk rings of 2, 3 or 4 buffers and 2-4 fragments in flight.
+  // Every element's arithmetic is the same in all of them.
+  if (variant >= 0 && variant <= 2) {
     if (!Wo.b16f || !W1.b16f || !W2.b16f || F > 1024) return hipErrorInvalidValue;
     const dim3 grid4((unsigned)((g.M + 127) / 128)), block4(256);
-    if (g.proj_out)
-      hipLaunchKernelGGL((k_oproj_mlp4<256, 1024, true, 3>), grid4, block4, 0, s, g, Wo.b16f, bo, lnx_g, lnx_b, W1.b16f,
-                         b1, W2.b16f, F);
-    else
-      hipLaunchKernelGGL((k_oproj_mlp4<256, 1024, false, 3>), grid4, block4, 0, s, g, Wo.b16f, bo, lnx_g, lnx_b,
-                         W1.b16f, b1, W2.b16f, F);
+#define CIDER_OM4(PF)                                                                                             \
+  if (g.proj_out)                                                                                                 \
+    hipLaunchKernelGGL((k_oproj_mlp4<256, 1024, true, PF>), grid4, block4, 0, s, g, Wo.b16f, bo, lnx_g, lnx_b,     \
+                       W1.b16f, b1, W2.b16f, F);                                                                   \
+  else                                                                                                            \
+    hipLaunchKernelGGL((k_oproj_mlp4<256, 1024, false, PF>), grid4, block4, 0, s, g, Wo.b16f, bo, lnx_g, lnx_b,    \
+                       W1.b16f, b1, W2.b16f, F);
+    if (variant == 1) { CIDER_OM4(2) }
+    else if (variant == 2) { CIDER_OM4(4) }
+    else { CIDER_OM4(3) }
+#undef CIDER_OM4
     return hipGetLastError();
   }
-  if (variant == 1) { CIDER_OM(3, 3) }
-  else if (variant == 2) { CIDER_OM(2, 2) }
-  else if (variant == 3) { CIDER_OM(2, 4) }
-  else if (variant == 4) { CIDER_OM(4, 3) }
+  if (variant == 4) { CIDER_OM(3, 3) }
+  else if (variant == 5) { CIDER_OM(2, 2) }
+  else if (variant == 6) { CIDER_OM(2, 4) }
+  else if (variant == 7) { CIDER_OM(4, 3) }
   else { CIDER_OM(2, 3) }
 #undef CIDER_OM
   return hipGetLastError();
 }
 
-int oproj_mlp3_variants() { return 6; }
+int oproj_mlp3_variants() { return 8; }
 
 // The fragment-major copies k_oproj_mlp4 reads (see there): fragment f is
 // elements 512 f .. 512 f + 511, lane l's eight at 8 l, lane l = 32 g2 + l32.

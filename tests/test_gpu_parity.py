@@ -332,7 +332,7 @@ def test_every_gemm_tile_teacher_forced(K, n, L, d, h):
     ref = denoise(X, p, code, w, L, h, gamma)
     for fused in (1, 0):
         base = None
-        for tile in (0, 1, 2, 3, 5, 0):
+        for tile in (0, 1, 2, 3, 4, 5, 0):
             say(f"forced tile {tile} d={d} fused_blocks={fused}")
             opts = P.cider_opts_default(precision=P.CIDER_BF16, autotune=2 + tile, fused_blocks=fused)
             lg = torch.zeros(K, n, 2, dtype=torch.float32, device="cuda")
@@ -403,7 +403,7 @@ def test_every_gemm_tile_gives_identical_decodes():
         bins = synth.make_bins(code, K, 6, 4.0, seed=60 + d)
         y = _dev(bins.y)
         ref = None
-        for mode in (0, 1, 2, 3, 4, 5, 6, 7):
+        for mode in (0, 1, 2, 3, 4, 5, 6, 7, 8, 9):
             say(f"tiles d={d} autotune={mode}")
             opts = P.cider_opts_default(precision=P.CIDER_BF16, autotune=mode)
             out = torch.zeros(6, K, n, dtype=torch.uint8, device="cuda")
@@ -420,8 +420,8 @@ def test_every_gemm_tile_gives_identical_decodes():
             # the user sublayer + MLP kernel's variants (forced tiles 0-3 above)
             assert "user_mlp_tr" in roles, roles
         elif d == 256:
-            # the output projection + MLP kernel's variants (forced tiles 0-5 above;
-            # tile 5 is the four-wave kernel on the fragment-major weights)
+            # the output projection + MLP kernel's variants (forced tiles 0-7 above:
+            # 0-2 the four-wave kernel on the fragment-major weights, 3-7 the eight-wave one)
             assert "oproj_mlp3" in roles, roles
         else:
             assert len(roles) > 0
