@@ -1489,9 +1489,11 @@ int cider_weights_create(const cider_model_cfg* cfg, const float* blob, size_t n
     L.ln1_g = vec(d); L.ln1_b = vec(d);
     if ((rc = mat(3 * d, d, &L.Wqkv_r))) goto bad;
     L.bqkv_r = vec(3 * (size_t)d);
+    const size_t off_wor = off;
     if ((rc = mat(d, d, &L.Wo_r))) goto bad;
     L.bo_r = vec(d);
     L.ln2_g = vec(d); L.ln2_b = vec(d);
+    const size_t off_wqu = off;
     if ((rc = mat(3 * d, d, &L.Wqkv_u))) goto bad;
     L.bqkv_u = vec(3 * (size_t)d);
     const size_t off_wou = off;
@@ -1529,25 +1531,26 @@ int cider_weights_create(const cider_model_cfg* cfg, const float* blob, size_t n
     {
       const size_t off_w1 = off - (size_t)F - (size_t)F * d, off_w2 = off;
       if ((rc = mat(d, F, &L.W2))) goto bad;
-      if (oproj_mlp3_ok(d, F)) {
-        // fragment-major copies of W_o, W1 and W2 for the four-wave output
-        // projection + MLP kernel
-        const Mat* ms[3] = {&L.Wo_u, &L.W1, &L.W2};
-        const size_t offs[3] = {off_wou, off_w1, off_w2};
-        Mat* dstm[3] = {&L.Wo_u, &L.W1, &L.W2};
-        for (int role = 0; role < 3; ++role) {
-          const size_t cnt = (size_t)ms[role]->rows * ms[role]->cols;
-          std::vector<uint16_t> hf(cnt);
-          om4_fragment_copy(role, d, F, blob + offs[role], hf.data(), f32_to_bf16_bits);
-          void* df = nullptr;
-          if (hipMalloc(&df, cnt * 2) != hipSuccess) { rc = fail(CIDER_ENOMEM, "weights hipMalloc"); goto bad; }
-          w->allocs.push_back(df);
-          if (hipMemcpy(df, hf.data(), cnt * 2, hipMemcpyHostToDevice) != hipSuccess) {
-            rc = fail(CIDER_EDEVICE, "weights upload");
-            goto bad;
-          }
-          dstm[role]->b16f = (const bf16*)df;
+      // fragment-major copies for the four-wave kernels: W_o (user), W1 and
+      // W2 for the output projection + MLP, W_o (row) and the user Wqkv for
+      // the row output projection + user attention
+      const bool om4 = oproj_mlp3_ok(d, F), ou4 = oproj_user_attn_ok(d, cfg->heads);
+      Mat* dstm[5] = {&L.Wo_u, &L.W1, &L.W2, &L.Wo_r, &L.Wqkv_u};
+      const int roles[5] = {0, 1, 2, 0, 3};
+      const size_t offs[5] = {off_wou, off_w1, off_w2, off_wor, off_wqu};
+      for (int k = 0; k < 5; ++k) {
+        if (!(k < 3 ? om4 : ou4)) continue;
+        const size_t cnt = (size_t)dstm[k]->rows * dstm[k]->cols;
+        std::vector<uint16_t> hf(cnt);
+        om4_fragment_copy(roles[k], d, F, blob + offs[k], hf.data(), f32_to_bf16_bits);
+        void* df = nullptr;
+        if (hipMalloc(&df, cnt * 2) != hipSuccess) { rc = fail(CIDER_ENOMEM, "weights hipMalloc"); goto bad; }
+        w->allocs.push_back(df);
+        if (hipMemcpy(df, hf.data(), cnt * 2, hipMemcpyHostToDevice) != hipSuccess) {
+          rc = fail(CIDER_EDEVICE, "weights upload");
+          goto bad;
         }
+        dstm[k]->b16f = (const bf16*)df;
       }
     }
     L.b2 = vec(d);

@@ -2659,6 +2659,271 @@ void k_oproj_user_attn(StepCtx c, const bf16* __restrict__ Orow, const bf16* __r
 }
 
 // ---------------------------------------------------------------------------
+// k_oproj_user_attn4: the computation of k_oproj_user_attn (the same MFMA
+// sequence for every output, so the same bits) in workgroups of four user
+// groups whose LDS fits twice in a CU (78 KB at d = 256), on fragment-major
+// weight copies (Mat::b16f; see k_oproj_mlp4): W_o in chunks of 64 k-columns
+// (double-buffered), the user QKV projection in chunks of half a head's k
+// range (its Q, K and V fragments of eight k-steps, 24 KB) in a ring of three.
+template <int D>
+struct OU4Smem {
+  static constexpr int KCH = 64, NBQ = 3;
+  static constexpr size_t wo = (size_t)D * KCH * 2;             // a W_o chunk
+  static constexpr size_t wq = (size_t)3 * 32 * (D / 2) * 2;    // Q, K, V rows of a head over half of k
+  static constexpr size_t vec = (size_t)6 * D * 4;              // bqkv; b_o, LN2 gain, LN2 bias
+  static constexpr size_t region = 2 * wo > NBQ * wq ? 2 * wo : NBQ * wq;
+  static constexpr size_t bytes = vec + region;
+  static_assert(vec % 1024 == 0 && bytes <= 80 * 1024, "two workgroups per CU");
+};
+
+template <int D>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_oproj_user_attn4(StepCtx c, const bf16* __restrict__ Orow, const bf16* __restrict__ Wof,
+                        const float* __restrict__ bo, const float* __restrict__ ln_g, const float* __restrict__ ln_b,
+                        float* __restrict__ R, const bf16* __restrict__ Wqf, const float* __restrict__ bqkv,
+                        bf16* __restrict__ O) {
+  using S = OU4Smem<D>;
+  constexpr int NW = 4, KCH = S::KCH, NCH = D / KCH, KSC = KCH / 16, OBK = D / 32, KS = D / 16, HEADS = D / 32;
+  constexpr int NBO = (int)(S::wo / 1024), KH = KS / 2, NBQ = 3 * KH;   // 1 KB fragments per chunk
+  constexpr int NQ = 2 * HEADS, NBUF = S::NBQ, DIST = NBUF - 1;        // QKV chunks; ring
+  static_assert(NBO % NW == 0 && NBQ % NW == 0, "DMA blocks split evenly over the waves");
+  constexpr int QPW = NBQ / NW;                     // DMA blocks per wave per QKV chunk
+  __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
+  char* const wreg = smem + S::vec;
+  float* sbias = (float*)smem;                      // bqkv [3D]
+  float* svo = sbias + 3 * D;                       // b_o, LN2 gain, LN2 bias
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
+
+  // ---- this lane's slot of the wave's group
+  const int gi = blockIdx.x * NW + wave;
+  int tok = -1, K = 1;
+  if (gi < c.total_ugrp32) {
+    const int bi = c.ugrp32[2 * gi], c0 = c.ugrp32[2 * gi + 1];
+    const DevBin& b = c.bins[bi];
+    K = b.K;
+    const int C = 32 / K, cl = l32 / K, k = l32 - cl * K;
+    if (l32 < C * K && c0 + cl < b.n) tok = b.tok_off + k * b.n + c0 + cl;
+  }
+  const unsigned long long vmask = __ballot(tok >= 0);
+  unsigned okbits = 0;                               // register r of S^T: key slot 8(r/4) + 4 g2 + r%4
+  const int col_lo = (l32 / K) * K;                 // key slots of this lane's column: col_lo .. col_lo + K - 1
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int kr = 8 * (r >> 2) + 4 * g2 + (r & 3);
+    if (((vmask >> kr) & 1ull) && (unsigned)(kr - col_lo) < (unsigned)K) okbits |= 1u << r;
+  }
+  const bool tv = tok >= 0;
+
+  auto dma_o = [&](int cc, int buf) {
+#pragma unroll
+    for (int k = 0; k < NBO / NW; ++k) {
+      const int u = wave + NW * k;
+      __builtin_amdgcn_global_load_lds(Wof + ((long)cc * NBO + u) * 512 + lane * 8,
+                                       (__attribute__((address_space(3))) void*)(wreg + buf * S::wo + u * 1024), 16, 0, 0);
+    }
+  };
+  // QKV chunk t: head t / 2, k-steps KH (t % 2) .. KH (t % 2) + KH - 1
+  auto dma_q = [&](int t, int buf) {
+#pragma unroll
+    for (int k = 0; k < QPW; ++k) {
+      const int u = wave + NW * k;
+      __builtin_amdgcn_global_load_lds(Wqf + ((long)t * NBQ + u) * 512 + lane * 8,
+                                       (__attribute__((address_space(3))) void*)(wreg + buf * S::wq + u * 1024), 16, 0, 0);
+    }
+  };
+  auto afrag = [&](int cc, bf16x8 (&f)[KSC]) {
+#pragma unroll
+    for (int s = 0; s < KSC; ++s)
+      f[s] = tv ? *(const bf16x8*)(Orow + (long)tok * D + cc * KCH + 16 * s + 8 * g2) : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+  };
+  for (int i = tid; i < 3 * D; i += NW * 64) sbias[i] = bqkv[i];
+  for (int i = tid; i < D; i += NW * 64) {
+    svo[i] = bo[i];
+    svo[D + i] = ln_g[i];
+    svo[2 * D + i] = ln_b[i];
+  }
+
+  // ================= row output projection =================
+  f32x16 acc2[OBK];
+#pragma unroll
+  for (int b = 0; b < OBK; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc2[b][r] = 0.f;
+  {
+    bf16x8 fa[KSC], fn[KSC];
+    afrag(0, fa);
+    dma_o(0, 0);
+    __syncthreads();
+#pragma unroll 1
+    for (int cc = 0; cc < NCH; ++cc) {
+      const int buf = cc & 1;
+      if (cc + 1 < NCH) {
+        dma_o(cc + 1, buf ^ 1);
+        afrag(cc + 1, fn);
+      }
+      const char* sw = wreg + buf * S::wo + lane * 16;
+      // fragment i: output block i % OBK, k-step i / OBK of the chunk
+      mfma_pipe<KSC * OBK, 3>([&](int i) { return *(const bf16x8*)(sw + i * 1024); },
+                              [&](int i, const bf16x8& w) {
+                                acc2[i % OBK] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, fa[i / OBK], acc2[i % OBK], 0, 0, 0);
+                              });
+      if (cc + 1 < NCH) {
+#pragma unroll
+        for (int s = 0; s < KSC; ++s) fa[s] = fn[s];
+      }
+      __syncthreads();                              // every wave is done with this buffer
+    }
+  }
+  // the W_o buffers are dead: the QKV ring takes the region (DIST chunks ahead)
+#pragma unroll
+  for (int t = 0; t < DIST; ++t) dma_q(t, t);
+
+  // ---- R1 = R + acc2 + b_o (written), X2 = LN2(R1) in the accumulator layout
+  bf16x8 xf[KS];
+  {
+    float* Rrow = R + (long)(tv ? tok : 0) * D;
+    float sum = 0.f;
+#pragma unroll
+    for (int b = 0; b < OBK; ++b) {
+      f32x4 rr[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        rr[q] = tv ? *(const f32x4*)(Rrow + 32 * b + 8 * q + 4 * g2) : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f32x4 bias = *(const f32x4*)&svo[32 * b + 8 * q + 4 * g2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float res = rr[q][i] + (acc2[b][4 * q + i] + bias[i]);
+          acc2[b][4 * q + i] = res;
+          sum += res;
+        }
+        if (tv)
+          *(f32x4*)(Rrow + 32 * b + 8 * q + 4 * g2) =
+              f32x4{acc2[b][4 * q], acc2[b][4 * q + 1], acc2[b][4 * q + 2], acc2[b][4 * q + 3]};
+      }
+      asm volatile("" : "+v"(acc2[b]), "+v"(sum)::"memory");   // bounds the loads in flight
+    }
+    sum = xhalf_sum(sum);
+    const float mean = sum / (float)D;
+    float qv = 0.f;
+#pragma unroll
+    for (int b = 0; b < OBK; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float dv = acc2[b][r] - mean;
+        qv = fmaf(dv, dv, qv);
+      }
+    qv = xhalf_sum(qv);
+    const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
+#pragma unroll
+    for (int b = 0; b < OBK; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int f = 32 * b + 8 * q + 4 * g2;
+        const f32x4 lg = *(const f32x4*)&svo[D + f];
+        const f32x4 lb = *(const f32x4*)&svo[2 * D + f];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          xf[2 * b + (q >> 1)][4 * (q & 1) + i] = (bf16)((acc2[b][4 * q + i] - mean) * rstd * lg[i] + lb[i]);
+        if (q & 1) asm volatile("" : "+v"(xf[2 * b + (q >> 1)])::"memory");
+      }
+  }
+
+  // ================= user attention (as k_oproj_user_attn) =================
+  const float scale = 1.4426950408889634f / sqrtf(32.0f);
+  constexpr int HB = 2;                             // heads per O store batch (registers)
+  bf16x4 ob[HB][4];
+  bf16* orow = O + (long)(tv ? tok : 0) * D;
+#pragma unroll
+  for (int h = 0; h < HEADS; ++h) {
+    f32x16 aq, ak, av;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) aq[r] = ak[r] = av[r] = 0.f;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const int t = 2 * h + half;
+      // chunk t complete in every wave (later chunks may be in flight), and
+      // every wave done with chunk t - 1, whose buffer the next DMA refills
+      m3_wait_barrier(QPW * (min(t + DIST - 1, NQ - 1) - t));
+      // the previous batch of heads' O, stored between the wait and the next
+      // DMA so that the next wait does not cover that DMA
+      if (half == 0 && h % HB == 0 && h > 0 && tv) {
+#pragma unroll
+        for (int hh = 0; hh < HB; ++hh)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) *(bf16x4*)(orow + (h - HB + hh) * 32 + 8 * q + 4 * g2) = ob[hh][q];
+      }
+      if (t + DIST < NQ) dma_q(t + DIST, (t + DIST) % NBUF);
+      const char* sw = wreg + (t % NBUF) * S::wq + lane * 16;
+      // fragment 3 s + m: k-step KH half + s of Q (m = 0), K (1) and V (2)
+#pragma unroll
+      for (int s = 0; s < KH; ++s) {
+        const bf16x8 wq = *(const bf16x8*)(sw + (3 * s) * 1024);
+        const bf16x8 wk = *(const bf16x8*)(sw + (3 * s + 1) * 1024);
+        const bf16x8 wv = *(const bf16x8*)(sw + (3 * s + 2) * 1024);
+        aq = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wq, xf[KH * half + s], aq, 0, 0, 0);
+        ak = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wk, xf[KH * half + s], ak, 0, 0, 0);
+        av = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xf[KH * half + s], wv, av, 0, 0, 0);
+      }
+    }
+    bf16x8 qf[2], kf[2], vf[2];
+    const float bv = sbias[2 * D + h * 32 + l32];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int f = h * 32 + 8 * q + 4 * g2;
+      const f32x4 bq = *(const f32x4*)&sbias[f];
+      const f32x4 bk = *(const f32x4*)&sbias[D + f];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 4 * q + i;
+        qf[r >> 3][r & 7] = (bf16)(aq[r] + bq[i]);
+        kf[r >> 3][r & 7] = (bf16)(ak[r] + bk[i]);
+        vf[r >> 3][r & 7] = (bf16)(av[r] + bv);
+      }
+    }
+    f32x16 st;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) st[r] = 0.f;
+    st = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kf[0], qf[0], st, 0, 0, 0);
+    st = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kf[1], qf[1], st, 0, 0, 0);
+    float mx = -INFINITY;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      st[r] = ((okbits >> r) & 1u) ? st[r] : -INFINITY;
+      mx = fmaxf(mx, st[r]);
+    }
+    mx = xhalf_max(mx);
+    const float mxs = mx == -INFINITY ? 0.f : -mx * scale;   // a padding query has no valid key
+    float ps = 0.f;
+    bf16x8 pf[2];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float p = __builtin_amdgcn_exp2f(fmaf(st[r], scale, mxs));
+      ps += p;
+      pf[r >> 3][r & 7] = (bf16)p;
+    }
+    ps = xhalf_sum(ps);
+    f32x16 o;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) o[r] = 0.f;
+    o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vf[0], pf[0], o, 0, 0, 0);
+    o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vf[1], pf[1], o, 0, 0, 0);
+    const float inv = ps > 0.f ? 1.0f / ps : 0.f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      ob[h % HB][q] = bf16x4{(bf16)(o[4 * q] * inv), (bf16)(o[4 * q + 1] * inv), (bf16)(o[4 * q + 2] * inv),
+                             (bf16)(o[4 * q + 3] * inv)};
+  }
+  if (tv) {
+#pragma unroll
+    for (int hh = 0; hh < HB; ++hh)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) *(bf16x4*)(orow + (HEADS - HB + hh) * 32 + 8 * q + 4 * g2) = ob[hh][q];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Module A for the BF16 path, from the symbol grid to the first LayerNorm in
 // one token-resident kernel (method section, Module A; Appendix, one-step
 // algorithm):
@@ -3403,6 +3668,12 @@ hipError_t launch_oproj_user_attn(const StepCtx& c, const void* Orow, const Mat&
                                   void* O, int d, int heads, hipStream_t s) {
   if (c.total_ugrp32 == 0) return hipSuccess;
   if (!oproj_user_attn_ok(d, heads) || !c.ugrp32 || !Wo.b16 || !Wqkv.b16k) return hipErrorInvalidValue;
+  if (Wo.b16f && Wqkv.b16f) {
+    // four groups per workgroup, two workgroups per CU, fragment-major weights
+    hipLaunchKernelGGL((k_oproj_user_attn4<256>), dim3((c.total_ugrp32 + 3) / 4), dim3(256), 0, s, c,
+                       (const bf16*)Orow, Wo.b16f, bo, ln_g, ln_b, R, Wqkv.b16f, bqkv, (bf16*)O);
+    return hipGetLastError();
+  }
   // the user QKV projection multiplies X2 held in the accumulator layout: Wqkv's k-ordered copy
   hipLaunchKernelGGL((k_oproj_user_attn<256>), dim3((c.total_ugrp32 + 7) / 8), dim3(512), 0, s, c,
                      (const bf16*)Orow, Wo.b16, bo, ln_g, ln_b, R, Wqkv.b16k, bqkv, (bf16*)O);
@@ -3478,9 +3749,12 @@ int oproj_mlp3_variants() { return 8; }
 //     k-ordered columns 16 s + 8 g2 + e (the order of X1's accumulator layout)
 //   role 2, W2 [d][F]: f = (d / 16) ch + 2 b + ks -> row 32 b + l32, columns
 //     32 ch + 16 ks + 8 g2 + e
+//   role 3, Wqkv [3d][d] (k_oproj_user_attn4): f = (3 d / 32) t + 3 s + m ->
+//     row m d + 32 (t / 2) + l32, the k-ordered columns 16 (d / 32 (t % 2) + s)
+//     + 8 g2 + e (chunk t: head t / 2, half t % 2 of the k range; m = Q, K, V)
 void om4_fragment_copy(int role, int d, int F, const float* src, uint16_t* dst, uint16_t (*to_bf16)(float)) {
   static const int kperm[16] = {0, 1, 2, 3, 8, 9, 10, 11, 4, 5, 6, 7, 12, 13, 14, 15};
-  const int rows = role == 1 ? F : d, cols = role == 2 ? F : d;
+  const int rows = role == 1 ? F : role == 3 ? 3 * d : d, cols = role == 2 ? F : d;
   const size_t nfrag = (size_t)rows * cols / 512;
   const int obk = d / 32, ks = d / 16;
   for (size_t f = 0; f < nfrag; ++f)
@@ -3497,6 +3771,11 @@ void om4_fragment_copy(int role, int d, int F, const float* src, uint16_t* dst, 
           const int q = l32 >> 3, g = (l32 >> 2) & 1, i = l32 & 3;
           r = 32 * ch + 16 * (q >> 1) + 8 * g + 4 * (q & 1) + i;   // sigma(l32)
           const int kc = 16 * s + 8 * g2 + e;
+          c = (kc & ~15) + kperm[kc & 15];
+        } else if (role == 3) {
+          const int kh = ks / 2, t = (int)(f / (3 * kh)), i3 = (int)(f % (3 * kh)), s = i3 / 3, m = i3 % 3;
+          r = m * d + 32 * (t / 2) + l32;
+          const int kc = 16 * (kh * (t % 2) + s) + 8 * g2 + e;
           c = (kc & ~15) + kperm[kc & 15];
         } else {
           const int ch = (int)(f / (2 * obk)), j = (int)(f % (2 * obk));
