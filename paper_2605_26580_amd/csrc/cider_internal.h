@@ -116,6 +116,7 @@ struct Mat {
   // BF16 in MFMA-fragment order for the four-wave output projection + MLP
   // kernel (W_o, W1 and W2 of the d = 256 model; om4_fragment_copy)
   const bf16* b16f = nullptr;
+  const uint8_t* f8f = nullptr;   // W1 only: f8p in the four-wave kernel's fragment order
   int rows = 0, cols = 0;
 };
 
@@ -281,6 +282,7 @@ hipError_t launch_oproj_mlp3_bf16(const GemmArgs& g, const Mat& Wo, const float*
                                   hipStream_t s, int variant = 0, bool f8_up = false);
 int oproj_mlp3_variants();
 void om4_fragment_copy(int role, int d, int F, const float* src, uint16_t* dst, uint16_t (*to_bf16)(float));
+void om4_fragment_copy_f8(int d, int F, const uint8_t* w1p, uint8_t* dst);
 bool mlp16_ok(int d, int F);
 hipError_t launch_mlp16_bf16(const GemmArgs& g, const Mat& W1, const float* b1, const Mat& W2, int F, hipStream_t s);
 bool user_mlp_tr_ok(int d, int heads, int F);

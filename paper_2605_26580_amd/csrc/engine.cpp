@@ -1525,6 +1525,18 @@ int cider_weights_create(const cider_model_cfg* cfg, const float* blob, size_t n
           goto bad;
         }
         L.W1.f8p = (const uint8_t*)dp;
+        if (oproj_mlp3_ok(d, F)) {
+          std::vector<uint8_t> f8f(p8.size());
+          om4_fragment_copy_f8(d, F, p8.data(), f8f.data());
+          void* df = nullptr;
+          if (hipMalloc(&df, f8f.size()) != hipSuccess) { rc = fail(CIDER_ENOMEM, "weights hipMalloc"); goto bad; }
+          w->allocs.push_back(df);
+          if (hipMemcpy(df, f8f.data(), f8f.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            rc = fail(CIDER_EDEVICE, "weights upload");
+            goto bad;
+          }
+          L.W1.f8f = (const uint8_t*)df;
+        }
       }
     }
     L.b1 = vec(F);

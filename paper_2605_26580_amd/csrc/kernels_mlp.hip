@@ -2204,14 +2204,17 @@ struct OM4Smem {
   static_assert(bytes <= 80 * 1024, "two workgroups per CU");
 };
 
-template <int D, int MAXF, bool PROJ, int PF>
+template <int D, int MAXF, bool PROJ, int PF, bool F8 = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_oproj_mlp4(GemmArgs g, const bf16* __restrict__ Wof, const float* __restrict__ bo,
                   const float* __restrict__ lnx_g, const float* __restrict__ lnx_b, const bf16* __restrict__ W1f,
-                  const float* __restrict__ b1, const bf16* __restrict__ W2f, int F) {
+                  const float* __restrict__ b1, const bf16* __restrict__ W2f, int F,
+                  const uint8_t* __restrict__ W1qf, float w1s) {
   using S = OM4Smem<D, MAXF>;
   constexpr int NW = 4, KCH = S::KCH, NCH = D / KCH, KSC = KCH / 16, OBK = D / 32, KS = D / 16;
-  constexpr int NBO = (int)(S::wo / 1024), NB1 = KS, NB2 = 2 * OBK;   // 1 KB fragments per chunk
+  // 1 KB fragments per chunk; with F8 a W1 k-step of 64 is 2 KB (lane l's
+  // 32 e4m3 bytes as two 16-byte halves, at 16 l and 1024 + 16 l)
+  constexpr int NBO = (int)(S::wo / 1024), NB1 = F8 ? 2 * (D / 64) : KS, NB2 = 2 * OBK;
   static_assert(NBO % NW == 0 && (NB1 + NB2) % NW == 0 && NB1 % NW == 0, "DMA blocks split evenly over the waves");
   constexpr int TPW = NW * 32;                      // tokens per workgroup
   __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
@@ -2240,8 +2243,10 @@ void k_oproj_mlp4(GemmArgs g, const bf16* __restrict__ Wof, const float* __restr
 #pragma unroll
     for (int k = 0; k < (NB1 + NB2) / NW; ++k) {
       const int u = wave + NW * k;
-      const bf16* src = u < NB1 ? W1f + ((long)ch * NB1 + u) * 512 : W2f + ((long)ch * NB2 + (u - NB1)) * 512;
-      __builtin_amdgcn_global_load_lds(src + lane * 8,
+      const char* src = u < NB1 ? (F8 ? (const char*)W1qf + ((long)ch * NB1 + u) * 1024
+                                      : (const char*)(W1f + ((long)ch * NB1 + u) * 512))
+                                : (const char*)(W2f + ((long)ch * NB2 + (u - NB1)) * 512);
+      __builtin_amdgcn_global_load_lds(src + lane * 16,
                                        (__attribute__((address_space(3))) void*)(wreg + buf * S::buf + u * 1024), 16, 0, 0);
     }
   };
@@ -2293,6 +2298,8 @@ void k_oproj_mlp4(GemmArgs g, const bf16* __restrict__ Wof, const float* __restr
 
   // ---- R1 = R + acc2 + b_o in place, X1 = LN(R1) in the accumulator layout, then acc2 = R1 + b2
   bf16x8 x1[KS];
+  i32x8 xq[F8 ? D / 64 : 1];
+  float xsc = 1.f;
   {
     const float* Rrow = g.R + (long)(tv ? tok0 : 0) * D;
     float sum = 0.f;
@@ -2341,6 +2348,28 @@ void k_oproj_mlp4(GemmArgs g, const bf16* __restrict__ Wof, const float* __restr
         }
         if (q & 1) asm volatile("" : "+v"(x1[2 * b + (q >> 1)]), "+v"(acc2[b][0])::"memory");
       }
+    if constexpr (F8) {
+      // e4m3 fragments of X1 with the token's scale amax / 448, as in k_oproj_mlp3
+      float amax = 0.f;
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) amax = fmaxf(amax, fabsf((float)x1[s][e]));
+      amax = xhalf_max(amax);
+      xsc = amax > 0.f ? amax / 448.0f : 1.0f;
+      const float inv = 1.0f / xsc;
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          float hq[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) hq[i] = fminf(fmaxf((float)x1[s][4 * h + i] * inv, -448.f), 448.f);
+          int pk = __builtin_amdgcn_cvt_pk_fp8_f32(hq[0], hq[1], 0, false);
+          pk = __builtin_amdgcn_cvt_pk_fp8_f32(hq[2], hq[3], pk, true);
+          xq[s >> 2][2 * (s & 3) + h] = pk;
+        }
+    }
   }
 
   // ================= MLP (one chunk of 32 hidden units at a time) =================
@@ -2353,14 +2382,34 @@ void k_oproj_mlp4(GemmArgs g, const bf16* __restrict__ Wof, const float* __restr
     const float* sb = sb1 + ch * kM3FCH;
     // up: acc1 = b1 + W1 X1 for the chunk's 32 hidden units (W1 fragments in X1's k order)
     f32x16 acc1;
+    if constexpr (F8) {
+      // acc1 = b1 + (scale of X1 x w1s) (W1q X1q) over D / 64 steps of 64
+      f32x16 a;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const f32x4 bq = *(const f32x4*)&sb[16 * (q >> 1) + 8 * g2 + 4 * (q & 1)];
+      for (int r = 0; r < 16; ++r) a[r] = 0.f;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) acc1[4 * q + i] = bq[i];
+      for (int t = 0; t < D / 64; ++t) {
+        const int4 lo = *(const int4*)(s1 + 2 * t * 1024), hi = *(const int4*)(s1 + (2 * t + 1) * 1024);
+        const i32x8 wa = i32x8{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+        a = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(wa, xq[t], a, 0, 0, 0, 127, 0, 127);
+      }
+      const float sc = xsc * w1s;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f32x4 bq = *(const f32x4*)&sb[16 * (q >> 1) + 8 * g2 + 4 * (q & 1)];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc1[4 * q + i] = a[4 * q + i] * sc + bq[i];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f32x4 bq = *(const f32x4*)&sb[16 * (q >> 1) + 8 * g2 + 4 * (q & 1)];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc1[4 * q + i] = bq[i];
+      }
+      mfma_pipe<KS, PF>([&](int s) { return *(const bf16x8*)(s1 + s * 1024); },
+                        [&](int s, const bf16x8& w) { acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, x1[s], acc1, 0, 0, 0); });
     }
-    mfma_pipe<KS, PF>([&](int s) { return *(const bf16x8*)(s1 + s * 1024); },
-                      [&](int s, const bf16x8& w) { acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, x1[s], acc1, 0, 0, 0); });
     bf16x8 hf[2];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -3698,6 +3747,18 @@ hipError_t launch_oproj_mlp3_bf16(const GemmArgs& g, const Mat& Wo, const float*
   else                                                                                                            \
     hipLaunchKernelGGL((k_oproj_mlp3<256, NB, 1024, false, PF>), grid, block, 0, s, g, Wo.b16, bo, lnx_g, lnx_b,   \
                        W1.b16k, b1, W2.b16, F, nullptr, 1.f);
+  if (f8_up && W1.f8f && Wo.b16f && W2.b16f) {
+    // the up projection in e4m3 on the four-wave kernel (W1.f8f: the reordered
+    // e4m3 copy in fragment order)
+    const dim3 grid4((unsigned)((g.M + 127) / 128)), block4(256);
+    if (g.proj_out)
+      hipLaunchKernelGGL((k_oproj_mlp4<256, 1024, true, 2, true>), grid4, block4, 0, s, g, Wo.b16f, bo, lnx_g, lnx_b,
+                         W1.b16f, b1, W2.b16f, F, W1.f8f, W1.f8_scale);
+    else
+      hipLaunchKernelGGL((k_oproj_mlp4<256, 1024, false, 2, true>), grid4, block4, 0, s, g, Wo.b16f, bo, lnx_g, lnx_b,
+                         W1.b16f, b1, W2.b16f, F, W1.f8f, W1.f8_scale);
+    return hipGetLastError();
+  }
   if (f8_up) {
     // the up projection in e4m3 (W1.f8p, the reordered copy)
     if (!W1.f8p) return hipErrorInvalidValue;
@@ -3720,10 +3781,10 @@ hipError_t launch_oproj_mlp3_bf16(const GemmArgs& g, const Mat& Wo, const float*
 #define CIDER_OM4(PF)                                                                                             \
   if (g.proj_out)                                                                                                 \
     hipLaunchKernelGGL((k_oproj_mlp4<256, 1024, true, PF>), grid4, block4, 0, s, g, Wo.b16f, bo, lnx_g, lnx_b,     \
-                       W1.b16f, b1, W2.b16f, F);                                                                   \
+                       W1.b16f, b1, W2.b16f, F, nullptr, 1.f);                                                     \
   else                                                                                                            \
     hipLaunchKernelGGL((k_oproj_mlp4<256, 1024, false, PF>), grid4, block4, 0, s, g, Wo.b16f, bo, lnx_g, lnx_b,    \
-                       W1.b16f, b1, W2.b16f, F);
+                       W1.b16f, b1, W2.b16f, F, nullptr, 1.f);
     if (variant == 1) { CIDER_OM4(2) }
     else if (variant == 2) { CIDER_OM4(4) }
     else { CIDER_OM4(3) }
@@ -3752,6 +3813,25 @@ int oproj_mlp3_variants() { return 8; }
 //   role 3, Wqkv [3d][d] (k_oproj_user_attn4): f = (3 d / 32) t + 3 s + m ->
 //     row m d + 32 (t / 2) + l32, the k-ordered columns 16 (d / 32 (t % 2) + s)
 //     + 8 g2 + e (chunk t: head t / 2, half t % 2 of the k range; m = Q, K, V)
+// The e4m3 W1 of k_oproj_mlp4<..., F8>: from the reordered e4m3 rows w1p
+// (Mat::f8p's layout, rows of d bytes), fragment (ch, t) of 2 KB holds, for
+// lane l = 32 h + l32, bytes 64 t + 32 h .. + 31 of row 32 ch + sigma(l32) as
+// two 16-byte halves at 16 l and 1024 + 16 l.
+void om4_fragment_copy_f8(int d, int F, const uint8_t* w1p, uint8_t* dst) {
+  const int nt = d / 64;
+  for (int ch = 0; ch < F / 32; ++ch)
+    for (int t = 0; t < nt; ++t)
+      for (int l = 0; l < 64; ++l) {
+        const int h = l >> 5, l32 = l & 31;
+        const int q = l32 >> 3, g = (l32 >> 2) & 1, i = l32 & 3;
+        const int row = 32 * ch + 16 * (q >> 1) + 8 * g + 4 * (q & 1) + i;   // sigma(l32)
+        for (int half = 0; half < 2; ++half)
+          for (int e = 0; e < 16; ++e)
+            dst[((size_t)ch * nt + t) * 2048 + half * 1024 + (size_t)l * 16 + e] =
+                w1p[(size_t)row * d + 64 * t + 32 * h + 16 * half + e];
+      }
+}
+
 void om4_fragment_copy(int role, int d, int F, const float* src, uint16_t* dst, uint16_t (*to_bf16)(float)) {
   static const int kperm[16] = {0, 1, 2, 3, 8, 9, 10, 11, 4, 5, 6, 7, 12, 13, 14, 15};
   const int rows = role == 1 ? F : role == 3 ? 3 * d : d, cols = role == 2 ? F : d;
