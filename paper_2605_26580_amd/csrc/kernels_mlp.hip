@@ -2432,288 +2432,16 @@ void k_oproj_mlp4(GemmArgs g, const bf16* __restrict__ Wof, const float* __restr
 // projection and attention (BF16, d = 256, head width 32), in one kernel per
 // 32-slot user group (the output projection is per token, so it runs on the
 // user grouping): R1 = R + O_row W_o^T + b_o is written, X2 = LN2(R1) stays
-// in registers in the accumulator's layout and feeds the QKV projection,
-// whose weight fragments are read in that order (two 8-byte reads per
-// fragment; for the transposed V projection both operands use it); the user
-// attention then proceeds as in k_user_qkv_attn and writes O_user.  The W_o
-// chunk ring and the per-head QKV buffers share one LDS region.  Saves the
-// XN round trip between the two sublayers.
-template <int D>
-struct OUSmem {
-  using O = O3Smem<D, 128>;
-  using U = UQSmem<D>;
-  static constexpr size_t wo = 2 * O::wa;
-  static constexpr size_t wu = 2 * U::wa;
-  static constexpr size_t w = wo > wu ? wo : wu;
-  static constexpr size_t vec = (size_t)(3 * D + 3 * D) * 4;   // bqkv; b_o, LN2 gain, LN2 bias
-  static constexpr size_t bytes = w + vec;
-  static_assert(bytes <= 160 * 1024, "LDS");
-};
-
-template <int D>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
-void k_oproj_user_attn(StepCtx c, const bf16* __restrict__ Orow, const bf16* __restrict__ Wo,
-                       const float* __restrict__ bo, const float* __restrict__ ln_g, const float* __restrict__ ln_b,
-                       float* __restrict__ R, const bf16* __restrict__ W, const float* __restrict__ bqkv,
-                       bf16* __restrict__ O) {
-  constexpr int KCH = 128;
-  using S = OUSmem<D>;
-  using OS = typename S::O;
-  using U = typename S::U;
-  constexpr int RBO = OS::RB, NCH = OS::NCH, KSC = KCH / 16, OBK = D / 32;
-  constexpr int NBO = (int)(OS::wa / 1024), NPWO = (NBO + 7) / 8;
-  constexpr int RB = U::RB, KS = D / 16, HEADS = D / 32;
-  constexpr int NB = (int)((U::w + 1023) / 1024), NPW = (NB + 7) / 8;
-  __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
-  // the vectors sit at the start of LDS, where one base register plus an
-  // immediate offset reaches each of them; the weight buffers follow
-  static_assert(S::vec % 1024 == 0, "weight region 1 KB aligned");
-  char* const wreg = smem + S::vec;
-  float* sbias = (float*)smem;                      // bqkv [3D]
-  float* svo = sbias + 3 * D;                       // b_o, LN2 gain, LN2 bias
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
-
-  // ---- this lane's slot of the wave's group
-  const int gi = blockIdx.x * 8 + wave;
-  int tok = -1, K = 1;
-  if (gi < c.total_ugrp32) {
-    const int bi = c.ugrp32[2 * gi], c0 = c.ugrp32[2 * gi + 1];
-    const DevBin& b = c.bins[bi];
-    K = b.K;
-    const int C = 32 / K, cl = l32 / K, k = l32 - cl * K;
-    if (l32 < C * K && c0 + cl < b.n) tok = b.tok_off + k * b.n + c0 + cl;
-  }
-  const unsigned long long vmask = __ballot(tok >= 0);
-  unsigned okbits = 0;                               // register r of S^T: key slot 8(r/4) + 4 g2 + r%4
-  const int col_lo = (l32 / K) * K;                 // key slots of this lane's column: col_lo .. col_lo + K - 1
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int kr = 8 * (r >> 2) + 4 * g2 + (r & 3);
-    if (((vmask >> kr) & 1ull) && (unsigned)(kr - col_lo) < (unsigned)K) okbits |= 1u << r;
-  }
-  const bool tv = tok >= 0;
-
-  auto dma_o = [&](int cc, int buf) {
-    char* base = wreg + buf * OS::wa;
-#pragma unroll
-    for (int k = 0; k < NPWO; ++k) {
-      const int u = wave + k * 8;
-      if (u >= NBO) break;
-      const int pos = u * 1024 + lane * 16, j = pos / RBO, o = pos - j * RBO;
-      const bool data = o < RBO - 16;
-      const bf16* src = Wo + (long)(data ? j : 0) * D + cc * KCH + (data ? o / 2 : 0);
-      if (pos < (int)OS::w)
-        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(base + u * 1024), 16, 0, 0);
-    }
-  };
-  auto afrag = [&](int cc, bf16x8 (&f)[KSC]) {
-#pragma unroll
-    for (int s = 0; s < KSC; ++s)
-      f[s] = tv ? *(const bf16x8*)(Orow + (long)tok * D + cc * KCH + 16 * s + 8 * g2) : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
-  };
-  auto dma = [&](int h, int buf) {
-    char* base = wreg + buf * U::wa;
-#pragma unroll
-    for (int k = 0; k < NPW; ++k) {
-      const int u = wave + k * 8;                   // uniform over the wave
-      if (u >= NB) break;
-      const int pos = u * 1024 + lane * 16, j = pos / RB, o = pos - j * RB;
-      const bool data = o < RB - 16;                 // else a pad (copy something in bounds)
-      const int jj = data ? j : 0;
-      const bf16* src = W + (long)((jj >> 5) * D + h * 32 + (jj & 31)) * D + (data ? o / 2 : 0);
-      if (pos < (int)U::w)
-        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(base + u * 1024), 16, 0, 0);
-    }
-  };
-  for (int i = tid; i < 3 * D; i += 512) sbias[i] = bqkv[i];
-  for (int i = tid; i < D; i += 512) {
-    svo[i] = bo[i];
-    svo[D + i] = ln_g[i];
-    svo[2 * D + i] = ln_b[i];
-  }
-
-  // ================= row output projection (as k_oproj3) =================
-  f32x16 acc2[OBK];
-#pragma unroll
-  for (int b = 0; b < OBK; ++b)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc2[b][r] = 0.f;
-  {
-    bf16x8 fa[KSC], fn[KSC];
-    afrag(0, fa);
-    dma_o(0, 0);
-    __syncthreads();
-#pragma unroll 1
-    for (int cc = 0; cc < NCH; ++cc) {
-      const int buf = cc & 1;
-      if (cc + 1 < NCH) {
-        dma_o(cc + 1, buf ^ 1);
-        afrag(cc + 1, fn);
-      }
-      const char* sw = wreg + buf * OS::wa;
-#pragma unroll
-      for (int s = 0; s < KSC; ++s)
-#pragma unroll
-        for (int b = 0; b < OBK; ++b) {
-          const bf16x8 w = *(const bf16x8*)(sw + (32 * b + l32) * RBO + (2 * s + g2) * 16);
-          acc2[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, fa[s], acc2[b], 0, 0, 0);
-        }
-      if (cc + 1 < NCH) {
-#pragma unroll
-        for (int s = 0; s < KSC; ++s) fa[s] = fn[s];
-      }
-      __syncthreads();                              // every wave is done with this buffer
-    }
-  }
-  dma(0, 0);                                        // the W_o buffers are dead
-
-  // ---- R1 = R + acc2 + b_o (written), X2 = LN2(R1) in the accumulator layout
-  bf16x8 xf[KS];
-  {
-    float* Rrow = R + (long)(tv ? tok : 0) * D;
-    float sum = 0.f;
-#pragma unroll
-    for (int b = 0; b < OBK; ++b) {
-      f32x4 rr[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        rr[q] = tv ? *(const f32x4*)(Rrow + 32 * b + 8 * q + 4 * g2) : f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const f32x4 bias = *(const f32x4*)&svo[32 * b + 8 * q + 4 * g2];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const float res = rr[q][i] + (acc2[b][4 * q + i] + bias[i]);
-          acc2[b][4 * q + i] = res;
-          sum += res;
-        }
-        if (tv)
-          *(f32x4*)(Rrow + 32 * b + 8 * q + 4 * g2) =
-              f32x4{acc2[b][4 * q], acc2[b][4 * q + 1], acc2[b][4 * q + 2], acc2[b][4 * q + 3]};
-      }
-      asm volatile("" : "+v"(acc2[b]), "+v"(sum)::"memory");   // bounds the loads in flight
-    }
-    sum = xhalf_sum(sum);
-    const float mean = sum / (float)D;
-    float qv = 0.f;
-#pragma unroll
-    for (int b = 0; b < OBK; ++b)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const float dv = acc2[b][r] - mean;
-        qv = fmaf(dv, dv, qv);
-      }
-    qv = xhalf_sum(qv);
-    const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
-#pragma unroll
-    for (int b = 0; b < OBK; ++b)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int f = 32 * b + 8 * q + 4 * g2;
-        const f32x4 lg = *(const f32x4*)&svo[D + f];
-        const f32x4 lb = *(const f32x4*)&svo[2 * D + f];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          xf[2 * b + (q >> 1)][4 * (q & 1) + i] = (bf16)((acc2[b][4 * q + i] - mean) * rstd * lg[i] + lb[i]);
-        if (q & 1) asm volatile("" : "+v"(xf[2 * b + (q >> 1)])::"memory");
-      }
-  }
-
-  // ================= user attention (as k_user_qkv_attn; k order of X2) =================
-  const float scale = 1.4426950408889634f / sqrtf(32.0f);
-  constexpr int HB = 2;                             // heads per O store batch (registers)
-  bf16x4 ob[HB][4];
-  bf16* orow = O + (long)(tv ? tok : 0) * D;
-  auto wfrag = [&](const char* rowp, int s) {      // weight k-values in X2's order (k-ordered rows)
-    return *(const bf16x8*)(rowp + (16 * s + 8 * g2) * 2);
-  };
-#pragma unroll
-  for (int h = 0; h < HEADS; ++h) {
-    // chunk h in LDS; every wave is done with the previous head's buffer
-    m3_wait_barrier(0);
-    if (h % HB == 0 && h > 0 && tv) {
-#pragma unroll
-      for (int hh = 0; hh < HB; ++hh)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) *(bf16x4*)(orow + (h - HB + hh) * 32 + 8 * q + 4 * g2) = ob[hh][q];
-    }
-    if (h + 1 < HEADS) dma(h + 1, (h + 1) & 1);
-    const char* sw = wreg + (h & 1) * U::wa;
-    f32x16 aq, ak, av;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) aq[r] = ak[r] = av[r] = 0.f;
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const bf16x8 wq = wfrag(sw + l32 * RB, s);
-      const bf16x8 wk = wfrag(sw + (32 + l32) * RB, s);
-      const bf16x8 wv = wfrag(sw + (64 + l32) * RB, s);
-      aq = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wq, xf[s], aq, 0, 0, 0);
-      ak = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wk, xf[s], ak, 0, 0, 0);
-      av = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xf[s], wv, av, 0, 0, 0);
-    }
-    bf16x8 qf[2], kf[2], vf[2];
-    const float bv = sbias[2 * D + h * 32 + l32];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int f = h * 32 + 8 * q + 4 * g2;
-      const f32x4 bq = *(const f32x4*)&sbias[f];
-      const f32x4 bk = *(const f32x4*)&sbias[D + f];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = 4 * q + i;
-        qf[r >> 3][r & 7] = (bf16)(aq[r] + bq[i]);
-        kf[r >> 3][r & 7] = (bf16)(ak[r] + bk[i]);
-        vf[r >> 3][r & 7] = (bf16)(av[r] + bv);
-      }
-    }
-    f32x16 st;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) st[r] = 0.f;
-    st = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kf[0], qf[0], st, 0, 0, 0);
-    st = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kf[1], qf[1], st, 0, 0, 0);
-    float mx = -INFINITY;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      st[r] = ((okbits >> r) & 1u) ? st[r] : -INFINITY;
-      mx = fmaxf(mx, st[r]);
-    }
-    mx = xhalf_max(mx);
-    const float mxs = mx == -INFINITY ? 0.f : -mx * scale;   // a padding query has no valid key
-    float ps = 0.f;
-    bf16x8 pf[2];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const float p = __builtin_amdgcn_exp2f(fmaf(st[r], scale, mxs));
-      ps += p;
-      pf[r >> 3][r & 7] = (bf16)p;
-    }
-    ps = xhalf_sum(ps);
-    f32x16 o;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) o[r] = 0.f;
-    o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vf[0], pf[0], o, 0, 0, 0);
-    o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vf[1], pf[1], o, 0, 0, 0);
-    const float inv = ps > 0.f ? 1.0f / ps : 0.f;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      ob[h % HB][q] = bf16x4{(bf16)(o[4 * q] * inv), (bf16)(o[4 * q + 1] * inv), (bf16)(o[4 * q + 2] * inv),
-                             (bf16)(o[4 * q + 3] * inv)};
-  }
-  if (tv) {
-#pragma unroll
-    for (int hh = 0; hh < HB; ++hh)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) *(bf16x4*)(orow + (HEADS - HB + hh) * 32 + 8 * q + 4 * g2) = ob[hh][q];
-  }
-}
-
-// ---------------------------------------------------------------------------
-// k_oproj_user_attn4: the computation of k_oproj_user_attn (the same MFMA
-// sequence for every output, so the same bits) in workgroups of four user
-// groups whose LDS fits twice in a CU (78 KB at d = 256), on fragment-major
-// weight copies (Mat::b16f; see k_oproj_mlp4): W_o in chunks of 64 k-columns
-// (double-buffered), the user QKV projection in chunks of half a head's k
-// range (its Q, K and V fragments of eight k-steps, 24 KB) in a ring of three.
+// in registers in the accumulator's layout and feeds the QKV projection
+// (for the transposed V projection both operands use that layout); the user
+// attention then proceeds as in k_user_qkv_attn and writes O_user.  Saves the
+// XN round trip between the two sublayers.  A workgroup holds four user
+// groups and its LDS fits twice in a CU (78 KB at d = 256), so one
+// workgroup's loads and stores run under the other's compute.  The weights
+// come from fragment-major copies (Mat::b16f; see k_oproj_mlp4): W_o in
+// chunks of 64 k-columns (double-buffered), the user QKV projection in
+// chunks of half a head's k range (its Q, K and V fragments of eight
+// k-steps, 24 KB) in a ring of three.
 template <int D>
 struct OU4Smem {
   static constexpr int KCH = 64, NBQ = 3;
@@ -2879,7 +2607,7 @@ void k_oproj_user_attn4(StepCtx c, const bf16* __restrict__ Orow, const bf16* __
       }
   }
 
-  // ================= user attention (as k_oproj_user_attn) =================
+  // ================= user attention (as k_user_qkv_attn; k order of X2) =================
   const float scale = 1.4426950408889634f / sqrtf(32.0f);
   constexpr int HB = 2;                             // heads per O store batch (registers)
   bf16x4 ob[HB][4];
@@ -3716,16 +3444,10 @@ hipError_t launch_oproj_user_attn(const StepCtx& c, const void* Orow, const Mat&
                                   const float* ln_g, const float* ln_b, float* R, const Mat& Wqkv, const float* bqkv,
                                   void* O, int d, int heads, hipStream_t s) {
   if (c.total_ugrp32 == 0) return hipSuccess;
-  if (!oproj_user_attn_ok(d, heads) || !c.ugrp32 || !Wo.b16 || !Wqkv.b16k) return hipErrorInvalidValue;
-  if (Wo.b16f && Wqkv.b16f) {
-    // four groups per workgroup, two workgroups per CU, fragment-major weights
-    hipLaunchKernelGGL((k_oproj_user_attn4<256>), dim3((c.total_ugrp32 + 3) / 4), dim3(256), 0, s, c,
-                       (const bf16*)Orow, Wo.b16f, bo, ln_g, ln_b, R, Wqkv.b16f, bqkv, (bf16*)O);
-    return hipGetLastError();
-  }
-  // the user QKV projection multiplies X2 held in the accumulator layout: Wqkv's k-ordered copy
-  hipLaunchKernelGGL((k_oproj_user_attn<256>), dim3((c.total_ugrp32 + 7) / 8), dim3(512), 0, s, c,
-                     (const bf16*)Orow, Wo.b16, bo, ln_g, ln_b, R, Wqkv.b16k, bqkv, (bf16*)O);
+  if (!oproj_user_attn_ok(d, heads) || !c.ugrp32 || !Wo.b16f || !Wqkv.b16f) return hipErrorInvalidValue;
+  // four groups per workgroup, two workgroups per CU, fragment-major weights
+  hipLaunchKernelGGL((k_oproj_user_attn4<256>), dim3((c.total_ugrp32 + 3) / 4), dim3(256), 0, s, c,
+                     (const bf16*)Orow, Wo.b16f, bo, ln_g, ln_b, R, Wqkv.b16f, bqkv, (bf16*)O);
   return hipGetLastError();
 }
 
