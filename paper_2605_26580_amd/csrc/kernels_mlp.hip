@@ -1421,17 +1421,24 @@ void k_row_qkv_attn(StepCtx c, const bf16* __restrict__ XN, const bf16* __restri
     f32x16 o;
 #pragma unroll
     for (int r = 0; r < 16; ++r) o[r] = 0.f;
+    // K fragments of key block kb (read one block ahead of their MFMAs)
+    auto kfrag = [&](int kb, int s) {
+      const bf16* kr = &sK[(32 * kb + l32) * LDK + 16 * s + 4 * g2];
+      const bf16x4 k0 = *(const bf16x4*)kr, k1 = *(const bf16x4*)(kr + 8);
+      return bf16x8{k0[0], k0[1], k0[2], k0[3], k1[0], k1[1], k1[2], k1[3]};
+    };
+    bf16x8 kn[2] = {kfrag(0, 0), kfrag(0, 1)};
 #pragma unroll 1
     for (int kb = 0; kb < nkb; ++kb) {
       f32x16 st;
 #pragma unroll
       for (int r = 0; r < 16; ++r) st[r] = 0.f;
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const bf16* kr = &sK[(32 * kb + l32) * LDK + 16 * s + 4 * g2];
-        const bf16x4 k0 = *(const bf16x4*)kr, k1 = *(const bf16x4*)(kr + 8);
-        const bf16x8 kfr = bf16x8{k0[0], k0[1], k0[2], k0[3], k1[0], k1[1], k1[2], k1[3]};
-        st = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kfr, qf[s], st, 0, 0, 0);
+      const bf16x8 kc0 = kn[0], kc1 = kn[1];
+      st = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kc0, qf[0], st, 0, 0, 0);
+      st = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kc1, qf[1], st, 0, 0, 0);
+      if (kb + 1 < nkb) {
+        kn[0] = kfrag(kb + 1, 0);
+        kn[1] = kfrag(kb + 1, 1);
       }
       // register r: key 32 kb + 8(r/4) + 4 g2 + r%4; only the last block can
       // hold keys past n (a uniform branch)
