@@ -113,8 +113,10 @@ struct Mat {
   // 0-3, 8-11, 4-7, 12-15: the k order of an operand held in the 32 x 32
   // accumulator layout, so that a lane's 8 k-values are one 16-byte read
   const bf16* b16k = nullptr;
-  // BF16 in MFMA-fragment order for the four-wave output projection + MLP
-  // kernel (W_o, W1 and W2 of the d = 256 model; om4_fragment_copy)
+  // BF16 in MFMA-fragment order for the four-wave kernels (om4_fragment_copy):
+  // at d = 256 W_o, W1, W2 (output projection + MLP), W_o (row) and the user
+  // Wqkv (row output projection + user attention); at d = 128 the user Wqkv
+  // and W_o, W1, W2 (user sublayer + MLP)
   const bf16* b16f = nullptr;
   const uint8_t* f8f = nullptr;   // W1 only: f8p in the four-wave kernel's fragment order
   int rows = 0, cols = 0;

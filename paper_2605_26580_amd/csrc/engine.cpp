@@ -1546,12 +1546,14 @@ int cider_weights_create(const cider_model_cfg* cfg, const float* blob, size_t n
       // fragment-major copies for the four-wave kernels: W_o (user), W1 and
       // W2 for the output projection + MLP, W_o (row) and the user Wqkv for
       // the row output projection + user attention
+      // (d = 256); at d = 128 the same for the user sublayer + MLP kernel
       const bool om4 = oproj_mlp3_ok(d, F), ou4 = oproj_user_attn_ok(d, cfg->heads);
-      Mat* dstm[5] = {&L.Wo_u, &L.W1, &L.W2, &L.Wo_r, &L.Wqkv_u};
-      const int roles[5] = {0, 1, 2, 0, 3};
-      const size_t offs[5] = {off_wou, off_w1, off_w2, off_wor, off_wqu};
-      for (int k = 0; k < 5; ++k) {
-        if (!(k < 3 ? om4 : ou4)) continue;
+      const bool umf = user_mlp_tr_ok(d, cfg->heads, F);
+      Mat* dstm[9] = {&L.Wo_u, &L.W1, &L.W2, &L.Wo_r, &L.Wqkv_u, &L.Wqkv_u, &L.Wo_u, &L.W1, &L.W2};
+      const int roles[9] = {0, 1, 2, 0, 3, 5, 6, 1, 2};
+      const size_t offs[9] = {off_wou, off_w1, off_w2, off_wor, off_wqu, off_wqu, off_wou, off_w1, off_w2};
+      for (int k = 0; k < 9; ++k) {
+        if (!(k < 3 ? om4 : k < 5 ? ou4 : umf)) continue;
         const size_t cnt = (size_t)dstm[k]->rows * dstm[k]->cols;
         std::vector<uint16_t> hf(cnt);
         om4_fragment_copy(roles[k], d, F, blob + offs[k], hf.data(), f32_to_bf16_bits);

@@ -1902,6 +1902,278 @@ void k_user_mlp_tr(StepCtx c, UserMlpArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// k_user_mlp_f: the computation of k_user_mlp_tr (the same MFMA sequence for
+// every output, so the same bits) on fragment-major weight copies
+// (Mat::b16f; see k_oproj_mlp4), four waves per workgroup, two workgroups
+// per CU.  The user sublayer's weights of a head pair (its Wqkv fragments,
+// then its W_o fragments, 32 KB at d = 128) are double-buffered, so a pair
+// costs one barrier instead of four; the MLP's first two chunks are DMA'd
+// into the first pair buffer during the last pair, and the MLP chunks (16 KB)
+// then run through a ring of two.
+template <int D, int MAXF>
+struct UMFSmem {
+  static constexpr int KS = D / 16, OBK = D / 32;
+  static constexpr size_t ub = (size_t)(3 * KS + 2 * OBK) * 1024;   // a head pair's Wqkv and W_o fragments
+  static constexpr size_t mb = (size_t)(KS + 2 * OBK) * 1024;       // an MLP chunk's W1 and W2 fragments
+  static constexpr size_t vec = ((size_t)(3 * D + 3 * D + MAXF + 5 * D) * 4 + 1023) / 1024 * 1024;
+  static constexpr size_t bytes = vec + 2 * ub;
+  static_assert(2 * mb <= ub, "the MLP ring fits in the first pair buffer");
+  static_assert(bytes <= 80 * 1024, "two workgroups per CU");
+};
+
+template <int D, int MAXF, bool PROJ, int PF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_user_mlp_f(StepCtx c, UserMlpArgs a) {
+  using S = UMFSmem<D, MAXF>;
+  constexpr int NW = 4, KS = D / 16, NP = D / 32, OBK = D / 32, NTHR = NW * 64;
+  constexpr int NQ = 3 * KS, NO = 2 * OBK, NUB = NQ + NO, NM = KS + NO;   // 1 KB fragments per pair / MLP chunk
+  static_assert(NUB % NW == 0 && NM % NW == 0 && NP % 2 == 0, "DMA blocks split evenly; the last pair in buffer 1");
+  __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
+  float* sbias = (float*)smem;                      // bqkv [3D]
+  float* svu = sbias + 3 * D;                       // b_o, LN3 gain, LN3 bias
+  float* sb1 = svu + 3 * D;                         // b1 [MAXF]
+  float* svm = sb1 + MAXF;                          // b2, next LayerNorm, projection rows
+  char* const wreg = smem + S::vec;
+  const GemmArgs& g = a.g;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
+  const int F = a.F, nch = F / kM3FCH;
+
+  // ---- this lane's slot of the wave's group
+  const int gi = blockIdx.x * NW + wave;
+  int tok = -1, K = 1;
+  if (gi < c.total_ugrp32) {
+    const int bi = c.ugrp32[2 * gi], c0 = c.ugrp32[2 * gi + 1];
+    const DevBin& b = c.bins[bi];
+    K = b.K;
+    const int C = 32 / K, cl = l32 / K, k = l32 - cl * K;
+    if (l32 < C * K && c0 + cl < b.n) tok = b.tok_off + k * b.n + c0 + cl;
+  }
+  const unsigned long long vmask = __ballot(tok >= 0);
+  unsigned okbits = 0;                               // register r of S^T: key slot 8(r/4) + 4 g2 + r%4
+  const int col_lo = (l32 / K) * K;                 // key slots of this lane's column: col_lo .. col_lo + K - 1
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int kr = 8 * (r >> 2) + 4 * g2 + (r & 3);
+    if (((vmask >> kr) & 1ull) && (unsigned)(kr - col_lo) < (unsigned)K) okbits |= 1u << r;
+  }
+
+  // head pair p: its NQ Wqkv fragments (3 s + m: k-step s of Q, K, V), then its NO W_o fragments
+  auto dma_u = [&](int p, int buf) {
+#pragma unroll
+    for (int k = 0; k < NUB / NW; ++k) {
+      const int u = wave + NW * k;
+      const bf16* src = u < NQ ? a.Wqkv + ((long)p * NQ + u) * 512 : a.Wo + ((long)p * NO + (u - NQ)) * 512;
+      __builtin_amdgcn_global_load_lds(src + lane * 8,
+                                       (__attribute__((address_space(3))) void*)(wreg + buf * S::ub + u * 1024), 16, 0, 0);
+    }
+  };
+  // MLP chunk ch: its KS W1 fragments, then its NO W2 fragments
+  auto dma_m = [&](int ch, int buf) {
+#pragma unroll
+    for (int k = 0; k < NM / NW; ++k) {
+      const int u = wave + NW * k;
+      const bf16* src = u < KS ? a.W1 + ((long)ch * KS + u) * 512 : a.W2 + ((long)ch * NO + (u - KS)) * 512;
+      __builtin_amdgcn_global_load_lds(src + lane * 8,
+                                       (__attribute__((address_space(3))) void*)(wreg + buf * S::mb + u * 1024), 16, 0, 0);
+    }
+  };
+
+  for (int i = tid; i < 3 * D; i += NTHR) sbias[i] = a.bqkv[i];
+  for (int i = tid; i < D; i += NTHR) {
+    svu[i] = a.bo[i];
+    svu[D + i] = a.ln3_g[i];
+    svu[2 * D + i] = a.ln3_b[i];
+  }
+  for (int i = tid; i < F; i += NTHR) sb1[i] = a.b1[i];
+  m3_stage_vectors<D>(svm, g, PROJ, tid, NTHR);
+  const bf16* __restrict__ XN = (const bf16*)g.A;
+  bf16x8 xf[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s)
+    xf[s] = tok >= 0 ? *(const bf16x8*)(XN + (long)tok * D + 16 * s + 8 * g2) : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+  dma_u(0, 0);
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // staged vectors written (visible after the first barrier)
+
+  // ================= user sublayer (as k_user_mlp_tr) =================
+  const float scale = 1.4426950408889634f / 4.0f;     // log2(e) / sqrt(16)
+  f32x16 acc2[OBK][1];
+#pragma unroll
+  for (int ob = 0; ob < OBK; ++ob)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc2[ob][0][r] = 0.f;
+#pragma unroll 1
+  for (int p = 0; p < NP; ++p) {
+    // pair p in LDS in every wave, and every wave done with pair p - 1, whose buffer the next DMA refills
+    m3_wait_barrier(0);
+    if (p + 1 < NP) {
+      dma_u(p + 1, (p + 1) & 1);
+    } else {
+      // the last pair reads buffer 1: the MLP ring's first two chunks go into buffer 0
+      dma_m(0, 0);
+      if (nch > 1) dma_m(1, 1);
+    }
+    const char* su = wreg + (p & 1) * S::ub + lane * 16;
+    f32x16 aq, ak, av;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) aq[r] = ak[r] = av[r] = 0.f;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const bf16x8 wq = *(const bf16x8*)(su + (3 * s) * 1024);
+      const bf16x8 wk = *(const bf16x8*)(su + (3 * s + 1) * 1024);
+      const bf16x8 wv = *(const bf16x8*)(su + (3 * s + 2) * 1024);
+      aq = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wq, xf[s], aq, 0, 0, 0);
+      ak = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wk, xf[s], ak, 0, 0, 0);
+      av = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xf[s], wv, av, 0, 0, 0);
+    }
+    bf16x8 qf[2], kf[2], vf[2];
+    const float bv = sbias[2 * D + 32 * p + l32];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int f = 32 * p + 8 * q + 4 * g2;
+      const f32x4 bq = *(const f32x4*)&sbias[f];
+      const f32x4 bk = *(const f32x4*)&sbias[D + f];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 4 * q + i;
+        qf[r >> 3][r & 7] = (bf16)(aq[r] + bq[i]);
+        kf[r >> 3][r & 7] = (bf16)(ak[r] + bk[i]);
+        vf[r >> 3][r & 7] = (bf16)(av[r] + bv);
+      }
+    }
+    f32x16 ob;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      f32x16 st;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) st[r] = 0.f;
+      st = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kf[e], qf[e], st, 0, 0, 0);
+      float mx = -INFINITY;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        st[r] = ((okbits >> r) & 1u) ? st[r] : -INFINITY;
+        mx = fmaxf(mx, st[r]);
+      }
+      mx = xhalf_max(mx);
+      const float mxs = mx == -INFINITY ? 0.f : -mx * scale;   // a padding query has no valid key
+      float ps = 0.f;
+      bf16x8 pf[2];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float pv = __builtin_amdgcn_exp2f(fmaf(st[r], scale, mxs));
+        ps += pv;
+        pf[r >> 3][r & 7] = (bf16)pv;
+      }
+      ps = xhalf_sum(ps);
+      f32x16 o;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) o[r] = 0.f;
+      o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vf[0], pf[0], o, 0, 0, 0);
+      o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vf[1], pf[1], o, 0, 0, 0);
+      const float inv = ps > 0.f ? 1.0f / ps : 0.f;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) ob[8 * e + r] = o[8 * e + r] * inv;
+    }
+    bf16x8 of[2];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) of[r >> 3][r & 7] = (bf16)ob[r];
+    // W_o fragment 2 bo + s: output block bo, k-step s of the pair's columns
+#pragma unroll
+    for (int bo = 0; bo < OBK; ++bo)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const bf16x8 w = *(const bf16x8*)(su + (NQ + 2 * bo + s) * 1024);
+        acc2[bo][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, of[s], acc2[bo][0], 0, 0, 0);
+      }
+  }
+
+  // ---- R1 = R + acc2 + b_o in place, X1 = LN3(R1) as the up projection's B
+  // operand; acc2 then starts the MLP at R1 + b2
+  bf16x8 x1[KS];
+  {
+    const bool tv = tok >= 0;
+    const float* Rrow = g.R + (long)(tv ? tok : 0) * D;
+    float sum = 0.f;
+#pragma unroll
+    for (int b = 0; b < OBK; ++b) {
+      f32x4 rr[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        rr[q] = tv ? *(const f32x4*)(Rrow + 32 * b + 8 * q + 4 * g2) : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f32x4 bias = *(const f32x4*)&svu[32 * b + 8 * q + 4 * g2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float res = rr[q][i] + (acc2[b][0][4 * q + i] + bias[i]);
+          acc2[b][0][4 * q + i] = res;
+          sum += res;
+        }
+      }
+      asm volatile("" : "+v"(acc2[b][0]), "+v"(sum)::"memory");   // bounds the loads in flight
+    }
+    sum = xhalf_sum(sum);
+    const float mean = sum / (float)D;
+    float qv = 0.f;
+#pragma unroll
+    for (int b = 0; b < OBK; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float dv = acc2[b][0][r] - mean;
+        qv = fmaf(dv, dv, qv);
+      }
+    qv = xhalf_sum(qv);
+    const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
+#pragma unroll
+    for (int b = 0; b < OBK; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int f = 32 * b + 8 * q + 4 * g2;
+        const f32x4 lg = *(const f32x4*)&svu[D + f];
+        const f32x4 lb = *(const f32x4*)&svu[2 * D + f];
+        const f32x4 b2 = *(const f32x4*)&svm[f];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          x1[2 * b + (q >> 1)][4 * (q & 1) + i] = (bf16)((acc2[b][0][4 * q + i] - mean) * rstd * lg[i] + lb[i]);
+          acc2[b][0][4 * q + i] += b2[i];
+        }
+        if (q & 1) asm volatile("" : "+v"(x1[2 * b + (q >> 1)]), "+v"(acc2[b][0])::"memory");
+      }
+  }
+
+  // ================= MLP (one chunk of 32 hidden units at a time) =================
+  m3_wait_barrier(0);                               // chunks 0 and 1 in LDS, every wave done with the user weights
+#pragma unroll 1
+  for (int ch = 0; ch < nch; ++ch) {
+    // the other buffer was last read in iteration ch - 1, before its closing barrier
+    if (ch >= 1 && ch + 1 < nch) dma_m(ch + 1, (ch + 1) & 1);
+    const char* s1 = wreg + (ch & 1) * S::mb + lane * 16;
+    const float* sb = sb1 + ch * kM3FCH;
+    f32x16 acc1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const f32x4 bq = *(const f32x4*)&sb[16 * (q >> 1) + 8 * g2 + 4 * (q & 1)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc1[4 * q + i] = bq[i];
+    }
+    mfma_pipe<KS, PF>([&](int s) { return *(const bf16x8*)(s1 + s * 1024); },
+                      [&](int s, const bf16x8& w) { acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, x1[s], acc1, 0, 0, 0); });
+    bf16x8 hf[2];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) hf[q >> 1][4 * (q & 1) + i] = (bf16)gelu_f(acc1[4 * q + i]);
+    mfma_pipe<NO, PF>(
+        [&](int j) { return *(const bf16x8*)(s1 + (KS + j) * 1024); },
+        [&](int j, const bf16x8& w) {
+          acc2[j >> 1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, hf[j & 1], acc2[j >> 1][0], 0, 0, 0);
+        });
+    // chunk ch + 1 complete in every wave, and every wave done with buffer ch & 1
+    if (ch + 1 < nch) m3_wait_barrier(0);
+  }
+  m3_epilogue_final<D, PROJ>(acc2, tok, g, g2, svm);
+}
+
+// ---------------------------------------------------------------------------
 // The output projection of an attention sublayer and the MLP that follows,
 // in one token-resident kernel (BF16, d = 256): the residual stream and the
 // LayerNorm output between them stay in registers.
@@ -3542,6 +3814,10 @@ int oproj_mlp3_variants() { return 8; }
 //   role 3, Wqkv [3d][d] (k_oproj_user_attn4): f = (3 d / 32) t + 3 s + m ->
 //     row m d + 32 (t / 2) + l32, the k-ordered columns 16 (d / 32 (t % 2) + s)
 //     + 8 g2 + e (chunk t: head t / 2, half t % 2 of the k range; m = Q, K, V)
+//   role 5, Wqkv [3d][d] (k_user_mlp_f): f = (3 d / 16) p + 3 s + m -> row
+//     m d + 32 p + l32, columns 16 s + 8 g2 + e (head pair p, k-step s)
+//   role 6, W_o [d][d] (k_user_mlp_f): f = (d / 16) p + 2 b + s -> row
+//     32 b + l32, the k-ordered columns 32 p + 16 s + 8 g2 + e
 // The e4m3 W1 of k_oproj_mlp4<..., F8>: from the reordered e4m3 rows w1p
 // (Mat::f8p's layout, rows of d bytes), fragment (ch, t) of 2 KB holds, for
 // lane l = 32 h + l32, bytes 64 t + 32 h .. + 31 of row 32 ch + sigma(l32) as
@@ -3563,7 +3839,7 @@ void om4_fragment_copy_f8(int d, int F, const uint8_t* w1p, uint8_t* dst) {
 
 void om4_fragment_copy(int role, int d, int F, const float* src, uint16_t* dst, uint16_t (*to_bf16)(float)) {
   static const int kperm[16] = {0, 1, 2, 3, 8, 9, 10, 11, 4, 5, 6, 7, 12, 13, 14, 15};
-  const int rows = role == 1 ? F : role == 3 ? 3 * d : d, cols = role == 2 ? F : d;
+  const int rows = role == 1 ? F : (role == 3 || role == 5) ? 3 * d : d, cols = role == 2 ? F : d;
   const size_t nfrag = (size_t)rows * cols / 512;
   const int obk = d / 32, ks = d / 16;
   for (size_t f = 0; f < nfrag; ++f)
@@ -3580,6 +3856,15 @@ void om4_fragment_copy(int role, int d, int F, const float* src, uint16_t* dst, 
           const int q = l32 >> 3, g = (l32 >> 2) & 1, i = l32 & 3;
           r = 32 * ch + 16 * (q >> 1) + 8 * g + 4 * (q & 1) + i;   // sigma(l32)
           const int kc = 16 * s + 8 * g2 + e;
+          c = (kc & ~15) + kperm[kc & 15];
+        } else if (role == 5) {
+          const int p = (int)(f / (3 * ks)), i3 = (int)(f % (3 * ks)), s = i3 / 3, m = i3 % 3;
+          r = m * d + 32 * p + l32;
+          c = 16 * s + 8 * g2 + e;
+        } else if (role == 6) {
+          const int p = (int)(f / (2 * obk)), j = (int)(f % (2 * obk));
+          r = 32 * (j >> 1) + l32;
+          const int kc = 32 * p + 16 * (j & 1) + 8 * g2 + e;
           c = (kc & ~15) + kperm[kc & 15];
         } else if (role == 3) {
           const int kh = ks / 2, t = (int)(f / (3 * kh)), i3 = (int)(f % (3 * kh)), s = i3 / 3, m = i3 % 3;
@@ -3634,20 +3919,35 @@ hipError_t launch_user_mlp_tr(const StepCtx& c, void* XN, const DevLayer& L, con
     if (g2.proj_out) hipLaunchKernelGGL((k_user_mlp_tr<128, NW, NB, 512, true, PF>), grid, block, 0, s, c, a); \
     else hipLaunchKernelGGL((k_user_mlp_tr<128, NW, NB, 512, false, PF>), grid, block, 0, s, c, a);            \
   }
-  // variants: waves per workgroup (4: two workgroups per CU; 8: one, which
-  // halves the weight traffic per token), the depth of the MLP chunk ring and
-  // the MLP weight fragments each wave keeps in flight; each wave's arithmetic
-  // on its own 32 tokens is the same in all of them
-  if (variant == 1) CIDER_UM(4, 3, 3)
-  else if (variant == 2) CIDER_UM(4, 2, 2)
-  else if (variant == 3) CIDER_UM(4, 2, 4)
-  else if (variant == 4) CIDER_UM(8, 3, 3)
+  // Variants 0-1: k_user_mlp_f (fragment-major weights, double-buffered
+  // head-pair weights) with 3 or 2 weight fragments in flight; 2-6:
+  // k_user_mlp_tr with 4 waves per workgroup (two workgroups per CU) or 8
+  // (one, which halves the weight traffic per token), MLP chunk rings of 2 or
+  // 3 and 2-4 fragments in flight.  Each wave's arithmetic on its own 32
+  // tokens is the same in all of them.
+  if (variant == 0 || variant == 1) {
+    if (!L.Wqkv_u.b16f || !L.Wo_u.b16f || !L.W1.b16f || !L.W2.b16f) return hipErrorInvalidValue;
+    UserMlpArgs af = a;
+    af.Wqkv = L.Wqkv_u.b16f; af.Wo = L.Wo_u.b16f; af.W1 = L.W1.b16f; af.W2 = L.W2.b16f;
+    const dim3 grid((c.total_ugrp32 + 3) / 4), block(256);
+#define CIDER_UMF(PF)                                                                             \
+  if (g2.proj_out) hipLaunchKernelGGL((k_user_mlp_f<128, 512, true, PF>), grid, block, 0, s, c, af); \
+  else hipLaunchKernelGGL((k_user_mlp_f<128, 512, false, PF>), grid, block, 0, s, c, af);
+    if (variant == 1) { CIDER_UMF(2) }
+    else { CIDER_UMF(3) }
+#undef CIDER_UMF
+    return hipGetLastError();
+  }
+  if (variant == 3) CIDER_UM(4, 3, 3)
+  else if (variant == 4) CIDER_UM(4, 2, 2)
+  else if (variant == 5) CIDER_UM(4, 2, 4)
+  else if (variant == 6) CIDER_UM(8, 3, 3)
   else CIDER_UM(4, 2, 3)
 #undef CIDER_UM
   return hipGetLastError();
 }
 
-int user_mlp_tr_variants() { return 5; }
+int user_mlp_tr_variants() { return 7; }
 
 bool row_qkv_attn_ok(int d, int heads, int max_n) { return d == 256 && heads * 32 == d && max_n <= 256; }
 

@@ -417,7 +417,8 @@ def test_every_gemm_tile_gives_identical_decodes():
                 assert torch.equal(out, ref[0]) and torch.equal(lg, ref[1]), mode
         roles = {t[0] for t in P.cider_tuning_read(wh)}
         if d == 128:
-            # the user sublayer + MLP kernel's variants (forced tiles 0-3 above)
+            # the user sublayer + MLP kernel's variants (forced tiles 0-6 above: 0-1
+            # on the fragment-major weights, 2-6 the padded layouts)
             assert "user_mlp_tr" in roles, roles
         elif d == 256:
             # the output projection + MLP kernel's variants (forced tiles 0-7 above:
