@@ -116,7 +116,7 @@ struct Mat {
   // BF16 in MFMA-fragment order for the four-wave kernels (om4_fragment_copy):
   // at d = 256 W_o, W1, W2 (output projection + MLP), W_o (row) and the user
   // Wqkv (row output projection + user attention); at d = 128 the user Wqkv
-  // and W_o, W1, W2 (user sublayer + MLP)
+  // and W_o, W1, W2 (user sublayer + MLP) and the row Wqkv and W_o
   const bf16* b16f = nullptr;
   const uint8_t* f8f = nullptr;   // W1 only: f8p in the four-wave kernel's fragment order
   int rows = 0, cols = 0;

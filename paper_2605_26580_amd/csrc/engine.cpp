@@ -1487,6 +1487,7 @@ int cider_weights_create(const cider_model_cfg* cfg, const float* blob, size_t n
   for (int l = 0; l < cfg->n_layers; ++l) {
     DevLayer& L = m.layer[l];
     L.ln1_g = vec(d); L.ln1_b = vec(d);
+    const size_t off_wqr = off;
     if ((rc = mat(3 * d, d, &L.Wqkv_r))) goto bad;
     L.bqkv_r = vec(3 * (size_t)d);
     const size_t off_wor = off;
@@ -1548,12 +1549,15 @@ int cider_weights_create(const cider_model_cfg* cfg, const float* blob, size_t n
       // the row output projection + user attention
       // (d = 256); at d = 128 the same for the user sublayer + MLP kernel
       const bool om4 = oproj_mlp3_ok(d, F), ou4 = oproj_user_attn_ok(d, cfg->heads);
-      const bool umf = user_mlp_tr_ok(d, cfg->heads, F);
-      Mat* dstm[9] = {&L.Wo_u, &L.W1, &L.W2, &L.Wo_r, &L.Wqkv_u, &L.Wqkv_u, &L.Wo_u, &L.W1, &L.W2};
-      const int roles[9] = {0, 1, 2, 0, 3, 5, 6, 1, 2};
-      const size_t offs[9] = {off_wou, off_w1, off_w2, off_wor, off_wqu, off_wqu, off_wou, off_w1, off_w2};
-      for (int k = 0; k < 9; ++k) {
-        if (!(k < 3 ? om4 : k < 5 ? ou4 : umf)) continue;
+      // and the row sublayer
+      const bool umf = user_mlp_tr_ok(d, cfg->heads, F), rbf = row_block_tr_ok(d, cfg->heads, 1);
+      Mat* dstm[11] = {&L.Wo_u,   &L.W1,    &L.W2, &L.Wo_r, &L.Wqkv_u, &L.Wqkv_u,
+                       &L.Wo_u,   &L.W1,    &L.W2, &L.Wqkv_r, &L.Wo_r};
+      const int roles[11] = {0, 1, 2, 0, 3, 5, 6, 1, 2, 5, 6};
+      const size_t offs[11] = {off_wou, off_w1, off_w2, off_wor, off_wqu, off_wqu,
+                               off_wou, off_w1, off_w2, off_wqr, off_wor};
+      for (int k = 0; k < 11; ++k) {
+        if (!(k < 3 ? om4 : k < 5 ? ou4 : k < 9 ? umf : rbf)) continue;
         const size_t cnt = (size_t)dstm[k]->rows * dstm[k]->cols;
         std::vector<uint16_t> hf(cnt);
         om4_fragment_copy(roles[k], d, F, blob + offs[k], hf.data(), f32_to_bf16_bits);

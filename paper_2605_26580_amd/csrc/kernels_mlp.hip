@@ -1078,19 +1078,17 @@ void k_user_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const
 // transposed) to LDS, then every wave runs its 32 queries over the row's key
 // blocks with an online softmax (S^T = K Q^T from the shared K rows, O^T +=
 // V^T P^T from the shared V^T rows, both in P's key order), and feeds the
-// pair's O to the output projection.  The pair's Wqkv rows and W_o columns
-// sit in one LDS buffer each; each DMA is issued as soon as every wave is
-// done with the buffer it refills (Wqkv after the K/V publication, W_o after
-// the output projection), so it lands behind the attention or the next
-// projection.  59 KB of LDS: two workgroups per CU.
+// pair's O to the output projection.  The weights come from fragment-major
+// copies of Wqkv (role 5 of om4_fragment_copy) and W_o (role 6), each MFMA
+// operand fragment 1 KB with lane l's 16 bytes at 16 l; the pair's Wqkv
+// fragments sit in one buffer, refilled once every wave has published K and
+// V^T, and its W_o fragments in two, so that a pair costs two barriers (its
+// weights in LDS; K and V^T published).  62 KB of LDS: two workgroups per CU.
 template <int D>
-struct RBSmem {
-  static constexpr int RB1 = D * 2 + 16;               // bytes per stored Wqkv row
-  static constexpr int RB2 = 32 * 2 + 16;              // bytes per stored W_o row (the pair's 32 columns)
-  static constexpr size_t w1 = (size_t)96 * RB1;
-  static constexpr size_t w2 = (size_t)D * RB2;
-  static constexpr size_t w1a = (w1 + 15) / 16 * 16;
-  static constexpr size_t w2a = (w2 + 15) / 16 * 16;
+struct RBFSmem {
+  static constexpr size_t w1a = (size_t)3 * (D / 16) * 1024;   // a head pair's Wqkv fragments
+  static constexpr size_t w2 = (size_t)2 * (D / 32) * 1024;    // its W_o fragments
+  static constexpr size_t w2a = 2 * w2;                        // double-buffered
   // tile pitches of 18 and 66 dwords: the 8-byte accesses of 32 lanes to 32
   // consecutive rows then cover all 64 banks once (a pitch that is a
   // multiple of 4 dwords puts rows l and l + 16 on the same banks)
@@ -1106,13 +1104,13 @@ struct RBSmem {
 
 template <int D>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
-void k_row_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const float* __restrict__ bqkv,
-                    const bf16* __restrict__ Wo) {
-  using S = RBSmem<D>;
-  constexpr int RB1 = S::RB1, RB2 = S::RB2, LDK = S::LDK, LDV = S::LDV;
+void k_row_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqf, const float* __restrict__ bqkv,
+                    const bf16* __restrict__ Wof) {
+  using S = RBFSmem<D>;
+  constexpr int LDK = S::LDK, LDV = S::LDV;
   constexpr int KS = D / 16, NP = D / 32, OBK = D / 32;
-  constexpr int N1 = (int)((S::w1 + 1023) / 1024), N2 = (int)((S::w2 + 1023) / 1024);
-  constexpr int NP1 = (N1 + 3) / 4, NP2 = (N2 + 3) / 4;
+  constexpr int NQ = 3 * KS, NO = 2 * OBK;           // 1 KB fragments of a pair's Wqkv, W_o
+  static_assert(NQ % 4 == 0 && NO % 4 == 0, "DMA blocks split evenly over the waves");
   __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
   char* sw1 = smem;
   char* sw2 = smem + S::w1a;
@@ -1130,31 +1128,23 @@ void k_row_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const 
   const int tok = slot < n ? b.tok_off + (row - b.row_off) * n + slot : -1;
   const int nkb = (n + 31) / 32;                    // key blocks holding a token
 
-  // DMA blocks of this wave (uniform counts for the partial waits)
-  const int nw1 = N1 / 4 + (wave < N1 % 4 ? 1 : 0), nw2 = N2 / 4 + (wave < N2 % 4 ? 1 : 0);
+  // pair p's Wqkv fragments (3 s + m: k-step s of Q, K, V) and W_o fragments
+  // (2 b + s), NQ / 4 and NO / 4 DMA blocks per wave
   auto dma_qkv = [&](int p) {
 #pragma unroll
-    for (int k = 0; k < NP1; ++k) {
+    for (int k = 0; k < NQ / 4; ++k) {
       const int u = wave + 4 * k;
-      if (u >= N1) break;
-      const int pos = u * 1024 + lane * 16, j = pos / RB1, o = pos - j * RB1;
-      const bool data = o < RB1 - 16;
-      const int jj = data ? j : 0;
-      const bf16* src = Wqkv + (long)((jj >> 5) * D + 32 * p + (jj & 31)) * D + (data ? o / 2 : 0);
-      if (pos < (int)S::w1)
-        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(sw1 + u * 1024), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(Wqf + ((long)p * NQ + u) * 512 + lane * 8,
+                                       (__attribute__((address_space(3))) void*)(sw1 + u * 1024), 16, 0, 0);
     }
   };
   auto dma_o = [&](int p) {
 #pragma unroll
-    for (int k = 0; k < NP2; ++k) {
+    for (int k = 0; k < NO / 4; ++k) {
       const int u = wave + 4 * k;
-      if (u >= N2) break;
-      const int pos = u * 1024 + lane * 16, j = pos / RB2, o = pos - j * RB2;
-      const bool data = o < RB2 - 16;
-      const bf16* src = Wo + (long)(data ? j : 0) * D + 32 * p + (data ? o / 2 : 0);
-      if (pos < (int)S::w2)
-        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(sw2 + u * 1024), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(Wof + ((long)p * NO + u) * 512 + lane * 8,
+                                       (__attribute__((address_space(3))) void*)(sw2 + (p & 1) * S::w2 + u * 1024), 16, 0,
+                                       0);
     }
   };
   for (int i = tid; i < 3 * D; i += 256) sbias[i] = bqkv[i];
@@ -1177,16 +1167,18 @@ void k_row_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const 
 
 #pragma unroll 1
   for (int p = 0; p < NP; ++p) {
-    // Wqkv of pair p in LDS (issued before W_o of pair p, which may still be in flight)
-    m3_wait_barrier(nw2);
+    // Wqkv of pair p in LDS (issued before W_o of pair p, which may still be
+    // in flight); every wave done with the previous pair's K and V^T
+    m3_wait_barrier(NO / 4);
+    const char* sq = sw1 + lane * 16;
     f32x16 aq, ak, av;
 #pragma unroll
     for (int r = 0; r < 16; ++r) aq[r] = ak[r] = av[r] = 0.f;
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      const bf16x8 wq = *(const bf16x8*)(sw1 + l32 * RB1 + (2 * s + g2) * 16);
-      const bf16x8 wk = *(const bf16x8*)(sw1 + (32 + l32) * RB1 + (2 * s + g2) * 16);
-      const bf16x8 wv = *(const bf16x8*)(sw1 + (64 + l32) * RB1 + (2 * s + g2) * 16);
+      const bf16x8 wq = *(const bf16x8*)(sq + (3 * s) * 1024);
+      const bf16x8 wk = *(const bf16x8*)(sq + (3 * s + 1) * 1024);
+      const bf16x8 wv = *(const bf16x8*)(sq + (3 * s + 2) * 1024);
       aq = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wq, xf[s], aq, 0, 0, 0);
       ak = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wk, xf[s], ak, 0, 0, 0);
       av = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xf[s], wv, av, 0, 0, 0);
@@ -1210,10 +1202,13 @@ void k_row_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const 
       *(bf16x4*)&sK[slot * LDK + 8 * q + 4 * g2] = kq;
       *(bf16x4*)&sVt[l32 * LDV + 32 * wave + 8 * q + 4 * g2] = vq;
     }
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    __builtin_amdgcn_s_barrier();                   // K, V^T of the row published; Wqkv buffer free
-    asm volatile("" ::: "memory");
-    if (p + 1 < NP) dma_qkv(p + 1);
+    // K, V^T of the row published, W_o of pair p in LDS; the Wqkv buffer
+    // and the other W_o buffer (last read in pair p - 1) are free
+    m3_wait_barrier(0);
+    if (p + 1 < NP) {
+      dma_qkv(p + 1);
+      dma_o(p + 1);
+    }
 
     f32x16 ob;                                       // O of the pair, pair features as Q's
 #pragma unroll
@@ -1273,9 +1268,6 @@ void k_row_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const 
 #pragma unroll
       for (int r = 0; r < 8; ++r) ob[8 * e + r] = o[8 * e + r] * inv;
     }
-    // W_o of pair p in LDS (the Wqkv DMA of pair p + 1, issued after it, may
-    // be in flight); every wave is done with K and V^T of this pair
-    m3_wait_barrier(p + 1 < NP ? nw1 : 0);
     bf16x8 of[2];
 #pragma unroll
     for (int r = 0; r < 16; ++r) of[r >> 3][r & 7] = (bf16)ob[r];
@@ -1283,16 +1275,9 @@ void k_row_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqkv, const 
     for (int bo = 0; bo < OBK; ++bo)
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
-        const char* wr = sw2 + (32 * bo + l32) * RB2;
-        const bf16x8 w = *(const bf16x8*)(wr + (16 * s + 8 * g2) * 2);   // k-ordered rows
+        const bf16x8 w = *(const bf16x8*)(sw2 + (p & 1) * S::w2 + (2 * bo + s) * 1024 + lane * 16);
         acc2[bo][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, of[s], acc2[bo][0], 0, 0, 0);
       }
-    if (p + 1 < NP) {
-      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-      __builtin_amdgcn_s_barrier();                 // every wave is done with W_o of pair p
-      asm volatile("" ::: "memory");
-      dma_o(p + 1);
-    }
   }
   m3_residual_epilogue<D, 1, false>(acc2, tok >= 0 ? (long)tok : g.M, g, g2, sv);
 }
@@ -1313,7 +1298,7 @@ struct RQSmem {
   static constexpr int RB = D * 2 + 16;                // bytes per stored weight row
   static constexpr size_t w = (size_t)96 * RB;
   static constexpr size_t wa = (w + 15) / 16 * 16;
-  // tile pitches of 18 and 130 dwords (see RBSmem)
+  // tile pitches of 18 and 130 dwords (see RBFSmem)
   static constexpr int LDK = 32 + 4;                   // K row: the head's 32 features + pad (bf16)
   static constexpr int LDV = 256 + 4;                  // V^T row: 256 keys + pad (bf16)
   static constexpr size_t k = (size_t)256 * LDK * 2;
@@ -3971,7 +3956,7 @@ bool row_block_tr_ok(int d, int heads, int max_n) { return d == 128 && heads * 1
 hipError_t launch_row_block_tr(const StepCtx& c, void* XN, const DevLayer& L, const float* ln_g, const float* ln_b,
                                float* R, int d, int heads, hipStream_t s) {
   if (c.total_rows == 0) return hipSuccess;
-  if (!row_block_tr_ok(d, heads, c.max_n) || !L.Wqkv_r.b16 || !L.Wo_r.b16k) return hipErrorInvalidValue;
+  if (!row_block_tr_ok(d, heads, c.max_n) || !L.Wqkv_r.b16f || !L.Wo_r.b16f) return hipErrorInvalidValue;
   GemmArgs g{};
   g.M = c.total_tokens;
   g.N = d;
@@ -3982,8 +3967,9 @@ hipError_t launch_row_block_tr(const StepCtx& c, void* XN, const DevLayer& L, co
   g.R = R;
   g.ln_g = ln_g;
   g.ln_b = ln_b;
-  hipLaunchKernelGGL((k_row_block_tr<128>), dim3(c.total_rows), dim3(256), 0, s, c, g, L.Wqkv_r.b16, L.bqkv_r,
-                     L.Wo_r.b16k);   // W_o k-ordered (its operand is in the accumulator layout)
+  // fragment-major weights, W_o double-buffered
+  hipLaunchKernelGGL((k_row_block_tr<128>), dim3(c.total_rows), dim3(256), 0, s, c, g, L.Wqkv_r.b16f, L.bqkv_r,
+                     L.Wo_r.b16f);
   return hipGetLastError();
 }
 
