@@ -2142,15 +2142,20 @@ void k_user_mlp_f(StepCtx c, UserMlpArgs a) {
     }
     mfma_pipe<KS, PF>([&](int s) { return *(const bf16x8*)(s1 + s * 1024); },
                       [&](int s, const bf16x8& w) { acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, x1[s], acc1, 0, 0, 0); });
+    // GELU of the first 8 hidden values (the down projection's k-step 0);
+    // the other 8 are computed between the k-step 0 MFMAs, which run first
+    // (per output block the k-steps keep their order)
     bf16x8 hf[2];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) hf[q >> 1][4 * (q & 1) + i] = (bf16)gelu_f(acc1[4 * q + i]);
+    for (int v = 0; v < 8; ++v) hf[0][v] = (bf16)gelu_f(acc1[v]);
     mfma_pipe<NO, PF>(
-        [&](int j) { return *(const bf16x8*)(s1 + (KS + j) * 1024); },
-        [&](int j, const bf16x8& w) {
-          acc2[j >> 1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, hf[j & 1], acc2[j >> 1][0], 0, 0, 0);
+        [&](int i) { return *(const bf16x8*)(s1 + (KS + 2 * (i % OBK) + i / OBK) * 1024); },
+        [&](int i, const bf16x8& w) {
+          acc2[i % OBK][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, hf[i / OBK], acc2[i % OBK][0], 0, 0, 0);
+          if (i < OBK) {
+#pragma unroll
+            for (int v = (i * 8) / OBK; v < ((i + 1) * 8) / OBK; ++v) hf[1][v] = (bf16)gelu_f(acc1[8 + v]);
+          }
         });
     // chunk ch + 1 complete in every wave, and every wave done with buffer ch & 1
     if (ch + 1 < nch) m3_wait_barrier(0);
