@@ -1221,15 +1221,21 @@ void k_row_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqf, const f
       f32x16 o;
 #pragma unroll
       for (int r = 0; r < 16; ++r) o[r] = 0.f;
-#pragma unroll 1
-      for (int kb = 0; kb < nkb; ++kb) {
+      // K fragment of key block kb (read one block ahead of its MFMA)
+      auto kfrag = [&](int kb) {
         const bf16* kr = &sK[(32 * kb + l32) * LDK + 16 * e + 4 * g2];
         const bf16x4 k0 = *(const bf16x4*)kr, k1 = *(const bf16x4*)(kr + 8);
-        const bf16x8 kfr = bf16x8{k0[0], k0[1], k0[2], k0[3], k1[0], k1[1], k1[2], k1[3]};
+        return bf16x8{k0[0], k0[1], k0[2], k0[3], k1[0], k1[1], k1[2], k1[3]};
+      };
+      bf16x8 kn = kfrag(0);
+#pragma unroll 1
+      for (int kb = 0; kb < nkb; ++kb) {
+        const bf16x8 kfr = kn;
         f32x16 st;
 #pragma unroll
         for (int r = 0; r < 16; ++r) st[r] = 0.f;
         st = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kfr, qf[e], st, 0, 0, 0);
+        if (kb + 1 < nkb) kn = kfrag(kb + 1);
         // register r: key 32 kb + 8(r/4) + 4 g2 + r%4; only the last block can
         // hold keys past n (a uniform branch)
         if (32 * kb + 32 > n) {
