@@ -1607,6 +1607,115 @@ __device__ __forceinline__ void m3_epilogue_final(f32x16 (&acc2)[D / 32][1], int
   }
 }
 
+// The same results as m3_epilogue_final, with the R and XN rows leaving the
+// wave as whole 256-byte row segments instead of 32- and 16-byte pieces of
+// 32 rows per store instruction (a quarter of the cache lines per store).
+// The accumulator-layout values pass through an 8 KB LDS slice of the wave:
+// 32 rows of 256 bytes, the 16-byte pieces of row r stored at piece index
+// XOR (r mod 16), so that the accumulator-layout writes (32 rows, one piece
+// each) and the row-order reads (4 rows of 16 pieces) both spread over all
+// banks.  R goes out in D / 64 rounds of 64 columns, XN in D / 128 rounds of
+// 128.  rowtok(r) is the token of the wave's row r (lane r's token) or -1.
+template <int D, bool PROJ, class RowTok>
+__device__ __forceinline__ void m3_epilogue_rows(f32x16 (&acc2)[D / 32][1], int tok, const GemmArgs& g, int g2,
+                                                 const float* sv, char* lds, int lane, RowTok rowtok) {
+  static_assert(D % 128 == 0, "whole 128-column rounds");
+  constexpr int OBK = D / 32;
+  const int l32 = lane & 31, sw = l32 & 15, rr = lane >> 4, pp = lane & 15;
+  const float* slg = sv + D;
+  const float* slb = sv + 2 * D;
+  float sum = 0.f;
+#pragma unroll
+  for (int b = 0; b < OBK; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) sum += acc2[b][0][r];
+  sum = xhalf_sum(sum);
+  const float mean = sum / (float)D;
+  float qv = 0.f;
+#pragma unroll
+  for (int b = 0; b < OBK; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float dv = acc2[b][0][r] - mean;
+      qv = fmaf(dv, dv, qv);
+    }
+  qv = xhalf_sum(qv);
+  const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
+  // the same values under new names: the compiler would otherwise keep every
+  // (acc2 - mean) of the variance loop alive for the LayerNorm below
+  float mean2 = mean, rstd2 = rstd;
+  asm volatile("" : "+v"(mean2), "+v"(rstd2));
+  if (!PROJ) {
+    bf16* xo = (bf16*)g.out;
+#pragma unroll
+    for (int j = 0; j < D / 128; ++j) {
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int b = 4 * j + bb, p = 4 * bb + q, f = 32 * b + 8 * q + 4 * g2;
+          const f32x4 lg = *(const f32x4*)&slg[f];
+          const f32x4 lb = *(const f32x4*)&slb[f];
+          bf16x4 h;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) h[i] = (bf16)((acc2[b][0][4 * q + i] - mean2) * rstd2 * lg[i] + lb[i]);
+          *(bf16x4*)(lds + l32 * 256 + 16 * (p ^ sw) + 8 * g2) = h;
+        }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int r = 4 * t + rr;
+        const bf16x8 v = *(const bf16x8*)(lds + r * 256 + 16 * (pp ^ (r & 15)));
+        const long tr = rowtok(r);
+        if (tr >= 0) *(bf16x8*)(xo + tr * D + 128 * j + 8 * pp) = v;
+      }
+    }
+  } else {
+    const float* sp0 = sv + 3 * D;
+    const float* sp1 = sv + 4 * D;
+    float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+    for (int b = 0; b < OBK; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int f = 32 * b + 8 * q + 4 * g2;
+        const f32x4 lg = *(const f32x4*)&slg[f];
+        const f32x4 lb = *(const f32x4*)&slb[f];
+        const f32x4 w0 = *(const f32x4*)&sp0[f];
+        const f32x4 w1 = *(const f32x4*)&sp1[f];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float hv = (acc2[b][0][4 * q + i] - mean2) * rstd2 * lg[i] + lb[i];
+          a0 = fmaf(hv, w0[i], a0);
+          a1 = fmaf(hv, w1[i], a1);
+        }
+      }
+    a0 = xhalf_sum(a0);
+    a1 = xhalf_sum(a1);
+    if (tok >= 0 && g2 == 0) {
+      g.proj_out[2 * (long)tok] = a0;
+      g.proj_out[2 * (long)tok + 1] = a1;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < D / 64; ++j) {
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int b = 2 * j + bb, p = 8 * bb + 2 * q + g2;
+        *(f32x4*)(lds + l32 * 256 + 16 * (p ^ sw)) =
+            f32x4{acc2[b][0][4 * q], acc2[b][0][4 * q + 1], acc2[b][0][4 * q + 2], acc2[b][0][4 * q + 3]};
+      }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int r = 4 * t + rr;
+      const f32x4 v = *(const f32x4*)(lds + r * 256 + 16 * (pp ^ (r & 15)));
+      const long tr = rowtok(r);
+      if (tr >= 0) *(f32x4*)(g.R + tr * D + 64 * j + 4 * pp) = v;
+    }
+  }
+}
+
 template <int D, int NW, int NBUF, int MAXF, bool PROJ, int PF>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_user_mlp_tr(StepCtx c, UserMlpArgs a) {
@@ -1909,6 +2018,7 @@ struct UMFSmem {
   static constexpr size_t vec = ((size_t)(3 * D + 3 * D + MAXF + 5 * D) * 4 + 1023) / 1024 * 1024;
   static constexpr size_t bytes = vec + 2 * ub;
   static_assert(2 * mb <= ub, "the MLP ring fits in the first pair buffer");
+  static_assert(ub >= 4 * 8192, "the second pair buffer holds the four waves' 8 KB epilogue slices");
   static_assert(bytes <= 80 * 1024, "two workgroups per CU");
 };
 
@@ -2166,7 +2276,10 @@ void k_user_mlp_f(StepCtx c, UserMlpArgs a) {
     // chunk ch + 1 complete in every wave, and every wave done with buffer ch & 1
     if (ch + 1 < nch) m3_wait_barrier(0);
   }
-  m3_epilogue_final<D, PROJ>(acc2, tok, g, g2, svm);
+  // the second head-pair buffer was last read in the user sublayer, before
+  // the barrier ahead of the MLP loop; row r of the wave is lane r's token
+  m3_epilogue_rows<D, PROJ>(acc2, tok, g, g2, svm, wreg + S::ub + wave * 8192, lane,
+                            [&](int r) { return (long)__shfl(tok, r); });
 }
 
 // ---------------------------------------------------------------------------
@@ -2477,6 +2590,7 @@ struct OM4Smem {
   static constexpr size_t vec = ((size_t)(3 * D + MAXF + 5 * D) * 4 + 1023) / 1024 * 1024;
   static constexpr size_t bytes = vec + 2 * buf;
   static_assert(bytes <= 80 * 1024, "two workgroups per CU");
+  static_assert(buf >= 4 * 8192, "one buffer holds the four waves' 8 KB epilogue slices");
 };
 
 template <int D, int MAXF, bool PROJ, int PF, bool F8 = false>
@@ -2705,7 +2819,10 @@ void k_oproj_mlp4(GemmArgs g, const bf16* __restrict__ Wof, const float* __restr
     // chunk ch + 1 complete in every wave, and every wave done with buffer ch & 1
     if (ch + 1 < nch) m3_wait_barrier(0);
   }
-  m3_epilogue_final<D, PROJ>(acc2, tok, g, g2, svm);
+  // the MLP ring's buffer (nch & 1) was last read before the closing barrier of chunk nch - 2
+  const long row0 = (long)blockIdx.x * TPW + wave * 32;
+  m3_epilogue_rows<D, PROJ>(acc2, tok, g, g2, svm, wreg + (nch & 1) * S::buf + wave * 8192, lane,
+                            [&](int r) { return row0 + r < g.M ? row0 + r : -1L; });
 }
 
 // ---------------------------------------------------------------------------
