@@ -302,6 +302,58 @@ __device__ __forceinline__ void m3_residual_epilogue(f32x16 (&acc2)[D / 32][TB],
   }
 }
 
+// Row stores of a wave's 32 tokens held in the accumulator layout (lane
+// (l32, g2) holds features 32 b + 8 q + 4 g2 + i of the wave's row l32 as
+// value (b, q, i)) as whole 256-byte row segments, instead of 32- or 16-byte
+// pieces of 32 rows per store instruction (a quarter of the cache lines per
+// store).  The values pass through an 8 KB LDS slice of the wave: 32 rows of
+// 256 bytes, the 16-byte pieces of row r stored at piece index XOR (r mod
+// 16), so that the accumulator-layout writes (32 rows, one piece each) and
+// the row-order reads (4 rows of 16 pieces) both spread over all banks.
+// val(b, q) returns the lane's four values of block b, step q; rowtok(r) is
+// the token of the wave's row r (lane r's token) or -1 (no store).  FP32 rows
+// go out in D / 64 rounds of 64 columns, BF16 rows in D / 128 rounds of 128.
+template <int D, class Val, class RowTok>
+__device__ __forceinline__ void rows_store_f32(Val val, float* dst, char* lds, int lane, RowTok rowtok) {
+  static_assert(D % 64 == 0, "whole 64-column rounds");
+  const int l32 = lane & 31, g2 = lane >> 5, sw = l32 & 15, rr = lane >> 4, pp = lane & 15;
+#pragma unroll
+  for (int j = 0; j < D / 64; ++j) {
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) *(f32x4*)(lds + l32 * 256 + 16 * ((8 * bb + 2 * q + g2) ^ sw)) = val(2 * j + bb, q);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int r = 4 * t + rr;
+      const f32x4 v = *(const f32x4*)(lds + r * 256 + 16 * (pp ^ (r & 15)));
+      const long tr = rowtok(r);
+      if (tr >= 0) *(f32x4*)(dst + tr * D + 64 * j + 4 * pp) = v;
+    }
+  }
+}
+
+template <int D, class Val, class RowTok>
+__device__ __forceinline__ void rows_store_bf16(Val val, bf16* dst, char* lds, int lane, RowTok rowtok) {
+  static_assert(D % 128 == 0, "whole 128-column rounds");
+  const int l32 = lane & 31, g2 = lane >> 5, sw = l32 & 15, rr = lane >> 4, pp = lane & 15;
+#pragma unroll
+  for (int j = 0; j < D / 128; ++j) {
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        *(bf16x4*)(lds + l32 * 256 + 16 * ((4 * bb + q) ^ sw) + 8 * g2) = val(4 * j + bb, q);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int r = 4 * t + rr;
+      const bf16x8 v = *(const bf16x8*)(lds + r * 256 + 16 * (pp ^ (r & 15)));
+      const long tr = rowtok(r);
+      if (tr >= 0) *(bf16x8*)(dst + tr * D + 128 * j + 8 * pp) = v;
+    }
+  }
+}
+
 template <int D, int TB, int NW, int WPE, int NBUF, bool PIPE, int SCHED, int MAXF, bool PROJ>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void k_mlp3(GemmArgs g, const bf16* __restrict__ W1, const float* __restrict__ b1, const bf16* __restrict__ W2,
@@ -1607,21 +1659,12 @@ __device__ __forceinline__ void m3_epilogue_final(f32x16 (&acc2)[D / 32][1], int
   }
 }
 
-// The same results as m3_epilogue_final, with the R and XN rows leaving the
-// wave as whole 256-byte row segments instead of 32- and 16-byte pieces of
-// 32 rows per store instruction (a quarter of the cache lines per store).
-// The accumulator-layout values pass through an 8 KB LDS slice of the wave:
-// 32 rows of 256 bytes, the 16-byte pieces of row r stored at piece index
-// XOR (r mod 16), so that the accumulator-layout writes (32 rows, one piece
-// each) and the row-order reads (4 rows of 16 pieces) both spread over all
-// banks.  R goes out in D / 64 rounds of 64 columns, XN in D / 128 rounds of
-// 128.  rowtok(r) is the token of the wave's row r (lane r's token) or -1.
+// The same results as m3_epilogue_final, with the R and XN rows stored
+// through the wave's 8 KB LDS slice `lds` (rows_store_f32 / rows_store_bf16).
 template <int D, bool PROJ, class RowTok>
 __device__ __forceinline__ void m3_epilogue_rows(f32x16 (&acc2)[D / 32][1], int tok, const GemmArgs& g, int g2,
                                                  const float* sv, char* lds, int lane, RowTok rowtok) {
-  static_assert(D % 128 == 0, "whole 128-column rounds");
   constexpr int OBK = D / 32;
-  const int l32 = lane & 31, sw = l32 & 15, rr = lane >> 4, pp = lane & 15;
   const float* slg = sv + D;
   const float* slb = sv + 2 * D;
   float sum = 0.f;
@@ -1646,29 +1689,17 @@ __device__ __forceinline__ void m3_epilogue_rows(f32x16 (&acc2)[D / 32][1], int 
   float mean2 = mean, rstd2 = rstd;
   asm volatile("" : "+v"(mean2), "+v"(rstd2));
   if (!PROJ) {
-    bf16* xo = (bf16*)g.out;
-#pragma unroll
-    for (int j = 0; j < D / 128; ++j) {
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int b = 4 * j + bb, p = 4 * bb + q, f = 32 * b + 8 * q + 4 * g2;
+    rows_store_bf16<D>(
+        [&](int b, int q) {
+          const int f = 32 * b + 8 * q + 4 * g2;
           const f32x4 lg = *(const f32x4*)&slg[f];
           const f32x4 lb = *(const f32x4*)&slb[f];
           bf16x4 h;
 #pragma unroll
           for (int i = 0; i < 4; ++i) h[i] = (bf16)((acc2[b][0][4 * q + i] - mean2) * rstd2 * lg[i] + lb[i]);
-          *(bf16x4*)(lds + l32 * 256 + 16 * (p ^ sw) + 8 * g2) = h;
-        }
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int r = 4 * t + rr;
-        const bf16x8 v = *(const bf16x8*)(lds + r * 256 + 16 * (pp ^ (r & 15)));
-        const long tr = rowtok(r);
-        if (tr >= 0) *(bf16x8*)(xo + tr * D + 128 * j + 8 * pp) = v;
-      }
-    }
+          return h;
+        },
+        (bf16*)g.out, lds, lane, rowtok);
   } else {
     const float* sp0 = sv + 3 * D;
     const float* sp1 = sv + 4 * D;
@@ -1696,24 +1727,11 @@ __device__ __forceinline__ void m3_epilogue_rows(f32x16 (&acc2)[D / 32][1], int 
       g.proj_out[2 * (long)tok + 1] = a1;
     }
   }
-#pragma unroll
-  for (int j = 0; j < D / 64; ++j) {
-#pragma unroll
-    for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int b = 2 * j + bb, p = 8 * bb + 2 * q + g2;
-        *(f32x4*)(lds + l32 * 256 + 16 * (p ^ sw)) =
-            f32x4{acc2[b][0][4 * q], acc2[b][0][4 * q + 1], acc2[b][0][4 * q + 2], acc2[b][0][4 * q + 3]};
-      }
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int r = 4 * t + rr;
-      const f32x4 v = *(const f32x4*)(lds + r * 256 + 16 * (pp ^ (r & 15)));
-      const long tr = rowtok(r);
-      if (tr >= 0) *(f32x4*)(g.R + tr * D + 64 * j + 4 * pp) = v;
-    }
-  }
+  rows_store_f32<D>(
+      [&](int b, int q) {
+        return f32x4{acc2[b][0][4 * q], acc2[b][0][4 * q + 1], acc2[b][0][4 * q + 2], acc2[b][0][4 * q + 3]};
+      },
+      g.R, lds, lane, rowtok);
 }
 
 template <int D, int NW, int NBUF, int MAXF, bool PROJ, int PF>
@@ -3131,7 +3149,8 @@ struct EG3Smem {
   // the start of LDS, so that every vector address is a register base + an
   // immediate
   static constexpr size_t vec = ((size_t)(13 * D + 12) * 4 + 8 * 4 + 1023) / 1024 * 1024;
-  static constexpr size_t bytes = vec + NCH * buf;
+  static constexpr size_t epi = (size_t)8 * 8192;       // the waves' 8 KB row-store slices
+  static constexpr size_t bytes = vec + NCH * buf + epi;
   static_assert(bytes <= 160 * 1024, "LDS");
 };
 
@@ -3145,6 +3164,7 @@ void k_embed_gate3(StepCtx c, EmbedW m, EmbedGateArgs a, int ntiles) {
   __shared__ __attribute__((aligned(1024))) char smem[S::bytes];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g2 = lane >> 5, l32 = lane & 31;
   char* wsm = smem + S::vec;                      // the weight chunks
+  char* const epi = smem + S::vec + NCH * S::buf + wave * 8192;   // this wave's row-store slice
   // E's three rows at a pitch of D + 4 floats: lanes of different symbols
   // read their row at the same feature, which a pitch of D (a multiple of
   // the bank count) would put on the same banks
@@ -3302,7 +3322,6 @@ void k_embed_gate3(StepCtx c, EmbedW m, EmbedGateArgs a, int ntiles) {
 
     // ---- blend R = g Z + (1 - g) e, then the first LayerNorm.  Lane l holds
     // output features 32 ob + 8 q + 4 g2 + i of its token in register 4 q + i.
-    float* Rrow = a.R + tq * D;
     float sum = 0.f;
 #pragma unroll
     for (int ob = 0; ob < OBK; ++ob)
@@ -3324,8 +3343,6 @@ void k_embed_gate3(StepCtx c, EmbedW m, EmbedGateArgs a, int ntiles) {
           acc2[ob][4 * q + i] = res;
           sum += res;
         }
-        if (tv)
-          *(f32x4*)(Rrow + f) = f32x4{acc2[ob][4 * q], acc2[ob][4 * q + 1], acc2[ob][4 * q + 2], acc2[ob][4 * q + 3]};
         asm volatile("" ::: "memory");            // bound the loads in flight
       }
     sum = xhalf_sum(sum);
@@ -3340,21 +3357,28 @@ void k_embed_gate3(StepCtx c, EmbedW m, EmbedGateArgs a, int ntiles) {
       }
     qv = xhalf_sum(qv);
     const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
-    if (tv) {
-      bf16* xo = a.XN + tok * D;
-#pragma unroll
-      for (int ob = 0; ob < OBK; ++ob)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
+    // R and XN leave as whole row segments (rows_store_*): row r of the wave
+    // is token tile * kM3BM + 32 wave + r
+    const long row0 = (long)tile * kM3BM + wave * 32;
+    const auto rowtok = [&](int r) { return row0 + r < c.total_tokens ? row0 + r : -1L; };
+    float mean2 = mean, rstd2 = rstd;
+    asm volatile("" : "+v"(mean2), "+v"(rstd2));   // no (acc2 - mean) kept from the variance loop
+    rows_store_bf16<D>(
+        [&](int ob, int q) {
           const int f = 32 * ob + 8 * q + 4 * g2;
           const f32x4 lg = *(const f32x4*)(slg + f);
           const f32x4 lb = *(const f32x4*)(slb + f);
           bf16x4 h;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) h[i] = (bf16)((acc2[ob][4 * q + i] - mean) * rstd * lg[i] + lb[i]);
-          *(bf16x4*)(xo + f) = h;
-        }
-    }
+          for (int i = 0; i < 4; ++i) h[i] = (bf16)((acc2[ob][4 * q + i] - mean2) * rstd2 * lg[i] + lb[i]);
+          return h;
+        },
+        a.XN, epi, lane, rowtok);
+    rows_store_f32<D>(
+        [&](int ob, int q) {
+          return f32x4{acc2[ob][4 * q], acc2[ob][4 * q + 1], acc2[ob][4 * q + 2], acc2[ob][4 * q + 3]};
+        },
+        a.R, epi, lane, rowtok);
   }
   if (!weights_ready) __syncthreads();            // no tile: drain the DMA before the workgroup ends
 }
