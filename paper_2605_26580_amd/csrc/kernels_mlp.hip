@@ -312,7 +312,10 @@ __device__ __forceinline__ void m3_residual_epilogue(f32x16 (&acc2)[D / 32][TB],
 // the row-order reads (4 rows of 16 pieces) both spread over all banks.
 // val(b, q) returns the lane's four values of block b, step q; rowtok(r) is
 // the token of the wave's row r (lane r's token) or -1 (no store).  FP32 rows
-// go out in D / 64 rounds of 64 columns, BF16 rows in D / 128 rounds of 128.
+// go out in D / 64 rounds of 64 columns, BF16 rows in D / 128 rounds of 128
+// (pairs of steps exchanged between the wave's halves first, so that the
+// BF16 slice is also written in whole 16-byte pieces: 8-byte writes to
+// 16-byte slots would meet on the banks).
 template <int D, class Val, class RowTok>
 __device__ __forceinline__ void rows_store_f32(Val val, float* dst, char* lds, int lane, RowTok rowtok) {
   static_assert(D % 64 == 0, "whole 64-column rounds");
@@ -342,8 +345,18 @@ __device__ __forceinline__ void rows_store_bf16(Val val, bf16* dst, char* lds, i
 #pragma unroll
     for (int bb = 0; bb < 4; ++bb)
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        *(bf16x4*)(lds + l32 * 256 + 16 * ((4 * bb + q) ^ sw) + 8 * g2) = val(4 * j + bb, q);
+      for (int k = 0; k < 2; ++k) {
+        // steps 2k and 2k + 1: this lane holds half g2 of pieces 4 bb + 2k and
+        // 4 bb + 2k + 1, lane l ^ 32 the other halves; one exchange leaves
+        // piece 4 bb + 2k + g2 whole in this lane (low half, then high half)
+        typedef unsigned u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned))));
+        typedef unsigned u32x4 __attribute__((__vector_size__(4 * sizeof(unsigned))));
+        const u32x2 h0 = __builtin_bit_cast(u32x2, val(4 * j + bb, 2 * k));
+        const u32x2 h1 = __builtin_bit_cast(u32x2, val(4 * j + bb, 2 * k + 1));
+        const auto s0 = __builtin_amdgcn_permlane32_swap(h0[0], h1[0], false, false);
+        const auto s1 = __builtin_amdgcn_permlane32_swap(h0[1], h1[1], false, false);
+        *(u32x4*)(lds + l32 * 256 + 16 * ((4 * bb + 2 * k + g2) ^ sw)) = u32x4{s0[0], s1[0], s0[1], s1[1]};
+      }
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int r = 4 * t + rr;
