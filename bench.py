@@ -565,7 +565,7 @@ def run_batched(args, wl, P, torch):
         psi = synth.make_quality_head(cfg.d, args.qhead, seed=7, b2=30.0)
         qbuf = torch.from_numpy(psi).to(dev)
         ro = dict(remask=1, qhead=qbuf, qhead_hidden=args.qhead)
-    opts = P.cider_opts_default(precision=prec, use_graph=1, **ro)
+    opts = P.cider_opts_default(precision=prec, use_graph=1, autotune=args.autotune, **ro)
     blist = [{"y": ys[i], "sigma2": s2[i], "code": chs[i], "K": shapes[i][0], "n": shapes[i][1],
               "out_symbols": outs[i], "out_rounds": rounds[i:i + 1]} for i in range(B)]
     stream = torch.cuda.Stream()
@@ -894,6 +894,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="c2: skip the stored-grid agreement and the c3 record")
     ap.add_argument("--qhead", type=int, default=0, help="quality head with this many hidden units as the remask criterion")
     ap.add_argument("--calib-copy", action="store_true", help="end with a 256 MiB device copy (counter calibration)")
+    ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
+                    help="batched workloads: 0 keeps every kernel at its default variant (profiling runs)")
     ap.add_argument("--load", default="0.5,0.9")
     ap.add_argument("--duration", type=float, default=15.0)
     ap.add_argument("--burst", type=int, default=96)
