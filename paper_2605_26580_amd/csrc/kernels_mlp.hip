@@ -3570,7 +3570,6 @@ void k_embed_gate_z(StepCtx c, EmbedW m, EmbedGateArgs a) {
 
   // ---- blend R = g Z + (1 - g) e, then the first LayerNorm.  Lane l holds
   // output features 32 ob + 8 q + 4 g2 + i of its token in register 4 q + i.
-  float* Rrow = a.R + tq * D;
   float sum = 0.f;
 #pragma unroll
   for (int ob = 0; ob < OBK; ++ob)
@@ -3592,8 +3591,6 @@ void k_embed_gate_z(StepCtx c, EmbedW m, EmbedGateArgs a) {
         acc2[ob][4 * q + i] = res;
         sum += res;
       }
-      if (tv)
-        *(f32x4*)(Rrow + f) = f32x4{acc2[ob][4 * q], acc2[ob][4 * q + 1], acc2[ob][4 * q + 2], acc2[ob][4 * q + 3]};
       asm volatile("" ::: "memory");              // bounds the loads in flight
     }
   sum = xhalf_sum(sum);
@@ -3608,21 +3605,33 @@ void k_embed_gate_z(StepCtx c, EmbedW m, EmbedGateArgs a) {
     }
   qv = xhalf_sum(qv);
   const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
-  if (tv) {
-    bf16* xo = a.XN + tok * D;
-#pragma unroll
-    for (int ob = 0; ob < OBK; ++ob)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
+  // R and XN leave as whole row segments (rows_store_*), through the two ring
+  // buffers that do not hold the last chunk: both were last read before the
+  // barrier that closed chunk NCH - 2, and no DMA targets them any more.
+  // Waves 0-3 use one, waves 4-7 the other; row r of the wave is token
+  // 256 blockIdx.x + 32 wave + r.
+  static_assert(NW == 8 && 4 * 8192 <= M::buf && NCH >= NBUF - 1, "four 8 KB slices per free ring buffer");
+  char* const slice = wreg + ((NCH + (wave >> 2)) % NBUF) * M::buf + (wave & 3) * 8192;
+  const long row0 = (long)blockIdx.x * kM3BM + wave * 32;
+  const auto rowtok = [&](int r) { return row0 + r < c.total_tokens ? row0 + r : -1L; };
+  float mean2 = mean, rstd2 = rstd;
+  asm volatile("" : "+v"(mean2), "+v"(rstd2));   // no (acc2 - mean) kept from the variance loop
+  rows_store_bf16<D>(
+      [&](int ob, int q) {
         const int f = 32 * ob + 8 * q + 4 * g2;
         const f32x4 lg = *(const f32x4*)(slg + f);
         const f32x4 lb = *(const f32x4*)(slb + f);
         bf16x4 h;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) h[i] = (bf16)((acc2[ob][4 * q + i] - mean) * rstd * lg[i] + lb[i]);
-        *(bf16x4*)(xo + f) = h;
-      }
-  }
+        for (int i = 0; i < 4; ++i) h[i] = (bf16)((acc2[ob][4 * q + i] - mean2) * rstd2 * lg[i] + lb[i]);
+        return h;
+      },
+      a.XN, slice, lane, rowtok);
+  rows_store_f32<D>(
+      [&](int ob, int q) {
+        return f32x4{acc2[ob][4 * q], acc2[ob][4 * q + 1], acc2[ob][4 * q + 2], acc2[ob][4 * q + 3]};
+      },
+      a.R, slice, lane, rowtok);
 }
 
 }  // namespace
