@@ -316,22 +316,26 @@ __device__ __forceinline__ void m3_residual_epilogue(f32x16 (&acc2)[D / 32][TB],
 // (pairs of steps exchanged between the wave's halves first, so that the
 // BF16 slice is also written in whole 16-byte pieces: 8-byte writes to
 // 16-byte slots would meet on the banks).
-template <int D, class Val, class RowTok>
+// RB = 128 gives 4 KB slices: 32 rows of 128 bytes (32 columns per round,
+// pieces at index XOR (r mod 8), 8 rows per read instruction).
+template <int D, int RB = 256, class Val, class RowTok>
 __device__ __forceinline__ void rows_store_f32(Val val, float* dst, char* lds, int lane, RowTok rowtok) {
-  static_assert(D % 64 == 0, "whole 64-column rounds");
-  const int l32 = lane & 31, g2 = lane >> 5, sw = l32 & 15, rr = lane >> 4, pp = lane & 15;
+  static_assert(RB == 128 || RB == 256, "row segments of 128 or 256 bytes");
+  constexpr int NP = RB / 16, CPR = RB / 4, BPR = RB / 128, RPI = 64 / NP;   // pieces/row, columns, blocks, rows
+  static_assert(D % CPR == 0, "whole rounds");
+  const int l32 = lane & 31, g2 = lane >> 5, sw = l32 & (NP - 1), rr = lane / NP, pp = lane % NP;
 #pragma unroll
-  for (int j = 0; j < D / 64; ++j) {
+  for (int j = 0; j < D / CPR; ++j) {
 #pragma unroll
-    for (int bb = 0; bb < 2; ++bb)
+    for (int bb = 0; bb < BPR; ++bb)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) *(f32x4*)(lds + l32 * 256 + 16 * ((8 * bb + 2 * q + g2) ^ sw)) = val(2 * j + bb, q);
+      for (int q = 0; q < 4; ++q) *(f32x4*)(lds + l32 * RB + 16 * ((8 * bb + 2 * q + g2) ^ sw)) = val(BPR * j + bb, q);
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int r = 4 * t + rr;
-      const f32x4 v = *(const f32x4*)(lds + r * 256 + 16 * (pp ^ (r & 15)));
+    for (int t = 0; t < 32 / RPI; ++t) {
+      const int r = RPI * t + rr;
+      const f32x4 v = *(const f32x4*)(lds + r * RB + 16 * (pp ^ (r & (NP - 1))));
       const long tr = rowtok(r);
-      if (tr >= 0) *(f32x4*)(dst + tr * D + 64 * j + 4 * pp) = v;
+      if (tr >= 0) *(f32x4*)(dst + tr * D + CPR * j + 4 * pp) = v;
     }
   }
 }
@@ -3004,12 +3008,18 @@ void k_oproj_user_attn4(StepCtx c, const bf16* __restrict__ Orow, const bf16* __
           acc2[b][4 * q + i] = res;
           sum += res;
         }
-        if (tv)
-          *(f32x4*)(Rrow + 32 * b + 8 * q + 4 * g2) =
-              f32x4{acc2[b][4 * q], acc2[b][4 * q + 1], acc2[b][4 * q + 2], acc2[b][4 * q + 3]};
       }
       asm volatile("" : "+v"(acc2[b]), "+v"(sum)::"memory");   // bounds the loads in flight
     }
+    // R1 leaves as whole 128-byte row segments (rows_store_f32) through ring
+    // buffer DIST: the last W_o chunk's barrier freed it, and its first DMA
+    // is issued after the QKV loop's first barrier; row r of the wave is lane
+    // r's token
+    static_assert(NW * 4096 <= S::wq, "a 4 KB slice per wave in one ring buffer");
+    rows_store_f32<D, 128>([&](int b, int q) {
+                        return f32x4{acc2[b][4 * q], acc2[b][4 * q + 1], acc2[b][4 * q + 2], acc2[b][4 * q + 3]};
+                      },
+                      R, wreg + DIST * S::wq + wave * 4096, lane, [&](int r) { return (long)__shfl(tok, r); });
     sum = xhalf_sum(sum);
     const float mean = sum / (float)D;
     float qv = 0.f;
