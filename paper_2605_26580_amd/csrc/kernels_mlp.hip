@@ -371,6 +371,74 @@ __device__ __forceinline__ void rows_store_bf16(Val val, bf16* dst, char* lds, i
   }
 }
 
+// m3_residual_epilogue for one 32-token block without projection or gate
+// (R += acc2 + bias, then the next LayerNorm into g.out), with R and XN
+// stored as whole 256-byte row segments through the wave's 8 KB LDS slice
+// (rows_store_f32 / rows_store_bf16); the residual rows are loaded as in
+// m3_residual_epilogue.
+template <int D, class RowTok>
+__device__ __forceinline__ void m3_residual_rows(f32x16 (&acc2)[D / 32][1], long tok, const GemmArgs& g, int g2,
+                                                 const float* sv, char* lds, int lane, RowTok rowtok) {
+  constexpr int OBK = D / 32, HB = 4 < OBK ? 4 : OBK;
+  const float* sbias = sv;
+  const float* slg = sv + D;
+  const float* slb = sv + 2 * D;
+  const bool tv = tok < g.M;
+  const float* Rrow = g.R + (tv ? tok : 0) * D;
+  float sum = 0.f;
+#pragma unroll
+  for (int b0 = 0; b0 < OBK; b0 += HB) {
+    f32x4 rr[HB][4];
+#pragma unroll
+    for (int bb = 0; bb < HB; ++bb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        rr[bb][q] = tv ? *(const f32x4*)(Rrow + 32 * (b0 + bb) + 8 * q + 4 * g2) : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int bb = 0; bb < HB; ++bb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f32x4 bias = *(const f32x4*)&sbias[32 * (b0 + bb) + 8 * q + 4 * g2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float res = rr[bb][q][i] + (acc2[b0 + bb][0][4 * q + i] + bias[i]);
+          acc2[b0 + bb][0][4 * q + i] = res;
+          sum += res;
+        }
+      }
+  }
+  sum = xhalf_sum(sum);
+  const float mean = sum / (float)D;
+  float qv = 0.f;
+#pragma unroll
+  for (int b = 0; b < OBK; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float dv = acc2[b][0][r] - mean;
+      qv = fmaf(dv, dv, qv);
+    }
+  qv = xhalf_sum(qv);
+  const float rstd = 1.0f / sqrtf(qv / (float)D + 1e-5f);
+  float mean2 = mean, rstd2 = rstd;
+  asm volatile("" : "+v"(mean2), "+v"(rstd2));   // no (acc2 - mean) kept from the variance loop
+  rows_store_bf16<D>(
+      [&](int b, int q) {
+        const int f = 32 * b + 8 * q + 4 * g2;
+        const f32x4 lg = *(const f32x4*)&slg[f];
+        const f32x4 lb = *(const f32x4*)&slb[f];
+        bf16x4 h;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) h[i] = (bf16)((acc2[b][0][4 * q + i] - mean2) * rstd2 * lg[i] + lb[i]);
+        return h;
+      },
+      (bf16*)g.out, lds, lane, rowtok);
+  rows_store_f32<D>(
+      [&](int b, int q) {
+        return f32x4{acc2[b][0][4 * q], acc2[b][0][4 * q + 1], acc2[b][0][4 * q + 2], acc2[b][0][4 * q + 3]};
+      },
+      g.R, lds, lane, rowtok);
+}
+
 template <int D, int TB, int NW, int WPE, int NBUF, bool PIPE, int SCHED, int MAXF, bool PROJ>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void k_mlp3(GemmArgs g, const bf16* __restrict__ W1, const float* __restrict__ b1, const bf16* __restrict__ W2,
@@ -1354,7 +1422,15 @@ void k_row_block_tr(StepCtx c, GemmArgs g, const bf16* __restrict__ Wqf, const f
         acc2[bo][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, of[s], acc2[bo][0], 0, 0, 0);
       }
   }
-  m3_residual_epilogue<D, 1, false>(acc2, tok >= 0 ? (long)tok : g.M, g, g2, sv);
+  // R and XN through the row-store epilogue: the Wqkv buffer was last read
+  // before the last pair's publish barrier and W_o buffer NP & 1 before its
+  // start barrier (8 KB slices for waves 0-2 and wave 3); row r of the wave
+  // is slot 32 wave + r
+  static_assert(S::w1a >= 3 * 8192 && S::w2 >= 8192, "an 8 KB slice per wave");
+  char* const slice = wave < 3 ? sw1 + wave * 8192 : sw2 + (NP & 1) * S::w2;
+  const long tok0 = b.tok_off + (long)(row - b.row_off) * n + 32 * wave;
+  m3_residual_rows<D>(acc2, tok >= 0 ? (long)tok : g.M, g, g2, sv, slice, lane,
+                      [&](int r) { return 32 * wave + r < n ? tok0 + r : -1L; });
 }
 
 // ---------------------------------------------------------------------------
