@@ -1455,8 +1455,9 @@ struct RQSmem {
   static constexpr size_t k = (size_t)256 * LDK * 2;
   static constexpr size_t vt = (size_t)32 * LDV * 2;
   static constexpr size_t bias = (size_t)3 * D * 4;
-  static constexpr size_t bytes = 2 * wa + k + vt + bias;
-  static_assert(bytes <= 160 * 1024, "LDS");
+  static constexpr size_t os = (size_t)8 * 2048;       // the waves' 2 KB O row-store slices
+  static constexpr size_t bytes = 2 * wa + k + vt + bias + os;
+  static_assert(bytes <= 160 * 1024 && (bytes - os) % 16 == 0, "LDS");
 };
 
 template <int D>
@@ -1505,19 +1506,43 @@ void k_row_qkv_attn(StepCtx c, const bf16* __restrict__ XN, const bf16* __restri
   const float scale = 1.4426950408889634f / sqrtf(32.0f);
   constexpr int HB = 4;
   bf16x4 ob[HB][4];
-  bf16* orow = O + (long)(tok >= 0 ? tok : 0) * D;
+  // O of a batch of heads leaves as whole 64-byte row segments (one head of
+  // one row), through the wave's 2 KB LDS slice: 32 rows of 64 bytes, piece p
+  // of row r at index p XOR ((r / 2) mod 4), so that both the writes (8 rows
+  // of 2 lanes' pieces) and the row-order reads spread over all banks.  Each
+  // pair of steps is first exchanged between the wave's halves, so that
+  // every lane writes one whole 16-byte piece.  Row r of the wave is slot
+  // 32 wave + r.
+  char* const oslice = smem + (S::bytes - S::os) + wave * 2048;
+  const long orow0 = b.tok_off + (long)(row - b.row_off) * n + 32 * wave;
+  auto store_o = [&](int h0) {
+    typedef unsigned u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned))));
+    typedef unsigned u32x4 __attribute__((__vector_size__(4 * sizeof(unsigned))));
+#pragma unroll
+    for (int hh = 0; hh < HB; ++hh) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const u32x2 a0 = __builtin_bit_cast(u32x2, ob[hh][2 * k]);
+        const u32x2 a1 = __builtin_bit_cast(u32x2, ob[hh][2 * k + 1]);
+        const auto s0 = __builtin_amdgcn_permlane32_swap(a0[0], a1[0], false, false);
+        const auto s1 = __builtin_amdgcn_permlane32_swap(a0[1], a1[1], false, false);
+        *(u32x4*)(oslice + l32 * 64 + 16 * ((2 * k + g2) ^ ((l32 >> 1) & 3))) = u32x4{s0[0], s1[0], s0[1], s1[1]};
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int r = 16 * t + (lane >> 2), pp = lane & 3;
+        const u32x4 v = *(const u32x4*)(oslice + r * 64 + 16 * (pp ^ ((r >> 1) & 3)));
+        if (32 * wave + r < n) *(u32x4*)(O + (orow0 + r) * D + (h0 + hh) * 32 + 8 * pp) = v;
+      }
+    }
+  };
 #pragma unroll
   for (int h = 0; h < HEADS; ++h) {
     // chunk h in LDS; every wave is done with the previous head's K, V^T and
     // with the buffer the next DMA refills; the previous batch's O stores
     // are complete too
     m3_wait_barrier(0);
-    if (h % HB == 0 && h > 0 && tok >= 0) {
-#pragma unroll
-      for (int hh = 0; hh < HB; ++hh)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) *(bf16x4*)(orow + (h - HB + hh) * 32 + 8 * q + 4 * g2) = ob[hh][q];
-    }
+    if (h % HB == 0 && h > 0) store_o(h - HB);      // every lane joins the exchange
     if (h + 1 < HEADS) dma(h + 1, (h + 1) & 1);
     const char* sw = smem + (h & 1) * S::wa;
     f32x16 aq, ak, av;
@@ -1620,12 +1645,7 @@ void k_row_qkv_attn(StepCtx c, const bf16* __restrict__ XN, const bf16* __restri
       ob[h % HB][q] = bf16x4{(bf16)(o[4 * q] * inv), (bf16)(o[4 * q + 1] * inv), (bf16)(o[4 * q + 2] * inv),
                              (bf16)(o[4 * q + 3] * inv)};
   }
-  if (tok >= 0) {
-#pragma unroll
-    for (int hh = 0; hh < HB; ++hh)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) *(bf16x4*)(orow + (HEADS - HB + hh) * 32 + 8 * q + 4 * g2) = ob[hh][q];
-  }
+  store_o(HEADS - HB);
 }
 
 // ---------------------------------------------------------------------------
