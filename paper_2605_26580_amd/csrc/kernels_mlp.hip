@@ -3146,7 +3146,36 @@ void k_oproj_user_attn4(StepCtx c, const bf16* __restrict__ Orow, const bf16* __
   const float scale = 1.4426950408889634f / sqrtf(32.0f);
   constexpr int HB = 2;                             // heads per O store batch (registers)
   bf16x4 ob[HB][4];
-  bf16* orow = O + (long)(tv ? tok : 0) * D;
+  // O of a batch of heads leaves as whole 128-byte row segments through four
+  // 1 KB blocks of a ring buffer that only this wave's DMA refills (blocks
+  // wave + 4 j; block j holds rows 8 j .. 8 j + 7, piece p of row r at index
+  // p XOR (r mod 8)), after each pair of steps is exchanged between the
+  // wave's halves so that every lane writes one whole 16-byte piece; row r
+  // of the wave is lane r's token
+  static_assert(NW == 4 && QPW >= 4 && HB == 2, "four own DMA blocks per ring buffer; 8 pieces per row");
+  auto store_o = [&](int h0, int buf) {
+    typedef unsigned u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned))));
+    typedef unsigned u32x4 __attribute__((__vector_size__(4 * sizeof(unsigned))));
+    char* const blk = wreg + buf * S::wq + wave * 1024;   // block j at blk + 4096 j
+#pragma unroll
+    for (int hh = 0; hh < HB; ++hh)
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const u32x2 a0 = __builtin_bit_cast(u32x2, ob[hh][2 * k]);
+        const u32x2 a1 = __builtin_bit_cast(u32x2, ob[hh][2 * k + 1]);
+        const auto s0 = __builtin_amdgcn_permlane32_swap(a0[0], a1[0], false, false);
+        const auto s1 = __builtin_amdgcn_permlane32_swap(a0[1], a1[1], false, false);
+        *(u32x4*)(blk + (l32 >> 3) * 4096 + (l32 & 7) * 128 + 16 * ((4 * hh + 2 * k + g2) ^ (l32 & 7))) =
+            u32x4{s0[0], s1[0], s0[1], s1[1]};
+      }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = 8 * j + (lane >> 3), pp = lane & 7;
+      const u32x4 v = *(const u32x4*)(blk + j * 4096 + (r & 7) * 128 + 16 * (pp ^ (r & 7)));
+      const int tr = __shfl(tok, r);
+      if (tr >= 0) *(u32x4*)(O + (long)tr * D + h0 * 32 + 8 * pp) = v;
+    }
+  };
 #pragma unroll
   for (int h = 0; h < HEADS; ++h) {
     f32x16 aq, ak, av;
@@ -3160,12 +3189,9 @@ void k_oproj_user_attn4(StepCtx c, const bf16* __restrict__ Orow, const bf16* __
       m3_wait_barrier(QPW * (min(t + DIST - 1, NQ - 1) - t));
       // the previous batch of heads' O, stored between the wait and the next
       // DMA so that the next wait does not cover that DMA
-      if (half == 0 && h % HB == 0 && h > 0 && tv) {
-#pragma unroll
-        for (int hh = 0; hh < HB; ++hh)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) *(bf16x4*)(orow + (h - HB + hh) * 32 + 8 * q + 4 * g2) = ob[hh][q];
-      }
+      // (through the buffer of chunk t - 1, which that DMA refills; every lane
+      // joins the exchange)
+      if (half == 0 && h % HB == 0 && h > 0) store_o(h - HB, (t + DIST) % NBUF);
       if (t + DIST < NQ) dma_q(t + DIST, (t + DIST) % NBUF);
       const char* sw = wreg + (t % NBUF) * S::wq + lane * 16;
       // fragment 3 s + m: k-step KH half + s of Q (m = 0), K (1) and V (2)
@@ -3227,12 +3253,9 @@ void k_oproj_user_attn4(StepCtx c, const bf16* __restrict__ Orow, const bf16* __
       ob[h % HB][q] = bf16x4{(bf16)(o[4 * q] * inv), (bf16)(o[4 * q + 1] * inv), (bf16)(o[4 * q + 2] * inv),
                              (bf16)(o[4 * q + 3] * inv)};
   }
-  if (tv) {
-#pragma unroll
-    for (int hh = 0; hh < HB; ++hh)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) *(bf16x4*)(orow + (HEADS - HB + hh) * 32 + 8 * q + 4 * g2) = ob[hh][q];
-  }
+  // the last batch through the buffer of chunk NQ - 2: every wave was done
+  // with it at the last barrier, and no DMA refills it any more
+  store_o(HEADS - HB, (NQ - 2) % NBUF);
 }
 
 // ---------------------------------------------------------------------------
